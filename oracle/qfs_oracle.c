@@ -1,0 +1,650 @@
+/*
+ * qfs_oracle.c -- FP64 CPU oracle of QFactor-Sample instantiation (arXiv 2405.12866).
+ *
+ * TEST INFRASTRUCTURE ONLY (see qfs_oracle.h): plain loops in complex128, written from
+ * the paper's description of the method, with no blocking, fusion or reordering beyond
+ * what the method states. Each function names the passage it follows. Conventions are
+ * listed in qfs_oracle.h.
+ */
+#include "qfs_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define QO_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------------------
+ * Random numbers. The method draws its training states, validation states and initial
+ * gates at random (Sec. 3; App. A "multistarts and seed"). The paper uses SciPy's
+ * unitary_group; here the same Haar distribution is built from Philox4x32-10, written
+ * from its published definition (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications with a
+ * Weyl-sequence key schedule.
+ * ---------------------------------------------------------------------------------- */
+void qo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    k0 += 0x9E3779B9u; /* golden ratio */
+    k1 += 0xBB67AE85u; /* sqrt(3) - 1  */
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* One complex standard normal per Philox block, by the Box-Muller transform:
+ * two 53-bit uniforms u1 in (0,1], u2 in [0,1); |z|^2 = -ln u1 is Exp(1), so E|z|^2 = 1,
+ * and arg z = 2 pi u2 is uniform. */
+qo_cplx qo_cgauss(uint64_t seed, uint32_t role, uint32_t stream, uint64_t idx) {
+  uint32_t ctr[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), role, stream};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  qo_philox4x32_10(ctr, key, w);
+  uint64_t a = (((uint64_t)w[1] << 32) | w[0]) >> 11;
+  uint64_t b = (((uint64_t)w[3] << 32) | w[2]) >> 11;
+  double u1 = ((double)a + 1.0) * 0x1.0p-53;
+  double u2 = (double)b * 0x1.0p-53;
+  double r = sqrt(-log(u1));
+  double t = 2.0 * QO_PI * u2;
+  return r * cos(t) + I * (r * sin(t));
+}
+
+void qo_ginibre(int64_t rows, int64_t cols, uint64_t seed, uint32_t role, uint32_t stream,
+                qo_cplx *out) {
+  for (int64_t j = 0; j < cols; ++j)
+    for (int64_t i = 0; i < rows; ++i)
+      out[j * rows + i] = qo_cgauss(seed, role, stream, (uint64_t)(j * rows + i));
+}
+
+/* Column j of Q is the part of column j of A orthogonal to columns 0..j-1, normalised
+ * to unit length: the Q of A = QR with diag(R) real and positive, which makes Q Haar
+ * distributed for Ginibre A (Mezzadri, "How to generate random matrices from the
+ * classical compact groups", 2007). Gram-Schmidt with one re-orthogonalisation pass. */
+static int qo_gram_schmidt_columns(int64_t rows, int64_t first, int64_t cols, qo_cplx *A) {
+  for (int64_t j = first; j < cols; ++j) {
+    qo_cplx *v = A + j * rows;
+    double norm0 = 0.0;
+    for (int64_t i = 0; i < rows; ++i) norm0 += creal(v[i] * conj(v[i]));
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int64_t k = 0; k < j; ++k) {
+        const qo_cplx *q = A + k * rows;
+        qo_cplx r = 0.0;
+        for (int64_t i = 0; i < rows; ++i) r += conj(q[i]) * v[i];
+        for (int64_t i = 0; i < rows; ++i) v[i] -= r * q[i];
+      }
+    }
+    double norm = 0.0;
+    for (int64_t i = 0; i < rows; ++i) norm += creal(v[i] * conj(v[i]));
+    norm = sqrt(norm);
+    if (!(norm > 1e-12 * sqrt(norm0)) || norm == 0.0) return -1;
+    for (int64_t i = 0; i < rows; ++i) v[i] /= norm;
+  }
+  return 0;
+}
+
+int qo_orthonormalize(int64_t rows, int64_t cols, qo_cplx *A) {
+  return qo_gram_schmidt_columns(rows, 0, cols, A);
+}
+
+/* Sample states (Sec. 2.3 and Sec. 3: M mutually orthogonal Haar states; App. A: the
+ * columns of a Haar unitary). Column j is drawn from Philox index j*N + i, so the first
+ * M columns do not depend on how many more are drawn later. */
+int qo_draw_states(int n, int M, uint64_t seed, uint32_t role, uint32_t stream,
+                   qo_cplx *out) {
+  const int64_t N = (int64_t)1 << n;
+  qo_ginibre(N, M, seed, role, stream, out);
+  return qo_gram_schmidt_columns(N, 0, M, out);
+}
+
+/* Extension on doubling (Sec. 3 "double-and-restart"; Fig. pre-comp: A and B_0 are
+ * recomputed when the training set changes): columns m_old..m_new-1 of the same
+ * Ginibre stream, orthogonalised against every earlier column. */
+static int qo_extend_states(int n, int m_old, int m_new, uint64_t seed, qo_cplx *psi) {
+  const int64_t N = (int64_t)1 << n;
+  for (int64_t j = m_old; j < m_new; ++j)
+    for (int64_t i = 0; i < N; ++i)
+      psi[j * N + i] = qo_cgauss(seed, QO_ROLE_TRAIN, 0, (uint64_t)(j * N + i));
+  return qo_gram_schmidt_columns(N, m_old, m_new, psi);
+}
+
+/* Initial gate of one start (App. A: random initial unitaries controlled by the seed):
+ * Haar on U(4) from a 4x4 Ginibre block. Stored row-major u[q][p] = Q[q][p]. */
+void qo_haar_gate(uint64_t seed, uint32_t start, uint32_t gate, qo_cplx u[16]) {
+  qo_cplx cols[16]; /* column-major */
+  for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 4; ++i)
+      cols[j * 4 + i] = qo_cgauss(seed, QO_ROLE_INIT, start, (uint64_t)gate * 16u + j * 4 + i);
+  qo_gram_schmidt_columns(4, 0, 4, cols);
+  for (int q = 0; q < 4; ++q)
+    for (int p = 0; p < 4; ++p) u[q * 4 + p] = cols[p * 4 + q];
+}
+
+/* ------------------------------------------------------------------------------------
+ * State simulation (Sec. 3, Fig. pre-comp: the B list holds C's intermediate states).
+ * ---------------------------------------------------------------------------------- */
+static void qo_group_indices(int n, int qa, int qb, int64_t base, int64_t idx[4]) {
+  const int64_t ma = (int64_t)1 << (n - 1 - qa);
+  const int64_t mb = (int64_t)1 << (n - 1 - qb);
+  idx[0] = base;
+  idx[1] = base | mb;
+  idx[2] = base | ma;
+  idx[3] = base | ma | mb;
+}
+
+static void qo_apply_gate_impl(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16],
+                               int dagger) {
+  const int64_t N = (int64_t)1 << n;
+  const int64_t ma = (int64_t)1 << (n - 1 - qa);
+  const int64_t mb = (int64_t)1 << (n - 1 - qb);
+  qo_cplx m[16];
+  for (int q = 0; q < 4; ++q)
+    for (int p = 0; p < 4; ++p) m[q * 4 + p] = dagger ? conj(u[p * 4 + q]) : u[q * 4 + p];
+  for (int64_t j = 0; j < M; ++j) {
+    qo_cplx *s = st + j * N;
+    for (int64_t i = 0; i < N; ++i) {
+      if ((i & ma) || (i & mb)) continue;
+      int64_t idx[4];
+      qo_group_indices(n, qa, qb, i, idx);
+      qo_cplx v[4], w[4];
+      for (int p = 0; p < 4; ++p) v[p] = s[idx[p]];
+      for (int q = 0; q < 4; ++q) {
+        w[q] = 0.0;
+        for (int p = 0; p < 4; ++p) w[q] += m[q * 4 + p] * v[p];
+      }
+      for (int q = 0; q < 4; ++q) s[idx[q]] = w[q];
+    }
+  }
+}
+
+void qo_apply_gate(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16]) {
+  qo_apply_gate_impl(n, M, st, qa, qb, u, 0);
+}
+
+void qo_apply_gate_dag(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16]) {
+  qo_apply_gate_impl(n, M, st, qa, qb, u, 1);
+}
+
+void qo_apply_circuit(int n, int M, qo_cplx *st, int L, const int32_t *pairs,
+                      const qo_cplx *gates) {
+  for (int k = 0; k < L; ++k)
+    qo_apply_gate(n, M, st, pairs[2 * k], pairs[2 * k + 1], gates + 16 * k);
+}
+
+/* Output training states U psi_j for a dense target (Sec. 2.3: the training pairs are
+ * (psi_j, U psi_j)). */
+void qo_dense_apply(int n, int M, const qo_cplx *U, const qo_cplx *psi, qo_cplx *out) {
+  const int64_t N = (int64_t)1 << n;
+  for (int64_t j = 0; j < M; ++j)
+    for (int64_t r = 0; r < N; ++r) {
+      qo_cplx acc = 0.0;
+      for (int64_t c = 0; c < N; ++c) acc += U[r * N + c] * psi[j * N + c];
+      out[j * N + r] = acc;
+    }
+}
+
+/* Environment of one two-qubit gate (Sec. 3, Eq. 10 and Fig. env_calc_tensor): the
+ * contraction of the backward state a with the conjugate forward state B over every
+ * sample j and every index r of the other n-2 qubits. */
+void qo_environment(int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, int qb,
+                    qo_cplx G[16]) {
+  const int64_t N = (int64_t)1 << n;
+  const int64_t ma = (int64_t)1 << (n - 1 - qa);
+  const int64_t mb = (int64_t)1 << (n - 1 - qb);
+  for (int e = 0; e < 16; ++e) G[e] = 0.0;
+  for (int64_t j = 0; j < M; ++j)
+    for (int64_t i = 0; i < N; ++i) {
+      if ((i & ma) || (i & mb)) continue;
+      int64_t idx[4];
+      qo_group_indices(n, qa, qb, i, idx);
+      for (int q = 0; q < 4; ++q)
+        for (int p = 0; p < 4; ++p) G[q * 4 + p] += a[j * N + idx[q]] * conj(b[j * N + idx[p]]);
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * SVD and gate update (Sec. 2.1, Eq. 2: E = X D Y^dagger, u = Y X^dagger).
+ * One-sided Jacobi (Hestenes 1958): rotate pairs of columns of G by 2x2 unitaries until
+ * all columns are mutually orthogonal; then G V = W diag(s).
+ * ---------------------------------------------------------------------------------- */
+void qo_svd4(const qo_cplx Gin[16], qo_cplx W[16], double s[4], qo_cplx V[16]) {
+  qo_cplx g[4][4], v[4][4]; /* [column][row] */
+  for (int c = 0; c < 4; ++c)
+    for (int r = 0; r < 4; ++r) {
+      g[c][r] = Gin[r * 4 + c];
+      v[c][r] = (r == c) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        double alpha = 0.0, beta = 0.0;
+        qo_cplx gamma = 0.0;
+        for (int r = 0; r < 4; ++r) {
+          alpha += creal(g[p][r] * conj(g[p][r]));
+          beta += creal(g[q][r] * conj(g[q][r]));
+          gamma += conj(g[p][r]) * g[q][r];
+        }
+        double ag = cabs(gamma);
+        if (ag == 0.0 || ag <= 1e-15 * sqrt(alpha * beta)) continue;
+        rotated = 1;
+        /* Hermitian 2x2 Gram block [[alpha, gamma], [conj(gamma), beta]] =
+         * D R D^dagger with D = diag(1, e^{-i phi}), R real symmetric; J = D * (real
+         * Jacobi rotation diagonalising R) (Golub & Van Loan, sym.schur2). */
+        qo_cplx e = gamma / ag; /* e^{i phi} */
+        double tau = (beta - alpha) / (2.0 * ag);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t);
+        double sn = c * t;
+        for (int r = 0; r < 4; ++r) {
+          qo_cplx gp = g[p][r], gq = g[q][r];
+          g[p][r] = c * gp - sn * conj(e) * gq;
+          g[q][r] = sn * gp + c * conj(e) * gq;
+          qo_cplx vp = v[p][r], vq = v[q][r];
+          v[p][r] = c * vp - sn * conj(e) * vq;
+          v[q][r] = sn * vp + c * conj(e) * vq;
+        }
+      }
+    if (!rotated) break;
+  }
+  /* Singular values, and left vectors in decreasing-s order re-orthonormalised (and
+   * completed with unit vectors where s is negligible), so that W is unitary. */
+  double nrm[4];
+  int order[4] = {0, 1, 2, 3};
+  for (int c = 0; c < 4; ++c) {
+    double acc = 0.0;
+    for (int r = 0; r < 4; ++r) acc += creal(g[c][r] * conj(g[c][r]));
+    nrm[c] = sqrt(acc);
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b)
+      if (nrm[order[b]] > nrm[order[a]]) {
+        int tmp = order[a]; order[a] = order[b]; order[b] = tmp;
+      }
+  double smax = nrm[order[0]];
+  qo_cplx w[4][4];
+  int filled = 0;
+  for (int k = 0; k < 4; ++k) {
+    int c = order[k];
+    s[k] = nrm[c];
+    for (int r = 0; r < 4; ++r) V[r * 4 + k] = v[c][r];
+    qo_cplx x[4];
+    int ok = 0;
+    if (nrm[c] > 1e-13 * smax && nrm[c] > 0.0) {
+      for (int r = 0; r < 4; ++r) x[r] = g[c][r] / nrm[c];
+      ok = 1;
+    }
+    if (ok) {
+      for (int pass = 0; pass < 2; ++pass)
+        for (int m = 0; m < filled; ++m) {
+          qo_cplx d = 0.0;
+          for (int r = 0; r < 4; ++r) d += conj(w[m][r]) * x[r];
+          for (int r = 0; r < 4; ++r) x[r] -= d * w[m][r];
+        }
+      double l = 0.0;
+      for (int r = 0; r < 4; ++r) l += creal(x[r] * conj(x[r]));
+      l = sqrt(l);
+      if (l > 0.5) {
+        for (int r = 0; r < 4; ++r) x[r] /= l;
+      } else {
+        ok = 0;
+      }
+    }
+    if (!ok) {
+      /* complete with the unit vector that keeps the largest orthogonal part */
+      double best = -1.0;
+      qo_cplx bx[4];
+      for (int e = 0; e < 4; ++e) {
+        qo_cplx y[4] = {0, 0, 0, 0};
+        y[e] = 1.0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int m = 0; m < filled; ++m) {
+            qo_cplx d = 0.0;
+            for (int r = 0; r < 4; ++r) d += conj(w[m][r]) * y[r];
+            for (int r = 0; r < 4; ++r) y[r] -= d * w[m][r];
+          }
+        double l = 0.0;
+        for (int r = 0; r < 4; ++r) l += creal(y[r] * conj(y[r]));
+        if (l > best) {
+          best = l;
+          for (int r = 0; r < 4; ++r) bx[r] = y[r];
+        }
+      }
+      best = sqrt(best);
+      for (int r = 0; r < 4; ++r) x[r] = bx[r] / best;
+    }
+    for (int r = 0; r < 4; ++r) w[filled][r] = x[r];
+    ++filled;
+  }
+  for (int k = 0; k < 4; ++k)
+    for (int r = 0; r < 4; ++r) W[r * 4 + k] = w[k][r];
+}
+
+/* Gate update. The paper's update (Sec. 2.1, Eq. 2; Sec. 3 reuses it) is u = Y X^dagger
+ * with E = X D Y^dagger; with Gamma = E^dagger this is u = W V^dagger for
+ * Gamma = W S V^dagger. App. A's regularised form takes the SVD of (1-beta) E +
+ * beta u^dagger, whose conjugate transpose is (1-beta) Gamma + beta u. */
+void qo_update_gate(const qo_cplx G[16], double beta, qo_cplx u[16]) {
+  qo_cplx X[16], W[16], V[16];
+  double s[4];
+  for (int e = 0; e < 16; ++e) X[e] = (1.0 - beta) * G[e] + beta * u[e];
+  qo_svd4(X, W, s, V);
+  for (int q = 0; q < 4; ++q)
+    for (int p = 0; p < 4; ++p) {
+      qo_cplx acc = 0.0;
+      for (int k = 0; k < 4; ++k) acc += W[q * 4 + k] * conj(V[p * 4 + k]);
+      u[q * 4 + p] = acc;
+    }
+}
+
+/* (1/M) sum_j ||x_j - y_j||^2: the QFactor-Sample cost (Sec. 3, Eq. 9, left side). */
+double qo_state_distance(int n, int M, const qo_cplx *x, const qo_cplx *y) {
+  const int64_t N = (int64_t)1 << n;
+  double acc = 0.0;
+  for (int64_t e = 0; e < (int64_t)M * N; ++e) {
+    qo_cplx d = x[e] - y[e];
+    acc += creal(d * conj(d));
+  }
+  return acc / (double)M;
+}
+
+static double qo_re_tr_gdag_u(const qo_cplx G[16], const qo_cplx u[16]) {
+  double acc = 0.0;
+  for (int e = 0; e < 16; ++e) acc += creal(conj(G[e]) * u[e]);
+  return acc;
+}
+
+/* One sweep (Sec. 3; Fig. pre-comp; Fig. env_calc_tensor). The B list is computed
+ * from the gates as they were before the sweep; the backward state a starts at
+ * U psi (the A tensor) and is moved through each gate right after that gate has been
+ * updated, so every environment mixes updated (left of the gate in time order, i.e.
+ * later in the circuit) and not-yet-updated gates. Returns the cost (Eq. 9) of the
+ * updated gates, computed from a_0 = C^dagger U psi. */
+double qo_sweep(int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
+                const qo_cplx *phi, qo_cplx *gates, double beta, double *f_before,
+                double *f_after, qo_cplx *gammas) {
+  const int64_t N = (int64_t)1 << n;
+  const int64_t S = (int64_t)M * N;
+  qo_cplx *B = (qo_cplx *)malloc(sizeof(qo_cplx) * S * (size_t)L);
+  qo_cplx *a = (qo_cplx *)malloc(sizeof(qo_cplx) * S);
+  memcpy(B, psi, sizeof(qo_cplx) * S);
+  for (int k = 1; k < L; ++k) {
+    memcpy(B + (size_t)k * S, B + (size_t)(k - 1) * S, sizeof(qo_cplx) * S);
+    qo_apply_gate(n, M, B + (size_t)k * S, pairs[2 * (k - 1)], pairs[2 * (k - 1) + 1],
+                  gates + 16 * (k - 1));
+  }
+  memcpy(a, phi, sizeof(qo_cplx) * S);
+  for (int k = L - 1; k >= 0; --k) {
+    qo_cplx G[16];
+    qo_environment(n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
+    if (f_before) f_before[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
+    qo_update_gate(G, beta, gates + 16 * k);
+    if (f_after) f_after[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
+    if (gammas) memcpy(gammas + 16 * k, G, sizeof(G));
+    qo_apply_gate_dag(n, M, a, pairs[2 * k], pairs[2 * k + 1], gates + 16 * k);
+  }
+  double c = qo_state_distance(n, M, a, psi);
+  free(a);
+  free(B);
+  return c;
+}
+
+/* Cost of fixed gates on a state set: (1/M) sum ||U psi - C psi||^2 by simulation. */
+static double qo_forward_cost(int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
+                              const qo_cplx *phi, const qo_cplx *gates) {
+  const int64_t S = (int64_t)M << n;
+  qo_cplx *x = (qo_cplx *)malloc(sizeof(qo_cplx) * S);
+  memcpy(x, psi, sizeof(qo_cplx) * S);
+  qo_apply_circuit(n, M, x, L, pairs, gates);
+  double c = qo_state_distance(n, M, phi, x);
+  free(x);
+  return c;
+}
+
+/* ------------------------------------------------------------------------------------
+ * The control loop (Sec. 3 "on-the-fly" generalisation check and double-and-restart;
+ * the success relations of Eq. 12; App. A plateau test Eq. 13, min_iter, max_iter,
+ * multistarts). Readings where the paper is silent are listed in the design notes:
+ * validation set of size M drawn independently and redrawn on doubling; a doubling
+ * extends the training set and keeps every gate; the iteration and plateau counters
+ * restart after a doubling; at M = 2^n the training cost is the exact full distance
+ * (Eq. 1 over 2^n), so the generalisation test is not applied there.
+ * ---------------------------------------------------------------------------------- */
+enum { ST_RUNNING = 0, ST_STOPPED = 1, ST_OVERTRAINED = 2 };
+
+static double qo_now(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+static void qo_targets(int n, int kind, const qo_cplx *U, int Lt, const int32_t *tpairs,
+                       const qo_cplx *tgates, int M, const qo_cplx *psi, qo_cplx *phi) {
+  const int64_t S = (int64_t)M << n;
+  if (kind == QO_TARGET_DENSE) {
+    qo_dense_apply(n, M, U, psi, phi);
+  } else {
+    memcpy(phi, psi, sizeof(qo_cplx) * S);
+    qo_apply_circuit(n, M, phi, Lt, tpairs, tgates);
+  }
+}
+
+int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind, const qo_cplx *U,
+                   int Lt, const int32_t *tpairs, const qo_cplx *tgates,
+                   const qo_cplx *samples_psi, const qo_cplx *samples_phi, int n_samples,
+                   int n_val, const qo_params *p, const qo_cplx *gates_in,
+                   qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
+  const double t0 = qo_now();
+  if (n < 2 || n > 24 || L < 1 || !p || !gates_out || !res) return -1;
+  for (int k = 0; k < L; ++k) {
+    int a = pairs[2 * k], b = pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= n || b >= n || a == b) return -1;
+  }
+  const int64_t N = (int64_t)1 << n;
+  const int S = p->multistarts > 0 ? p->multistarts : 1;
+  int m_cap = (p->m_max > 0 && p->m_max < N) ? p->m_max : (int)N;
+  int n_train = 0;
+  if (target_kind == QO_TARGET_SAMPLES) {
+    n_train = n_samples - n_val;
+    if (n_train < 1 || n_val < 0) return -1;
+    if (n_train < m_cap) m_cap = n_train;
+  }
+  int M = p->m_init < 1 ? 1 : p->m_init;
+  if (M > m_cap) M = m_cap;
+  if (p->fixed_m) m_cap = M;
+
+  qo_cplx *psi = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)m_cap * N);
+  qo_cplx *phi = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)m_cap * N);
+  qo_cplx *psiv = NULL, *phiv = NULL;
+  int Mv = 0, generation = 0;
+
+  /* training set (A tensor = U Psi, computed once per training set: Fig. pre-comp) */
+  if (target_kind == QO_TARGET_SAMPLES) {
+    memcpy(psi, samples_psi, sizeof(qo_cplx) * (size_t)M * N);
+    memcpy(phi, samples_phi, sizeof(qo_cplx) * (size_t)M * N);
+  } else {
+    if (qo_draw_states(n, M, p->seed, QO_ROLE_TRAIN, 0, psi) != 0) return -2;
+    qo_targets(n, target_kind, U, Lt, tpairs, tgates, M, psi, phi);
+  }
+  /* validation set */
+  if (target_kind == QO_TARGET_SAMPLES) {
+    Mv = n_val;
+    if (Mv > 0) {
+      psiv = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)Mv * N);
+      phiv = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)Mv * N);
+      memcpy(psiv, samples_psi + (size_t)n_train * N, sizeof(qo_cplx) * (size_t)Mv * N);
+      memcpy(phiv, samples_phi + (size_t)n_train * N, sizeof(qo_cplx) * (size_t)Mv * N);
+    }
+  } else {
+    Mv = p->m_val > 0 ? p->m_val : M;
+    psiv = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)Mv * N);
+    phiv = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)Mv * N);
+    if (qo_draw_states(n, Mv, p->seed, QO_ROLE_VAL, (uint32_t)generation, psiv) != 0) return -2;
+    qo_targets(n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
+  }
+
+  qo_cplx *gates = (qo_cplx *)malloc(sizeof(qo_cplx) * 16 * (size_t)L * S);
+  for (int s = 0; s < S; ++s)
+    for (int k = 0; k < L; ++k) {
+      if (gates_in)
+        memcpy(gates + 16 * ((size_t)s * L + k), gates_in + 16 * ((size_t)s * L + k),
+               sizeof(qo_cplx) * 16);
+      else
+        qo_haar_gate(p->seed, (uint32_t)s, (uint32_t)k, gates + 16 * ((size_t)s * L + k));
+    }
+
+  int *status = (int *)calloc(S, sizeof(int));
+  int *reason = (int *)calloc(S, sizeof(int));
+  int *iter = (int *)calloc(S, sizeof(int));
+  int *zcount = (int *)calloc(S, sizeof(int));
+  int64_t *total = (int64_t *)calloc(S, sizeof(int64_t));
+  double *c_prev = (double *)calloc(S, sizeof(double));
+  double *c_tr = (double *)calloc(S, sizeof(double));
+  double *c_v = (double *)calloc(S, sizeof(double));
+  int *success = (int *)calloc(S, sizeof(int));
+
+#pragma omp parallel for schedule(dynamic)
+  for (int s = 0; s < S; ++s) {
+    c_prev[s] = qo_forward_cost(n, L, pairs, M, psi, phi, gates + 16 * (size_t)s * L);
+    c_tr[s] = c_prev[s];
+    c_v[s] = Mv > 0 ? qo_forward_cost(n, L, pairs, Mv, psiv, phiv, gates + 16 * (size_t)s * L)
+                    : c_tr[s];
+  }
+
+  int restarts = 0, m_total = M, chosen = -1;
+  for (;;) {
+#pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < S; ++s) {
+      if (status[s] != ST_RUNNING) continue;
+      qo_cplx *g = gates + 16 * (size_t)s * L;
+      c_tr[s] = qo_sweep(n, L, pairs, M, psi, phi, g, p->beta, NULL, NULL, NULL);
+      c_v[s] = Mv > 0 ? qo_forward_cost(n, L, pairs, Mv, psiv, phiv, g) : c_tr[s];
+    }
+    const int full = (M == (int)N);
+    int any_success = 0, any_over = 0, any_running = 0;
+    for (int s = 0; s < S; ++s) {
+      if (status[s] != ST_RUNNING) continue;
+      iter[s] += 1;
+      total[s] += 1;
+      if (trace && trace->count < trace->capacity) {
+        int t = trace->count++;
+        trace->start[t] = s;
+        trace->sweep[t] = (int32_t)total[s];
+        trace->m[t] = M;
+        trace->c_train[t] = c_tr[s];
+        trace->c_val[t] = c_v[s];
+      }
+      /* App. A, Eq. 13: relative improvement test over consecutive iterations. */
+      int improved = fabs(c_prev[s]) - fabs(c_tr[s]) > p->diff_tol_r * fabs(c_tr[s]);
+      zcount[s] = improved ? 0 : zcount[s] + 1;
+      c_prev[s] = c_tr[s];
+      /* Sec. 3, success relations: c_train < dist_tol and c_val / c_train <= 1 + otr. */
+      int gen_ok = full || Mv == 0 || c_v[s] <= (1.0 + p->overtrain_ratio) * c_tr[s];
+      if (c_tr[s] < p->dist_tol && gen_ok) {
+        status[s] = ST_STOPPED;
+        reason[s] = QO_SUCCESS;
+        success[s] = 1;
+        any_success = 1;
+        continue;
+      }
+      if (iter[s] >= p->min_iter && !gen_ok) {
+        if (M < m_cap) {
+          status[s] = ST_OVERTRAINED;
+          any_over = 1;
+          continue;
+        }
+        if (c_tr[s] < p->dist_tol) {
+          status[s] = ST_STOPPED;
+          reason[s] = QO_NOT_GENERALIZED;
+          continue;
+        }
+      }
+      if (iter[s] >= p->min_iter && zcount[s] >= p->plateau_window) {
+        status[s] = ST_STOPPED;
+        reason[s] = QO_PLATEAU;
+        continue;
+      }
+      if (total[s] >= p->max_iter) {
+        status[s] = ST_STOPPED;
+        reason[s] = QO_MAX_ITER;
+        continue;
+      }
+    }
+    if (any_success) {
+      double best = INFINITY;
+      for (int s = 0; s < S; ++s)
+        if (success[s] && c_tr[s] < best) {
+          best = c_tr[s];
+          chosen = s;
+        }
+      break;
+    }
+    if (any_over) {
+      /* double-and-restart: extend the training set, keep every gate (App. A) */
+      int M_new = 2 * M < m_cap ? 2 * M : m_cap;
+      if (target_kind == QO_TARGET_SAMPLES) {
+        memcpy(psi, samples_psi, sizeof(qo_cplx) * (size_t)M_new * N);
+        memcpy(phi, samples_phi, sizeof(qo_cplx) * (size_t)M_new * N);
+      } else {
+        if (qo_extend_states(n, M, M_new, p->seed, psi) != 0) return -2;
+        qo_targets(n, target_kind, U, Lt, tpairs, tgates, M_new - M, psi + (size_t)M * N,
+                   phi + (size_t)M * N);
+        ++generation;
+        Mv = p->m_val > 0 ? p->m_val : M_new;
+        psiv = (qo_cplx *)realloc(psiv, sizeof(qo_cplx) * (size_t)Mv * N);
+        phiv = (qo_cplx *)realloc(phiv, sizeof(qo_cplx) * (size_t)Mv * N);
+        if (qo_draw_states(n, Mv, p->seed, QO_ROLE_VAL, (uint32_t)generation, psiv) != 0)
+          return -2;
+        qo_targets(n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
+      }
+      M = M_new;
+      m_total += M;
+      ++restarts;
+#pragma omp parallel for schedule(dynamic)
+      for (int s = 0; s < S; ++s) {
+        if (status[s] == ST_STOPPED) continue;
+        status[s] = ST_RUNNING;
+        iter[s] = 0;
+        zcount[s] = 0;
+        c_prev[s] = qo_forward_cost(n, L, pairs, M, psi, phi, gates + 16 * (size_t)s * L);
+      }
+      continue;
+    }
+    for (int s = 0; s < S; ++s)
+      if (status[s] == ST_RUNNING) any_running = 1;
+    if (!any_running) {
+      double best = INFINITY;
+      for (int s = 0; s < S; ++s)
+        if (c_tr[s] < best) {
+          best = c_tr[s];
+          chosen = s;
+        }
+      break;
+    }
+  }
+
+  memcpy(gates_out, gates + 16 * (size_t)chosen * L, sizeof(qo_cplx) * 16 * (size_t)L);
+  res->reason = reason[chosen];
+  res->m_final = M;
+  res->sweeps = (int32_t)total[chosen];
+  res->restarts = restarts;
+  res->best_start = chosen;
+  res->m_total = m_total;
+  res->c_train = c_tr[chosen];
+  res->c_val = c_v[chosen];
+  res->seconds = qo_now() - t0;
+
+  free(status); free(reason); free(iter); free(zcount); free(total);
+  free(c_prev); free(c_tr); free(c_v); free(success);
+  free(gates); free(psi); free(phi); free(psiv); free(phiv);
+  return 0;
+}

@@ -1,0 +1,132 @@
+/*
+ * qfs_oracle.h -- FP64 CPU oracle of QFactor-Sample instantiation
+ * (Kukliansky et al., "Leveraging Quantum Machine Learning Generalization to
+ * Significantly Speed-up Quantum Compilation", arXiv 2405.12866).
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow, obviously-correct reference used
+ * by the test-suite, the smoke check and the CPU-baseline leg of the benchmark. It
+ * shares no code, header, table or helper with the HIP implementation, and the
+ * product path never loads it.
+ *
+ * Conventions (the paper fixes none of them; chosen once and pinned by the dense
+ * brute-force tests):
+ *   - n qubits, N = 2^n amplitudes. Qubit 0 is the MOST significant bit of the
+ *     amplitude index (textbook Kronecker order): bit position of qubit q is n-1-q.
+ *   - A two-qubit gate acts on the ordered pair (qa, qb), qa != qb. Its 4x4 matrix
+ *     u[q][p] is row-major, q = output local index, p = input local index, and the
+ *     local index of an amplitude is 2*bit(qa) + bit(qb).
+ *   - Gates are applied in list order: C = u_{L-1} ... u_1 u_0.
+ *   - A state set is [M][N] complex128 (sample-major, each state contiguous).
+ *   - Environment Gamma_k[q][p] = sum_j sum_r a_j(q,r) conj(B_j(p,r)); the paper's
+ *     environment E (Sec. 3, Eq. 10 and Sec. 2.1, Eq. 2) is Gamma^dagger, so the
+ *     update u = Y X^dagger with E = X D Y^dagger is u = W V^dagger with
+ *     Gamma = W S V^dagger, i.e. the unitary polar factor of Gamma.
+ */
+#ifndef QFS_ORACLE_H
+#define QFS_ORACLE_H
+
+#include <complex.h>
+#include <stdint.h>
+
+typedef double _Complex qo_cplx;
+
+/* Random-number roles (counter word 2 of Philox). */
+enum { QO_ROLE_TRAIN = 1, QO_ROLE_VAL = 2, QO_ROLE_INIT = 3 };
+
+/* Target kinds. */
+enum { QO_TARGET_DENSE = 0, QO_TARGET_CIRCUIT = 1, QO_TARGET_SAMPLES = 2 };
+
+/* Termination reasons (the paper's termination kinds, Sec. 4 per-run runtimes). */
+enum {
+  QO_SUCCESS = 0,
+  QO_PLATEAU = 1,
+  QO_MAX_ITER = 2,
+  QO_NOT_GENERALIZED = 3,
+  QO_TIMEOUT = 4
+};
+
+typedef struct {
+  double dist_tol;        /* App. A: dist_tol                                  */
+  double diff_tol_r;      /* App. A: diff_tol_r (plateau relative improvement) */
+  int32_t plateau_window; /* App. A: plateau_windows_size                      */
+  int32_t min_iter;       /* App. A: min_iter                                  */
+  int64_t max_iter;       /* App. A: max_iter (total sweeps per start)         */
+  int32_t m_init;         /* App. A: number_of_training_states                 */
+  int32_t m_max;          /* cap on M; 0 means 2^n (Sec. 3)                    */
+  double overtrain_ratio; /* App. A: overtrain_ratio                           */
+  int32_t multistarts;    /* App. A: multistarts                               */
+  double beta;            /* App. A: Beta (regularised update)                 */
+  uint64_t seed;          /* App. A: seed                                      */
+  int32_t fixed_m;        /* 1: never double M                                 */
+  int32_t m_val;          /* validation-set size; 0 means M                    */
+} qo_params;
+
+typedef struct {
+  int32_t reason;
+  int32_t m_final;
+  int32_t sweeps;     /* sweeps of the returned start                          */
+  int32_t restarts;   /* number of doublings                                   */
+  int32_t best_start;
+  int32_t m_total;    /* sum of the M values used, one entry per training set  */
+  double c_train;
+  double c_val;
+  double seconds;
+} qo_result;
+
+/* Optional per-sweep trace: one row per (start, sweep). */
+typedef struct {
+  int32_t capacity;
+  int32_t count;
+  int32_t *start;     /* [capacity] */
+  int32_t *sweep;     /* [capacity] total sweep index of that start (1-based) */
+  int32_t *m;         /* [capacity] */
+  double *c_train;    /* [capacity] */
+  double *c_val;      /* [capacity] */
+} qo_trace;
+
+/* Counter-based generator Philox4x32-10 (Salmon et al., SC'11). */
+void qo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Standard complex normal (E|z|^2 = 1) for (seed, role, stream, index). */
+qo_cplx qo_cgauss(uint64_t seed, uint32_t role, uint32_t stream, uint64_t idx);
+/* Complex Ginibre matrix, column-major rows x cols: entry (i, j) uses index j*rows+i. */
+void qo_ginibre(int64_t rows, int64_t cols, uint64_t seed, uint32_t role, uint32_t stream,
+                qo_cplx *out /* [cols][rows] */);
+/* Q of the QR factorisation with real positive diag(R) (Mezzadri 2007), in place on
+ * column-major columns; returns 0, or -1 if a column is numerically dependent. */
+int qo_orthonormalize(int64_t rows, int64_t cols, qo_cplx *cols_inout);
+/* Training / validation sample states: first M columns of a Haar unitary (Sec. 3,
+ * App. A). Training columns come from one fixed Ginibre stream so that the set for
+ * 2M extends the set for M. Validation uses stream `generation`. */
+int qo_draw_states(int n, int M, uint64_t seed, uint32_t role, uint32_t stream,
+                   qo_cplx *out /* [M][N] */);
+/* Haar-random 4x4 initial gate (App. A, multistarts and seed). */
+void qo_haar_gate(uint64_t seed, uint32_t start, uint32_t gate, qo_cplx u[16]);
+
+void qo_apply_gate(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16]);
+void qo_apply_gate_dag(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16]);
+void qo_apply_circuit(int n, int M, qo_cplx *st, int L, const int32_t *pairs,
+                      const qo_cplx *gates);
+void qo_dense_apply(int n, int M, const qo_cplx *U /*[N][N] row-major*/,
+                    const qo_cplx *psi, qo_cplx *out);
+void qo_environment(int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, int qb,
+                    qo_cplx G[16]);
+/* 4x4 complex SVD G = W diag(s) V^dagger by one-sided (Hestenes) Jacobi. */
+void qo_svd4(const qo_cplx G[16], qo_cplx W[16], double s[4], qo_cplx V[16]);
+/* Update of one gate: u <- polar((1-beta) Gamma + beta u). */
+void qo_update_gate(const qo_cplx G[16], double beta, qo_cplx u[16]);
+double qo_state_distance(int n, int M, const qo_cplx *x, const qo_cplx *y);
+
+/* One sweep (forward B list, right-to-left update). Returns c_train after the sweep.
+ * Optional outputs: per gate f before/after its update, and each Gamma. */
+double qo_sweep(int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
+                const qo_cplx *phi, qo_cplx *gates, double beta, double *f_before,
+                double *f_after, qo_cplx *gammas);
+
+/* Full instantiation with the paper's control loop. */
+int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind,
+                   const qo_cplx *U, int Lt, const int32_t *tpairs, const qo_cplx *tgates,
+                   const qo_cplx *samples_psi, const qo_cplx *samples_phi, int n_samples,
+                   int n_val, const qo_params *p, const qo_cplx *gates_in,
+                   qo_cplx *gates_out, qo_result *res, qo_trace *trace);
+
+#endif

@@ -1,0 +1,156 @@
+"""Seeded synthetic problem generators, shared by the tests, the benchmark and the
+smoke check.
+
+This module only builds problem *inputs* (circuit templates, target gates, fixed
+sample sets for lock-step comparisons). It holds none of the instantiation method's
+arithmetic: the states and initial gates that the method itself draws are drawn by
+each implementation from its own counter-based generator.
+
+The paper's workloads are partitions of real circuits (U3 + CNOT, 3-12 qubits); they
+are not available here, so seeded synthetic circuits of the same sizes stand in:
+brickwork and random-pair templates of general two-qubit gates, with targets built
+from the same template with Haar-random gates, so that an exact solution exists.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 finaliser (Steele, Lea, Flood 2014): seed derivation only."""
+    x = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = x
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+ROLE_TARGET, ROLE_TRAIN, ROLE_VAL, ROLE_INIT = 0x7A, 0x7B, 0x7C, 0x7D
+
+
+def derive_seed(base: int, problem: int = 0, role: int = ROLE_TARGET, start: int = 0) -> int:
+    """seed = SplitMix64(base ^ problem ^ role ^ start), each field in its own bits."""
+    return splitmix64((base ^ (problem << 20) ^ (role << 52) ^ (start << 40)) & MASK64)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def linear_template(n: int, repeats: int):
+    """Pairs (0,1),(1,2),...,(n-2,n-1) repeated: the 3-qubit workload of 6 gates is
+    linear_template(3, 3)."""
+    pairs = []
+    for _ in range(repeats):
+        for q in range(n - 1):
+            pairs.append((q, q + 1))
+    return np.asarray(pairs, dtype=np.int32)
+
+
+def brickwork_template(n: int, sublayers: int):
+    """Alternating sublayers of nearest-neighbour gates, even pairs (0,1),(2,3),...
+    then odd pairs (1,2),(3,4),... . 8 qubits x 6 sublayers = 21 gates; 12 qubits x 8
+    sublayers = 44 gates."""
+    pairs = []
+    for s in range(sublayers):
+        first = 0 if s % 2 == 0 else 1
+        for q in range(first, n - 1, 2):
+            pairs.append((q, q + 1))
+    return np.asarray(pairs, dtype=np.int32)
+
+
+def random_pair_template(n: int, L: int, g: np.random.Generator):
+    """L gates on pairs drawn uniformly from the distinct unordered pairs, as (lo, hi)."""
+    pairs = []
+    for _ in range(L):
+        a, b = g.choice(n, size=2, replace=False)
+        pairs.append((min(a, b), max(a, b)))
+    return np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+
+
+def haar_unitary(d: int, g: np.random.Generator):
+    """Haar-random d x d unitary for target construction (numpy QR of a complex
+    Ginibre matrix with the phases of diag(R) divided out)."""
+    z = (g.standard_normal((d, d)) + 1j * g.standard_normal((d, d))) / np.sqrt(2.0)
+    q, r = np.linalg.qr(z)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return q * ph[None, :]
+
+
+def haar_gates(L: int, g: np.random.Generator):
+    return np.stack([haar_unitary(4, g) for _ in range(L)]) if L else np.zeros((0, 4, 4), complex)
+
+
+def orthonormal_samples(n: int, M: int, g: np.random.Generator):
+    """M orthonormal states of 2^n amplitudes, [M][N], for fixed-sample comparisons."""
+    N = 1 << n
+    z = (g.standard_normal((N, M)) + 1j * g.standard_normal((N, M))) / np.sqrt(2.0)
+    q, _ = np.linalg.qr(z)
+    return np.ascontiguousarray(q.T)
+
+
+def circuit_unitary_columns(n: int, pairs, gates, states):
+    """Apply a gate list to [M][N] states by explicit 2^n x 2^n Kronecker embedding.
+    Input construction only (used to build fixed target samples); O(4^n) per gate."""
+    N = 1 << n
+    out = np.array(states, dtype=np.complex128, copy=True)
+    for (a, b), u in zip(np.asarray(pairs).reshape(-1, 2), gates):
+        full = embed_two_qubit(n, int(a), int(b), u)
+        out = out @ full.T
+    return out
+
+
+def embed_two_qubit(n: int, a: int, b: int, u):
+    """2^n x 2^n matrix of a 4x4 gate on ordered qubits (a, b), qubit 0 most significant."""
+    N = 1 << n
+    full = np.zeros((N, N), dtype=np.complex128)
+    pa, pb = n - 1 - a, n - 1 - b
+    for col in range(N):
+        p = 2 * ((col >> pa) & 1) + ((col >> pb) & 1)
+        base = col & ~((1 << pa) | (1 << pb))
+        for q in range(4):
+            row = base | (((q >> 1) & 1) << pa) | ((q & 1) << pb)
+            full[row, col] += u[q, p]
+    return full
+
+
+# ----------------------------------------------------------------------------------
+# Named workloads (sizes of the paper's partitions; synthetic content).
+# ----------------------------------------------------------------------------------
+def workload_3q(seed_base: int = 0x5A17 + 1):
+    """3 qubits, pairs (0,1),(1,2) x 3 (L = 6); target = same template, Haar gates."""
+    g = rng(derive_seed(seed_base, 0, ROLE_TARGET))
+    pairs = linear_template(3, 3)
+    return dict(n=3, pairs=pairs, target_pairs=pairs, target_gates=haar_gates(len(pairs), g))
+
+
+def workload_brickwork(n: int, sublayers: int, seed_base: int, problem: int = 0):
+    g = rng(derive_seed(seed_base, problem, ROLE_TARGET))
+    pairs = brickwork_template(n, sublayers)
+    return dict(n=n, pairs=pairs, target_pairs=pairs, target_gates=haar_gates(len(pairs), g))
+
+
+def workload_8q(seed_base: int = 0x5A17 + 2):
+    """8-qubit brickwork, 6 sublayers (21 gates)."""
+    return workload_brickwork(8, 6, seed_base)
+
+
+def workload_12q(seed_base: int = 0x5A17 + 3):
+    """12-qubit brickwork, 8 sublayers (44 gates)."""
+    return workload_brickwork(12, 8, seed_base)
+
+
+def batched_problems(count: int, seed_base: int = 0x5A17 + 4, n_range=(3, 7), L_range=(2, 20)):
+    """Uneven problem set: n ~ U{3..7}, L ~ U{2..20}, random distinct pairs, target =
+    the template with Haar gates."""
+    probs = []
+    for pid in range(count):
+        g = rng(derive_seed(seed_base, pid, ROLE_TARGET))
+        n = int(g.integers(n_range[0], n_range[1] + 1))
+        L = int(g.integers(L_range[0], L_range[1] + 1))
+        pairs = random_pair_template(n, L, g)
+        probs.append(dict(n=n, pairs=pairs, target_pairs=pairs, target_gates=haar_gates(L, g),
+                          seed=derive_seed(seed_base, pid, ROLE_INIT)))
+    return probs

@@ -1,0 +1,384 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test names the passage or the mathematical fact it relies on. None of them
+re-types the oracle's own formula: the checks go through the dense brute-force
+checker (tensor reshapes, full 2^n x 2^n matrices), library routines (LAPACK SVD,
+SciPy polar), closed forms, known-answer vectors and invariants.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+from brute import dense as D
+from paper_2405_12866_amd import inputs as I
+
+
+def _rand_c(g, *shape):
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- random numbers
+def test_philox_known_answers():
+    """Philox4x32-10 known-answer vectors published with Random123 (Salmon et al.,
+    SC'11): zero counter/key, all-ones, and the digits of pi."""
+    assert [hex(x) for x in O.philox4x32_10([0, 0, 0, 0], [0, 0])] == [
+        "0x6627e8d5", "0xe169c58d", "0xbc57ac4c", "0x9b00dbd8"]
+    assert [hex(x) for x in O.philox4x32_10([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2)] == [
+        "0x408f276d", "0x41c83b0e", "0xa20bc7c6", "0x6d5451fd"]
+    assert [hex(x) for x in O.philox4x32_10(
+        [0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0])] == [
+        "0xd16cfe09", "0x94fdcceb", "0x5001e420", "0x24126ea1"]
+
+
+def test_complex_gaussian_distribution():
+    """A standard complex normal: |z|^2 ~ Exp(1), arg z uniform, E z = E z^2 = 0."""
+    import scipy.stats as st
+    z = O.ginibre(4096, 8, seed=123, role=O.ROLE_TRAIN, stream=0).ravel()
+    assert abs(np.mean(z)) < 4 / np.sqrt(z.size)
+    assert abs(np.mean(z * z)) < 4 / np.sqrt(z.size)
+    assert st.kstest(np.abs(z) ** 2, "expon").pvalue > 1e-3
+    assert st.kstest((np.angle(z) + np.pi) / (2 * np.pi), "uniform").pvalue > 1e-3
+
+
+def test_states_are_qr_of_ginibre_with_positive_diagonal():
+    """Sec. 3 / App. A: training states are columns of a Haar unitary. Mezzadri's
+    construction: Q of the QR factorisation of a Ginibre matrix with diag(R) > 0,
+    which is unique. Check Q^dag Q = I and that R = Q^dag G is upper triangular with
+    a real positive diagonal."""
+    n, M = 5, 12
+    G = O.ginibre(1 << n, M, seed=9, role=O.ROLE_TRAIN, stream=0)  # [M][N] columns
+    Q = O.draw_states(n, M, seed=9)
+    assert np.allclose(Q.conj() @ Q.T, np.eye(M), atol=1e-14)
+    R = Q.conj() @ G.T  # R[i][j] = <q_i, g_j>
+    assert np.max(np.abs(np.tril(R, -1))) < 1e-13
+    d = np.diag(R)
+    assert np.all(d.real > 0) and np.max(np.abs(d.imag)) < 1e-13
+    # and it reconstructs G
+    assert np.allclose(Q.T @ R, G.T, atol=1e-12)
+
+
+def test_states_nested_under_doubling():
+    """The set for 2M extends the set for M (doubling keeps the old states)."""
+    a = O.draw_states(4, 4, seed=5)
+    b = O.draw_states(4, 8, seed=5)
+    assert np.array_equal(a, b[:4])
+
+
+def test_haar_gate_moments():
+    """Haar measure on U(d): E|Tr U|^2 = 1 and E|Tr U|^4 = 2 (d >= 2), E|U_ij|^2 = 1/d.
+    Without Mezzadri's phase correction the trace moments come out wrong."""
+    us = np.stack([O.haar_gate(77, s, k) for s in range(64) for k in range(64)])
+    assert np.allclose(np.einsum("kij,kil->kjl", us.conj(), us), np.eye(4), atol=1e-14)
+    tr = np.einsum("kii->k", us)
+    K = len(us)
+    assert abs(np.mean(np.abs(tr) ** 2) - 1.0) < 5 * np.sqrt(1.0 / K)
+    assert abs(np.mean(np.abs(tr) ** 4) - 2.0) < 5 * np.sqrt(24.0 / K)
+    assert abs(np.mean(np.abs(us) ** 2) - 0.25) < 0.01
+
+
+# ------------------------------------------------------------ state simulation
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_apply_gate_matches_tensor_brute_force(n):
+    g = np.random.default_rng(1)
+    st = _rand_c(g, 3, 1 << n)
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            u = I.haar_unitary(4, g)
+            assert np.allclose(O.apply_gate(n, st, a, b, u), D.apply_gate_tensor(n, st, a, b, u),
+                               atol=1e-13)
+            assert np.allclose(O.apply_gate(n, st, a, b, u, dagger=True),
+                               D.apply_gate_tensor(n, st, a, b, u.conj().T), atol=1e-13)
+
+
+def test_big_endian_convention():
+    """Qubit 0 is the most significant bit: a gate flipping the second qubit of the
+    pair on qubits (0, 1) of 3 qubits maps |000> to |010> (index 2)."""
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    u = np.kron(np.eye(2), X)
+    e0 = np.zeros((1, 8), dtype=complex)
+    e0[0, 0] = 1
+    out = O.apply_gate(3, e0, 0, 1, u)
+    assert out[0, 2] == 1 and np.sum(np.abs(out)) == 1
+
+
+def test_dense_and_circuit_targets_agree():
+    w = I.workload_3q()
+    U = D.circuit_matrix(3, w["target_pairs"], w["target_gates"])
+    psi = O.draw_states(3, 5, seed=3)
+    a = O.dense_apply(3, U, psi)
+    b = O.apply_circuit(3, psi, w["target_pairs"], w["target_gates"])
+    assert np.allclose(a, b, atol=1e-13)
+
+
+# ----------------------------------------------------------------- environment
+@pytest.mark.parametrize("n,M", [(3, 2), (4, 5), (5, 3)])
+def test_environment_linear_functional(n, M):
+    """Pin P4 (Sec. 3, Eq. 10): with gate k replaced by an ARBITRARY complex 4x4 X,
+    Re sum_j <U psi_j | C_X psi_j> = Re Tr(Gamma_k^dag X), by dense brute force."""
+    g = np.random.default_rng(n * 10 + M)
+    pairs = I.random_pair_template(n, 5, g)
+    gates = I.haar_gates(5, g)
+    U = I.haar_unitary(1 << n, g)
+    psi = I.orthonormal_samples(n, M, g)
+    phi = psi @ U.T
+    for k in range(5):
+        B = O.apply_circuit(n, psi, pairs[:k], gates[:k])
+        a = phi.copy()
+        for j in range(4, k, -1):
+            a = O.apply_gate(n, a, pairs[j][0], pairs[j][1], gates[j], dagger=True)
+        G = O.environment(n, a, B, pairs[k][0], pairs[k][1])
+        X = _rand_c(g, 4, 4)
+        gx = gates.copy()
+        gx[k] = X
+        C = D.circuit_matrix(n, pairs, gx)
+        f_dense = np.real(np.trace(psi.conj() @ U.conj().T @ C @ psi.T))
+        assert abs(f_dense - np.real(np.sum(G.conj() * X))) < 1e-12 * (1 + abs(f_dense))
+
+
+def test_environment_permutation_invariance():
+    """Pin P14: permuting the samples leaves Gamma unchanged (up to rounding)."""
+    g = np.random.default_rng(4)
+    a, b = _rand_c(g, 6, 32), _rand_c(g, 6, 32)
+    G1 = O.environment(5, a, b, 1, 3)
+    perm = g.permutation(6)
+    G2 = O.environment(5, a[perm], b[perm], 1, 3)
+    assert np.allclose(G1, G2, atol=1e-12)
+
+
+# ----------------------------------------------------------------- SVD / update
+def _check_svd(G):
+    W, s, V = O.svd4(G)
+    assert np.allclose(W.conj().T @ W, np.eye(4), atol=1e-13)
+    assert np.allclose(V.conj().T @ V, np.eye(4), atol=1e-13)
+    assert np.allclose(W @ np.diag(s) @ V.conj().T, G, atol=1e-12 * max(1.0, np.abs(G).max()))
+    assert np.allclose(s, np.linalg.svd(G, compute_uv=False), atol=1e-12 * max(1.0, s.max()))
+
+
+def test_svd4_against_lapack_random():
+    g = np.random.default_rng(5)
+    for _ in range(200):
+        _check_svd(_rand_c(g, 4, 4) * 10 ** g.uniform(-3, 3))
+
+
+def test_svd4_rank_deficient_and_degenerate():
+    g = np.random.default_rng(6)
+    cases = [np.zeros((4, 4), complex), np.eye(4, dtype=complex),
+             np.outer(_rand_c(g, 4), _rand_c(g, 4).conj()),
+             _rand_c(g, 4, 2) @ _rand_c(g, 2, 4), np.diag([3, 3, 1, 0]).astype(complex),
+             I.haar_unitary(4, g) * 2.5]
+    for G in cases:
+        _check_svd(G)
+        u = O.update_gate(G)
+        assert np.allclose(u.conj().T @ u, np.eye(4), atol=1e-13)
+        assert abs(np.real(np.sum(G.conj() * u)) - np.linalg.svd(G, compute_uv=False).sum()) < 1e-12 * (
+            1 + np.abs(G).max())
+
+
+def test_update_is_polar_factor():
+    """Sec. 2.1, Eq. 2 with E = Gamma^dag: the update is the unitary polar factor of
+    Gamma (SciPy's polar decomposition, Gamma = u P)."""
+    g = np.random.default_rng(7)
+    for _ in range(50):
+        G = _rand_c(g, 4, 4)
+        up, _ = scipy.linalg.polar(G, side="right")
+        assert np.allclose(O.update_gate(G), up, atol=1e-12)
+
+
+def test_update_is_optimal():
+    """Pin P3 (Sec. 3 via QFactor's optimality proof; von Neumann's trace inequality):
+    Re Tr(Gamma^dag u_new) = sum of singular values >= Re Tr(Gamma^dag V) for any
+    unitary V."""
+    g = np.random.default_rng(8)
+    G = _rand_c(g, 4, 4)
+    u = O.update_gate(G)
+    best = np.real(np.sum(G.conj() * u))
+    assert abs(best - np.linalg.svd(G, compute_uv=False).sum()) < 1e-12
+    Vs = [I.haar_unitary(4, g) for _ in range(10000)]
+    vals = np.array([np.real(np.sum(G.conj() * V)) for V in Vs])
+    assert np.all(vals <= best + 1e-12)
+
+
+def test_beta_one_keeps_gate():
+    """Pin P9 (App. A, Beta): beta = 1 results in no update."""
+    g = np.random.default_rng(9)
+    u0 = I.haar_unitary(4, g)
+    assert np.allclose(O.update_gate(_rand_c(g, 4, 4), beta=1.0, u=u0), u0, atol=1e-13)
+
+
+# ----------------------------------------------------------------------- sweeps
+def _problem(n, L, M, seed, full_basis=False):
+    g = np.random.default_rng(seed)
+    pairs = I.random_pair_template(n, L, g)
+    tg = I.haar_gates(L, g)
+    U = D.circuit_matrix(n, pairs, tg)
+    psi = I.orthonormal_samples(n, (1 << n) if full_basis else M, g)
+    phi = psi @ U.T
+    gates = I.haar_gates(L, g)
+    return pairs, U, psi, phi, gates
+
+
+def test_cost_forms_and_full_basis_reduction():
+    """Pins P1 and P2 (Sec. 2.1 Eq. 1; Sec. 3 Eq. 9): (1/M) sum ||U psi - C psi||^2 =
+    2 - (2/M) Re sum <psi|U^dag C|psi>, and with a full basis (M = 2^n) times 2^n it is
+    ||U - C||_F^2."""
+    n = 4
+    pairs, U, psi, phi, gates = _problem(n, 6, 16, 11, full_basis=True)
+    C = D.circuit_matrix(n, pairs, gates)
+    Cpsi = O.apply_circuit(n, psi, pairs, gates)
+    c = O.state_distance(n, phi, Cpsi)
+    M = psi.shape[0]
+    assert abs(c - (2 - 2 / M * np.real(np.sum(phi.conj() * Cpsi)))) < 1e-13
+    assert abs(c * (1 << n) - np.linalg.norm(U - C) ** 2) < 1e-11
+
+
+def test_sweep_monotone_unitary_and_end_cost():
+    """Pins P5, P6, P10: within a sweep f never decreases (block-coordinate ascent,
+    Sec. 3: same update as QFactor); f before gate k's update equals f after gate
+    k+1's; gates stay unitary; and at beta = 0 the cost after the sweep equals
+    2 - (2/M) * (sum of singular values of the last environment)."""
+    n, L, M = 5, 9, 6
+    pairs, U, psi, phi, gates = _problem(n, L, M, 12)
+    for _ in range(6):
+        new, c, fb, fa, gam = O.sweep(n, pairs, psi, phi, gates, record=True)
+        assert np.all(fa >= fb - 1e-12 * M)
+        assert np.allclose(fb[:-1], fa[1:], atol=1e-12 * M)
+        for u in new:
+            assert np.max(np.abs(u.conj().T @ u - np.eye(4))) < 1e-12
+        s0 = np.linalg.svd(gam[0], compute_uv=False).sum()
+        assert abs(c - (2 - 2 * s0 / M)) < 1e-12
+        C = O.apply_circuit(n, psi, pairs, new)
+        assert abs(c - O.state_distance(n, phi, C)) < 1e-12
+        gates = new
+
+
+def test_two_qubit_single_gate_recovers_target():
+    """Pin P7: n = 2, L = 1, M = 4 (full basis): Gamma = U, so one sweep returns U."""
+    g = np.random.default_rng(13)
+    U = I.haar_unitary(4, g)
+    psi = I.orthonormal_samples(2, 4, g)
+    new, c = O.sweep(2, [(0, 1)], psi, psi @ U.T, I.haar_gates(1, g))
+    assert np.allclose(new[0], U, atol=1e-13)
+    assert c < 1e-26 + 1e-28
+
+
+def test_full_basis_reproduces_dense_qfactor_trajectory():
+    """Pin P8: with M = 2^n and any orthonormal basis, QFactor-Sample's sweep is the
+    full-unitary QFactor sweep (Sec. 3: same basic step; the environment depends on
+    the samples only through sum_j psi_j psi_j^dag = I)."""
+    n, L = 4, 7
+    pairs, U, psi, phi, gates = _problem(n, L, 0, 14, full_basis=True)
+    g_s, g_d = gates.copy(), gates.copy()
+    for _ in range(5):
+        g_s, _ = O.sweep(n, pairs, psi, phi, g_s)
+        g_d = D.dense_qfactor_sweep(n, pairs, g_d, U)
+        assert np.allclose(g_s, g_d, atol=1e-12)
+
+
+def test_validation_estimator_converges_to_full_distance():
+    """Pin P11 (Sec. 3 on-the-fly generalisation estimate): for fixed gates the mean
+    loss over K Haar states is an unbiased estimate of ||U - C||_F^2 / 2^n, because
+    E[|psi><psi|] = I / 2^n; checked within 5 standard errors."""
+    n, L = 5, 6
+    pairs, U, _, _, gates = _problem(n, L, 1, 15)
+    C = D.circuit_matrix(n, pairs, gates)
+    d_full = D.full_distance(U, C)
+    losses = []
+    for stream in range(40):
+        psi = O.draw_states(n, 8, seed=99, role=O.ROLE_VAL, stream=stream)
+        for s in psi:
+            losses.append(np.linalg.norm((U - C) @ s) ** 2)
+    losses = np.array(losses)
+    se = losses.std() / np.sqrt(len(losses))
+    assert abs(losses.mean() - d_full) < 5 * se + 1e-12
+
+
+# ------------------------------------------------------------------ control loop
+RECOVERY_TEMPLATES = [
+    [(0, 1), (1, 2), (0, 1), (1, 2)],
+    [(0, 1), (1, 2), (0, 2), (0, 1)],
+    [(1, 2), (0, 1), (1, 2)],
+]
+
+
+@pytest.mark.parametrize("pairs", RECOVERY_TEMPLATES)
+def test_recovery_three_qubits(pairs):
+    """Pin P12: a target built from the template is recovered (d_full from the dense
+    8x8 product below 1e-10) by the best of 16 starts, with the on-the-fly doubling
+    from M = 2. (The 6-gate linear template converges too, but its last decades take
+    thousands of sweeps; it is exercised by the GPU parity tests instead.)"""
+    g = np.random.default_rng(5)
+    tg = I.haar_gates(len(pairs), g)
+    p = O.default_params(dist_tol=1e-11, multistarts=16, seed=3, max_iter=3000, diff_tol_r=1e-7)
+    gates, info = O.instantiate(3, pairs, target_pairs=pairs, target_gates=tg, params=p)
+    U = D.circuit_matrix(3, pairs, tg)
+    C = D.circuit_matrix(3, pairs, gates)
+    assert info["reason_name"] == "SUCCESS"
+    assert D.full_distance(U, C) < 1e-10
+
+
+def test_double_and_restart_accounting():
+    """Pin P13 (Sec. 3: 2 + 4 + ... + m < 2m; doubling stops at 2^n)."""
+    w = I.workload_3q()
+    p = O.default_params(dist_tol=1e-10, multistarts=4, seed=5, max_iter=400, m_init=1)
+    _, info = O.instantiate(3, w["pairs"], target_pairs=w["target_pairs"],
+                            target_gates=w["target_gates"], params=p, trace_capacity=100000)
+    ms = info["trace"]["m"]
+    assert info["restarts"] >= 1
+    assert np.all(np.diff(ms) >= 0)  # the trace is chronological
+    assert ms.max() <= 8 and info["m_final"] <= 8
+    assert info["m_total"] < 2 * info["m_final"]
+    assert sorted(set(ms.tolist())) == [1 << i for i in range(len(set(ms.tolist())))]
+
+
+def test_plateau_detected_when_target_unreachable():
+    """App. A, Eq. 13: a template that cannot express the target stops on the plateau
+    test (one gate on (0,1) versus an entangling target on (1,2))."""
+    g = np.random.default_rng(16)
+    p = O.default_params(multistarts=2, seed=1, m_init=8, fixed_m=1, max_iter=500)
+    _, info = O.instantiate(3, [(0, 1)], target_pairs=[(1, 2)],
+                            target_gates=I.haar_gates(1, g), params=p, trace_capacity=2000)
+    assert info["reason_name"] == "PLATEAU"
+    assert info["sweeps"] >= p["min_iter"] and info["sweeps"] < 500
+    assert info["c_train"] > 1e-3
+
+
+def test_max_iter_stops_exactly():
+    w = I.workload_3q()
+    p = O.default_params(multistarts=1, seed=2, m_init=8, max_iter=7, dist_tol=1e-30,
+                         diff_tol_r=0.0, plateau_window=1000)
+    _, info = O.instantiate(3, w["pairs"], target_pairs=w["target_pairs"],
+                            target_gates=w["target_gates"], params=p)
+    assert info["reason_name"] == "MAX_ITER" and info["sweeps"] == 7
+
+
+def test_success_implies_small_loss_on_fresh_states():
+    """Sec. 3, Eq. 12: on success, ||U psi - C psi||^2 < d_tol (1 + otr) for a random
+    state with high probability (checked on the mean over 64 fresh Haar states)."""
+    pairs = RECOVERY_TEMPLATES[0]
+    tg = I.haar_gates(len(pairs), np.random.default_rng(8))
+    p = O.default_params(dist_tol=1e-9, multistarts=8, seed=8, max_iter=3000, diff_tol_r=1e-7)
+    gates, info = O.instantiate(3, pairs, target_pairs=pairs, target_gates=tg, params=p)
+    assert info["reason_name"] == "SUCCESS"
+    U = D.circuit_matrix(3, pairs, tg)
+    C = D.circuit_matrix(3, pairs, gates)
+    psi = O.draw_states(3, 8, seed=1234, role=O.ROLE_VAL, stream=77)
+    loss = np.mean([np.linalg.norm((U - C) @ s) ** 2 for s in psi])
+    assert loss < p["dist_tol"] * (1 + p["overtrain_ratio"]) * 4
+
+
+def test_samples_target_matches_circuit_target():
+    """A fixed sample set (the spec minimal entry) drives the same sweeps as the
+    circuit target when it holds the same states."""
+    w = I.workload_3q()
+    psi = O.draw_states(3, 4, seed=21)
+    phi = O.apply_circuit(3, psi, w["target_pairs"], w["target_gates"])
+    p = O.default_params(multistarts=2, seed=21, m_init=4, fixed_m=1, max_iter=20, dist_tol=1e-30,
+                         diff_tol_r=0.0, plateau_window=1000)
+    g1, i1 = O.instantiate(3, w["pairs"], psi=psi, phi=phi, n_val=0, params=p)
+    g2, i2 = O.instantiate(3, w["pairs"], target_pairs=w["target_pairs"],
+                           target_gates=w["target_gates"], params=dict(p, m_val=1))
+    assert abs(i1["c_train"] - i2["c_train"]) < 1e-13
+    assert np.allclose(g1, g2, atol=1e-12)
