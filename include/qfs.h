@@ -1,0 +1,230 @@
+/*
+ * qfs.h -- C ABI of the MI355X (gfx950) implementation of QFactor-Sample instantiation
+ * (Kukliansky et al., "Leveraging Quantum Machine Learning Generalization to
+ * Significantly Speed-up Quantum Compilation", arXiv 2405.12866).
+ *
+ * Library: libqfs_hip.so (HIP, gfx950). Plain C types only; no exception crosses this
+ * boundary; every function returns an error code (QFS_OK = 0) unless stated.
+ *
+ * Conventions, shared by every entry point:
+ *   - n qubits, N = 2^n amplitudes; qubit 0 is the MOST significant bit of the
+ *     amplitude index (textbook Kronecker order).
+ *   - A template is an ordered list of L two-qubit gates; gate k acts on the ordered
+ *     qubit pair (pairs[2k], pairs[2k+1]), distinct and in [0, n). Gates are applied
+ *     in list order: C = u_{L-1} ... u_0.
+ *   - A gate is a 4x4 complex matrix stored row-major, u[q][p] (q output, p input
+ *     local index), local index = 2*bit(first qubit) + bit(second qubit). Gate
+ *     tensors are [L][4][4] qfs_c128 (interleaved re, im doubles).
+ *   - A state set is [M][N] qfs_c128, sample-major (each state contiguous).
+ *   - "device" pointers are HIP device memory of the current device; "host" pointers
+ *     are ordinary host memory. Every pointer is caller-owned, used only during the
+ *     call and never retained. Outputs are defined only when the call returns QFS_OK.
+ *   - Calls are stream-ordered on params->hip_stream (or the stream argument; NULL is
+ *     the null stream) and return after the work has completed unless stated.
+ *   - Random draws use the counter-based generator Philox4x32-10 (Salmon et al., SC'11)
+ *     keyed by the 64-bit seed; a complex standard normal is formed from one Philox
+ *     block by the Box-Muller transform. Counter words: (index lo, index hi, role,
+ *     stream). Ginibre entry (row i, column j) of an R-row matrix has index j*R + i.
+ */
+#ifndef QFS_H
+#define QFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} qfs_c128;
+
+/* ---------------------------------------------------------------- error codes */
+enum {
+  QFS_OK = 0,
+  QFS_EINVAL = 1,       /* bad argument: n < 2 or n > 24, pair out of range or equal,
+                           M > 2^n, non-finite or non-unitary input gate, ...        */
+  QFS_ENOMEM = 2,       /* does not fit the device-memory budget even with one start */
+  QFS_EDEVICE = 3,      /* a HIP runtime error; see qfs_last_error_detail()          */
+  QFS_EUNSUPPORTED = 4, /* a combination this build does not implement               */
+  QFS_ENUMERIC = 5      /* orthonormalisation of a drawn sample set failed            */
+};
+
+/* Human-readable text of an error code (static storage). */
+const char *qfs_strerror(int code);
+/* Detail of the most recent error on the calling thread (static per thread). */
+const char *qfs_last_error_detail(void);
+/* Library version string. */
+const char *qfs_version(void);
+
+/* ---------------------------------------------------------------- problem */
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_gates;
+  const int32_t *pairs; /* host, [n_gates][2] */
+} qfs_template;
+
+enum { QFS_TARGET_DENSE = 0, QFS_TARGET_CIRCUIT = 1, QFS_TARGET_SAMPLES = 2 };
+
+/* Target of an instantiation (Sec. 2.3: training pairs (psi, U psi)).
+ *   DENSE:   U, device [N][N] row-major.
+ *   CIRCUIT: circuit (host template) + circuit_gates (device [Lt][4][4]); U psi is
+ *            formed by simulating that circuit.
+ *   SAMPLES: psi, phi device [n_samples][N]; rows 0 .. n_samples-n_val-1 are the
+ *            training pairs (used in order; doubling takes more of them), the last
+ *            n_val rows the validation pairs (n_val = 0: no generalisation test). */
+typedef struct {
+  int32_t kind;
+  const qfs_c128 *U;
+  const qfs_template *circuit;
+  const qfs_c128 *circuit_gates;
+  const qfs_c128 *psi;
+  const qfs_c128 *phi;
+  int32_t n_samples;
+  int32_t n_val;
+} qfs_target;
+
+enum { QFS_PREC_FP64 = 0, QFS_PREC_MIXED = 1 };
+
+/* Hyperparameters (App. A; defaults are the paper's recommended values) plus the
+ * execution controls of this implementation. */
+typedef struct {
+  double dist_tol;           /* success threshold on c_train (App. A: dist_tol)      */
+  double diff_tol_r;         /* plateau relative improvement (App. A, Eq. 13)        */
+  int32_t plateau_window;    /* consecutive non-improving sweeps (App. A)            */
+  int32_t min_iter;          /* sweeps before plateau/overtraining tests (App. A)    */
+  int64_t max_iter;          /* total sweeps per start (App. A)                      */
+  int32_t m_init;            /* initial number of training states (App. A)           */
+  int32_t m_max;             /* cap on M; 0 = 2^n (Sec. 3)                           */
+  double overtrain_ratio;    /* c_val / c_train - 1 threshold (Sec. 3, App. A)       */
+  int32_t multistarts;       /* independent random starts (App. A)                   */
+  double beta;               /* regularised update (App. A); 0 = full update         */
+  uint64_t seed;             /* seeds states, validation states and initial gates    */
+  int32_t fixed_m;           /* 1: never double M                                    */
+  int32_t m_val;             /* validation-set size; 0 = M                           */
+  int32_t precision;         /* QFS_PREC_FP64: complex128 states throughout.
+                                QFS_PREC_MIXED: complex64 states with FP64
+                                environment sums, polar update and cost, and
+                                complex128 refinement sweeps once the best running
+                                start's c_train drops below refine_below.           */
+  double refine_below;       /* MIXED: refinement threshold (default 1e-5)           */
+  uint64_t device_mem_budget;/* bytes the call may allocate; 0 = free device memory  */
+  double time_budget_s;      /* wall-clock budget; 0 = none (reason TIMEOUT)         */
+  void *hip_stream;          /* hipStream_t for all work; NULL = null stream          */
+} qfs_params;
+
+/* Termination reasons (the paper's run outcomes: success, distance not reached,
+ * timeout). */
+enum {
+  QFS_SUCCESS = 0,
+  QFS_PLATEAU = 1,
+  QFS_MAX_ITER = 2,
+  QFS_NOT_GENERALIZED = 3, /* c_train < dist_tol but c_val / c_train > 1 + otr at m_max */
+  QFS_TIMEOUT = 4
+};
+
+typedef struct {
+  int32_t reason;
+  int32_t m_final;           /* M of the last training set                         */
+  int32_t sweeps;            /* sweeps run by the returned start                   */
+  int32_t restarts;          /* doublings                                          */
+  int32_t best_start;        /* index of the returned start                        */
+  int32_t m_total;           /* sum of M over the training sets used               */
+  int32_t start_groups;      /* multistart groups run (> 1 when memory was split)  */
+  int32_t refined;           /* 1 if complex128 refinement sweeps ran              */
+  double c_train;            /* Eq. 9 cost of the returned gates on the training set */
+  double c_val;              /* same on the validation set                         */
+  double seconds;            /* wall time of the call                              */
+  int64_t start_sweeps;      /* sum over starts of sweeps run (throughput count)   */
+  double sweep_seconds;      /* device time spent in sweeps (hipEvent)             */
+} qfs_result;
+
+/* Fill *p with the defaults: dist_tol 1e-8, diff_tol_r 1e-5, plateau_window 5,
+ * min_iter 6, max_iter 1e4, m_init 2, overtrain_ratio 0.1, multistarts 16, beta 0
+ * (App. A recommended values); precision MIXED, refine_below 1e-5, seed 0. */
+void qfs_default_params(qfs_params *p);
+
+/* QFactor-Sample instantiation with the paper's control loop (Sec. 3, App. A):
+ * draw M orthonormal Haar sample states, form U psi, and sweep every running start
+ * right to left (environment, SVD, unitary polar update) until success, plateau,
+ * max_iter or timeout; double M and restart (keeping the gates) when the
+ * normalised generalisation error exceeds overtrain_ratio. When the plan does not
+ * fit device_mem_budget the multistarts are run in halves, recursively (App. A).
+ *   gates_in:  device [multistarts][L][4][4], or NULL for Haar-random initial gates
+ *              drawn from params->seed (role 3, stream = start, index 16*gate + 4*col
+ *              + row of a column-major 4x4 Ginibre block).
+ *   gates_out: device [L][4][4]: the returned start's gates (complex128).
+ *   res:       host.
+ * Errors: QFS_EINVAL (invalid template/target/params, or gates_in not unitary to
+ * 1e-10), QFS_ENOMEM, QFS_EDEVICE, QFS_ENUMERIC. */
+int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target,
+                    const qfs_params *params, const qfs_c128 *gates_in,
+                    qfs_c128 *gates_out, qfs_result *res);
+
+/* Minimal entry: fixed sample set of M pairs (psi, phi = U psi; device [M][N]), one
+ * start, App. A defaults, no validation set, FP64 states, dist_tol = tol. Writes the
+ * gates (device [L][4][4]) and the final Eq. 9 cost (host double). */
+int qfs_instantiate_samples(const qfs_template *tmpl, const qfs_c128 *psi,
+                            const qfs_c128 *phi, int32_t M, double tol,
+                            qfs_c128 *gates_out, double *cost_out);
+
+/* ------------------------------------------------- steps of the method (device) */
+/* M orthonormal Haar states (Sec. 3; App. A: columns of a Haar unitary): the Q of the
+ * QR factorisation, with real positive diag(R), of the N x M complex Ginibre matrix
+ * drawn with (seed, role, stream). out: device [M][N]. M <= 2^n. */
+int qfs_draw_states(int32_t n, int32_t M, uint64_t seed, uint32_t role, uint32_t stream,
+                    qfs_c128 *out, void *hip_stream);
+
+/* Haar-random 4x4 initial gates for `starts` starts of L gates each (App. A,
+ * multistarts and seed). out: device [starts][L][4][4]. */
+int qfs_haar_gates(uint64_t seed, int32_t starts, int32_t L, qfs_c128 *out,
+                   void *hip_stream);
+
+/* Apply a gate list in order to M states in place (Fig. pre-comp, the B list; the
+ * circuit form of the target). states: device [M][N]; pairs: host [L][2];
+ * gates: device [L][4][4]. dagger = 1 applies u^dagger of each gate instead. */
+int qfs_apply_gates(int32_t n, int32_t M, qfs_c128 *states, int32_t L,
+                    const int32_t *pairs, const qfs_c128 *gates, int32_t dagger,
+                    void *hip_stream);
+
+/* out = U psi for a dense target (Sec. 2.3). U: device [N][N] row-major; psi, out:
+ * device [M][N]. */
+int qfs_dense_apply(int32_t n, int32_t M, const qfs_c128 *U, const qfs_c128 *psi,
+                    qfs_c128 *out, void *hip_stream);
+
+/* Environment of the gate on qubits (qa, qb) (Sec. 3, Eq. 10; Fig. env_calc_tensor):
+ * Gamma[q][p] = sum_j sum_r a_j(q, r) conj(b_j(p, r)) over the M samples and the
+ * other n-2 qubits r. The paper's E is Gamma^dagger. a, b: device [M][N];
+ * gamma: device [4][4]. */
+int qfs_environment(int32_t n, int32_t M, const qfs_c128 *a, const qfs_c128 *b,
+                    int32_t qa, int32_t qb, qfs_c128 *gamma, void *hip_stream);
+
+/* Gate update (Sec. 2.1, Eq. 2; App. A Beta): u <- W V^dagger where
+ * (1 - beta) Gamma + beta u = W S V^dagger (FP64 one-sided Jacobi SVD). count
+ * independent 4x4 problems; gamma: device [count][4][4]; u: device [count][4][4]
+ * (read when beta != 0, always written). */
+int qfs_polar_update(int32_t count, const qfs_c128 *gamma, double beta, qfs_c128 *u,
+                     void *hip_stream);
+
+/* One sweep for `starts` starts sharing a training set (Sec. 3; Fig. pre-comp;
+ * Fig. env_calc_tensor): forward B list from the current gates, then right to left
+ * environment, polar update, and backward propagation through the updated gate;
+ * returns the Eq. 9 cost of the updated gates per start.
+ *   psi, phi:  device [M][N] (training states and U psi).
+ *   gates:     device [starts][L][4][4], updated in place (complex128 master).
+ *   precision: QFS_PREC_FP64 or QFS_PREC_MIXED (complex64 states).
+ *   c_train:   host [starts]. */
+int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c128 *psi,
+              const qfs_c128 *phi, int32_t starts, qfs_c128 *gates, int32_t precision,
+              double beta, double *c_train, void *hip_stream);
+
+/* (1/M) sum_j ||x_j - y_j||^2 accumulated in FP64 (Sec. 3, Eq. 9). x, y: device
+ * [M][N]; result: host. */
+int qfs_state_distance(int32_t n, int32_t M, const qfs_c128 *x, const qfs_c128 *y,
+                       double *result, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFS_H */

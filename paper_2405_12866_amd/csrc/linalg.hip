@@ -1,0 +1,290 @@
+// Complex FP64 dense linear algebra for the sample draw (CholeskyQR2 with block
+// Gram-Schmidt projection) and the dense-target product, plus layout conversions.
+#include <algorithm>
+
+#include "qfs_internal.h"
+
+namespace qfs {
+
+// ------------------------------------------------------------------ ZGEMM
+// 32x32 output tile per 256-thread block, K tiles of 16 staged in LDS; each thread
+// owns a 2x2 sub-tile at rows ty, ty+16 and columns tx, tx+16.
+template <bool CT>
+__global__ __launch_bounds__(256) void k_zgemm(int m, int n, int k, c128 alpha, const c128 *A,
+                                               int lda, const c128 *B, int ldb, c128 beta,
+                                               c128 *C, int ldc) {
+  __shared__ c128 As[16][33];
+  __shared__ c128 Bs[16][33];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  c128 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = cmake(0.0, 0.0);
+  for (int kb = 0; kb < k; kb += 16) {
+    for (int e = tid; e < 512; e += 256) {
+      int ii, kk;
+      if (CT) {
+        ii = e & 31;
+        kk = e >> 5;
+      } else {
+        kk = e & 15;
+        ii = e >> 4;
+      }
+      const int gi = i0 + ii, gk = kb + kk;
+      c128 v = cmake(0.0, 0.0);
+      if (gi < m && gk < k) v = CT ? cconj(A[(int64_t)gk * lda + gi]) : A[(int64_t)gi * lda + gk];
+      As[kk][ii] = v;
+    }
+    for (int e = tid; e < 512; e += 256) {
+      const int jj = e & 31, kk = e >> 5;
+      const int gj = j0 + jj, gk = kb + kk;
+      Bs[kk][jj] = (gk < k && gj < n) ? B[(int64_t)gk * ldb + gj] : cmake(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const c128 a0 = As[kk][ty], a1 = As[kk][ty + 16];
+      const c128 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+      cfma(acc[0][0], a0, b0);
+      cfma(acc[0][1], a0, b1);
+      cfma(acc[1][0], a1, b0);
+      cfma(acc[1][1], a1, b1);
+    }
+    __syncthreads();
+  }
+  const bool read_c = !(beta.re == 0.0 && beta.im == 0.0);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
+      if (gi < m && gj < n) {
+        c128 v = alpha * acc[a][b];
+        if (read_c) v = v + beta * C[(int64_t)gi * ldc + gj];
+        C[(int64_t)gi * ldc + gj] = v;
+      }
+    }
+}
+
+int launch_zgemm(bool conjtrans_a, int m, int n, int k, c128 alpha, const c128 *A, int lda,
+                 const c128 *B, int ldb, c128 beta, c128 *C, int ldc, hipStream_t s) {
+  if (m <= 0 || n <= 0) return QFS_OK;
+  dim3 grid((n + 31) / 32, (m + 31) / 32);
+  if (conjtrans_a)
+    hipLaunchKernelGGL(k_zgemm<true>, grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+  else
+    hipLaunchKernelGGL(k_zgemm<false>, grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb,
+                       beta, C, ldc);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+// ------------------------------------------------------------------ Cholesky, R^-1
+// In-place upper Cholesky G = R^H R of an m x m Hermitian positive-definite matrix
+// (row-major, ld m), one work-group, right-looking. flag[0] is set on a non-positive
+// pivot.
+__global__ __launch_bounds__(1024) void k_cholesky_upper(int m, c128 *G, int *flag) {
+  __shared__ double inv_pivot;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < m; ++j) {
+    if (tid == 0) {
+      const double d = G[(int64_t)j * m + j].re;
+      if (!(d > 0.0)) {
+        flag[0] = 1;
+        inv_pivot = 0.0;
+        G[(int64_t)j * m + j] = cmake(1.0, 0.0);
+      } else {
+        const double r = sqrt(d);
+        G[(int64_t)j * m + j] = cmake(r, 0.0);
+        inv_pivot = 1.0 / r;
+      }
+    }
+    __syncthreads();
+    const double ip = inv_pivot;
+    for (int c = j + 1 + tid; c < m; c += nt) G[(int64_t)j * m + c] = cscale(G[(int64_t)j * m + c], ip);
+    __syncthreads();
+    const int w = m - j - 1;
+    for (int64_t e = tid; e < (int64_t)w * w; e += nt) {
+      const int i = j + 1 + (int)(e / w), c = j + 1 + (int)(e % w);
+      if (c < i) continue;
+      c128 v = G[(int64_t)i * m + c];
+      cfma(v, cscale(cconj(G[(int64_t)j * m + i]), -1.0), G[(int64_t)j * m + c]);
+      G[(int64_t)i * m + c] = v;
+    }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)m * m; e += nt) {
+    const int i = (int)(e / m), c = (int)(e % m);
+    if (c < i) G[e] = cmake(0.0, 0.0);
+  }
+}
+
+// T = R^-1 for upper-triangular R (m x m); one thread per column of T.
+__global__ void k_tri_inverse_upper(int m, const c128 *R, c128 *T) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  for (int i = c + 1; i < m; ++i) T[(int64_t)i * m + c] = cmake(0.0, 0.0);
+  const c128 rcc = R[(int64_t)c * m + c];
+  T[(int64_t)c * m + c] = cmake(1.0 / rcc.re, 0.0);
+  for (int i = c - 1; i >= 0; --i) {
+    c128 acc = cmake(0.0, 0.0);
+    for (int k = i + 1; k <= c; ++k) cfma(acc, R[(int64_t)i * m + k], T[(int64_t)k * m + c]);
+    const double rii = R[(int64_t)i * m + i].re;
+    T[(int64_t)i * m + c] = cscale(acc, -1.0 / rii);
+  }
+}
+
+__global__ void k_copy_cols(int64_t rows, int cols, const c128 *src, int lds, c128 *dst, int ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols;
+    const int j = (int)(e - i * cols);
+    dst[i * ldd + j] = src[i * lds + j];
+  }
+}
+
+size_t work_bytes_orth(int64_t rows, int64_t cols) {
+  const size_t m = (size_t)cols;
+  return sizeof(c128) * (m * m * 3 + (size_t)rows * m) + 256;
+}
+
+int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c128 *A, void *work,
+                           hipStream_t s) {
+  const int m = (int)(c1 - c0);
+  if (m <= 0) return QFS_OK;
+  c128 *P = static_cast<c128 *>(work);          // c0 x m (<= c1 x c1)
+  c128 *Gm = P + (size_t)c1 * c1;                 // m x m
+  c128 *T = Gm + (size_t)m * m;                   // m x m
+  c128 *Tmp = T + (size_t)m * m;                  // rows x m
+  int *flag = reinterpret_cast<int *>(Tmp + (size_t)rows * m);
+  QFS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  c128 *An = A + c0;
+  const c128 one = cmake(1.0, 0.0), zero = cmake(0.0, 0.0), mone = cmake(-1.0, 0.0);
+  if (c0 > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      QFS_TRY(launch_zgemm(true, (int)c0, m, (int)rows, one, A, (int)ld, An, (int)ld, zero, P, m, s));
+      QFS_TRY(launch_zgemm(false, (int)rows, m, (int)c0, mone, A, (int)ld, P, m, one, An, (int)ld, s));
+    }
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    QFS_TRY(launch_zgemm(true, m, m, (int)rows, one, An, (int)ld, An, (int)ld, zero, Gm, m, s));
+    hipLaunchKernelGGL(k_cholesky_upper, dim3(1), dim3(1024), 0, s, m, Gm, flag);
+    QFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_tri_inverse_upper, dim3((m + 63) / 64), dim3(64), 0, s, m, Gm, T);
+    QFS_HIP(hipGetLastError());
+    QFS_TRY(launch_zgemm(false, (int)rows, m, m, one, An, (int)ld, T, m, zero, Tmp, m, s));
+    const int64_t total = rows * m;
+    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)),
+                       dim3(256), 0, s, rows, m, Tmp, m, An, (int)ld);
+    QFS_HIP(hipGetLastError());
+  }
+  int h_flag = 0;
+  QFS_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  QFS_HIP(hipStreamSynchronize(s));
+  if (h_flag) {
+    set_error_detail("orthonormalisation: non-positive Cholesky pivot (dependent columns)");
+    return QFS_ENUMERIC;
+  }
+  return QFS_OK;
+}
+
+// ------------------------------------------------------------------ layout conversions
+// sample-major [M][N] c128 -> amplitude-major [N][ld] (32x32 LDS transpose tiles).
+template <typename R>
+__global__ __launch_bounds__(256) void k_to_internal(int64_t N, int64_t M, int64_t ld,
+                                                     const c128 *src, cx<R> *dst) {
+  __shared__ c128 tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows per pass
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    tile[r][tx] = (j < M && i < N) ? src[j * N + i] : cmake(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    if (i < N && j < ld) {
+      const c128 v = tile[tx][r];
+      dst[i * ld + j] = cmake<R>((R)v.re, (R)v.im);
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_from_internal(int64_t N, int64_t M, int64_t ld,
+                                                       const cx<R> *src, c128 *dst) {
+  __shared__ c128 tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    if (i < N && j < M) {
+      const cx<R> v = src[i * ld + j];
+      tile[r][tx] = cmake<double>(v.re, v.im);
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    if (j < M && i < N) dst[j * N + i] = tile[tx][r];
+  }
+}
+
+template <typename R>
+int launch_to_internal(int64_t N, int64_t M, int64_t ld, const c128 *src, cx<R> *dst,
+                       hipStream_t s) {
+  dim3 grid((unsigned)((N + 31) / 32), (unsigned)((ld + 31) / 32));
+  hipLaunchKernelGGL(k_to_internal<R>, grid, dim3(256), 0, s, N, M, ld, src, dst);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+template <typename R>
+int launch_from_internal(int64_t N, int64_t M, int64_t ld, const cx<R> *src, c128 *dst,
+                         hipStream_t s) {
+  dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
+  hipLaunchKernelGGL(k_from_internal<R>, grid, dim3(256), 0, s, N, M, ld, src, dst);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+template int launch_to_internal<float>(int64_t, int64_t, int64_t, const c128 *, c64 *, hipStream_t);
+template int launch_to_internal<double>(int64_t, int64_t, int64_t, const c128 *, c128 *, hipStream_t);
+template int launch_from_internal<float>(int64_t, int64_t, int64_t, const c64 *, c128 *, hipStream_t);
+template int launch_from_internal<double>(int64_t, int64_t, int64_t, const c128 *, c128 *, hipStream_t);
+
+__global__ void k_narrow(int64_t count, const c128 *src, c64 *dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = cmake<float>((float)src[e].re, (float)src[e].im);
+}
+
+int launch_narrow(int64_t count, const c128 *src, c64 *dst, hipStream_t s) {
+  if (count <= 0) return QFS_OK;
+  hipLaunchKernelGGL(k_narrow, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 65536)),
+                     dim3(256), 0, s, count, src, dst);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+// Fill with zeros by a kernel (safe inside captured graphs).
+__global__ void k_zero(uint4 *p, int64_t n16) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n16;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = make_uint4(0, 0, 0, 0);
+}
+
+int launch_zero(void *p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return QFS_OK;
+  if (bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(p) & 15) != 0) {
+    QFS_HIP(hipMemsetAsync(p, 0, bytes, s));
+    return QFS_OK;
+  }
+  const int64_t n16 = (int64_t)(bytes / 16);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)std::min<int64_t>((n16 + 255) / 256, 65536)), dim3(256),
+                     0, s, static_cast<uint4 *>(p), n16);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+}  // namespace qfs

@@ -1,0 +1,216 @@
+// Internal declarations of the HIP implementation (not part of the C ABI).
+//
+// Device state layout ("amplitude-major"): a set of M states of N = 2^n amplitudes is
+// an N x ld row-major matrix, element (i, j) = amplitude i of sample j, ld >= M even,
+// columns M..ld-1 zero. Columns are states, so the linear algebra of the sample
+// draw works on it directly, and every two-qubit gate touches four rows whose
+// sample runs are contiguous: loads are 16-byte vectors over consecutive samples
+// whatever qubits the gate acts on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/qfs.h"
+
+namespace qfs {
+
+// ------------------------------------------------------------------ complex helpers
+template <typename R>
+struct cx {
+  R re, im;
+};
+
+template <typename R>
+__host__ __device__ inline cx<R> cmake(R re, R im) {
+  cx<R> z;
+  z.re = re;
+  z.im = im;
+  return z;
+}
+template <typename R>
+__host__ __device__ inline cx<R> operator+(cx<R> a, cx<R> b) {
+  return cmake<R>(a.re + b.re, a.im + b.im);
+}
+template <typename R>
+__host__ __device__ inline cx<R> operator-(cx<R> a, cx<R> b) {
+  return cmake<R>(a.re - b.re, a.im - b.im);
+}
+template <typename R>
+__host__ __device__ inline cx<R> operator*(cx<R> a, cx<R> b) {
+  return cmake<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename R>
+__host__ __device__ inline cx<R> cscale(cx<R> a, R s) {
+  return cmake<R>(a.re * s, a.im * s);
+}
+template <typename R>
+__host__ __device__ inline cx<R> cconj(cx<R> a) {
+  return cmake<R>(a.re, -a.im);
+}
+template <typename R>
+__host__ __device__ inline R cabs2(cx<R> a) {
+  return a.re * a.re + a.im * a.im;
+}
+// acc += a * b
+template <typename R>
+__host__ __device__ inline void cfma(cx<R> &acc, cx<R> a, cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+// acc += a * conj(b)
+template <typename R>
+__host__ __device__ inline void cfma_conj(cx<R> &acc, cx<R> a, cx<R> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.im, b.re, acc.im);
+  acc.im = fma(-a.re, b.im, acc.im);
+}
+
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+// ------------------------------------------------------------------ errors
+struct Status {
+  int code = QFS_OK;
+};
+
+void set_error_detail(const std::string &s);
+
+#define QFS_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e__ = (call);                                                           \
+    if (e__ != hipSuccess) {                                                           \
+      ::qfs::set_error_detail(std::string(#call) + ": " + hipGetErrorString(e__) +     \
+                              " (" + __FILE__ + ":" + std::to_string(__LINE__) + ")"); \
+      return QFS_EDEVICE;                                                              \
+    }                                                                                  \
+  } while (0)
+
+#define QFS_TRY(expr)         \
+  do {                        \
+    int rc__ = (expr);        \
+    if (rc__ != QFS_OK) return rc__; \
+  } while (0)
+
+// ------------------------------------------------------------------ device buffers
+// A simple owning device allocation; the engine keeps a few of these per call.
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  int alloc(size_t b) {
+    release();
+    if (b == 0) return QFS_OK;
+    hipError_t e = hipMalloc(&ptr, b);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      (void)hipGetLastError();
+      set_error_detail(std::string("hipMalloc(") + std::to_string(b) + "): " + hipGetErrorString(e));
+      return e == hipErrorOutOfMemory ? QFS_ENOMEM : QFS_EDEVICE;
+    }
+    bytes = b;
+    return QFS_OK;
+  }
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(ptr);
+  }
+};
+
+// ------------------------------------------------------------------ kernels (host API)
+// Random numbers (rng.hip)
+int launch_ginibre(int64_t rows, int64_t col0, int64_t col1, int64_t ld, uint64_t seed,
+                   uint32_t role, uint32_t stream, c128 *A, hipStream_t s);
+int launch_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L, c128 *out,
+                      hipStream_t s);
+
+// Linear algebra (linalg.hip), all complex FP64, row-major with leading dimensions.
+// C[m x n] = alpha * op(A) * B + beta * C, op(A) = A (m x k) or A^H (A is k x m).
+int launch_zgemm(bool conjtrans_a, int m, int n, int k, c128 alpha, const c128 *A, int lda,
+                 const c128 *B, int ldb, c128 beta, c128 *C, int ldc, hipStream_t s);
+// Orthonormalise columns [c0, c1) of the rows x ld matrix A against columns [0, c0)
+// and among themselves: QR with real positive diag(R) (CholeskyQR2 after two block
+// Gram-Schmidt projections). Uses `work` (device, >= work_bytes_orth(rows, c1)).
+size_t work_bytes_orth(int64_t rows, int64_t cols);
+int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c128 *A,
+                           void *work, hipStream_t s);
+
+// Layout conversions (linalg.hip)
+// sample-major [M][N] c128  <->  amplitude-major [N][ld] in R (zero padding).
+template <typename R>
+int launch_to_internal(int64_t N, int64_t M, int64_t ld, const c128 *src, cx<R> *dst,
+                       hipStream_t s);
+template <typename R>
+int launch_from_internal(int64_t N, int64_t M, int64_t ld, const cx<R> *src, c128 *dst,
+                         hipStream_t s);
+int launch_narrow(int64_t count, const c128 *src, c64 *dst, hipStream_t s);
+int launch_zero(void *p, size_t bytes, hipStream_t s);
+
+// ------------------------------------------------------------------ sweep kernels
+// Per-start addressing for the sweep kernels: a buffer "X" of starts is at
+// base + stride * start (elements); stride 0 means shared by all starts.
+template <typename R>
+struct SBuf {
+  cx<R> *base;
+  int64_t stride;
+};
+
+struct GateRef {
+  const c128 *g64;   // [S][L][16]
+  const void *gR;    // [S][L][16] in state precision (c64 copy or the c128 master)
+  int32_t gstride;   // L * 16
+};
+
+struct Geometry {
+  int32_t n;       // qubits
+  int32_t N;       // 2^n
+  int32_t ld;      // leading dimension (even, >= M)
+  int32_t M;       // live columns (<= ld); padding columns are zero
+};
+
+// Forward / generic apply: dst_s = op(u_s[k]) src_s on qubits (qa, qb), for the
+// slots [0, nslots) mapped to starts by slot_to_start (device).
+template <typename R>
+int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
+                 SBuf<R> src, SBuf<R> dst, const int32_t *slot_to_start, int nslots,
+                 hipStream_t s);
+
+// Backward step: optionally a_s <- u_s[k_apply]^dagger a_s (qubits of k_apply), then
+// Gamma_s = environment of gate k_env from a_s and b_s; partial sums in FP64, and the
+// last block of each start reduces them and writes u_s[k_env] <- polar((1-beta)Gamma
+// + beta u) to both gate copies. Optionally stores Gamma (FP64) to gamma_out[s].
+struct StepScratch {
+  c128 *partials;        // [S][P][16]
+  unsigned *counters;    // [S], zero between launches
+  c128 *gamma_out;       // optional [S][16]
+};
+template <typename R>
+int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
+                    GateRef gates, c128 *g64_mut, void *gR_mut, double beta,
+                    SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b, const int32_t *slot_to_start,
+                    int nslots, int P, StepScratch sc, bool do_update, hipStream_t s);
+
+// out[s] = (1/M) sum ||op(u_s[k]) x_s - ref_s||^2 (FP64 accumulation); k < 0: no gate.
+template <typename R>
+int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
+                      SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots, int P,
+                      double *partials, unsigned *counters, double *out, hipStream_t s);
+
+// Batched polar update on device (count problems).
+int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipStream_t s);
+
+}  // namespace qfs

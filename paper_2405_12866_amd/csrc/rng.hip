@@ -1,0 +1,111 @@
+// Counter-based random numbers for the method's own draws (training and validation
+// states, initial gates): Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the
+// Box-Muller transform, one complex standard normal per Philox block.
+#include "qfs_internal.h"
+
+namespace qfs {
+
+struct Philox4 {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+  constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+    const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+    const uint32_t n0 = hiB ^ c1 ^ k0;
+    const uint32_t n2 = hiA ^ c3 ^ k1;
+    c0 = n0;
+    c1 = loB;
+    c2 = n2;
+    c3 = loA;
+    k0 += kWeylA;
+    k1 += kWeylB;
+  }
+  return Philox4{{c0, c1, c2, c3}};
+}
+
+// Complex normal with E|z|^2 = 1: |z|^2 = -ln(u1) ~ Exp(1), arg z = 2 pi u2.
+__device__ __forceinline__ c128 complex_normal(uint64_t seed, uint32_t role, uint32_t stream,
+                                               uint64_t idx) {
+  const Philox4 x = philox4x32_10((uint32_t)idx, (uint32_t)(idx >> 32), role, stream,
+                                  (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t m1 = ((((uint64_t)x.w[1]) << 32) | x.w[0]) >> 11;  // 53 bits
+  const uint64_t m2 = ((((uint64_t)x.w[3]) << 32) | x.w[2]) >> 11;
+  const double u1 = ((double)m1 + 1.0) * 0x1.0p-53;  // (0, 1]
+  const double u2 = (double)m2 * 0x1.0p-53;          // [0, 1)
+  const double radius = sqrt(-log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  return cmake<double>(radius * cs, radius * sn);
+}
+
+// Ginibre columns [col0, col1) of a rows-row matrix into the amplitude-major layout:
+// A[i * ld + j] = z(index j * rows + i).
+__global__ void k_ginibre(int64_t rows, int64_t col0, int64_t ncols, int64_t ld, uint64_t seed,
+                          uint32_t role, uint32_t stream, c128 *A) {
+  const int64_t total = rows * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / ncols;
+    const int64_t j = col0 + (e - i * ncols);
+    A[i * ld + j] = complex_normal(seed, role, stream, (uint64_t)(j * rows + i));
+  }
+}
+
+int launch_ginibre(int64_t rows, int64_t col0, int64_t col1, int64_t ld, uint64_t seed,
+                   uint32_t role, uint32_t stream, c128 *A, hipStream_t s) {
+  const int64_t total = rows * (col1 - col0);
+  if (total <= 0) return QFS_OK;
+  const int threads = 256;
+  const int64_t blocks = std::min<int64_t>((total + threads - 1) / threads, 65536);
+  hipLaunchKernelGGL(k_ginibre, dim3((unsigned)blocks), dim3(threads), 0, s, rows, col0,
+                     col1 - col0, ld, seed, role, stream, A);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+// Haar 4x4 per (start, gate): 4x4 Ginibre block (index 16*gate + 4*col + row, role 3,
+// stream = start), orthonormalised column by column with positive diag(R); one thread
+// per gate, written row-major u[q][p] = Q[q][p].
+__global__ void k_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L,
+                             c128 *out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)starts * L) return;
+  const int32_t s = (int32_t)(t / L), k = (int32_t)(t - (int64_t)s * L);
+  c128 q[4][4];  // [col][row]
+  for (int c = 0; c < 4; ++c)
+    for (int r = 0; r < 4; ++r)
+      q[c][r] = complex_normal(seed, 3u, (uint32_t)(start0 + s), (uint64_t)k * 16u + 4u * c + r);
+  for (int c = 0; c < 4; ++c) {
+    for (int rep = 0; rep < 2; ++rep)
+      for (int o = 0; o < c; ++o) {
+        c128 d = cmake(0.0, 0.0);
+        for (int r = 0; r < 4; ++r) cfma(d, cconj(q[o][r]), q[c][r]);
+        for (int r = 0; r < 4; ++r) q[c][r] = q[c][r] - d * q[o][r];
+      }
+    double nrm = 0.0;
+    for (int r = 0; r < 4; ++r) nrm += cabs2(q[c][r]);
+    const double inv = 1.0 / sqrt(nrm);
+    for (int r = 0; r < 4; ++r) q[c][r] = cscale(q[c][r], inv);
+  }
+  c128 *u = out + (int64_t)t * 16;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) u[r * 4 + c] = q[c][r];
+}
+
+int launch_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L, c128 *out,
+                      hipStream_t s) {
+  const int64_t total = (int64_t)starts * L;
+  if (total <= 0) return QFS_OK;
+  hipLaunchKernelGGL(k_haar_gates, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s,
+                     seed, start0, starts, L, out);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+}  // namespace qfs

@@ -1,0 +1,734 @@
+// Sweep kernels of QFactor-Sample (Sec. 3; Fig. pre-comp; Fig. env_calc_tensor).
+//
+// All kernels stream state sets in the amplitude-major layout (see qfs_internal.h):
+// a "packet" is 16 bytes of consecutive samples of one amplitude (two complex64 or
+// one complex128), so every load and store is a 16-byte vector access and a wave
+// covers contiguous runs of memory whatever qubits a gate acts on.
+//
+// Work decomposition: grid = (P blocks, active starts). Each thread owns "super
+// groups": the 2^t amplitudes closed under the t <= 4 bit positions touched by the
+// gate it applies and the gate whose environment it accumulates, times one packet of
+// samples. Environments are reduced thread -> wave (cross-lane shuffles) -> block
+// (LDS, FP64) -> start (the last block to finish reads every block's FP64 partial in
+// a fixed order, then runs the 4x4 FP64 polar update on one wave).
+#include <algorithm>
+
+#include "qfs_internal.h"
+
+namespace qfs {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+template <typename R>
+struct Pk;  // 16-byte packet of samples
+template <>
+struct Pk<float> {
+  static constexpr int V = 2;
+  c64 v[2];
+};
+template <>
+struct Pk<double> {
+  static constexpr int V = 1;
+  c128 v[1];
+};
+
+__device__ __forceinline__ Pk<float> ld_pk(const c64 *p) {
+  const float4 x = *reinterpret_cast<const float4 *>(p);
+  Pk<float> r;
+  r.v[0] = cmake(x.x, x.y);
+  r.v[1] = cmake(x.z, x.w);
+  return r;
+}
+__device__ __forceinline__ Pk<double> ld_pk(const c128 *p) {
+  const double2 x = *reinterpret_cast<const double2 *>(p);
+  Pk<double> r;
+  r.v[0] = cmake(x.x, x.y);
+  return r;
+}
+__device__ __forceinline__ void st_pk(c64 *p, const Pk<float> &r) {
+  *reinterpret_cast<float4 *>(p) = make_float4(r.v[0].re, r.v[0].im, r.v[1].re, r.v[1].im);
+}
+__device__ __forceinline__ void st_pk(c128 *p, const Pk<double> &r) {
+  *reinterpret_cast<double2 *>(p) = make_double2(r.v[0].re, r.v[0].im);
+}
+
+// Insert a zero bit at each of the t ascending positions.
+__device__ __forceinline__ int64_t deposit(int64_t r, const int *sorted_pos, int t) {
+  for (int m = 0; m < t; ++m) {
+    const int p = sorted_pos[m];
+    const int64_t low = r & ((int64_t(1) << p) - 1);
+    r = ((r >> p) << (p + 1)) | low;
+  }
+  return r;
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Local index of the environment gate's (q, sigma) inside a super group, per variant
+// (see host-side classify_step for how the canonical bit order is built).
+template <int VAR>
+__device__ __forceinline__ constexpr int env_index(int q, int sg) {
+  return VAR == 0   ? q
+         : VAR == 1 ? ((q & 1) << 1) | (q >> 1)
+         : VAR == 2 ? ((q >> 1) << 2) | (sg << 1) | (q & 1)
+         : VAR == 3 ? (sg << 2) | ((q >> 1) << 1) | (q & 1)
+         : VAR == 4 ? ((q & 1) << 2) | (sg << 1) | (q >> 1)
+         : VAR == 5 ? (sg << 2) | ((q & 1) << 1) | (q >> 1)
+                    : (sg << 2) | ((q >> 1) << 1) | (q & 1);
+}
+template <int VAR>
+__device__ __forceinline__ constexpr int var_bits() {
+  return VAR <= 1 ? 2 : (VAR <= 5 ? 3 : 4);
+}
+
+struct StepGeom {
+  int32_t ld, M, t;
+  int32_t sorted_pos[4];
+  int32_t off[16];  // amplitude-index offset of each local index
+  int64_t items;    // super groups x packets per row
+  int32_t J;        // packets per row
+};
+
+template <typename R>
+__device__ __forceinline__ void load_gate(const cx<R> *src, cx<R> (&u)[16], bool dagger) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) u[q * 4 + p] = dagger ? cconj(src[p * 4 + q]) : src[q * 4 + p];
+}
+
+// ------------------------------------------------------------------ FP64 4x4 polar
+// One-sided (Hestenes) Jacobi on one wave: lane l = 4c + r (of each 16-lane group)
+// holds column c, row r of the working matrix G and of V. Each round rotates the two
+// disjoint column pairs c <-> c ^ (m >> 2), m in {4, 8, 12}; the pair's Gram entries
+// are summed over the four rows of a quad, so both columns' lanes compute bitwise
+// equal rotations. Then W = normalised columns of G (re-orthonormalised and completed
+// when a singular value is negligible) and u = W V^dagger.
+__device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
+                            c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s) {
+  const int lane = threadIdx.x & 63;
+  const int l = lane & 15, c = l >> 2, r = l & 3;
+  c128 g = G[r * 4 + c];
+  if (beta != 0.0) {
+    const c128 up = u_prev[r * 4 + c];
+    g = cmake((1.0 - beta) * g.re + beta * up.re, (1.0 - beta) * g.im + beta * up.im);
+  }
+  c128 v = cmake(r == c ? 1.0 : 0.0, 0.0);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rotated = 0;
+#pragma unroll
+    for (int m = 4; m <= 12; m += 4) {
+      const c128 go = cmake(__shfl_xor(g.re, m), __shfl_xor(g.im, m));
+      const c128 vo = cmake(__shfl_xor(v.re, m), __shfl_xor(v.im, m));
+      const bool is_p = (l ^ m) > l;
+      const c128 gp = is_p ? g : go, gq = is_p ? go : g;
+      const c128 vp = is_p ? v : vo, vq = is_p ? vo : v;
+      double al = cabs2(gp), be = cabs2(gq);
+      double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) * gq
+      double gi = gp.re * gq.im - gp.im * gq.re;
+#pragma unroll
+      for (int o = 1; o <= 2; o <<= 1) {
+        al += __shfl_xor(al, o);
+        be += __shfl_xor(be, o);
+        gr += __shfl_xor(gr, o);
+        gi += __shfl_xor(gi, o);
+      }
+      const double ag = sqrt(gr * gr + gi * gi);
+      if (ag > 0.0 && ag > 1e-15 * sqrt(al * be)) {
+        rotated = 1;
+        const c128 ec = cmake(gr / ag, -gi / ag);  // conj(e^{i phi})
+        const double tau = (be - al) / (2.0 * ag);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        const c128 egq = ec * gq, evq = ec * vq;
+        if (is_p) {
+          g = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+          v = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+        } else {
+          g = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+          v = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+        }
+      }
+    }
+    if (!__any(rotated)) break;
+  }
+  double s2 = cabs2(g);
+  s2 += __shfl_xor(s2, 1);
+  s2 += __shfl_xor(s2, 2);
+  if (lane < 16) {
+    lds_g[c * 4 + r] = g;
+    lds_v[c * 4 + r] = v;
+    if (r == 0) lds_s[c] = sqrt(s2);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    int ord[4] = {0, 1, 2, 3};
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (lds_s[ord[b]] > lds_s[ord[a]]) {
+          const int tmp = ord[a];
+          ord[a] = ord[b];
+          ord[b] = tmp;
+        }
+    const double smax = lds_s[ord[0]];
+    c128 w[4][4];  // [k][row]
+    for (int k = 0; k < 4; ++k) {
+      const int cc = ord[k];
+      const double sk = lds_s[cc];
+      c128 x[4];
+      bool ok = sk > 0.0 && sk > 1e-13 * smax;
+      if (ok) {
+        for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(lds_g[cc * 4 + rr], 1.0 / sk);
+        for (int rep = 0; rep < 2; ++rep)
+          for (int o = 0; o < k; ++o) {
+            c128 d = cmake(0.0, 0.0);
+            for (int rr = 0; rr < 4; ++rr) cfma(d, cconj(w[o][rr]), x[rr]);
+            for (int rr = 0; rr < 4; ++rr) x[rr] = x[rr] - d * w[o][rr];
+          }
+        double nn = 0.0;
+        for (int rr = 0; rr < 4; ++rr) nn += cabs2(x[rr]);
+        nn = sqrt(nn);
+        if (nn > 0.5)
+          for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(x[rr], 1.0 / nn);
+        else
+          ok = false;
+      }
+      if (!ok) {  // complete with the unit vector of largest orthogonal remainder
+        double best = -1.0;
+        c128 bx[4];
+        for (int e = 0; e < 4; ++e) {
+          c128 y[4];
+          for (int rr = 0; rr < 4; ++rr) y[rr] = cmake(rr == e ? 1.0 : 0.0, 0.0);
+          for (int rep = 0; rep < 2; ++rep)
+            for (int o = 0; o < k; ++o) {
+              c128 d = cmake(0.0, 0.0);
+              for (int rr = 0; rr < 4; ++rr) cfma(d, cconj(w[o][rr]), y[rr]);
+              for (int rr = 0; rr < 4; ++rr) y[rr] = y[rr] - d * w[o][rr];
+            }
+          double nn = 0.0;
+          for (int rr = 0; rr < 4; ++rr) nn += cabs2(y[rr]);
+          if (nn > best) {
+            best = nn;
+            for (int rr = 0; rr < 4; ++rr) bx[rr] = y[rr];
+          }
+        }
+        const double inv = 1.0 / sqrt(best);
+        for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(bx[rr], inv);
+      }
+      for (int rr = 0; rr < 4; ++rr) w[k][rr] = x[rr];
+    }
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < 4; ++p) {
+        c128 acc = cmake(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) cfma_conj(acc, w[k][q], lds_v[ord[k] * 4 + p]);
+        out64[q * 4 + p] = acc;
+        if (out32) out32[q * 4 + p] = cmake<float>((float)acc.re, (float)acc.im);
+      }
+  }
+}
+
+// ------------------------------------------------------------------ forward apply
+template <typename R>
+struct ApplySeg {
+  const cx<R> *src;
+  int64_t src_stride;
+  cx<R> *dst;
+  int64_t dst_stride;
+  int32_t ld;
+  int32_t J;
+  int64_t items;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_apply(ApplySeg<R> seg0, ApplySeg<R> seg1, int pa,
+                                                  int pb, const cx<R> *gates, int32_t gstride,
+                                                  int k, int dagger,
+                                                  const int32_t *slot_to_start) {
+  const ApplySeg<R> sg = blockIdx.z == 0 ? seg0 : seg1;
+  const int s = slot_to_start[blockIdx.y];
+  cx<R> u[16];
+  load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, dagger != 0);
+  const cx<R> *src = sg.src + sg.src_stride * s;
+  cx<R> *dst = sg.dst + sg.dst_stride * s;
+  const int lo = min(pa, pb), hi = max(pa, pb);
+  const int sorted[2] = {lo, hi};
+  const int64_t ma = int64_t(1) << pa, mb = int64_t(1) << pb;
+  constexpr int V = Pk<R>::V;
+  for (int64_t it = blockIdx.x * (int64_t)kBlock + threadIdx.x; it < sg.items;
+       it += (int64_t)gridDim.x * kBlock) {
+    const int64_t rr = it / sg.J;
+    const int jv = (int)(it - rr * sg.J);
+    const int64_t i0 = deposit(rr, sorted, 2);
+    int64_t o[4];
+    o[0] = i0 * sg.ld + jv * V;
+    o[1] = (i0 + mb) * sg.ld + jv * V;
+    o[2] = (i0 + ma) * sg.ld + jv * V;
+    o[3] = (i0 + ma + mb) * sg.ld + jv * V;
+    Pk<R> x[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) x[p] = ld_pk(src + o[p]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Pk<R> y;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        cx<R> acc = cmake<R>(0, 0);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) cfma(acc, u[q * 4 + p], x[p].v[e]);
+        y.v[e] = acc;
+      }
+      st_pk(dst + o[q], y);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ backward step
+template <typename R>
+struct StepArgs {
+  const cx<R> *a_in;
+  int64_t a_in_stride;
+  cx<R> *a_out;
+  int64_t a_out_stride;
+  const cx<R> *b;
+  int64_t b_stride;
+  const cx<R> *gR;      // gates in state precision
+  const c128 *g64;      // FP64 master gates
+  c128 *g64_mut;
+  c64 *g32_mut;         // complex64 copy to refresh (nullptr when R = double)
+  int32_t gstride;
+  int32_t k_apply, k_env;
+  double beta;
+  c128 *partials;       // [S][P][16]
+  unsigned *counters;   // [S]
+  c128 *gamma_out;      // optional [S][16]
+  int32_t do_update;
+  const int32_t *slot_to_start;
+  StepGeom geo;
+};
+
+template <typename R, int VAR, bool APPLY>
+__global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
+  constexpr int t = var_bits<VAR>();
+  constexpr int NL = 1 << t;
+  constexpr int NS = NL / 4;
+  constexpr int V = Pk<R>::V;
+  __shared__ c128 red[kWaves][16];
+  __shared__ c128 gam[16];
+  __shared__ c128 pg[16], pv[16];
+  __shared__ double psig[4];
+  __shared__ int is_last;
+
+  const int s = A.slot_to_start[blockIdx.y];
+  const int P = gridDim.x;
+  cx<R> ud[16];
+  if (APPLY) load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k_apply * 16, ud, true);
+  const cx<R> *a_in = A.a_in + A.a_in_stride * s;
+  cx<R> *a_out = A.a_out + A.a_out_stride * s;
+  const cx<R> *b = A.b + A.b_stride * s;
+  const StepGeom &G = A.geo;
+
+  cx<R> acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = cmake<R>(0, 0);
+
+  for (int64_t it = blockIdx.x * (int64_t)kBlock + threadIdx.x; it < G.items;
+       it += (int64_t)P * kBlock) {
+    const int64_t rr = it / G.J;
+    const int jv = (int)(it - rr * G.J);
+    const int64_t base = deposit(rr, G.sorted_pos, t) * G.ld + jv * V;
+    Pk<R> a[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) a[l] = ld_pk(a_in + base + (int64_t)G.off[l] * G.ld);
+    if (APPLY) {
+#pragma unroll
+      for (int rho = 0; rho < NS; ++rho) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          cx<R> x[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) x[p] = a[p * NS + rho].v[e];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            cx<R> y = cmake<R>(0, 0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) cfma(y, ud[q * 4 + p], x[p]);
+            a[q * NS + rho].v[e] = y;
+          }
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < NL; ++l) st_pk(a_out + base + (int64_t)G.off[l] * G.ld, a[l]);
+    }
+#pragma unroll
+    for (int sg = 0; sg < NS; ++sg) {
+      Pk<R> bb[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        bb[p] = ld_pk(b + base + (int64_t)G.off[env_index<VAR>(p, sg)] * G.ld);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const Pk<R> &aq = a[env_index<VAR>(q, sg)];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int e = 0; e < V; ++e) cfma_conj(acc[q * 4 + p], aq.v[e], bb[p].v[e]);
+      }
+    }
+  }
+
+  // thread -> wave -> block partial (FP64 across waves)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const R re = wave_sum<R>(acc[e].re);
+    const R im = wave_sum<R>(acc[e].im);
+    if (lane == 0) red[wv][e] = cmake<double>(re, im);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    c128 sum = red[0][threadIdx.x];
+    for (int w = 1; w < kWaves; ++w) sum = sum + red[w][threadIdx.x];
+    A.partials[((int64_t)s * P + blockIdx.x) * 16 + threadIdx.x] = sum;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev =
+        __hip_atomic_fetch_add(&A.counters[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == (unsigned)(P - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+
+  // last block of this start: fixed-order FP64 sum of the P partials
+  {
+    const int e = threadIdx.x & 15, grp = threadIdx.x >> 4;  // 16 groups
+    c128 sum = cmake(0.0, 0.0);
+    for (int blk = grp; blk < P; blk += 16) sum = sum + A.partials[((int64_t)s * P + blk) * 16 + e];
+    __shared__ c128 red2[16][16];
+    red2[grp][e] = sum;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      c128 tot = red2[0][threadIdx.x];
+      for (int g2 = 1; g2 < 16; ++g2) tot = tot + red2[g2][threadIdx.x];
+      gam[threadIdx.x] = tot;
+      if (A.gamma_out) A.gamma_out[(int64_t)s * 16 + threadIdx.x] = tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.counters[s] = 0u;
+  if (A.do_update && threadIdx.x < 64) {
+    c128 *u64 = A.g64_mut + (int64_t)s * A.gstride + A.k_env * 16;
+    c64 *u32 = A.g32_mut ? A.g32_mut + (int64_t)s * A.gstride + A.k_env * 16 : nullptr;
+    polar4_wave(gam, A.beta, A.g64 + (int64_t)s * A.gstride + A.k_env * 16, u64, u32, pg, pv,
+                psig);
+  }
+}
+
+// ------------------------------------------------------------------ apply + distance
+template <typename R>
+struct DistArgs {
+  const cx<R> *x;
+  int64_t x_stride;
+  const cx<R> *ref;
+  int64_t ref_stride;
+  const cx<R> *gR;
+  int32_t gstride;
+  int32_t k;        // gate to apply (< 0: none)
+  int32_t dagger;
+  int32_t pa, pb;
+  int32_t ld, J, M;
+  int64_t items;
+  double *partials;  // [S][P]
+  unsigned *counters;
+  double *out;       // [S]
+  const int32_t *slot_to_start;
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_apply_dist(DistArgs<R> A) {
+  __shared__ double red[kWaves];
+  __shared__ int is_last;
+  const int s = A.slot_to_start[blockIdx.y];
+  const int P = gridDim.x;
+  cx<R> u[16];
+  const bool has_gate = A.k >= 0;
+  if (has_gate) load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k * 16, u, A.dagger != 0);
+  const cx<R> *x = A.x + A.x_stride * s;
+  const cx<R> *ref = A.ref + A.ref_stride * s;
+  const int lo = min(A.pa, A.pb), hi = max(A.pa, A.pb);
+  const int sorted[2] = {lo, hi};
+  const int64_t ma = int64_t(1) << A.pa, mb = int64_t(1) << A.pb;
+  constexpr int V = Pk<R>::V;
+  double acc = 0.0;
+  for (int64_t it = blockIdx.x * (int64_t)kBlock + threadIdx.x; it < A.items;
+       it += (int64_t)P * kBlock) {
+    const int64_t rr = it / A.J;
+    const int jv = (int)(it - rr * A.J);
+    const int64_t i0 = deposit(rr, sorted, 2);
+    int64_t o[4];
+    o[0] = i0 * A.ld + jv * V;
+    o[1] = (i0 + mb) * A.ld + jv * V;
+    o[2] = (i0 + ma) * A.ld + jv * V;
+    o[3] = (i0 + ma + mb) * A.ld + jv * V;
+    Pk<R> xv[4], rv[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      xv[p] = ld_pk(x + o[p]);
+      rv[p] = ld_pk(ref + o[p]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        cx<R> y;
+        if (has_gate) {
+          y = cmake<R>(0, 0);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) cfma(y, u[q * 4 + p], xv[p].v[e]);
+        } else {
+          y = xv[q].v[e];
+        }
+        const R dr = y.re - rv[q].v[e].re, di = y.im - rv[q].v[e].im;
+        acc += (double)dr * (double)dr + (double)di * (double)di;
+      }
+  }
+  acc = wave_sum<double>(acc);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = red[0];
+    for (int w = 1; w < kWaves; ++w) sum += red[w];
+    A.partials[(int64_t)s * P + blockIdx.x] = sum;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev =
+        __hip_atomic_fetch_add(&A.counters[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == (unsigned)(P - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int blk = 0; blk < P; ++blk) tot += A.partials[(int64_t)s * P + blk];
+    A.out[s] = tot / (double)A.M;
+    A.counters[s] = 0u;
+  }
+}
+
+__global__ void k_polar_batch(int count, const c128 *gamma, double beta, c128 *u) {
+  __shared__ c128 pg[16], pv[16];
+  __shared__ double psig[4];
+  const int i = blockIdx.x;
+  if (i >= count) return;
+  polar4_wave(gamma + (int64_t)i * 16, beta, u + (int64_t)i * 16, u + (int64_t)i * 16, nullptr,
+              pg, pv, psig);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host launchers
+static int packet_v(size_t rbytes) { return rbytes == 4 ? 2 : 1; }
+
+template <typename R>
+int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
+                 SBuf<R> src, SBuf<R> dst, const int32_t *slot_to_start, int nslots,
+                 hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  ApplySeg<R> seg;
+  const int V = packet_v(sizeof(R));
+  seg.src = src.base;
+  seg.src_stride = src.stride;
+  seg.dst = dst.base;
+  seg.dst_stride = dst.stride;
+  seg.ld = g.ld;
+  seg.J = g.ld / V;
+  seg.items = (int64_t(g.N) >> 2) * seg.J;
+  const int P = (int)std::max<int64_t>(
+      1, std::min<int64_t>((seg.items + kBlock - 1) / kBlock, std::max(1, 2048 / nslots)));
+  const int pa = g.n - 1 - qa, pb = g.n - 1 - qb;
+  hipLaunchKernelGGL(k_apply<R>, dim3(P, nslots, 1), dim3(kBlock), 0, s, seg, seg, pa, pb,
+                     static_cast<const cx<R> *>(gates.gR), gates.gstride, k, dagger ? 1 : 0,
+                     slot_to_start);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+// Canonical bit order for a backward step and its variant id (see env_index).
+static int classify_step(int n, const int32_t *pairs, int k_apply, int k_env, int32_t tq[4],
+                         int *t) {
+  const int a0 = pairs[2 * k_env], b0 = pairs[2 * k_env + 1];
+  if (k_apply < 0) {
+    tq[0] = a0;
+    tq[1] = b0;
+    *t = 2;
+    return 0;
+  }
+  const int a1 = pairs[2 * k_apply], b1 = pairs[2 * k_apply + 1];
+  tq[0] = a1;
+  tq[1] = b1;
+  if ((a0 == a1 && b0 == b1)) {
+    *t = 2;
+    return 0;
+  }
+  if (a0 == b1 && b0 == a1) {
+    *t = 2;
+    return 1;
+  }
+  *t = 3;
+  if (a0 == a1) { tq[2] = b0; return 2; }
+  if (a0 == b1) { tq[2] = b0; return 3; }
+  if (b0 == a1) { tq[2] = a0; return 4; }
+  if (b0 == b1) { tq[2] = a0; return 5; }
+  *t = 4;
+  tq[2] = a0;
+  tq[3] = b0;
+  (void)n;
+  return 6;
+}
+
+template <typename R, int VAR, bool APPLY>
+static void launch_step_kernel(dim3 grid, const StepArgs<R> &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_bwd_step<R, VAR, APPLY>), grid, dim3(kBlock), 0, s, a);
+}
+
+template <typename R>
+int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
+                    GateRef gates, c128 *g64_mut, void *gR_mut, double beta, SBuf<R> a_in,
+                    SBuf<R> a_out, SBuf<R> b, const int32_t *slot_to_start, int nslots, int P,
+                    StepScratch sc, bool do_update, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  int32_t tq[4];
+  int t = 0;
+  const int var = classify_step(g.n, pairs_host, k_apply, k_env, tq, &t);
+  StepArgs<R> a;
+  a.a_in = a_in.base;
+  a.a_in_stride = a_in.stride;
+  a.a_out = a_out.base;
+  a.a_out_stride = a_out.stride;
+  a.b = b.base;
+  a.b_stride = b.stride;
+  a.gR = static_cast<const cx<R> *>(gates.gR);
+  a.g64 = gates.g64;
+  a.g64_mut = g64_mut;
+  a.g32_mut = sizeof(R) == 4 ? static_cast<c64 *>(gR_mut) : nullptr;
+  a.gstride = gates.gstride;
+  a.k_apply = k_apply;
+  a.k_env = k_env;
+  a.beta = beta;
+  a.partials = sc.partials;
+  a.counters = sc.counters;
+  a.gamma_out = sc.gamma_out;
+  a.do_update = do_update ? 1 : 0;
+  a.slot_to_start = slot_to_start;
+  StepGeom &G = a.geo;
+  const int V = packet_v(sizeof(R));
+  G.ld = g.ld;
+  G.M = g.M;
+  G.t = t;
+  int32_t pos[4];
+  for (int m = 0; m < t; ++m) pos[m] = g.n - 1 - tq[m];
+  for (int m = 0; m < 4; ++m) G.sorted_pos[m] = 0;
+  for (int m = 0; m < t; ++m) G.sorted_pos[m] = pos[m];
+  std::sort(G.sorted_pos, G.sorted_pos + t);
+  for (int l = 0; l < 16; ++l) {
+    int32_t o = 0;
+    if (l < (1 << t))
+      for (int m = 0; m < t; ++m)
+        if ((l >> (t - 1 - m)) & 1) o += 1 << pos[m];
+    G.off[l] = o;
+  }
+  G.J = g.ld / V;
+  G.items = (int64_t(g.N) >> t) * G.J;
+  if (P <= 0) {
+    const int64_t pmax = std::max<int64_t>(1, (G.items + kBlock - 1) / kBlock);
+    P = (int)std::min<int64_t>(pmax, std::max(1, 2048 / nslots));
+  }
+  dim3 grid(P, nslots);
+  const bool apply = k_apply >= 0;
+  if (!apply) {
+    launch_step_kernel<R, 0, false>(grid, a, s);
+  } else {
+    switch (var) {
+      case 0: launch_step_kernel<R, 0, true>(grid, a, s); break;
+      case 1: launch_step_kernel<R, 1, true>(grid, a, s); break;
+      case 2: launch_step_kernel<R, 2, true>(grid, a, s); break;
+      case 3: launch_step_kernel<R, 3, true>(grid, a, s); break;
+      case 4: launch_step_kernel<R, 4, true>(grid, a, s); break;
+      case 5: launch_step_kernel<R, 5, true>(grid, a, s); break;
+      default: launch_step_kernel<R, 6, true>(grid, a, s); break;
+    }
+  }
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+template <typename R>
+int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
+                      SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots, int P,
+                      double *partials, unsigned *counters, double *out, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  DistArgs<R> a;
+  const int V = packet_v(sizeof(R));
+  a.x = x.base;
+  a.x_stride = x.stride;
+  a.ref = ref.base;
+  a.ref_stride = ref.stride;
+  a.gR = static_cast<const cx<R> *>(gates.gR);
+  a.gstride = gates.gstride;
+  a.k = k;
+  a.dagger = dagger ? 1 : 0;
+  a.pa = g.n - 1 - qa;
+  a.pb = g.n - 1 - qb;
+  a.ld = g.ld;
+  a.J = g.ld / V;
+  a.M = g.M;
+  a.items = (int64_t(g.N) >> 2) * a.J;
+  a.partials = partials;
+  a.counters = counters;
+  a.out = out;
+  a.slot_to_start = slot_to_start;
+  if (P <= 0) {
+    const int64_t pmax = std::max<int64_t>(1, (a.items + kBlock - 1) / kBlock);
+    P = (int)std::min<int64_t>(pmax, std::max(1, 2048 / nslots));
+  }
+  hipLaunchKernelGGL(k_apply_dist<R>, dim3(P, nslots), dim3(kBlock), 0, s, a);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipStream_t s) {
+  if (count <= 0) return QFS_OK;
+  hipLaunchKernelGGL(k_polar_batch, dim3(count), dim3(64), 0, s, count, gamma, beta, u);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+#define QFS_INST(R)                                                                          \
+  template int launch_apply<R>(const Geometry &, int, int, int, bool, GateRef, SBuf<R>,       \
+                               SBuf<R>, const int32_t *, int, hipStream_t);                   \
+  template int launch_bwd_step<R>(const Geometry &, const int32_t *, int, int, GateRef, c128 *, \
+                                  void *, double, SBuf<R>, SBuf<R>, SBuf<R>, const int32_t *, \
+                                  int, int, StepScratch, bool, hipStream_t);                  \
+  template int launch_apply_dist<R>(const Geometry &, int, int, int, bool, GateRef, SBuf<R>,  \
+                                    SBuf<R>, const int32_t *, int, int, double *, unsigned *, \
+                                    double *, hipStream_t);
+QFS_INST(float)
+QFS_INST(double)
+#undef QFS_INST
+
+}  // namespace qfs

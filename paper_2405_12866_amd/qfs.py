@@ -1,0 +1,274 @@
+"""Python binding of libqfs_hip.so (the C ABI in include/qfs.h).
+
+Argument marshalling only: every step runs in the HIP library. Device buffers are
+torch complex128 tensors on a ROCm device (interleaved re/im doubles, the layout of
+qfs_c128); work is issued on torch's current stream. The functions keep the C names.
+There is no CPU fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqfs_hip.so")
+_lib = None
+_lock = threading.Lock()
+
+QFS_OK, QFS_EINVAL, QFS_ENOMEM, QFS_EDEVICE, QFS_EUNSUPPORTED, QFS_ENUMERIC = range(6)
+QFS_TARGET_DENSE, QFS_TARGET_CIRCUIT, QFS_TARGET_SAMPLES = 0, 1, 2
+QFS_PREC_FP64, QFS_PREC_MIXED = 0, 1
+REASONS = {0: "SUCCESS", 1: "PLATEAU", 2: "MAX_ITER", 3: "NOT_GENERALIZED", 4: "TIMEOUT"}
+
+
+class QfsError(RuntimeError):
+    def __init__(self, code, where):
+        lib = load()
+        super().__init__(f"{where}: {lib.qfs_strerror(code).decode()} ({code}): "
+                         f"{lib.qfs_last_error_detail().decode()}")
+        self.code = code
+
+
+class Template(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("pairs", C.POINTER(C.c_int32))]
+
+
+class Target(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("U", C.c_void_p), ("circuit", C.POINTER(Template)),
+                ("circuit_gates", C.c_void_p), ("psi", C.c_void_p), ("phi", C.c_void_p),
+                ("n_samples", C.c_int32), ("n_val", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("dist_tol", C.c_double), ("diff_tol_r", C.c_double),
+                ("plateau_window", C.c_int32), ("min_iter", C.c_int32), ("max_iter", C.c_int64),
+                ("m_init", C.c_int32), ("m_max", C.c_int32), ("overtrain_ratio", C.c_double),
+                ("multistarts", C.c_int32), ("beta", C.c_double), ("seed", C.c_uint64),
+                ("fixed_m", C.c_int32), ("m_val", C.c_int32), ("precision", C.c_int32),
+                ("refine_below", C.c_double), ("device_mem_budget", C.c_uint64),
+                ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("reason", C.c_int32), ("m_final", C.c_int32), ("sweeps", C.c_int32),
+                ("restarts", C.c_int32), ("best_start", C.c_int32), ("m_total", C.c_int32),
+                ("start_groups", C.c_int32), ("refined", C.c_int32), ("c_train", C.c_double),
+                ("c_val", C.c_double), ("seconds", C.c_double), ("start_sweeps", C.c_int64),
+                ("sweep_seconds", C.c_double)]
+
+
+EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",
+           "qfs_instantiate", "qfs_instantiate_samples", "qfs_draw_states", "qfs_haar_gates",
+           "qfs_apply_gates", "qfs_dense_apply", "qfs_environment", "qfs_polar_update",
+           "qfs_sweep", "qfs_state_distance"]
+
+
+def load():
+    """Load libqfs_hip.so (built by paper_2405_12866_amd.build); raises if absent."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(hipcc --offload-arch=gfx950) first")
+        lib = C.CDLL(LIB_PATH)
+        P, I32, U32, U64, D = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_double
+        lib.qfs_strerror.restype = C.c_char_p
+        lib.qfs_strerror.argtypes = [C.c_int]
+        lib.qfs_last_error_detail.restype = C.c_char_p
+        lib.qfs_version.restype = C.c_char_p
+        lib.qfs_default_params.argtypes = [C.POINTER(Params)]
+        lib.qfs_instantiate.argtypes = [C.POINTER(Template), C.POINTER(Target), C.POINTER(Params),
+                                        P, P, C.POINTER(Result)]
+        lib.qfs_instantiate_samples.argtypes = [C.POINTER(Template), P, P, I32, D, P,
+                                                C.POINTER(C.c_double)]
+        lib.qfs_draw_states.argtypes = [I32, I32, U64, U32, U32, P, P]
+        lib.qfs_haar_gates.argtypes = [U64, I32, I32, P, P]
+        lib.qfs_apply_gates.argtypes = [I32, I32, P, I32, P, P, I32, P]
+        lib.qfs_dense_apply.argtypes = [I32, I32, P, P, P, P]
+        lib.qfs_environment.argtypes = [I32, I32, P, P, I32, I32, P, P]
+        lib.qfs_polar_update.argtypes = [I32, P, D, P, P]
+        lib.qfs_sweep.argtypes = [I32, I32, P, I32, P, P, I32, P, I32, D, P, P]
+        lib.qfs_state_distance.argtypes = [I32, I32, P, P, C.POINTER(C.c_double), P]
+        for name in EXPORTS:
+            if name not in ("qfs_strerror", "qfs_last_error_detail", "qfs_version",
+                            "qfs_default_params"):
+                getattr(lib, name).restype = C.c_int
+        _lib = lib
+        return lib
+
+
+def _check(code, where):
+    if code != QFS_OK:
+        raise QfsError(code, where)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_c128(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.complex128):
+        raise TypeError(f"{name} must be a complex128 tensor on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _pairs(pairs):
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    return arr, arr.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def qfs_default_params(**overrides) -> dict:
+    p = Params()
+    load().qfs_default_params(C.byref(p))
+    d = {f: getattr(p, f) for f, _ in Params._fields_ if f != "hip_stream"}
+    for k, v in overrides.items():
+        if k not in d:
+            raise KeyError(k)
+        d[k] = v
+    return d
+
+
+def _params(d):
+    p = Params()
+    load().qfs_default_params(C.byref(p))
+    for k, v in (d or {}).items():
+        setattr(p, k, v)
+    p.hip_stream = _stream()
+    return p
+
+
+def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=None,
+                    phi=None, n_val=0, params=None, gates_in=None):
+    """QFactor-Sample instantiation on the device. Exactly one target form: dense ``U``
+    [N, N]; a circuit (``target_pairs``, ``target_gates`` [Lt, 4, 4]); or samples
+    ``psi``/``phi`` [n_samples, N] whose last ``n_val`` rows validate. Returns
+    (gates [L, 4, 4] complex128 device tensor, result dict)."""
+    import torch
+    lib = load()
+    arr, pp = _pairs(pairs)
+    L = arr.shape[0]
+    tmpl = Template(n, L, pp)
+    tgt = Target()
+    keep = [arr]
+    dev = None
+    if U is not None:
+        tgt.kind = QFS_TARGET_DENSE
+        tgt.U = _dev_c128(U, "U")
+        dev = U.device
+    elif target_pairs is not None:
+        tarr, tp = _pairs(target_pairs)
+        keep.append(tarr)
+        ct = Template(n, tarr.shape[0], tp)
+        keep.append(ct)
+        tgt.kind = QFS_TARGET_CIRCUIT
+        tgt.circuit = C.pointer(ct)
+        tgt.circuit_gates = _dev_c128(target_gates, "target_gates")
+        dev = target_gates.device
+    else:
+        tgt.kind = QFS_TARGET_SAMPLES
+        tgt.psi = _dev_c128(psi, "psi")
+        tgt.phi = _dev_c128(phi, "phi")
+        tgt.n_samples = psi.shape[0]
+        tgt.n_val = n_val
+        dev = psi.device
+    par = _params(params)
+    gi = _dev_c128(gates_in, "gates_in") if gates_in is not None else None
+    out = torch.empty((L, 4, 4), dtype=torch.complex128, device=dev)
+    res = Result()
+    _check(lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), gi,
+                               C.c_void_p(out.data_ptr()), C.byref(res)), "qfs_instantiate")
+    info = {f: getattr(res, f) for f, _ in Result._fields_}
+    info["reason_name"] = REASONS.get(res.reason, "?")
+    return out, info
+
+
+def qfs_instantiate_samples(n, pairs, psi, phi, M, tol):
+    import torch
+    arr, pp = _pairs(pairs)
+    tmpl = Template(n, arr.shape[0], pp)
+    out = torch.empty((arr.shape[0], 4, 4), dtype=torch.complex128, device=psi.device)
+    cost = C.c_double()
+    _check(load().qfs_instantiate_samples(C.byref(tmpl), _dev_c128(psi, "psi"),
+                                          _dev_c128(phi, "phi"), M, tol,
+                                          C.c_void_p(out.data_ptr()), C.byref(cost)),
+           "qfs_instantiate_samples")
+    return out, cost.value
+
+
+def qfs_draw_states(n, M, seed, role=1, stream=0, device="cuda"):
+    import torch
+    out = torch.empty((M, 1 << n), dtype=torch.complex128, device=device)
+    _check(load().qfs_draw_states(n, M, seed, role, stream, C.c_void_p(out.data_ptr()), _stream()),
+           "qfs_draw_states")
+    return out
+
+
+def qfs_haar_gates(seed, starts, L, device="cuda"):
+    import torch
+    out = torch.empty((starts, L, 4, 4), dtype=torch.complex128, device=device)
+    _check(load().qfs_haar_gates(seed, starts, L, C.c_void_p(out.data_ptr()), _stream()),
+           "qfs_haar_gates")
+    return out
+
+
+def qfs_apply_gates(n, states, pairs, gates, dagger=False):
+    """In place on ``states`` [M, N]; returns it."""
+    arr, pp = _pairs(pairs)
+    _check(load().qfs_apply_gates(n, states.shape[0], _dev_c128(states, "states"), arr.shape[0],
+                                  pp, _dev_c128(gates, "gates"), 1 if dagger else 0, _stream()),
+           "qfs_apply_gates")
+    return states
+
+
+def qfs_dense_apply(n, U, psi):
+    import torch
+    out = torch.empty_like(psi)
+    _check(load().qfs_dense_apply(n, psi.shape[0], _dev_c128(U, "U"), _dev_c128(psi, "psi"),
+                                  C.c_void_p(out.data_ptr()), _stream()), "qfs_dense_apply")
+    return out
+
+
+def qfs_environment(n, a, b, qa, qb):
+    import torch
+    g = torch.empty((4, 4), dtype=torch.complex128, device=a.device)
+    _check(load().qfs_environment(n, a.shape[0], _dev_c128(a, "a"), _dev_c128(b, "b"), qa, qb,
+                                  C.c_void_p(g.data_ptr()), _stream()), "qfs_environment")
+    return g
+
+
+def qfs_polar_update(gamma, beta=0.0, u=None):
+    """gamma [count, 4, 4]; returns the updated gates (a new tensor unless ``u`` given)."""
+    import torch
+    count = gamma.shape[0]
+    if u is None:
+        u = torch.zeros_like(gamma)
+    _check(load().qfs_polar_update(count, _dev_c128(gamma, "gamma"), beta, _dev_c128(u, "u"),
+                                   _stream()), "qfs_polar_update")
+    return u
+
+
+def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0):
+    """One sweep of ``gates`` [starts, L, 4, 4] (updated in place); returns c_train list."""
+    import numpy as np
+    arr, pp = _pairs(pairs)
+    starts = gates.shape[0]
+    c = np.zeros(starts)
+    _check(load().qfs_sweep(n, arr.shape[0], pp, psi.shape[0], _dev_c128(psi, "psi"),
+                            _dev_c128(phi, "phi"), starts, _dev_c128(gates, "gates"), precision,
+                            beta, c.ctypes.data_as(C.c_void_p), _stream()), "qfs_sweep")
+    return c
+
+
+def qfs_state_distance(n, x, y):
+    out = C.c_double()
+    _check(load().qfs_state_distance(n, x.shape[0], _dev_c128(x, "x"), _dev_c128(y, "y"),
+                                     C.byref(out), _stream()), "qfs_state_distance")
+    return out.value

@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function that
+include/qfs.h declares, the binding's struct layouts match the header (checked by
+compiling a probe against the header with gcc), defaults are App. A's recommended
+hyperparameters, and argument validation rejects bad input before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2405_12866_amd import qfs as Q
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qfs.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(qfs_\w+)\s*\(", src, re.M)
+
+
+def test_library_exports_every_declared_function():
+    lib = Q.load()
+    names = _declared()
+    assert len(names) >= 14
+    assert sorted(names) == sorted(Q.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.qfs_version().decode().startswith("qfs-hip")
+
+
+def test_struct_layouts_match_header(tmp_path):
+    probe = tmp_path / "probe.c"
+    probe.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "qfs.h"\n'
+        "int main(void){\n"
+        ' printf("%zu %zu %zu %zu %zu\\n", sizeof(qfs_template), sizeof(qfs_target),'
+        " sizeof(qfs_params), sizeof(qfs_result), sizeof(qfs_c128));\n"
+        ' printf("%zu %zu %zu\\n", offsetof(qfs_params, hip_stream),'
+        " offsetof(qfs_result, sweep_seconds), offsetof(qfs_target, n_val));\n"
+        " return 0;}\n")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(probe), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    got = [int(x) for x in out]
+    want = [C.sizeof(Q.Template), C.sizeof(Q.Target), C.sizeof(Q.Params), C.sizeof(Q.Result), 16,
+            Q.Params.hip_stream.offset, Q.Result.sweep_seconds.offset, Q.Target.n_val.offset]
+    assert got == want
+
+
+def test_default_params_are_paper_recommendations():
+    p = Q.qfs_default_params()
+    assert p["dist_tol"] == 1e-8 and p["diff_tol_r"] == 1e-5 and p["plateau_window"] == 5
+    assert p["min_iter"] == 6 and p["max_iter"] == 10000 and p["m_init"] == 2
+    assert p["overtrain_ratio"] == 0.1 and p["multistarts"] == 16 and p["beta"] == 0.0
+    assert p["precision"] == Q.QFS_PREC_MIXED and p["refine_below"] == 1e-5
+
+
+def test_strerror_covers_codes():
+    lib = Q.load()
+    texts = {c: lib.qfs_strerror(c).decode() for c in range(6)}
+    assert texts[0] == "ok" and len(set(texts.values())) == 6
+
+
+@pytest.mark.parametrize("pairs,n", [([(0, 0)], 3), ([(0, 3)], 3), ([(-1, 1)], 3), ([(0, 1)], 1),
+                                     ([(0, 1)], 25)])
+def test_invalid_templates_rejected_without_device_work(pairs, n):
+    lib = Q.load()
+    arr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32))
+    pp = arr.ctypes.data_as(C.POINTER(C.c_int32))
+    c = np.zeros(1)
+    rc = lib.qfs_sweep(n, 1, pp, 1, C.c_void_p(16), C.c_void_p(16), 1, C.c_void_p(16), 0, 0.0,
+                       c.ctypes.data_as(C.c_void_p), None)
+    assert rc == Q.QFS_EINVAL
+    tmpl = Q.Template(n, 1, pp)
+    par = Q.Params()
+    lib.qfs_default_params(C.byref(par))
+    res = Q.Result()
+    tgt = Q.Target()
+    rc = lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), None, C.c_void_p(16),
+                             C.byref(res))
+    assert rc == Q.QFS_EINVAL
+    assert "template" in lib.qfs_last_error_detail().decode()
+
+
+def test_invalid_params_rejected():
+    lib = Q.load()
+    arr = np.ascontiguousarray(np.asarray([(0, 1)], dtype=np.int32))
+    tmpl = Q.Template(3, 1, arr.ctypes.data_as(C.POINTER(C.c_int32)))
+    tgt = Q.Target()
+    tgt.kind = Q.QFS_TARGET_DENSE
+    tgt.U = C.c_void_p(16)
+    for field, bad in [("multistarts", 0), ("m_init", 9), ("beta", 1.5), ("precision", 7),
+                       ("max_iter", 0)]:
+        par = Q.Params()
+        lib.qfs_default_params(C.byref(par))
+        setattr(par, field, bad)
+        res = Q.Result()
+        rc = lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), None, C.c_void_p(16),
+                                 C.byref(res))
+        assert rc == Q.QFS_EINVAL, field
