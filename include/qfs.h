@@ -111,6 +111,8 @@ typedef struct {
   uint64_t device_mem_budget;/* bytes the call may allocate; 0 = free device memory  */
   double time_budget_s;      /* wall-clock budget; 0 = none (reason TIMEOUT)         */
   void *hip_stream;          /* hipStream_t for all work; NULL = null stream          */
+  int32_t timing;            /* 1: time every sweep kernel with hipEvents on
+                                hip_stream and report it in qfs_result             */
 } qfs_params;
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,
@@ -137,6 +139,13 @@ typedef struct {
   double seconds;            /* wall time of the call                              */
   int64_t start_sweeps;      /* sum over starts of sweeps run (throughput count)   */
   double sweep_seconds;      /* device time spent in sweeps (hipEvent)             */
+  /* With params->timing: per kernel class, launches, summed hipEvent durations and
+   * the bytes the kernels must move (state reads + writes, per the layout above).
+   * Class 0: backward step (apply + environment + polar); class 1: forward apply;
+   * class 2: distance (cost) kernels. */
+  int64_t kernel_launches[3];
+  double kernel_seconds[3];
+  double kernel_bytes[3];
 } qfs_result;
 
 /* Fill *p with the defaults: dist_tol 1e-8, diff_tol_r 1e-5, plateau_window 5,

@@ -78,7 +78,61 @@ struct GroupResult {
   int refined = 0;
   int64_t start_sweeps = 0;
   double sweep_seconds = 0.0;
+  int64_t kl[3] = {0, 0, 0};
+  double ks[3] = {0, 0, 0}, kb[3] = {0, 0, 0};
   std::vector<qfs_c128> gates;  // [L][16] of the chosen start (host copy)
+};
+
+// Optional per-kernel timing: a start/stop hipEvent pair around every timed launch on
+// the call's stream, read back after the next stream synchronisation.
+class KernelTimer {
+ public:
+  ~KernelTimer() {
+    for (hipEvent_t e : ev_) (void)hipEventDestroy(e);
+  }
+  bool on = false;
+  int begin(hipStream_t s) {
+    if (!on) return QFS_OK;
+    if (ev_.size() < 2 * (used_ + 1)) {
+      hipEvent_t a, b;
+      QFS_HIP(hipEventCreate(&a));
+      QFS_HIP(hipEventCreate(&b));
+      ev_.push_back(a);
+      ev_.push_back(b);
+    }
+    QFS_HIP(hipEventRecord(ev_[2 * used_], s));
+    return QFS_OK;
+  }
+  int end(hipStream_t s, int cls, double bytes) {
+    if (!on) return QFS_OK;
+    QFS_HIP(hipEventRecord(ev_[2 * used_ + 1], s));
+    if (cls_.size() <= used_) {
+      cls_.resize(used_ + 1);
+      bytes_.resize(used_ + 1);
+    }
+    cls_[used_] = cls;
+    bytes_[used_] = bytes;
+    ++used_;
+    return QFS_OK;
+  }
+  // Call only after the stream has been synchronised.
+  int flush(GroupResult &r) {
+    for (size_t i = 0; i < used_; ++i) {
+      float ms = 0.f;
+      QFS_HIP(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]));
+      r.kl[cls_[i]] += 1;
+      r.ks[cls_[i]] += 1e-3 * ms;
+      r.kb[cls_[i]] += bytes_[i];
+    }
+    used_ = 0;
+    return QFS_OK;
+  }
+
+ private:
+  std::vector<hipEvent_t> ev_;
+  std::vector<int> cls_;
+  std::vector<double> bytes_;
+  size_t used_ = 0;
 };
 
 enum { ST_RUN = 0, ST_STOP = 1, ST_OVER = 2 };
@@ -88,7 +142,7 @@ class Group {
  public:
   Group(const qfs_template *t, const qfs_target *tg, const qfs_params &p, const qfs_c128 *gates_in,
         int start0, int S, Arena &arena)
-      : tmpl_(t), tgt_(tg), p_(p), gates_in_(gates_in), start0_(start0), S_(S), arena_(arena) {
+      : tgt_(tg), p_(p), gates_in_(gates_in), start0_(start0), S_(S), arena_(arena) {
     n_ = t->n_qubits;
     L_ = t->n_gates;
     N_ = int64_t(1) << n_;
@@ -104,7 +158,6 @@ class Group {
   int run(GroupResult &out, double t_start);
 
  private:
-  const qfs_template *tmpl_;
   const qfs_target *tgt_;
   qfs_params p_;
   const qfs_c128 *gates_in_;
@@ -121,15 +174,19 @@ class Group {
   DevBuf psi32_, phi32_, psiv32_, phiv32_;  // complex64 working copies (MIXED)
   DevBuf blist_, astate_, vstate_;          // sized for complex128
   DevBuf g64_, g32_;
-  DevBuf partials_, counters_, dpart_, dcount_, costs_, slots_, work_;
+  DevBuf partials_, dpart_, costs_, slots_, work_;
   double *h_costs_ = nullptr;  // pinned [3 S]: c_train, c_val, c_0
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   int nslots_ = 0;
+  KernelTimer timer_;
+  GroupResult *res_ = nullptr;
+  double state_bytes(int ld) const {
+    return (double)N_ * ld * (fp64_ ? sizeof(c128) : sizeof(c64)) * (double)nslots_;
+  }
 
   int draw_training(int c0, int c1);
   int make_targets(DevBuf &psi, DevBuf &phi, int M, int ld);
   int draw_validation();
-  int relayout(DevBuf &buf, int rows_ld_old, int ld_new, int cols);
   int alloc_states();
   int refresh_working_copies();
   int set_slots(const std::vector<int> &active);
@@ -263,25 +320,33 @@ int Group::forward(bool with_c0) {
   for (int k = 1; k < L_; ++k) {
     const int qa = pairs_[2 * (k - 1)], qb = pairs_[2 * (k - 1) + 1];
     SBuf<R> src = k == 1 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 2) * sN, bstride};
+    QFS_TRY(timer_.begin(stream_));
     QFS_TRY(launch_apply<R>(g, qa, qb, k - 1, false, gr, src, SBuf<R>{B + (k - 1) * sN, bstride},
                             slots, nslots_, stream_));
-    if (Mv_ > 0)
+    QFS_TRY(timer_.end(stream_, 1, 2.0 * state_bytes(ld_)));
+    if (Mv_ > 0) {
+      QFS_TRY(timer_.begin(stream_));
       QFS_TRY(launch_apply<R>(gv, qa, qb, k - 1, false, gr,
                               k == 1 ? SBuf<R>{psiv, 0} : SBuf<R>{V, vstride}, SBuf<R>{V, vstride},
                               slots, nslots_, stream_));
+      QFS_TRY(timer_.end(stream_, 1, 2.0 * state_bytes(ldv_)));
+    }
   }
   const int qa = pairs_[2 * (L_ - 1)], qb = pairs_[2 * (L_ - 1) + 1];
   double *costs = costs_.as<double>();
-  if (Mv_ > 0)
+  if (Mv_ > 0) {
+    QFS_TRY(timer_.begin(stream_));
     QFS_TRY(launch_apply_dist<R>(gv, qa, qb, L_ - 1, false, gr,
                                  L_ == 1 ? SBuf<R>{psiv, 0} : SBuf<R>{V, vstride},
                                  SBuf<R>{phiv, 0}, slots, nslots_, 0, dpart_.as<double>(),
-                                 dcount_.as<unsigned>(), costs + S_, stream_));
+                                 costs + S_, stream_));
+    QFS_TRY(timer_.end(stream_, 2, 2.0 * state_bytes(ldv_)));
+  }
   if (with_c0)
     QFS_TRY(launch_apply_dist<R>(g, qa, qb, L_ - 1, false, gr,
                                  L_ == 1 ? SBuf<R>{psi, 0} : SBuf<R>{B + (L_ - 2) * sN, bstride},
                                  SBuf<R>{phi, 0}, slots, nslots_, 0, dpart_.as<double>(),
-                                 dcount_.as<unsigned>(), costs + 2 * S_, stream_));
+                                 costs + 2 * S_, stream_));
   return QFS_OK;
 }
 
@@ -301,25 +366,30 @@ int Group::backward() {
   cx<R> *B = cast_state<R>(blist_);
   cx<R> *A = cast_state<R>(astate_);
   const int32_t *slots = slots_.as<int32_t>();
-  StepScratch sc{partials_.as<c128>(), counters_.as<unsigned>(), nullptr};
+  StepScratch sc{partials_.as<c128>(), nullptr};
   for (int k = L_ - 1; k >= 0; --k) {
     const int k_apply = (k == L_ - 1) ? -1 : k + 1;
     SBuf<R> a_in = (k >= L_ - 2) ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
     SBuf<R> b = k == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 1) * sN, bstride};
+    QFS_TRY(timer_.begin(stream_));
     QFS_TRY(launch_bwd_step<R>(g, pairs_.data(), k_apply, k, gr, g64_.as<c128>(),
                                f32 ? g32_.ptr : nullptr, p_.beta, a_in, SBuf<R>{A, sN}, b, slots,
                                nslots_, 0, sc, true, stream_));
+    QFS_TRY(timer_.end(stream_, 0, (k_apply < 0 ? 2.0 : 3.0) * state_bytes(ld_)));
   }
   const int qa = pairs_[0], qb = pairs_[1];
+  QFS_TRY(timer_.begin(stream_));
   QFS_TRY(launch_apply_dist<R>(g, qa, qb, 0, true, gr, L_ == 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN},
                                SBuf<R>{psi, 0}, slots, nslots_, 0, dpart_.as<double>(),
-                               dcount_.as<unsigned>(), costs_.as<double>(), stream_));
+                               costs_.as<double>(), stream_));
+  QFS_TRY(timer_.end(stream_, 2, 2.0 * state_bytes(ld_)));
   return QFS_OK;
 }
 
 int Group::read_costs(std::vector<double> &ct, std::vector<double> &cv, std::vector<double> *c0) {
   QFS_HIP(hipMemcpyAsync(h_costs_, costs_.ptr, sizeof(double) * 3 * S_, hipMemcpyDeviceToHost, stream_));
   QFS_HIP(hipStreamSynchronize(stream_));
+  if (res_) QFS_TRY(timer_.flush(*res_));
   for (int s = 0; s < S_; ++s) {
     ct[s] = h_costs_[s];
     cv[s] = h_costs_[S_ + s];
@@ -339,19 +409,17 @@ int Group::run(GroupResult &out, double t_start) {
   if (p_.fixed_m) m_cap_ = M_;
   ld_ = (int)even_up(M_);
   fp64_ = p_.precision != QFS_PREC_MIXED;
+  timer_.on = p_.timing != 0;
+  res_ = &out;
 
   QFS_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_costs_), sizeof(double) * 3 * S_));
   QFS_HIP(hipEventCreate(&ev0_));
   QFS_HIP(hipEventCreate(&ev1_));
   const int Pcap = 4096;
   QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)Pcap * S_));
-  QFS_TRY(arena_.alloc(counters_, sizeof(unsigned) * S_));
   QFS_TRY(arena_.alloc(dpart_, sizeof(double) * (size_t)Pcap * S_));
-  QFS_TRY(arena_.alloc(dcount_, sizeof(unsigned) * S_));
   QFS_TRY(arena_.alloc(costs_, sizeof(double) * 3 * S_));
   QFS_TRY(arena_.alloc(slots_, sizeof(int32_t) * S_));
-  QFS_TRY(launch_zero(counters_.ptr, counters_.bytes, stream_));
-  QFS_TRY(launch_zero(dcount_.ptr, dcount_.bytes, stream_));
 
   // training set and A tensor (computed once per training set)
   QFS_TRY(arena_.alloc(psi64_, sizeof(c128) * N_ * ld_));
@@ -533,24 +601,23 @@ int Group::run(GroupResult &out, double t_start) {
       break;
     }
     // precision policy: complex128 refinement once the best running start is close
+    bool switch_now = false;
     if (!fp64_) {
       double best = INFINITY;
       for (int s : next) best = std::min(best, ct[s]);
-      if (best < p_.refine_below) {
-        fp64_ = true;
-        out.refined = 1;
-      }
+      switch_now = best < p_.refine_below;
     }
-    if (next.size() != active.size() || (fp64_ && out.refined == 1)) {
+    if (next.size() != active.size()) {
+      // the forward pass just run already holds valid B lists for the survivors
       active = next;
       QFS_TRY(set_slots(active));
-      // redo the forward pass (only the B lists of the still-running starts, or in
-      // complex128 after the switch)
-      QFS_TRY(forward_any(false));
-      if (out.refined == 1) out.refined = 2;
+    }
+    if (switch_now) {
+      fp64_ = true;
+      out.refined = 1;
+      QFS_TRY(forward_any(false));  // B lists again, in complex128, from the FP64 gates
     }
   }
-  if (out.refined == 2) out.refined = 1;
 
   out.best = start0_ + chosen;
   out.reason = reason[chosen];
@@ -732,6 +799,11 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
   for (const auto &x : results) {
     res->start_sweeps += x.start_sweeps;
     res->sweep_seconds += x.sweep_seconds;
+    for (int c = 0; c < 3; ++c) {
+      res->kernel_launches[c] += x.kl[c];
+      res->kernel_seconds[c] += x.ks[c];
+      res->kernel_bytes[c] += x.kb[c];
+    }
   }
   res->seconds = now_s() - t0;
   return QFS_OK;
@@ -839,18 +911,16 @@ int qfs_environment(int32_t n, int32_t M, const qfs_c128 *a, const qfs_c128 *b, 
   if (M < 1 || !a || !b || !gamma) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
   const int64_t N = int64_t(1) << n, ld = even_up(M);
-  DevBuf A, B, slot, part, cnt;
+  DevBuf A, B, slot, part;
   QFS_TRY(A.alloc(sizeof(c128) * N * ld));
   QFS_TRY(B.alloc(sizeof(c128) * N * ld));
   QFS_TRY(part.alloc(sizeof(c128) * 16 * 4096));
-  QFS_TRY(cnt.alloc(sizeof(unsigned)));
-  QFS_TRY(launch_zero(cnt.ptr, 16, s));
   QFS_TRY(one_slot(slot, s));
   QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(a), A.as<c128>(), s));
   QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(b), B.as<c128>(), s));
   Geometry g{n, (int32_t)N, (int32_t)ld, M};
   GateRef gr{nullptr, nullptr, 0};
-  StepScratch sc{part.as<c128>(), cnt.as<unsigned>(), reinterpret_cast<c128 *>(gamma)};
+  StepScratch sc{part.as<c128>(), reinterpret_cast<c128 *>(gamma)};
   QFS_TRY(launch_bwd_step<double>(g, pr, -1, 0, gr, nullptr, nullptr, 0.0,
                                   SBuf<double>{A.as<c128>(), 0}, SBuf<double>{A.as<c128>(), 0},
                                   SBuf<double>{B.as<c128>(), 0}, slot.as<int32_t>(), 1, 0, sc,
@@ -874,13 +944,11 @@ int qfs_state_distance(int32_t n, int32_t M, const qfs_c128 *x, const qfs_c128 *
   if (n < 2 || n > 24 || M < 1 || !x || !y || !result) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
   const int64_t N = int64_t(1) << n, ld = even_up(M);
-  DevBuf A, B, slot, part, cnt, out;
+  DevBuf A, B, slot, part, out;
   QFS_TRY(A.alloc(sizeof(c128) * N * ld));
   QFS_TRY(B.alloc(sizeof(c128) * N * ld));
   QFS_TRY(part.alloc(sizeof(double) * 4096));
-  QFS_TRY(cnt.alloc(16));
   QFS_TRY(out.alloc(16));
-  QFS_TRY(launch_zero(cnt.ptr, 16, s));
   QFS_TRY(one_slot(slot, s));
   QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(x), A.as<c128>(), s));
   QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(y), B.as<c128>(), s));
@@ -888,7 +956,7 @@ int qfs_state_distance(int32_t n, int32_t M, const qfs_c128 *x, const qfs_c128 *
   GateRef gr{nullptr, nullptr, 0};
   QFS_TRY(launch_apply_dist<double>(g, 0, 1, -1, false, gr, SBuf<double>{A.as<c128>(), 0},
                                     SBuf<double>{B.as<c128>(), 0}, slot.as<int32_t>(), 1, 0,
-                                    part.as<double>(), cnt.as<unsigned>(), out.as<double>(), s));
+                                    part.as<double>(), out.as<double>(), s));
   QFS_HIP(hipMemcpyAsync(result, out.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
@@ -906,7 +974,7 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c
   const int64_t N = int64_t(1) << n, ld = even_up(M);
   const bool f32 = precision == QFS_PREC_MIXED;
   const size_t b = f32 ? sizeof(c64) : sizeof(c128);
-  DevBuf ps, ph, Bl, As, g32, slots, part, cnt, dpart, dcnt, costs;
+  DevBuf ps, ph, Bl, As, g32, slots, part, dpart, costs;
   QFS_TRY(ps.alloc(b * N * ld));
   QFS_TRY(ph.alloc(b * N * ld));
   QFS_TRY(Bl.alloc(b * N * ld * (size_t)std::max(L - 1, 1) * starts));
@@ -914,12 +982,8 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c
   QFS_TRY(g32.alloc(sizeof(c64) * 16 * (size_t)L * starts));
   QFS_TRY(slots.alloc(sizeof(int32_t) * starts));
   QFS_TRY(part.alloc(sizeof(c128) * 16 * 4096 * (size_t)starts));
-  QFS_TRY(cnt.alloc(sizeof(unsigned) * starts + 16));
   QFS_TRY(dpart.alloc(sizeof(double) * 4096 * (size_t)starts));
-  QFS_TRY(dcnt.alloc(sizeof(unsigned) * starts + 16));
   QFS_TRY(costs.alloc(sizeof(double) * starts));
-  QFS_TRY(launch_zero(cnt.ptr, cnt.bytes & ~size_t(15), s));
-  QFS_TRY(launch_zero(dcnt.ptr, dcnt.bytes & ~size_t(15), s));
   std::vector<int32_t> sl(starts);
   for (int i = 0; i < starts; ++i) sl[i] = i;
   QFS_HIP(hipMemcpyAsync(slots.ptr, sl.data(), sizeof(int32_t) * starts, hipMemcpyHostToDevice, s));
@@ -937,7 +1001,7 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c
   const int64_t sN = N * ld;
   const int64_t bstride = sN * std::max(L - 1, 1);
   const int32_t *sp = slots.as<int32_t>();
-  StepScratch sc{part.as<c128>(), cnt.as<unsigned>(), nullptr};
+  StepScratch sc{part.as<c128>(), nullptr};
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
     cx<R> *P0 = static_cast<cx<R> *>(ps.ptr), *F0 = static_cast<cx<R> *>(ph.ptr);
@@ -956,7 +1020,7 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c
     }
     QFS_TRY(launch_apply_dist<R>(g, pairs[0], pairs[1], 0, true, gr,
                                  L == 1 ? SBuf<R>{F0, 0} : SBuf<R>{Ap, sN}, SBuf<R>{P0, 0}, sp,
-                                 starts, 0, dpart.as<double>(), dcnt.as<unsigned>(),
+                                 starts, 0, dpart.as<double>(),
                                  costs.as<double>(), s));
     return QFS_OK;
   };

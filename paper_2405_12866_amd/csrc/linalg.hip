@@ -118,19 +118,31 @@ __global__ __launch_bounds__(1024) void k_cholesky_upper(int m, c128 *G, int *fl
   }
 }
 
-// T = R^-1 for upper-triangular R (m x m); one thread per column of T.
-__global__ void k_tri_inverse_upper(int m, const c128 *R, c128 *T) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m) return;
-  for (int i = c + 1; i < m; ++i) T[(int64_t)i * m + c] = cmake(0.0, 0.0);
-  const c128 rcc = R[(int64_t)c * m + c];
-  T[(int64_t)c * m + c] = cmake(1.0 / rcc.re, 0.0);
+// T = R^-1 for upper-triangular R (m x m): one wave per column c of T, back
+// substitution T[i][c] = -(sum_{k=i+1..c} R[i][k] T[k][c]) / R[i][i] with each dot
+// product split over the 64 lanes and combined by a butterfly (every lane ends with
+// the same sum); the column being built lives in LDS.
+__global__ __launch_bounds__(64) void k_tri_inverse_upper(int m, const c128 *R, c128 *T) {
+  extern __shared__ c128 tcol[];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < m; i += 64) tcol[i] = cmake(0.0, 0.0);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __syncthreads();
+  if (lane == 0) tcol[c] = cmake(1.0 / R[(int64_t)c * m + c].re, 0.0);
+  __syncthreads();
   for (int i = c - 1; i >= 0; --i) {
     c128 acc = cmake(0.0, 0.0);
-    for (int k = i + 1; k <= c; ++k) cfma(acc, R[(int64_t)i * m + k], T[(int64_t)k * m + c]);
+    for (int k = i + 1 + lane; k <= c; k += 64) cfma(acc, R[(int64_t)i * m + k], tcol[k]);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      acc.re += __shfl_xor(acc.re, o);
+      acc.im += __shfl_xor(acc.im, o);
+    }
     const double rii = R[(int64_t)i * m + i].re;
-    T[(int64_t)i * m + c] = cscale(acc, -1.0 / rii);
+    if (lane == 0) tcol[i] = cscale(acc, -1.0 / rii);
+    __syncthreads();
   }
+  for (int i = lane; i < m; i += 64) T[(int64_t)i * m + c] = tcol[i];
 }
 
 __global__ void k_copy_cols(int64_t rows, int cols, const c128 *src, int lds, c128 *dst, int ldd) {
@@ -170,7 +182,8 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
     QFS_TRY(launch_zgemm(true, m, m, (int)rows, one, An, (int)ld, An, (int)ld, zero, Gm, m, s));
     hipLaunchKernelGGL(k_cholesky_upper, dim3(1), dim3(1024), 0, s, m, Gm, flag);
     QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_tri_inverse_upper, dim3((m + 63) / 64), dim3(64), 0, s, m, Gm, T);
+    hipLaunchKernelGGL(k_tri_inverse_upper, dim3(m), dim3(64), sizeof(c128) * (size_t)m, s, m, Gm,
+                       T);
     QFS_HIP(hipGetLastError());
     QFS_TRY(launch_zgemm(false, (int)rows, m, m, one, An, (int)ld, T, m, zero, Tmp, m, s));
     const int64_t total = rows * m;

@@ -190,12 +190,12 @@ int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef 
                  hipStream_t s);
 
 // Backward step: optionally a_s <- u_s[k_apply]^dagger a_s (qubits of k_apply), then
-// Gamma_s = environment of gate k_env from a_s and b_s; partial sums in FP64, and the
-// last block of each start reduces them and writes u_s[k_env] <- polar((1-beta)Gamma
-// + beta u) to both gate copies. Optionally stores Gamma (FP64) to gamma_out[s].
+// Gamma_s = environment of gate k_env from a_s and b_s as per-block FP64 partial sums;
+// a second kernel (one wave per start) reduces them in a fixed order and writes
+// u_s[k_env] <- polar((1-beta)Gamma + beta u) to both gate copies. Optionally stores
+// Gamma (FP64) to gamma_out[s].
 struct StepScratch {
   c128 *partials;        // [S][P][16]
-  unsigned *counters;    // [S], zero between launches
   c128 *gamma_out;       // optional [S][16]
 };
 template <typename R>
@@ -208,7 +208,7 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
 template <typename R>
 int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
                       SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots, int P,
-                      double *partials, unsigned *counters, double *out, hipStream_t s);
+                      double *partials, double *out, hipStream_t s);
 
 // Batched polar update on device (count problems).
 int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipStream_t s);

@@ -122,6 +122,7 @@ __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128
     g = cmake((1.0 - beta) * g.re + beta * up.re, (1.0 - beta) * g.im + beta * up.im);
   }
   c128 v = cmake(r == c ? 1.0 : 0.0, 0.0);
+  bool converged = false;
   for (int sweep = 0; sweep < 40; ++sweep) {
     int rotated = 0;
 #pragma unroll
@@ -158,15 +159,46 @@ __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128
         }
       }
     }
-    if (!__any(rotated)) break;
+    if (!__any(rotated)) {
+      converged = true;
+      break;
+    }
   }
   double s2 = cabs2(g);
   s2 += __shfl_xor(s2, 1);
   s2 += __shfl_xor(s2, 2);
+  const double sig = sqrt(s2);
+  double smin = sig, smax = sig;
+  smin = fmin(smin, __shfl_xor(smin, 4));
+  smin = fmin(smin, __shfl_xor(smin, 8));
+  smax = fmax(smax, __shfl_xor(smax, 4));
+  smax = fmax(smax, __shfl_xor(smax, 8));
+  if (converged && smin > 1e-200 && smin > 1e-15 * smax) {
+    // W = G diag(1/sigma) is unitary to the Jacobi tolerance; u = W V^dagger with
+    // lane 4q + p computing u[q][p] = sum_k W[q][k] conj(V[p][k]); W[q][k] and V[p][k]
+    // live on lanes 4k + q and 4k + p.
+    const c128 w = cscale(g, 1.0 / sig);
+    const int q = l >> 2, p = l & 3, base = lane & ~15;
+    c128 acc = cmake(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int lw = base + 4 * k + q, lv = base + 4 * k + p;
+      const c128 wk = cmake(__shfl(w.re, lw), __shfl(w.im, lw));
+      const c128 vk = cmake(__shfl(v.re, lv), __shfl(v.im, lv));
+      cfma_conj(acc, wk, vk);
+    }
+    if (lane < 16) {
+      out64[l] = acc;
+      if (out32) out32[l] = cmake<float>((float)acc.re, (float)acc.im);
+    }
+    return;
+  }
+  // Rank-deficient (or unconverged) case: lane 0 orders the columns by singular value,
+  // re-orthonormalises them and completes W with unit vectors where sigma vanishes.
   if (lane < 16) {
     lds_g[c * 4 + r] = g;
     lds_v[c * 4 + r] = v;
-    if (r == 0) lds_s[c] = sqrt(s2);
+    if (r == 0) lds_s[c] = sig;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -179,13 +211,13 @@ __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128
           ord[a] = ord[b];
           ord[b] = tmp;
         }
-    const double smax = lds_s[ord[0]];
+    const double sm = lds_s[ord[0]];
     c128 w[4][4];  // [k][row]
     for (int k = 0; k < 4; ++k) {
       const int cc = ord[k];
       const double sk = lds_s[cc];
       c128 x[4];
-      bool ok = sk > 0.0 && sk > 1e-13 * smax;
+      bool ok = sk > 0.0 && sk > 1e-13 * sm;
       if (ok) {
         for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(lds_g[cc * 4 + rr], 1.0 / sk);
         for (int rep = 0; rep < 2; ++rep)
@@ -301,16 +333,9 @@ struct StepArgs {
   const cx<R> *b;
   int64_t b_stride;
   const cx<R> *gR;      // gates in state precision
-  const c128 *g64;      // FP64 master gates
-  c128 *g64_mut;
-  c64 *g32_mut;         // complex64 copy to refresh (nullptr when R = double)
   int32_t gstride;
-  int32_t k_apply, k_env;
-  double beta;
+  int32_t k_apply;
   c128 *partials;       // [S][P][16]
-  unsigned *counters;   // [S]
-  c128 *gamma_out;      // optional [S][16]
-  int32_t do_update;
   const int32_t *slot_to_start;
   StepGeom geo;
 };
@@ -322,10 +347,6 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   constexpr int NS = NL / 4;
   constexpr int V = Pk<R>::V;
   __shared__ c128 red[kWaves][16];
-  __shared__ c128 gam[16];
-  __shared__ c128 pg[16], pv[16];
-  __shared__ double psig[4];
-  __shared__ int is_last;
 
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
@@ -399,39 +420,34 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
     for (int w = 1; w < kWaves; ++w) sum = sum + red[w][threadIdx.x];
     A.partials[((int64_t)s * P + blockIdx.x) * 16 + threadIdx.x] = sum;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev =
-        __hip_atomic_fetch_add(&A.counters[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)(P - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
 
-  // last block of this start: fixed-order FP64 sum of the P partials
-  {
-    const int e = threadIdx.x & 15, grp = threadIdx.x >> 4;  // 16 groups
-    c128 sum = cmake(0.0, 0.0);
-    for (int blk = grp; blk < P; blk += 16) sum = sum + A.partials[((int64_t)s * P + blk) * 16 + e];
-    __shared__ c128 red2[16][16];
-    red2[grp][e] = sum;
-    __syncthreads();
-    if (threadIdx.x < 16) {
-      c128 tot = red2[0][threadIdx.x];
-      for (int g2 = 1; g2 < 16; ++g2) tot = tot + red2[g2][threadIdx.x];
-      gam[threadIdx.x] = tot;
-      if (A.gamma_out) A.gamma_out[(int64_t)s * 16 + threadIdx.x] = tot;
-    }
-    __syncthreads();
+// Per start (one wave): fixed-order FP64 sum of the P block partials of the
+// environment, then the gate update u <- polar((1 - beta) Gamma + beta u).
+__global__ __launch_bounds__(64) void k_env_finalize(const c128 *partials, int P,
+                                                     const int32_t *slot_to_start, c128 *gamma_out,
+                                                     int do_update, double beta, c128 *g64,
+                                                     c64 *g32, int32_t gstride, int32_t k_env) {
+  __shared__ c128 gam[16];
+  __shared__ c128 pg[16], pv[16];
+  __shared__ double psig[4];
+  const int s = slot_to_start[blockIdx.x];
+  const int lane = threadIdx.x, e = lane & 15, grp = lane >> 4;
+  c128 sum = cmake(0.0, 0.0);
+  for (int blk = grp; blk < P; blk += 4) sum = sum + partials[((int64_t)s * P + blk) * 16 + e];
+  c128 tot = cmake(0.0, 0.0);
+#pragma unroll
+  for (int g2 = 0; g2 < 4; ++g2)
+    tot = tot + cmake(__shfl(sum.re, e + 16 * g2), __shfl(sum.im, e + 16 * g2));
+  if (lane < 16) {
+    gam[e] = tot;
+    if (gamma_out) gamma_out[(int64_t)s * 16 + e] = tot;
   }
-  if (threadIdx.x == 0) A.counters[s] = 0u;
-  if (A.do_update && threadIdx.x < 64) {
-    c128 *u64 = A.g64_mut + (int64_t)s * A.gstride + A.k_env * 16;
-    c64 *u32 = A.g32_mut ? A.g32_mut + (int64_t)s * A.gstride + A.k_env * 16 : nullptr;
-    polar4_wave(gam, A.beta, A.g64 + (int64_t)s * A.gstride + A.k_env * 16, u64, u32, pg, pv,
-                psig);
+  __syncthreads();
+  if (do_update) {
+    c128 *u64 = g64 + (int64_t)s * gstride + k_env * 16;
+    c64 *u32 = g32 ? g32 + (int64_t)s * gstride + k_env * 16 : nullptr;
+    polar4_wave(gam, beta, u64, u64, u32, pg, pv, psig);
   }
 }
 
@@ -450,15 +466,12 @@ struct DistArgs {
   int32_t ld, J, M;
   int64_t items;
   double *partials;  // [S][P]
-  unsigned *counters;
-  double *out;       // [S]
   const int32_t *slot_to_start;
 };
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_apply_dist(DistArgs<R> A) {
   __shared__ double red[kWaves];
-  __shared__ int is_last;
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
   cx<R> u[16];
@@ -512,22 +525,19 @@ __global__ __launch_bounds__(kBlock) void k_apply_dist(DistArgs<R> A) {
     for (int w = 1; w < kWaves; ++w) sum += red[w];
     A.partials[(int64_t)s * P + blockIdx.x] = sum;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev =
-        __hip_atomic_fetch_add(&A.counters[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)(P - 1));
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int blk = 0; blk < P; ++blk) tot += A.partials[(int64_t)s * P + blk];
-    A.out[s] = tot / (double)A.M;
-    A.counters[s] = 0u;
-  }
+}
+
+// Per start (one wave): fixed-order sum of the P block partials, divided by M.
+__global__ __launch_bounds__(64) void k_dist_finalize(const double *partials, int P,
+                                                      const int32_t *slot_to_start, double inv_m,
+                                                      double *out) {
+  const int s = slot_to_start[blockIdx.x];
+  double sum = 0.0;
+  for (int blk = threadIdx.x; blk < P; blk += 64) sum += partials[(int64_t)s * P + blk];
+  // fixed-order combination across lanes
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) sum += __shfl_down(sum, o);
+  if (threadIdx.x == 0) out[s] = sum * inv_m;
 }
 
 __global__ void k_polar_batch(int count, const c128 *gamma, double beta, c128 *u) {
@@ -623,17 +633,9 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
   a.b = b.base;
   a.b_stride = b.stride;
   a.gR = static_cast<const cx<R> *>(gates.gR);
-  a.g64 = gates.g64;
-  a.g64_mut = g64_mut;
-  a.g32_mut = sizeof(R) == 4 ? static_cast<c64 *>(gR_mut) : nullptr;
   a.gstride = gates.gstride;
   a.k_apply = k_apply;
-  a.k_env = k_env;
-  a.beta = beta;
   a.partials = sc.partials;
-  a.counters = sc.counters;
-  a.gamma_out = sc.gamma_out;
-  a.do_update = do_update ? 1 : 0;
   a.slot_to_start = slot_to_start;
   StepGeom &G = a.geo;
   const int V = packet_v(sizeof(R));
@@ -674,13 +676,17 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
     }
   }
   QFS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_env_finalize, dim3(nslots), dim3(64), 0, s, sc.partials, P, slot_to_start,
+                     sc.gamma_out, do_update ? 1 : 0, beta, g64_mut,
+                     sizeof(R) == 4 ? static_cast<c64 *>(gR_mut) : nullptr, gates.gstride, k_env);
+  QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
 
 template <typename R>
 int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
                       SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots, int P,
-                      double *partials, unsigned *counters, double *out, hipStream_t s) {
+                      double *partials, double *out, hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   DistArgs<R> a;
   const int V = packet_v(sizeof(R));
@@ -699,14 +705,15 @@ int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, Gat
   a.M = g.M;
   a.items = (int64_t(g.N) >> 2) * a.J;
   a.partials = partials;
-  a.counters = counters;
-  a.out = out;
   a.slot_to_start = slot_to_start;
   if (P <= 0) {
     const int64_t pmax = std::max<int64_t>(1, (a.items + kBlock - 1) / kBlock);
     P = (int)std::min<int64_t>(pmax, std::max(1, 2048 / nslots));
   }
   hipLaunchKernelGGL(k_apply_dist<R>, dim3(P, nslots), dim3(kBlock), 0, s, a);
+  QFS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_dist_finalize, dim3(nslots), dim3(64), 0, s, partials, P, slot_to_start,
+                     1.0 / (double)g.M, out);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
@@ -725,8 +732,8 @@ int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipSt
                                   void *, double, SBuf<R>, SBuf<R>, SBuf<R>, const int32_t *, \
                                   int, int, StepScratch, bool, hipStream_t);                  \
   template int launch_apply_dist<R>(const Geometry &, int, int, int, bool, GateRef, SBuf<R>,  \
-                                    SBuf<R>, const int32_t *, int, int, double *, unsigned *, \
-                                    double *, hipStream_t);
+                                    SBuf<R>, const int32_t *, int, int, double *, double *,   \
+                                    hipStream_t);
 QFS_INST(float)
 QFS_INST(double)
 #undef QFS_INST

@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("multistarts", C.c_int32), ("beta", C.c_double), ("seed", C.c_uint64),
                 ("fixed_m", C.c_int32), ("m_val", C.c_int32), ("precision", C.c_int32),
                 ("refine_below", C.c_double), ("device_mem_budget", C.c_uint64),
-                ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p)]
+                ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p),
+                ("timing", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -55,7 +56,8 @@ class Result(C.Structure):
                 ("restarts", C.c_int32), ("best_start", C.c_int32), ("m_total", C.c_int32),
                 ("start_groups", C.c_int32), ("refined", C.c_int32), ("c_train", C.c_double),
                 ("c_val", C.c_double), ("seconds", C.c_double), ("start_sweeps", C.c_int64),
-                ("sweep_seconds", C.c_double)]
+                ("sweep_seconds", C.c_double), ("kernel_launches", C.c_int64 * 3),
+                ("kernel_seconds", C.c_double * 3), ("kernel_bytes", C.c_double * 3)]
 
 
 EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",
@@ -186,6 +188,8 @@ def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, p
     _check(lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), gi,
                                C.c_void_p(out.data_ptr()), C.byref(res)), "qfs_instantiate")
     info = {f: getattr(res, f) for f, _ in Result._fields_}
+    for f in ("kernel_launches", "kernel_seconds", "kernel_bytes"):
+        info[f] = list(info[f])
     info["reason_name"] = REASONS.get(res.reason, "?")
     return out, info
 
