@@ -113,6 +113,12 @@ typedef struct {
   void *hip_stream;          /* hipStream_t for all work; NULL = null stream          */
   int32_t timing;            /* 1: time every sweep kernel with hipEvents on
                                 hip_stream and report it in qfs_result             */
+  int32_t batch_sweeps;      /* qfs_instantiate_batch: sweeps per persistent launch
+                                (0 = 8; 1 keeps every start of a problem in lock
+                                step, as qfs_instantiate does)                      */
+  int32_t batch_threads;     /* qfs_instantiate_batch: work-group size 64, 128 or 256
+                                (0 = chosen by the built-in autotuner, cached per
+                                precision and state-size class for the process)     */
 } qfs_params;
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,
@@ -140,12 +146,13 @@ typedef struct {
   int64_t start_sweeps;      /* sum over starts of sweeps run (throughput count)   */
   double sweep_seconds;      /* device time spent in sweeps (hipEvent)             */
   /* With params->timing: per kernel class, launches, summed hipEvent durations and
-   * the bytes the kernels must move (state reads + writes, per the layout above).
-   * Class 0: backward step (apply + environment + polar); class 1: forward apply;
-   * class 2: distance (cost) kernels. */
-  int64_t kernel_launches[3];
-  double kernel_seconds[3];
-  double kernel_bytes[3];
+   * the bytes the kernels must move (state reads + writes). Class 0: backward step
+   * (apply u^dagger + environment partial sums); class 1: forward pass (B list and
+   * validation states); class 2: distance (cost) kernels; class 3: environment
+   * reduction + FP64 polar update. */
+  int64_t kernel_launches[4];
+  double kernel_seconds[4];
+  double kernel_bytes[4];
 } qfs_result;
 
 /* Fill *p with the defaults: dist_tol 1e-8, diff_tol_r 1e-5, plateau_window 5,
@@ -169,6 +176,26 @@ void qfs_default_params(qfs_params *p);
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target,
                     const qfs_params *params, const qfs_c128 *gates_in,
                     qfs_c128 *gates_out, qfs_result *res);
+
+/* Batched instantiation of P independent problems, each with params->multistarts
+ * starts (Sec. 3 and App. A per problem), in persistent launches: every
+ * (problem, start) job is one work-group that keeps its two working state sets in LDS
+ * (per-work-group global scratch when they exceed 128 KB) and recovers the forward
+ * intermediate states during the backward pass with the gates as they were before the
+ * sweep. Control decisions run on the device after every sweep; doublings and the
+ * complex128 refinement switch happen between launches. Problem p uses seed
+ * params->seed + p. With batch_sweeps = 1 every problem follows qfs_instantiate's
+ * lock-step control flow; with batch_sweeps = K > 1 the starts of a problem advance up
+ * to K sweeps independently, and a success or overtraining found by one start takes
+ * effect at that start's sweep count (the others stop there), so the returned start is
+ * the same as in lock step unless a start that would succeed later was overtaken by a
+ * doubling. MIXED precision switches each start to complex128 on its own.
+ *   tmpl, targets: host arrays [P] (targets' device pointers as in qfs_instantiate).
+ *   gates_out: host array [P] of device pointers [L_p][4][4] (NULL entries skipped).
+ *   res: host [P].
+ * Limits: 2 <= n_qubits <= 10 per problem (QFS_EUNSUPPORTED above). */
+int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                          const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res);
 
 /* Minimal entry: fixed sample set of M pairs (psi, phi = U psi; device [M][N]), one
  * start, App. A defaults, no validation set, FP64 states, dist_tol = tol. Writes the

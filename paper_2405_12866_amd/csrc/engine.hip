@@ -7,7 +7,6 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <limits>
 #include <memory>
 #include <vector>
 
@@ -21,6 +20,8 @@ void set_error_detail(const std::string &s) { g_detail = s; }
 namespace {
 
 enum { kRoleTrain = 1, kRoleVal = 2 };
+enum { kClsStep = 0, kClsForward = 1, kClsDist = 2, kClsPolar = 3, kClasses = 4 };
+constexpr int kPcap = 4096;  // capacity of per-start block partials
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -28,7 +29,28 @@ double now_s() {
 
 hipStream_t as_stream(void *p) { return static_cast<hipStream_t>(p); }
 
-int64_t even_up(int64_t m) { return (m + 1) & ~int64_t(1); }
+int ceil_log2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+// Row-major N x ld masters (states as columns) use ld = 2^ceil(log2 max(M, 2)), so
+// that the same buffer is also a one-chunk set of the chunked layout.
+int master_ld(int M) { return 1 << std::max(1, ceil_log2(std::max(M, 2))); }
+
+size_t lds_max_bytes() {
+  static size_t cached = 0;
+  if (cached == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      cached = (size_t)v;
+    else
+      cached = 64 * 1024;
+  }
+  return cached;
+}
 
 int validate_template(const qfs_template *t) {
   if (!t || t->n_qubits < 2 || t->n_qubits > 24 || t->n_gates < 1 || !t->pairs) {
@@ -68,19 +90,9 @@ struct Arena {
   }
 };
 
-struct GroupResult {
-  int rc = QFS_OK;
-  int reason = QFS_MAX_ITER;
-  int best = -1;  // absolute start index
-  double c_train = INFINITY, c_val = INFINITY;
-  int m_final = 0, sweeps = 0, restarts = 0, m_total = 0;
-  int64_t success_round = -1;  // sweep round at which the success was found
-  int refined = 0;
-  int64_t start_sweeps = 0;
-  double sweep_seconds = 0.0;
-  int64_t kl[3] = {0, 0, 0};
-  double ks[3] = {0, 0, 0}, kb[3] = {0, 0, 0};
-  std::vector<qfs_c128> gates;  // [L][16] of the chosen start (host copy)
+struct Counters {
+  int64_t kl[kClasses] = {0, 0, 0, 0};
+  double ks[kClasses] = {0, 0, 0, 0}, kb[kClasses] = {0, 0, 0, 0};
 };
 
 // Optional per-kernel timing: a start/stop hipEvent pair around every timed launch on
@@ -116,7 +128,7 @@ class KernelTimer {
     return QFS_OK;
   }
   // Call only after the stream has been synchronised.
-  int flush(GroupResult &r) {
+  int flush(Counters &r) {
     for (size_t i = 0; i < used_; ++i) {
       float ms = 0.f;
       QFS_HIP(hipEventElapsedTime(&ms, ev_[2 * i], ev_[2 * i + 1]));
@@ -133,6 +145,159 @@ class KernelTimer {
   std::vector<int> cls_;
   std::vector<double> bytes_;
   size_t used_ = 0;
+};
+
+// ------------------------------------------------------------------ one sweep
+// Everything one forward pass or one right-to-left update needs, for a set of starts
+// sharing a training set. Used by the control loop and by qfs_sweep.
+struct SweepCtx {
+  int n = 0, L = 0;
+  const int32_t *pairs_host = nullptr;
+  const int32_t *pairs_dev = nullptr;
+  Geometry g{}, gv{};  // training / validation sets (gv.M == 0: no validation)
+  bool fused = false;
+  const int32_t *slots = nullptr;
+  int nslots = 0;
+  c128 *g64 = nullptr;
+  c64 *g32 = nullptr;
+  c128 *vstore = nullptr;  // [S][L][16] Jacobi warm start (nullable)
+  double beta = 0.0;
+  void *psi = nullptr, *phi = nullptr, *psiv = nullptr, *phiv = nullptr;  // working sets
+  void *blist = nullptr, *astate = nullptr, *vstate = nullptr;
+  c128 *partials = nullptr;  // [S][kPcap][16]
+  double *dpart0 = nullptr, *dpart1 = nullptr;  // [S][kPcap] each
+  double *costs = nullptr;   // [3 S]: c_train, c_val, c_0
+  int S = 0;
+  KernelTimer *timer = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+template <typename R>
+GateRef gate_ref(const SweepCtx &c) {
+  const bool f32 = sizeof(R) == 4;
+  return GateRef{c.g64, f32 ? static_cast<const void *>(c.g32) : static_cast<const void *>(c.g64),
+                 c.L * 16};
+}
+
+template <typename R>
+double set_bytes(const SweepCtx &c, const Geometry &g) {
+  return (double)g.elems() * sizeof(cx<R>) * (double)c.nslots;
+}
+
+// Forward pass (Fig. pre-comp): B_k = u_{k-1} B_{k-1}, k = 1 .. L-1, from the gates as
+// they are before the sweep; the validation states go through every gate and their
+// Eq. 9 cost against U psi_val is c_val of the current gates. with_c0 also takes the
+// training cost of the current gates (needed once per training set).
+template <typename R>
+int sweep_forward(SweepCtx &c, bool with_c0) {
+  const GateRef gr = gate_ref<R>(c);
+  cx<R> *psi = static_cast<cx<R> *>(c.psi), *phi = static_cast<cx<R> *>(c.phi);
+  cx<R> *psiv = static_cast<cx<R> *>(c.psiv), *phiv = static_cast<cx<R> *>(c.phiv);
+  cx<R> *B = static_cast<cx<R> *>(c.blist);
+  const int64_t sN = c.g.elems();
+  const int64_t bstride = sN * std::max(c.L - 1, 1);
+  const bool val = c.gv.M > 0;
+  KernelTimer &T = *c.timer;
+  if (c.fused) {
+    QFS_TRY(T.begin(c.stream));
+    QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
+                                    with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
+                                    c.nslots, c.stream));
+    const double bytes = set_bytes<R>(c, c.g) * (c.L + (with_c0 ? 1 : 0)) +
+                         (val ? 2.0 * set_bytes<R>(c, c.gv) : 0.0);
+    QFS_TRY(T.end(c.stream, kClsForward, bytes));
+    if (val) QFS_TRY(launch_dist_finalize(c.gv.nch, c.dpart1, c.slots, c.nslots, c.gv.M, c.costs + c.S, c.stream));
+    if (with_c0)
+      QFS_TRY(launch_dist_finalize(c.g.nch, c.dpart0, c.slots, c.nslots, c.g.M, c.costs + 2 * c.S, c.stream));
+    return QFS_OK;
+  }
+  cx<R> *Vs = static_cast<cx<R> *>(c.vstate);
+  const int64_t vstride = c.gv.elems();
+  for (int k = 1; k < c.L; ++k) {
+    const int qa = c.pairs_host[2 * (k - 1)], qb = c.pairs_host[2 * (k - 1) + 1];
+    SBuf<R> src = k == 1 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 2) * sN, bstride};
+    QFS_TRY(T.begin(c.stream));
+    QFS_TRY(launch_apply<R>(c.g, qa, qb, k - 1, false, gr, src, SBuf<R>{B + (k - 1) * sN, bstride},
+                            c.slots, c.nslots, c.stream));
+    QFS_TRY(T.end(c.stream, kClsForward, 2.0 * set_bytes<R>(c, c.g)));
+    if (val) {
+      QFS_TRY(T.begin(c.stream));
+      QFS_TRY(launch_apply<R>(c.gv, qa, qb, k - 1, false, gr,
+                              k == 1 ? SBuf<R>{psiv, 0} : SBuf<R>{Vs, vstride}, SBuf<R>{Vs, vstride},
+                              c.slots, c.nslots, c.stream));
+      QFS_TRY(T.end(c.stream, kClsForward, 2.0 * set_bytes<R>(c, c.gv)));
+    }
+  }
+  const int qa = c.pairs_host[2 * (c.L - 1)], qb = c.pairs_host[2 * (c.L - 1) + 1];
+  int P = 0;
+  if (val) {
+    QFS_TRY(T.begin(c.stream));
+    QFS_TRY(launch_apply_dist<R>(c.gv, qa, qb, c.L - 1, false, gr,
+                                 c.L == 1 ? SBuf<R>{psiv, 0} : SBuf<R>{Vs, vstride}, SBuf<R>{phiv, 0},
+                                 c.slots, c.nslots, c.dpart1, &P, c.stream));
+    QFS_TRY(T.end(c.stream, kClsDist, 2.0 * set_bytes<R>(c, c.gv)));
+    QFS_TRY(launch_dist_finalize(P, c.dpart1, c.slots, c.nslots, c.gv.M, c.costs + c.S, c.stream));
+  }
+  if (with_c0) {
+    QFS_TRY(T.begin(c.stream));
+    QFS_TRY(launch_apply_dist<R>(c.g, qa, qb, c.L - 1, false, gr,
+                                 c.L == 1 ? SBuf<R>{psi, 0} : SBuf<R>{B + (c.L - 2) * sN, bstride},
+                                 SBuf<R>{phi, 0}, c.slots, c.nslots, c.dpart0, &P, c.stream));
+    QFS_TRY(T.end(c.stream, kClsDist, 2.0 * set_bytes<R>(c, c.g)));
+    QFS_TRY(launch_dist_finalize(P, c.dpart0, c.slots, c.nslots, c.g.M, c.costs + 2 * c.S, c.stream));
+  }
+  return QFS_OK;
+}
+
+// Right-to-left update (Sec. 3; Fig. env_calc_tensor): for k = L-1 .. 0 the backward
+// state is moved through the just-updated gate k+1, the environment of gate k is
+// reduced against B_k, and gate k is replaced by its polar factor. Then the Eq. 9
+// cost of the updated gates from a_0 = C^dagger U psi.
+template <typename R>
+int sweep_backward(SweepCtx &c) {
+  const GateRef gr = gate_ref<R>(c);
+  cx<R> *psi = static_cast<cx<R> *>(c.psi), *phi = static_cast<cx<R> *>(c.phi);
+  cx<R> *B = static_cast<cx<R> *>(c.blist), *A = static_cast<cx<R> *>(c.astate);
+  const int64_t sN = c.g.elems();
+  const int64_t bstride = sN * std::max(c.L - 1, 1);
+  KernelTimer &T = *c.timer;
+  for (int k = c.L - 1; k >= 0; --k) {
+    const int k_apply = (k == c.L - 1) ? -1 : k + 1;
+    SBuf<R> a_in = (k >= c.L - 2) ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
+    SBuf<R> b = k == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 1) * sN, bstride};
+    int P = 0;
+    QFS_TRY(T.begin(c.stream));
+    QFS_TRY(launch_bwd_step<R>(c.g, c.pairs_host, k_apply, k, gr, a_in, SBuf<R>{A, sN}, b, c.slots,
+                               c.nslots, c.partials, &P, c.stream));
+    QFS_TRY(T.end(c.stream, kClsStep, (k_apply < 0 ? 2.0 : 3.0) * set_bytes<R>(c, c.g)));
+    QFS_TRY(T.begin(c.stream));
+    QFS_TRY(launch_env_finalize(P, c.partials, c.slots, c.nslots, nullptr, true, c.beta, c.g64,
+                                sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, k, c.vstore, c.stream));
+    QFS_TRY(T.end(c.stream, kClsPolar, (double)P * 256.0 * c.nslots));
+  }
+  int P = 0;
+  QFS_TRY(T.begin(c.stream));
+  QFS_TRY(launch_apply_dist<R>(c.g, c.pairs_host[0], c.pairs_host[1], 0, true, gr,
+                               c.L == 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN}, SBuf<R>{psi, 0}, c.slots,
+                               c.nslots, c.dpart0, &P, c.stream));
+  QFS_TRY(T.end(c.stream, kClsDist, 2.0 * set_bytes<R>(c, c.g)));
+  QFS_TRY(launch_dist_finalize(P, c.dpart0, c.slots, c.nslots, c.g.M, c.costs, c.stream));
+  return QFS_OK;
+}
+
+// ------------------------------------------------------------------ control loop
+struct GroupResult {
+  int rc = QFS_OK;
+  int reason = QFS_MAX_ITER;
+  int best = -1;  // absolute start index
+  double c_train = INFINITY, c_val = INFINITY;
+  int m_final = 0, sweeps = 0, restarts = 0, m_total = 0;
+  int64_t success_round = -1;  // sweep round at which the success was found
+  int refined = 0;
+  int64_t start_sweeps = 0;
+  double sweep_seconds = 0.0;
+  Counters k;
+  std::vector<qfs_c128> gates;  // [L][16] of the chosen start (host copy)
 };
 
 enum { ST_RUN = 0, ST_STOP = 1, ST_OVER = 2 };
@@ -168,57 +333,51 @@ class Group {
   std::vector<int32_t> pairs_;
   hipStream_t stream_ = nullptr;
 
-  int M_ = 0, ld_ = 0, Mv_ = 0, ldv_ = 0, m_cap_ = 0, n_train_ = 0, generation_ = 0;
+  int M_ = 0, ldm_ = 0, Mv_ = 0, ldmv_ = 0, m_cap_ = 0, n_train_ = 0, generation_ = 0;
   bool fp64_ = true;
-  DevBuf psi64_, phi64_, psiv64_, phiv64_;  // complex128 masters
-  DevBuf psi32_, phi32_, psiv32_, phiv32_;  // complex64 working copies (MIXED)
-  DevBuf blist_, astate_, vstate_;          // sized for complex128
-  DevBuf g64_, g32_;
+  DevBuf psi64_, phi64_, psiv64_, phiv64_;  // complex128 masters, row-major N x ldm
+  DevBuf psiw_, phiw_, psivw_, phivw_;      // working sets in the sweep precision
+  DevBuf blist_, astate_, vstate_;
+  DevBuf g64_, g32_, vstore_, pairs_dev_;
   DevBuf partials_, dpart_, costs_, slots_, work_;
   double *h_costs_ = nullptr;  // pinned [3 S]: c_train, c_val, c_0
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
-  int nslots_ = 0;
   KernelTimer timer_;
+  SweepCtx ctx_;
   GroupResult *res_ = nullptr;
-  double state_bytes(int ld) const {
-    return (double)N_ * ld * (fp64_ ? sizeof(c128) : sizeof(c64)) * (double)nslots_;
-  }
 
   int draw_training(int c0, int c1);
   int make_targets(DevBuf &psi, DevBuf &phi, int M, int ld);
   int draw_validation();
-  int alloc_states();
-  int refresh_working_copies();
+  int setup_working();
   int set_slots(const std::vector<int> &active);
-  template <typename R>
-  int forward(bool with_c0);
-  template <typename R>
-  int backward();
-  int forward_any(bool with_c0) { return fp64_ ? forward<double>(with_c0) : forward<float>(with_c0); }
-  int backward_any() { return fp64_ ? backward<double>() : backward<float>(); }
+  int forward_any(bool with_c0) {
+    return fp64_ ? sweep_forward<double>(ctx_, with_c0) : sweep_forward<float>(ctx_, with_c0);
+  }
+  int backward_any() { return fp64_ ? sweep_backward<double>(ctx_) : sweep_backward<float>(ctx_); }
   int read_costs(std::vector<double> &ct, std::vector<double> &cv, std::vector<double> *c0);
 };
 
 int Group::draw_training(int c0, int c1) {
-  QFS_TRY(launch_ginibre(N_, c0, c1, ld_, p_.seed, kRoleTrain, 0, psi64_.as<c128>(), stream_));
+  QFS_TRY(launch_ginibre(N_, c0, c1, ldm_, p_.seed, kRoleTrain, 0, psi64_.as<c128>(), stream_));
   QFS_TRY(arena_.alloc(work_, work_bytes_orth(N_, c1)));
-  QFS_TRY(orthonormalize_columns(N_, ld_, c0, c1, psi64_.as<c128>(), work_.ptr, stream_));
+  QFS_TRY(orthonormalize_columns(N_, ldm_, c0, c1, psi64_.as<c128>(), work_.ptr, stream_));
   arena_.free(work_);
   return QFS_OK;
 }
 
 // phi = U psi (dense product, or simulation of the target circuit), FP64.
 int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld) {
-  const size_t bytes = sizeof(c128) * (size_t)N_ * ld;
   if (tgt_->kind == QFS_TARGET_DENSE) {
     QFS_TRY(launch_zgemm(false, (int)N_, M, (int)N_, cmake(1.0, 0.0),
                          reinterpret_cast<const c128 *>(tgt_->U), (int)N_, psi.as<c128>(), ld,
                          cmake(0.0, 0.0), phi.as<c128>(), ld, stream_));
     return QFS_OK;
   }
-  QFS_HIP(hipMemcpyAsync(phi.ptr, psi.ptr, bytes, hipMemcpyDeviceToDevice, stream_));
+  QFS_HIP(hipMemcpyAsync(phi.ptr, psi.ptr, sizeof(c128) * (size_t)N_ * ld, hipMemcpyDeviceToDevice,
+                         stream_));
   const qfs_template *ct = tgt_->circuit;
-  Geometry g{n_, (int32_t)N_, ld, M};
+  const Geometry g{n_, (int32_t)N_, ceil_log2(ld), 1, M};  // the master is one chunk
   int32_t zero = 0;
   DevBuf slot;
   QFS_TRY(slot.alloc(sizeof(int32_t)));
@@ -237,159 +396,94 @@ int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld) {
 int Group::draw_validation() {
   if (tgt_->kind == QFS_TARGET_SAMPLES) {
     Mv_ = tgt_->n_val;
-    ldv_ = (int)even_up(std::max(Mv_, 1));
+    ldmv_ = master_ld(std::max(Mv_, 1));
     if (Mv_ == 0) return QFS_OK;
-    QFS_TRY(arena_.alloc(psiv64_, sizeof(c128) * N_ * ldv_));
-    QFS_TRY(arena_.alloc(phiv64_, sizeof(c128) * N_ * ldv_));
+    QFS_TRY(arena_.alloc(psiv64_, sizeof(c128) * N_ * ldmv_));
+    QFS_TRY(arena_.alloc(phiv64_, sizeof(c128) * N_ * ldmv_));
     const c128 *ps = reinterpret_cast<const c128 *>(tgt_->psi) + (size_t)n_train_ * N_;
     const c128 *ph = reinterpret_cast<const c128 *>(tgt_->phi) + (size_t)n_train_ * N_;
-    QFS_TRY(launch_to_internal<double>(N_, Mv_, ldv_, ps, psiv64_.as<c128>(), stream_));
-    QFS_TRY(launch_to_internal<double>(N_, Mv_, ldv_, ph, phiv64_.as<c128>(), stream_));
+    QFS_TRY(launch_to_internal<double>(n_, Mv_, ceil_log2(ldmv_), 1, ps, psiv64_.as<c128>(), stream_));
+    QFS_TRY(launch_to_internal<double>(n_, Mv_, ceil_log2(ldmv_), 1, ph, phiv64_.as<c128>(), stream_));
     return QFS_OK;
   }
   Mv_ = p_.m_val > 0 ? p_.m_val : M_;
   if (Mv_ > N_) Mv_ = (int)N_;
-  ldv_ = (int)even_up(Mv_);
-  QFS_TRY(arena_.alloc(psiv64_, sizeof(c128) * N_ * ldv_));
-  QFS_TRY(arena_.alloc(phiv64_, sizeof(c128) * N_ * ldv_));
+  ldmv_ = master_ld(Mv_);
+  QFS_TRY(arena_.alloc(psiv64_, sizeof(c128) * N_ * ldmv_));
+  QFS_TRY(arena_.alloc(phiv64_, sizeof(c128) * N_ * ldmv_));
   QFS_TRY(launch_zero(psiv64_.ptr, psiv64_.bytes, stream_));
-  QFS_TRY(launch_ginibre(N_, 0, Mv_, ldv_, p_.seed, kRoleVal, (uint32_t)generation_,
+  QFS_TRY(launch_ginibre(N_, 0, Mv_, ldmv_, p_.seed, kRoleVal, (uint32_t)generation_,
                          psiv64_.as<c128>(), stream_));
   QFS_TRY(arena_.alloc(work_, work_bytes_orth(N_, Mv_)));
-  QFS_TRY(orthonormalize_columns(N_, ldv_, 0, Mv_, psiv64_.as<c128>(), work_.ptr, stream_));
+  QFS_TRY(orthonormalize_columns(N_, ldmv_, 0, Mv_, psiv64_.as<c128>(), work_.ptr, stream_));
   arena_.free(work_);
-  return make_targets(psiv64_, phiv64_, Mv_, ldv_);
+  return make_targets(psiv64_, phiv64_, Mv_, ldmv_);
 }
 
-int Group::alloc_states() {
-  const size_t state = sizeof(c128) * (size_t)N_ * ld_;
-  QFS_TRY(arena_.alloc(blist_, state * (size_t)S_ * (size_t)std::max(L_ - 1, 1)));
-  QFS_TRY(arena_.alloc(astate_, state * (size_t)S_));
-  QFS_TRY(arena_.alloc(vstate_, sizeof(c128) * (size_t)N_ * ldv_ * (size_t)S_));
-  return QFS_OK;
-}
-
-int Group::refresh_working_copies() {
-  if (p_.precision != QFS_PREC_MIXED) return QFS_OK;
-  QFS_TRY(arena_.alloc(psi32_, sizeof(c64) * N_ * ld_));
-  QFS_TRY(arena_.alloc(phi32_, sizeof(c64) * N_ * ld_));
-  QFS_TRY(launch_narrow(N_ * ld_, psi64_.as<c128>(), psi32_.as<c64>(), stream_));
-  QFS_TRY(launch_narrow(N_ * ld_, phi64_.as<c128>(), phi32_.as<c64>(), stream_));
+// Working sets in the sweep precision (chunk width chosen for the fused forward pass
+// when a chunk of whole samples fits in LDS), and the per-start state buffers.
+int Group::setup_working() {
+  const size_t rb = fp64_ ? sizeof(double) : sizeof(float);
+  const size_t cb = 2 * rb;
+  const size_t lds = lds_max_bytes();
+  const bool fused = forward_fusable(n_, rb, lds);
+  const int logC = choose_log_chunk(n_, M_, rb, fused, S_, lds);
+  const int C = 1 << logC;
+  SweepCtx &c = ctx_;
+  c.n = n_;
+  c.L = L_;
+  c.pairs_host = pairs_.data();
+  c.pairs_dev = pairs_dev_.as<int32_t>();
+  c.g = Geometry{n_, (int32_t)N_, logC, (M_ + C - 1) / C, M_};
+  c.gv = Geometry{n_, (int32_t)N_, logC, std::max(1, (Mv_ + C - 1) / C), Mv_};
+  c.fused = fused;
+  const size_t set = (size_t)c.g.elems() * cb, vset = (size_t)c.gv.elems() * cb;
+  QFS_TRY(arena_.alloc(psiw_, set));
+  QFS_TRY(arena_.alloc(phiw_, set));
+  QFS_TRY(arena_.alloc(blist_, set * (size_t)S_ * (size_t)std::max(L_ - 1, 1)));
+  QFS_TRY(arena_.alloc(astate_, set * (size_t)S_));
   if (Mv_ > 0) {
-    QFS_TRY(arena_.alloc(psiv32_, sizeof(c64) * N_ * ldv_));
-    QFS_TRY(arena_.alloc(phiv32_, sizeof(c64) * N_ * ldv_));
-    QFS_TRY(launch_narrow(N_ * ldv_, psiv64_.as<c128>(), psiv32_.as<c64>(), stream_));
-    QFS_TRY(launch_narrow(N_ * ldv_, phiv64_.as<c128>(), phiv32_.as<c64>(), stream_));
+    QFS_TRY(arena_.alloc(psivw_, vset));
+    QFS_TRY(arena_.alloc(phivw_, vset));
+    if (!fused) QFS_TRY(arena_.alloc(vstate_, vset * (size_t)S_));
   }
+  if (fp64_) {
+    QFS_TRY(launch_pack<double>(c.g, ldm_, psi64_.as<c128>(), psiw_.as<c128>(), stream_));
+    QFS_TRY(launch_pack<double>(c.g, ldm_, phi64_.as<c128>(), phiw_.as<c128>(), stream_));
+    if (Mv_ > 0) {
+      QFS_TRY(launch_pack<double>(c.gv, ldmv_, psiv64_.as<c128>(), psivw_.as<c128>(), stream_));
+      QFS_TRY(launch_pack<double>(c.gv, ldmv_, phiv64_.as<c128>(), phivw_.as<c128>(), stream_));
+    }
+  } else {
+    QFS_TRY(launch_pack<float>(c.g, ldm_, psi64_.as<c128>(), psiw_.as<c64>(), stream_));
+    QFS_TRY(launch_pack<float>(c.g, ldm_, phi64_.as<c128>(), phiw_.as<c64>(), stream_));
+    if (Mv_ > 0) {
+      QFS_TRY(launch_pack<float>(c.gv, ldmv_, psiv64_.as<c128>(), psivw_.as<c64>(), stream_));
+      QFS_TRY(launch_pack<float>(c.gv, ldmv_, phiv64_.as<c128>(), phivw_.as<c64>(), stream_));
+    }
+  }
+  c.psi = psiw_.ptr;
+  c.phi = phiw_.ptr;
+  c.psiv = psivw_.ptr;
+  c.phiv = phivw_.ptr;
+  c.blist = blist_.ptr;
+  c.astate = astate_.ptr;
+  c.vstate = vstate_.ptr;
   return QFS_OK;
 }
 
 int Group::set_slots(const std::vector<int> &active) {
-  nslots_ = (int)active.size();
-  if (nslots_ == 0) return QFS_OK;
+  ctx_.nslots = (int)active.size();
+  if (ctx_.nslots == 0) return QFS_OK;
   QFS_HIP(hipMemcpyAsync(slots_.ptr, active.data(), sizeof(int32_t) * active.size(),
                          hipMemcpyHostToDevice, stream_));
-  return QFS_OK;
-}
-
-template <typename R>
-static cx<R> *cast_state(const DevBuf &b) {
-  return static_cast<cx<R> *>(b.ptr);
-}
-
-// Forward pass (Fig. pre-comp): B_k = u_k B_{k-1}, k = 1 .. L-1, from the gates as
-// they are before the sweep; the validation states go through every gate and their
-// Eq. 9 cost is taken against U psi_val (c_val of the current gates). with_c0 also
-// takes the training cost of the current gates (needed once per training set).
-template <typename R>
-int Group::forward(bool with_c0) {
-  Geometry g{n_, (int32_t)N_, ld_, M_};
-  Geometry gv{n_, (int32_t)N_, ldv_, Mv_};
-  const bool f32 = sizeof(R) == 4;
-  GateRef gr{g64_.as<c128>(), f32 ? g32_.ptr : g64_.ptr, L_ * 16};
-  cx<R> *psi = f32 ? reinterpret_cast<cx<R> *>(psi32_.ptr) : reinterpret_cast<cx<R> *>(psi64_.ptr);
-  cx<R> *phi = f32 ? reinterpret_cast<cx<R> *>(phi32_.ptr) : reinterpret_cast<cx<R> *>(phi64_.ptr);
-  cx<R> *psiv = f32 ? reinterpret_cast<cx<R> *>(psiv32_.ptr) : reinterpret_cast<cx<R> *>(psiv64_.ptr);
-  cx<R> *phiv = f32 ? reinterpret_cast<cx<R> *>(phiv32_.ptr) : reinterpret_cast<cx<R> *>(phiv64_.ptr);
-  const int64_t sN = N_ * (int64_t)ld_;
-  const int64_t bstride = sN * std::max(L_ - 1, 1);
-  cx<R> *B = cast_state<R>(blist_);
-  cx<R> *V = cast_state<R>(vstate_);
-  const int64_t vstride = N_ * (int64_t)ldv_;
-  const int32_t *slots = slots_.as<int32_t>();
-  for (int k = 1; k < L_; ++k) {
-    const int qa = pairs_[2 * (k - 1)], qb = pairs_[2 * (k - 1) + 1];
-    SBuf<R> src = k == 1 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 2) * sN, bstride};
-    QFS_TRY(timer_.begin(stream_));
-    QFS_TRY(launch_apply<R>(g, qa, qb, k - 1, false, gr, src, SBuf<R>{B + (k - 1) * sN, bstride},
-                            slots, nslots_, stream_));
-    QFS_TRY(timer_.end(stream_, 1, 2.0 * state_bytes(ld_)));
-    if (Mv_ > 0) {
-      QFS_TRY(timer_.begin(stream_));
-      QFS_TRY(launch_apply<R>(gv, qa, qb, k - 1, false, gr,
-                              k == 1 ? SBuf<R>{psiv, 0} : SBuf<R>{V, vstride}, SBuf<R>{V, vstride},
-                              slots, nslots_, stream_));
-      QFS_TRY(timer_.end(stream_, 1, 2.0 * state_bytes(ldv_)));
-    }
-  }
-  const int qa = pairs_[2 * (L_ - 1)], qb = pairs_[2 * (L_ - 1) + 1];
-  double *costs = costs_.as<double>();
-  if (Mv_ > 0) {
-    QFS_TRY(timer_.begin(stream_));
-    QFS_TRY(launch_apply_dist<R>(gv, qa, qb, L_ - 1, false, gr,
-                                 L_ == 1 ? SBuf<R>{psiv, 0} : SBuf<R>{V, vstride},
-                                 SBuf<R>{phiv, 0}, slots, nslots_, 0, dpart_.as<double>(),
-                                 costs + S_, stream_));
-    QFS_TRY(timer_.end(stream_, 2, 2.0 * state_bytes(ldv_)));
-  }
-  if (with_c0)
-    QFS_TRY(launch_apply_dist<R>(g, qa, qb, L_ - 1, false, gr,
-                                 L_ == 1 ? SBuf<R>{psi, 0} : SBuf<R>{B + (L_ - 2) * sN, bstride},
-                                 SBuf<R>{phi, 0}, slots, nslots_, 0, dpart_.as<double>(),
-                                 costs + 2 * S_, stream_));
-  return QFS_OK;
-}
-
-// Right-to-left update (Sec. 3; Fig. env_calc_tensor): for k = L-1 .. 0 the backward
-// state is moved through the just-updated gate k+1, the environment of gate k is
-// reduced against B_k, and gate k is replaced by its polar factor. Then the Eq. 9
-// cost of the updated gates from a_0 = C^dagger U psi.
-template <typename R>
-int Group::backward() {
-  Geometry g{n_, (int32_t)N_, ld_, M_};
-  const bool f32 = sizeof(R) == 4;
-  GateRef gr{g64_.as<c128>(), f32 ? g32_.ptr : g64_.ptr, L_ * 16};
-  cx<R> *psi = f32 ? reinterpret_cast<cx<R> *>(psi32_.ptr) : reinterpret_cast<cx<R> *>(psi64_.ptr);
-  cx<R> *phi = f32 ? reinterpret_cast<cx<R> *>(phi32_.ptr) : reinterpret_cast<cx<R> *>(phi64_.ptr);
-  const int64_t sN = N_ * (int64_t)ld_;
-  const int64_t bstride = sN * std::max(L_ - 1, 1);
-  cx<R> *B = cast_state<R>(blist_);
-  cx<R> *A = cast_state<R>(astate_);
-  const int32_t *slots = slots_.as<int32_t>();
-  StepScratch sc{partials_.as<c128>(), nullptr};
-  for (int k = L_ - 1; k >= 0; --k) {
-    const int k_apply = (k == L_ - 1) ? -1 : k + 1;
-    SBuf<R> a_in = (k >= L_ - 2) ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
-    SBuf<R> b = k == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 1) * sN, bstride};
-    QFS_TRY(timer_.begin(stream_));
-    QFS_TRY(launch_bwd_step<R>(g, pairs_.data(), k_apply, k, gr, g64_.as<c128>(),
-                               f32 ? g32_.ptr : nullptr, p_.beta, a_in, SBuf<R>{A, sN}, b, slots,
-                               nslots_, 0, sc, true, stream_));
-    QFS_TRY(timer_.end(stream_, 0, (k_apply < 0 ? 2.0 : 3.0) * state_bytes(ld_)));
-  }
-  const int qa = pairs_[0], qb = pairs_[1];
-  QFS_TRY(timer_.begin(stream_));
-  QFS_TRY(launch_apply_dist<R>(g, qa, qb, 0, true, gr, L_ == 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN},
-                               SBuf<R>{psi, 0}, slots, nslots_, 0, dpart_.as<double>(),
-                               costs_.as<double>(), stream_));
-  QFS_TRY(timer_.end(stream_, 2, 2.0 * state_bytes(ld_)));
   return QFS_OK;
 }
 
 int Group::read_costs(std::vector<double> &ct, std::vector<double> &cv, std::vector<double> *c0) {
   QFS_HIP(hipMemcpyAsync(h_costs_, costs_.ptr, sizeof(double) * 3 * S_, hipMemcpyDeviceToHost, stream_));
   QFS_HIP(hipStreamSynchronize(stream_));
-  if (res_) QFS_TRY(timer_.flush(*res_));
+  if (res_) QFS_TRY(timer_.flush(res_->k));
   for (int s = 0; s < S_; ++s) {
     ct[s] = h_costs_[s];
     cv[s] = h_costs_[S_ + s];
@@ -407,7 +501,7 @@ int Group::run(GroupResult &out, double t_start) {
   }
   M_ = std::max(1, std::min(p_.m_init, m_cap_));
   if (p_.fixed_m) m_cap_ = M_;
-  ld_ = (int)even_up(M_);
+  ldm_ = master_ld(M_);
   fp64_ = p_.precision != QFS_PREC_MIXED;
   timer_.on = p_.timing != 0;
   res_ = &out;
@@ -415,28 +509,29 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_costs_), sizeof(double) * 3 * S_));
   QFS_HIP(hipEventCreate(&ev0_));
   QFS_HIP(hipEventCreate(&ev1_));
-  const int Pcap = 4096;
-  QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)Pcap * S_));
-  QFS_TRY(arena_.alloc(dpart_, sizeof(double) * (size_t)Pcap * S_));
+  QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)kPcap * S_));
+  QFS_TRY(arena_.alloc(dpart_, sizeof(double) * 2 * (size_t)kPcap * S_));
   QFS_TRY(arena_.alloc(costs_, sizeof(double) * 3 * S_));
   QFS_TRY(arena_.alloc(slots_, sizeof(int32_t) * S_));
+  QFS_TRY(arena_.alloc(pairs_dev_, sizeof(int32_t) * 2 * (size_t)L_));
+  QFS_HIP(hipMemcpyAsync(pairs_dev_.ptr, pairs_.data(), sizeof(int32_t) * 2 * L_, hipMemcpyHostToDevice,
+                         stream_));
+  QFS_TRY(launch_zero(costs_.ptr, costs_.bytes, stream_));
 
   // training set and A tensor (computed once per training set)
-  QFS_TRY(arena_.alloc(psi64_, sizeof(c128) * N_ * ld_));
-  QFS_TRY(arena_.alloc(phi64_, sizeof(c128) * N_ * ld_));
+  QFS_TRY(arena_.alloc(psi64_, sizeof(c128) * N_ * ldm_));
+  QFS_TRY(arena_.alloc(phi64_, sizeof(c128) * N_ * ldm_));
   QFS_TRY(launch_zero(psi64_.ptr, psi64_.bytes, stream_));
   if (samples) {
-    QFS_TRY(launch_to_internal<double>(N_, M_, ld_, reinterpret_cast<const c128 *>(tgt_->psi),
+    QFS_TRY(launch_to_internal<double>(n_, M_, ceil_log2(ldm_), 1, reinterpret_cast<const c128 *>(tgt_->psi),
                                        psi64_.as<c128>(), stream_));
-    QFS_TRY(launch_to_internal<double>(N_, M_, ld_, reinterpret_cast<const c128 *>(tgt_->phi),
+    QFS_TRY(launch_to_internal<double>(n_, M_, ceil_log2(ldm_), 1, reinterpret_cast<const c128 *>(tgt_->phi),
                                        phi64_.as<c128>(), stream_));
   } else {
     QFS_TRY(draw_training(0, M_));
-    QFS_TRY(make_targets(psi64_, phi64_, M_, ld_));
+    QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
   }
   QFS_TRY(draw_validation());
-  QFS_TRY(alloc_states());
-  QFS_TRY(refresh_working_copies());
 
   // initial gates (App. A: random per start from the seed, or given)
   QFS_TRY(arena_.alloc(g64_, sizeof(c128) * 16 * (size_t)L_ * S_));
@@ -448,6 +543,23 @@ int Group::run(GroupResult &out, double t_start) {
     QFS_TRY(launch_haar_gates(p_.seed, start0_, S_, L_, g64_.as<c128>(), stream_));
   }
   QFS_TRY(launch_narrow((int64_t)16 * L_ * S_, g64_.as<c128>(), g32_.as<c64>(), stream_));
+  QFS_TRY(arena_.alloc(vstore_, sizeof(c128) * 16 * (size_t)L_ * S_));
+  QFS_TRY(launch_identity4((int64_t)L_ * S_, vstore_.as<c128>(), stream_));
+
+  SweepCtx &c = ctx_;
+  c.slots = slots_.as<int32_t>();
+  c.g64 = g64_.as<c128>();
+  c.g32 = g32_.as<c64>();
+  c.vstore = vstore_.as<c128>();
+  c.beta = p_.beta;
+  c.partials = partials_.as<c128>();
+  c.dpart0 = dpart_.as<double>();
+  c.dpart1 = dpart_.as<double>() + (size_t)kPcap * S_;
+  c.costs = costs_.as<double>();
+  c.S = S_;
+  c.timer = &timer_;
+  c.stream = stream_;
+  QFS_TRY(setup_working());
 
   std::vector<int> status(S_, ST_RUN), reason(S_, QFS_MAX_ITER), iter(S_, 0), z(S_, 0);
   std::vector<int64_t> total(S_, 0);
@@ -540,14 +652,16 @@ int Group::run(GroupResult &out, double t_start) {
     }
     if (any_over) {
       // double-and-restart: extend the training set, keep every gate (App. A)
+      QFS_HIP(hipStreamSynchronize(stream_));
       const int M_new = std::min(2 * M_, m_cap_);
-      const int ld_new = (int)even_up(M_new);
+      const int ld_new = master_ld(M_new);
       DevBuf npsi, nphi;
       QFS_TRY(arena_.alloc(npsi, sizeof(c128) * N_ * ld_new));
       QFS_TRY(arena_.alloc(nphi, sizeof(c128) * N_ * ld_new));
       QFS_TRY(launch_zero(npsi.ptr, npsi.bytes, stream_));
-      QFS_HIP(hipMemcpy2DAsync(npsi.ptr, sizeof(c128) * ld_new, psi64_.ptr, sizeof(c128) * ld_,
+      QFS_HIP(hipMemcpy2DAsync(npsi.ptr, sizeof(c128) * ld_new, psi64_.ptr, sizeof(c128) * ldm_,
                                sizeof(c128) * M_, N_, hipMemcpyDeviceToDevice, stream_));
+      QFS_HIP(hipStreamSynchronize(stream_));
       arena_.free(psi64_);
       arena_.free(phi64_);
       std::swap(psi64_.ptr, npsi.ptr);
@@ -556,22 +670,21 @@ int Group::run(GroupResult &out, double t_start) {
       std::swap(phi64_.bytes, nphi.bytes);
       const int M_old = M_;
       M_ = M_new;
-      ld_ = ld_new;
+      ldm_ = ld_new;
       if (samples) {
-        QFS_TRY(launch_to_internal<double>(N_, M_, ld_, reinterpret_cast<const c128 *>(tgt_->psi),
+        QFS_TRY(launch_to_internal<double>(n_, M_, ceil_log2(ldm_), 1, reinterpret_cast<const c128 *>(tgt_->psi),
                                            psi64_.as<c128>(), stream_));
-        QFS_TRY(launch_to_internal<double>(N_, M_, ld_, reinterpret_cast<const c128 *>(tgt_->phi),
+        QFS_TRY(launch_to_internal<double>(n_, M_, ceil_log2(ldm_), 1, reinterpret_cast<const c128 *>(tgt_->phi),
                                            phi64_.as<c128>(), stream_));
       } else {
         QFS_TRY(draw_training(M_old, M_));
-        QFS_TRY(make_targets(psi64_, phi64_, M_, ld_));
+        QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
         ++generation_;
         arena_.free(psiv64_);
         arena_.free(phiv64_);
         QFS_TRY(draw_validation());
       }
-      QFS_TRY(alloc_states());
-      QFS_TRY(refresh_working_copies());
+      QFS_TRY(setup_working());
       m_total += M_;
       ++restarts;
       active.clear();
@@ -613,8 +726,10 @@ int Group::run(GroupResult &out, double t_start) {
       QFS_TRY(set_slots(active));
     }
     if (switch_now) {
+      QFS_HIP(hipStreamSynchronize(stream_));
       fp64_ = true;
       out.refined = 1;
+      QFS_TRY(setup_working());
       QFS_TRY(forward_any(false));  // B lists again, in complex128, from the FP64 gates
     }
   }
@@ -652,6 +767,7 @@ int run_split(const qfs_template *t, const qfs_target *tg, const qfs_params &p,
     arena.budget = budget;
     Group grp(t, tg, p, gates_in, start0, S, arena);
     r.rc = grp.run(r, t0);
+    if (r.rc != QFS_OK) (void)hipStreamSynchronize(as_stream(p.hip_stream));
   }
   if (r.rc == QFS_ENOMEM && S > 1) {
     (void)hipGetLastError();
@@ -688,6 +804,20 @@ int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, hipStream_t s) 
   return QFS_OK;
 }
 
+// A per-gate (unfused) chunked geometry for the step entry points.
+Geometry api_geometry(int n, int M) {
+  const int logC = choose_log_chunk(n, M, sizeof(double), false, 1, 0);
+  const int C = 1 << logC;
+  return Geometry{n, 1 << n, logC, (M + C - 1) / C, M};
+}
+
+int one_slot(DevBuf &slot, hipStream_t s) {
+  int32_t zero = 0;
+  QFS_TRY(slot.alloc(sizeof(int32_t)));
+  QFS_HIP(hipMemcpyAsync(slot.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  return QFS_OK;
+}
+
 }  // namespace
 }  // namespace qfs
 
@@ -709,7 +839,7 @@ const char *qfs_strerror(int code) {
 
 const char *qfs_last_error_detail(void) { return g_detail.c_str(); }
 
-const char *qfs_version(void) { return "qfs-hip 0.1 (gfx950)"; }
+const char *qfs_version(void) { return "qfs-hip 0.2 (gfx950)"; }
 
 void qfs_default_params(qfs_params *p) {
   if (!p) return;
@@ -732,6 +862,9 @@ void qfs_default_params(qfs_params *p) {
   p->device_mem_budget = 0;
   p->time_budget_s = 0.0;
   p->hip_stream = nullptr;
+  p->timing = 0;
+  p->batch_sweeps = 0;
+  p->batch_threads = 0;
 }
 
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
@@ -799,10 +932,10 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
   for (const auto &x : results) {
     res->start_sweeps += x.start_sweeps;
     res->sweep_seconds += x.sweep_seconds;
-    for (int c = 0; c < 3; ++c) {
-      res->kernel_launches[c] += x.kl[c];
-      res->kernel_seconds[c] += x.ks[c];
-      res->kernel_bytes[c] += x.kb[c];
+    for (int c = 0; c < kClasses; ++c) {
+      res->kernel_launches[c] += x.k.kl[c];
+      res->kernel_seconds[c] += x.k.ks[c];
+      res->kernel_bytes[c] += x.k.kb[c];
     }
   }
   res->seconds = now_s() - t0;
@@ -836,14 +969,14 @@ int qfs_draw_states(int32_t n, int32_t M, uint64_t seed, uint32_t role, uint32_t
                     qfs_c128 *out, void *hip_stream) {
   if (n < 1 || n > 24 || M < 1 || (int64_t)M > (int64_t(1) << n) || !out) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
-  const int64_t N = int64_t(1) << n, ld = even_up(M);
+  const int64_t N = int64_t(1) << n, ld = master_ld(M);
   DevBuf A, W;
   QFS_TRY(A.alloc(sizeof(c128) * N * ld));
   QFS_TRY(launch_zero(A.ptr, A.bytes, s));
   QFS_TRY(launch_ginibre(N, 0, M, ld, seed, role, stream, A.as<c128>(), s));
   QFS_TRY(W.alloc(work_bytes_orth(N, M)));
   QFS_TRY(orthonormalize_columns(N, ld, 0, M, A.as<c128>(), W.ptr, s));
-  QFS_TRY(launch_from_internal<double>(N, M, ld, A.as<c128>(), reinterpret_cast<c128 *>(out), s));
+  QFS_TRY(launch_from_internal<double>(n, M, ceil_log2(ld), A.as<c128>(), reinterpret_cast<c128 *>(out), s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
 }
@@ -856,25 +989,17 @@ int qfs_haar_gates(uint64_t seed, int32_t starts, int32_t L, qfs_c128 *out, void
   return QFS_OK;
 }
 
-static int one_slot(DevBuf &slot, hipStream_t s) {
-  int32_t zero = 0;
-  QFS_TRY(slot.alloc(sizeof(int32_t)));
-  QFS_HIP(hipMemcpyAsync(slot.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  return QFS_OK;
-}
-
 int qfs_apply_gates(int32_t n, int32_t M, qfs_c128 *states, int32_t L, const int32_t *pairs,
                     const qfs_c128 *gates, int32_t dagger, void *hip_stream) {
   qfs_template t{n, L, pairs};
   QFS_TRY(validate_template(&t));
   if (M < 1 || !states || !gates) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
-  const int64_t N = int64_t(1) << n, ld = even_up(M);
+  const Geometry g = api_geometry(n, M);
   DevBuf A, slot;
-  QFS_TRY(A.alloc(sizeof(c128) * N * ld));
+  QFS_TRY(A.alloc(sizeof(c128) * g.elems()));
   QFS_TRY(one_slot(slot, s));
-  QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(states), A.as<c128>(), s));
-  Geometry g{n, (int32_t)N, (int32_t)ld, M};
+  QFS_TRY(launch_to_internal<double>(n, M, g.logC, g.nch, reinterpret_cast<const c128 *>(states), A.as<c128>(), s));
   GateRef gr{reinterpret_cast<const c128 *>(gates), gates, 0};
   for (int i = 0; i < L; ++i) {
     const int k = dagger ? L - 1 - i : i;
@@ -882,7 +1007,7 @@ int qfs_apply_gates(int32_t n, int32_t M, qfs_c128 *states, int32_t L, const int
                                  SBuf<double>{A.as<c128>(), 0}, SBuf<double>{A.as<c128>(), 0},
                                  slot.as<int32_t>(), 1, s));
   }
-  QFS_TRY(launch_from_internal<double>(N, M, ld, A.as<c128>(), reinterpret_cast<c128 *>(states), s));
+  QFS_TRY(launch_from_internal<double>(n, M, g.logC, A.as<c128>(), reinterpret_cast<c128 *>(states), s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
 }
@@ -891,14 +1016,14 @@ int qfs_dense_apply(int32_t n, int32_t M, const qfs_c128 *U, const qfs_c128 *psi
                     void *hip_stream) {
   if (n < 1 || n > 16 || M < 1 || !U || !psi || !out) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
-  const int64_t N = int64_t(1) << n, ld = even_up(M);
+  const int64_t N = int64_t(1) << n, ld = master_ld(M);
   DevBuf A, B;
   QFS_TRY(A.alloc(sizeof(c128) * N * ld));
   QFS_TRY(B.alloc(sizeof(c128) * N * ld));
-  QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(psi), A.as<c128>(), s));
+  QFS_TRY(launch_to_internal<double>(n, M, ceil_log2(ld), 1, reinterpret_cast<const c128 *>(psi), A.as<c128>(), s));
   QFS_TRY(launch_zgemm(false, (int)N, (int)ld, (int)N, cmake(1.0, 0.0), reinterpret_cast<const c128 *>(U),
                        (int)N, A.as<c128>(), (int)ld, cmake(0.0, 0.0), B.as<c128>(), (int)ld, s));
-  QFS_TRY(launch_from_internal<double>(N, M, ld, B.as<c128>(), reinterpret_cast<c128 *>(out), s));
+  QFS_TRY(launch_from_internal<double>(n, M, ceil_log2(ld), B.as<c128>(), reinterpret_cast<c128 *>(out), s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
 }
@@ -910,21 +1035,21 @@ int qfs_environment(int32_t n, int32_t M, const qfs_c128 *a, const qfs_c128 *b, 
   QFS_TRY(validate_template(&t));
   if (M < 1 || !a || !b || !gamma) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
-  const int64_t N = int64_t(1) << n, ld = even_up(M);
+  const Geometry g = api_geometry(n, M);
   DevBuf A, B, slot, part;
-  QFS_TRY(A.alloc(sizeof(c128) * N * ld));
-  QFS_TRY(B.alloc(sizeof(c128) * N * ld));
-  QFS_TRY(part.alloc(sizeof(c128) * 16 * 4096));
+  QFS_TRY(A.alloc(sizeof(c128) * g.elems()));
+  QFS_TRY(B.alloc(sizeof(c128) * g.elems()));
+  QFS_TRY(part.alloc(sizeof(c128) * 16 * kPcap));
   QFS_TRY(one_slot(slot, s));
-  QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(a), A.as<c128>(), s));
-  QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(b), B.as<c128>(), s));
-  Geometry g{n, (int32_t)N, (int32_t)ld, M};
+  QFS_TRY(launch_to_internal<double>(n, M, g.logC, g.nch, reinterpret_cast<const c128 *>(a), A.as<c128>(), s));
+  QFS_TRY(launch_to_internal<double>(n, M, g.logC, g.nch, reinterpret_cast<const c128 *>(b), B.as<c128>(), s));
   GateRef gr{nullptr, nullptr, 0};
-  StepScratch sc{part.as<c128>(), reinterpret_cast<c128 *>(gamma)};
-  QFS_TRY(launch_bwd_step<double>(g, pr, -1, 0, gr, nullptr, nullptr, 0.0,
-                                  SBuf<double>{A.as<c128>(), 0}, SBuf<double>{A.as<c128>(), 0},
-                                  SBuf<double>{B.as<c128>(), 0}, slot.as<int32_t>(), 1, 0, sc,
-                                  false, s));
+  int P = 0;
+  QFS_TRY(launch_bwd_step<double>(g, pr, -1, 0, gr, SBuf<double>{A.as<c128>(), 0},
+                                  SBuf<double>{A.as<c128>(), 0}, SBuf<double>{B.as<c128>(), 0},
+                                  slot.as<int32_t>(), 1, part.as<c128>(), &P, s));
+  QFS_TRY(launch_env_finalize(P, part.as<c128>(), slot.as<int32_t>(), 1, reinterpret_cast<c128 *>(gamma),
+                              false, 0.0, nullptr, nullptr, 0, 0, nullptr, s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
 }
@@ -943,20 +1068,21 @@ int qfs_state_distance(int32_t n, int32_t M, const qfs_c128 *x, const qfs_c128 *
                        void *hip_stream) {
   if (n < 2 || n > 24 || M < 1 || !x || !y || !result) return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
-  const int64_t N = int64_t(1) << n, ld = even_up(M);
+  const Geometry g = api_geometry(n, M);
   DevBuf A, B, slot, part, out;
-  QFS_TRY(A.alloc(sizeof(c128) * N * ld));
-  QFS_TRY(B.alloc(sizeof(c128) * N * ld));
-  QFS_TRY(part.alloc(sizeof(double) * 4096));
+  QFS_TRY(A.alloc(sizeof(c128) * g.elems()));
+  QFS_TRY(B.alloc(sizeof(c128) * g.elems()));
+  QFS_TRY(part.alloc(sizeof(double) * kPcap));
   QFS_TRY(out.alloc(16));
   QFS_TRY(one_slot(slot, s));
-  QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(x), A.as<c128>(), s));
-  QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(y), B.as<c128>(), s));
-  Geometry g{n, (int32_t)N, (int32_t)ld, M};
+  QFS_TRY(launch_to_internal<double>(n, M, g.logC, g.nch, reinterpret_cast<const c128 *>(x), A.as<c128>(), s));
+  QFS_TRY(launch_to_internal<double>(n, M, g.logC, g.nch, reinterpret_cast<const c128 *>(y), B.as<c128>(), s));
   GateRef gr{nullptr, nullptr, 0};
+  int P = 0;
   QFS_TRY(launch_apply_dist<double>(g, 0, 1, -1, false, gr, SBuf<double>{A.as<c128>(), 0},
-                                    SBuf<double>{B.as<c128>(), 0}, slot.as<int32_t>(), 1, 0,
-                                    part.as<double>(), out.as<double>(), s));
+                                    SBuf<double>{B.as<c128>(), 0}, slot.as<int32_t>(), 1,
+                                    part.as<double>(), &P, s));
+  QFS_TRY(launch_dist_finalize(P, part.as<double>(), slot.as<int32_t>(), 1, M, out.as<double>(), s));
   QFS_HIP(hipMemcpyAsync(result, out.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
@@ -971,63 +1097,68 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c
       (precision != QFS_PREC_FP64 && precision != QFS_PREC_MIXED) || !(beta >= 0 && beta <= 1))
     return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
-  const int64_t N = int64_t(1) << n, ld = even_up(M);
   const bool f32 = precision == QFS_PREC_MIXED;
-  const size_t b = f32 ? sizeof(c64) : sizeof(c128);
-  DevBuf ps, ph, Bl, As, g32, slots, part, dpart, costs;
-  QFS_TRY(ps.alloc(b * N * ld));
-  QFS_TRY(ph.alloc(b * N * ld));
-  QFS_TRY(Bl.alloc(b * N * ld * (size_t)std::max(L - 1, 1) * starts));
-  QFS_TRY(As.alloc(b * N * ld * starts));
+  const size_t rb = f32 ? sizeof(float) : sizeof(double), cb = 2 * rb;
+  const size_t lds = lds_max_bytes();
+  const bool fused = forward_fusable(n, rb, lds);
+  const int logC = choose_log_chunk(n, M, rb, fused, starts, lds);
+  const int C = 1 << logC;
+  SweepCtx c;
+  c.n = n;
+  c.L = L;
+  c.pairs_host = pairs;
+  c.g = Geometry{n, 1 << n, logC, (M + C - 1) / C, M};
+  c.gv = Geometry{n, 1 << n, logC, 1, 0};
+  c.fused = fused;
+  c.beta = beta;
+  c.S = starts;
+  KernelTimer timer;
+  c.timer = &timer;
+  c.stream = s;
+  const size_t set = (size_t)c.g.elems() * cb;
+  DevBuf ps, ph, Bl, As, g32, slots, part, dpart, costs, pdev;
+  QFS_TRY(ps.alloc(set));
+  QFS_TRY(ph.alloc(set));
+  QFS_TRY(Bl.alloc(set * (size_t)std::max(L - 1, 1) * starts));
+  QFS_TRY(As.alloc(set * starts));
   QFS_TRY(g32.alloc(sizeof(c64) * 16 * (size_t)L * starts));
   QFS_TRY(slots.alloc(sizeof(int32_t) * starts));
-  QFS_TRY(part.alloc(sizeof(c128) * 16 * 4096 * (size_t)starts));
-  QFS_TRY(dpart.alloc(sizeof(double) * 4096 * (size_t)starts));
-  QFS_TRY(costs.alloc(sizeof(double) * starts));
+  QFS_TRY(part.alloc(sizeof(c128) * 16 * kPcap * (size_t)starts));
+  QFS_TRY(dpart.alloc(sizeof(double) * 2 * kPcap * (size_t)starts));
+  QFS_TRY(costs.alloc(sizeof(double) * 3 * starts));
+  QFS_TRY(pdev.alloc(sizeof(int32_t) * 2 * L));
+  QFS_HIP(hipMemcpyAsync(pdev.ptr, pairs, sizeof(int32_t) * 2 * L, hipMemcpyHostToDevice, s));
   std::vector<int32_t> sl(starts);
   for (int i = 0; i < starts; ++i) sl[i] = i;
   QFS_HIP(hipMemcpyAsync(slots.ptr, sl.data(), sizeof(int32_t) * starts, hipMemcpyHostToDevice, s));
   if (f32) {
-    QFS_TRY(launch_to_internal<float>(N, M, ld, reinterpret_cast<const c128 *>(psi), ps.as<c64>(), s));
-    QFS_TRY(launch_to_internal<float>(N, M, ld, reinterpret_cast<const c128 *>(phi), ph.as<c64>(), s));
+    QFS_TRY(launch_to_internal<float>(n, M, logC, c.g.nch, reinterpret_cast<const c128 *>(psi), ps.as<c64>(), s));
+    QFS_TRY(launch_to_internal<float>(n, M, logC, c.g.nch, reinterpret_cast<const c128 *>(phi), ph.as<c64>(), s));
     QFS_TRY(launch_narrow((int64_t)16 * L * starts, reinterpret_cast<const c128 *>(gates), g32.as<c64>(), s));
   } else {
-    QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(psi), ps.as<c128>(), s));
-    QFS_TRY(launch_to_internal<double>(N, M, ld, reinterpret_cast<const c128 *>(phi), ph.as<c128>(), s));
+    QFS_TRY(launch_to_internal<double>(n, M, logC, c.g.nch, reinterpret_cast<const c128 *>(psi), ps.as<c128>(), s));
+    QFS_TRY(launch_to_internal<double>(n, M, logC, c.g.nch, reinterpret_cast<const c128 *>(phi), ph.as<c128>(), s));
   }
-  Geometry g{n, (int32_t)N, (int32_t)ld, M};
-  c128 *g64 = reinterpret_cast<c128 *>(gates);
-  GateRef gr{g64, f32 ? g32.ptr : static_cast<void *>(g64), L * 16};
-  const int64_t sN = N * ld;
-  const int64_t bstride = sN * std::max(L - 1, 1);
-  const int32_t *sp = slots.as<int32_t>();
-  StepScratch sc{part.as<c128>(), nullptr};
-  auto run = [&](auto tag) -> int {
-    using R = decltype(tag);
-    cx<R> *P0 = static_cast<cx<R> *>(ps.ptr), *F0 = static_cast<cx<R> *>(ph.ptr);
-    cx<R> *Bp = static_cast<cx<R> *>(Bl.ptr), *Ap = static_cast<cx<R> *>(As.ptr);
-    for (int k = 1; k < L; ++k) {
-      SBuf<R> src = k == 1 ? SBuf<R>{P0, 0} : SBuf<R>{Bp + (k - 2) * sN, bstride};
-      QFS_TRY(launch_apply<R>(g, pairs[2 * (k - 1)], pairs[2 * (k - 1) + 1], k - 1, false, gr, src,
-                              SBuf<R>{Bp + (k - 1) * sN, bstride}, sp, starts, s));
-    }
-    for (int k = L - 1; k >= 0; --k) {
-      const int ka = (k == L - 1) ? -1 : k + 1;
-      SBuf<R> a_in = (k >= L - 2) ? SBuf<R>{F0, 0} : SBuf<R>{Ap, sN};
-      SBuf<R> bb = k == 0 ? SBuf<R>{P0, 0} : SBuf<R>{Bp + (k - 1) * sN, bstride};
-      QFS_TRY(launch_bwd_step<R>(g, pairs, ka, k, gr, g64, f32 ? g32.ptr : nullptr, beta, a_in,
-                                 SBuf<R>{Ap, sN}, bb, sp, starts, 0, sc, true, s));
-    }
-    QFS_TRY(launch_apply_dist<R>(g, pairs[0], pairs[1], 0, true, gr,
-                                 L == 1 ? SBuf<R>{F0, 0} : SBuf<R>{Ap, sN}, SBuf<R>{P0, 0}, sp,
-                                 starts, 0, dpart.as<double>(),
-                                 costs.as<double>(), s));
-    return QFS_OK;
-  };
-  if (f32)
-    QFS_TRY(run(float{}));
-  else
-    QFS_TRY(run(double{}));
+  c.pairs_dev = pdev.as<int32_t>();
+  c.slots = slots.as<int32_t>();
+  c.nslots = starts;
+  c.g64 = reinterpret_cast<c128 *>(gates);
+  c.g32 = g32.as<c64>();
+  c.psi = ps.ptr;
+  c.phi = ph.ptr;
+  c.blist = Bl.ptr;
+  c.astate = As.ptr;
+  c.partials = part.as<c128>();
+  c.dpart0 = dpart.as<double>();
+  c.dpart1 = dpart.as<double>() + (size_t)kPcap * starts;
+  c.costs = costs.as<double>();
+  if (f32) {
+    QFS_TRY(sweep_forward<float>(c, false));
+    QFS_TRY(sweep_backward<float>(c));
+  } else {
+    QFS_TRY(sweep_forward<double>(c, false));
+    QFS_TRY(sweep_backward<double>(c));
+  }
   QFS_HIP(hipMemcpyAsync(c_train, costs.ptr, sizeof(double) * starts, hipMemcpyDeviceToHost, s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;

@@ -202,11 +202,13 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
 }
 
 // ------------------------------------------------------------------ layout conversions
-// sample-major [M][N] c128 -> amplitude-major [N][ld] (32x32 LDS transpose tiles).
+// sample-major [M][N] c128 -> chunked amplitude-major (32x32 LDS transpose tiles);
+// element (i, j) of the chunked set is at (j >> logC) * N * C + i * C + (j & (C - 1)).
 template <typename R>
-__global__ __launch_bounds__(256) void k_to_internal(int64_t N, int64_t M, int64_t ld,
+__global__ __launch_bounds__(256) void k_to_internal(int n, int64_t M, int logC, int64_t cols,
                                                      const c128 *src, cx<R> *dst) {
   __shared__ c128 tile[32][33];
+  const int64_t N = int64_t(1) << n;
   const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows per pass
   for (int r = ty; r < 32; r += 8) {
@@ -216,23 +218,25 @@ __global__ __launch_bounds__(256) void k_to_internal(int64_t N, int64_t M, int64
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int64_t i = i0 + r, j = j0 + tx;
-    if (i < N && j < ld) {
+    if (i < N && j < cols) {
       const c128 v = tile[tx][r];
-      dst[i * ld + j] = cmake<R>((R)v.re, (R)v.im);
+      dst[((j >> logC) << (n + logC)) + (i << logC) + (j & ((1 << logC) - 1))] =
+          cmake<R>((R)v.re, (R)v.im);
     }
   }
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_from_internal(int64_t N, int64_t M, int64_t ld,
-                                                       const cx<R> *src, c128 *dst) {
+__global__ __launch_bounds__(256) void k_from_internal(int n, int64_t M, int logC, const cx<R> *src,
+                                                       c128 *dst) {
   __shared__ c128 tile[32][33];
+  const int64_t N = int64_t(1) << n;
   const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int r = ty; r < 32; r += 8) {
     const int64_t i = i0 + r, j = j0 + tx;
     if (i < N && j < M) {
-      const cx<R> v = src[i * ld + j];
+      const cx<R> v = src[((j >> logC) << (n + logC)) + (i << logC) + (j & ((1 << logC) - 1))];
       tile[r][tx] = cmake<double>(v.re, v.im);
     }
   }
@@ -244,27 +248,28 @@ __global__ __launch_bounds__(256) void k_from_internal(int64_t N, int64_t M, int
 }
 
 template <typename R>
-int launch_to_internal(int64_t N, int64_t M, int64_t ld, const c128 *src, cx<R> *dst,
+int launch_to_internal(int n, int64_t M, int logC, int64_t nch, const c128 *src, cx<R> *dst,
                        hipStream_t s) {
-  dim3 grid((unsigned)((N + 31) / 32), (unsigned)((ld + 31) / 32));
-  hipLaunchKernelGGL(k_to_internal<R>, grid, dim3(256), 0, s, N, M, ld, src, dst);
+  const int64_t N = int64_t(1) << n, cols = nch << logC;
+  dim3 grid((unsigned)((N + 31) / 32), (unsigned)((cols + 31) / 32));
+  hipLaunchKernelGGL(k_to_internal<R>, grid, dim3(256), 0, s, n, M, logC, cols, src, dst);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
 
 template <typename R>
-int launch_from_internal(int64_t N, int64_t M, int64_t ld, const cx<R> *src, c128 *dst,
-                         hipStream_t s) {
+int launch_from_internal(int n, int64_t M, int logC, const cx<R> *src, c128 *dst, hipStream_t s) {
+  const int64_t N = int64_t(1) << n;
   dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
-  hipLaunchKernelGGL(k_from_internal<R>, grid, dim3(256), 0, s, N, M, ld, src, dst);
+  hipLaunchKernelGGL(k_from_internal<R>, grid, dim3(256), 0, s, n, M, logC, src, dst);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
 
-template int launch_to_internal<float>(int64_t, int64_t, int64_t, const c128 *, c64 *, hipStream_t);
-template int launch_to_internal<double>(int64_t, int64_t, int64_t, const c128 *, c128 *, hipStream_t);
-template int launch_from_internal<float>(int64_t, int64_t, int64_t, const c64 *, c128 *, hipStream_t);
-template int launch_from_internal<double>(int64_t, int64_t, int64_t, const c128 *, c128 *, hipStream_t);
+template int launch_to_internal<float>(int, int64_t, int, int64_t, const c128 *, c64 *, hipStream_t);
+template int launch_to_internal<double>(int, int64_t, int, int64_t, const c128 *, c128 *, hipStream_t);
+template int launch_from_internal<float>(int, int64_t, int, const c64 *, c128 *, hipStream_t);
+template int launch_from_internal<double>(int, int64_t, int, const c128 *, c128 *, hipStream_t);
 
 __global__ void k_narrow(int64_t count, const c128 *src, c64 *dst) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;

@@ -150,18 +150,17 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
                            void *work, hipStream_t s);
 
 // Layout conversions (linalg.hip)
-// sample-major [M][N] c128  <->  amplitude-major [N][ld] in R (zero padding).
+// sample-major [M][N] c128  <->  chunked amplitude-major layout in R (zero padding).
 template <typename R>
-int launch_to_internal(int64_t N, int64_t M, int64_t ld, const c128 *src, cx<R> *dst,
+int launch_to_internal(int n, int64_t M, int logC, int64_t nch, const c128 *src, cx<R> *dst,
                        hipStream_t s);
 template <typename R>
-int launch_from_internal(int64_t N, int64_t M, int64_t ld, const cx<R> *src, c128 *dst,
-                         hipStream_t s);
+int launch_from_internal(int n, int64_t M, int logC, const cx<R> *src, c128 *dst, hipStream_t s);
 int launch_narrow(int64_t count, const c128 *src, c64 *dst, hipStream_t s);
 int launch_zero(void *p, size_t bytes, hipStream_t s);
 
 // ------------------------------------------------------------------ sweep kernels
-// Per-start addressing for the sweep kernels: a buffer "X" of starts is at
+// Per-start addressing for the sweep kernels: a buffer of starts is at
 // base + stride * start (elements); stride 0 means shared by all starts.
 template <typename R>
 struct SBuf {
@@ -175,40 +174,71 @@ struct GateRef {
   int32_t gstride;   // L * 16
 };
 
+// A chunked state set: nch chunks of C = 2^logC samples, each chunk N x C row-major;
+// element (i, j) at (j >> logC) * N * C + i * C + (j & (C - 1)). M live samples, the
+// padding samples are zero.
 struct Geometry {
   int32_t n;       // qubits
   int32_t N;       // 2^n
-  int32_t ld;      // leading dimension (even, >= M)
-  int32_t M;       // live columns (<= ld); padding columns are zero
+  int32_t logC;    // log2 chunk width (>= 1)
+  int32_t nch;     // chunks
+  int32_t M;       // live samples
+  int64_t elems() const { return (int64_t)nch << (n + logC); }
 };
 
-// Forward / generic apply: dst_s = op(u_s[k]) src_s on qubits (qa, qb), for the
-// slots [0, nslots) mapped to starts by slot_to_start (device).
+// Chunk width: the fused forward pass needs a whole chunk in LDS (N * C complex);
+// otherwise chunks of up to 32 samples keep rows coalesced.
+int choose_log_chunk(int n, int M, size_t rbytes, bool fused, int starts, size_t lds_max);
+bool forward_fusable(int n, size_t rbytes, size_t lds_max);
+size_t forward_lds_bytes(int n, int logC, size_t rbytes);
+
+// Per-gate apply: dst_s = op(u_s[k]) src_s on qubits (qa, qb), for the slots
+// [0, nslots) mapped to starts by slot_to_start (device).
 template <typename R>
 int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
                  SBuf<R> src, SBuf<R> dst, const int32_t *slot_to_start, int nslots,
                  hipStream_t s);
 
+// Fused forward pass for every slot: B list (B_{k+1} at list index k, k < L-1) from
+// psi; optionally the Eq. 9 distance of the full circuit against phi_ref (block
+// partials [S][g.nch]); optionally the validation set through all L gates with its
+// distance partials [S][gv->nch]. pairs_dev: device [L][2].
+template <typename R>
+int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *pairs_dev, int L,
+                         GateRef gates, const cx<R> *psi, cx<R> *blist, int64_t bstride,
+                         const cx<R> *phi_ref, double *c0_partials, const cx<R> *psiv,
+                         const cx<R> *phiv, double *val_partials, const int32_t *slot_to_start,
+                         int nslots, hipStream_t s);
+
+template <typename R>
+int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, hipStream_t s);
+
 // Backward step: optionally a_s <- u_s[k_apply]^dagger a_s (qubits of k_apply), then
-// Gamma_s = environment of gate k_env from a_s and b_s as per-block FP64 partial sums;
-// a second kernel (one wave per start) reduces them in a fixed order and writes
-// u_s[k_env] <- polar((1-beta)Gamma + beta u) to both gate copies. Optionally stores
-// Gamma (FP64) to gamma_out[s].
-struct StepScratch {
-  c128 *partials;        // [S][P][16]
-  c128 *gamma_out;       // optional [S][16]
-};
+// the environment of gate k_env from a_s and b_s as per-block FP64 partial sums
+// [S][P][16] (P returned). launch_env_finalize (one wave per start) reduces them in a
+// fixed order and writes u_s[k_env] <- polar((1-beta) Gamma + beta u) to both gate
+// copies; optionally stores Gamma (FP64) to gamma_out[s].
 template <typename R>
 int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
-                    GateRef gates, c128 *g64_mut, void *gR_mut, double beta,
-                    SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b, const int32_t *slot_to_start,
-                    int nslots, int P, StepScratch sc, bool do_update, hipStream_t s);
+                    GateRef gates, SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b,
+                    const int32_t *slot_to_start, int nslots, c128 *partials, int *P_out,
+                    hipStream_t s);
+// vstore (nullable, [S][L][16]): right singular vectors of each gate's last update,
+// used to warm-start the Jacobi iteration and updated in place.
+int launch_env_finalize(int P, const c128 *partials, const int32_t *slot_to_start, int nslots,
+                        c128 *gamma_out, bool do_update, double beta, c128 *g64, c64 *g32,
+                        int32_t gstride, int32_t k_env, c128 *vstore, hipStream_t s);
+// count 4x4 identity matrices.
+int launch_identity4(int64_t count, c128 *v, hipStream_t s);
 
-// out[s] = (1/M) sum ||op(u_s[k]) x_s - ref_s||^2 (FP64 accumulation); k < 0: no gate.
+// Block partials of sum ||op(u_s[k]) x_s - ref_s||^2 (k < 0: no gate), P returned;
+// launch_dist_finalize writes out[s] = (1/M) * (fixed-order sum).
 template <typename R>
 int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
-                      SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots, int P,
-                      double *partials, double *out, hipStream_t s);
+                      SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots,
+                      double *partials, int *P_out, hipStream_t s);
+int launch_dist_finalize(int P, const double *partials, const int32_t *slot_to_start, int nslots,
+                         int M, double *out, hipStream_t s);
 
 // Batched polar update on device (count problems).
 int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipStream_t s);

@@ -1,16 +1,19 @@
 // Sweep kernels of QFactor-Sample (Sec. 3; Fig. pre-comp; Fig. env_calc_tensor).
 //
-// All kernels stream state sets in the amplitude-major layout (see qfs_internal.h):
-// a "packet" is 16 bytes of consecutive samples of one amplitude (two complex64 or
-// one complex128), so every load and store is a 16-byte vector access and a wave
-// covers contiguous runs of memory whatever qubits a gate acts on.
+// State sets use the chunked amplitude-major layout (see qfs_internal.h): element
+// (amplitude i, sample j) of a set lives at (j / C) * N * C + i * C + (j % C), C a power
+// of two. A "packet" is 16 bytes of consecutive samples of one amplitude (two complex64
+// or one complex128), so every access is a 16-byte vector access and a wave covers
+// contiguous memory whatever qubits a gate acts on.
 //
-// Work decomposition: grid = (P blocks, active starts). Each thread owns "super
-// groups": the 2^t amplitudes closed under the t <= 4 bit positions touched by the
-// gate it applies and the gate whose environment it accumulates, times one packet of
-// samples. Environments are reduced thread -> wave (cross-lane shuffles) -> block
-// (LDS, FP64) -> start (the last block to finish reads every block's FP64 partial in
-// a fixed order, then runs the 4x4 FP64 polar update on one wave).
+// Forward pass: one block per (chunk of C samples, start) holds the whole chunk in LDS,
+// applies the gates in order and streams each intermediate state B_k to HBM straight
+// from registers; validation states go through every gate without leaving LDS.
+// Backward pass: grid = (P blocks, active starts); each thread owns "super groups": the
+// 2^t amplitudes closed under the t <= 4 bit positions of the gate it applies (u^dag)
+// and of the gate whose environment it accumulates. Environments are reduced thread ->
+// wave (cross-lane shuffles) -> block (LDS, FP64 partial); a one-wave-per-start kernel
+// then sums the block partials in a fixed order and runs the FP64 polar update.
 #include <algorithm>
 
 #include "qfs_internal.h"
@@ -21,17 +24,20 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kFwdBlock = 512;
 
 template <typename R>
 struct Pk;  // 16-byte packet of samples
 template <>
 struct Pk<float> {
   static constexpr int V = 2;
+  static constexpr int LOGV = 1;
   c64 v[2];
 };
 template <>
 struct Pk<double> {
   static constexpr int V = 1;
+  static constexpr int LOGV = 0;
   c128 v[1];
 };
 
@@ -56,10 +62,10 @@ __device__ __forceinline__ void st_pk(c128 *p, const Pk<double> &r) {
 }
 
 // Insert a zero bit at each of the t ascending positions.
-__device__ __forceinline__ int64_t deposit(int64_t r, const int *sorted_pos, int t) {
+__device__ __forceinline__ uint32_t deposit(uint32_t r, const int *sorted_pos, int t) {
   for (int m = 0; m < t; ++m) {
     const int p = sorted_pos[m];
-    const int64_t low = r & ((int64_t(1) << p) - 1);
+    const uint32_t low = r & ((1u << p) - 1u);
     r = ((r >> p) << (p + 1)) | low;
   }
   return r;
@@ -89,13 +95,23 @@ __device__ __forceinline__ constexpr int var_bits() {
   return VAR <= 1 ? 2 : (VAR <= 5 ? 3 : 4);
 }
 
-struct StepGeom {
-  int32_t ld, M, t;
-  int32_t sorted_pos[4];
-  int32_t off[16];  // amplitude-index offset of each local index
-  int64_t items;    // super groups x packets per row
-  int32_t J;        // packets per row
+// Chunked index decomposition shared by the streaming kernels: item ->
+// (chunk q, super group r, packet jv), packets fastest.
+struct ChunkGeom {
+  int32_t logC;     // log2 chunk width
+  int32_t logJ;     // log2 packets per chunk row (C / V)
+  int32_t logG;     // log2 super groups per chunk (n - t)
+  int32_t n;
+  uint32_t items;   // nch << (logG + logJ)
 };
+
+__device__ __forceinline__ void split_item(uint32_t it, const ChunkGeom &cg, uint32_t &q,
+                                           uint32_t &r, uint32_t &jv) {
+  jv = it & ((1u << cg.logJ) - 1u);
+  const uint32_t rest = it >> cg.logJ;
+  r = rest & ((1u << cg.logG) - 1u);
+  q = rest >> cg.logG;
+}
 
 template <typename R>
 __device__ __forceinline__ void load_gate(const cx<R> *src, cx<R> (&u)[16], bool dagger) {
@@ -112,16 +128,56 @@ __device__ __forceinline__ void load_gate(const cx<R> *src, cx<R> (&u)[16], bool
 // are summed over the four rows of a quad, so both columns' lanes compute bitwise
 // equal rotations. Then W = normalised columns of G (re-orthonormalised and completed
 // when a singular value is negligible) and u = W V^dagger.
+//
+// Warm start (vstore != nullptr): Jacobi starts from G V_prev and V_prev, the right
+// singular vectors this gate had after its previous update (the environment changes
+// little between sweeps), so it converges in one or two sweeps instead of ~6. V_prev is
+// first made unitary to rounding by one Newton-Schulz step V (3I - V^dag V) / 2, so no
+// error accumulates across sweeps; the new V is stored back.
+__device__ __forceinline__ c128 shfl_c(c128 x, int src) {
+  return cmake(__shfl(x.re, src), __shfl(x.im, src));
+}
+__device__ __forceinline__ c128 quad_sum(c128 x) {
+  x.re += __shfl_xor(x.re, 1);
+  x.im += __shfl_xor(x.im, 1);
+  x.re += __shfl_xor(x.re, 2);
+  x.im += __shfl_xor(x.im, 2);
+  return x;
+}
+
 __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
-                            c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s) {
+                            c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s,
+                            c128 *vstore = nullptr) {
   const int lane = threadIdx.x & 63;
-  const int l = lane & 15, c = l >> 2, r = l & 3;
-  c128 g = G[r * 4 + c];
-  if (beta != 0.0) {
-    const c128 up = u_prev[r * 4 + c];
-    g = cmake((1.0 - beta) * g.re + beta * up.re, (1.0 - beta) * g.im + beta * up.im);
+  const int l = lane & 15, c = l >> 2, r = l & 3, base = lane & ~15;
+  auto gm = [&](int row, int col) {
+    c128 x = G[row * 4 + col];
+    if (beta != 0.0) {
+      const c128 up = u_prev[row * 4 + col];
+      x = cmake((1.0 - beta) * x.re + beta * up.re, (1.0 - beta) * x.im + beta * up.im);
+    }
+    return x;
+  };
+  c128 g, v;
+  if (vstore) {
+    // lane 4c + r holds X[r][c]; Y[a][c] = sum_k conj(X[k][a]) X[k][c] (quad c);
+    // Z[r][c] = (3 X[r][c] - sum_a X[r][a] Y[a][c]) / 2
+    const c128 x = vstore[r * 4 + c];
+    c128 acc = cmake(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const c128 xca = shfl_c(x, base + 4 * a + r);  // X[r][a]
+      const c128 yac = quad_sum(cconj(xca) * x);     // Y[a][c]
+      cfma(acc, xca, yac);
+    }
+    v = cmake(0.5 * (3.0 * x.re - acc.re), 0.5 * (3.0 * x.im - acc.im));
+    g = cmake(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cfma(g, gm(r, k), shfl_c(v, base + 4 * c + k));  // (G V)[r][c]
+  } else {
+    g = gm(r, c);
+    v = cmake(r == c ? 1.0 : 0.0, 0.0);
   }
-  c128 v = cmake(r == c ? 1.0 : 0.0, 0.0);
   bool converged = false;
   for (int sweep = 0; sweep < 40; ++sweep) {
     int rotated = 0;
@@ -190,6 +246,7 @@ __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128
     if (lane < 16) {
       out64[l] = acc;
       if (out32) out32[l] = cmake<float>((float)acc.re, (float)acc.im);
+      if (vstore) vstore[r * 4 + c] = v;
     }
     return;
   }
@@ -199,6 +256,7 @@ __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128
     lds_g[c * 4 + r] = g;
     lds_v[c * 4 + r] = v;
     if (r == 0) lds_s[c] = sig;
+    if (vstore) vstore[r * 4 + c] = v;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -268,24 +326,21 @@ __device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128
   }
 }
 
-// ------------------------------------------------------------------ forward apply
+
+// ------------------------------------------------------------------ per-gate apply
 template <typename R>
 struct ApplySeg {
   const cx<R> *src;
   int64_t src_stride;
   cx<R> *dst;
   int64_t dst_stride;
-  int32_t ld;
-  int32_t J;
-  int64_t items;
+  ChunkGeom cg;
 };
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_apply(ApplySeg<R> seg0, ApplySeg<R> seg1, int pa,
-                                                  int pb, const cx<R> *gates, int32_t gstride,
-                                                  int k, int dagger,
-                                                  const int32_t *slot_to_start) {
-  const ApplySeg<R> sg = blockIdx.z == 0 ? seg0 : seg1;
+__global__ __launch_bounds__(kBlock) void k_apply(ApplySeg<R> sg, int pa, int pb,
+                                                  const cx<R> *gates, int32_t gstride, int k,
+                                                  int dagger, const int32_t *slot_to_start) {
   const int s = slot_to_start[blockIdx.y];
   cx<R> u[16];
   load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, dagger != 0);
@@ -293,37 +348,136 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplySeg<R> seg0, ApplySeg<R> 
   cx<R> *dst = sg.dst + sg.dst_stride * s;
   const int lo = min(pa, pb), hi = max(pa, pb);
   const int sorted[2] = {lo, hi};
-  const int64_t ma = int64_t(1) << pa, mb = int64_t(1) << pb;
   constexpr int V = Pk<R>::V;
-  for (int64_t it = blockIdx.x * (int64_t)kBlock + threadIdx.x; it < sg.items;
-       it += (int64_t)gridDim.x * kBlock) {
-    const int64_t rr = it / sg.J;
-    const int jv = (int)(it - rr * sg.J);
-    const int64_t i0 = deposit(rr, sorted, 2);
+  const int logC = sg.cg.logC, n = sg.cg.n;
+  const uint32_t ma = 1u << pa, mb = 1u << pb;
+  for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < sg.cg.items; it += gridDim.x * kBlock) {
+    uint32_t q, rr, jv;
+    split_item(it, sg.cg, q, rr, jv);
+    const uint32_t i0 = deposit(rr, sorted, 2);
+    const int64_t base = ((int64_t)q << (n + logC)) + jv * V;
     int64_t o[4];
-    o[0] = i0 * sg.ld + jv * V;
-    o[1] = (i0 + mb) * sg.ld + jv * V;
-    o[2] = (i0 + ma) * sg.ld + jv * V;
-    o[3] = (i0 + ma + mb) * sg.ld + jv * V;
+    o[0] = base + ((int64_t)i0 << logC);
+    o[1] = base + ((int64_t)(i0 + mb) << logC);
+    o[2] = base + ((int64_t)(i0 + ma) << logC);
+    o[3] = base + ((int64_t)(i0 + ma + mb) << logC);
     Pk<R> x[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) x[p] = ld_pk(src + o[p]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int qq = 0; qq < 4; ++qq) {
       Pk<R> y;
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         cx<R> acc = cmake<R>(0, 0);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) cfma(acc, u[q * 4 + p], x[p].v[e]);
+        for (int p = 0; p < 4; ++p) cfma(acc, u[qq * 4 + p], x[p].v[e]);
         y.v[e] = acc;
       }
-      st_pk(dst + o[q], y);
+      st_pk(dst + o[qq], y);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ fused forward
+template <typename R>
+struct FwdSeg {
+  const cx<R> *src;     // initial states (shared by all starts), chunked
+  cx<R> *blist;         // B list (B_{k+1} at list index k) or nullptr
+  int64_t bstride;      // per start
+  int64_t sN;           // per list entry
+  const cx<R> *ref;     // states to compare against after the last applied gate, or nullptr
+  double *partials;     // [S][nch] distance partials
+  int32_t nch;          // chunks
+  int32_t kapply;       // gates applied: 0 .. kapply-1
+  int32_t kstore;       // outputs stored for gates 0 .. kstore-1
+};
+
+template <typename R>
+__global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int n,
+                                                             int logC, const int32_t *pairs,
+                                                             const cx<R> *gates, int32_t gstride,
+                                                             const int32_t *slot_to_start) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
+  __shared__ double red[kFwdBlock / 64];
+  const FwdSeg<R> sg = blockIdx.z == 0 ? seg0 : seg1;
+  const int q = blockIdx.x;
+  if (q >= sg.nch) return;
+  const int s = slot_to_start[blockIdx.y];
+  constexpr int V = Pk<R>::V, LOGV = Pk<R>::LOGV;
+  const int logJ = logC - LOGV;
+  const uint32_t chunk = 1u << (n + logC);                 // elements per chunk
+  const int64_t cbase = (int64_t)q << (n + logC);
+  const cx<R> *src = sg.src + cbase;
+  for (uint32_t e = threadIdx.x * V; e < chunk; e += kFwdBlock * V) st_pk(lds + e, ld_pk(src + e));
+  __syncthreads();
+  const uint32_t groups = 1u << (n - 2 + logJ);
+  for (int k = 0; k < sg.kapply; ++k) {
+    const int pa = n - 1 - pairs[2 * k], pb = n - 1 - pairs[2 * k + 1];
+    const int sorted[2] = {min(pa, pb), max(pa, pb)};
+    const uint32_t ma = 1u << pa, mb = 1u << pb;
+    cx<R> u[16];
+    load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, false);
+    const bool store = k < sg.kstore;
+    cx<R> *dst = store ? sg.blist + sg.bstride * s + sg.sN * k + cbase : nullptr;
+    for (uint32_t g = threadIdx.x; g < groups; g += kFwdBlock) {
+      const uint32_t jv = g & ((1u << logJ) - 1u);
+      const uint32_t i0 = deposit(g >> logJ, sorted, 2);
+      uint32_t o[4];
+      o[0] = (i0 << logC) + jv * V;
+      o[1] = ((i0 + mb) << logC) + jv * V;
+      o[2] = ((i0 + ma) << logC) + jv * V;
+      o[3] = ((i0 + ma + mb) << logC) + jv * V;
+      Pk<R> x[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) x[p] = ld_pk(lds + o[p]);
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        Pk<R> y;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          cx<R> acc = cmake<R>(0, 0);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) cfma(acc, u[qq * 4 + p], x[p].v[e]);
+          y.v[e] = acc;
+        }
+        st_pk(lds + o[qq], y);
+        if (store) st_pk(dst + o[qq], y);
+      }
+    }
+    __syncthreads();
+  }
+  if (sg.ref) {
+    const cx<R> *ref = sg.ref + cbase;
+    double acc = 0.0;
+    for (uint32_t e = threadIdx.x * V; e < chunk; e += kFwdBlock * V) {
+      const Pk<R> a = ld_pk(lds + e), b = ld_pk(ref + e);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const R dr = a.v[v].re - b.v[v].re, di = a.v[v].im - b.v[v].im;
+        acc += (double)dr * (double)dr + (double)di * (double)di;
+      }
+    }
+    acc = wave_sum<double>(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < kFwdBlock / 64; ++w) tot += red[w];
+      sg.partials[(int64_t)s * sg.nch + q] = tot;
     }
   }
 }
 
 // ------------------------------------------------------------------ backward step
+struct StepGeom {
+  ChunkGeom cg;
+  int32_t t;
+  int32_t sorted_pos[4];
+  int32_t off[16];  // amplitude-index offset of each local index
+};
+
 template <typename R>
 struct StepArgs {
   const cx<R> *a_in;
@@ -356,19 +510,19 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   cx<R> *a_out = A.a_out + A.a_out_stride * s;
   const cx<R> *b = A.b + A.b_stride * s;
   const StepGeom &G = A.geo;
+  const int logC = G.cg.logC, n = G.cg.n;
 
   cx<R> acc[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = cmake<R>(0, 0);
 
-  for (int64_t it = blockIdx.x * (int64_t)kBlock + threadIdx.x; it < G.items;
-       it += (int64_t)P * kBlock) {
-    const int64_t rr = it / G.J;
-    const int jv = (int)(it - rr * G.J);
-    const int64_t base = deposit(rr, G.sorted_pos, t) * G.ld + jv * V;
+  for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < G.cg.items; it += P * kBlock) {
+    uint32_t q, rr, jv;
+    split_item(it, G.cg, q, rr, jv);
+    const int64_t base = ((int64_t)q << (n + logC)) + ((int64_t)deposit(rr, G.sorted_pos, t) << logC) + jv * V;
     Pk<R> a[NL];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) a[l] = ld_pk(a_in + base + (int64_t)G.off[l] * G.ld);
+    for (int l = 0; l < NL; ++l) a[l] = ld_pk(a_in + base + ((int64_t)G.off[l] << logC));
     if (APPLY) {
 #pragma unroll
       for (int rho = 0; rho < NS; ++rho) {
@@ -378,30 +532,30 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
 #pragma unroll
           for (int p = 0; p < 4; ++p) x[p] = a[p * NS + rho].v[e];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int qq = 0; qq < 4; ++qq) {
             cx<R> y = cmake<R>(0, 0);
 #pragma unroll
-            for (int p = 0; p < 4; ++p) cfma(y, ud[q * 4 + p], x[p]);
-            a[q * NS + rho].v[e] = y;
+            for (int p = 0; p < 4; ++p) cfma(y, ud[qq * 4 + p], x[p]);
+            a[qq * NS + rho].v[e] = y;
           }
         }
       }
 #pragma unroll
-      for (int l = 0; l < NL; ++l) st_pk(a_out + base + (int64_t)G.off[l] * G.ld, a[l]);
+      for (int l = 0; l < NL; ++l) st_pk(a_out + base + ((int64_t)G.off[l] << logC), a[l]);
     }
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) {
       Pk<R> bb[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
-        bb[p] = ld_pk(b + base + (int64_t)G.off[env_index<VAR>(p, sg)] * G.ld);
+        bb[p] = ld_pk(b + base + ((int64_t)G.off[env_index<VAR>(p, sg)] << logC));
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const Pk<R> &aq = a[env_index<VAR>(q, sg)];
+      for (int qq = 0; qq < 4; ++qq) {
+        const Pk<R> &aq = a[env_index<VAR>(qq, sg)];
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int e = 0; e < V; ++e) cfma_conj(acc[q * 4 + p], aq.v[e], bb[p].v[e]);
+          for (int e = 0; e < V; ++e) cfma_conj(acc[qq * 4 + p], aq.v[e], bb[p].v[e]);
       }
     }
   }
@@ -427,7 +581,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
 __global__ __launch_bounds__(64) void k_env_finalize(const c128 *partials, int P,
                                                      const int32_t *slot_to_start, c128 *gamma_out,
                                                      int do_update, double beta, c128 *g64,
-                                                     c64 *g32, int32_t gstride, int32_t k_env) {
+                                                     c64 *g32, int32_t gstride, int32_t k_env,
+                                                     c128 *vstore) {
   __shared__ c128 gam[16];
   __shared__ c128 pg[16], pv[16];
   __shared__ double psig[4];
@@ -447,7 +602,8 @@ __global__ __launch_bounds__(64) void k_env_finalize(const c128 *partials, int P
   if (do_update) {
     c128 *u64 = g64 + (int64_t)s * gstride + k_env * 16;
     c64 *u32 = g32 ? g32 + (int64_t)s * gstride + k_env * 16 : nullptr;
-    polar4_wave(gam, beta, u64, u64, u32, pg, pv, psig);
+    c128 *vs = vstore ? vstore + (int64_t)s * gstride + k_env * 16 : nullptr;
+    polar4_wave(gam, beta, u64, u64, u32, pg, pv, psig, vs);
   }
 }
 
@@ -463,8 +619,7 @@ struct DistArgs {
   int32_t k;        // gate to apply (< 0: none)
   int32_t dagger;
   int32_t pa, pb;
-  int32_t ld, J, M;
-  int64_t items;
+  ChunkGeom cg;
   double *partials;  // [S][P]
   const int32_t *slot_to_start;
 };
@@ -481,19 +636,20 @@ __global__ __launch_bounds__(kBlock) void k_apply_dist(DistArgs<R> A) {
   const cx<R> *ref = A.ref + A.ref_stride * s;
   const int lo = min(A.pa, A.pb), hi = max(A.pa, A.pb);
   const int sorted[2] = {lo, hi};
-  const int64_t ma = int64_t(1) << A.pa, mb = int64_t(1) << A.pb;
+  const uint32_t ma = 1u << A.pa, mb = 1u << A.pb;
   constexpr int V = Pk<R>::V;
+  const int logC = A.cg.logC, n = A.cg.n;
   double acc = 0.0;
-  for (int64_t it = blockIdx.x * (int64_t)kBlock + threadIdx.x; it < A.items;
-       it += (int64_t)P * kBlock) {
-    const int64_t rr = it / A.J;
-    const int jv = (int)(it - rr * A.J);
-    const int64_t i0 = deposit(rr, sorted, 2);
+  for (uint32_t it = blockIdx.x * kBlock + threadIdx.x; it < A.cg.items; it += P * kBlock) {
+    uint32_t q, rr, jv;
+    split_item(it, A.cg, q, rr, jv);
+    const uint32_t i0 = deposit(rr, sorted, 2);
+    const int64_t base = ((int64_t)q << (n + logC)) + jv * V;
     int64_t o[4];
-    o[0] = i0 * A.ld + jv * V;
-    o[1] = (i0 + mb) * A.ld + jv * V;
-    o[2] = (i0 + ma) * A.ld + jv * V;
-    o[3] = (i0 + ma + mb) * A.ld + jv * V;
+    o[0] = base + ((int64_t)i0 << logC);
+    o[1] = base + ((int64_t)(i0 + mb) << logC);
+    o[2] = base + ((int64_t)(i0 + ma) << logC);
+    o[3] = base + ((int64_t)(i0 + ma + mb) << logC);
     Pk<R> xv[4], rv[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
@@ -501,18 +657,18 @@ __global__ __launch_bounds__(kBlock) void k_apply_dist(DistArgs<R> A) {
       rv[p] = ld_pk(ref + o[p]);
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         cx<R> y;
         if (has_gate) {
           y = cmake<R>(0, 0);
 #pragma unroll
-          for (int p = 0; p < 4; ++p) cfma(y, u[q * 4 + p], xv[p].v[e]);
+          for (int p = 0; p < 4; ++p) cfma(y, u[qq * 4 + p], xv[p].v[e]);
         } else {
-          y = xv[q].v[e];
+          y = xv[qq].v[e];
         }
-        const R dr = y.re - rv[q].v[e].re, di = y.im - rv[q].v[e].im;
+        const R dr = y.re - rv[qq].v[e].re, di = y.im - rv[qq].v[e].im;
         acc += (double)dr * (double)dr + (double)di * (double)di;
       }
   }
@@ -534,7 +690,6 @@ __global__ __launch_bounds__(64) void k_dist_finalize(const double *partials, in
   const int s = slot_to_start[blockIdx.x];
   double sum = 0.0;
   for (int blk = threadIdx.x; blk < P; blk += 64) sum += partials[(int64_t)s * P + blk];
-  // fixed-order combination across lanes
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_down(sum, o);
   if (threadIdx.x == 0) out[s] = sum * inv_m;
@@ -549,10 +704,69 @@ __global__ void k_polar_batch(int count, const c128 *gamma, double beta, c128 *u
               pg, pv, psig);
 }
 
+__global__ void k_identity4(int64_t count, c128 *v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count * 16;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int q = (int)(e & 15);
+    v[e] = cmake(((q >> 2) == (q & 3)) ? 1.0 : 0.0, 0.0);
+  }
+}
+
+// Pack FP64 masters [N][ld] (row-major, states as columns) into the chunked working
+// layout in R, zero beyond column M.
+template <typename R>
+__global__ void k_pack(int n, int logC, int64_t ld, int M, int64_t total, const c128 *src,
+                       cx<R> *dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e >> (n + logC);
+    const int64_t rem = e & ((int64_t(1) << (n + logC)) - 1);
+    const int64_t i = rem >> logC, j = (q << logC) + (rem & ((1 << logC) - 1));
+    c128 v = cmake(0.0, 0.0);
+    if (j < M) v = src[i * ld + j];
+    dst[e] = cmake<R>((R)v.re, (R)v.im);
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host launchers
-static int packet_v(size_t rbytes) { return rbytes == 4 ? 2 : 1; }
+static int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+bool forward_fusable(int n, size_t rbytes, size_t lds_max) {
+  return forward_lds_bytes(n, 1, rbytes) <= std::min<size_t>(lds_max, 128 * 1024);
+}
+
+int choose_log_chunk(int n, int M, size_t rbytes, bool fused, int starts, size_t lds_max) {
+  const int pm = std::max(1, ilog2(std::max(M, 2)));
+  if (!fused) return std::min(pm, 5);
+  const size_t lim = std::min<size_t>(lds_max, 128 * 1024);
+  int logC = 1;
+  while (logC + 1 <= pm && forward_lds_bytes(n, logC + 1, rbytes) <= lim) ++logC;
+  // keep at least ~two blocks per compute unit in the forward pass
+  while (logC > 1 && (int64_t)((M + (1 << logC) - 1) >> logC) * starts < 512) --logC;
+  return logC;
+}
+
+static ChunkGeom chunk_geom(const Geometry &g, int t, size_t rbytes) {
+  ChunkGeom cg;
+  const int logV = rbytes == 4 ? 1 : 0;
+  cg.n = g.n;
+  cg.logC = g.logC;
+  cg.logJ = g.logC - logV;
+  cg.logG = g.n - t;
+  cg.items = (uint32_t)((uint64_t)g.nch << (cg.logG + cg.logJ));
+  return cg;
+}
+
+static int blocks_for(uint32_t items, int nslots) {
+  const int64_t pmax = std::max<int64_t>(1, ((int64_t)items + kBlock - 1) / kBlock);
+  return (int)std::min<int64_t>(pmax, std::max(1, 2048 / std::max(1, nslots)));
+}
 
 template <typename R>
 int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
@@ -560,27 +774,84 @@ int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef 
                  hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   ApplySeg<R> seg;
-  const int V = packet_v(sizeof(R));
   seg.src = src.base;
   seg.src_stride = src.stride;
   seg.dst = dst.base;
   seg.dst_stride = dst.stride;
-  seg.ld = g.ld;
-  seg.J = g.ld / V;
-  seg.items = (int64_t(g.N) >> 2) * seg.J;
-  const int P = (int)std::max<int64_t>(
-      1, std::min<int64_t>((seg.items + kBlock - 1) / kBlock, std::max(1, 2048 / nslots)));
+  seg.cg = chunk_geom(g, 2, sizeof(R));
+  const int P = blocks_for(seg.cg.items, nslots);
   const int pa = g.n - 1 - qa, pb = g.n - 1 - qb;
-  hipLaunchKernelGGL(k_apply<R>, dim3(P, nslots, 1), dim3(kBlock), 0, s, seg, seg, pa, pb,
+  hipLaunchKernelGGL(k_apply<R>, dim3(P, nslots, 1), dim3(kBlock), 0, s, seg, pa, pb,
                      static_cast<const cx<R> *>(gates.gR), gates.gstride, k, dagger ? 1 : 0,
                      slot_to_start);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
 
+size_t forward_lds_bytes(int n, int logC, size_t rbytes) {
+  return (size_t(1) << (n + logC)) * 2 * rbytes;
+}
+
+template <typename R>
+int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *pairs_dev, int L,
+                         GateRef gates, const cx<R> *psi, cx<R> *blist, int64_t bstride,
+                         const cx<R> *phi_ref, double *c0_partials, const cx<R> *psiv,
+                         const cx<R> *phiv, double *val_partials, const int32_t *slot_to_start,
+                         int nslots, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  FwdSeg<R> a{}, b{};
+  a.src = psi;
+  a.blist = blist;
+  a.bstride = bstride;
+  a.sN = (int64_t)g.nch * ((int64_t)g.N << g.logC);
+  a.ref = phi_ref;
+  a.partials = c0_partials;
+  a.nch = g.nch;
+  a.kstore = L - 1;
+  a.kapply = phi_ref ? L : L - 1;
+  int nz = 1;
+  if (gv) {
+    if (gv->logC != g.logC) {
+      set_error_detail("fused forward: training and validation chunk widths differ");
+      return QFS_EINVAL;
+    }
+    b.src = psiv;
+    b.blist = nullptr;
+    b.bstride = 0;
+    b.sN = 0;
+    b.ref = phiv;
+    b.partials = val_partials;
+    b.nch = gv->nch;
+    b.kstore = 0;
+    b.kapply = L;
+    nz = 2;
+  }
+  const int gx = std::max(a.nch, gv ? b.nch : 0);
+  const size_t lds = forward_lds_bytes(g.n, g.logC, sizeof(R));
+  static size_t attr_bytes = 0;  // dynamic LDS above 64 KB must be requested per kernel
+  if (lds > 64 * 1024 && lds > attr_bytes) {
+    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forward_fused<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_bytes = lds;
+  }
+  hipLaunchKernelGGL(k_forward_fused<R>, dim3(gx, nslots, nz), dim3(kFwdBlock), lds, s, a, b, g.n,
+                     g.logC, pairs_dev, static_cast<const cx<R> *>(gates.gR), gates.gstride,
+                     slot_to_start);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+template <typename R>
+int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, hipStream_t s) {
+  const int64_t total = (int64_t)g.nch * ((int64_t)g.N << g.logC);
+  hipLaunchKernelGGL(k_pack<R>, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)),
+                     dim3(256), 0, s, g.n, g.logC, ld, g.M, total, master, dst);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
 // Canonical bit order for a backward step and its variant id (see env_index).
-static int classify_step(int n, const int32_t *pairs, int k_apply, int k_env, int32_t tq[4],
-                         int *t) {
+static int classify_step(const int32_t *pairs, int k_apply, int k_env, int32_t tq[4], int *t) {
   const int a0 = pairs[2 * k_env], b0 = pairs[2 * k_env + 1];
   if (k_apply < 0) {
     tq[0] = a0;
@@ -591,7 +862,7 @@ static int classify_step(int n, const int32_t *pairs, int k_apply, int k_env, in
   const int a1 = pairs[2 * k_apply], b1 = pairs[2 * k_apply + 1];
   tq[0] = a1;
   tq[1] = b1;
-  if ((a0 == a1 && b0 == b1)) {
+  if (a0 == a1 && b0 == b1) {
     *t = 2;
     return 0;
   }
@@ -607,7 +878,6 @@ static int classify_step(int n, const int32_t *pairs, int k_apply, int k_env, in
   *t = 4;
   tq[2] = a0;
   tq[3] = b0;
-  (void)n;
   return 6;
 }
 
@@ -618,13 +888,13 @@ static void launch_step_kernel(dim3 grid, const StepArgs<R> &a, hipStream_t s) {
 
 template <typename R>
 int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
-                    GateRef gates, c128 *g64_mut, void *gR_mut, double beta, SBuf<R> a_in,
-                    SBuf<R> a_out, SBuf<R> b, const int32_t *slot_to_start, int nslots, int P,
-                    StepScratch sc, bool do_update, hipStream_t s) {
+                    GateRef gates, SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b,
+                    const int32_t *slot_to_start, int nslots, c128 *partials, int *P_out,
+                    hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   int32_t tq[4];
   int t = 0;
-  const int var = classify_step(g.n, pairs_host, k_apply, k_env, tq, &t);
+  const int var = classify_step(pairs_host, k_apply, k_env, tq, &t);
   StepArgs<R> a;
   a.a_in = a_in.base;
   a.a_in_stride = a_in.stride;
@@ -635,12 +905,10 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
   a.gR = static_cast<const cx<R> *>(gates.gR);
   a.gstride = gates.gstride;
   a.k_apply = k_apply;
-  a.partials = sc.partials;
+  a.partials = partials;
   a.slot_to_start = slot_to_start;
   StepGeom &G = a.geo;
-  const int V = packet_v(sizeof(R));
-  G.ld = g.ld;
-  G.M = g.M;
+  G.cg = chunk_geom(g, t, sizeof(R));
   G.t = t;
   int32_t pos[4];
   for (int m = 0; m < t; ++m) pos[m] = g.n - 1 - tq[m];
@@ -654,15 +922,10 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
         if ((l >> (t - 1 - m)) & 1) o += 1 << pos[m];
     G.off[l] = o;
   }
-  G.J = g.ld / V;
-  G.items = (int64_t(g.N) >> t) * G.J;
-  if (P <= 0) {
-    const int64_t pmax = std::max<int64_t>(1, (G.items + kBlock - 1) / kBlock);
-    P = (int)std::min<int64_t>(pmax, std::max(1, 2048 / nslots));
-  }
+  const int P = blocks_for(G.cg.items, nslots);
+  *P_out = P;
   dim3 grid(P, nslots);
-  const bool apply = k_apply >= 0;
-  if (!apply) {
+  if (k_apply < 0) {
     launch_step_kernel<R, 0, false>(grid, a, s);
   } else {
     switch (var) {
@@ -676,20 +939,25 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
     }
   }
   QFS_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_env_finalize, dim3(nslots), dim3(64), 0, s, sc.partials, P, slot_to_start,
-                     sc.gamma_out, do_update ? 1 : 0, beta, g64_mut,
-                     sizeof(R) == 4 ? static_cast<c64 *>(gR_mut) : nullptr, gates.gstride, k_env);
+  return QFS_OK;
+}
+
+int launch_env_finalize(int P, const c128 *partials, const int32_t *slot_to_start, int nslots,
+                        c128 *gamma_out, bool do_update, double beta, c128 *g64, c64 *g32,
+                        int32_t gstride, int32_t k_env, c128 *vstore, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  hipLaunchKernelGGL(k_env_finalize, dim3(nslots), dim3(64), 0, s, partials, P, slot_to_start,
+                     gamma_out, do_update ? 1 : 0, beta, g64, g32, gstride, k_env, vstore);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
 
 template <typename R>
 int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
-                      SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots, int P,
-                      double *partials, double *out, hipStream_t s) {
+                      SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots,
+                      double *partials, int *P_out, hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   DistArgs<R> a;
-  const int V = packet_v(sizeof(R));
   a.x = x.base;
   a.x_stride = x.stride;
   a.ref = ref.base;
@@ -700,20 +968,29 @@ int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, Gat
   a.dagger = dagger ? 1 : 0;
   a.pa = g.n - 1 - qa;
   a.pb = g.n - 1 - qb;
-  a.ld = g.ld;
-  a.J = g.ld / V;
-  a.M = g.M;
-  a.items = (int64_t(g.N) >> 2) * a.J;
+  a.cg = chunk_geom(g, 2, sizeof(R));
   a.partials = partials;
   a.slot_to_start = slot_to_start;
-  if (P <= 0) {
-    const int64_t pmax = std::max<int64_t>(1, (a.items + kBlock - 1) / kBlock);
-    P = (int)std::min<int64_t>(pmax, std::max(1, 2048 / nslots));
-  }
+  const int P = blocks_for(a.cg.items, nslots);
+  *P_out = P;
   hipLaunchKernelGGL(k_apply_dist<R>, dim3(P, nslots), dim3(kBlock), 0, s, a);
   QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+int launch_dist_finalize(int P, const double *partials, const int32_t *slot_to_start, int nslots,
+                         int M, double *out, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
   hipLaunchKernelGGL(k_dist_finalize, dim3(nslots), dim3(64), 0, s, partials, P, slot_to_start,
-                     1.0 / (double)g.M, out);
+                     1.0 / (double)M, out);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+int launch_identity4(int64_t count, c128 *v, hipStream_t s) {
+  if (count <= 0) return QFS_OK;
+  hipLaunchKernelGGL(k_identity4, dim3((unsigned)std::min<int64_t>((count * 16 + 255) / 256, 65536)),
+                     dim3(256), 0, s, count, v);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
@@ -728,12 +1005,17 @@ int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipSt
 #define QFS_INST(R)                                                                          \
   template int launch_apply<R>(const Geometry &, int, int, int, bool, GateRef, SBuf<R>,       \
                                SBuf<R>, const int32_t *, int, hipStream_t);                   \
-  template int launch_bwd_step<R>(const Geometry &, const int32_t *, int, int, GateRef, c128 *, \
-                                  void *, double, SBuf<R>, SBuf<R>, SBuf<R>, const int32_t *, \
-                                  int, int, StepScratch, bool, hipStream_t);                  \
+  template int launch_bwd_step<R>(const Geometry &, const int32_t *, int, int, GateRef,       \
+                                  SBuf<R>, SBuf<R>, SBuf<R>, const int32_t *, int, c128 *,    \
+                                  int *, hipStream_t);                                       \
   template int launch_apply_dist<R>(const Geometry &, int, int, int, bool, GateRef, SBuf<R>,  \
-                                    SBuf<R>, const int32_t *, int, int, double *, double *,   \
-                                    hipStream_t);
+                                    SBuf<R>, const int32_t *, int, double *, int *,           \
+                                    hipStream_t);                                            \
+  template int launch_forward_fused<R>(const Geometry &, const Geometry *, const int32_t *,   \
+                                       int, GateRef, const cx<R> *, cx<R> *, int64_t,         \
+                                       const cx<R> *, double *, const cx<R> *, const cx<R> *, \
+                                       double *, const int32_t *, int, hipStream_t);          \
+  template int launch_pack<R>(const Geometry &, int64_t, const c128 *, cx<R> *, hipStream_t);
 QFS_INST(float)
 QFS_INST(double)
 #undef QFS_INST

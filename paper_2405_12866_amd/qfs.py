@@ -48,7 +48,7 @@ class Params(C.Structure):
                 ("fixed_m", C.c_int32), ("m_val", C.c_int32), ("precision", C.c_int32),
                 ("refine_below", C.c_double), ("device_mem_budget", C.c_uint64),
                 ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("batch_sweeps", C.c_int32), ("batch_threads", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -56,12 +56,12 @@ class Result(C.Structure):
                 ("restarts", C.c_int32), ("best_start", C.c_int32), ("m_total", C.c_int32),
                 ("start_groups", C.c_int32), ("refined", C.c_int32), ("c_train", C.c_double),
                 ("c_val", C.c_double), ("seconds", C.c_double), ("start_sweeps", C.c_int64),
-                ("sweep_seconds", C.c_double), ("kernel_launches", C.c_int64 * 3),
-                ("kernel_seconds", C.c_double * 3), ("kernel_bytes", C.c_double * 3)]
+                ("sweep_seconds", C.c_double), ("kernel_launches", C.c_int64 * 4),
+                ("kernel_seconds", C.c_double * 4), ("kernel_bytes", C.c_double * 4)]
 
 
 EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",
-           "qfs_instantiate", "qfs_instantiate_samples", "qfs_draw_states", "qfs_haar_gates",
+           "qfs_instantiate", "qfs_instantiate_batch", "qfs_instantiate_samples", "qfs_draw_states", "qfs_haar_gates",
            "qfs_apply_gates", "qfs_dense_apply", "qfs_environment", "qfs_polar_update",
            "qfs_sweep", "qfs_state_distance"]
 
@@ -84,6 +84,9 @@ def load():
         lib.qfs_default_params.argtypes = [C.POINTER(Params)]
         lib.qfs_instantiate.argtypes = [C.POINTER(Template), C.POINTER(Target), C.POINTER(Params),
                                         P, P, C.POINTER(Result)]
+        lib.qfs_instantiate_batch.argtypes = [I32, C.POINTER(Template), C.POINTER(Target),
+                                              C.POINTER(Params), C.POINTER(C.c_void_p),
+                                              C.POINTER(Result)]
         lib.qfs_instantiate_samples.argtypes = [C.POINTER(Template), P, P, I32, D, P,
                                                 C.POINTER(C.c_double)]
         lib.qfs_draw_states.argtypes = [I32, I32, U64, U32, U32, P, P]
@@ -192,6 +195,58 @@ def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, p
         info[f] = list(info[f])
     info["reason_name"] = REASONS.get(res.reason, "?")
     return out, info
+
+
+def qfs_instantiate_batch(problems, params=None):
+    """Batched instantiation. ``problems``: list of dicts with ``n``, ``pairs`` and one
+    target form (``U``; ``target_pairs`` + ``target_gates``; or ``psi``/``phi`` with
+    ``n_val``), device tensors as in qfs_instantiate. Problem p uses seed
+    params["seed"] + p. Returns (list of gate tensors [L, 4, 4], list of result dicts)."""
+    import torch
+    lib = load()
+    P = len(problems)
+    tmpls = (Template * P)()
+    tgts = (Target * P)()
+    keep = []
+    outs = []
+    for i, pr in enumerate(problems):
+        arr, pp = _pairs(pr["pairs"])
+        keep.append(arr)
+        tmpls[i] = Template(pr["n"], arr.shape[0], pp)
+        t = tgts[i]
+        if pr.get("U") is not None:
+            t.kind = QFS_TARGET_DENSE
+            t.U = _dev_c128(pr["U"], "U")
+            dev = pr["U"].device
+        elif pr.get("target_pairs") is not None:
+            tarr, tp = _pairs(pr["target_pairs"])
+            ct = Template(pr["n"], tarr.shape[0], tp)
+            keep += [tarr, ct]
+            t.kind = QFS_TARGET_CIRCUIT
+            t.circuit = C.pointer(ct)
+            t.circuit_gates = _dev_c128(pr["target_gates"], "target_gates")
+            dev = pr["target_gates"].device
+        else:
+            t.kind = QFS_TARGET_SAMPLES
+            t.psi = _dev_c128(pr["psi"], "psi")
+            t.phi = _dev_c128(pr["phi"], "phi")
+            t.n_samples = pr["psi"].shape[0]
+            t.n_val = pr.get("n_val", 0)
+            dev = pr["psi"].device
+        outs.append(torch.empty((arr.shape[0], 4, 4), dtype=torch.complex128, device=dev))
+    ptrs = (C.c_void_p * P)(*[o.data_ptr() for o in outs])
+    res = (Result * P)()
+    par = _params(params)
+    _check(lib.qfs_instantiate_batch(P, tmpls, tgts, C.byref(par), ptrs, res),
+           "qfs_instantiate_batch")
+    infos = []
+    for r in res:
+        d = {f: getattr(r, f) for f, _ in Result._fields_}
+        for f in ("kernel_launches", "kernel_seconds", "kernel_bytes"):
+            d[f] = list(d[f])
+        d["reason_name"] = REASONS.get(r.reason, "?")
+        infos.append(d)
+    return outs, infos
 
 
 def qfs_instantiate_samples(n, pairs, psi, phi, M, tol):

@@ -1,0 +1,128 @@
+"""GPU parity of the batched engine (qfs_instantiate_batch) against the FP64 oracle.
+
+With one sweep per launch and FP64 states every problem follows the lock-step control
+flow of the plain method, so each problem must match the oracle's instantiation with
+the same per-problem seed: same returned start, reason, sweep count, doublings and
+final M, costs to 1e-9 relative, gates to 1e-8. With K sweeps per launch and complex64
+states, every reported success must be a real solution: the full distance of the
+returned gates, by the oracle's simulation on a complete basis, is below 1e-8.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2405_12866_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_12866_amd import qfs as Q  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.complex128)).to(DEV)
+
+
+def full_distance(n, pairs, gates, tpairs, tgates):
+    basis = np.eye(1 << n, dtype=np.complex128)
+    return O.state_distance(n, O.apply_circuit(n, basis, pairs, gates),
+                            O.apply_circuit(n, basis, tpairs, tgates))
+
+
+def _problems(count, seed, n_range=(3, 5), L_range=(2, 6)):
+    g = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(g.integers(n_range[0], n_range[1] + 1))
+        L = int(g.integers(L_range[0], L_range[1] + 1))
+        pairs = I.random_pair_template(n, L, g)
+        out.append(dict(n=n, pairs=pairs, target_pairs=pairs, target_gates=I.haar_gates(L, g)))
+    return out
+
+
+def test_batch_lockstep_matches_oracle():
+    say("batch K=1 FP64 vs oracle, 6 problems x 4 starts")
+    probs = _problems(6, seed=21)
+    base_seed = 1000
+    params = Q.qfs_default_params(multistarts=4, seed=base_seed, max_iter=300, dist_tol=1e-10,
+                                  precision=Q.QFS_PREC_FP64, batch_sweeps=1, m_init=2,
+                                  diff_tol_r=1e-6)
+    dprobs = [dict(n=p["n"], pairs=p["pairs"], target_pairs=p["target_pairs"],
+                   target_gates=dev(p["target_gates"])) for p in probs]
+    gates, infos = Q.qfs_instantiate_batch(dprobs, params)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        op = O.default_params(multistarts=4, seed=base_seed + i, max_iter=300, dist_tol=1e-10,
+                              m_init=2, diff_tol_r=1e-6)
+        g_ref, ref = O.instantiate(p["n"], p["pairs"], target_pairs=p["target_pairs"],
+                                   target_gates=p["target_gates"], params=op)
+        got = infos[i]
+        say(f"  problem {i}: n={p['n']} L={len(p['pairs'])} ref={ref['reason_name']}/{ref['sweeps']} "
+            f"gpu={got['reason_name']}/{got['sweeps']}")
+        assert got["reason_name"] == ref["reason_name"]
+        assert got["best_start"] == ref["best_start"]
+        assert got["sweeps"] == ref["sweeps"]
+        assert got["m_final"] == ref["m_final"] and got["restarts"] == ref["restarts"]
+        assert abs(got["c_train"] - ref["c_train"]) <= 1e-9 * max(ref["c_train"], 1e-12) + 1e-18
+        assert np.max(np.abs(gates[i].cpu().numpy() - g_ref)) < 1e-8
+
+
+def test_batch_mixed_successes_are_solutions():
+    say("batch K=8 MIXED, 48 problems x 8 starts")
+    probs = _problems(48, seed=33, n_range=(3, 6), L_range=(2, 10))
+    params = Q.qfs_default_params(multistarts=8, seed=7, max_iter=2000, dist_tol=1e-9,
+                                  batch_sweeps=8, m_init=2, diff_tol_r=1e-7)
+    dprobs = [dict(n=p["n"], pairs=p["pairs"], target_pairs=p["target_pairs"],
+                   target_gates=dev(p["target_gates"])) for p in probs]
+    gates, infos = Q.qfs_instantiate_batch(dprobs, params)
+    torch.cuda.synchronize()
+    ok = 0
+    for i, p in enumerate(probs):
+        info = infos[i]
+        if info["reason_name"] != "SUCCESS":
+            continue
+        ok += 1
+        d = full_distance(p["n"], p["pairs"], gates[i].cpu().numpy(), p["target_pairs"],
+                          p["target_gates"])
+        assert d <= 1e-8, (i, d, info)
+    say(f"  successes: {ok}/48")
+    assert ok >= 36
+
+
+def test_batch_dense_and_samples_targets():
+    say("batch DENSE + SAMPLES targets")
+    g = np.random.default_rng(5)
+    pairs = [(0, 1), (1, 2), (0, 1)]
+    tg = I.haar_gates(3, g)
+    U = I.circuit_unitary_columns(3, pairs, tg, np.eye(8)).T  # columns: U e_i
+    psi = I.orthonormal_samples(3, 8, g)
+    phi = psi @ U.T
+    params = Q.qfs_default_params(multistarts=4, seed=3, max_iter=500, dist_tol=1e-10,
+                                  precision=Q.QFS_PREC_FP64, batch_sweeps=4, m_init=8)
+    gates, infos = Q.qfs_instantiate_batch(
+        [dict(n=3, pairs=pairs, U=dev(U)), dict(n=3, pairs=pairs, psi=dev(psi), phi=dev(phi), n_val=0)],
+        params)
+    for i in range(2):
+        assert infos[i]["reason_name"] == "SUCCESS", infos[i]
+        d = full_distance(3, pairs, gates[i].cpu().numpy(), pairs, tg)
+        assert d < 1e-9
+
+
+def test_batch_rejects_large_problems():
+    with pytest.raises(Q.QfsError) as e:
+        Q.qfs_instantiate_batch([dict(n=11, pairs=[(0, 1)], target_pairs=[(0, 1)],
+                                      target_gates=dev(np.eye(4)[None]))],
+                                Q.qfs_default_params(multistarts=1))
+    assert e.value.code == Q.QFS_EUNSUPPORTED
