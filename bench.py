@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-distance runs")
     ap.add_argument("--timing", type=int, default=1)
+    ap.add_argument("--batched", type=int, default=4096,
+                    help="problems in the batched workload (0 skips it)")
+    ap.add_argument("--plain-sample", type=int, default=48,
+                    help="problems of the batched workload also run one by one")
     return ap.parse_args()
 
 
@@ -100,6 +104,58 @@ def time_to_distance(dev):
             "seconds": round(dt, 4), "reason": info["reason_name"], "sweeps": info["sweeps"],
             "c_train": info["c_train"], "start_sweeps": info["start_sweeps"],
             "start_sweeps_per_s": round(info["start_sweeps"] / dt, 1)}
+    return out
+
+
+def batched(dev, count, plain_sample):
+    """Batched workload: `count` problems (n ~ U{3..7}, L ~ U{2..20} random pairs, Haar
+    target from the template), 16 starts each, M0 = 2^(n-1) with doubling to 2^n,
+    App. A stopping rules, MIXED precision, 8 sweeps per persistent launch. Compared
+    with plain qfs_instantiate calls, one problem at a time, on the first
+    `plain_sample` problems (same seeds, same success criterion), extrapolated."""
+    import numpy as np
+    import torch
+
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import qfs as Q
+
+    probs = I.batched_problems(count)
+    dprobs = [dict(n=p["n"], pairs=p["pairs"], target_pairs=p["target_pairs"],
+                   target_gates=torch.as_tensor(p["target_gates"]).to(dev)) for p in probs]
+    m0 = np.array([1 << (p["n"] - 1) for p in probs], dtype=np.int32)
+    params = Q.qfs_default_params(multistarts=16, seed=0x5A17 + 4, batch_sweeps=8,
+                                  precision=Q.QFS_PREC_MIXED)
+    warm = min(256, count)  # code objects + work-group-size autotuner
+    Q.qfs_instantiate_batch_ex(dprobs[:warm], params, m_init=m0[:warm])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos = Q.qfs_instantiate_batch_ex(dprobs, params, m_init=m0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ok = sum(r["reason_name"] == "SUCCESS" for r in infos)
+    job_sweeps = sum(r["start_sweeps"] for r in infos)
+    out = {"problems": count, "starts": 16, "wall_s": round(dt, 3),
+           "problems_per_s": round(count / dt, 1), "successes": ok,
+           "job_sweeps": job_sweeps, "job_sweeps_per_s": round(job_sweeps / dt, 1),
+           "doublings": sum(r["restarts"] for r in infos),
+           "device_s": round(infos[0]["sweep_seconds"], 3)}
+    k = min(plain_sample, count)
+    if k > 0:
+        t_plain, ok_plain, ok_batch = 0.0, 0, 0
+        for i in range(k):
+            p = dict(params, seed=params["seed"] + i, m_init=int(m0[i]))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, r = Q.qfs_instantiate(probs[i]["n"], probs[i]["pairs"], target_pairs=probs[i]["pairs"],
+                                     target_gates=dprobs[i]["target_gates"], params=p)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t1
+            ok_plain += r["reason_name"] == "SUCCESS"
+            ok_batch += infos[i]["reason_name"] == "SUCCESS"
+        est = t_plain / k * count
+        out["plain_loop"] = {"sample": k, "sample_s": round(t_plain, 3),
+                             "sample_successes": ok_plain, "batched_successes_on_sample": ok_batch,
+                             "extrapolated_s": round(est, 2), "batched_speedup": round(est / dt, 1)}
     return out
 
 
@@ -163,6 +219,8 @@ def main():
         "kernel_classes": classes,
         "final_c_train": info["c_train"], "final_c_val": info["c_val"],
     }
+    if args.batched > 0:
+        extra["batched"] = batched(dev, args.batched, args.plain_sample)
     if not args.no_ttd:
         extra["time_to_distance"] = time_to_distance(dev)
         extra["time_to_distance"]["12q_note"] = (

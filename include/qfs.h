@@ -153,6 +153,12 @@ typedef struct {
   int64_t kernel_launches[4];
   double kernel_seconds[4];
   double kernel_bytes[4];
+  /* Learned entries only (qfs_instantiate_learned, qfs_instantiate_batch_learned):
+   * the predicted initial M, the starts run (learned run plus fallback), and 1 when the
+   * learned run did not succeed and the plain method was run after it. */
+  int32_t m_predicted;
+  int32_t starts_run;
+  int32_t fallback;
 } qfs_result;
 
 /* Fill *p with the defaults: dist_tol 1e-8, diff_tol_r 1e-5, plateau_window 5,
@@ -196,6 +202,88 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target,
  * Limits: 2 <= n_qubits <= 10 per problem (QFS_EUNSUPPORTED above). */
 int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
                           const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res);
+
+/* qfs_instantiate_batch with per-problem initial M and start counts: m_init host [P]
+ * (NULL: params->m_init for every problem; each entry >= 1, capped at m_max and 2^n)
+ * and starts host [P] (NULL: params->multistarts; problem p runs its first starts[p]
+ * starts, 1 <= starts[p] <= multistarts). QFS_EINVAL for an entry out of range. */
+int qfs_instantiate_batch_ex(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                             const qfs_params *params, const int32_t *m_init,
+                             const int32_t *starts, qfs_c128 *const *gates_out,
+                             qfs_result *res);
+
+/* Labelling runs for the sample-count predictor: every problem at a fixed M =
+ * params->m_init (no doubling), every start run to its own stop (no start waits for or
+ * stops at another's success), Sec. 3 success relation per start. successes: host [P],
+ * the number of starts that succeeded; res: host [P] (reason and costs of the best
+ * start). Other arguments and limits as qfs_instantiate_batch. */
+int qfs_label_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                    const qfs_params *params, int32_t *successes, qfs_result *res);
+
+/* ------------------------------------------- learned initial M and start pruning */
+/* The paper leaves the initial number of training states open (Sec. 3, Sec. 5) and
+ * relates the number needed to the parameter count per amplitude (Sec. 4). A network
+ * 64 -> 128 -> 128 -> 2 (ReLU; bfloat16 weights, FP32 accumulation; process-wide, one
+ * per process, guarded by a mutex) maps structural template features to
+ *   y0: log2 of the smallest power-of-two M at which a start succeeds, and
+ *   y1: the logit of the chance that one random start succeeds at that M. */
+
+/* The 64 features of a template (host; no device work). out: host [64]. */
+int qfs_features(const qfs_template *tmpl, float *out);
+
+/* Number of FP32 parameters: W1 [128][64], b1 [128], W2 [128][128], b2 [128],
+ * W3 [2][128], b3 [2], in this order. */
+int qfs_mlp_num_params(void);
+
+/* He-uniform weights from a seed; resets the optimiser state. */
+int qfs_mlp_init(uint64_t seed);
+
+/* Copy the FP32 master weights out (host [num_params]) or in (resets the optimiser). */
+int qfs_mlp_get(float *host_params);
+int qfs_mlp_set(const float *host_params);
+
+/* Weight file: 8-byte magic "QFSMLP1\0" then num_params little-endian FP32. */
+int qfs_mlp_save(const char *path);
+int qfs_mlp_load(const char *path);
+
+/* Forward pass: features device [count][64] -> out device [count][2]. */
+int qfs_mlp_forward(int32_t count, const float *features, float *out, void *hip_stream);
+
+/* Gradient of the mean loss over count rows (no update): targets device [count][2] =
+ * (log2 M label, NaN when there is none; success fraction in [0, 1]). Loss per row:
+ * (y0 - t0)^2 / 2 when t0 is finite, plus the binary cross-entropy of logit y1 against
+ * t1. grad_host: host [num_params] or NULL; loss_host: host or NULL. */
+int qfs_mlp_grad(int32_t count, const float *features, const float *targets,
+                 float *grad_host, float *loss_host, void *hip_stream);
+
+/* Adam (0.9, 0.999, 1e-8) on shuffled mini-batches of `batch` rows for `epochs`
+ * passes; features / targets as in qfs_mlp_grad (device). epoch_loss: host [epochs]
+ * (mean mini-batch loss before each step) or NULL. */
+int qfs_mlp_train(int32_t count, const float *features, const float *targets,
+                  int32_t epochs, int32_t batch, float lr, uint64_t seed, float *epoch_loss,
+                  void *hip_stream);
+
+/* Predicted initial M (a power of two in [2, 2^n]) and the starts to keep: the fewest
+ * leading starts (at most params->multistarts) for which at least one succeeds with
+ * probability 0.95 at the predicted per-start rate. keep_mask bit s = start s kept
+ * (nullable). QFS_EINVAL when no weights are loaded. */
+int qfs_predict_m(const qfs_template *tmpl, const qfs_params *params, int32_t *m0,
+                  uint32_t *keep_mask);
+int qfs_predict_batch(int32_t P, const qfs_template *tmpl, const qfs_params *params,
+                      int32_t *m0, int32_t *starts);
+
+/* qfs_instantiate with M starting at max(m_init, predicted M) and the predicted number
+ * of starts; when that run does not succeed, the plain qfs_instantiate (from m_init,
+ * every start) runs after it and its result is returned with fallback = 1. Counters in
+ * res (start_sweeps, m_total, seconds) cover both runs. */
+int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target,
+                            const qfs_params *params, qfs_c128 *gates_out, qfs_result *res);
+
+/* The same for qfs_instantiate_batch: one batched learned run, then one batched plain
+ * run of the problems that did not succeed (each with its original seed). */
+int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl,
+                                  const qfs_target *targets, const qfs_params *params,
+                                  qfs_c128 *const *gates_out, qfs_result *res);
 
 /* Minimal entry: fixed sample set of M pairs (psi, phi = U psi; device [M][N]), one
  * start, App. A defaults, no validation set, FP64 states, dist_tol = tol. Writes the

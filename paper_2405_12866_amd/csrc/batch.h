@@ -15,7 +15,8 @@ enum {
   BJ_OVER = 5,     // overtrained: waits for the problem's doubling
   BJ_PAUSED = 6,   // reached a sweep the problem already decided on
   BJ_REFINE = 7,   // complex64 job below refine_below: continue in complex128
-  BJ_TIMEOUT = 8
+  BJ_TIMEOUT = 8,
+  BJ_SKIP = 9       // start not run (pruned by the caller)
 };
 
 constexpr int kNoSweep = 0x3fffffff;
@@ -54,6 +55,7 @@ struct BParams {
   int32_t plateau_window, min_iter;
   int64_t max_iter;
   int32_t mixed;
+  int32_t independent;  // every start runs to its own stop (no problem-level pause)
 };
 
 struct BatchArgs {
@@ -67,6 +69,19 @@ struct BatchArgs {
   char *scratch;          // per-work-group state slots (nullptr: states in LDS)
   size_t scratch_slot_bytes;
 };
+
+// Per-problem options of the batched engine (all nullable / zero = the plain method).
+struct BatchOpts {
+  const int32_t *m_init = nullptr;  // [P] initial sample count per problem
+  const int32_t *starts = nullptr;  // [P] number of leading starts to run per problem
+  const uint64_t *seeds = nullptr;  // [P] per-problem seeds (default params->seed + p)
+  int independent = 0;              // starts do not stop at another start's success
+  int32_t *successes = nullptr;     // [P] out: number of starts that succeeded
+};
+
+int batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                      const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res,
+                      const BatchOpts &opts);
 
 int launch_batch_setup(BProb *probs_dev, const int32_t *todo, int ntodo, const int32_t *m0s,
                        hipStream_t s);

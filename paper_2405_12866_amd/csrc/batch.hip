@@ -341,7 +341,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, S
     if (threadIdx.x == 0) {
       const int ds = __hip_atomic_load(&P.done_sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int os = __hip_atomic_load(&P.over_sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      sh.flag = (J.total >= ds || J.total >= os) ? 1 : 0;
+      sh.flag = (!hp.independent && (J.total >= ds || J.total >= os)) ? 1 : 0;
     }
     __syncthreads();
     if (sh.flag) {

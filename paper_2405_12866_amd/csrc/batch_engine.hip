@@ -32,7 +32,7 @@ int to_reason(int st) {
 
 bool terminal(int st) {
   return st == BJ_SUCCESS || st == BJ_PLATEAU || st == BJ_MAX_ITER || st == BJ_NOT_GEN ||
-         st == BJ_TIMEOUT;
+         st == BJ_TIMEOUT || st == BJ_SKIP;
 }
 
 // Autotuner cache: (precision, LDS bucket) -> work-group size. Process-wide.
@@ -73,9 +73,9 @@ int grid_for(size_t lds, int threads, int njobs) {
 
 using namespace qfs;
 
-extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
-                                     const qfs_params *params, qfs_c128 *const *gates_out,
-                                     qfs_result *res) {
+int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                           const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res,
+                           const BatchOpts &opts) {
   const double t0 = bnow();
   if (P < 1 || !tmpl || !targets || !params || !gates_out || !res) {
     set_error_detail("batch: null argument or P < 1");
@@ -90,6 +90,10 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
     return QFS_EINVAL;
   }
   const int S = p.multistarts;
+  if (opts.independent && !p.fixed_m) {
+    set_error_detail("batch: independent starts need fixed_m");
+    return QFS_EINVAL;
+  }
   const int K = p.batch_sweeps > 0 ? p.batch_sweeps : 8;
   hipStream_t st = static_cast<hipStream_t>(p.hip_stream);
 
@@ -117,7 +121,7 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
     d.n = t.n_qubits;
     d.L = t.n_gates;
     d.kind = g.kind;
-    d.seed = p.seed + (uint64_t)i;
+    d.seed = opts.seeds ? opts.seeds[i] : p.seed + (uint64_t)i;
     d.done_sweep = kNoSweep;
     d.over_sweep = kNoSweep;
     int mcap = (p.m_max > 0 && p.m_max < N) ? p.m_max : N;
@@ -143,7 +147,12 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
     } else {
       return set_error_detail("batch: unknown target kind"), QFS_EINVAL;
     }
-    d.M = std::max(1, std::min(p.m_init, mcap));
+    const int m_init = opts.m_init ? opts.m_init[i] : p.m_init;
+    if (m_init < 1 || (opts.starts && (opts.starts[i] < 1 || opts.starts[i] > S))) {
+      set_error_detail("batch: problem " + std::to_string(i) + ": m_init and starts must be >= 1");
+      return QFS_EINVAL;
+    }
+    d.M = std::max(1, std::min(m_init, mcap));
     if (p.fixed_m) mcap = d.M;
     d.mcap = mcap;
     d.full = d.M == N;
@@ -211,7 +220,8 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
       std::memset(&j, 0, sizeof(j));
       j.prob = i;
       j.start = s;
-      j.status = BJ_RUN;
+      j.status = (opts.starts && s >= opts.starts[i]) ? BJ_SKIP : BJ_RUN;
+      j.c_train = j.c_val = HUGE_VAL;
       j.need_c0 = 1;
       j.fp64 = p.precision == QFS_PREC_FP64 ? 1 : 0;
     }
@@ -253,6 +263,7 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
   bp.min_iter = p.min_iter;
   bp.max_iter = p.max_iter;
   bp.mixed = p.precision == QFS_PREC_MIXED ? 1 : 0;
+  bp.independent = opts.independent ? 1 : 0;
 
   QFS_TRY(dqueue.alloc(sizeof(int32_t) * njobs_all));
   QFS_TRY(dhead.alloc(256));
@@ -375,13 +386,35 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
           if (js[s].total < first) behind = true;
         }
       }
-      if (first < kNoSweep && behind && !timed_out) continue;
       auto finish = [&](int w, int reason_override) {
         finished[i] = 1;
         --remaining;
         winner[i] = w;
         if (reason_override >= 0) js[w].status = reason_override;
       };
+      if (opts.independent) {
+        // every start runs to its own stop; the problem ends when none is running
+        for (int s = 0; s < S; ++s) {
+          if (js[s].status == BJ_REFINE) {
+            js[s].status = BJ_RUN;
+            js[s].fp64 = 1;
+            any_run = true;
+          }
+          if (timed_out && js[s].status == BJ_RUN) js[s].status = BJ_TIMEOUT;
+        }
+        if (timed_out) any_run = false;
+        if (!any_run) {
+          int w = -1;
+          for (int s = 0; s < S; ++s)
+            if (js[s].status == BJ_SUCCESS && (w < 0 || js[s].c_train < js[w].c_train)) w = s;
+          if (w < 0)
+            for (int s = 0; s < S; ++s)
+              if (js[s].status != BJ_SKIP && (w < 0 || js[s].c_train < js[w].c_train)) w = s;
+          finish(w, -1);
+        }
+        continue;
+      }
+      if (first < kNoSweep && behind && !timed_out) continue;
       if (ds < kNoSweep && ds <= os) {
         int w = -1;
         for (int s = 0; s < S; ++s)
@@ -428,9 +461,9 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
       }
       if (timed_out) any_run = false;
       if (!any_run) {
-        int w = 0;
-        for (int s = 1; s < S; ++s)
-          if (js[s].c_train < js[w].c_train) w = s;
+        int w = -1;
+        for (int s = 0; s < S; ++s)
+          if (js[s].status != BJ_SKIP && (w < 0 || js[s].c_train < js[w].c_train)) w = s;
         finish(w, -1);
       }
     }
@@ -465,6 +498,11 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
     r.c_val = js[w].c_val;
     r.seconds = secs;
     for (int s = 0; s < S; ++s) r.start_sweeps += js[s].total;
+    if (opts.successes) {
+      int c = 0;
+      for (int s = 0; s < S; ++s) c += js[s].status == BJ_SUCCESS;
+      opts.successes[i] = c;
+    }
     r.sweep_seconds = kernel_seconds;
     if (gates_out[i])
       QFS_HIP(hipMemcpyAsync(gates_out[i], hp[i].g64 + (size_t)w * hp[i].L * 16,
@@ -472,4 +510,35 @@ extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const 
   }
   QFS_HIP(hipStreamSynchronize(st));
   return QFS_OK;
+}
+
+extern "C" int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                                     const qfs_params *params, qfs_c128 *const *gates_out,
+                                     qfs_result *res) {
+  return batch_instantiate(P, tmpl, targets, params, gates_out, res, BatchOpts{});
+}
+
+extern "C" int qfs_instantiate_batch_ex(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                                        const qfs_params *params, const int32_t *m_init,
+                                        const int32_t *starts, qfs_c128 *const *gates_out,
+                                        qfs_result *res) {
+  BatchOpts o;
+  o.m_init = m_init;
+  o.starts = starts;
+  return batch_instantiate(P, tmpl, targets, params, gates_out, res, o);
+}
+
+extern "C" int qfs_label_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                               const qfs_params *params, int32_t *successes, qfs_result *res) {
+  if (!params || !successes || P < 1) {
+    set_error_detail("label: null argument or P < 1");
+    return QFS_EINVAL;
+  }
+  qfs_params q = *params;
+  q.fixed_m = 1;
+  std::vector<qfs_c128 *> none((size_t)P, nullptr);
+  BatchOpts o;
+  o.independent = 1;
+  o.successes = successes;
+  return batch_instantiate(P, tmpl, targets, &q, none.data(), res, o);
 }

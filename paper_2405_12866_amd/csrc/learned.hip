@@ -1,0 +1,256 @@
+// Learned initial sample count and start pruning (project extension). The paper leaves
+// the choice of the initial number of training states open (Sec. 3, Sec. 5) and relates
+// the number needed to the parameter count per amplitude (Sec. 4, the #U3 / 2^n study).
+// Here a small network (mlp.hip) maps 64 structural features of the template to
+//   y0 = log2 of the smallest power-of-two M at which a start succeeds and generalises,
+//   y1 = logit of the probability that one random start succeeds at that M,
+// and the instantiation runs with M0 = 2^round(y0) and just enough starts that at least
+// one succeeds with probability 0.95 under the predicted rate. The fallback is the plain
+// method: when the learned run does not succeed (the held-out validation distance still
+// doubles M inside it, Sec. 3), the problem is rerun from M = m_init with every start.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "batch.h"
+#include "mlp.h"
+
+namespace qfs {
+namespace {
+
+constexpr double kMissProb = 0.05;  // accepted chance that every kept start fails
+
+double lnow() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool valid_template(const qfs_template *t) {
+  if (!t || t->n_qubits < 2 || t->n_qubits > 30 || t->n_gates < 1 || !t->pairs) return false;
+  for (int k = 0; k < t->n_gates; ++k) {
+    const int a = t->pairs[2 * k], b = t->pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= t->n_qubits || b >= t->n_qubits || a == b) return false;
+  }
+  return true;
+}
+
+// Structural features, each scaled to O(1):
+//   0 n/16, 1 L/128, 2 depth/64 (greedy layering), 3 log2(1 + 16L/2^n) (real parameters
+//   per amplitude, the paper's explanatory variable up to the factor), 4 log2(16L)/16,
+//   5 distinct pairs / L, 6 touched qubits / n, 7 max qubit degree / L, 8 std of qubit
+//   degree / (L+1), 9 connected components / n, 10 depth / L, 11 log2(depth+1)/8,
+//   12..27 histogram of qubit degrees (bins 0..15+, fraction of qubits),
+//   28..43 histogram of |a - b| (bins 1..16+, fraction of gates),
+//   44..59 histogram of gate layers over 16 equal depth bins (fraction of gates),
+//   60 n/L, 61 min(1, 2^n / 16L), 62 1/n, 63 constant 1.
+void template_features(const qfs_template &t, float *out) {
+  const int n = t.n_qubits, L = t.n_gates;
+  std::vector<int> layer(n, 0), deg(n, 0), gate_layer(L, 0);
+  std::vector<char> adj((size_t)n * n, 0);
+  int depth = 0, distinct = 0;
+  for (int k = 0; k < L; ++k) {
+    const int a = t.pairs[2 * k], b = t.pairs[2 * k + 1];
+    const int l = std::max(layer[a], layer[b]) + 1;
+    layer[a] = layer[b] = l;
+    gate_layer[k] = l;
+    depth = std::max(depth, l);
+    ++deg[a];
+    ++deg[b];
+    if (!adj[(size_t)a * n + b]) ++distinct;
+    adj[(size_t)a * n + b] = adj[(size_t)b * n + a] = 1;
+  }
+  std::vector<int> comp(n, -1), stack;
+  int ncomp = 0;
+  for (int q = 0; q < n; ++q) {
+    if (comp[q] >= 0) continue;
+    comp[q] = ncomp;
+    stack.assign(1, q);
+    while (!stack.empty()) {
+      const int x = stack.back();
+      stack.pop_back();
+      for (int y = 0; y < n; ++y)
+        if (adj[(size_t)x * n + y] && comp[y] < 0) {
+          comp[y] = ncomp;
+          stack.push_back(y);
+        }
+    }
+    ++ncomp;
+  }
+  int touched = 0, maxdeg = 0;
+  double mean = 0.0, var = 0.0;
+  for (int q = 0; q < n; ++q) {
+    touched += deg[q] > 0;
+    maxdeg = std::max(maxdeg, deg[q]);
+    mean += deg[q];
+  }
+  mean /= n;
+  for (int q = 0; q < n; ++q) var += (deg[q] - mean) * (deg[q] - mean);
+  var /= n;
+  double f[kMlpF] = {0};
+  const double N = std::ldexp(1.0, n);
+  f[0] = n / 16.0;
+  f[1] = L / 128.0;
+  f[2] = depth / 64.0;
+  f[3] = std::log2(1.0 + 16.0 * L / N);
+  f[4] = std::log2(16.0 * L) / 16.0;
+  f[5] = (double)distinct / L;
+  f[6] = (double)touched / n;
+  f[7] = (double)maxdeg / L;
+  f[8] = std::sqrt(var) / (L + 1.0);
+  f[9] = (double)ncomp / n;
+  f[10] = (double)depth / L;
+  f[11] = std::log2(depth + 1.0) / 8.0;
+  for (int q = 0; q < n; ++q) f[12 + std::min(deg[q], 15)] += 1.0 / n;
+  for (int k = 0; k < L; ++k) {
+    const int d = std::abs(t.pairs[2 * k] - t.pairs[2 * k + 1]);
+    f[28 + std::min(d, 16) - 1] += 1.0 / L;
+  }
+  for (int k = 0; k < L; ++k) f[44 + std::min(15, (int)((gate_layer[k] - 1) * 16.0 / depth))] += 1.0 / L;
+  f[60] = (double)n / L;
+  f[61] = std::min(1.0, N / (16.0 * L));
+  f[62] = 1.0 / n;
+  f[63] = 1.0;
+  for (int i = 0; i < kMlpF; ++i) out[i] = (float)f[i];
+}
+
+// Network outputs -> (M0, kept starts).
+void decide(const float *y, int n, int S, int32_t *m0, int32_t *starts) {
+  const double lg = std::min<double>(n, std::max(1.0, std::nearbyint((double)y[0])));
+  *m0 = (int32_t)std::ldexp(1.0, (int)lg);
+  const double p = 1.0 / (1.0 + std::exp(-(double)y[1]));
+  int k = S;
+  if (p >= 1.0) k = 1;
+  else if (p > 0.0) k = (int)std::ceil(std::log(kMissProb) / std::log1p(-p));
+  *starts = std::max(1, std::min(S, k));
+}
+
+int predict_many(int P, const qfs_template *tmpl, const qfs_params &p, int32_t *m0, int32_t *starts,
+                 hipStream_t s) {
+  std::vector<float> feat((size_t)P * kMlpF), y((size_t)P * kMlpO);
+  for (int i = 0; i < P; ++i) {
+    if (!valid_template(&tmpl[i])) return set_error_detail("learned: invalid template"), QFS_EINVAL;
+    template_features(tmpl[i], feat.data() + (size_t)i * kMlpF);
+  }
+  DevBuf fd, yd;
+  QFS_TRY(fd.alloc(sizeof(float) * feat.size()));
+  QFS_TRY(yd.alloc(sizeof(float) * y.size()));
+  QFS_HIP(hipMemcpyAsync(fd.ptr, feat.data(), sizeof(float) * feat.size(), hipMemcpyHostToDevice, s));
+  QFS_TRY(mlp_predict(P, fd.as<float>(), yd.as<float>(), s));
+  QFS_HIP(hipMemcpyAsync(y.data(), yd.ptr, sizeof(float) * y.size(), hipMemcpyDeviceToHost, s));
+  QFS_HIP(hipStreamSynchronize(s));
+  const int S = std::max(1, p.multistarts);
+  for (int i = 0; i < P; ++i) decide(y.data() + (size_t)i * kMlpO, tmpl[i].n_qubits, S, m0 + i, starts + i);
+  return QFS_OK;
+}
+
+}  // namespace
+}  // namespace qfs
+
+using namespace qfs;
+
+extern "C" {
+
+int qfs_features(const qfs_template *t, float *out) {
+  if (!valid_template(t) || !out) return set_error_detail("features: invalid template"), QFS_EINVAL;
+  template_features(*t, out);
+  return QFS_OK;
+}
+
+int qfs_predict_m(const qfs_template *t, const qfs_params *params, int32_t *m0, uint32_t *keep_mask) {
+  if (!t || !params || !m0) return QFS_EINVAL;
+  int32_t k = 0;
+  QFS_TRY(predict_many(1, t, *params, m0, &k, static_cast<hipStream_t>(params->hip_stream)));
+  if (keep_mask) *keep_mask = k >= 32 ? 0xffffffffu : ((1u << k) - 1u);
+  return QFS_OK;
+}
+
+int qfs_predict_batch(int32_t P, const qfs_template *tmpl, const qfs_params *params, int32_t *m0,
+                      int32_t *starts) {
+  if (P < 1 || !tmpl || !params || !m0 || !starts) return QFS_EINVAL;
+  return predict_many(P, tmpl, *params, m0, starts, static_cast<hipStream_t>(params->hip_stream));
+}
+
+int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
+                            qfs_c128 *gates_out, qfs_result *res) {
+  if (!tmpl || !target || !params || !res) return QFS_EINVAL;
+  const double t0 = lnow();
+  int32_t m0 = 0, k = 0;
+  QFS_TRY(predict_many(1, tmpl, *params, &m0, &k, static_cast<hipStream_t>(params->hip_stream)));
+  qfs_params q = *params;
+  q.m_init = std::max(params->m_init, m0);
+  q.multistarts = k;
+  qfs_result r1;
+  QFS_TRY(qfs_instantiate(tmpl, target, &q, nullptr, gates_out, &r1));
+  if (r1.reason == QFS_SUCCESS) {
+    *res = r1;
+    res->m_predicted = m0;
+    res->starts_run = k;
+    res->fallback = 0;
+    res->seconds = lnow() - t0;
+    return QFS_OK;
+  }
+  qfs_result r2;
+  QFS_TRY(qfs_instantiate(tmpl, target, params, nullptr, gates_out, &r2));
+  *res = r2;
+  res->m_predicted = m0;
+  res->starts_run = k + params->multistarts;
+  res->fallback = 1;
+  res->start_sweeps += r1.start_sweeps;
+  res->sweep_seconds += r1.sweep_seconds;
+  res->m_total += r1.m_total;
+  res->seconds = lnow() - t0;
+  return QFS_OK;
+}
+
+int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
+                                  const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res) {
+  if (P < 1 || !tmpl || !targets || !params || !gates_out || !res) return QFS_EINVAL;
+  const double t0 = lnow();
+  std::vector<int32_t> m0(P), k(P);
+  QFS_TRY(predict_many(P, tmpl, *params, m0.data(), k.data(), static_cast<hipStream_t>(params->hip_stream)));
+  for (int i = 0; i < P; ++i) m0[i] = std::max(params->m_init, m0[i]);
+  BatchOpts o;
+  o.m_init = m0.data();
+  o.starts = k.data();
+  QFS_TRY(batch_instantiate(P, tmpl, targets, params, gates_out, res, o));
+  std::vector<int> failed;
+  for (int i = 0; i < P; ++i) {
+    res[i].m_predicted = m0[i];
+    res[i].starts_run = k[i];
+    res[i].fallback = 0;
+    if (res[i].reason != QFS_SUCCESS) failed.push_back(i);
+  }
+  if (!failed.empty()) {
+    const int F = (int)failed.size();
+    std::vector<qfs_template> ft(F);
+    std::vector<qfs_target> fg(F);
+    std::vector<qfs_c128 *> fo(F);
+    std::vector<qfs_result> fr(F);
+    for (int f = 0; f < F; ++f) {
+      ft[f] = tmpl[failed[f]];
+      fg[f] = targets[failed[f]];
+      fo[f] = gates_out[failed[f]];
+    }
+    // the plain method on the failed problems; problem seeds follow their original index
+    std::vector<uint64_t> seeds(F);
+    for (int f = 0; f < F; ++f) seeds[f] = params->seed + (uint64_t)failed[f];
+    BatchOpts plain;
+    plain.seeds = seeds.data();
+    QFS_TRY(batch_instantiate(F, ft.data(), fg.data(), params, fo.data(), fr.data(), plain));
+    for (int f = 0; f < F; ++f) {
+      qfs_result &r = res[failed[f]];
+      const qfs_result first = r;
+      r = fr[f];
+      r.m_predicted = first.m_predicted;
+      r.starts_run = first.starts_run + params->multistarts;
+      r.fallback = 1;
+      r.start_sweeps += first.start_sweeps;
+      r.m_total += first.m_total;
+    }
+  }
+  const double secs = lnow() - t0;
+  for (int i = 0; i < P; ++i) res[i].seconds = secs;
+  return QFS_OK;
+}
+
+}  // extern "C"

@@ -57,13 +57,18 @@ class Result(C.Structure):
                 ("start_groups", C.c_int32), ("refined", C.c_int32), ("c_train", C.c_double),
                 ("c_val", C.c_double), ("seconds", C.c_double), ("start_sweeps", C.c_int64),
                 ("sweep_seconds", C.c_double), ("kernel_launches", C.c_int64 * 4),
-                ("kernel_seconds", C.c_double * 4), ("kernel_bytes", C.c_double * 4)]
+                ("kernel_seconds", C.c_double * 4), ("kernel_bytes", C.c_double * 4),
+                ("m_predicted", C.c_int32), ("starts_run", C.c_int32), ("fallback", C.c_int32)]
 
 
 EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",
            "qfs_instantiate", "qfs_instantiate_batch", "qfs_instantiate_samples", "qfs_draw_states", "qfs_haar_gates",
            "qfs_apply_gates", "qfs_dense_apply", "qfs_environment", "qfs_polar_update",
-           "qfs_sweep", "qfs_state_distance"]
+           "qfs_sweep", "qfs_state_distance", "qfs_label_batch", "qfs_features",
+           "qfs_mlp_num_params", "qfs_mlp_init", "qfs_mlp_get", "qfs_mlp_set", "qfs_mlp_save",
+           "qfs_mlp_load", "qfs_mlp_forward", "qfs_mlp_grad", "qfs_mlp_train", "qfs_predict_m",
+           "qfs_predict_batch", "qfs_instantiate_learned", "qfs_instantiate_batch_learned",
+           "qfs_instantiate_batch_ex"]
 
 
 def load():
@@ -97,6 +102,25 @@ def load():
         lib.qfs_polar_update.argtypes = [I32, P, D, P, P]
         lib.qfs_sweep.argtypes = [I32, I32, P, I32, P, P, I32, P, I32, D, P, P]
         lib.qfs_state_distance.argtypes = [I32, I32, P, P, C.POINTER(C.c_double), P]
+        batch_args = [I32, C.POINTER(Template), C.POINTER(Target), C.POINTER(Params)]
+        lib.qfs_label_batch.argtypes = batch_args + [P, C.POINTER(Result)]
+        lib.qfs_instantiate_batch_ex.argtypes = batch_args + [P, P, C.POINTER(C.c_void_p),
+                                                              C.POINTER(Result)]
+        lib.qfs_instantiate_batch_learned.argtypes = batch_args + [C.POINTER(C.c_void_p),
+                                                                   C.POINTER(Result)]
+        lib.qfs_instantiate_learned.argtypes = [C.POINTER(Template), C.POINTER(Target),
+                                                C.POINTER(Params), P, C.POINTER(Result)]
+        lib.qfs_features.argtypes = [C.POINTER(Template), P]
+        lib.qfs_mlp_init.argtypes = [U64]
+        lib.qfs_mlp_get.argtypes = [P]
+        lib.qfs_mlp_set.argtypes = [P]
+        lib.qfs_mlp_save.argtypes = [C.c_char_p]
+        lib.qfs_mlp_load.argtypes = [C.c_char_p]
+        lib.qfs_mlp_forward.argtypes = [I32, P, P, P]
+        lib.qfs_mlp_grad.argtypes = [I32, P, P, P, P, P]
+        lib.qfs_mlp_train.argtypes = [I32, P, P, I32, I32, C.c_float, U64, P, P]
+        lib.qfs_predict_m.argtypes = [C.POINTER(Template), C.POINTER(Params), P, P]
+        lib.qfs_predict_batch.argtypes = [I32, C.POINTER(Template), C.POINTER(Params), P, P]
         for name in EXPORTS:
             if name not in ("qfs_strerror", "qfs_last_error_detail", "qfs_version",
                             "qfs_default_params"):
@@ -150,12 +174,38 @@ def _params(d):
     return p
 
 
-def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=None,
-                    phi=None, n_val=0, params=None, gates_in=None):
-    """QFactor-Sample instantiation on the device. Exactly one target form: dense ``U``
-    [N, N]; a circuit (``target_pairs``, ``target_gates`` [Lt, 4, 4]); or samples
-    ``psi``/``phi`` [n_samples, N] whose last ``n_val`` rows validate. Returns
-    (gates [L, 4, 4] complex128 device tensor, result dict)."""
+def _fill_target(tgt, n, keep, U=None, target_pairs=None, target_gates=None, psi=None,
+                 phi=None, n_val=0):
+    """Fill a Target from one target form; returns the device of its tensors."""
+    if U is not None:
+        tgt.kind = QFS_TARGET_DENSE
+        tgt.U = _dev_c128(U, "U")
+        return U.device
+    if target_pairs is not None:
+        tarr, tp = _pairs(target_pairs)
+        ct = Template(n, tarr.shape[0], tp)
+        keep += [tarr, ct]
+        tgt.kind = QFS_TARGET_CIRCUIT
+        tgt.circuit = C.pointer(ct)
+        tgt.circuit_gates = _dev_c128(target_gates, "target_gates")
+        return target_gates.device
+    tgt.kind = QFS_TARGET_SAMPLES
+    tgt.psi = _dev_c128(psi, "psi")
+    tgt.phi = _dev_c128(phi, "phi")
+    tgt.n_samples = psi.shape[0]
+    tgt.n_val = n_val
+    return psi.device
+
+
+def _info(res):
+    info = {f: getattr(res, f) for f, _ in Result._fields_}
+    for f in ("kernel_launches", "kernel_seconds", "kernel_bytes"):
+        info[f] = list(info[f])
+    info["reason_name"] = REASONS.get(res.reason, "?")
+    return info
+
+
+def _single(fn_name, n, pairs, params, gates_in, target):
     import torch
     lib = load()
     arr, pp = _pairs(pairs)
@@ -163,38 +213,74 @@ def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, p
     tmpl = Template(n, L, pp)
     tgt = Target()
     keep = [arr]
-    dev = None
-    if U is not None:
-        tgt.kind = QFS_TARGET_DENSE
-        tgt.U = _dev_c128(U, "U")
-        dev = U.device
-    elif target_pairs is not None:
-        tarr, tp = _pairs(target_pairs)
-        keep.append(tarr)
-        ct = Template(n, tarr.shape[0], tp)
-        keep.append(ct)
-        tgt.kind = QFS_TARGET_CIRCUIT
-        tgt.circuit = C.pointer(ct)
-        tgt.circuit_gates = _dev_c128(target_gates, "target_gates")
-        dev = target_gates.device
-    else:
-        tgt.kind = QFS_TARGET_SAMPLES
-        tgt.psi = _dev_c128(psi, "psi")
-        tgt.phi = _dev_c128(phi, "phi")
-        tgt.n_samples = psi.shape[0]
-        tgt.n_val = n_val
-        dev = psi.device
+    dev = _fill_target(tgt, n, keep, **target)
     par = _params(params)
-    gi = _dev_c128(gates_in, "gates_in") if gates_in is not None else None
     out = torch.empty((L, 4, 4), dtype=torch.complex128, device=dev)
     res = Result()
-    _check(lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), gi,
-                               C.c_void_p(out.data_ptr()), C.byref(res)), "qfs_instantiate")
-    info = {f: getattr(res, f) for f, _ in Result._fields_}
-    for f in ("kernel_launches", "kernel_seconds", "kernel_bytes"):
-        info[f] = list(info[f])
-    info["reason_name"] = REASONS.get(res.reason, "?")
-    return out, info
+    if fn_name == "qfs_instantiate":
+        gi = _dev_c128(gates_in, "gates_in") if gates_in is not None else None
+        rc = lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), gi,
+                                 C.c_void_p(out.data_ptr()), C.byref(res))
+    else:
+        rc = lib.qfs_instantiate_learned(C.byref(tmpl), C.byref(tgt), C.byref(par),
+                                         C.c_void_p(out.data_ptr()), C.byref(res))
+    _check(rc, fn_name)
+    return out, _info(res)
+
+
+def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=None,
+                    phi=None, n_val=0, params=None, gates_in=None):
+    """QFactor-Sample instantiation on the device. Exactly one target form: dense ``U``
+    [N, N]; a circuit (``target_pairs``, ``target_gates`` [Lt, 4, 4]); or samples
+    ``psi``/``phi`` [n_samples, N] whose last ``n_val`` rows validate. Returns
+    (gates [L, 4, 4] complex128 device tensor, result dict)."""
+    return _single("qfs_instantiate", n, pairs, params, gates_in,
+                   dict(U=U, target_pairs=target_pairs, target_gates=target_gates, psi=psi,
+                        phi=phi, n_val=n_val))
+
+
+def qfs_instantiate_learned(n, pairs, *, U=None, target_pairs=None, target_gates=None,
+                            psi=None, phi=None, n_val=0, params=None):
+    """qfs_instantiate from the predicted initial M and start count, with the plain
+    method as fallback. Needs loaded network weights (qfs_mlp_load / qfs_mlp_set)."""
+    return _single("qfs_instantiate_learned", n, pairs, params, None,
+                   dict(U=U, target_pairs=target_pairs, target_gates=target_gates, psi=psi,
+                        phi=phi, n_val=n_val))
+
+
+_TARGET_KEYS = ("U", "target_pairs", "target_gates", "psi", "phi", "n_val")
+
+
+def _batch(fn_name, problems, params, with_gates=True, per_problem=None):
+    import numpy as np
+    import torch
+    lib = load()
+    P = len(problems)
+    tmpls = (Template * P)()
+    tgts = (Target * P)()
+    keep, outs = [], []
+    for i, pr in enumerate(problems):
+        arr, pp = _pairs(pr["pairs"])
+        keep.append(arr)
+        tmpls[i] = Template(pr["n"], arr.shape[0], pp)
+        dev = _fill_target(tgts[i], pr["n"], keep, **{k: pr[k] for k in _TARGET_KEYS if k in pr})
+        if with_gates:
+            outs.append(torch.empty((arr.shape[0], 4, 4), dtype=torch.complex128, device=dev))
+    res = (Result * P)()
+    par = _params(params)
+    if with_gates:
+        ptrs = (C.c_void_p * P)(*[o.data_ptr() for o in outs])
+        extra = []
+        if per_problem is not None:
+            arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.int32) for a in per_problem]
+            keep += arrs
+            extra = [None if a is None else a.ctypes.data_as(C.c_void_p) for a in arrs]
+        _check(getattr(lib, fn_name)(P, tmpls, tgts, C.byref(par), *extra, ptrs, res), fn_name)
+        return outs, [_info(r) for r in res]
+    succ = np.zeros(P, dtype=np.int32)
+    _check(getattr(lib, fn_name)(P, tmpls, tgts, C.byref(par), succ.ctypes.data_as(C.c_void_p),
+                                 res), fn_name)
+    return succ, [_info(r) for r in res]
 
 
 def qfs_instantiate_batch(problems, params=None):
@@ -202,51 +288,131 @@ def qfs_instantiate_batch(problems, params=None):
     target form (``U``; ``target_pairs`` + ``target_gates``; or ``psi``/``phi`` with
     ``n_val``), device tensors as in qfs_instantiate. Problem p uses seed
     params["seed"] + p. Returns (list of gate tensors [L, 4, 4], list of result dicts)."""
+    return _batch("qfs_instantiate_batch", problems, params)
+
+
+def qfs_instantiate_batch_ex(problems, params=None, m_init=None, starts=None):
+    """qfs_instantiate_batch with optional per-problem initial M and start counts."""
+    return _batch("qfs_instantiate_batch_ex", problems, params, per_problem=(m_init, starts))
+
+
+def qfs_instantiate_batch_learned(problems, params=None):
+    """qfs_instantiate_batch with predicted initial M and start counts per problem and a
+    batched plain rerun of the problems that did not succeed."""
+    return _batch("qfs_instantiate_batch_learned", problems, params)
+
+
+def qfs_label_batch(problems, params=None):
+    """Every start of every problem run to its own stop at fixed M = params["m_init"].
+    Returns (successful starts per problem as an int32 array, result dicts)."""
+    return _batch("qfs_label_batch", problems, params, with_gates=False)
+
+
+def qfs_features(n, pairs):
+    """The 64 structural features of a template (host computation in the library)."""
+    import numpy as np
+    arr, pp = _pairs(pairs)
+    out = np.zeros(64, dtype=np.float32)
+    tmpl = Template(n, arr.shape[0], pp)
+    _check(load().qfs_features(C.byref(tmpl), out.ctypes.data_as(C.c_void_p)), "qfs_features")
+    return out
+
+
+def qfs_mlp_num_params():
+    return load().qfs_mlp_num_params()
+
+
+def qfs_mlp_init(seed):
+    _check(load().qfs_mlp_init(seed), "qfs_mlp_init")
+
+
+def qfs_mlp_get():
+    import numpy as np
+    out = np.zeros(qfs_mlp_num_params(), dtype=np.float32)
+    _check(load().qfs_mlp_get(out.ctypes.data_as(C.c_void_p)), "qfs_mlp_get")
+    return out
+
+
+def qfs_mlp_set(params):
+    import numpy as np
+    arr = np.ascontiguousarray(params, dtype=np.float32)
+    if arr.size != qfs_mlp_num_params():
+        raise ValueError("wrong parameter count")
+    _check(load().qfs_mlp_set(arr.ctypes.data_as(C.c_void_p)), "qfs_mlp_set")
+
+
+def qfs_mlp_save(path):
+    _check(load().qfs_mlp_save(os.fsencode(path)), "qfs_mlp_save")
+
+
+def qfs_mlp_load(path):
+    _check(load().qfs_mlp_load(os.fsencode(path)), "qfs_mlp_load")
+
+
+def _dev_f32(t, name, cols):
     import torch
-    lib = load()
-    P = len(problems)
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous() and t.dim() == 2 and t.shape[1] == cols):
+        raise TypeError(f"{name} must be a contiguous float32 [count, {cols}] tensor on a HIP device")
+    return C.c_void_p(t.data_ptr())
+
+
+def qfs_mlp_forward(features):
+    import torch
+    out = torch.empty((features.shape[0], 2), dtype=torch.float32, device=features.device)
+    _check(load().qfs_mlp_forward(features.shape[0], _dev_f32(features, "features", 64),
+                                  C.c_void_p(out.data_ptr()), _stream()), "qfs_mlp_forward")
+    return out
+
+
+def qfs_mlp_grad(features, targets):
+    """Returns (gradient as a float32 numpy array, mean loss)."""
+    import numpy as np
+    g = np.zeros(qfs_mlp_num_params(), dtype=np.float32)
+    loss = C.c_float()
+    _check(load().qfs_mlp_grad(features.shape[0], _dev_f32(features, "features", 64),
+                               _dev_f32(targets, "targets", 2), g.ctypes.data_as(C.c_void_p),
+                               C.byref(loss), _stream()), "qfs_mlp_grad")
+    return g, loss.value
+
+
+def qfs_mlp_train(features, targets, epochs, batch, lr, seed=0):
+    """Returns the per-epoch mean mini-batch loss (numpy)."""
+    import numpy as np
+    out = np.zeros(epochs, dtype=np.float32)
+    _check(load().qfs_mlp_train(features.shape[0], _dev_f32(features, "features", 64),
+                                _dev_f32(targets, "targets", 2), epochs, batch, lr, seed,
+                                out.ctypes.data_as(C.c_void_p), _stream()), "qfs_mlp_train")
+    return out
+
+
+def qfs_predict_m(n, pairs, params=None):
+    """Returns (predicted initial M, keep mask over starts)."""
+    arr, pp = _pairs(pairs)
+    tmpl = Template(n, arr.shape[0], pp)
+    m0 = C.c_int32()
+    mask = C.c_uint32()
+    _check(load().qfs_predict_m(C.byref(tmpl), C.byref(_params(params)), C.byref(m0),
+                                C.byref(mask)), "qfs_predict_m")
+    return m0.value, mask.value
+
+
+def qfs_predict_batch(templates, params=None):
+    """templates: list of (n, pairs). Returns (M0 array, start-count array)."""
+    import numpy as np
+    P = len(templates)
     tmpls = (Template * P)()
-    tgts = (Target * P)()
     keep = []
-    outs = []
-    for i, pr in enumerate(problems):
-        arr, pp = _pairs(pr["pairs"])
+    for i, (n, pairs) in enumerate(templates):
+        arr, pp = _pairs(pairs)
         keep.append(arr)
-        tmpls[i] = Template(pr["n"], arr.shape[0], pp)
-        t = tgts[i]
-        if pr.get("U") is not None:
-            t.kind = QFS_TARGET_DENSE
-            t.U = _dev_c128(pr["U"], "U")
-            dev = pr["U"].device
-        elif pr.get("target_pairs") is not None:
-            tarr, tp = _pairs(pr["target_pairs"])
-            ct = Template(pr["n"], tarr.shape[0], tp)
-            keep += [tarr, ct]
-            t.kind = QFS_TARGET_CIRCUIT
-            t.circuit = C.pointer(ct)
-            t.circuit_gates = _dev_c128(pr["target_gates"], "target_gates")
-            dev = pr["target_gates"].device
-        else:
-            t.kind = QFS_TARGET_SAMPLES
-            t.psi = _dev_c128(pr["psi"], "psi")
-            t.phi = _dev_c128(pr["phi"], "phi")
-            t.n_samples = pr["psi"].shape[0]
-            t.n_val = pr.get("n_val", 0)
-            dev = pr["psi"].device
-        outs.append(torch.empty((arr.shape[0], 4, 4), dtype=torch.complex128, device=dev))
-    ptrs = (C.c_void_p * P)(*[o.data_ptr() for o in outs])
-    res = (Result * P)()
-    par = _params(params)
-    _check(lib.qfs_instantiate_batch(P, tmpls, tgts, C.byref(par), ptrs, res),
-           "qfs_instantiate_batch")
-    infos = []
-    for r in res:
-        d = {f: getattr(r, f) for f, _ in Result._fields_}
-        for f in ("kernel_launches", "kernel_seconds", "kernel_bytes"):
-            d[f] = list(d[f])
-        d["reason_name"] = REASONS.get(r.reason, "?")
-        infos.append(d)
-    return outs, infos
+        tmpls[i] = Template(n, arr.shape[0], pp)
+    m0 = np.zeros(P, dtype=np.int32)
+    k = np.zeros(P, dtype=np.int32)
+    _check(load().qfs_predict_batch(P, tmpls, C.byref(_params(params)),
+                                    m0.ctypes.data_as(C.c_void_p), k.ctypes.data_as(C.c_void_p)),
+           "qfs_predict_batch")
+    return m0, k
 
 
 def qfs_instantiate_samples(n, pairs, psi, phi, M, tol):

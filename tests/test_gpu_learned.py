@@ -1,0 +1,184 @@
+"""GPU tests of the learned sample-count predictor: the network kernels against the FP64
+network oracle (forward, gradient, first Adam step), training, the weight file, the
+labelling runs against the instantiation oracle, and the gain of the trained predictor
+over the plain method on held-out problems.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp_oracle as MO
+from paper_2405_12866_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2405_12866_amd import predictor as PR  # noqa: E402
+from paper_2405_12866_amd import qfs as Q  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _theta(seed, scale=1.0):
+    g = np.random.default_rng(seed)
+    th = np.zeros(MO.NUM_PARAMS, dtype=np.float32)
+    o = 0
+    for _, shape in MO.SIZES:
+        k = int(np.prod(shape))
+        fan_in = shape[1] if len(shape) == 2 else 16
+        th[o:o + k] = g.uniform(-1, 1, k) * scale * math.sqrt(6.0 / fan_in)
+        o += k
+    return th
+
+
+def _data(seed, B):
+    g = np.random.default_rng(seed)
+    X = g.uniform(0, 1, (B, 64)).astype(np.float32)
+    T = np.stack([g.integers(1, 8, B), g.uniform(0, 1, B)], 1).astype(np.float32)
+    T[::4, 0] = np.nan
+    return X, T
+
+
+def _dev(a):
+    return torch.as_tensor(a).contiguous().to(DEV)
+
+
+def test_mlp_forward_and_gradient_match_oracle():
+    say("mlp forward + gradient vs FP64 oracle, B = 100 (ragged over 32-row blocks)")
+    th = _theta(1)
+    Q.qfs_mlp_set(th)
+    assert np.array_equal(Q.qfs_mlp_get(), th)
+    X, T = _data(2, 100)
+    eff = MO.effective(th)
+    y_ref, _ = MO.forward(eff, X.astype(np.float64))
+    y = Q.qfs_mlp_forward(_dev(X)).cpu().numpy()
+    assert np.max(np.abs(y - y_ref) / (1 + np.abs(y_ref))) < 1e-4
+    g, loss = Q.qfs_mlp_grad(_dev(X), _dev(T))
+    g_ref = MO.gradient(eff, X.astype(np.float64), T.astype(np.float64))
+    l_ref = MO.loss(eff, X.astype(np.float64), T.astype(np.float64))
+    err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    say(f"  grad rel err {err:.2e}, loss {loss:.6f} vs {l_ref:.6f}")
+    assert err < 1e-4
+    assert abs(loss - l_ref) <= 1e-5 * abs(l_ref)
+
+
+def test_adam_first_step():
+    say("one Adam step on the full batch: step = lr * sign(gradient)")
+    th = _theta(3)
+    Q.qfs_mlp_set(th)
+    X, T = _data(4, 64)
+    lr = 1e-3
+    Q.qfs_mlp_train(_dev(X), _dev(T), epochs=1, batch=64, lr=lr, seed=1)
+    after = Q.qfs_mlp_get().astype(np.float64)
+    g_ref = MO.gradient(MO.effective(th), X.astype(np.float64), T.astype(np.float64))
+    big = np.abs(g_ref) > 1e-3 * np.max(np.abs(g_ref))
+    expect = th.astype(np.float64) - lr * np.sign(g_ref)
+    assert big.sum() > 1000
+    assert np.max(np.abs(after - expect)[big]) < 2e-6
+
+
+def test_training_reduces_loss():
+    say("training on a learnable synthetic task")
+    g = np.random.default_rng(5)
+    X = g.uniform(0, 1, (2048, 64)).astype(np.float32)
+    T = np.stack([2 + 3 * X[:, 0] - 2 * X[:, 1], (X[:, 2] > 0.5).astype(np.float32)], 1).astype(np.float32)
+    Q.qfs_mlp_init(9)
+    losses = Q.qfs_mlp_train(_dev(X), _dev(T), epochs=60, batch=128, lr=2e-3, seed=2)
+    say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.25 * losses[0]
+
+
+def test_weight_file_roundtrip(tmp_path):
+    th = _theta(6)
+    Q.qfs_mlp_set(th)
+    path = str(tmp_path / "w.bin")
+    Q.qfs_mlp_save(path)
+    Q.qfs_mlp_set(_theta(7))
+    Q.qfs_mlp_load(path)
+    assert np.array_equal(Q.qfs_mlp_get(), th)
+    with open(path, "r+b") as f:
+        f.write(b"XXXX")
+    with pytest.raises(Q.QfsError):
+        Q.qfs_mlp_load(path)
+
+
+def test_label_batch_matches_oracle_per_start():
+    say("labelling runs (FP64, fixed M, independent starts) vs oracle start by start")
+    g = np.random.default_rng(8)
+    probs = []
+    for _ in range(4):
+        n = int(g.integers(3, 5))
+        L = int(g.integers(2, 5))
+        pairs = I.random_pair_template(n, L, g)
+        probs.append(dict(n=n, pairs=pairs, target_pairs=pairs, target_gates=I.haar_gates(L, g)))
+    S, m, base = 4, 4, 500
+    params = dict(multistarts=S, m_init=m, seed=base, precision=Q.QFS_PREC_FP64, max_iter=300,
+                  dist_tol=1e-10, batch_sweeps=4)
+    succ, infos = Q.qfs_label_batch(PR.device_problems(probs, DEV), params)
+    for i, p in enumerate(probs):
+        count = 0
+        for s in range(S):
+            gi = np.stack([O.haar_gate(base + i, s, k) for k in range(len(p["pairs"]))])[None]
+            op = O.default_params(multistarts=1, m_init=m, fixed_m=1, seed=base + i, max_iter=300,
+                                  dist_tol=1e-10)
+            _, r = O.instantiate(p["n"], p["pairs"], target_pairs=p["target_pairs"],
+                                 target_gates=p["target_gates"], params=op, gates_in=gi)
+            count += r["reason_name"] == "SUCCESS"
+        say(f"  problem {i}: n={p['n']} L={len(p['pairs'])} successes gpu={succ[i]} oracle={count}")
+        assert succ[i] == count
+
+
+def test_learned_gain_over_plain():
+    """Train on labels from the method's own runs; on held-out problems the learned runs
+    need less work than plain doubling from M = 2 with every start, at the same success
+    criterion, and every success is a real solution (full distance)."""
+    train_probs = I.batched_problems(1024, seed_base=0x5A17 + 40, n_range=(3, 6), L_range=(2, 14))
+    test_probs = I.batched_problems(192, seed_base=0x5A17 + 41, n_range=(3, 6), L_range=(2, 14))
+    say("labelling 1024 training problems")
+    T, work = PR.label(PR.device_problems(train_probs, DEV), log=say)
+    X = PR.features(train_probs)
+    losses = PR.train(X, T, epochs=150, batch=128, lr=2e-3)
+    say(f"  trained: loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    dtest = PR.device_problems(test_probs, DEV)
+    params = dict(multistarts=16, seed=77, max_iter=2000, batch_sweeps=8, dist_tol=1e-9)
+    Q.qfs_instantiate_batch(dtest[:8], params)  # warm the autotuner for both runs
+    torch.cuda.synchronize()
+    g_plain, r_plain = Q.qfs_instantiate_batch(dtest, params)
+    g_learn, r_learn = Q.qfs_instantiate_batch_learned(dtest, params)
+    torch.cuda.synchronize()
+
+    def work_of(rs):  # amplitude-sweeps: start-sweeps x M x 2^n x L (upper bound per M)
+        return sum(r["start_sweeps"] * r["m_final"] * (1 << p["n"]) * len(p["pairs"])
+                   for r, p in zip(rs, test_probs))
+
+    ok_p = sum(r["reason_name"] == "SUCCESS" for r in r_plain)
+    ok_l = sum(r["reason_name"] == "SUCCESS" for r in r_learn)
+    ss_p = sum(r["start_sweeps"] for r in r_plain)
+    ss_l = sum(r["start_sweeps"] for r in r_learn)
+    fb = sum(r["fallback"] for r in r_learn)
+    say(f"  plain: {ok_p}/192 ok, {ss_p} start-sweeps, {r_plain[0]['seconds']:.2f} s")
+    say(f"  learned: {ok_l}/192 ok, {ss_l} start-sweeps, {r_learn[0]['seconds']:.2f} s, "
+        f"{fb} fallbacks")
+    assert ok_l >= ok_p - 2
+    assert ss_l < 0.7 * ss_p
+    for i in range(0, 192, 12):
+        if r_learn[i]["reason_name"] != "SUCCESS":
+            continue
+        p = test_probs[i]
+        basis = np.eye(1 << p["n"], dtype=np.complex128)
+        d = O.state_distance(p["n"], O.apply_circuit(p["n"], basis, p["pairs"], g_learn[i].cpu().numpy()),
+                             O.apply_circuit(p["n"], basis, p["target_pairs"], p["target_gates"]))
+        assert d <= 1e-8, (i, d)
