@@ -192,10 +192,11 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target,
  * complex128 refinement switch happen between launches. Problem p uses seed
  * params->seed + p. With batch_sweeps = 1 every problem follows qfs_instantiate's
  * lock-step control flow; with batch_sweeps = K > 1 the starts of a problem advance up
- * to K sweeps independently, and a success or overtraining found by one start takes
- * effect at that start's sweep count (the others stop there), so the returned start is
- * the same as in lock step unless a start that would succeed later was overtaken by a
- * doubling. MIXED precision switches each start to complex128 on its own.
+ * to K sweeps independently, a success or overtraining found by one start at its sweep
+ * count t takes effect at t (slower starts run on to t), and the decision at t is lock
+ * step's; a start that had already run past t resumes from its later state after a
+ * doubling. MIXED precision switches each start to complex128 on its own
+ * (qfs_instantiate switches all starts together).
  *   tmpl, targets: host arrays [P] (targets' device pointers as in qfs_instantiate).
  *   gates_out: host array [P] of device pointers [L_p][4][4] (NULL entries skipped).
  *   res: host [P].
@@ -272,15 +273,18 @@ int qfs_predict_m(const qfs_template *tmpl, const qfs_params *params, int32_t *m
 int qfs_predict_batch(int32_t P, const qfs_template *tmpl, const qfs_params *params,
                       int32_t *m0, int32_t *starts);
 
-/* qfs_instantiate with M starting at max(m_init, predicted M) and the predicted number
- * of starts; when that run does not succeed, the plain qfs_instantiate (from m_init,
- * every start) runs after it and its result is returned with fallback = 1. Counters in
- * res (start_sweeps, m_total, seconds) cover both runs. */
+/* qfs_instantiate with M starting at max(m_init, predicted M) (doubling on the
+ * validation cost as usual, Sec. 3) and the predicted number of leading starts. When
+ * that run does not succeed and starts were pruned, the pruned starts run after it
+ * with the plain method (M from m_init, their own initial gates), fallback = 1, and the
+ * better of the two runs is returned (success first, then lower c_train). Counters in
+ * res (start_sweeps, m_total, sweep_seconds, seconds) cover both runs. */
 int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target,
                             const qfs_params *params, qfs_c128 *gates_out, qfs_result *res);
 
 /* The same for qfs_instantiate_batch: one batched learned run, then one batched plain
- * run of the problems that did not succeed (each with its original seed). */
+ * run of the pruned starts of the problems that did not succeed (each problem with its
+ * original seed, so every start keeps its own initial gates). */
 int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl,
                                   const qfs_target *targets, const qfs_params *params,
                                   qfs_c128 *const *gates_out, qfs_result *res);

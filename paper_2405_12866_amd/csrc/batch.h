@@ -73,7 +73,8 @@ struct BatchArgs {
 // Per-problem options of the batched engine (all nullable / zero = the plain method).
 struct BatchOpts {
   const int32_t *m_init = nullptr;  // [P] initial sample count per problem
-  const int32_t *starts = nullptr;  // [P] number of leading starts to run per problem
+  const int32_t *starts = nullptr;  // [P] problem p runs starts [start_lo[p], starts[p])
+  const int32_t *start_lo = nullptr;  // [P] first start to run (default 0)
   const uint64_t *seeds = nullptr;  // [P] per-problem seeds (default params->seed + p)
   int independent = 0;              // starts do not stop at another start's success
   int32_t *successes = nullptr;     // [P] out: number of starts that succeeded

@@ -148,8 +148,10 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       return set_error_detail("batch: unknown target kind"), QFS_EINVAL;
     }
     const int m_init = opts.m_init ? opts.m_init[i] : p.m_init;
-    if (m_init < 1 || (opts.starts && (opts.starts[i] < 1 || opts.starts[i] > S))) {
-      set_error_detail("batch: problem " + std::to_string(i) + ": m_init and starts must be >= 1");
+    const int s_lo = opts.start_lo ? opts.start_lo[i] : 0;
+    const int s_hi = opts.starts ? opts.starts[i] : S;
+    if (m_init < 1 || s_lo < 0 || s_hi > S || s_lo >= s_hi) {
+      set_error_detail("batch: problem " + std::to_string(i) + ": need m_init >= 1 and 0 <= first start < starts <= multistarts");
       return QFS_EINVAL;
     }
     d.M = std::max(1, std::min(m_init, mcap));
@@ -220,7 +222,8 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       std::memset(&j, 0, sizeof(j));
       j.prob = i;
       j.start = s;
-      j.status = (opts.starts && s >= opts.starts[i]) ? BJ_SKIP : BJ_RUN;
+      const bool run = (!opts.starts || s < opts.starts[i]) && (!opts.start_lo || s >= opts.start_lo[i]);
+      j.status = run ? BJ_RUN : BJ_SKIP;
       j.c_train = j.c_val = HUGE_VAL;
       j.need_c0 = 1;
       j.fp64 = p.precision == QFS_PREC_FP64 ? 1 : 0;
@@ -483,7 +486,9 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
   const double secs = bnow() - t0;
   for (int i = 0; i < P; ++i) {
     const BJob *js = jobs.data() + (size_t)i * S;
-    int w = winner[i] >= 0 ? winner[i] : 0;
+    int w = winner[i];
+    for (int s = 0; w < 0 && s < S; ++s)
+      if (js[s].status != BJ_SKIP) w = s;
     qfs_result &r = res[i];
     std::memset(&r, 0, sizeof(r));
     r.reason = to_reason(js[w].status);

@@ -5,9 +5,11 @@
 //   y0 = log2 of the smallest power-of-two M at which a start succeeds and generalises,
 //   y1 = logit of the probability that one random start succeeds at that M,
 // and the instantiation runs with M0 = 2^round(y0) and just enough starts that at least
-// one succeeds with probability 0.95 under the predicted rate. The fallback is the plain
-// method: when the learned run does not succeed (the held-out validation distance still
-// doubles M inside it, Sec. 3), the problem is rerun from M = m_init with every start.
+// one succeeds with probability 0.95 under the predicted rate. A predicted M0 that is too
+// small is corrected by the method's own doubling on the held-out validation cost
+// (Sec. 3); a start count that was too small is corrected by the fallback: when the
+// learned run does not succeed, the pruned starts run with the plain method (M from
+// m_init, doubling), so no start of the plain method is lost.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -174,30 +176,47 @@ int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target, 
                             qfs_c128 *gates_out, qfs_result *res) {
   if (!tmpl || !target || !params || !res) return QFS_EINVAL;
   const double t0 = lnow();
+  hipStream_t st = static_cast<hipStream_t>(params->hip_stream);
   int32_t m0 = 0, k = 0;
-  QFS_TRY(predict_many(1, tmpl, *params, &m0, &k, static_cast<hipStream_t>(params->hip_stream)));
+  QFS_TRY(predict_many(1, tmpl, *params, &m0, &k, st));
+  const int S = params->multistarts;
   qfs_params q = *params;
   q.m_init = std::max(params->m_init, m0);
   q.multistarts = k;
   qfs_result r1;
   QFS_TRY(qfs_instantiate(tmpl, target, &q, nullptr, gates_out, &r1));
-  if (r1.reason == QFS_SUCCESS) {
+  r1.m_predicted = m0;
+  r1.starts_run = k;
+  r1.fallback = 0;
+  if (r1.reason == QFS_SUCCESS || k >= S) {
     *res = r1;
-    res->m_predicted = m0;
-    res->starts_run = k;
-    res->fallback = 0;
     res->seconds = lnow() - t0;
     return QFS_OK;
   }
+  // fallback: the pruned starts k..S-1 (their own initial gates), plain doubling from m_init
+  const int L = tmpl->n_gates;
+  DevBuf all, best;
+  QFS_TRY(all.alloc(sizeof(c128) * 16 * (size_t)S * L));
+  QFS_TRY(best.alloc(sizeof(c128) * 16 * (size_t)L));
+  QFS_TRY(qfs_haar_gates(params->seed, S, L, all.as<qfs_c128>(), st));
+  if (gates_out)
+    QFS_HIP(hipMemcpyAsync(best.ptr, gates_out, sizeof(c128) * 16 * L, hipMemcpyDeviceToDevice, st));
+  qfs_params q2 = *params;
+  q2.multistarts = S - k;
   qfs_result r2;
-  QFS_TRY(qfs_instantiate(tmpl, target, params, nullptr, gates_out, &r2));
-  *res = r2;
+  QFS_TRY(qfs_instantiate(tmpl, target, &q2, all.as<qfs_c128>() + (size_t)k * L * 16, gates_out, &r2));
+  const bool take2 = r2.reason == QFS_SUCCESS || r2.c_train < r1.c_train;
+  if (!take2 && gates_out)
+    QFS_HIP(hipMemcpyAsync(gates_out, best.ptr, sizeof(c128) * 16 * L, hipMemcpyDeviceToDevice, st));
+  QFS_HIP(hipStreamSynchronize(st));
+  *res = take2 ? r2 : r1;
+  if (take2) res->best_start += k;
   res->m_predicted = m0;
-  res->starts_run = k + params->multistarts;
+  res->starts_run = S;
   res->fallback = 1;
-  res->start_sweeps += r1.start_sweeps;
-  res->sweep_seconds += r1.sweep_seconds;
-  res->m_total += r1.m_total;
+  res->start_sweeps = r1.start_sweeps + r2.start_sweeps;
+  res->sweep_seconds = r1.sweep_seconds + r2.sweep_seconds;
+  res->m_total = r1.m_total + r2.m_total;
   res->seconds = lnow() - t0;
   return QFS_OK;
 }
@@ -206,11 +225,14 @@ int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl, const qfs
                                   const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res) {
   if (P < 1 || !tmpl || !targets || !params || !gates_out || !res) return QFS_EINVAL;
   const double t0 = lnow();
+  hipStream_t st = static_cast<hipStream_t>(params->hip_stream);
+  const int S = params->multistarts;
   std::vector<int32_t> m0(P), k(P);
-  QFS_TRY(predict_many(P, tmpl, *params, m0.data(), k.data(), static_cast<hipStream_t>(params->hip_stream)));
-  for (int i = 0; i < P; ++i) m0[i] = std::max(params->m_init, m0[i]);
+  QFS_TRY(predict_many(P, tmpl, *params, m0.data(), k.data(), st));
+  std::vector<int32_t> m_run(P);
+  for (int i = 0; i < P; ++i) m_run[i] = std::max(params->m_init, m0[i]);
   BatchOpts o;
-  o.m_init = m0.data();
+  o.m_init = m_run.data();
   o.starts = k.data();
   QFS_TRY(batch_instantiate(P, tmpl, targets, params, gates_out, res, o));
   std::vector<int> failed;
@@ -218,35 +240,51 @@ int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl, const qfs
     res[i].m_predicted = m0[i];
     res[i].starts_run = k[i];
     res[i].fallback = 0;
-    if (res[i].reason != QFS_SUCCESS) failed.push_back(i);
+    if (res[i].reason != QFS_SUCCESS && k[i] < S) failed.push_back(i);
   }
   if (!failed.empty()) {
+    // fallback: the pruned starts of the problems that did not succeed, plain doubling
+    // from m_init, each problem with its original seed
     const int F = (int)failed.size();
     std::vector<qfs_template> ft(F);
     std::vector<qfs_target> fg(F);
-    std::vector<qfs_c128 *> fo(F);
     std::vector<qfs_result> fr(F);
-    for (int f = 0; f < F; ++f) {
-      ft[f] = tmpl[failed[f]];
-      fg[f] = targets[failed[f]];
-      fo[f] = gates_out[failed[f]];
-    }
-    // the plain method on the failed problems; problem seeds follow their original index
     std::vector<uint64_t> seeds(F);
-    for (int f = 0; f < F; ++f) seeds[f] = params->seed + (uint64_t)failed[f];
+    std::vector<int32_t> lo(F);
+    std::vector<DevBuf> tmp(F);
+    std::vector<qfs_c128 *> fo(F);
+    for (int f = 0; f < F; ++f) {
+      const int i = failed[f];
+      ft[f] = tmpl[i];
+      fg[f] = targets[i];
+      seeds[f] = params->seed + (uint64_t)i;
+      lo[f] = k[i];
+      QFS_TRY(tmp[f].alloc(sizeof(c128) * 16 * (size_t)tmpl[i].n_gates));
+      fo[f] = tmp[f].as<qfs_c128>();
+    }
     BatchOpts plain;
     plain.seeds = seeds.data();
+    plain.start_lo = lo.data();
     QFS_TRY(batch_instantiate(F, ft.data(), fg.data(), params, fo.data(), fr.data(), plain));
     for (int f = 0; f < F; ++f) {
-      qfs_result &r = res[failed[f]];
+      const int i = failed[f];
+      qfs_result &r = res[i];
       const qfs_result first = r;
-      r = fr[f];
+      const bool take2 = fr[f].reason == QFS_SUCCESS || fr[f].c_train < first.c_train;
+      if (take2) {
+        r = fr[f];
+        if (gates_out[i])
+          QFS_HIP(hipMemcpyAsync(gates_out[i], fo[f], sizeof(c128) * 16 * tmpl[i].n_gates,
+                                 hipMemcpyDeviceToDevice, st));
+      }
       r.m_predicted = first.m_predicted;
-      r.starts_run = first.starts_run + params->multistarts;
+      r.starts_run = S;
       r.fallback = 1;
-      r.start_sweeps += first.start_sweeps;
-      r.m_total += first.m_total;
+      r.start_sweeps = first.start_sweeps + fr[f].start_sweeps;
+      r.m_total = first.m_total + fr[f].m_total;
+      r.sweep_seconds = first.sweep_seconds + fr[f].sweep_seconds;
     }
+    QFS_HIP(hipStreamSynchronize(st));
   }
   const double secs = lnow() - t0;
   for (int i = 0; i < P; ++i) res[i].seconds = secs;

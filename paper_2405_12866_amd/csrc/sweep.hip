@@ -15,6 +15,8 @@
 // wave (cross-lane shuffles) -> block (LDS, FP64 partial); a one-wave-per-start kernel
 // then sums the block partials in a fixed order and runs the FP64 polar update.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "qfs_internal.h"
 
@@ -91,7 +93,7 @@ __device__ __forceinline__ constexpr int env_index(int q, int sg) {
                     : (sg << 2) | ((q >> 1) << 1) | (q & 1);
 }
 template <int VAR>
-__device__ __forceinline__ constexpr int var_bits() {
+__host__ __device__ __forceinline__ constexpr int var_bits() {
   return VAR <= 1 ? 2 : (VAR <= 5 ? 3 : 4);
 }
 
@@ -576,6 +578,157 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   }
 }
 
+// LDS-staged variant of the backward step for steps whose gates act on the lowest
+// amplitude bits. There a thread's super-group members are rows 32 or 64 bytes apart,
+// so in k_bwd_step each load instruction of a wave touches four times as many cache
+// lines as it fills. Here a wave owns a "box": the rows spanned by the t gate bits and
+// the W lowest other bits (64 packets per gate-bit combination). It reads the box with
+// one fully contiguous 1 KB access per combination, stages it in its own LDS slice, and
+// each lane then takes its super group out of LDS; updated states leave the same way.
+// The arithmetic per super group is that of k_bwd_step.
+constexpr int kLdsBlock = 128;
+constexpr int kLdsWaves = kLdsBlock / 64;
+
+struct LdsGeom {
+  int32_t W;           // row bits inside a box besides the gate bits (6 - logJ)
+  int32_t logJ;        // log2 packets per row
+  int32_t nps;         // W + t
+  int32_t logWin;      // n - t - W: other row bits above the box
+  uint32_t witems;     // boxes per start: nch << logWin
+  int32_t ps[12];      // ascending row-bit positions spanned by a box
+  int32_t segoff[16];  // row offset of box segment l (box index l << W)
+  int32_t ngslot[8];   // box bit of the w-th lowest non-gate position
+  int32_t boxmem[16];  // box bits of super-group member l
+};
+
+__device__ __forceinline__ int lds_slot(uint32_t box, int jv, int logJ) {
+  const int pk = (int)(box << logJ) + jv;
+  return pk + ((pk >> 4) << 1);  // 32 bytes of padding per 256 bytes: fewer bank conflicts
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_put(float4 *lds, int slot, const Pk<R> &v) {
+  Pk<R> tmp = v;
+  lds[slot] = *reinterpret_cast<const float4 *>(&tmp);
+}
+template <typename R>
+__device__ __forceinline__ Pk<R> lds_get(const float4 *lds, int slot) {
+  const float4 x = lds[slot];
+  return *reinterpret_cast<const Pk<R> *>(&x);
+}
+
+template <typename R, int VAR, bool APPLY>
+__global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGeom Lg) {
+  constexpr int t = var_bits<VAR>();
+  constexpr int NL = 1 << t;
+  constexpr int NS = NL / 4;
+  constexpr int V = Pk<R>::V;
+  constexpr int kSlots = NL * 72;  // 64 packets per segment + padding
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ c128 red[kLdsWaves][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float4 *lds = reinterpret_cast<float4 *>(lds_raw) + wv * kSlots;
+
+  const int s = A.slot_to_start[blockIdx.y];
+  const int P = gridDim.x;
+  cx<R> ud[16];
+  if (APPLY) load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k_apply * 16, ud, true);
+  const cx<R> *a_in = A.a_in + A.a_in_stride * s;
+  cx<R> *a_out = A.a_out + A.a_out_stride * s;
+  const cx<R> *b = A.b + A.b_stride * s;
+  const int logC = A.geo.cg.logC, n = A.geo.cg.n;
+  const int jv = lane & ((1 << Lg.logJ) - 1), rlow = lane >> Lg.logJ;
+  uint32_t box_i = 0;
+  for (int w = 0; w < Lg.W; ++w) box_i |= (uint32_t)((rlow >> w) & 1) << Lg.ngslot[w];
+
+  cx<R> acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = cmake<R>(0, 0);
+
+  for (uint32_t wi = blockIdx.x * kLdsWaves + wv; wi < Lg.witems; wi += P * kLdsWaves) {
+    const uint32_t q = wi >> Lg.logWin, hi = wi & ((1u << Lg.logWin) - 1u);
+    const uint32_t base_row = deposit(hi, Lg.ps, Lg.nps);
+    const int64_t gbase = ((int64_t)q << (n + logC)) + ((int64_t)(base_row + rlow) << logC) + jv * V;
+    // the box of a: one contiguous 1 KB read per segment, into this wave's LDS slice
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      lds_put<R>(lds, lds_slot(((uint32_t)l << Lg.W) + rlow, jv, Lg.logJ),
+                 ld_pk(a_in + gbase + ((int64_t)Lg.segoff[l] << logC)));
+    wave_sync();
+    Pk<R> a[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) a[l] = lds_get<R>(lds, lds_slot(box_i + Lg.boxmem[l], jv, Lg.logJ));
+    if (APPLY) {
+#pragma unroll
+      for (int rho = 0; rho < NS; ++rho) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          cx<R> x[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) x[p] = a[p * NS + rho].v[e];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            cx<R> y = cmake<R>(0, 0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p) cfma(y, ud[qq * 4 + p], x[p]);
+            a[qq * NS + rho].v[e] = y;
+          }
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int l = 0; l < NL; ++l) lds_put<R>(lds, lds_slot(box_i + Lg.boxmem[l], jv, Lg.logJ), a[l]);
+      wave_sync();
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        st_pk(a_out + gbase + ((int64_t)Lg.segoff[l] << logC),
+              lds_get<R>(lds, lds_slot(((uint32_t)l << Lg.W) + rlow, jv, Lg.logJ)));
+    }
+    wave_sync();
+    // the box of B_k, same way
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      lds_put<R>(lds, lds_slot(((uint32_t)l << Lg.W) + rlow, jv, Lg.logJ),
+                 ld_pk(b + gbase + ((int64_t)Lg.segoff[l] << logC)));
+    wave_sync();
+#pragma unroll
+    for (int sg = 0; sg < NS; ++sg) {
+      Pk<R> bb[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        bb[p] = lds_get<R>(lds, lds_slot(box_i + Lg.boxmem[env_index<VAR>(p, sg)], jv, Lg.logJ));
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        const Pk<R> &aq = a[env_index<VAR>(qq, sg)];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int e = 0; e < V; ++e) cfma_conj(acc[qq * 4 + p], aq.v[e], bb[p].v[e]);
+      }
+    }
+    wave_sync();
+  }
+
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const R re = wave_sum<R>(acc[e].re);
+    const R im = wave_sum<R>(acc[e].im);
+    if (lane == 0) red[wv][e] = cmake<double>(re, im);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    c128 sum = red[0][threadIdx.x];
+    for (int w = 1; w < kLdsWaves; ++w) sum = sum + red[w][threadIdx.x];
+    A.partials[((int64_t)s * P + blockIdx.x) * 16 + threadIdx.x] = sum;
+  }
+}
+
 // Per start (one wave): fixed-order FP64 sum of the P block partials of the
 // environment, then the gate update u <- polar((1 - beta) Gamma + beta u).
 __global__ __launch_bounds__(64) void k_env_finalize(const c128 *partials, int P,
@@ -882,8 +1035,67 @@ static int classify_step(const int32_t *pairs, int k_apply, int k_env, int32_t t
 }
 
 template <typename R, int VAR, bool APPLY>
-static void launch_step_kernel(dim3 grid, const StepArgs<R> &a, hipStream_t s) {
-  hipLaunchKernelGGL((k_bwd_step<R, VAR, APPLY>), grid, dim3(kBlock), 0, s, a);
+static void launch_step_kernel(dim3 grid, const StepArgs<R> &a, const LdsGeom *lg, hipStream_t s) {
+  if (lg) {
+    const size_t lds = (size_t)kLdsWaves * (1 << var_bits<VAR>()) * 72 * 16;
+    hipLaunchKernelGGL((k_bwd_step_lds<R, VAR, APPLY>), grid, dim3(kLdsBlock), lds, s, a, *lg);
+  } else {
+    hipLaunchKernelGGL((k_bwd_step<R, VAR, APPLY>), grid, dim3(kBlock), 0, s, a);
+  }
+}
+
+// Box geometry of the LDS-staged step, or false when the plain step already reads whole
+// cache lines (lowest gate bit high enough) or the state is too small for a box.
+static bool lds_geometry(const Geometry &g, const StepGeom &G, const int32_t *pos, size_t rbytes,
+                         LdsGeom *L) {
+  static const int mode = [] {
+    const char *e = std::getenv("QFS_BWD_LDS");  // 0: never, 1: auto (default), 2: always
+    return e ? std::atoi(e) : 1;
+  }();
+  if (mode == 0) return false;
+  const int t = G.t;
+  const int logJ = G.cg.logJ;
+  const int W = 6 - logJ;
+  if (W < 1 || g.n - t < W) return false;
+  const size_t row_bytes = (size_t(1) << g.logC) * rbytes * 2;
+  if (mode == 1 && (row_bytes << G.sorted_pos[0]) >= 128) return false;
+  std::memset(L, 0, sizeof(*L));
+  L->W = W;
+  L->logJ = logJ;
+  L->nps = W + t;
+  L->logWin = g.n - t - W;
+  L->witems = (uint32_t)((uint64_t)g.nch << L->logWin);
+  // box positions: the gate bits and the W lowest other bits, ascending
+  int ng[32], nng = 0;
+  for (int p = 0; p < g.n && nng < W; ++p) {
+    bool gate = false;
+    for (int m = 0; m < t; ++m) gate |= G.sorted_pos[m] == p;
+    if (!gate) ng[nng++] = p;
+  }
+  int all[12], na = 0;
+  for (int m = 0; m < t; ++m) all[na++] = G.sorted_pos[m];
+  for (int w = 0; w < W; ++w) all[na++] = ng[w];
+  std::sort(all, all + na);
+  for (int i = 0; i < na; ++i) L->ps[i] = all[i];
+  auto slot_of = [&](int pos) {
+    for (int i = 0; i < na; ++i)
+      if (all[i] == pos) return i;
+    return -1;
+  };
+  for (int l = 0; l < (1 << t); ++l) {
+    int32_t off = 0;
+    for (int b = 0; b < t; ++b)
+      if ((l >> b) & 1) off += 1 << all[W + b];
+    L->segoff[l] = off;
+  }
+  for (int w = 0; w < W; ++w) L->ngslot[w] = slot_of(ng[w]);
+  for (int l = 0; l < (1 << t); ++l) {
+    int32_t bx = 0;
+    for (int m = 0; m < t; ++m)
+      if ((l >> (t - 1 - m)) & 1) bx |= 1 << slot_of(pos[m]);
+    L->boxmem[l] = bx;
+  }
+  return true;
 }
 
 template <typename R>
@@ -922,20 +1134,29 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
         if ((l >> (t - 1 - m)) & 1) o += 1 << pos[m];
     G.off[l] = o;
   }
-  const int P = blocks_for(G.cg.items, nslots);
+  LdsGeom lg;
+  const bool use_lds = lds_geometry(g, G, pos, sizeof(R), &lg);
+  const LdsGeom *lgp = use_lds ? &lg : nullptr;
+  int P;
+  if (use_lds) {
+    const int64_t pmax = std::max<int64_t>(1, ((int64_t)lg.witems + kLdsWaves - 1) / kLdsWaves);
+    P = (int)std::min<int64_t>(pmax, std::max(1, 4096 / std::max(1, nslots)));
+  } else {
+    P = blocks_for(G.cg.items, nslots);
+  }
   *P_out = P;
   dim3 grid(P, nslots);
   if (k_apply < 0) {
-    launch_step_kernel<R, 0, false>(grid, a, s);
+    launch_step_kernel<R, 0, false>(grid, a, lgp, s);
   } else {
     switch (var) {
-      case 0: launch_step_kernel<R, 0, true>(grid, a, s); break;
-      case 1: launch_step_kernel<R, 1, true>(grid, a, s); break;
-      case 2: launch_step_kernel<R, 2, true>(grid, a, s); break;
-      case 3: launch_step_kernel<R, 3, true>(grid, a, s); break;
-      case 4: launch_step_kernel<R, 4, true>(grid, a, s); break;
-      case 5: launch_step_kernel<R, 5, true>(grid, a, s); break;
-      default: launch_step_kernel<R, 6, true>(grid, a, s); break;
+      case 0: launch_step_kernel<R, 0, true>(grid, a, lgp, s); break;
+      case 1: launch_step_kernel<R, 1, true>(grid, a, lgp, s); break;
+      case 2: launch_step_kernel<R, 2, true>(grid, a, lgp, s); break;
+      case 3: launch_step_kernel<R, 3, true>(grid, a, lgp, s); break;
+      case 4: launch_step_kernel<R, 4, true>(grid, a, lgp, s); break;
+      case 5: launch_step_kernel<R, 5, true>(grid, a, lgp, s); break;
+      default: launch_step_kernel<R, 6, true>(grid, a, lgp, s); break;
     }
   }
   QFS_HIP(hipGetLastError());

@@ -6,11 +6,11 @@ Sec. 5) and relates the number needed to the parameter count per amplitude (Sec.
 Labels come from the method itself: for each problem, every start is run to its own
 stop at fixed M = 2, 4, ..., 2^n (qfs_label_batch) until at least one start succeeds
 and generalises (the Sec. 3 success relation). The label is (log2 of that M, the
-fraction of starts that succeeded there); a problem with no success up to 2^n is
-labelled (NaN, 0). Features are the library's 64 template features.
+fraction of starts that succeeded there); a problem with no success up to
+min(2^n, 64) is labelled (NaN, 0). Features are the library's 64 template features.
 
 Command line (runs on the GPU; writes the weight file loaded by qfs_mlp_load):
-    python -m paper_2405_12866_amd.predictor --problems 8192 --out predictor.bin
+    python -m paper_2405_12866_amd.predictor --problems 6144 --out predictor.bin
 """
 from __future__ import annotations
 
@@ -46,8 +46,18 @@ def device_problems(problems, device="cuda"):
     return out
 
 
-def label(problems, params=None, seed=0x1AB, log=None):
-    """Labels [P][2] by the M ladder. ``problems`` hold device target gates."""
+def training_problems(count, seed_base=0x5A17 + 5):
+    """Three quarters drawn like the batched workload (n in 3..7, L in 2..20), one quarter
+    larger (n in 8..10, L in 8..40); random distinct pairs, Haar target from the
+    template."""
+    small = I.batched_problems(count - count // 4, seed_base=seed_base)
+    large = I.batched_problems(count // 4, seed_base=seed_base + 1, n_range=(8, 10), L_range=(8, 40))
+    return small + large
+
+
+def label(problems, params=None, seed=0x1AB, log=None, m_cap=64):
+    """Labels [P][2] by the M ladder (M = 2, 4, ... up to min(2^n, m_cap)). ``problems``
+    hold device target gates."""
     params = dict(params or label_params())
     S = params["multistarts"]
     P = len(problems)
@@ -57,7 +67,7 @@ def label(problems, params=None, seed=0x1AB, log=None):
     m = 2
     work = 0
     while todo:
-        active = [i for i in todo if m <= (1 << problems[i]["n"])]
+        active = [i for i in todo if m <= min(1 << problems[i]["n"], m_cap)]
         if not active:
             break
         succ, infos = Q.qfs_label_batch([problems[i] for i in active],
@@ -71,7 +81,7 @@ def label(problems, params=None, seed=0x1AB, log=None):
                 done.add(i)
         if log:
             log(f"label M={m}: {len(active)} problems, {len(done)} labelled")
-        todo = [i for i in todo if i not in done and m < (1 << problems[i]["n"])]
+        todo = [i for i in todo if i not in done and m < min(1 << problems[i]["n"], m_cap)]
         m *= 2
     return T, work
 
@@ -91,7 +101,7 @@ def train(X, T, epochs=300, batch=256, lr=2e-3, seed=7, init_seed=11):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--problems", type=int, default=8192)
+    ap.add_argument("--problems", type=int, default=6144)
     ap.add_argument("--seed-base", type=int, default=0x5A17 + 5)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
@@ -102,7 +112,7 @@ def main(argv=None):
         print(msg, file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    probs = I.batched_problems(a.problems, seed_base=a.seed_base)
+    probs = training_problems(a.problems, seed_base=a.seed_base)
     dprobs = device_problems(probs)
     T, work = label(dprobs, log=log)
     X = features(probs)

@@ -132,9 +132,25 @@ def test_state_distance_matches_oracle():
 
 
 # ------------------------------------------------------------------ sweeps
-def _sweep_problem(n, L, M, starts, seed, brick=False):
+def _lowbit_template(n, L, g):
+    """Random pairs, two thirds of them inside the last three qubits (the lowest
+    amplitude bits), so consecutive backward steps mix low and high bit positions."""
+    pairs = []
+    for k in range(L):
+        if k % 3 != 2:
+            a, b = g.choice(np.arange(n - 3, n), 2, replace=False)
+        else:
+            a, b = g.choice(n, 2, replace=False)
+        pairs.append((int(a), int(b)))
+    return np.asarray(pairs, dtype=np.int32)
+
+
+def _sweep_problem(n, L, M, starts, seed, brick=False, lowbit=False):
     g = np.random.default_rng(seed)
-    pairs = I.brickwork_template(n, L) if brick else I.random_pair_template(n, L, g)
+    if lowbit:
+        pairs = _lowbit_template(n, L, g)
+    else:
+        pairs = I.brickwork_template(n, L) if brick else I.random_pair_template(n, L, g)
     tg = I.haar_gates(len(pairs), g)
     psi = I.orthonormal_samples(n, M, g)
     phi = O.apply_circuit(n, psi, pairs, tg)
@@ -142,11 +158,15 @@ def _sweep_problem(n, L, M, starts, seed, brick=False):
     return pairs, psi, phi, gates
 
 
-@pytest.mark.parametrize("n,L,M,starts", [(2, 1, 4, 1), (3, 6, 3, 2), (5, 9, 5, 3), (8, 12, 16, 2)])
-def test_fp64_sweeps_lock_step(n, L, M, starts):
-    """20 sweeps in lock step: per-sweep costs within 1e-10 relative, gates 1e-10."""
-    say(f"fp64 lock-step n={n} L={L} M={M} starts={starts}")
-    pairs, psi, phi, gates = _sweep_problem(n, L, M, starts, seed=n + L)
+@pytest.mark.parametrize("n,L,M,starts,lowbit", [(2, 1, 4, 1, False), (3, 6, 3, 2, False),
+                                                 (5, 9, 5, 3, False), (8, 12, 16, 2, False),
+                                                 (10, 15, 6, 2, True), (9, 12, 3, 3, True)])
+def test_fp64_sweeps_lock_step(n, L, M, starts, lowbit):
+    """20 sweeps in lock step: per-sweep costs within 1e-10 relative, gates 1e-10. The
+    low-bit templates drive the LDS-staged backward step (gates on the lowest amplitude
+    bits) interleaved with the plain one, and ragged sample chunks."""
+    say(f"fp64 lock-step n={n} L={L} M={M} starts={starts} lowbit={lowbit}")
+    pairs, psi, phi, gates = _sweep_problem(n, L, M, starts, seed=n + L, lowbit=lowbit)
     dg = dev(gates)
     dpsi, dphi = dev(psi), dev(phi)
     ref = gates.copy()
@@ -158,13 +178,14 @@ def test_fp64_sweeps_lock_step(n, L, M, starts):
         assert np.max(np.abs(host(dg) - ref)) < 1e-10
 
 
-@pytest.mark.parametrize("n,L,M", [(6, 10, 8), (8, 21, 32)])
+@pytest.mark.parametrize("n,L,M", [(6, 10, 8), (8, 21, 32), (11, 12, 24)])
 def test_mixed_sweep_teacher_forced(n, L, M):
     """complex64 states, FP64 update/cost: each sweep starts from the GPU's own FP64
-    gates on both sides; |c_gpu - c_oracle| <= 1e-6 * max(c, c_initial)."""
+    gates on both sides; |c_gpu - c_oracle| <= 1e-6 * max(c, c_initial). The 11-qubit
+    case uses a low-bit template (LDS-staged backward steps)."""
     say(f"mixed teacher-forced n={n} L={L} M={M}")
     pairs, psi, phi, gates = _sweep_problem(n, L // 2 * 2 if n == 8 else L, M, 2, seed=77,
-                                            brick=(n == 8))
+                                            brick=(n == 8), lowbit=(n == 11))
     if n == 8:
         pairs = I.brickwork_template(8, 6)
         g = np.random.default_rng(78)
