@@ -28,6 +28,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "instantiation sweeps/s + time-to-dist 1e-8 (12q, HBM GB/s); batched vs plain"
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_bwd_step_12q_M256_S16_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_12866_amd", "csrc", "sweep.hip")
+
+
+def measured_traffic():
+    """HBM bytes per k_bwd_step launch from the committed PMC summary, when it was taken
+    on the current kernel source (sha256 of sweep.hip recorded there); else None."""
+    import hashlib
+    try:
+        with open(PMC_SUMMARY) as f:
+            text = f.read()
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -45,6 +71,11 @@ def parse():
                     help="problems in the batched workload (0 skips it)")
     ap.add_argument("--plain-sample", type=int, default=48,
                     help="problems of the batched workload also run one by one")
+    ap.add_argument("--learned", type=int, default=1024,
+                    help="held-out problems for the learned-M comparison (0 skips it)")
+    ap.add_argument("--learned-large", type=int, default=0,
+                    help="10-14 qubit random-pair problems (30-120 gates) for the learned-M "
+                         "comparison through qfs_instantiate (0 skips it)")
     return ap.parse_args()
 
 
@@ -110,7 +141,7 @@ def time_to_distance(dev):
 def batched(dev, count, plain_sample):
     """Batched workload: `count` problems (n ~ U{3..7}, L ~ U{2..20} random pairs, Haar
     target from the template), 16 starts each, M0 = 2^(n-1) with doubling to 2^n,
-    App. A stopping rules, MIXED precision, 8 sweeps per persistent launch. Compared
+    App. A stopping rules, MIXED precision, automatic sweeps per launch (8, raised as jobs finish). Compared
     with plain qfs_instantiate calls, one problem at a time, on the first
     `plain_sample` problems (same seeds, same success criterion), extrapolated."""
     import numpy as np
@@ -123,7 +154,7 @@ def batched(dev, count, plain_sample):
     dprobs = [dict(n=p["n"], pairs=p["pairs"], target_pairs=p["target_pairs"],
                    target_gates=torch.as_tensor(p["target_gates"]).to(dev)) for p in probs]
     m0 = np.array([1 << (p["n"] - 1) for p in probs], dtype=np.int32)
-    params = Q.qfs_default_params(multistarts=16, seed=0x5A17 + 4, batch_sweeps=8,
+    params = Q.qfs_default_params(multistarts=16, seed=0x5A17 + 4, batch_sweeps=0,
                                   precision=Q.QFS_PREC_MIXED)
     warm = min(256, count)  # code objects + work-group-size autotuner
     Q.qfs_instantiate_batch_ex(dprobs[:warm], params, m_init=m0[:warm])
@@ -156,6 +187,65 @@ def batched(dev, count, plain_sample):
         out["plain_loop"] = {"sample": k, "sample_s": round(t_plain, 3),
                              "sample_successes": ok_plain, "batched_successes_on_sample": ok_batch,
                              "extrapolated_s": round(est, 2), "batched_speedup": round(est / dt, 1)}
+    return out
+
+
+def learned(dev, count, large):
+    """Learned initial M and start pruning against the plain method (M from 2, doubling,
+    16 starts, App. A rules, MIXED), both batched, on `count` held-out problems drawn like
+    the predictor's training set (new seeds); optionally `large` 10-14 qubit random-pair
+    problems through the single-problem entry points. Needs the trained weight file."""
+    import torch
+
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import predictor as PR
+    from paper_2405_12866_amd import qfs as Q
+
+    if not os.path.exists(PR.DEFAULT_WEIGHTS):
+        return {"skipped": f"no weight file {os.path.basename(PR.DEFAULT_WEIGHTS)}"}
+    Q.qfs_mlp_load(PR.DEFAULT_WEIGHTS)
+    out = {}
+    if count > 0:
+        probs = PR.training_problems(count, seed_base=0x5A17 + 6)
+        dprobs = PR.device_problems(probs, dev)
+        params = Q.qfs_default_params(multistarts=16, seed=0x5A17 + 6, batch_sweeps=0,
+                                      precision=Q.QFS_PREC_MIXED)
+        Q.qfs_instantiate_batch(dprobs[:128], params)  # code objects and autotuner
+        rows = {}
+        for name, fn in (("plain", Q.qfs_instantiate_batch), ("learned", Q.qfs_instantiate_batch_learned)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos = fn(dprobs, params)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows[name] = {"wall_s": round(dt, 3), "successes": sum(r["reason_name"] == "SUCCESS" for r in infos),
+                          "start_sweeps": sum(r["start_sweeps"] for r in infos),
+                          "doublings": sum(r["restarts"] for r in infos)}
+            if name == "learned":
+                rows[name]["fallbacks"] = sum(r["fallback"] for r in infos)
+                rows[name]["mean_starts_run"] = round(sum(r["starts_run"] for r in infos) / count, 2)
+                rows[name]["mean_m_predicted"] = round(sum(r["m_predicted"] for r in infos) / count, 2)
+        rows["problems"] = count
+        rows["time_to_solution_speedup"] = round(rows["plain"]["wall_s"] / rows["learned"]["wall_s"], 2)
+        out["held_out"] = rows
+    if large > 0:
+        g = I.rng(I.derive_seed(0x5A17 + 7))
+        res = {"plain": [], "learned": []}
+        for i in range(large):
+            n = int(g.integers(10, 15))
+            L = int(g.integers(30, 121))
+            pairs = I.random_pair_template(n, L, g)
+            tg = torch.as_tensor(I.haar_gates(L, g)).to(dev)
+            p = Q.qfs_default_params(multistarts=16, seed=100 + i, max_iter=2000, time_budget_s=20.0)
+            for name, fn in (("plain", Q.qfs_instantiate), ("learned", Q.qfs_instantiate_learned)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, r = fn(n, pairs, target_pairs=pairs, target_gates=tg, params=p)
+                torch.cuda.synchronize()
+                res[name].append({"n": n, "L": L, "s": round(time.perf_counter() - t0, 2),
+                                  "reason": r["reason_name"], "c_train": r["c_train"],
+                                  "m_final": r["m_final"]})
+        out["large"] = res
     return out
 
 
@@ -203,7 +293,8 @@ def main():
         if kl[0] > 0:
             achieved = kb[0] / ks[0] / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": measured_traffic(),
                     "kernel": "k_bwd_step (apply u^dag + environment partial sums)",
                     "avg_launch_us": round(1e6 * ks[0] / kl[0], 2),
                     "bytes_per_launch": kb[0] / kl[0]}
@@ -221,6 +312,8 @@ def main():
     }
     if args.batched > 0:
         extra["batched"] = batched(dev, args.batched, args.plain_sample)
+    if args.learned > 0 or args.learned_large > 0:
+        extra["learned"] = learned(dev, args.learned, args.learned_large)
     if not args.no_ttd:
         extra["time_to_distance"] = time_to_distance(dev)
         extra["time_to_distance"]["12q_note"] = (

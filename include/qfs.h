@@ -114,8 +114,10 @@ typedef struct {
   int32_t timing;            /* 1: time every sweep kernel with hipEvents on
                                 hip_stream and report it in qfs_result             */
   int32_t batch_sweeps;      /* qfs_instantiate_batch: sweeps per persistent launch
-                                (0 = 8; 1 keeps every start of a problem in lock
-                                step, as qfs_instantiate does)                      */
+                                (0 = automatic: 8, doubled up to 256 while fewer
+                                than 1/4, 1/8, ... of the jobs still run; 1 keeps
+                                every start of a problem in lock step, as
+                                qfs_instantiate does)                               */
   int32_t batch_threads;     /* qfs_instantiate_batch: work-group size 64, 128 or 256
                                 (0 = chosen by the built-in autotuner, cached per
                                 precision and state-size class for the process)     */

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -52,6 +54,15 @@ size_t pow2_at_least(size_t x, size_t lo) {
 }
 
 constexpr size_t kLdsLimit = 128 * 1024;
+
+// QFS_BATCH_TRACE=1 prints one line per persistent launch to stderr (tuning aid).
+bool batch_trace() {
+  static const bool on = [] {
+    const char *e = std::getenv("QFS_BATCH_TRACE");
+    return e && std::atoi(e) != 0;
+  }();
+  return on;
+}
 constexpr int kCUs = 256;
 
 int default_threads(size_t bucket, int fp64) {
@@ -94,7 +105,10 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     set_error_detail("batch: independent starts need fixed_m");
     return QFS_EINVAL;
   }
-  const int K = p.batch_sweeps > 0 ? p.batch_sweeps : 8;
+  // sweeps per launch: fixed when given; otherwise 8, raised as the set of running jobs
+  // thins out (a long tail of slowly converging problems then costs few round trips)
+  const bool adaptive_k = p.batch_sweeps == 0;
+  const int K0 = p.batch_sweeps > 0 ? p.batch_sweeps : 8;
   hipStream_t st = static_cast<hipStream_t>(p.hip_stream);
 
   // ---------------------------------------------------------------- validation + sizes
@@ -292,6 +306,12 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       classes[ClassKey{J.fp64, pow2_at_least(bytes, 4096)}].push_back((int32_t)j);
     }
     if (classes.empty()) break;
+    int K = K0;
+    if (adaptive_k) {
+      size_t runnable = 0;
+      for (auto &kv : classes) runnable += kv.second.size();
+      while (K < 256 && runnable * (size_t)(K / K0) * 4 <= njobs_all) K *= 2;
+    }
     for (auto &kv : classes) {
       std::vector<int32_t> &ids = kv.second;
       std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
@@ -350,6 +370,9 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         float ms = 0.f;
         QFS_HIP(hipEventElapsedTime(&ms, e0, e1));
         kernel_seconds += 1e-3 * ms;
+        if (batch_trace())
+          std::fprintf(stderr, "qfs batch: fp64=%d state_bytes<=%zu threads=%d jobs=%d grid=%d lds=%zu %.3f ms\n",
+                       key.fp64, key.bucket, threads, nj, grid, lds, ms);
         if (!cands.empty()) {
           double work = 0.0;
           for (size_t q = lo; q < hi; ++q) {

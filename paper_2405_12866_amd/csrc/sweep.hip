@@ -395,11 +395,15 @@ struct FwdSeg {
   int32_t kstore;       // outputs stored for gates 0 .. kstore-1
 };
 
+// A gate on the lowest amplitude bits makes a thread's four outputs rows 32 or 64 bytes
+// apart; for such gates (when coalesce_b is set) B_k leaves LDS in a second, contiguous
+// pass instead of straight from registers.
 template <typename R>
 __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int n,
                                                              int logC, const int32_t *pairs,
                                                              const cx<R> *gates, int32_t gstride,
-                                                             const int32_t *slot_to_start) {
+                                                             const int32_t *slot_to_start,
+                                                             int coalesce_b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
   __shared__ double red[kFwdBlock / 64];
@@ -423,6 +427,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, Fwd
     load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, false);
     const bool store = k < sg.kstore;
     cx<R> *dst = store ? sg.blist + sg.bstride * s + sg.sN * k + cbase : nullptr;
+    const bool late = store && coalesce_b && ((sizeof(cx<R>) << (logC + min(pa, pb))) < 128);
     for (uint32_t g = threadIdx.x; g < groups; g += kFwdBlock) {
       const uint32_t jv = g & ((1u << logJ) - 1u);
       const uint32_t i0 = deposit(g >> logJ, sorted, 2);
@@ -445,10 +450,14 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, Fwd
           y.v[e] = acc;
         }
         st_pk(lds + o[qq], y);
-        if (store) st_pk(dst + o[qq], y);
+        if (store && !late) st_pk(dst + o[qq], y);
       }
     }
     __syncthreads();
+    if (late) {
+      for (uint32_t e = threadIdx.x * V; e < chunk; e += kFwdBlock * V) st_pk(dst + e, ld_pk(lds + e));
+      __syncthreads();
+    }
   }
   if (sg.ref) {
     const cx<R> *ref = sg.ref + cbase;
@@ -987,9 +996,13 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_bytes = lds;
   }
+  static const int coalesce_b = [] {
+    const char *e = std::getenv("QFS_FWD_COALESCE");  // 0: always store from registers
+    return e ? std::atoi(e) : 1;
+  }();
   hipLaunchKernelGGL(k_forward_fused<R>, dim3(gx, nslots, nz), dim3(kFwdBlock), lds, s, a, b, g.n,
                      g.logC, pairs_dev, static_cast<const cx<R> *>(gates.gR), gates.gstride,
-                     slot_to_start);
+                     slot_to_start, coalesce_b);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }

@@ -30,7 +30,7 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "pred
 
 def label_params(**over):
     """Run settings of the labelling ladder (App. A defaults otherwise)."""
-    d = dict(multistarts=16, dist_tol=1e-8, max_iter=400, batch_sweeps=8,
+    d = dict(multistarts=16, dist_tol=1e-8, max_iter=400, batch_sweeps=0,
              precision=Q.QFS_PREC_MIXED)
     d.update(over)
     return d

@@ -284,3 +284,36 @@ def test_invalid_gates_in_rejected():
         Q.qfs_instantiate(2, pairs, U=dev(np.eye(4)), params=Q.qfs_default_params(multistarts=1),
                           gates_in=bad)
     assert e.value.code == Q.QFS_EINVAL
+
+
+# ------------------------------------------------------------------ full-size workload
+def test_full_size_sweep_sampled_starts():
+    """The 12-qubit workload at its full size and in the bench's configuration (44
+    brickwork gates, M = 256, 16 starts, complex64 states): one sweep of all starts on
+    the device; two sampled starts re-run by the oracle from the same gates (teacher
+    forced, |dc| <= 1e-6 max(c, c_init)); every updated gate unitary to 1e-12; and the
+    cost can only fall (block-coordinate ascent, Sec. 3) for every start."""
+    n, M, S = 12, 256, 16
+    w = I.workload_12q()
+    pairs = w["pairs"]
+    g = np.random.default_rng(1212)
+    say("full size: drawing 12q states")
+    psi = I.orthonormal_samples(n, M, g)
+    phi = O.apply_circuit(n, psi, pairs, w["target_gates"])
+    gates = np.stack([I.haar_gates(len(pairs), g) for _ in range(S)])
+    dpsi, dphi, dg = dev(psi), dev(phi), dev(gates)
+    say("full size: GPU sweep (16 starts, MIXED)")
+    c_gpu = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED)
+    new = host(dg)
+    for s in range(S):
+        for u in new[s]:
+            assert np.max(np.abs(u.conj().T @ u - np.eye(4))) < 1e-12
+    for s in (0, 11):
+        say(f"full size: oracle sweep of start {s}")
+        c0 = O.state_distance(n, O.apply_circuit(n, psi, pairs, gates[s]), phi)
+        _, c_ref = O.sweep(n, pairs, psi, phi, gates[s])
+        assert abs(c_gpu[s] - c_ref) <= 1e-6 * max(c_ref, c0), (s, c_gpu[s], c_ref)
+        assert c_gpu[s] <= c0 + 1e-6 * c0
+    say("full size: second sweep must not increase any start's cost")
+    c2 = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED)
+    assert np.all(c2 <= c_gpu + 1e-6 * np.maximum(c_gpu, 1e-3))
