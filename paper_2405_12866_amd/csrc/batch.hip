@@ -290,9 +290,13 @@ struct SweepShared {
   int flag;
 };
 
+// Jobs with at most kGatesInLds gates keep all their gates (state precision) in LDS for
+// the whole launch; longer templates stage one gate at a time from the FP64 masters.
+constexpr int kGatesInLds = 24;
+
 template <typename R, int NT>
 __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, SweepShared &sh,
-                        cx<R> *gl) {
+                        cx<R> *gl, cx<R> *gates_l) {
   BJob &J = A.jobs[jid];
   BProb &P = A.probs[J.prob];
   const int n = P.n, L = P.L, M = P.M, Mv = P.Mv;
@@ -301,23 +305,34 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, S
   c128 *vst = P.vst + (size_t)J.start * L * 16;
   const BParams &hp = A.hp;
 
-  // gate k of this job, in R precision, staged in LDS slot gl
-  auto stage_gate = [&](int k) {
+  // gate k of this job in R precision: resident in LDS (short templates), or staged
+  // from the FP64 master into the slot gl
+  const bool resident = L <= kGatesInLds;
+  if (resident) {
+    for (int e = threadIdx.x; e < L * 16; e += NT) {
+      const c128 u = g64[e];
+      gates_l[e] = cmake<R>((R)u.re, (R)u.im);
+    }
+    __syncthreads();
+  }
+  auto gate = [&](int k) -> const cx<R> * {
+    if (resident) return gates_l + k * 16;
     if (threadIdx.x < 16) {
       const c128 u = g64[k * 16 + threadIdx.x];
       gl[threadIdx.x] = cmake<R>((R)u.re, (R)u.im);
     }
     __syncthreads();
+    return gl;
   };
   // forward: bufB <- C Psi (training), bufA <- C Psi_val; returns c_val; c0 optional
   auto forward = [&](double *c0) {
     load_states<R, NT>(bufB, P.psi, M, n);
     if (Mv > 0) load_states<R, NT>(bufA, P.psiv, Mv, n);
     for (int k = 0; k < L; ++k) {
-      stage_gate(k);
+      const cx<R> *u = gate(k);
       const int pa = n - 1 - pairs[2 * k], pb = n - 1 - pairs[2 * k + 1];
-      apply_states<R, NT>(bufB, M, n, pa, pb, gl, false);
-      if (Mv > 0) apply_states<R, NT>(bufA, Mv, n, pa, pb, gl, false);
+      apply_states<R, NT>(bufB, M, n, pa, pb, u, false);
+      if (Mv > 0) apply_states<R, NT>(bufA, Mv, n, pa, pb, u, false);
       __syncthreads();
     }
     if (c0) *c0 = dist_states<R, NT>(bufB, P.phi, M, n, sh.red);
@@ -354,13 +369,13 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, S
     for (int k = L - 1; k >= 0; --k) {
       const int pa = n - 1 - pairs[2 * k], pb = n - 1 - pairs[2 * k + 1];
       if (k < L - 1) {
-        stage_gate(k + 1);  // already updated
+        const cx<R> *u1 = gate(k + 1);  // already updated
         const int qa = n - 1 - pairs[2 * (k + 1)], qb = n - 1 - pairs[2 * (k + 1) + 1];
-        apply_states<R, NT>(bufA, M, n, qa, qb, gl, true);
+        apply_states<R, NT>(bufA, M, n, qa, qb, u1, true);
         __syncthreads();
       }
-      stage_gate(k);  // not yet updated
-      apply_states<R, NT>(bufB, M, n, pa, pb, gl, true);  // B_k
+      const cx<R> *u0 = gate(k);  // not yet updated
+      apply_states<R, NT>(bufB, M, n, pa, pb, u0, true);  // B_k
       __syncthreads();
       // environment of gate k
       cx<R> acc[16];
@@ -398,13 +413,16 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, S
         sh.gam[threadIdx.x] = t;
       }
       __syncthreads();
-      if (threadIdx.x < 64) batch_polar<R>(sh.gam, hp.beta, g64 + k * 16, gl, vst + k * 16, sh.pg, sh.pv, sh.ps);
+      // the new gate k goes to the FP64 master and (state precision) to its LDS slot;
+      // the old one has served its last use (B_k above)
+      cx<R> *unew = resident ? gates_l + k * 16 : gl;
+      if (threadIdx.x < 64) batch_polar<R>(sh.gam, hp.beta, g64 + k * 16, unew, vst + k * 16, sh.pg, sh.pv, sh.ps);
       __syncthreads();
     }
     // cost of the updated gates: a_0 = u_0^dag a
     {
       const int pa = n - 1 - pairs[0], pb = n - 1 - pairs[1];
-      apply_states<R, NT>(bufA, M, n, pa, pb, gl, true);  // gl holds the new u_0
+      apply_states<R, NT>(bufA, M, n, pa, pb, resident ? gates_l : gl, true);  // the new u_0
       __syncthreads();
     }
     const double ct = dist_states<R, NT>(bufA, P.psi, M, n, sh.red);
@@ -451,6 +469,7 @@ __global__ __launch_bounds__(NT) void k_batch_sweep(BatchArgs A) {
   __shared__ SweepShared sh;
   __shared__ int qi_s;
   __shared__ __align__(16) cx<R> gl[16];
+  __shared__ __align__(16) cx<R> gates_l[kGatesInLds * 16];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
   for (;;) {
     if (threadIdx.x == 0) qi_s = atomicAdd(A.queue_head, 1);
@@ -471,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_batch_sweep(BatchArgs A) {
       bufB = lds + rowsA;
     }
     (void)rowsB;
-    run_job<R, NT>(A, jid, bufA, bufB, sh, gl);
+    run_job<R, NT>(A, jid, bufA, bufB, sh, gl, gates_l);
     __syncthreads();
   }
 }

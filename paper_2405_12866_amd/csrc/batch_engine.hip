@@ -74,7 +74,7 @@ int default_threads(size_t bucket, int fp64) {
 
 int grid_for(size_t lds, int threads, int njobs) {
   int wpc = 2048 / threads;
-  if (lds > 0) wpc = std::min<int>(wpc, (int)((160 * 1024) / (lds + 2048)));
+  if (lds > 0) wpc = std::min<int>(wpc, (int)((160 * 1024) / (lds + 8192)));  // + static LDS
   wpc = std::max(1, wpc);
   return std::max(1, std::min(njobs, kCUs * wpc));
 }
