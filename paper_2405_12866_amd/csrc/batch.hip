@@ -61,20 +61,36 @@ __device__ __forceinline__ void apply_states(cx<R> *st, int rows, int n, int pa,
   const uint32_t ma = 1u << pa, mb = 1u << pb;
   const uint32_t gper = 1u << (n - 2);
   const uint32_t total = gper * rows;
-  for (uint32_t g = threadIdx.x; g < total; g += NT) {
-    const uint32_t j = g >> (n - 2), r = g & (gper - 1u);
-    cx<R> *s = st + ((size_t)j << n);
-    const uint32_t i0 = deposit2(r, lo, hi);
-    const uint32_t o[4] = {i0, i0 + mb, i0 + ma, i0 + ma + mb};
-    cx<R> x[4];
+  // two groups per iteration: both groups' loads are issued before any store, which
+  // doubles the memory accesses in flight when the states live in global scratch
+  for (uint32_t g0 = threadIdx.x; g0 < total; g0 += 2 * NT) {
+    cx<R> x[2][4];
+    cx<R> *sp[2];
+    uint32_t o[2][4];
+    const bool two = g0 + NT < total;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) x[p] = s[o[p]];
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t g = h ? (two ? g0 + NT : g0) : g0;
+      const uint32_t j = g >> (n - 2), r = g & (gper - 1u);
+      sp[h] = st + ((size_t)j << n);
+      const uint32_t i0 = deposit2(r, lo, hi);
+      o[h][0] = i0;
+      o[h][1] = i0 + mb;
+      o[h][2] = i0 + ma;
+      o[h][3] = i0 + ma + mb;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cx<R> y = cmake<R>(0, 0);
+      for (int p = 0; p < 4; ++p) x[h][p] = sp[h][o[h][p]];
+    }
 #pragma unroll
-      for (int p = 0; p < 4; ++p) cfma(y, m[q * 4 + p], x[p]);
-      s[o[q]] = y;
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !two) break;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cx<R> y = cmake<R>(0, 0);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) cfma(y, m[q * 4 + p], x[h][p]);
+        sp[h][o[h][q]] = y;
+      }
     }
   }
 }
@@ -281,12 +297,13 @@ __device__ void batch_polar(const c128 *G, double beta, c128 *u64, cx<R> *u_r, c
 }
 
 // ------------------------------------------------------------------ job sweeps
+template <int NW>
 struct SweepShared {
-  c128 wred[4][16];
+  c128 wred[NW][16];
   c128 gam[16];
   c128 pg[16], pv[16];
   double ps[4];
-  double red[4];
+  double red[NW];
   int flag;
 };
 
@@ -295,8 +312,8 @@ struct SweepShared {
 constexpr int kGatesInLds = 24;
 
 template <typename R, int NT>
-__device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, SweepShared &sh,
-                        cx<R> *gl, cx<R> *gates_l) {
+__device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
+                        SweepShared<NT / 64> &sh, cx<R> *gl, cx<R> *gates_l) {
   BJob &J = A.jobs[jid];
   BProb &P = A.probs[J.prob];
   const int n = P.n, L = P.L, M = P.M, Mv = P.Mv;
@@ -466,7 +483,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB, S
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_batch_sweep(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ SweepShared sh;
+  __shared__ SweepShared<NT / 64> sh;
   __shared__ int qi_s;
   __shared__ __align__(16) cx<R> gl[16];
   __shared__ __align__(16) cx<R> gates_l[kGatesInLds * 16];
@@ -685,12 +702,14 @@ int launch_batch_sweep(const BatchArgs &a, bool fp64, int threads, int grid, siz
     switch (threads) {
       case 64: return launch_sweep_t<double, 64>(a, grid, lds, s);
       case 128: return launch_sweep_t<double, 128>(a, grid, lds, s);
+      case 1024: return launch_sweep_t<double, 1024>(a, grid, lds, s);
       default: return launch_sweep_t<double, 256>(a, grid, lds, s);
     }
   }
   switch (threads) {
     case 64: return launch_sweep_t<float, 64>(a, grid, lds, s);
     case 128: return launch_sweep_t<float, 128>(a, grid, lds, s);
+    case 1024: return launch_sweep_t<float, 1024>(a, grid, lds, s);
     default: return launch_sweep_t<float, 256>(a, grid, lds, s);
   }
 }

@@ -64,6 +64,26 @@ bool batch_trace() {
   return on;
 }
 constexpr int kCUs = 256;
+constexpr int kSideStreams = 8;
+
+// Streams and join events for concurrent launches, released on scope exit.
+struct StreamSet {
+  hipStream_t s[kSideStreams] = {};
+  hipEvent_t ev[kSideStreams] = {};
+  int create() {
+    for (int i = 0; i < kSideStreams; ++i) {
+      QFS_HIP(hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking));
+      QFS_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    }
+    return QFS_OK;
+  }
+  ~StreamSet() {
+    for (int i = 0; i < kSideStreams; ++i) {
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+      if (s[i]) (void)hipStreamDestroy(s[i]);
+    }
+  }
+};
 
 int default_threads(size_t bucket, int fp64) {
   const size_t amps = bucket / (fp64 ? 16 : 8) / 2;  // per state set
@@ -292,6 +312,11 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
   hipEvent_t e0, e1;
   QFS_HIP(hipEventCreate(&e0));
   QFS_HIP(hipEventCreate(&e1));
+  // side streams for concurrent class launches (default priority)
+  StreamSet streams;
+  QFS_TRY(streams.create());
+  hipStream_t *side = streams.s;
+  hipEvent_t *side_done = streams.ev;
   std::vector<int32_t> queue;
 
   while (remaining > 0) {
@@ -312,6 +337,19 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       for (auto &kv : classes) runnable += kv.second.size();
       while (K < 256 && runnable * (size_t)(K / K0) * 4 <= njobs_all) K *= 2;
     }
+    // Size classes are launched concurrently on side streams (each with its own queue
+    // segment, queue head and scratch region); a class whose work-group size is not
+    // known yet is first autotuned on the call's stream: its jobs are split in three
+    // parts run with 64, 128 and 256 threads, one after the other.
+    struct Launch {
+      ClassKey key;
+      int threads, grid, nj;
+      size_t qoff, soff;
+    };
+    std::vector<Launch> plan;
+    size_t qfill = 0, sfill = 0;
+    std::vector<int32_t> qhost;
+    qhost.reserve(njobs_all);
     for (auto &kv : classes) {
       std::vector<int32_t> &ids = kv.second;
       std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
@@ -323,57 +361,45 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       const ClassKey key = kv.first;
       const bool use_lds = key.bucket <= kLdsLimit;
       const size_t lds = use_lds ? key.bucket : 0;
-      // work-group size: explicit, cached, or autotuned on this launch
-      std::vector<int> cands;
       int chosen = p.batch_threads;
+      if (!chosen && !use_lds) chosen = 1024;  // global-scratch states: widest groups
       if (!chosen) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find({key.fp64, key.bucket});
         if (it != g_tune.end()) chosen = it->second;
       }
       if (!chosen && ids.size() >= 3 * 64) {
-        cands = {64, 128, 256};
-      } else if (!chosen) {
-        chosen = default_threads(key.bucket, key.fp64);
-      }
-      const int parts = cands.empty() ? 1 : (int)cands.size();
-      double best_rate = -1.0;
-      int best_threads = chosen;
-      for (int part = 0; part < parts; ++part) {
-        const size_t lo = ids.size() * part / parts, hi = ids.size() * (part + 1) / parts;
-        const int nj = (int)(hi - lo);
-        if (nj <= 0) continue;
-        const int threads = cands.empty() ? chosen : cands[part];
-        QFS_HIP(hipMemcpyAsync(dqueue.ptr, ids.data() + lo, sizeof(int32_t) * nj, hipMemcpyHostToDevice, st));
-        QFS_TRY(launch_zero(dhead.ptr, 16, st));
-        const int grid = grid_for(lds, threads, nj);
-        BatchArgs a;
-        a.jobs = djobs.as<BJob>();
-        a.probs = dprobs.as<BProb>();
-        a.queue = dqueue.as<int32_t>();
-        a.njobs = nj;
-        a.queue_head = dhead.as<int32_t>();
-        a.sweeps_per_launch = K;
-        a.hp = bp;
-        a.scratch = nullptr;
-        a.scratch_slot_bytes = 0;
-        if (!use_lds) {
-          const size_t need_s = (size_t)grid * key.bucket;
-          if (scratch.bytes < need_s) QFS_TRY(scratch.alloc(need_s));
-          a.scratch = scratch.as<char>();
-          a.scratch_slot_bytes = key.bucket;
-        }
-        QFS_HIP(hipEventRecord(e0, st));
-        QFS_TRY(launch_batch_sweep(a, key.fp64 != 0, threads, grid, lds, st));
-        QFS_HIP(hipEventRecord(e1, st));
-        QFS_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        QFS_HIP(hipEventElapsedTime(&ms, e0, e1));
-        kernel_seconds += 1e-3 * ms;
-        if (batch_trace())
-          std::fprintf(stderr, "qfs batch: fp64=%d state_bytes<=%zu threads=%d jobs=%d grid=%d lds=%zu %.3f ms\n",
-                       key.fp64, key.bucket, threads, nj, grid, lds, ms);
-        if (!cands.empty()) {
+        // autotune on the call's stream
+        const int cands[3] = {64, 128, 256};
+        double best_rate = -1.0;
+        int best_threads = 64;
+        for (int part = 0; part < 3; ++part) {
+          const size_t lo = ids.size() * part / 3, hi = ids.size() * (part + 1) / 3;
+          const int nj = (int)(hi - lo);
+          const int threads = cands[part];
+          QFS_HIP(hipMemcpyAsync(dqueue.ptr, ids.data() + lo, sizeof(int32_t) * nj, hipMemcpyHostToDevice, st));
+          QFS_TRY(launch_zero(dhead.ptr, 16, st));
+          const int grid = grid_for(lds, threads, nj);
+          BatchArgs a;
+          a.jobs = djobs.as<BJob>();
+          a.probs = dprobs.as<BProb>();
+          a.queue = dqueue.as<int32_t>();
+          a.njobs = nj;
+          a.queue_head = dhead.as<int32_t>();
+          a.sweeps_per_launch = K;
+          a.hp = bp;
+          a.scratch = nullptr;
+          a.scratch_slot_bytes = 0;
+          QFS_HIP(hipEventRecord(e0, st));
+          QFS_TRY(launch_batch_sweep(a, key.fp64 != 0, threads, grid, lds, st));
+          QFS_HIP(hipEventRecord(e1, st));
+          QFS_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          QFS_HIP(hipEventElapsedTime(&ms, e0, e1));
+          kernel_seconds += 1e-3 * ms;
+          if (batch_trace())
+            std::fprintf(stderr, "qfs batch: tune fp64=%d state_bytes<=%zu threads=%d jobs=%d grid=%d %.3f ms\n",
+                         key.fp64, key.bucket, threads, nj, grid, ms);
           double work = 0.0;
           for (size_t q = lo; q < hi; ++q) {
             const BProb &d = hp[jobs[ids[q]].prob];
@@ -385,11 +411,61 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
             best_threads = threads;
           }
         }
-      }
-      if (!cands.empty()) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[{key.fp64, key.bucket}] = best_threads;
+        continue;
       }
+      if (!chosen) chosen = default_threads(key.bucket, key.fp64);
+      Launch l;
+      l.key = key;
+      l.threads = chosen;
+      l.nj = (int)ids.size();
+      l.grid = grid_for(lds, chosen, l.nj);
+      l.qoff = qfill;
+      qhost.insert(qhost.end(), ids.begin(), ids.end());
+      qfill += ids.size();
+      l.soff = sfill;
+      if (!use_lds) sfill += (size_t)l.grid * key.bucket;
+      plan.push_back(l);
+    }
+    if (!plan.empty()) {
+      const int nl = (int)plan.size();
+      if ((size_t)nl * 16 * sizeof(int32_t) > dhead.bytes) QFS_TRY(dhead.alloc((size_t)nl * 16 * sizeof(int32_t)));
+      if (sfill > scratch.bytes) QFS_TRY(scratch.alloc(sfill));
+      QFS_HIP(hipMemcpyAsync(dqueue.ptr, qhost.data(), sizeof(int32_t) * qfill, hipMemcpyHostToDevice, st));
+      QFS_TRY(launch_zero(dhead.ptr, (size_t)nl * 16 * sizeof(int32_t), st));
+      QFS_HIP(hipEventRecord(e0, st));
+      const int ns = std::min(nl, kSideStreams);
+      for (int c = 0; c < ns; ++c) QFS_HIP(hipStreamWaitEvent(side[c], e0, 0));
+      for (int c = 0; c < nl; ++c) {
+        const Launch &l = plan[c];
+        BatchArgs a;
+        a.jobs = djobs.as<BJob>();
+        a.probs = dprobs.as<BProb>();
+        a.queue = dqueue.as<int32_t>() + l.qoff;
+        a.njobs = l.nj;
+        a.queue_head = dhead.as<int32_t>() + 16 * c;
+        a.sweeps_per_launch = K;
+        a.hp = bp;
+        const bool use_lds = l.key.bucket <= kLdsLimit;
+        a.scratch = use_lds ? nullptr : scratch.as<char>() + l.soff;
+        a.scratch_slot_bytes = use_lds ? 0 : l.key.bucket;
+        QFS_TRY(launch_batch_sweep(a, l.key.fp64 != 0, l.threads, l.grid, use_lds ? l.key.bucket : 0,
+                                   side[c % ns]));
+        if (batch_trace())
+          std::fprintf(stderr, "qfs batch: K=%d fp64=%d state_bytes<=%zu threads=%d jobs=%d grid=%d\n", K,
+                       l.key.fp64, l.key.bucket, l.threads, l.nj, l.grid);
+      }
+      for (int c = 0; c < ns; ++c) {
+        QFS_HIP(hipEventRecord(side_done[c], side[c]));
+        QFS_HIP(hipStreamWaitEvent(st, side_done[c], 0));
+      }
+      QFS_HIP(hipEventRecord(e1, st));
+      QFS_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QFS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      kernel_seconds += 1e-3 * ms;
+      if (batch_trace()) std::fprintf(stderr, "qfs batch: round of %d launches %.3f ms\n", nl, ms);
     }
     QFS_HIP(hipMemcpyAsync(jobs.data(), djobs.ptr, sizeof(BJob) * njobs_all, hipMemcpyDeviceToHost, st));
     QFS_HIP(hipMemcpyAsync(hp.data(), dprobs.ptr, sizeof(BProb) * P, hipMemcpyDeviceToHost, st));
