@@ -136,7 +136,7 @@ __device__ __forceinline__ c128 bquad_sum(c128 x) {
 // and u_r (R copy, LDS). Falls back to a serial completion on lane 0 when a singular
 // value vanishes. Called by the 64 lanes of one wave.
 template <typename R>
-__device__ void batch_polar(const c128 *G, double beta, c128 *u64, cx<R> *u_r, c128 *vst,
+__device__ __forceinline__ void batch_polar(const c128 *G, double beta, c128 *u64, cx<R> *u_r, c128 *vst,
                             c128 *lds_g, c128 *lds_v, double *lds_s) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, c = l >> 2, r = l & 3, base = lane & ~15;
@@ -702,14 +702,14 @@ int launch_batch_sweep(const BatchArgs &a, bool fp64, int threads, int grid, siz
     switch (threads) {
       case 64: return launch_sweep_t<double, 64>(a, grid, lds, s);
       case 128: return launch_sweep_t<double, 128>(a, grid, lds, s);
-      case 1024: return launch_sweep_t<double, 1024>(a, grid, lds, s);
+      case 512: return launch_sweep_t<double, 512>(a, grid, lds, s);
       default: return launch_sweep_t<double, 256>(a, grid, lds, s);
     }
   }
   switch (threads) {
     case 64: return launch_sweep_t<float, 64>(a, grid, lds, s);
     case 128: return launch_sweep_t<float, 128>(a, grid, lds, s);
-    case 1024: return launch_sweep_t<float, 1024>(a, grid, lds, s);
+    case 512: return launch_sweep_t<float, 512>(a, grid, lds, s);
     default: return launch_sweep_t<float, 256>(a, grid, lds, s);
   }
 }

@@ -362,7 +362,7 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       const bool use_lds = key.bucket <= kLdsLimit;
       const size_t lds = use_lds ? key.bucket : 0;
       int chosen = p.batch_threads;
-      if (!chosen && !use_lds) chosen = 1024;  // global-scratch states: widest groups
+      if (!chosen && !use_lds) chosen = 512;  // global-scratch states: wider groups
       if (!chosen) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find({key.fp64, key.bucket});

@@ -147,7 +147,7 @@ __device__ __forceinline__ c128 quad_sum(c128 x) {
   return x;
 }
 
-__device__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
+__device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
                             c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s,
                             c128 *vstore = nullptr) {
   const int lane = threadIdx.x & 63;
@@ -738,30 +738,45 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
   }
 }
 
-// Per start (one wave): fixed-order FP64 sum of the P block partials of the
-// environment, then the gate update u <- polar((1 - beta) Gamma + beta u).
-__global__ __launch_bounds__(64) void k_env_finalize(const c128 *partials, int P,
-                                                     const int32_t *slot_to_start, c128 *gamma_out,
-                                                     int do_update, double beta, c128 *g64,
-                                                     c64 *g32, int32_t gstride, int32_t k_env,
-                                                     c128 *vstore) {
+// Per start: fixed-order FP64 sum of the P block partials of the environment (256
+// threads: thread 16 g + e sums entry e over blocks g, g + 16, ... with four independent
+// accumulators, so many loads are in flight; the 16 group sums are then added in group
+// order), then the gate update u <- polar((1 - beta) Gamma + beta u) on the first wave.
+constexpr int kFinBlock = 256;
+
+__global__ __launch_bounds__(kFinBlock) void k_env_finalize(const c128 *partials, int P,
+                                                            const int32_t *slot_to_start,
+                                                            c128 *gamma_out, int do_update,
+                                                            double beta, c128 *g64, c64 *g32,
+                                                            int32_t gstride, int32_t k_env,
+                                                            c128 *vstore) {
+  __shared__ c128 gsum[kFinBlock / 16][16];
   __shared__ c128 gam[16];
   __shared__ c128 pg[16], pv[16];
   __shared__ double psig[4];
   const int s = slot_to_start[blockIdx.x];
-  const int lane = threadIdx.x, e = lane & 15, grp = lane >> 4;
-  c128 sum = cmake(0.0, 0.0);
-  for (int blk = grp; blk < P; blk += 4) sum = sum + partials[((int64_t)s * P + blk) * 16 + e];
-  c128 tot = cmake(0.0, 0.0);
+  const int e = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  constexpr int G = kFinBlock / 16;
+  const c128 *src = partials + (int64_t)s * P * 16 + e;
+  c128 acc[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
+  int blk = grp;
+  for (; blk + 3 * G < P; blk += 4 * G) {
 #pragma unroll
-  for (int g2 = 0; g2 < 4; ++g2)
-    tot = tot + cmake(__shfl(sum.re, e + 16 * g2), __shfl(sum.im, e + 16 * g2));
-  if (lane < 16) {
+    for (int u = 0; u < 4; ++u) acc[u] = acc[u] + src[(int64_t)(blk + u * G) * 16];
+  }
+  if (blk < P) acc[0] = acc[0] + src[(int64_t)blk * 16];
+  if (blk + G < P) acc[1] = acc[1] + src[(int64_t)(blk + G) * 16];
+  if (blk + 2 * G < P) acc[2] = acc[2] + src[(int64_t)(blk + 2 * G) * 16];
+  gsum[grp][e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    c128 tot = gsum[0][e];
+    for (int g = 1; g < G; ++g) tot = tot + gsum[g][e];
     gam[e] = tot;
     if (gamma_out) gamma_out[(int64_t)s * 16 + e] = tot;
   }
   __syncthreads();
-  if (do_update) {
+  if (do_update && threadIdx.x < 64) {
     c128 *u64 = g64 + (int64_t)s * gstride + k_env * 16;
     c64 *u32 = g32 ? g32 + (int64_t)s * gstride + k_env * 16 : nullptr;
     c128 *vs = vstore ? vstore + (int64_t)s * gstride + k_env * 16 : nullptr;
@@ -1180,7 +1195,7 @@ int launch_env_finalize(int P, const c128 *partials, const int32_t *slot_to_star
                         c128 *gamma_out, bool do_update, double beta, c128 *g64, c64 *g32,
                         int32_t gstride, int32_t k_env, c128 *vstore, hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
-  hipLaunchKernelGGL(k_env_finalize, dim3(nslots), dim3(64), 0, s, partials, P, slot_to_start,
+  hipLaunchKernelGGL(k_env_finalize, dim3(nslots), dim3(kFinBlock), 0, s, partials, P, slot_to_start,
                      gamma_out, do_update ? 1 : 0, beta, g64, g32, gstride, k_env, vstore);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
