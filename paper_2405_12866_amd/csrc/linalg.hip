@@ -78,44 +78,167 @@ int launch_zgemm(bool conjtrans_a, int m, int n, int k, c128 alpha, const c128 *
   return QFS_OK;
 }
 
+// C = A^H B for a short, wide product (m x n output, k >> m, n; the Gram matrices of
+// the sample draw): the k range is split over up to kGramParts work-groups per output
+// tile, each writing a partial tile to `work` [parts][m][n]; k_sum_parts adds them in
+// part order.
+__global__ __launch_bounds__(256) void k_zgemm_ct_part(int m, int n, int k, int kchunk,
+                                                       const c128 *A, int lda, const c128 *B,
+                                                       int ldb, c128 *work) {
+  __shared__ c128 As[16][33];
+  __shared__ c128 Bs[16][33];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32, part = blockIdx.z;
+  const int k0 = part * kchunk, k1 = min(k, k0 + kchunk);
+  c128 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = cmake(0.0, 0.0);
+  for (int kb = k0; kb < k1; kb += 16) {
+    for (int e = tid; e < 512; e += 256) {
+      const int ii = e & 31, kk = e >> 5;
+      const int gi = i0 + ii, gk = kb + kk;
+      As[kk][ii] = (gi < m && gk < k1) ? cconj(A[(int64_t)gk * lda + gi]) : cmake(0.0, 0.0);
+      const int gj = j0 + ii;
+      Bs[kk][ii] = (gk < k1 && gj < n) ? B[(int64_t)gk * ldb + gj] : cmake(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const c128 a0 = As[kk][ty], a1 = As[kk][ty + 16];
+      const c128 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+      cfma(acc[0][0], a0, b0);
+      cfma(acc[0][1], a0, b1);
+      cfma(acc[1][0], a1, b0);
+      cfma(acc[1][1], a1, b1);
+    }
+    __syncthreads();
+  }
+  c128 *W = work + (int64_t)part * m * n;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int gi = i0 + ty + 16 * a, gj = j0 + tx + 16 * b;
+      if (gi < m && gj < n) W[(int64_t)gi * n + gj] = acc[a][b];
+    }
+}
+
+__global__ void k_sum_parts(int64_t mn, int parts, const c128 *work, c128 *C) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= mn) return;
+  c128 s = work[e];
+  for (int p = 1; p < parts; ++p) s = s + work[(int64_t)p * mn + e];
+  C[e] = s;
+}
+
+// k splits: enough work-groups to cover the chip (about 2048 with the m x m tiles),
+// at most 16
+static int gram_parts(int64_t m) {
+  const int64_t tiles = ((m + 31) / 32) * ((m + 31) / 32);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(16, 2048 / std::max<int64_t>(1, tiles)));
+}
+
+static int gram_splitk(int m, int n, int k, const c128 *A, int lda, const c128 *B, int ldb, c128 *C,
+                       c128 *work, hipStream_t s) {
+  const int nparts = gram_parts(std::max(m, n));
+  const int kchunk = ((k + nparts - 1) / nparts + 15) / 16 * 16;
+  const int parts = (k + kchunk - 1) / kchunk;
+  dim3 grid((n + 31) / 32, (m + 31) / 32, parts);
+  hipLaunchKernelGGL(k_zgemm_ct_part, grid, dim3(256), 0, s, m, n, k, kchunk, A, lda, B, ldb, work);
+  QFS_HIP(hipGetLastError());
+  const int64_t mn = (int64_t)m * n;
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, mn, parts, work, C);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
 // ------------------------------------------------------------------ Cholesky, R^-1
 // In-place upper Cholesky G = R^H R of an m x m Hermitian positive-definite matrix
-// (row-major, ld m), one work-group, right-looking. flag[0] is set on a non-positive
-// pivot.
-__global__ __launch_bounds__(1024) void k_cholesky_upper(int m, c128 *G, int *flag) {
+// (row-major, ld m), right-looking: R[j][j] = sqrt(G[j][j]), R[j][c] = G[j][c] / R[j][j],
+// G[i][c] -= conj(R[j][i]) R[j][c] for i, c > j. flag[0] is set on a non-positive pivot.
+// Blocked: rows [j, j + b) of the trailing matrix (the
+// "row panel", b x w with w = m - j, in LDS) are factored by one work-group with the
+// column steps above restricted to the panel; the rest of the trailing matrix is then
+// updated with one GEMM, G[j+b:, j+b:] -= R[J, j+b:]^H R[J, j+b:]. Only the upper
+// triangle is ever read; the strictly lower part is cleared at the end.
+__global__ __launch_bounds__(1024) void k_chol_panel(int m, int j, int b, c128 *G, int *flag) {
+  extern __shared__ c128 pan[];  // [b][w]
   __shared__ double inv_pivot;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int j = 0; j < m; ++j) {
+  const int tid = threadIdx.x, nt = blockDim.x, w = m - j;
+  for (int e = tid; e < b * w; e += nt) {
+    const int r = e / w, c = e % w;
+    pan[e] = G[(int64_t)(j + r) * m + j + c];
+  }
+  __syncthreads();
+  for (int jj = 0; jj < b; ++jj) {
     if (tid == 0) {
-      const double d = G[(int64_t)j * m + j].re;
+      const double d = pan[jj * w + jj].re;
       if (!(d > 0.0)) {
         flag[0] = 1;
         inv_pivot = 0.0;
-        G[(int64_t)j * m + j] = cmake(1.0, 0.0);
+        pan[jj * w + jj] = cmake(1.0, 0.0);
       } else {
         const double r = sqrt(d);
-        G[(int64_t)j * m + j] = cmake(r, 0.0);
+        pan[jj * w + jj] = cmake(r, 0.0);
         inv_pivot = 1.0 / r;
       }
     }
     __syncthreads();
     const double ip = inv_pivot;
-    for (int c = j + 1 + tid; c < m; c += nt) G[(int64_t)j * m + c] = cscale(G[(int64_t)j * m + c], ip);
+    for (int c = jj + 1 + tid; c < w; c += nt) pan[jj * w + c] = cscale(pan[jj * w + c], ip);
     __syncthreads();
-    const int w = m - j - 1;
-    for (int64_t e = tid; e < (int64_t)w * w; e += nt) {
-      const int i = j + 1 + (int)(e / w), c = j + 1 + (int)(e % w);
-      if (c < i) continue;
-      c128 v = G[(int64_t)i * m + c];
-      cfma(v, cscale(cconj(G[(int64_t)j * m + i]), -1.0), G[(int64_t)j * m + c]);
-      G[(int64_t)i * m + c] = v;
+    // rows jj+1 .. b-1 of the panel, columns from the row's diagonal on
+    const int rows = b - jj - 1;
+    for (int e = tid; e < rows * w; e += nt) {
+      const int ii = jj + 1 + e / w, c = e % w;
+      if (c < ii) continue;
+      c128 v = pan[ii * w + c];
+      cfma(v, cscale(cconj(pan[jj * w + ii]), -1.0), pan[jj * w + c]);
+      pan[ii * w + c] = v;
     }
     __syncthreads();
   }
-  for (int64_t e = tid; e < (int64_t)m * m; e += nt) {
+  for (int e = tid; e < b * w; e += nt) {
+    const int r = e / w, c = e % w;
+    G[(int64_t)(j + r) * m + j + c] = pan[e];
+  }
+}
+
+__global__ void k_zero_lower(int m, c128 *G) {
+  const int64_t total = (int64_t)m * m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / m), c = (int)(e % m);
     if (c < i) G[e] = cmake(0.0, 0.0);
   }
+}
+
+static int cholesky_upper_blocked(int m, c128 *G, int *flag, hipStream_t s) {
+  constexpr size_t kPanelLds = 144 * 1024;
+  static bool attr_set = false;
+  if (!attr_set) {
+    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol_panel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPanelLds));
+    attr_set = true;
+  }
+  const c128 one = cmake(1.0, 0.0), mone = cmake(-1.0, 0.0);
+  for (int j = 0; j < m;) {
+    const int w = m - j;
+    int b = (int)std::min<size_t>(32, kPanelLds / ((size_t)w * sizeof(c128)));
+    b = std::max(1, std::min(b, w));
+    hipLaunchKernelGGL(k_chol_panel, dim3(1), dim3(1024), sizeof(c128) * (size_t)b * w, s, m, j, b, G,
+                       flag);
+    QFS_HIP(hipGetLastError());
+    const int rest = w - b;
+    if (rest > 0) {
+      const c128 *panel = G + (int64_t)j * m + j + b;
+      QFS_TRY(launch_zgemm(true, rest, rest, b, mone, panel, m, panel, m, one,
+                           G + (int64_t)(j + b) * m + j + b, m, s));
+    }
+    j += b;
+  }
+  hipLaunchKernelGGL(k_zero_lower, dim3((unsigned)std::min<int64_t>(((int64_t)m * m + 255) / 256, 4096)),
+                     dim3(256), 0, s, m, G);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
 }
 
 // T = R^-1 for upper-triangular R (m x m): one wave per column c of T, back
@@ -157,7 +280,9 @@ __global__ void k_copy_cols(int64_t rows, int cols, const c128 *src, int lds, c1
 
 size_t work_bytes_orth(int64_t rows, int64_t cols) {
   const size_t m = (size_t)cols;
-  return sizeof(c128) * (m * m * 3 + (size_t)rows * m) + 256;
+  // gram_parts(x) x^2 over x <= m is at most max(min(16 m^2, 2^21), m^2)
+  const size_t parts = std::max(std::min(16 * m * m, size_t(1) << 21), m * m);
+  return sizeof(c128) * (m * m * 3 + parts + (size_t)rows * m) + 256;
 }
 
 int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c128 *A, void *work,
@@ -168,7 +293,8 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
   c128 *Gm = P + (size_t)c1 * c1;                 // m x m
   c128 *T = Gm + (size_t)m * m;                   // m x m
   c128 *Tmp = T + (size_t)m * m;                  // rows x m
-  int *flag = reinterpret_cast<int *>(Tmp + (size_t)rows * m);
+  c128 *parts = Tmp + (size_t)rows * m;           // gram_parts(m) x m x m
+  int *flag = reinterpret_cast<int *>(parts + (size_t)gram_parts(m) * m * m);
   QFS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
   c128 *An = A + c0;
   const c128 one = cmake(1.0, 0.0), zero = cmake(0.0, 0.0), mone = cmake(-1.0, 0.0);
@@ -179,9 +305,8 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
     }
   }
   for (int pass = 0; pass < 2; ++pass) {
-    QFS_TRY(launch_zgemm(true, m, m, (int)rows, one, An, (int)ld, An, (int)ld, zero, Gm, m, s));
-    hipLaunchKernelGGL(k_cholesky_upper, dim3(1), dim3(1024), 0, s, m, Gm, flag);
-    QFS_HIP(hipGetLastError());
+    QFS_TRY(gram_splitk(m, m, (int)rows, An, (int)ld, An, (int)ld, Gm, parts, s));
+    QFS_TRY(cholesky_upper_blocked(m, Gm, flag, s));
     hipLaunchKernelGGL(k_tri_inverse_upper, dim3(m), dim3(64), sizeof(c128) * (size_t)m, s, m, Gm,
                        T);
     QFS_HIP(hipGetLastError());
