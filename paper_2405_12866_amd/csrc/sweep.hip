@@ -398,15 +398,15 @@ struct FwdSeg {
 // A gate on the lowest amplitude bits makes a thread's four outputs rows 32 or 64 bytes
 // apart; for such gates (when coalesce_b is set) B_k leaves LDS in a second, contiguous
 // pass instead of straight from registers.
-template <typename R>
-__global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int n,
+template <typename R, int FB>
+__global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int n,
                                                              int logC, const int32_t *pairs,
                                                              const cx<R> *gates, int32_t gstride,
                                                              const int32_t *slot_to_start,
                                                              int coalesce_b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
-  __shared__ double red[kFwdBlock / 64];
+  __shared__ double red[FB / 64];
   const FwdSeg<R> sg = blockIdx.z == 0 ? seg0 : seg1;
   const int q = blockIdx.x;
   if (q >= sg.nch) return;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, Fwd
   const uint32_t chunk = 1u << (n + logC);                 // elements per chunk
   const int64_t cbase = (int64_t)q << (n + logC);
   const cx<R> *src = sg.src + cbase;
-  for (uint32_t e = threadIdx.x * V; e < chunk; e += kFwdBlock * V) st_pk(lds + e, ld_pk(src + e));
+  for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(lds + e, ld_pk(src + e));
   __syncthreads();
   const uint32_t groups = 1u << (n - 2 + logJ);
   for (int k = 0; k < sg.kapply; ++k) {
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, Fwd
     const bool store = k < sg.kstore;
     cx<R> *dst = store ? sg.blist + sg.bstride * s + sg.sN * k + cbase : nullptr;
     const bool late = store && coalesce_b && ((sizeof(cx<R>) << (logC + min(pa, pb))) < 128);
-    for (uint32_t g = threadIdx.x; g < groups; g += kFwdBlock) {
+    for (uint32_t g = threadIdx.x; g < groups; g += FB) {
       const uint32_t jv = g & ((1u << logJ) - 1u);
       const uint32_t i0 = deposit(g >> logJ, sorted, 2);
       uint32_t o[4];
@@ -455,14 +455,14 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, Fwd
     }
     __syncthreads();
     if (late) {
-      for (uint32_t e = threadIdx.x * V; e < chunk; e += kFwdBlock * V) st_pk(dst + e, ld_pk(lds + e));
+      for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(dst + e, ld_pk(lds + e));
       __syncthreads();
     }
   }
   if (sg.ref) {
     const cx<R> *ref = sg.ref + cbase;
     double acc = 0.0;
-    for (uint32_t e = threadIdx.x * V; e < chunk; e += kFwdBlock * V) {
+    for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) {
       const Pk<R> a = ld_pk(lds + e), b = ld_pk(ref + e);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kFwdBlock) void k_forward_fused(FwdSeg<R> seg0, Fwd
     __syncthreads();
     if (threadIdx.x == 0) {
       double tot = 0.0;
-      for (int w = 0; w < kFwdBlock / 64; ++w) tot += red[w];
+      for (int w = 0; w < FB / 64; ++w) tot += red[w];
       sg.partials[(int64_t)s * sg.nch + q] = tot;
     }
   }
@@ -1005,21 +1005,28 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
   }
   const int gx = std::max(a.nch, gv ? b.nch : 0);
   const size_t lds = forward_lds_bytes(g.n, g.logC, sizeof(R));
-  static size_t attr_bytes = 0;  // dynamic LDS above 64 KB must be requested per kernel
-  if (lds > 64 * 1024 && lds > attr_bytes) {
-    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forward_fused<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_bytes = lds;
-  }
   static const int coalesce_b = [] {
     const char *e = std::getenv("QFS_FWD_COALESCE");  // 0: always store from registers
     return e ? std::atoi(e) : 1;
   }();
-  hipLaunchKernelGGL(k_forward_fused<R>, dim3(gx, nslots, nz), dim3(kFwdBlock), lds, s, a, b, g.n,
-                     g.logC, pairs_dev, static_cast<const cx<R> *>(gates.gR), gates.gstride,
-                     slot_to_start, coalesce_b);
-  QFS_HIP(hipGetLastError());
-  return QFS_OK;
+  static const int fwd_threads = [] {
+    const char *e = std::getenv("QFS_FWD_THREADS");  // work-group size: 512 (default) or 1024
+    return (e && std::atoi(e) == 1024) ? 1024 : 512;
+  }();
+  auto go = [&](auto kernel, int threads) -> int {
+    static size_t attr_bytes = 0;  // dynamic LDS above 64 KB must be requested per kernel
+    if (lds > 64 * 1024 && lds > attr_bytes) {
+      QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      attr_bytes = lds;
+    }
+    hipLaunchKernelGGL(kernel, dim3(gx, nslots, nz), dim3(threads), lds, s, a, b, g.n, g.logC, pairs_dev,
+                       static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, coalesce_b);
+    QFS_HIP(hipGetLastError());
+    return QFS_OK;
+  };
+  if (fwd_threads == 1024) return go(k_forward_fused<R, 1024>, 1024);
+  return go(k_forward_fused<R, 512>, 512);
 }
 
 template <typename R>
