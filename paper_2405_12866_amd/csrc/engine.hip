@@ -4,6 +4,7 @@
 // half-multistart retry on device out-of-memory), device memory management and the
 // per-step entry points declared in include/qfs.h.
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -170,6 +171,11 @@ struct SweepCtx {
   int S = 0;
   KernelTimer *timer = nullptr;
   hipStream_t stream = nullptr;
+  // Second stream and join events: without kernel timing, the backward pass runs the
+  // two halves of the starts on two streams, so one half's environment reduction and
+  // polar update overlap the other half's backward step.
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 template <typename R>
@@ -261,19 +267,37 @@ int sweep_backward(SweepCtx &c) {
   const int64_t sN = c.g.elems();
   const int64_t bstride = sN * std::max(c.L - 1, 1);
   KernelTimer &T = *c.timer;
+  // halves of the active starts, each on its own stream (one half when timing or when
+  // a single start runs)
+  const bool split = !T.on && c.side && c.nslots >= 2;
+  const int halves = split ? 2 : 1;
+  const int h0 = split ? c.nslots / 2 : c.nslots;
+  const int32_t *hslots[2] = {c.slots, c.slots + h0};
+  const int hn[2] = {h0, c.nslots - h0};
+  hipStream_t hs[2] = {c.stream, c.side};
+  if (split) {
+    QFS_HIP(hipEventRecord(c.fork, c.stream));
+    QFS_HIP(hipStreamWaitEvent(c.side, c.fork, 0));
+  }
   for (int k = c.L - 1; k >= 0; --k) {
     const int k_apply = (k == c.L - 1) ? -1 : k + 1;
     SBuf<R> a_in = (k >= c.L - 2) ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
     SBuf<R> b = k == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 1) * sN, bstride};
-    int P = 0;
-    QFS_TRY(T.begin(c.stream));
-    QFS_TRY(launch_bwd_step<R>(c.g, c.pairs_host, k_apply, k, gr, a_in, SBuf<R>{A, sN}, b, c.slots,
-                               c.nslots, c.partials, &P, c.stream));
-    QFS_TRY(T.end(c.stream, kClsStep, (k_apply < 0 ? 2.0 : 3.0) * set_bytes<R>(c, c.g)));
-    QFS_TRY(T.begin(c.stream));
-    QFS_TRY(launch_env_finalize(P, c.partials, c.slots, c.nslots, nullptr, true, c.beta, c.g64,
-                                sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, k, c.vstore, c.stream));
-    QFS_TRY(T.end(c.stream, kClsPolar, (double)P * 256.0 * c.nslots));
+    for (int h = 0; h < halves; ++h) {
+      int P = 0;
+      QFS_TRY(T.begin(hs[h]));
+      QFS_TRY(launch_bwd_step<R>(c.g, c.pairs_host, k_apply, k, gr, a_in, SBuf<R>{A, sN}, b, hslots[h],
+                                 hn[h], c.partials, &P, hs[h]));
+      QFS_TRY(T.end(hs[h], kClsStep, (k_apply < 0 ? 2.0 : 3.0) * set_bytes<R>(c, c.g) * hn[h] / c.nslots));
+      QFS_TRY(T.begin(hs[h]));
+      QFS_TRY(launch_env_finalize(P, c.partials, hslots[h], hn[h], nullptr, true, c.beta, c.g64,
+                                  sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, k, c.vstore, hs[h]));
+      QFS_TRY(T.end(hs[h], kClsPolar, (double)P * 256.0 * hn[h]));
+    }
+  }
+  if (split) {
+    QFS_HIP(hipEventRecord(c.join, c.side));
+    QFS_HIP(hipStreamWaitEvent(c.stream, c.join, 0));
   }
   int P = 0;
   QFS_TRY(T.begin(c.stream));
@@ -318,6 +342,9 @@ class Group {
     if (h_costs_) (void)hipHostFree(h_costs_);
     if (ev0_) (void)hipEventDestroy(ev0_);
     if (ev1_) (void)hipEventDestroy(ev1_);
+    if (fork_) (void)hipEventDestroy(fork_);
+    if (join_) (void)hipEventDestroy(join_);
+    if (side_) (void)hipStreamDestroy(side_);
   }
 
   int run(GroupResult &out, double t_start);
@@ -332,6 +359,8 @@ class Group {
   int64_t N_ = 0;
   std::vector<int32_t> pairs_;
   hipStream_t stream_ = nullptr;
+  hipStream_t side_ = nullptr;  // second stream of the backward pass (default priority)
+  hipEvent_t fork_ = nullptr, join_ = nullptr;
 
   int M_ = 0, ldm_ = 0, Mv_ = 0, ldmv_ = 0, m_cap_ = 0, n_train_ = 0, generation_ = 0;
   bool fp64_ = true;
@@ -559,6 +588,18 @@ int Group::run(GroupResult &out, double t_start) {
   c.S = S_;
   c.timer = &timer_;
   c.stream = stream_;
+  static const bool split_ok = [] {
+    const char *e = std::getenv("QFS_BWD_SPLIT");  // 0: one stream for the backward pass
+    return !(e && std::atoi(e) == 0);
+  }();
+  if (S_ >= 2 && split_ok) {
+    QFS_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+    QFS_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+    QFS_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
+    c.side = side_;
+    c.fork = fork_;
+    c.join = join_;
+  }
   QFS_TRY(setup_working());
 
   std::vector<int> status(S_, ST_RUN), reason(S_, QFS_MAX_ITER), iter(S_, 0), z(S_, 0);
