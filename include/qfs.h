@@ -121,6 +121,10 @@ typedef struct {
   int32_t batch_threads;     /* qfs_instantiate_batch: work-group size 64, 128 or 256
                                 (0 = chosen by the built-in autotuner, cached per
                                 precision and state-size class for the process)     */
+  int32_t graphs;            /* qfs_instantiate: 1 (default) replays each sweep's
+                                launches as a captured HIP graph on an internal
+                                stream (re-captured when the running starts, M or
+                                the precision change); 0 launches every kernel     */
 } qfs_params;
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,

@@ -345,6 +345,10 @@ class Group {
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
     if (side_) (void)hipStreamDestroy(side_);
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    if (gfork_) (void)hipEventDestroy(gfork_);
+    if (gjoin_) (void)hipEventDestroy(gjoin_);
+    if (cap_) (void)hipStreamDestroy(cap_);
   }
 
   int run(GroupResult &out, double t_start);
@@ -361,6 +365,14 @@ class Group {
   hipStream_t stream_ = nullptr;
   hipStream_t side_ = nullptr;  // second stream of the backward pass (default priority)
   hipEvent_t fork_ = nullptr, join_ = nullptr;
+  // One sweep (backward pass, then the forward pass of the updated gates) captured as a
+  // HIP graph on the internal stream cap_, replayed while nothing it depends on changes
+  // (running starts, M, precision: each of those marks it dirty).
+  hipStream_t cap_ = nullptr;
+  hipEvent_t gfork_ = nullptr, gjoin_ = nullptr;
+  hipGraphExec_t gexec_ = nullptr;
+  bool gdirty_ = true;
+  int sweep_once();
 
   int M_ = 0, ldm_ = 0, Mv_ = 0, ldmv_ = 0, m_cap_ = 0, n_train_ = 0, generation_ = 0;
   bool fp64_ = true;
@@ -452,6 +464,7 @@ int Group::draw_validation() {
 // Working sets in the sweep precision (chunk width chosen for the fused forward pass
 // when a chunk of whole samples fits in LDS), and the per-start state buffers.
 int Group::setup_working() {
+  gdirty_ = true;
   const size_t rb = fp64_ ? sizeof(double) : sizeof(float);
   const size_t cb = 2 * rb;
   const size_t lds = lds_max_bytes();
@@ -501,7 +514,49 @@ int Group::setup_working() {
   return QFS_OK;
 }
 
+int Group::sweep_once() {
+  if (!p_.graphs || timer_.on) {
+    QFS_TRY(backward_any());
+    return forward_any(false);
+  }
+  if (!cap_) {
+    QFS_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+    QFS_HIP(hipEventCreateWithFlags(&gfork_, hipEventDisableTiming));
+    QFS_HIP(hipEventCreateWithFlags(&gjoin_, hipEventDisableTiming));
+  }
+  // order the internal stream after everything issued so far on the caller's stream
+  QFS_HIP(hipEventRecord(gfork_, stream_));
+  QFS_HIP(hipStreamWaitEvent(cap_, gfork_, 0));
+  if (gdirty_ || !gexec_) {
+    if (gexec_) {
+      QFS_HIP(hipGraphExecDestroy(gexec_));
+      gexec_ = nullptr;
+    }
+    ctx_.stream = cap_;
+    hipGraph_t graph = nullptr;
+    QFS_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+    int rc = backward_any();
+    if (rc == QFS_OK) rc = forward_any(false);
+    const hipError_t e = hipStreamEndCapture(cap_, &graph);
+    ctx_.stream = stream_;
+    if (rc != QFS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    QFS_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&gexec_, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    QFS_HIP(ei);
+    gdirty_ = false;
+  }
+  QFS_HIP(hipGraphLaunch(gexec_, cap_));
+  QFS_HIP(hipEventRecord(gjoin_, cap_));
+  QFS_HIP(hipStreamWaitEvent(stream_, gjoin_, 0));
+  return QFS_OK;
+}
+
 int Group::set_slots(const std::vector<int> &active) {
+  gdirty_ = true;
   ctx_.nslots = (int)active.size();
   if (ctx_.nslots == 0) return QFS_OK;
   QFS_HIP(hipMemcpyAsync(slots_.ptr, active.data(), sizeof(int32_t) * active.size(),
@@ -624,8 +679,7 @@ int Group::run(GroupResult &out, double t_start) {
     // one sweep of every running start, then the next forward pass (which also gives
     // the validation cost of the post-sweep gates)
     QFS_HIP(hipEventRecord(ev0_, stream_));
-    QFS_TRY(backward_any());
-    QFS_TRY(forward_any(false));
+    QFS_TRY(sweep_once());
     QFS_HIP(hipEventRecord(ev1_, stream_));
     std::vector<double> nct(S_), ncv(S_);
     QFS_TRY(read_costs(nct, ncv, nullptr));
@@ -906,6 +960,7 @@ void qfs_default_params(qfs_params *p) {
   p->timing = 0;
   p->batch_sweeps = 0;
   p->batch_threads = 0;
+  p->graphs = 1;
 }
 
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,

@@ -48,7 +48,8 @@ class Params(C.Structure):
                 ("fixed_m", C.c_int32), ("m_val", C.c_int32), ("precision", C.c_int32),
                 ("refine_below", C.c_double), ("device_mem_budget", C.c_uint64),
                 ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p),
-                ("timing", C.c_int32), ("batch_sweeps", C.c_int32), ("batch_threads", C.c_int32)]
+                ("timing", C.c_int32), ("batch_sweeps", C.c_int32), ("batch_threads", C.c_int32),
+                ("graphs", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -317,3 +317,27 @@ def test_full_size_sweep_sampled_starts():
     say("full size: second sweep must not increase any start's cost")
     c2 = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED)
     assert np.all(c2 <= c_gpu + 1e-6 * np.maximum(c_gpu, 1e-3))
+
+
+# ------------------------------------------------------------------ graph replay
+@pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
+def test_graph_replay_matches_eager(precision):
+    """Each sweep replayed from a captured HIP graph (the default) gives bit-identical
+    results to launching every kernel: many replays with host decisions and copies in
+    between, re-captures after starts stop, after doublings and after the switch to
+    complex128 refinement."""
+    say(f"graph replay vs eager, precision={precision}")
+    n = 6
+    g = np.random.default_rng(61)
+    pairs = I.random_pair_template(n, 8, g)
+    tg = dev(I.haar_gates(len(pairs), g))
+    base = dict(multistarts=6, seed=9, max_iter=400, dist_tol=1e-10, precision=precision)
+    g_on, r_on = Q.qfs_instantiate(n, pairs, target_pairs=pairs, target_gates=tg,
+                                   params=Q.qfs_default_params(graphs=1, **base))
+    g_off, r_off = Q.qfs_instantiate(n, pairs, target_pairs=pairs, target_gates=tg,
+                                     params=Q.qfs_default_params(graphs=0, **base))
+    for key in ("reason", "sweeps", "restarts", "best_start", "m_final", "start_sweeps", "refined"):
+        assert r_on[key] == r_off[key], (key, r_on[key], r_off[key])
+    assert r_on["c_train"] == r_off["c_train"] and r_on["c_val"] == r_off["c_val"]
+    assert np.array_equal(host(g_on), host(g_off))
+    say(f"  {r_on['reason_name']} after {r_on['sweeps']} sweeps, {r_on['restarts']} doublings")
