@@ -270,9 +270,10 @@ int qfs_mlp_train(int32_t count, const float *features, const float *targets,
                   int32_t epochs, int32_t batch, float lr, uint64_t seed, float *epoch_loss,
                   void *hip_stream);
 
-/* Predicted initial M (a power of two in [2, 2^n]) and the starts to keep: the fewest
- * leading starts (at most params->multistarts) for which at least one succeeds with
- * probability 0.95 at the predicted per-start rate. keep_mask bit s = start s kept
+/* Predicted initial M (a power of two in [2, 2^n]) and the starts to keep: with the
+ * predicted per-start success rate p, the number k of leading starts (1 <= k <=
+ * params->multistarts = S) that minimises k + (1 - p)^k (S - k), the expected start-runs
+ * when the pruned starts run only if all kept ones fail. keep_mask bit s = start s kept
  * (nullable). QFS_EINVAL when no weights are loaded. */
 int qfs_predict_m(const qfs_template *tmpl, const qfs_params *params, int32_t *m0,
                   uint32_t *keep_mask);
@@ -282,9 +283,10 @@ int qfs_predict_batch(int32_t P, const qfs_template *tmpl, const qfs_params *par
 /* qfs_instantiate with M starting at max(m_init, predicted M) (doubling on the
  * validation cost as usual, Sec. 3) and the predicted number of leading starts. When
  * that run does not succeed and starts were pruned, the pruned starts run after it
- * with the plain method (M from m_init, their own initial gates), fallback = 1, and the
- * better of the two runs is returned (success first, then lower c_train). Counters in
- * res (start_sweeps, m_total, sweep_seconds, seconds) cover both runs. */
+ * with the plain method's control from the M the first run ended at (their own initial
+ * gates), fallback = 1, and the better of the two runs is returned (success first, then
+ * lower c_train). Counters in res (start_sweeps, m_total, sweep_seconds, seconds) cover
+ * both runs. */
 int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target,
                             const qfs_params *params, qfs_c128 *gates_out, qfs_result *res);
 

@@ -4,12 +4,12 @@
 // Here a small network (mlp.hip) maps 64 structural features of the template to
 //   y0 = log2 of the smallest power-of-two M at which a start succeeds and generalises,
 //   y1 = logit of the probability that one random start succeeds at that M,
-// and the instantiation runs with M0 = 2^round(y0) and just enough starts that at least
-// one succeeds with probability 0.95 under the predicted rate. A predicted M0 that is too
-// small is corrected by the method's own doubling on the held-out validation cost
-// (Sec. 3); a start count that was too small is corrected by the fallback: when the
-// learned run does not succeed, the pruned starts run with the plain method (M from
-// m_init, doubling), so no start of the plain method is lost.
+// and the instantiation runs with M0 = 2^round(y0) and the number of starts that
+// minimises the expected start-runs under the predicted rate (see decide). A predicted M0
+// that is too small is corrected by the method's own doubling on the held-out validation
+// cost (Sec. 3); a start count that was too small is corrected by the fallback: when the
+// learned run does not succeed, the pruned starts run with the plain method's control,
+// from the M the learned run ended at, so no start of the plain method is lost.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -21,7 +21,6 @@
 namespace qfs {
 namespace {
 
-constexpr double kMissProb = 0.05;  // accepted chance that every kept start fails
 
 double lnow() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -115,15 +114,23 @@ void template_features(const qfs_template &t, float *out) {
   for (int i = 0; i < kMlpF; ++i) out[i] = (float)f[i];
 }
 
-// Network outputs -> (M0, kept starts).
+// Network outputs -> (M0, kept starts). With a predicted per-start success rate p, k
+// kept starts cost k start-runs and, with probability (1 - p)^k that none succeeds, the
+// S - k pruned ones run afterwards; k minimises k + (1 - p)^k (S - k).
 void decide(const float *y, int n, int S, int32_t *m0, int32_t *starts) {
   const double lg = std::min<double>(n, std::max(1.0, std::nearbyint((double)y[0])));
   *m0 = (int32_t)std::ldexp(1.0, (int)lg);
-  const double p = 1.0 / (1.0 + std::exp(-(double)y[1]));
-  int k = S;
-  if (p >= 1.0) k = 1;
-  else if (p > 0.0) k = (int)std::ceil(std::log(kMissProb) / std::log1p(-p));
-  *starts = std::max(1, std::min(S, k));
+  const double p = std::min(1.0, std::max(0.0, 1.0 / (1.0 + std::exp(-(double)y[1]))));
+  int best = S;
+  double best_cost = (double)S;
+  for (int k = 1; k < S; ++k) {
+    const double cost = k + std::pow(1.0 - p, k) * (S - k);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = k;
+    }
+  }
+  *starts = best;
 }
 
 int predict_many(int P, const qfs_template *tmpl, const qfs_params &p, int32_t *m0, int32_t *starts,
@@ -203,6 +210,7 @@ int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target, 
     QFS_HIP(hipMemcpyAsync(best.ptr, gates_out, sizeof(c128) * 16 * L, hipMemcpyDeviceToDevice, st));
   qfs_params q2 = *params;
   q2.multistarts = S - k;
+  q2.m_init = std::max(params->m_init, r1.m_final);
   qfs_result r2;
   QFS_TRY(qfs_instantiate(tmpl, target, &q2, all.as<qfs_c128>() + (size_t)k * L * 16, gates_out, &r2));
   const bool take2 = r2.reason == QFS_SUCCESS || r2.c_train < r1.c_train;
@@ -250,7 +258,7 @@ int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl, const qfs
     std::vector<qfs_target> fg(F);
     std::vector<qfs_result> fr(F);
     std::vector<uint64_t> seeds(F);
-    std::vector<int32_t> lo(F);
+    std::vector<int32_t> lo(F), mfb(F);
     std::vector<DevBuf> tmp(F);
     std::vector<qfs_c128 *> fo(F);
     for (int f = 0; f < F; ++f) {
@@ -259,12 +267,14 @@ int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl, const qfs
       fg[f] = targets[i];
       seeds[f] = params->seed + (uint64_t)i;
       lo[f] = k[i];
+      mfb[f] = std::max(params->m_init, res[i].m_final);
       QFS_TRY(tmp[f].alloc(sizeof(c128) * 16 * (size_t)tmpl[i].n_gates));
       fo[f] = tmp[f].as<qfs_c128>();
     }
     BatchOpts plain;
     plain.seeds = seeds.data();
     plain.start_lo = lo.data();
+    plain.m_init = mfb.data();
     QFS_TRY(batch_instantiate(F, ft.data(), fg.data(), params, fo.data(), fr.data(), plain));
     for (int f = 0; f < F; ++f) {
       const int i = failed[f];

@@ -1010,8 +1010,8 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
     return e ? std::atoi(e) : 1;
   }();
   static const int fwd_threads = [] {
-    const char *e = std::getenv("QFS_FWD_THREADS");  // work-group size: 512 (default) or 1024
-    return (e && std::atoi(e) == 1024) ? 1024 : 512;
+    const char *e = std::getenv("QFS_FWD_THREADS");  // work-group size: 1024 (default) or 512
+    return (e && std::atoi(e) == 512) ? 512 : 1024;
   }();
   auto go = [&](auto kernel, int threads) -> int {
     static size_t attr_bytes = 0;  // dynamic LDS above 64 KB must be requested per kernel

@@ -171,7 +171,9 @@ def test_learned_gain_over_plain():
     fb = sum(r["fallback"] for r in r_learn)
     say(f"  plain: {ok_p}/192 ok, {ss_p} start-sweeps, {r_plain[0]['seconds']:.2f} s")
     say(f"  learned: {ok_l}/192 ok, {ss_l} start-sweeps, {r_learn[0]['seconds']:.2f} s, "
-        f"{fb} fallbacks")
+        f"{fb} fallbacks, mean predicted M {np.mean([r['m_predicted'] for r in r_learn]):.1f}, "
+        f"mean starts {np.mean([r['starts_run'] for r in r_learn]):.1f}")
+    say(f"  M-weighted work: plain {work_of(r_plain):.3e}, learned {work_of(r_learn):.3e}")
     assert ok_l >= ok_p - 2
     assert ss_l < 0.7 * ss_p
     for i in range(0, 192, 12):
