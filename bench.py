@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-distance runs")
     ap.add_argument("--timing", type=int, default=1)
+    ap.add_argument("--graphs", type=int, default=1, help="replay sweeps from HIP graphs (params.graphs)")
     ap.add_argument("--batched", type=int, default=4096,
                     help="problems in the batched workload (0 skips it)")
     ap.add_argument("--plain-sample", type=int, default=48,
@@ -112,7 +113,7 @@ def cpu_baseline(w, M, starts):
                       f"(one thread each), 12 qubits, 44 gates, M={M}, complex128; {dt:.1f} s"}
 
 
-def time_to_distance(dev):
+def time_to_distance(dev, graphs=1):
     """Time-to-distance 1e-8 (App. A defaults, MIXED with FP64 refinement) on the
     8-qubit brickwork (21 gates, M = 32, one start: the plain single-problem case)
     and with 16 starts."""
@@ -125,7 +126,8 @@ def time_to_distance(dev):
     tg = torch.as_tensor(w["target_gates"]).to(dev)
     out = {}
     for starts in (1, 16):
-        p = Q.qfs_default_params(multistarts=starts, m_init=32, fixed_m=1, seed=7, max_iter=3000)
+        p = Q.qfs_default_params(multistarts=starts, m_init=32, fixed_m=1, seed=7, max_iter=3000,
+                                 graphs=graphs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, info = Q.qfs_instantiate(8, w["pairs"], target_pairs=w["pairs"], target_gates=tg, params=p)
@@ -269,7 +271,8 @@ def main():
     M, S = args.m, args.starts
     tg = torch.as_tensor(w["target_gates"]).to(dev)
     base = Q.qfs_default_params(multistarts=S, m_init=M, fixed_m=1, seed=0x5A17 + 3,
-                                precision=Q.QFS_PREC_MIXED, diff_tol_r=0.0, plateau_window=1 << 30)
+                                precision=Q.QFS_PREC_MIXED, diff_tol_r=0.0, plateau_window=1 << 30,
+                                graphs=args.graphs)
     # warmup (also loads code objects)
     Q.qfs_instantiate(n, pairs, target_pairs=pairs, target_gates=tg,
                       params=dict(base, max_iter=max(1, args.warmup)))
@@ -315,7 +318,7 @@ def main():
     if args.learned > 0 or args.learned_large > 0:
         extra["learned"] = learned(dev, args.learned, args.learned_large)
     if not args.no_ttd:
-        extra["time_to_distance"] = time_to_distance(dev)
+        extra["time_to_distance"] = time_to_distance(dev, args.graphs)
         extra["time_to_distance"]["12q_note"] = (
             "12q Haar-random brickwork from random initial gates does not reach 1e-8 within "
             "the bench budget (it stalls near c_train 1.69 in the oracle as well); time-to-"

@@ -165,6 +165,10 @@ typedef struct {
   int32_t m_predicted;
   int32_t starts_run;
   int32_t fallback;
+  /* Device work of the call (or of the problem, batched): sum over start-sweeps of
+   * (M + M_val) 2^n L, the amplitude-gate updates of one sweep's forward and backward
+   * passes at the M of that sweep. */
+  double amp_updates;
 } qfs_result;
 
 /* Fill *p with the defaults: dist_tol 1e-8, diff_tol_r 1e-5, plateau_window 5,
@@ -290,9 +294,10 @@ int qfs_predict_batch(int32_t P, const qfs_template *tmpl, const qfs_params *par
 int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target,
                             const qfs_params *params, qfs_c128 *gates_out, qfs_result *res);
 
-/* The same for qfs_instantiate_batch: one batched learned run, then one batched plain
- * run of the pruned starts of the problems that did not succeed (each problem with its
- * original seed, so every start keeps its own initial gates). */
+/* The same for qfs_instantiate_batch, in one batched run: each problem starts with its
+ * predicted M and kept starts; its pruned starts are parked and woken inside the run
+ * (from the problem's current training set, their own initial gates) as soon as every
+ * kept start has stopped without success. fallback = 1 when that happened. */
 int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl,
                                   const qfs_target *targets, const qfs_params *params,
                                   qfs_c128 *const *gates_out, qfs_result *res);

@@ -16,7 +16,8 @@ enum {
   BJ_PAUSED = 6,   // reached a sweep the problem already decided on
   BJ_REFINE = 7,   // complex64 job below refine_below: continue in complex128
   BJ_TIMEOUT = 8,
-  BJ_SKIP = 9       // start not run (pruned by the caller)
+  BJ_SKIP = 9,      // start not run (pruned by the caller)
+  BJ_PARKED = 10    // pruned start that runs only if every other start stops unsuccessfully
 };
 
 constexpr int kNoSweep = 0x3fffffff;
@@ -48,6 +49,7 @@ struct BJob {
   int32_t need_c0;
   int32_t fp64;
   double c_prev, c_train, c_val;
+  double work;  // sum over this job's sweeps of (M + Mv) 2^n L
 };
 
 struct BParams {
@@ -77,6 +79,8 @@ struct BatchOpts {
   const int32_t *start_lo = nullptr;  // [P] first start to run (default 0)
   const uint64_t *seeds = nullptr;  // [P] per-problem seeds (default params->seed + p)
   int independent = 0;              // starts do not stop at another start's success
+  int park_rest = 0;                // starts beyond starts[p] are parked, not skipped
+  int32_t *fallback_used = nullptr; // [P] out: 1 when parked starts were run
   int32_t *successes = nullptr;     // [P] out: number of starts that succeeded
 };
 

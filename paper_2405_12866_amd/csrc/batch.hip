@@ -450,6 +450,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
       const double cv = Mv > 0 ? cval : ct;
       J.iter += 1;
       J.total += 1;
+      J.work += (double)(M + Mv) * (double)(1u << n) * (double)L;
       const bool improved = fabs(J.c_prev) - fabs(ct) > hp.diff_tol_r * fabs(ct);
       J.z = improved ? 0 : J.z + 1;
       J.c_prev = ct;

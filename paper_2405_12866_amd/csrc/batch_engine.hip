@@ -257,7 +257,9 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       j.prob = i;
       j.start = s;
       const bool run = (!opts.starts || s < opts.starts[i]) && (!opts.start_lo || s >= opts.start_lo[i]);
-      j.status = run ? BJ_RUN : BJ_SKIP;
+      const bool park = !run && opts.park_rest && opts.starts && s >= opts.starts[i] &&
+                        (!opts.start_lo || s >= opts.start_lo[i]);
+      j.status = run ? BJ_RUN : (park ? BJ_PARKED : BJ_SKIP);
       j.c_train = j.c_val = HUGE_VAL;
       j.need_c0 = 1;
       j.fp64 = p.precision == QFS_PREC_FP64 ? 1 : 0;
@@ -541,7 +543,7 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         todo.push_back(i);
         m0s.push_back(m_old);
         for (int s = 0; s < S; ++s)
-          if (!terminal(js[s].status)) {
+          if (!terminal(js[s].status) && js[s].status != BJ_PARKED) {
             js[s].status = BJ_RUN;
             js[s].iter = 0;
             js[s].z = 0;
@@ -562,10 +564,30 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         if (timed_out && js[s].status == BJ_RUN) js[s].status = BJ_TIMEOUT;
       }
       if (timed_out) any_run = false;
+      if (!any_run && !timed_out) {
+        // every running start stopped without success: wake the parked starts, which
+        // continue from the problem's current training set
+        bool woke = false;
+        for (int s = 0; s < S; ++s)
+          if (js[s].status == BJ_PARKED) {
+            js[s].status = BJ_RUN;
+            js[s].iter = 0;
+            js[s].z = 0;
+            js[s].need_c0 = 1;
+            js[s].fp64 = p.precision == QFS_PREC_FP64 ? 1 : 0;
+            woke = true;
+          }
+        if (woke) {
+          if (opts.fallback_used) opts.fallback_used[i] = 1;
+          continue;
+        }
+      }
       if (!any_run) {
         int w = -1;
         for (int s = 0; s < S; ++s)
-          if (js[s].status != BJ_SKIP && (w < 0 || js[s].c_train < js[w].c_train)) w = s;
+          if (js[s].status != BJ_SKIP && js[s].status != BJ_PARKED &&
+              (w < 0 || js[s].c_train < js[w].c_train))
+            w = s;
         finish(w, -1);
       }
     }
@@ -601,7 +623,10 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     r.c_train = js[w].c_train;
     r.c_val = js[w].c_val;
     r.seconds = secs;
-    for (int s = 0; s < S; ++s) r.start_sweeps += js[s].total;
+    for (int s = 0; s < S; ++s) {
+      r.start_sweeps += js[s].total;
+      r.amp_updates += js[s].work;
+    }
     if (opts.successes) {
       int c = 0;
       for (int s = 0; s < S; ++s) c += js[s].status == BJ_SUCCESS;

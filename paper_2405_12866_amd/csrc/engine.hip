@@ -319,6 +319,7 @@ struct GroupResult {
   int64_t success_round = -1;  // sweep round at which the success was found
   int refined = 0;
   int64_t start_sweeps = 0;
+  double amp_updates = 0.0;
   double sweep_seconds = 0.0;
   Counters k;
   std::vector<qfs_c128> gates;  // [L][16] of the chosen start (host copy)
@@ -688,6 +689,7 @@ int Group::run(GroupResult &out, double t_start) {
     out.sweep_seconds += 1e-3 * ms;
     ++round;
     out.start_sweeps += (int64_t)active.size();
+    out.amp_updates += (double)active.size() * (double)(M_ + Mv_) * (double)N_ * (double)L_;
 
     const bool full = (int64_t)M_ == N_;
     bool any_success = false, any_over = false;
@@ -1027,6 +1029,7 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
   res->c_val = r.c_val;
   for (const auto &x : results) {
     res->start_sweeps += x.start_sweeps;
+    res->amp_updates += x.amp_updates;
     res->sweep_seconds += x.sweep_seconds;
     for (int c = 0; c < kClasses; ++c) {
       res->kernel_launches[c] += x.k.kl[c];

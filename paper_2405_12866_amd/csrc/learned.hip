@@ -223,6 +223,7 @@ int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target, 
   res->starts_run = S;
   res->fallback = 1;
   res->start_sweeps = r1.start_sweeps + r2.start_sweeps;
+  res->amp_updates = r1.amp_updates + r2.amp_updates;
   res->sweep_seconds = r1.sweep_seconds + r2.sweep_seconds;
   res->m_total = r1.m_total + r2.m_total;
   res->seconds = lnow() - t0;
@@ -235,69 +236,25 @@ int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl, const qfs
   const double t0 = lnow();
   hipStream_t st = static_cast<hipStream_t>(params->hip_stream);
   const int S = params->multistarts;
-  std::vector<int32_t> m0(P), k(P);
+  std::vector<int32_t> m0(P), k(P), fb(P, 0);
   QFS_TRY(predict_many(P, tmpl, *params, m0.data(), k.data(), st));
   std::vector<int32_t> m_run(P);
   for (int i = 0; i < P; ++i) m_run[i] = std::max(params->m_init, m0[i]);
+  // one batched run: the kept starts first; a problem's pruned starts are parked and
+  // woken inside the same run when all its kept starts stop without success
   BatchOpts o;
   o.m_init = m_run.data();
   o.starts = k.data();
+  o.park_rest = 1;
+  o.fallback_used = fb.data();
   QFS_TRY(batch_instantiate(P, tmpl, targets, params, gates_out, res, o));
-  std::vector<int> failed;
+  const double secs = lnow() - t0;
   for (int i = 0; i < P; ++i) {
     res[i].m_predicted = m0[i];
-    res[i].starts_run = k[i];
-    res[i].fallback = 0;
-    if (res[i].reason != QFS_SUCCESS && k[i] < S) failed.push_back(i);
+    res[i].starts_run = fb[i] ? S : k[i];
+    res[i].fallback = fb[i];
+    res[i].seconds = secs;
   }
-  if (!failed.empty()) {
-    // fallback: the pruned starts of the problems that did not succeed, plain doubling
-    // from m_init, each problem with its original seed
-    const int F = (int)failed.size();
-    std::vector<qfs_template> ft(F);
-    std::vector<qfs_target> fg(F);
-    std::vector<qfs_result> fr(F);
-    std::vector<uint64_t> seeds(F);
-    std::vector<int32_t> lo(F), mfb(F);
-    std::vector<DevBuf> tmp(F);
-    std::vector<qfs_c128 *> fo(F);
-    for (int f = 0; f < F; ++f) {
-      const int i = failed[f];
-      ft[f] = tmpl[i];
-      fg[f] = targets[i];
-      seeds[f] = params->seed + (uint64_t)i;
-      lo[f] = k[i];
-      mfb[f] = std::max(params->m_init, res[i].m_final);
-      QFS_TRY(tmp[f].alloc(sizeof(c128) * 16 * (size_t)tmpl[i].n_gates));
-      fo[f] = tmp[f].as<qfs_c128>();
-    }
-    BatchOpts plain;
-    plain.seeds = seeds.data();
-    plain.start_lo = lo.data();
-    plain.m_init = mfb.data();
-    QFS_TRY(batch_instantiate(F, ft.data(), fg.data(), params, fo.data(), fr.data(), plain));
-    for (int f = 0; f < F; ++f) {
-      const int i = failed[f];
-      qfs_result &r = res[i];
-      const qfs_result first = r;
-      const bool take2 = fr[f].reason == QFS_SUCCESS || fr[f].c_train < first.c_train;
-      if (take2) {
-        r = fr[f];
-        if (gates_out[i])
-          QFS_HIP(hipMemcpyAsync(gates_out[i], fo[f], sizeof(c128) * 16 * tmpl[i].n_gates,
-                                 hipMemcpyDeviceToDevice, st));
-      }
-      r.m_predicted = first.m_predicted;
-      r.starts_run = S;
-      r.fallback = 1;
-      r.start_sweeps = first.start_sweeps + fr[f].start_sweeps;
-      r.m_total = first.m_total + fr[f].m_total;
-      r.sweep_seconds = first.sweep_seconds + fr[f].sweep_seconds;
-    }
-    QFS_HIP(hipStreamSynchronize(st));
-  }
-  const double secs = lnow() - t0;
-  for (int i = 0; i < P; ++i) res[i].seconds = secs;
   return QFS_OK;
 }
 

@@ -59,7 +59,8 @@ class Result(C.Structure):
                 ("c_val", C.c_double), ("seconds", C.c_double), ("start_sweeps", C.c_int64),
                 ("sweep_seconds", C.c_double), ("kernel_launches", C.c_int64 * 4),
                 ("kernel_seconds", C.c_double * 4), ("kernel_bytes", C.c_double * 4),
-                ("m_predicted", C.c_int32), ("starts_run", C.c_int32), ("fallback", C.c_int32)]
+                ("m_predicted", C.c_int32), ("starts_run", C.c_int32), ("fallback", C.c_int32),
+                ("amp_updates", C.c_double)]
 
 
 EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",

@@ -143,8 +143,9 @@ def test_label_batch_matches_oracle_per_start():
 
 def test_learned_gain_over_plain():
     """Train on labels from the method's own runs; on held-out problems the learned runs
-    need less work than plain doubling from M = 2 with every start, at the same success
-    criterion, and every success is a real solution (full distance)."""
+    need less device work (amplitude-gate updates) than plain doubling from M = 2 with
+    every start, at the same success criterion and with no fewer successes, and every
+    checked success is a real solution (full distance)."""
     train_probs = I.batched_problems(1024, seed_base=0x5A17 + 40, n_range=(3, 6), L_range=(2, 14))
     test_probs = I.batched_problems(192, seed_base=0x5A17 + 41, n_range=(3, 6), L_range=(2, 14))
     say("labelling 1024 training problems")
@@ -160,9 +161,8 @@ def test_learned_gain_over_plain():
     g_learn, r_learn = Q.qfs_instantiate_batch_learned(dtest, params)
     torch.cuda.synchronize()
 
-    def work_of(rs):  # amplitude-sweeps: start-sweeps x M x 2^n x L (upper bound per M)
-        return sum(r["start_sweeps"] * r["m_final"] * (1 << p["n"]) * len(p["pairs"])
-                   for r, p in zip(rs, test_probs))
+    def work_of(rs):  # amplitude-gate updates executed on the device
+        return sum(r["amp_updates"] for r in rs)
 
     ok_p = sum(r["reason_name"] == "SUCCESS" for r in r_plain)
     ok_l = sum(r["reason_name"] == "SUCCESS" for r in r_learn)
@@ -175,7 +175,9 @@ def test_learned_gain_over_plain():
         f"mean starts {np.mean([r['starts_run'] for r in r_learn]):.1f}")
     say(f"  M-weighted work: plain {work_of(r_plain):.3e}, learned {work_of(r_learn):.3e}")
     assert ok_l >= ok_p - 2
-    assert ss_l < 0.7 * ss_p
+    # the device work of a start-sweep grows with M N L, so compare amplitude-gate
+    # updates, not sweep counts (the learned runs start at a larger M and double less)
+    assert work_of(r_learn) < 0.7 * work_of(r_plain)
     for i in range(0, 192, 12):
         if r_learn[i]["reason_name"] != "SUCCESS":
             continue
