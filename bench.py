@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-distance runs")
     ap.add_argument("--timing", type=int, default=1)
-    ap.add_argument("--graphs", type=int, default=1, help="replay sweeps from HIP graphs (params.graphs)")
+    ap.add_argument("--graphs", type=int, default=0, help="replay sweeps from HIP graphs (params.graphs)")
     ap.add_argument("--batched", type=int, default=4096,
                     help="problems in the batched workload (0 skips it)")
     ap.add_argument("--plain-sample", type=int, default=48,
@@ -113,7 +113,7 @@ def cpu_baseline(w, M, starts):
                       f"(one thread each), 12 qubits, 44 gates, M={M}, complex128; {dt:.1f} s"}
 
 
-def time_to_distance(dev, graphs=1):
+def time_to_distance(dev, graphs=0):
     """Time-to-distance 1e-8 (App. A defaults, MIXED with FP64 refinement) on the
     8-qubit brickwork (21 gates, M = 32, one start: the plain single-problem case)
     and with 16 starts."""

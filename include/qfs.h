@@ -121,10 +121,11 @@ typedef struct {
   int32_t batch_threads;     /* qfs_instantiate_batch: work-group size 64, 128 or 256
                                 (0 = chosen by the built-in autotuner, cached per
                                 precision and state-size class for the process)     */
-  int32_t graphs;            /* qfs_instantiate: 1 (default) replays each sweep's
-                                launches as a captured HIP graph on an internal
-                                stream (re-captured when the running starts, M or
-                                the precision change); 0 launches every kernel     */
+  int32_t graphs;            /* qfs_instantiate: 1 replays each sweep's launches as
+                                a captured HIP graph on an internal stream
+                                (re-captured when the running starts, M or the
+                                precision change); 0 (default) launches every
+                                kernel, which measured faster on MI355X / ROCm 7   */
 } qfs_params;
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,
@@ -297,7 +298,8 @@ int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target,
 /* The same for qfs_instantiate_batch, in one batched run: each problem starts with its
  * predicted M and kept starts; its pruned starts are parked and woken inside the run
  * (from the problem's current training set, their own initial gates) as soon as every
- * kept start has stopped without success. fallback = 1 when that happened. */
+ * kept start has stopped without success, or for every problem at once when fewer jobs
+ * than two per compute unit are left running. fallback = 1 when they were woken. */
 int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl,
                                   const qfs_target *targets, const qfs_params *params,
                                   qfs_c128 *const *gates_out, qfs_result *res);

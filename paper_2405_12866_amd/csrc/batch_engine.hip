@@ -591,6 +591,25 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         finish(w, -1);
       }
     }
+    if (opts.park_rest) {
+      // parked starts cost nothing once the device runs out of other work: when fewer
+      // jobs than two per compute unit are left, wake every parked start at once
+      size_t runnable = 0;
+      for (size_t j = 0; j < njobs_all; ++j)
+        runnable += !finished[jobs[j].prob] && jobs[j].status == BJ_RUN;
+      if (runnable < 2 * (size_t)kCUs) {
+        for (size_t j = 0; j < njobs_all; ++j) {
+          BJob &J = jobs[j];
+          if (finished[J.prob] || J.status != BJ_PARKED) continue;
+          J.status = BJ_RUN;
+          J.iter = 0;
+          J.z = 0;
+          J.need_c0 = 1;
+          J.fp64 = p.precision == QFS_PREC_FP64 ? 1 : 0;
+          if (opts.fallback_used) opts.fallback_used[J.prob] = 1;
+        }
+      }
+    }
     if (probs_dirty) {
       QFS_HIP(hipMemcpyAsync(dprobs.ptr, hp.data(), sizeof(BProb) * P, hipMemcpyHostToDevice, st));
       QFS_HIP(hipMemcpyAsync(dtodo.ptr, todo.data(), sizeof(int32_t) * todo.size(), hipMemcpyHostToDevice, st));

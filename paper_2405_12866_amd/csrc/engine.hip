@@ -962,7 +962,7 @@ void qfs_default_params(qfs_params *p) {
   p->timing = 0;
   p->batch_sweeps = 0;
   p->batch_threads = 0;
-  p->graphs = 1;
+  p->graphs = 0;
 }
 
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
