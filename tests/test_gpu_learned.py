@@ -147,7 +147,7 @@ def test_learned_gain_over_plain():
     every start, at the same success criterion and with no fewer successes, and every
     checked success is a real solution (full distance)."""
     train_probs = I.batched_problems(1024, seed_base=0x5A17 + 40, n_range=(3, 6), L_range=(2, 14))
-    test_probs = I.batched_problems(192, seed_base=0x5A17 + 41, n_range=(3, 6), L_range=(2, 14))
+    test_probs = I.batched_problems(768, seed_base=0x5A17 + 41, n_range=(3, 6), L_range=(2, 14))
     say("labelling 1024 training problems")
     T, work = PR.label(PR.device_problems(train_probs, DEV), log=say)
     X = PR.features(train_probs)
@@ -169,16 +169,16 @@ def test_learned_gain_over_plain():
     ss_p = sum(r["start_sweeps"] for r in r_plain)
     ss_l = sum(r["start_sweeps"] for r in r_learn)
     fb = sum(r["fallback"] for r in r_learn)
-    say(f"  plain: {ok_p}/192 ok, {ss_p} start-sweeps, {r_plain[0]['seconds']:.2f} s")
-    say(f"  learned: {ok_l}/192 ok, {ss_l} start-sweeps, {r_learn[0]['seconds']:.2f} s, "
+    say(f"  plain: {ok_p}/768 ok, {ss_p} start-sweeps, {r_plain[0]['seconds']:.2f} s")
+    say(f"  learned: {ok_l}/768 ok, {ss_l} start-sweeps, {r_learn[0]['seconds']:.2f} s, "
         f"{fb} fallbacks, mean predicted M {np.mean([r['m_predicted'] for r in r_learn]):.1f}, "
         f"mean starts {np.mean([r['starts_run'] for r in r_learn]):.1f}")
     say(f"  M-weighted work: plain {work_of(r_plain):.3e}, learned {work_of(r_learn):.3e}")
-    assert ok_l >= ok_p - 2
+    assert ok_l >= ok_p - 8
     # the device work of a start-sweep grows with M N L, so compare amplitude-gate
     # updates, not sweep counts (the learned runs start at a larger M and double less)
     assert work_of(r_learn) < 0.8 * work_of(r_plain)
-    for i in range(0, 192, 12):
+    for i in range(0, 768, 48):
         if r_learn[i]["reason_name"] != "SUCCESS":
             continue
         p = test_probs[i]
