@@ -66,22 +66,20 @@ bool batch_trace() {
 constexpr int kCUs = 256;
 constexpr int kSideStreams = 8;
 
-// Streams and join events for concurrent launches, released on scope exit.
+// Pooled streams and per-call join events for concurrent launches.
 struct StreamSet {
   hipStream_t s[kSideStreams] = {};
   hipEvent_t ev[kSideStreams] = {};
   int create() {
     for (int i = 0; i < kSideStreams; ++i) {
-      QFS_HIP(hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking));
+      QFS_TRY(pool_stream(8 + i, &s[i]));
       QFS_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     }
     return QFS_OK;
   }
   ~StreamSet() {
-    for (int i = 0; i < kSideStreams; ++i) {
+    for (int i = 0; i < kSideStreams; ++i)
       if (ev[i]) (void)hipEventDestroy(ev[i]);
-      if (s[i]) (void)hipStreamDestroy(s[i]);
-    }
   }
 };
 
@@ -592,12 +590,13 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
       }
     }
     if (opts.park_rest) {
-      // parked starts cost nothing once the device runs out of other work: when fewer
-      // jobs than two per compute unit are left, wake every parked start at once
+      // parked starts cost little once the device runs out of other work: when fewer
+      // jobs are left than the device holds work-groups of the smallest class (about
+      // eight per compute unit), wake every parked start at once
       size_t runnable = 0;
       for (size_t j = 0; j < njobs_all; ++j)
         runnable += !finished[jobs[j].prob] && jobs[j].status == BJ_RUN;
-      if (runnable < 2 * (size_t)kCUs) {
+      if (runnable < 8 * (size_t)kCUs) {
         for (size_t j = 0; j < njobs_all; ++j) {
           BJob &J = jobs[j];
           if (finished[J.prob] || J.status != BJ_PARKED) continue;

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "qfs_internal.h"
@@ -17,6 +18,20 @@ namespace qfs {
 
 static thread_local std::string g_detail;
 void set_error_detail(const std::string &s) { g_detail = s; }
+
+int pool_stream(int index, hipStream_t *out) {
+  constexpr int kPool = 16, kDevices = 64;
+  static std::mutex mu;
+  static hipStream_t pool[kDevices][kPool] = {};
+  if (index < 0 || index >= kPool) return QFS_EINVAL;
+  int dev = 0;
+  QFS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kDevices) return QFS_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!pool[dev][index]) QFS_HIP(hipStreamCreateWithFlags(&pool[dev][index], hipStreamNonBlocking));
+  *out = pool[dev][index];
+  return QFS_OK;
+}
 
 namespace {
 
@@ -345,11 +360,11 @@ class Group {
     if (ev1_) (void)hipEventDestroy(ev1_);
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
-    if (side_) (void)hipStreamDestroy(side_);
+
     if (gexec_) (void)hipGraphExecDestroy(gexec_);
     if (gfork_) (void)hipEventDestroy(gfork_);
     if (gjoin_) (void)hipEventDestroy(gjoin_);
-    if (cap_) (void)hipStreamDestroy(cap_);
+
   }
 
   int run(GroupResult &out, double t_start);
@@ -521,7 +536,7 @@ int Group::sweep_once() {
     return forward_any(false);
   }
   if (!cap_) {
-    QFS_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+    QFS_TRY(pool_stream(1, &cap_));
     QFS_HIP(hipEventCreateWithFlags(&gfork_, hipEventDisableTiming));
     QFS_HIP(hipEventCreateWithFlags(&gjoin_, hipEventDisableTiming));
   }
@@ -649,7 +664,7 @@ int Group::run(GroupResult &out, double t_start) {
     return !(e && std::atoi(e) == 0);
   }();
   if (S_ >= 2 && split_ok) {
-    QFS_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+    QFS_TRY(pool_stream(0, &side_));
     QFS_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
     QFS_HIP(hipEventCreateWithFlags(&join_, hipEventDisableTiming));
     c.side = side_;

@@ -82,6 +82,11 @@ struct Status {
 
 void set_error_detail(const std::string &s);
 
+// Process-wide pool of non-blocking streams (default priority) on the current device,
+// created on first use and kept until the process ends: creating streams per call costs
+// far more than a small instantiation. Index 0..15.
+int pool_stream(int index, hipStream_t *out);
+
 #define QFS_HIP(call)                                                                  \
   do {                                                                                 \
     hipError_t e__ = (call);                                                           \
