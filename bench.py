@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-distance runs")
     ap.add_argument("--timing", type=int, default=1)
     ap.add_argument("--graphs", type=int, default=0, help="replay sweeps from HIP graphs (params.graphs)")
+    ap.add_argument("--bwd-split", type=int, default=1,
+                    help="0: run the backward pass of all starts on one stream in every call (the "
+                         "instrumented call always does), so every step launch covers all starts, "
+                         "as needed to compare a profiler's per-launch averages with the roofline")
     ap.add_argument("--batched", type=int, default=4096,
                     help="problems in the batched workload (0 skips it)")
     ap.add_argument("--plain-sample", type=int, default=48,
@@ -258,6 +262,8 @@ def main():
               f"(asked for --gpus {args.gpus}); problems and multistarts are independent, "
               f"see the sharding notes in DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    if not args.bwd_split:
+        os.environ["QFS_BWD_SPLIT"] = "0"  # read once by the library when it first runs
     import torch
 
     from paper_2405_12866_amd import inputs as I

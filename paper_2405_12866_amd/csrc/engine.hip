@@ -284,7 +284,10 @@ int sweep_backward(SweepCtx &c) {
   KernelTimer &T = *c.timer;
   // halves of the active starts, each on its own stream (one half when timing or when
   // a single start runs)
-  const bool split = !T.on && c.side && c.nslots >= 2;
+  // (only worth it when each half still streams at least 2^20 amplitudes per step;
+  // small problems are launch-bound and would pay twice the launches)
+  const bool split = !T.on && c.side && c.nslots >= 2 &&
+                     (int64_t)(c.nslots / 2) * c.g.elems() >= (int64_t(1) << 20);
   const int halves = split ? 2 : 1;
   const int h0 = split ? c.nslots / 2 : c.nslots;
   const int32_t *hslots[2] = {c.slots, c.slots + h0};

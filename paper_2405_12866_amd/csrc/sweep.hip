@@ -1009,10 +1009,13 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
     const char *e = std::getenv("QFS_FWD_COALESCE");  // 0: always store from registers
     return e ? std::atoi(e) : 1;
   }();
-  static const int fwd_threads = [] {
-    const char *e = std::getenv("QFS_FWD_THREADS");  // work-group size: 1024 (default) or 512
-    return (e && std::atoi(e) == 512) ? 512 : 1024;
+  static const int fwd_env = [] {
+    const char *e = std::getenv("QFS_FWD_THREADS");  // work-group size: 512 or 1024 (0: by size)
+    return e ? std::atoi(e) : 0;
   }();
+  // 1024 threads once every thread has at least two gate groups per gate, else 512
+  const int64_t groups = int64_t(1) << (g.n - 2 + g.logC - (sizeof(R) == 4 ? 1 : 0));
+  const int fwd_threads = fwd_env == 512 || fwd_env == 1024 ? fwd_env : (groups >= 2048 ? 1024 : 512);
   auto go = [&](auto kernel, int threads) -> int {
     static size_t attr_bytes = 0;  // dynamic LDS above 64 KB must be requested per kernel
     if (lds > 64 * 1024 && lds > attr_bytes) {
