@@ -226,6 +226,7 @@ def learned(dev, count, large):
             dt = time.perf_counter() - t0
             rows[name] = {"wall_s": round(dt, 3), "successes": sum(r["reason_name"] == "SUCCESS" for r in infos),
                           "start_sweeps": sum(r["start_sweeps"] for r in infos),
+                          "amp_updates": sum(r["amp_updates"] for r in infos),
                           "doublings": sum(r["restarts"] for r in infos)}
             if name == "learned":
                 rows[name]["fallbacks"] = sum(r["fallback"] for r in infos)
@@ -233,6 +234,7 @@ def learned(dev, count, large):
                 rows[name]["mean_m_predicted"] = round(sum(r["m_predicted"] for r in infos) / count, 2)
         rows["problems"] = count
         rows["time_to_solution_speedup"] = round(rows["plain"]["wall_s"] / rows["learned"]["wall_s"], 2)
+        rows["work_ratio"] = round(rows["learned"]["amp_updates"] / max(1.0, rows["plain"]["amp_updates"]), 3)
         out["held_out"] = rows
     if large > 0:
         g = I.rng(I.derive_seed(0x5A17 + 7))
