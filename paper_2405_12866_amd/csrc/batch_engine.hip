@@ -66,6 +66,20 @@ bool batch_trace() {
 constexpr int kCUs = 256;
 constexpr int kSideStreams = 8;
 
+// Timing events of one call, released on every return path.
+struct TimingEvents {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int create() {
+    QFS_HIP(hipEventCreate(&e0));
+    QFS_HIP(hipEventCreate(&e1));
+    return QFS_OK;
+  }
+  ~TimingEvents() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
 // Pooled streams and per-call join events for concurrent launches.
 struct StreamSet {
   hipStream_t s[kSideStreams] = {};
@@ -309,9 +323,9 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
   for (int i = 0; i < P; ++i) m_total[i] = hp[i].M;
   int remaining = P;
   double kernel_seconds = 0.0;
-  hipEvent_t e0, e1;
-  QFS_HIP(hipEventCreate(&e0));
-  QFS_HIP(hipEventCreate(&e1));
+  TimingEvents tev;
+  QFS_TRY(tev.create());
+  hipEvent_t e0 = tev.e0, e1 = tev.e1;
   // side streams for concurrent class launches (default priority)
   StreamSet streams;
   QFS_TRY(streams.create());
@@ -618,8 +632,6 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     QFS_HIP(hipMemcpyAsync(djobs.ptr, jobs.data(), sizeof(BJob) * njobs_all, hipMemcpyHostToDevice, st));
     QFS_HIP(hipStreamSynchronize(st));
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
 
   // ---------------------------------------------------------------- results
   const double secs = bnow() - t0;
