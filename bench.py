@@ -260,9 +260,9 @@ def learned(dev, count, large):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(asked for --gpus {args.gpus}); problems and multistarts are independent, "
-              f"see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              f"has no multi-GPU path; problems and multistarts are independent and one GPU "
+              f"runs them all", file=sys.stderr)
         sys.exit(2)
     if not args.bwd_split:
         os.environ["QFS_BWD_SPLIT"] = "0"  # read once by the library when it first runs

@@ -242,7 +242,7 @@ def test_instantiate_samples_minimal_entry():
 
 def test_instantiate_mixed_reaches_distance_after_refinement():
     """MIXED precision: complex64 sweeps, then complex128 refinement below 1e-5; the
-    returned gates reach d_full <= 1e-8, judged by the oracle's own dense product."""
+    returned gates reach d_full <= 1e-8, checked by the oracle's own dense product."""
     say("instantiate mixed 6 qubits")
     n = 6
     pairs = I.brickwork_template(n, 4)
