@@ -46,7 +46,7 @@ enum {
                            M > 2^n, non-finite or non-unitary input gate, ...        */
   QFS_ENOMEM = 2,       /* does not fit the device-memory budget even with one start */
   QFS_EDEVICE = 3,      /* a HIP runtime error; see qfs_last_error_detail()          */
-  QFS_EUNSUPPORTED = 4, /* a combination this build does not implement               */
+  QFS_EUNSUPPORTED = 4, /* a combination the library does not implement             */
   QFS_ENUMERIC = 5      /* orthonormalisation of a drawn sample set failed            */
 };
 
