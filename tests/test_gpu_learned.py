@@ -186,3 +186,33 @@ def test_learned_gain_over_plain():
         d = O.state_distance(p["n"], O.apply_circuit(p["n"], basis, p["pairs"], g_learn[i].cpu().numpy()),
                              O.apply_circuit(p["n"], basis, p["target_pairs"], p["target_gates"]))
         assert d <= 1e-8, (i, d)
+
+
+def test_learned_single_problem_entry_with_shipped_weights():
+    """The shipped weight file drives qfs_instantiate_learned (plain engine): the predicted
+    M and start count agree between the single and batched prediction calls, a success is
+    a real solution, and the counters cover the runs that took place."""
+    Q.qfs_mlp_load(PR.DEFAULT_WEIGHTS)
+    probs = I.batched_problems(6, seed_base=0x5A17 + 42, n_range=(3, 5), L_range=(2, 6))
+    m0s, ks = Q.qfs_predict_batch([(p["n"], p["pairs"]) for p in probs], dict(multistarts=16))
+    ok = 0
+    for i, p in enumerate(probs):
+        m0, mask = Q.qfs_predict_m(p["n"], p["pairs"], dict(multistarts=16))
+        assert m0 == m0s[i] and mask == (1 << int(ks[i])) - 1
+        assert 2 <= m0 <= (1 << p["n"]) and (m0 & (m0 - 1)) == 0
+        params = dict(multistarts=16, seed=300 + i, max_iter=1500, dist_tol=1e-9)
+        g, info = Q.qfs_instantiate_learned(p["n"], p["pairs"], target_pairs=p["target_pairs"],
+                                            target_gates=torch.as_tensor(p["target_gates"]).to(DEV),
+                                            params=params)
+        say(f"  problem {i}: n={p['n']} L={len(p['pairs'])} M0={m0} k={ks[i]} -> "
+            f"{info['reason_name']} fallback={info['fallback']} starts_run={info['starts_run']}")
+        assert info["m_predicted"] == m0
+        assert info["starts_run"] == (16 if info["fallback"] else int(ks[i]))
+        assert info["m_final"] >= m0 or info["fallback"]
+        if info["reason_name"] == "SUCCESS":
+            ok += 1
+            basis = np.eye(1 << p["n"], dtype=np.complex128)
+            d = O.state_distance(p["n"], O.apply_circuit(p["n"], basis, p["pairs"], g.cpu().numpy()),
+                                 O.apply_circuit(p["n"], basis, p["target_pairs"], p["target_gates"]))
+            assert d <= 1e-8, (i, d)
+    assert ok >= 4
