@@ -573,7 +573,9 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
           js[s].status = BJ_RUN;
           any_run = true;
         }
-        if (timed_out && js[s].status == BJ_RUN) js[s].status = BJ_TIMEOUT;
+        // out of time: every start not already stopped for a reason of its own stops
+        // with TIMEOUT (running, waiting for a doubling, or paused)
+        if (timed_out && !terminal(js[s].status) && js[s].status != BJ_PARKED) js[s].status = BJ_TIMEOUT;
       }
       if (timed_out) any_run = false;
       if (!any_run && !timed_out) {
