@@ -299,7 +299,7 @@ int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target,
  * predicted M and kept starts; its pruned starts are parked and woken inside the run
  * (from the problem's current training set, their own initial gates) as soon as every
  * kept start has stopped without success, or for every problem at once when fewer jobs
- * than eight per compute unit are left running (the device would otherwise idle).
+ * than two per compute unit are left running (the device would otherwise idle).
  * fallback = 1 when they were woken. */
 int qfs_instantiate_batch_learned(int32_t P, const qfs_template *tmpl,
                                   const qfs_target *targets, const qfs_params *params,
