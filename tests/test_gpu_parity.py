@@ -228,7 +228,7 @@ def test_instantiate_fp64_matches_oracle_control_flow():
 
 
 def test_instantiate_samples_minimal_entry():
-    say("instantiate_samples (north-star minimal entry)")
+    say("instantiate_samples (minimal entry)")
     pairs = [(0, 1), (1, 2), (0, 2)]
     g = np.random.default_rng(8)
     tg = I.haar_gates(3, g)

@@ -370,7 +370,7 @@ def test_success_implies_small_loss_on_fresh_states():
 
 
 def test_samples_target_matches_circuit_target():
-    """A fixed sample set (the spec minimal entry) drives the same sweeps as the
+    """A fixed sample set (the minimal entry point) drives the same sweeps as the
     circuit target when it holds the same states."""
     w = I.workload_3q()
     psi = O.draw_states(3, 4, seed=21)
