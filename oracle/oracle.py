@@ -21,6 +21,7 @@ _lib = None
 
 ROLE_TRAIN, ROLE_VAL, ROLE_INIT = 1, 2, 3
 TARGET_DENSE, TARGET_CIRCUIT, TARGET_SAMPLES = 0, 1, 2
+GATE_2Q, GATE_1Q, GATE_FIXED = 0, 1, 2
 REASONS = {0: "SUCCESS", 1: "PLATEAU", 2: "MAX_ITER", 3: "NOT_GENERALIZED", 4: "TIMEOUT"}
 
 
@@ -110,18 +111,22 @@ def load():
         lib.qo_draw_states.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, P]
         lib.qo_draw_states.restype = C.c_int
         lib.qo_haar_gate.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P]
+        lib.qo_haar_gate2.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P]
+        lib.qo_initial_gate.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int, P, P]
         lib.qo_apply_gate.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_int, P]
         lib.qo_apply_gate_dag.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_int, P]
         lib.qo_apply_circuit.argtypes = [C.c_int, C.c_int, P, C.c_int, P, P]
         lib.qo_dense_apply.argtypes = [C.c_int, C.c_int, P, P, P]
         lib.qo_environment.argtypes = [C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
+        lib.qo_environment1.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P]
         lib.qo_svd4.argtypes = [P, P, P, P]
         lib.qo_update_gate.argtypes = [P, C.c_double, P]
+        lib.qo_update_gate1.argtypes = [P, C.c_double, P]
         lib.qo_state_distance.argtypes = [C.c_int, C.c_int, P, P]
         lib.qo_state_distance.restype = C.c_double
-        lib.qo_sweep.argtypes = [C.c_int, C.c_int, P, C.c_int, P, P, P, C.c_double, P, P, P]
+        lib.qo_sweep.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, C.c_double, P, P, P]
         lib.qo_sweep.restype = C.c_double
-        lib.qo_instantiate.argtypes = [C.c_int, C.c_int, P, C.c_int, P, C.c_int, P, P, P, P,
+        lib.qo_instantiate.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, C.c_int, P, P, P, P,
                                        C.c_int, C.c_int, C.POINTER(Params), P, P,
                                        C.POINTER(Result), C.POINTER(Trace)]
         lib.qo_instantiate.restype = C.c_int
@@ -182,6 +187,36 @@ def haar_gate(seed, start, gate):
     return u
 
 
+def haar_gate2(seed, start, gate):
+    v = np.zeros((2, 2), dtype=np.complex128)
+    load().qo_haar_gate2(seed, start, gate, _p(v))
+    return v
+
+
+def _kinds(kinds, L):
+    if kinds is None:
+        return None
+    k = np.ascontiguousarray(np.asarray(kinds, dtype=np.int32).reshape(-1))
+    if k.shape[0] != L:
+        raise ValueError("kinds needs one entry per gate")
+    return k
+
+
+def initial_gates(seed, start, kinds, fixed=None):
+    """Initial [L][4][4] slots of one start by gate kind."""
+    k = _kinds(kinds, len(kinds))
+    fx = None if fixed is None else _c128(fixed)
+    out = np.zeros((k.shape[0], 4, 4), dtype=np.complex128)
+    for i in range(k.shape[0]):
+        load().qo_initial_gate(seed, start, i, int(k[i]), _p(fx), _p(out[i]))
+    return out
+
+
+def kron_i2(v):
+    """The 4x4 slot of a one-qubit gate v: v (x) I_2."""
+    return np.kron(np.asarray(v, dtype=np.complex128), np.eye(2))
+
+
 def apply_gate(n, states, qa, qb, u, dagger=False):
     st = _c128(states).copy()
     M = st.shape[0]
@@ -213,6 +248,20 @@ def environment(n, a, b, qa, qb):
     return G
 
 
+def environment1(n, a, b, qa):
+    aa, bb = _c128(a), _c128(b)
+    G = np.zeros((2, 2), dtype=np.complex128)
+    load().qo_environment1(n, aa.shape[0], _p(aa), _p(bb), qa, _p(G))
+    return G
+
+
+def update_gate1(G, beta=0.0, u=None):
+    """One-qubit update; u is the 4x4 slot v (x) I_2 (read when beta != 0)."""
+    uu = np.zeros((4, 4), dtype=np.complex128) if u is None else _c128(u).copy()
+    load().qo_update_gate1(_p(_c128(G)), beta, _p(uu))
+    return uu
+
+
 def svd4(G):
     g = _c128(G)
     W = np.zeros((4, 4), dtype=np.complex128)
@@ -233,17 +282,18 @@ def state_distance(n, x, y):
     return load().qo_state_distance(n, xx.shape[0], _p(xx), _p(yy))
 
 
-def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False):
+def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False, kinds=None):
     """One sweep; returns (new_gates, c_train) or, with record, also f_before, f_after
-    and the environments."""
+    and the environments. kinds: per-gate GATE_2Q / GATE_1Q / GATE_FIXED (None: all 2Q)."""
     pr = _pairs(pairs)
     L = pr.shape[0]
+    kd = _kinds(kinds, L)
     g = _c128(gates).copy()
     ps, ph = _c128(psi), _c128(phi)
     fb = np.zeros(L) if record else None
     fa = np.zeros(L) if record else None
     gam = np.zeros((L, 4, 4), dtype=np.complex128) if record else None
-    c = load().qo_sweep(n, L, _p(pr), ps.shape[0], _p(ps), _p(ph), _p(g), beta, _p(fb),
+    c = load().qo_sweep(n, L, _p(pr), _p(kd), ps.shape[0], _p(ps), _p(ph), _p(g), beta, _p(fb),
                         _p(fa), _p(gam))
     if record:
         return g, c, fb, fa, gam
@@ -251,13 +301,18 @@ def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False):
 
 
 def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=None,
-                phi=None, n_val=0, params=None, gates_in=None, trace_capacity=0):
+                phi=None, n_val=0, params=None, gates_in=None, trace_capacity=0, kinds=None,
+                fixed=None):
     """Full QFactor-Sample instantiation. Exactly one target form: dense ``U``, a target
     circuit (``target_pairs`` + ``target_gates``), or fixed samples ``psi``/``phi``
-    whose last ``n_val`` rows are the validation set. Returns (gates, result dict)."""
+    whose last ``n_val`` rows are the validation set. ``kinds`` and ``fixed`` ([L][4][4],
+    read for fixed gates) describe a template with one-qubit and constant gates.
+    Returns (gates, result dict)."""
     lib = load()
     pr = _pairs(pairs)
     L = pr.shape[0]
+    kd = _kinds(kinds, L)
+    fx = None if fixed is None else _c128(fixed)
     par = Params(**(params or default_params()))
     keep = []
     if U is not None:
@@ -293,7 +348,7 @@ def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=N
                    bufs["m"].ctypes.data_as(C.POINTER(C.c_int32)),
                    bufs["c_train"].ctypes.data_as(C.POINTER(C.c_double)),
                    bufs["c_val"].ctypes.data_as(C.POINTER(C.c_double)))
-    rc = lib.qo_instantiate(n, L, _p(pr), kind, *args, C.byref(par), _p(gi), _p(out),
+    rc = lib.qo_instantiate(n, L, _p(pr), _p(kd), _p(fx), kind, *args, C.byref(par), _p(gi), _p(out),
                             C.byref(res), C.byref(tr) if tr is not None else None)
     if rc != 0:
         raise ValueError(f"qo_instantiate failed: {rc}")
@@ -308,6 +363,8 @@ def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=N
 __all__ = [
     "Params", "Result", "ROLE_TRAIN", "ROLE_VAL", "ROLE_INIT", "REASONS", "default_params",
     "philox4x32_10", "cgauss", "ginibre", "orthonormalize", "draw_states", "haar_gate",
-    "apply_gate", "apply_circuit", "dense_apply", "environment", "svd4", "update_gate",
+    "haar_gate2", "initial_gates", "kron_i2", "GATE_2Q", "GATE_1Q", "GATE_FIXED",
+    "apply_gate", "apply_circuit", "dense_apply", "environment", "environment1", "svd4",
+    "update_gate", "update_gate1",
     "state_distance", "sweep", "instantiate",
 ]

@@ -129,6 +129,39 @@ void qo_haar_gate(uint64_t seed, uint32_t start, uint32_t gate, qo_cplx u[16]) {
     for (int p = 0; p < 4; ++p) u[q * 4 + p] = cols[p * 4 + q];
 }
 
+/* Initial one-qubit gate: Haar on U(2) from a 2x2 Ginibre block of the same stream
+ * (indices 16*gate + 2*col + row), orthonormalised the same way. Row-major v[q][p]. */
+void qo_haar_gate2(uint64_t seed, uint32_t start, uint32_t gate, qo_cplx v[4]) {
+  qo_cplx cols[4]; /* column-major */
+  for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < 2; ++i)
+      cols[j * 2 + i] = qo_cgauss(seed, QO_ROLE_INIT, start, (uint64_t)gate * 16u + j * 2 + i);
+  qo_gram_schmidt_columns(2, 0, 2, cols);
+  for (int q = 0; q < 2; ++q)
+    for (int p = 0; p < 2; ++p) v[q * 2 + p] = cols[p * 2 + q];
+}
+
+/* v (x) I_2 in the local basis 2*bit(qa) + bit(qb): entry (2q + x, 2p + y) is
+ * v[q][p] when x = y, else 0. */
+static void qo_kron_i2(const qo_cplx v[4], qo_cplx u[16]) {
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      u[r * 4 + c] = ((r & 1) == (c & 1)) ? v[(r >> 1) * 2 + (c >> 1)] : 0.0;
+}
+
+void qo_initial_gate(uint64_t seed, uint32_t start, uint32_t gate, int kind,
+                     const qo_cplx *fixed, qo_cplx u[16]) {
+  if (kind == QO_GATE_FIXED) {
+    memcpy(u, fixed + 16 * (size_t)gate, sizeof(qo_cplx) * 16);
+  } else if (kind == QO_GATE_1Q) {
+    qo_cplx v[4];
+    qo_haar_gate2(seed, start, gate, v);
+    qo_kron_i2(v, u);
+  } else {
+    qo_haar_gate(seed, start, gate, u);
+  }
+}
+
 /* ------------------------------------------------------------------------------------
  * State simulation (Sec. 3, Fig. pre-comp: the B list holds C's intermediate states).
  * ---------------------------------------------------------------------------------- */
@@ -208,6 +241,22 @@ void qo_environment(int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, in
       qo_group_indices(n, qa, qb, i, idx);
       for (int q = 0; q < 4; ++q)
         for (int p = 0; p < 4; ++p) G[q * 4 + p] += a[j * N + idx[q]] * conj(b[j * N + idx[p]]);
+    }
+}
+
+/* Environment of a one-qubit gate on qubit qa (the same contraction with the gate's
+ * single qubit): the sum over every sample j and every index r of the other n-1 qubits
+ * of a_j(q, r) conj(b_j(p, r)). */
+void qo_environment1(int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, qo_cplx G[4]) {
+  const int64_t N = (int64_t)1 << n;
+  const int64_t ma = (int64_t)1 << (n - 1 - qa);
+  for (int e = 0; e < 4; ++e) G[e] = 0.0;
+  for (int64_t j = 0; j < M; ++j)
+    for (int64_t i = 0; i < N; ++i) {
+      if (i & ma) continue;
+      for (int q = 0; q < 2; ++q)
+        for (int p = 0; p < 2; ++p)
+          G[q * 2 + p] += a[j * N + i + q * ma] * conj(b[j * N + i + p * ma]);
     }
 }
 
@@ -346,6 +395,25 @@ void qo_update_gate(const qo_cplx G[16], double beta, qo_cplx u[16]) {
     }
 }
 
+/* Update of a one-qubit gate (the same rule for a 2x2 environment). With X the 2x2
+ * matrix (1-beta) G + beta v, the polar factor of the block-diagonal diag(X, I_2) is
+ * diag(polar(X), I_2) (the polar factor of an invertible matrix is unique, and a block
+ * diagonal SVD is one SVD of the whole), so the 4x4 routine gives polar(X) as its
+ * leading block. The slot keeps the form v (x) I_2. */
+void qo_update_gate1(const qo_cplx G[4], double beta, qo_cplx u[16]) {
+  qo_cplx X[16], P[16];
+  for (int e = 0; e < 16; ++e) X[e] = 0.0;
+  for (int q = 0; q < 2; ++q)
+    for (int p = 0; p < 2; ++p)
+      X[q * 4 + p] = (1.0 - beta) * G[q * 2 + p] + beta * u[(2 * q) * 4 + 2 * p];
+  X[10] = 1.0;
+  X[15] = 1.0;
+  for (int e = 0; e < 16; ++e) P[e] = 0.0;
+  qo_update_gate(X, 0.0, P);
+  qo_cplx v[4] = {P[0], P[1], P[4], P[5]};
+  qo_kron_i2(v, u);
+}
+
 /* (1/M) sum_j ||x_j - y_j||^2: the QFactor-Sample cost (Sec. 3, Eq. 9, left side). */
 double qo_state_distance(int n, int M, const qo_cplx *x, const qo_cplx *y) {
   const int64_t N = (int64_t)1 << n;
@@ -369,9 +437,18 @@ static double qo_re_tr_gdag_u(const qo_cplx G[16], const qo_cplx u[16]) {
  * updated, so every environment mixes updated (left of the gate in time order, i.e.
  * later in the circuit) and not-yet-updated gates. Returns the cost (Eq. 9) of the
  * updated gates, computed from a_0 = C^dagger U psi. */
-double qo_sweep(int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
-                const qo_cplx *phi, qo_cplx *gates, double beta, double *f_before,
-                double *f_after, qo_cplx *gammas) {
+static double qo_re_tr_gdag_v(const qo_cplx G[4], const qo_cplx u[16]) {
+  double acc = 0.0;
+  for (int q = 0; q < 2; ++q)
+    for (int p = 0; p < 2; ++p) acc += creal(conj(G[q * 2 + p]) * u[(2 * q) * 4 + 2 * p]);
+  return acc;
+}
+
+/* A fixed gate is applied on both passes and never updated; a one-qubit gate is
+ * updated from its 2x2 environment. */
+double qo_sweep(int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
+                const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
+                double *f_before, double *f_after, qo_cplx *gammas) {
   const int64_t N = (int64_t)1 << n;
   const int64_t S = (int64_t)M * N;
   qo_cplx *B = (qo_cplx *)malloc(sizeof(qo_cplx) * S * (size_t)L);
@@ -384,11 +461,23 @@ double qo_sweep(int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
   }
   memcpy(a, phi, sizeof(qo_cplx) * S);
   for (int k = L - 1; k >= 0; --k) {
+    const int kind = kinds ? kinds[k] : QO_GATE_2Q;
     qo_cplx G[16];
-    qo_environment(n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
-    if (f_before) f_before[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
-    qo_update_gate(G, beta, gates + 16 * k);
-    if (f_after) f_after[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
+    for (int e = 0; e < 16; ++e) G[e] = 0.0;
+    if (kind == QO_GATE_2Q) {
+      qo_environment(n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
+      if (f_before) f_before[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
+      qo_update_gate(G, beta, gates + 16 * k);
+      if (f_after) f_after[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
+    } else if (kind == QO_GATE_1Q) {
+      qo_environment1(n, M, a, B + (size_t)k * S, pairs[2 * k], G);
+      if (f_before) f_before[k] = qo_re_tr_gdag_v(G, gates + 16 * k);
+      qo_update_gate1(G, beta, gates + 16 * k);
+      if (f_after) f_after[k] = qo_re_tr_gdag_v(G, gates + 16 * k);
+    } else {
+      if (f_before) f_before[k] = NAN;
+      if (f_after) f_after[k] = NAN;
+    }
     if (gammas) memcpy(gammas + 16 * k, G, sizeof(G));
     qo_apply_gate_dag(n, M, a, pairs[2 * k], pairs[2 * k + 1], gates + 16 * k);
   }
@@ -438,7 +527,8 @@ static void qo_targets(int n, int kind, const qo_cplx *U, int Lt, const int32_t 
   }
 }
 
-int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind, const qo_cplx *U,
+int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
+                   const qo_cplx *fixed, int target_kind, const qo_cplx *U,
                    int Lt, const int32_t *tpairs, const qo_cplx *tgates,
                    const qo_cplx *samples_psi, const qo_cplx *samples_phi, int n_samples,
                    int n_val, const qo_params *p, const qo_cplx *gates_in,
@@ -448,6 +538,8 @@ int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind, const qo
   for (int k = 0; k < L; ++k) {
     int a = pairs[2 * k], b = pairs[2 * k + 1];
     if (a < 0 || b < 0 || a >= n || b >= n || a == b) return -1;
+    if (kinds && (kinds[k] < QO_GATE_2Q || kinds[k] > QO_GATE_FIXED)) return -1;
+    if (kinds && kinds[k] == QO_GATE_FIXED && !fixed) return -1;
   }
   const int64_t N = (int64_t)1 << n;
   const int S = p->multistarts > 0 ? p->multistarts : 1;
@@ -495,11 +587,14 @@ int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind, const qo
   qo_cplx *gates = (qo_cplx *)malloc(sizeof(qo_cplx) * 16 * (size_t)L * S);
   for (int s = 0; s < S; ++s)
     for (int k = 0; k < L; ++k) {
-      if (gates_in)
-        memcpy(gates + 16 * ((size_t)s * L + k), gates_in + 16 * ((size_t)s * L + k),
-               sizeof(qo_cplx) * 16);
+      const int kind = kinds ? kinds[k] : QO_GATE_2Q;
+      qo_cplx *u = gates + 16 * ((size_t)s * L + k);
+      if (kind == QO_GATE_FIXED)
+        memcpy(u, fixed + 16 * (size_t)k, sizeof(qo_cplx) * 16);
+      else if (gates_in)
+        memcpy(u, gates_in + 16 * ((size_t)s * L + k), sizeof(qo_cplx) * 16);
       else
-        qo_haar_gate(p->seed, (uint32_t)s, (uint32_t)k, gates + 16 * ((size_t)s * L + k));
+        qo_initial_gate(p->seed, (uint32_t)s, (uint32_t)k, kind, fixed, u);
     }
 
   int *status = (int *)calloc(S, sizeof(int));
@@ -526,7 +621,7 @@ int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind, const qo
     for (int s = 0; s < S; ++s) {
       if (status[s] != ST_RUNNING) continue;
       qo_cplx *g = gates + 16 * (size_t)s * L;
-      c_tr[s] = qo_sweep(n, L, pairs, M, psi, phi, g, p->beta, NULL, NULL, NULL);
+      c_tr[s] = qo_sweep(n, L, pairs, kinds, M, psi, phi, g, p->beta, NULL, NULL, NULL);
       c_v[s] = Mv > 0 ? qo_forward_cost(n, L, pairs, Mv, psiv, phiv, g) : c_tr[s];
     }
     const int full = (M == (int)N);

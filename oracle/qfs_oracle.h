@@ -36,6 +36,15 @@ enum { QO_ROLE_TRAIN = 1, QO_ROLE_VAL = 2, QO_ROLE_INIT = 3 };
 /* Target kinds. */
 enum { QO_TARGET_DENSE = 0, QO_TARGET_CIRCUIT = 1, QO_TARGET_SAMPLES = 2 };
 
+/* Gate kinds of a template (Sec. 2.1: QFactor updates gates of any size directly as
+ * unitaries; Sec. 4: the evaluated circuits hold U3 and CNOT gates).
+ *   QO_GATE_2Q:    variable two-qubit gate on (qa, qb), any 4x4 unitary.
+ *   QO_GATE_1Q:    variable one-qubit gate v on qubit qa; qb is a spectator qubit and the
+ *                  gate's 4x4 slot holds v (x) I_2 in the local basis of (qa, qb).
+ *   QO_GATE_FIXED: constant 4x4 gate on (qa, qb): applied, never updated.
+ * A NULL kinds array means every gate is QO_GATE_2Q. */
+enum { QO_GATE_2Q = 0, QO_GATE_1Q = 1, QO_GATE_FIXED = 2 };
+
 /* Termination reasons (the paper's termination kinds, Sec. 4 per-run runtimes). */
 enum {
   QO_SUCCESS = 0,
@@ -101,6 +110,12 @@ int qo_draw_states(int n, int M, uint64_t seed, uint32_t role, uint32_t stream,
                    qo_cplx *out /* [M][N] */);
 /* Haar-random 4x4 initial gate (App. A, multistarts and seed). */
 void qo_haar_gate(uint64_t seed, uint32_t start, uint32_t gate, qo_cplx u[16]);
+/* Haar-random 2x2 initial gate of a one-qubit gate, row-major. */
+void qo_haar_gate2(uint64_t seed, uint32_t start, uint32_t gate, qo_cplx v[4]);
+/* Initial 4x4 slot of gate `gate` of start `start` by kind: a Haar 4x4, v (x) I_2 with a
+ * Haar 2x2 v, or the constant gate fixed[gate] (fixed: [L][16], read for FIXED only). */
+void qo_initial_gate(uint64_t seed, uint32_t start, uint32_t gate, int kind,
+                     const qo_cplx *fixed, qo_cplx u[16]);
 
 void qo_apply_gate(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16]);
 void qo_apply_gate_dag(int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx u[16]);
@@ -110,20 +125,29 @@ void qo_dense_apply(int n, int M, const qo_cplx *U /*[N][N] row-major*/,
                     const qo_cplx *psi, qo_cplx *out);
 void qo_environment(int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, int qb,
                     qo_cplx G[16]);
+/* Environment of a one-qubit gate on qubit qa: G[q][p] = sum_j sum_r a_j(q,r) conj(b_j(p,r))
+ * over the other n-1 qubits r (2x2, row-major). */
+void qo_environment1(int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, qo_cplx G[4]);
 /* 4x4 complex SVD G = W diag(s) V^dagger by one-sided (Hestenes) Jacobi. */
 void qo_svd4(const qo_cplx G[16], qo_cplx W[16], double s[4], qo_cplx V[16]);
 /* Update of one gate: u <- polar((1-beta) Gamma + beta u). */
 void qo_update_gate(const qo_cplx G[16], double beta, qo_cplx u[16]);
+/* Update of a one-qubit gate stored as v (x) I_2 in u: v <- polar((1-beta) G + beta v). */
+void qo_update_gate1(const qo_cplx G[4], double beta, qo_cplx u[16]);
 double qo_state_distance(int n, int M, const qo_cplx *x, const qo_cplx *y);
 
 /* One sweep (forward B list, right-to-left update). Returns c_train after the sweep.
- * Optional outputs: per gate f before/after its update, and each Gamma. */
-double qo_sweep(int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
-                const qo_cplx *phi, qo_cplx *gates, double beta, double *f_before,
-                double *f_after, qo_cplx *gammas);
+ * kinds: [L] or NULL (all QO_GATE_2Q). Optional outputs: per gate f = Re Tr(G^dagger u)
+ * before/after its update (NaN for a fixed gate), and each environment G ([L][16]; a
+ * one-qubit gate's 2x2 in the first 4 entries, a fixed gate's all zero). */
+double qo_sweep(int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
+                const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
+                double *f_before, double *f_after, qo_cplx *gammas);
 
-/* Full instantiation with the paper's control loop. */
-int qo_instantiate(int n, int L, const int32_t *pairs, int target_kind,
+/* Full instantiation with the paper's control loop. kinds: [L] or NULL; fixed: [L][16]
+ * constant gates (read for QO_GATE_FIXED; replace those slots of gates_in too). */
+int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
+                   const qo_cplx *fixed, int target_kind,
                    const qo_cplx *U, int Lt, const int32_t *tpairs, const qo_cplx *tgates,
                    const qo_cplx *samples_psi, const qo_cplx *samples_phi, int n_samples,
                    int n_val, const qo_params *p, const qo_cplx *gates_in,

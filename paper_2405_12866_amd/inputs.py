@@ -8,8 +8,9 @@ each implementation from its own counter-based generator.
 
 The paper's workloads are partitions of real circuits (U3 + CNOT, 3-12 qubits); they
 are not available here, so seeded synthetic circuits of the same sizes stand in:
-brickwork and random-pair templates of general two-qubit gates, with targets built
-from the same template with Haar-random gates, so that an exact solution exists.
+brickwork and random-pair templates of general two-qubit gates, and U3 + CNOT style
+templates of variable one-qubit gates around constant CNOTs, with targets built from
+the same template with Haar-random gates, so that an exact solution exists.
 """
 from __future__ import annotations
 
@@ -28,6 +29,13 @@ def splitmix64(x: int) -> int:
 
 
 ROLE_TARGET, ROLE_TRAIN, ROLE_VAL, ROLE_INIT = 0x7A, 0x7B, 0x7C, 0x7D
+
+# Gate kinds of a template: variable two-qubit, variable one-qubit (slot v (x) I_2 on
+# (qubit, spectator)), constant.
+GATE_2Q, GATE_1Q, GATE_FIXED = 0, 1, 2
+
+# CNOT with the first qubit of the pair as control (local index 2*bit(a) + bit(b)).
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
 
 
 def derive_seed(base: int, problem: int = 0, role: int = ROLE_TARGET, start: int = 0) -> int:
@@ -116,6 +124,39 @@ def embed_two_qubit(n: int, a: int, b: int, u):
     return full
 
 
+def u3_cnot_template(n: int, sublayers: int):
+    """U3 + CNOT style template: a one-qubit gate on every qubit, then brickwork
+    sublayers of CNOT blocks, each block a constant CNOT on (q, q+1) followed by one-qubit
+    gates on q and q+1 (the shape of synthesised partitions). A one-qubit gate on q names
+    spectator (q + 1) mod n. Returns (pairs [L][2], kinds [L], fixed [L][4][4] with the
+    CNOTs at the constant gates and the identity elsewhere)."""
+    pairs, kinds = [], []
+    for q in range(n):
+        pairs.append((q, (q + 1) % n))
+        kinds.append(GATE_1Q)
+    for s in range(sublayers):
+        for q in range(s % 2, n - 1, 2):
+            pairs += [(q, q + 1), (q, q + 1), (q + 1, q)]
+            kinds += [GATE_FIXED, GATE_1Q, GATE_1Q]
+    kinds = np.asarray(kinds, dtype=np.int32)
+    fixed = np.stack([CNOT if k == GATE_FIXED else np.eye(4, dtype=np.complex128) for k in kinds])
+    return np.asarray(pairs, dtype=np.int32), kinds, fixed
+
+
+def kinds_target_gates(kinds, fixed, g: np.random.Generator):
+    """Target gates for a template with gate kinds: Haar 4x4, Haar 2x2 (x) I_2, or the
+    constant gate."""
+    out = []
+    for k, f in zip(kinds, fixed):
+        if k == GATE_FIXED:
+            out.append(np.array(f, dtype=np.complex128))
+        elif k == GATE_1Q:
+            out.append(np.kron(haar_unitary(2, g), np.eye(2)))
+        else:
+            out.append(haar_unitary(4, g))
+    return np.stack(out)
+
+
 # ----------------------------------------------------------------------------------
 # Named workloads (sizes of the paper's partitions; synthetic content).
 # ----------------------------------------------------------------------------------
@@ -140,6 +181,16 @@ def workload_8q(seed_base: int = 0x5A17 + 2):
 def workload_12q(seed_base: int = 0x5A17 + 3):
     """12-qubit brickwork, 8 sublayers (44 gates)."""
     return workload_brickwork(12, 8, seed_base)
+
+
+def workload_u3_cnot(n: int, sublayers: int, seed_base: int = 0x5A17 + 6, problem: int = 0):
+    """U3 + CNOT style template (u3_cnot_template); target = the same template with Haar
+    one-qubit gates and the same CNOTs. 12 qubits x 8 sublayers: 44 CNOTs, 100 one-qubit
+    gates."""
+    g = rng(derive_seed(seed_base, problem, ROLE_TARGET))
+    pairs, kinds, fixed = u3_cnot_template(n, sublayers)
+    return dict(n=n, pairs=pairs, kinds=kinds, fixed=fixed, target_pairs=pairs,
+                target_gates=kinds_target_gates(kinds, fixed, g))
 
 
 def batched_problems(count: int, seed_base: int = 0x5A17 + 4, n_range=(3, 7), L_range=(2, 20)):

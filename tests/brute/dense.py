@@ -55,15 +55,30 @@ def partial_trace_env(n, a, b, X):
     return np.einsum("prqr->pq", T)
 
 
+def partial_trace_env1(n, a, X):
+    """E[p][q] = sum_r X[(p,r),(q,r)] over the n-1 qubits other than a (2x2)."""
+    T = X.reshape((2,) * (2 * n))
+    order = [a] + [q for q in range(n) if q != a] + [n + a] + [n + q for q in range(n) if q != a]
+    T = np.transpose(T, order).reshape(2, (1 << n) // 2, 2, (1 << n) // 2)
+    return np.einsum("prqr->pq", T)
+
+
+def one_qubit_matrix(n, a, v):
+    """Full 2^n x 2^n matrix of the 2x2 v on qubit a: I_{2^a} (x) v (x) I_{2^(n-1-a)}."""
+    return np.kron(np.kron(np.eye(1 << a), v), np.eye(1 << (n - 1 - a)))
+
+
 def polar_unitary(A):
     W, s, Vh = np.linalg.svd(A)
     return W @ Vh
 
 
-def dense_qfactor_sweep(n, pairs, gates, U):
+def dense_qfactor_sweep(n, pairs, gates, U, kinds=None):
     """One full-unitary QFactor sweep, right to left (Sec. 2.1): for gate k with
     C = A u_k B, f = Re Tr(U^dag A u_k B) = Re Tr(E u_k), E = Tr_rest(B U^dag A);
-    u_k <- Y X^dag for E = X D Y^dag (Eq. 2). A uses already-updated gates."""
+    u_k <- Y X^dag for E = X D Y^dag (Eq. 2). A uses already-updated gates.
+    kinds (0 two-qubit, 1 one-qubit, 2 fixed): a one-qubit gate's slot is v (x) I_2 and v
+    is updated from the 2x2 partial trace over every other qubit; a fixed gate is kept."""
     pairs = np.asarray(pairs).reshape(-1, 2)
     g = [np.array(x, dtype=np.complex128) for x in gates]
     L = len(g)
@@ -75,6 +90,14 @@ def dense_qfactor_sweep(n, pairs, gates, U):
         B = np.eye(N, dtype=np.complex128)
         for j in range(k):
             B = gate_matrix(n, int(pairs[j][0]), int(pairs[j][1]), g[j]) @ B
+        kind = 0 if kinds is None else int(kinds[k])
+        if kind == 2:
+            continue
+        if kind == 1:
+            E = partial_trace_env1(n, int(pairs[k][0]), B @ U.conj().T @ A)
+            X, d, Yh = np.linalg.svd(E)
+            g[k] = np.kron(Yh.conj().T @ X.conj().T, np.eye(2))
+            continue
         E = partial_trace_env(n, int(pairs[k][0]), int(pairs[k][1]), B @ U.conj().T @ A)
         X, d, Yh = np.linalg.svd(E)
         g[k] = Yh.conj().T @ X.conj().T
