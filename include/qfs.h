@@ -58,10 +58,31 @@ const char *qfs_last_error_detail(void);
 const char *qfs_version(void);
 
 /* ---------------------------------------------------------------- problem */
+/* Gate kinds (Sec. 2.1: QFactor updates gates of any size directly as unitaries;
+ * Sec. 4: the instantiated partitions are U3 + CNOT circuits).
+ *   QFS_GATE_2Q:    variable two-qubit gate on (a, b): any 4x4 unitary, updated to the
+ *                   polar factor of its 4x4 environment.
+ *   QFS_GATE_1Q:    variable one-qubit gate v on qubit a; b is any other qubit (a
+ *                   spectator). Its 4x4 slot holds v (x) I_2 in the local basis of
+ *                   (a, b) and keeps that form: v is updated to the polar factor of the
+ *                   2x2 environment sum_j sum_r a_j(q, r) conj(B_j(p, r)) over the other
+ *                   n-1 qubits (read v as slot[2q][2p]).
+ *   QFS_GATE_FIXED: constant 4x4 gate on (a, b) (a CNOT; a constant one-qubit gate as
+ *                   w (x) I_2): applied in both passes, never updated. */
+enum { QFS_GATE_2Q = 0, QFS_GATE_1Q = 1, QFS_GATE_FIXED = 2 };
+
+/* Circuit template: L gates applied in list order, gate k on the ordered qubit pair
+ * pairs[k] (a != b; local index 2 bit(a) + bit(b), qubit 0 the most significant bit).
+ * kinds == NULL means every gate is QFS_GATE_2Q. fixed_gates holds the constant gates
+ * (device [n_gates][4][4]; only the QFS_GATE_FIXED entries are read, every start gets
+ * them); it may be NULL when no gate is constant. A target circuit's kinds and
+ * fixed_gates are ignored (its gates are all given). */
 typedef struct {
   int32_t n_qubits;
   int32_t n_gates;
-  const int32_t *pairs; /* host, [n_gates][2] */
+  const int32_t *pairs;         /* host, [n_gates][2]                        */
+  const int32_t *kinds;         /* host, [n_gates] or NULL                   */
+  const qfs_c128 *fixed_gates;  /* device, [n_gates][4][4] or NULL           */
 } qfs_template;
 
 enum { QFS_TARGET_DENSE = 0, QFS_TARGET_CIRCUIT = 1, QFS_TARGET_SAMPLES = 2 };
@@ -185,7 +206,10 @@ void qfs_default_params(qfs_params *p);
  * fit device_mem_budget the multistarts are run in halves, recursively (App. A).
  *   gates_in:  device [multistarts][L][4][4], or NULL for Haar-random initial gates
  *              drawn from params->seed (role 3, stream = start, index 16*gate + 4*col
- *              + row of a column-major 4x4 Ginibre block).
+ *              + row of a column-major 4x4 Ginibre block; a one-qubit gate takes
+ *              v (x) I_2 with v from the 2x2 block at indices 16*gate + 2*col + row).
+ *              Constant gates always come from tmpl->fixed_gates; a one-qubit gate's
+ *              entry must have the form v (x) I_2 (to 1e-10).
  *   gates_out: device [L][4][4]: the returned start's gates (complex128).
  *   res:       host.
  * Errors: QFS_EINVAL (invalid template/target/params, or gates_in not unitary to
@@ -211,7 +235,8 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target,
  *   tmpl, targets: host arrays [P] (targets' device pointers as in qfs_instantiate).
  *   gates_out: host array [P] of device pointers [L_p][4][4] (NULL entries skipped).
  *   res: host [P].
- * Limits: 2 <= n_qubits <= 10 per problem (QFS_EUNSUPPORTED above). */
+ * Limits: 2 <= n_qubits <= 10 per problem (QFS_EUNSUPPORTED above); two-qubit gates
+ * only (QFS_EUNSUPPORTED for a template with other gate kinds). */
 int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
                           const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res);
 
@@ -238,7 +263,9 @@ int qfs_label_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targe
  * 64 -> 128 -> 128 -> 2 (ReLU; bfloat16 weights, FP32 accumulation; process-wide, one
  * per process, guarded by a mutex) maps structural template features to
  *   y0: log2 of the smallest power-of-two M at which a start succeeds, and
- *   y1: the logit of the chance that one random start succeeds at that M. */
+ *   y1: the logit of the chance that one random start succeeds at that M.
+ * The network was fitted on templates of two-qubit gates: every entry below that takes
+ * a template returns QFS_EUNSUPPORTED for one with other gate kinds. */
 
 /* The 64 features of a template (host; no device work). out: host [64]. */
 int qfs_features(const qfs_template *tmpl, float *out);
@@ -354,13 +381,15 @@ int qfs_polar_update(int32_t count, const qfs_c128 *gamma, double beta, qfs_c128
  * Fig. env_calc_tensor): forward B list from the current gates, then right to left
  * environment, polar update, and backward propagation through the updated gate;
  * returns the Eq. 9 cost of the updated gates per start.
+ *   kinds:     host [L] gate kinds, or NULL (every gate QFS_GATE_2Q); constant gates
+ *              are the gates' own entries and are left unchanged.
  *   psi, phi:  device [M][N] (training states and U psi).
  *   gates:     device [starts][L][4][4], updated in place (complex128 master).
  *   precision: QFS_PREC_FP64 or QFS_PREC_MIXED (complex64 states).
  *   c_train:   host [starts]. */
-int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c128 *psi,
-              const qfs_c128 *phi, int32_t starts, qfs_c128 *gates, int32_t precision,
-              double beta, double *c_train, void *hip_stream);
+int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, int32_t M,
+              const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates,
+              int32_t precision, double beta, double *c_train, void *hip_stream);
 
 /* (1/M) sum_j ||x_j - y_j||^2 accumulated in FP64 (Sec. 3, Eq. 9). x, y: device
  * [M][N]; result: host. */

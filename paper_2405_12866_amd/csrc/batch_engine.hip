@@ -160,6 +160,10 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         set_error_detail("batch: problem " + std::to_string(i) + ": invalid qubit pair");
         return QFS_EINVAL;
       }
+      if (t.kinds && t.kinds[k] != QFS_GATE_2Q) {
+        set_error_detail("batch: problem " + std::to_string(i) + ": only two-qubit variable gates");
+        return QFS_EUNSUPPORTED;
+      }
     }
     const int N = 1 << t.n_qubits;
     BProb &d = hp[i];

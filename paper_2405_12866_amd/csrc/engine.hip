@@ -79,8 +79,26 @@ int validate_template(const qfs_template *t) {
       set_error_detail("template: gate " + std::to_string(k) + " has an invalid qubit pair");
       return QFS_EINVAL;
     }
+    if (t->kinds) {
+      const int kind = t->kinds[k];
+      if (kind != QFS_GATE_2Q && kind != QFS_GATE_1Q && kind != QFS_GATE_FIXED) {
+        set_error_detail("template: gate " + std::to_string(k) + " has an unknown kind");
+        return QFS_EINVAL;
+      }
+      if (kind == QFS_GATE_FIXED && !t->fixed_gates) {
+        set_error_detail("template: constant gates need fixed_gates");
+        return QFS_EINVAL;
+      }
+    }
   }
   return QFS_OK;
+}
+
+bool has_kinds(const qfs_template *t) {
+  if (!t->kinds) return false;
+  for (int k = 0; k < t->n_gates; ++k)
+    if (t->kinds[k] != QFS_GATE_2Q) return true;
+  return false;
 }
 
 // Memory accounting for one call: every allocation goes through here so that the
@@ -170,6 +188,7 @@ struct SweepCtx {
   int n = 0, L = 0;
   const int32_t *pairs_host = nullptr;
   const int32_t *pairs_dev = nullptr;
+  const int32_t *kinds = nullptr;  // host [L] gate kinds, or nullptr: all two-qubit
   Geometry g{}, gv{};  // training / validation sets (gv.M == 0: no validation)
   bool fused = false;
   const int32_t *slots = nullptr;
@@ -299,9 +318,20 @@ int sweep_backward(SweepCtx &c) {
   }
   for (int k = c.L - 1; k >= 0; --k) {
     const int k_apply = (k == c.L - 1) ? -1 : k + 1;
+    const int kind = c.kinds ? c.kinds[k] : QFS_GATE_2Q;
     SBuf<R> a_in = (k >= c.L - 2) ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
     SBuf<R> b = k == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 1) * sN, bstride};
     for (int h = 0; h < halves; ++h) {
+      if (kind == QFS_GATE_FIXED) {
+        // a constant gate has no environment: only move the backward state through
+        // the gate after it (nothing to do for the last gate)
+        if (k_apply < 0) continue;
+        QFS_TRY(T.begin(hs[h]));
+        QFS_TRY(launch_apply<R>(c.g, c.pairs_host[2 * k_apply], c.pairs_host[2 * k_apply + 1], k_apply,
+                                true, gr, a_in, SBuf<R>{A, sN}, hslots[h], hn[h], hs[h]));
+        QFS_TRY(T.end(hs[h], kClsStep, 2.0 * set_bytes<R>(c, c.g) * hn[h] / c.nslots));
+        continue;
+      }
       int P = 0;
       QFS_TRY(T.begin(hs[h]));
       QFS_TRY(launch_bwd_step<R>(c.g, c.pairs_host, k_apply, k, gr, a_in, SBuf<R>{A, sN}, b, hslots[h],
@@ -309,7 +339,7 @@ int sweep_backward(SweepCtx &c) {
       QFS_TRY(T.end(hs[h], kClsStep, (k_apply < 0 ? 2.0 : 3.0) * set_bytes<R>(c, c.g) * hn[h] / c.nslots));
       QFS_TRY(T.begin(hs[h]));
       QFS_TRY(launch_env_finalize(P, c.partials, hslots[h], hn[h], nullptr, true, c.beta, c.g64,
-                                  sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, k, c.vstore, hs[h]));
+                                  sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, k, c.vstore, kind, hs[h]));
       QFS_TRY(T.end(hs[h], kClsPolar, (double)P * 256.0 * hn[h]));
     }
   }
@@ -355,6 +385,10 @@ class Group {
     L_ = t->n_gates;
     N_ = int64_t(1) << n_;
     pairs_.assign(t->pairs, t->pairs + 2 * L_);
+    if (has_kinds(t)) {
+      kinds_.assign(t->kinds, t->kinds + L_);
+      fixed_ = reinterpret_cast<const c128 *>(t->fixed_gates);
+    }
     stream_ = as_stream(p.hip_stream);
   }
   ~Group() {
@@ -381,6 +415,8 @@ class Group {
   int n_ = 0, L_ = 0;
   int64_t N_ = 0;
   std::vector<int32_t> pairs_;
+  std::vector<int32_t> kinds_;  // empty: every gate two-qubit
+  const c128 *fixed_ = nullptr;
   hipStream_t stream_ = nullptr;
   hipStream_t side_ = nullptr;  // second stream of the backward pass (default priority)
   hipEvent_t fork_ = nullptr, join_ = nullptr;
@@ -398,7 +434,7 @@ class Group {
   DevBuf psi64_, phi64_, psiv64_, phiv64_;  // complex128 masters, row-major N x ldm
   DevBuf psiw_, phiw_, psivw_, phivw_;      // working sets in the sweep precision
   DevBuf blist_, astate_, vstate_;
-  DevBuf g64_, g32_, vstore_, pairs_dev_;
+  DevBuf g64_, g32_, vstore_, pairs_dev_, kinds_dev_;
   DevBuf partials_, dpart_, costs_, slots_, work_;
   double *h_costs_ = nullptr;  // pinned [3 S]: c_train, c_val, c_0
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
@@ -649,11 +685,19 @@ int Group::run(GroupResult &out, double t_start) {
   } else {
     QFS_TRY(launch_haar_gates(p_.seed, start0_, S_, L_, g64_.as<c128>(), stream_));
   }
+  if (!kinds_.empty()) {
+    QFS_TRY(arena_.alloc(kinds_dev_, sizeof(int32_t) * (size_t)L_));
+    QFS_HIP(hipMemcpyAsync(kinds_dev_.ptr, kinds_.data(), sizeof(int32_t) * L_, hipMemcpyHostToDevice,
+                           stream_));
+    QFS_TRY(launch_kind_gates(p_.seed, start0_, S_, L_, kinds_dev_.as<int32_t>(), fixed_, !gates_in_,
+                              g64_.as<c128>(), stream_));
+  }
   QFS_TRY(launch_narrow((int64_t)16 * L_ * S_, g64_.as<c128>(), g32_.as<c64>(), stream_));
   QFS_TRY(arena_.alloc(vstore_, sizeof(c128) * 16 * (size_t)L_ * S_));
   QFS_TRY(launch_identity4((int64_t)L_ * S_, vstore_.as<c128>(), stream_));
 
   SweepCtx &c = ctx_;
+  c.kinds = kinds_.empty() ? nullptr : kinds_.data();
   c.slots = slots_.as<int32_t>();
   c.g64 = g64_.as<c128>();
   c.g32 = g32_.as<c64>();
@@ -899,12 +943,29 @@ int run_split(const qfs_template *t, const qfs_target *tg, const qfs_params &p,
   return QFS_OK;
 }
 
-int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, hipStream_t s) {
+// Gate slots [count][4][4] (gate index gi % L of the template) must be unitary to 1e-10,
+// and a one-qubit slot must have the form v (x) I_2. fixed_only: check the constant gates
+// only (the template's fixed_gates); else every slot but the constant gates' (gates_in).
+int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, int L, const int32_t *kinds,
+                        bool fixed_only, const char *what, hipStream_t s) {
   std::vector<qfs_c128> h(count * 16);
   QFS_HIP(hipMemcpyAsync(h.data(), gates_dev, sizeof(qfs_c128) * h.size(), hipMemcpyDeviceToHost, s));
   QFS_HIP(hipStreamSynchronize(s));
   for (size_t gi = 0; gi < count; ++gi) {
     const qfs_c128 *u = h.data() + gi * 16;
+    const int kind = kinds ? kinds[gi % L] : QFS_GATE_2Q;
+    if ((kind == QFS_GATE_FIXED) != fixed_only) continue;
+    if (kind == QFS_GATE_1Q) {
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          const qfs_c128 want = ((r & 1) == (c & 1)) ? u[(r & 2) * 4 + (c & 2)] : qfs_c128{0.0, 0.0};
+          if (std::fabs(u[r * 4 + c].re - want.re) > 1e-10 || std::fabs(u[r * 4 + c].im - want.im) > 1e-10) {
+            set_error_detail(std::string(what) + ": one-qubit gate " + std::to_string(gi) +
+                             " is not of the form v (x) I_2");
+            return QFS_EINVAL;
+          }
+        }
+    }
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) {
         double re = 0.0, im = 0.0;
@@ -915,7 +976,7 @@ int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, hipStream_t s) 
         }
         re -= (i == j) ? 1.0 : 0.0;
         if (!std::isfinite(re) || !std::isfinite(im) || std::fabs(re) > 1e-10 || std::fabs(im) > 1e-10) {
-          set_error_detail("gates_in: gate " + std::to_string(gi) + " is not unitary to 1e-10");
+          set_error_detail(std::string(what) + ": gate " + std::to_string(gi) + " is not unitary to 1e-10");
           return QFS_EINVAL;
         }
       }
@@ -1022,7 +1083,12 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
       return set_error_detail("unknown target kind"), QFS_EINVAL;
   }
   hipStream_t s = static_cast<hipStream_t>(p.hip_stream);
-  if (gates_in) QFS_TRY(check_gates_unitary(gates_in, (size_t)p.multistarts * tmpl->n_gates, s));
+  if (gates_in)
+    QFS_TRY(check_gates_unitary(gates_in, (size_t)p.multistarts * tmpl->n_gates, tmpl->n_gates,
+                                tmpl->kinds, false, "gates_in", s));
+  if (has_kinds(tmpl) && tmpl->fixed_gates)
+    QFS_TRY(check_gates_unitary(tmpl->fixed_gates, (size_t)tmpl->n_gates, tmpl->n_gates, tmpl->kinds,
+                                true, "fixed_gates", s));
   size_t budget = p.device_mem_budget;
   if (budget == 0) {
     size_t fr = 0, tot = 0;
@@ -1170,7 +1236,7 @@ int qfs_environment(int32_t n, int32_t M, const qfs_c128 *a, const qfs_c128 *b, 
                                   SBuf<double>{A.as<c128>(), 0}, SBuf<double>{B.as<c128>(), 0},
                                   slot.as<int32_t>(), 1, part.as<c128>(), &P, s));
   QFS_TRY(launch_env_finalize(P, part.as<c128>(), slot.as<int32_t>(), 1, reinterpret_cast<c128 *>(gamma),
-                              false, 0.0, nullptr, nullptr, 0, 0, nullptr, s));
+                              false, 0.0, nullptr, nullptr, 0, 0, nullptr, QFS_GATE_2Q, s));
   QFS_HIP(hipStreamSynchronize(s));
   return QFS_OK;
 }
@@ -1209,10 +1275,17 @@ int qfs_state_distance(int32_t n, int32_t M, const qfs_c128 *x, const qfs_c128 *
   return QFS_OK;
 }
 
-int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c128 *psi,
-              const qfs_c128 *phi, int32_t starts, qfs_c128 *gates, int32_t precision, double beta,
-              double *c_train, void *hip_stream) {
-  qfs_template t{n, L, pairs};
+int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, int32_t M,
+              const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates,
+              int32_t precision, double beta, double *c_train, void *hip_stream) {
+  // constant gates are the gates' own entries here: validate the kinds without them
+  std::vector<int32_t> kv;
+  if (kinds) {
+    kv.assign(kinds, kinds + std::max(L, 0));
+    for (int32_t &k : kv)
+      if (k == QFS_GATE_FIXED) k = QFS_GATE_2Q;
+  }
+  qfs_template t{n, L, pairs, kinds ? kv.data() : nullptr, nullptr};
   QFS_TRY(validate_template(&t));
   if (M < 1 || (int64_t)M > (int64_t(1) << n) || starts < 1 || !psi || !phi || !gates || !c_train ||
       (precision != QFS_PREC_FP64 && precision != QFS_PREC_MIXED) || !(beta >= 0 && beta <= 1))
@@ -1228,6 +1301,7 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c
   c.n = n;
   c.L = L;
   c.pairs_host = pairs;
+  c.kinds = kinds;
   c.g = Geometry{n, 1 << n, logC, (M + C - 1) / C, M};
   c.gv = Geometry{n, 1 << n, logC, 1, 0};
   c.fused = fused;

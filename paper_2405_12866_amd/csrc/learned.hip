@@ -35,6 +35,14 @@ bool valid_template(const qfs_template *t) {
   return true;
 }
 
+// The network was fitted on templates of two-qubit gates only.
+bool two_qubit_only(const qfs_template *t) {
+  if (t->kinds)
+    for (int k = 0; k < t->n_gates; ++k)
+      if (t->kinds[k] != QFS_GATE_2Q) return false;
+  return true;
+}
+
 // Structural features, each scaled to O(1):
 //   0 n/16, 1 L/128, 2 depth/64 (greedy layering), 3 log2(1 + 16L/2^n) (real parameters
 //   per amplitude, the paper's explanatory variable up to the factor), 4 log2(16L)/16,
@@ -138,6 +146,8 @@ int predict_many(int P, const qfs_template *tmpl, const qfs_params &p, int32_t *
   std::vector<float> feat((size_t)P * kMlpF), y((size_t)P * kMlpO);
   for (int i = 0; i < P; ++i) {
     if (!valid_template(&tmpl[i])) return set_error_detail("learned: invalid template"), QFS_EINVAL;
+    if (!two_qubit_only(&tmpl[i]))
+      return set_error_detail("learned: templates of two-qubit gates only"), QFS_EUNSUPPORTED;
     template_features(tmpl[i], feat.data() + (size_t)i * kMlpF);
   }
   DevBuf fd, yd;
@@ -161,6 +171,7 @@ extern "C" {
 
 int qfs_features(const qfs_template *t, float *out) {
   if (!valid_template(t) || !out) return set_error_detail("features: invalid template"), QFS_EINVAL;
+  if (!two_qubit_only(t)) return set_error_detail("features: templates of two-qubit gates only"), QFS_EUNSUPPORTED;
   template_features(*t, out);
   return QFS_OK;
 }

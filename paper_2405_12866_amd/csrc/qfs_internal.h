@@ -142,6 +142,11 @@ int launch_ginibre(int64_t rows, int64_t col0, int64_t col1, int64_t ld, uint64_
                    uint32_t role, uint32_t stream, c128 *A, hipStream_t s);
 int launch_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L, c128 *out,
                       hipStream_t s);
+// Gate kinds applied to [starts][L] slots: constant gates copied from fixed, and, when the
+// slots were drawn, one-qubit gates redrawn as v (x) I_2. kinds: device [L] (NULL: no-op).
+int launch_kind_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L,
+                      const int32_t *kinds, const c128 *fixed, bool drawn, c128 *out,
+                      hipStream_t s);
 
 // Linear algebra (linalg.hip), all complex FP64, row-major with leading dimensions.
 // C[m x n] = alpha * op(A) * B + beta * C, op(A) = A (m x k) or A^H (A is k x m).
@@ -222,7 +227,8 @@ int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, h
 // the environment of gate k_env from a_s and b_s as per-block FP64 partial sums
 // [S][P][16] (P returned). launch_env_finalize (one wave per start) reduces them in a
 // fixed order and writes u_s[k_env] <- polar((1-beta) Gamma + beta u) to both gate
-// copies; optionally stores Gamma (FP64) to gamma_out[s].
+// copies (kind QFS_GATE_1Q: the one-qubit update of a v (x) I_2 slot); optionally stores
+// Gamma (FP64) to gamma_out[s].
 template <typename R>
 int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
                     GateRef gates, SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b,
@@ -232,7 +238,7 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
 // used to warm-start the Jacobi iteration and updated in place.
 int launch_env_finalize(int P, const c128 *partials, const int32_t *slot_to_start, int nslots,
                         c128 *gamma_out, bool do_update, double beta, c128 *g64, c64 *g32,
-                        int32_t gstride, int32_t k_env, c128 *vstore, hipStream_t s);
+                        int32_t gstride, int32_t k_env, c128 *vstore, int kind, hipStream_t s);
 // count 4x4 identity matrices.
 int launch_identity4(int64_t count, c128 *v, hipStream_t s);
 

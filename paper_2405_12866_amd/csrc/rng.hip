@@ -68,4 +68,49 @@ int launch_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L, 
   return QFS_OK;
 }
 
+// Gate kinds after the 4x4 draw (or copy) of every slot: a one-qubit gate of a drawn
+// start becomes v (x) I_2 with v Haar on U(2) from the 2x2 Ginibre block at indices
+// 16*gate + 2*col + row of the same stream; a constant gate is copied from fixed[gate].
+// One thread per (start, gate).
+__global__ void k_kind_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L,
+                             const int32_t *kinds, const c128 *fixed, int32_t drawn, c128 *out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)starts * L) return;
+  const int32_t s = (int32_t)(t / L), k = (int32_t)(t - (int64_t)s * L);
+  const int kind = kinds[k];
+  c128 *u = out + t * 16;
+  if (kind == QFS_GATE_FIXED) {
+    for (int e = 0; e < 16; ++e) u[e] = fixed[(int64_t)k * 16 + e];
+    return;
+  }
+  if (kind != QFS_GATE_1Q || !drawn) return;
+  c128 q[2][2];  // [col][row]
+  for (int c = 0; c < 2; ++c)
+    for (int r = 0; r < 2; ++r)
+      q[c][r] = complex_normal(seed, 3u, (uint32_t)(start0 + s), (uint64_t)k * 16u + 2u * c + r);
+  for (int c = 0; c < 2; ++c) {
+    for (int rep = 0; rep < 2; ++rep)
+      for (int o = 0; o < c; ++o) {
+        const c128 d = cconj(q[o][0]) * q[c][0] + cconj(q[o][1]) * q[c][1];
+        for (int r = 0; r < 2; ++r) q[c][r] = q[c][r] - d * q[o][r];
+      }
+    const double inv = 1.0 / sqrt(cabs2(q[c][0]) + cabs2(q[c][1]));
+    for (int r = 0; r < 2; ++r) q[c][r] = cscale(q[c][r], inv);
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c)
+      u[r * 4 + c] = ((r & 1) == (c & 1)) ? q[c >> 1][r >> 1] : cmake(0.0, 0.0);
+}
+
+int launch_kind_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L,
+                      const int32_t *kinds, const c128 *fixed, bool drawn, c128 *out,
+                      hipStream_t s) {
+  const int64_t total = (int64_t)starts * L;
+  if (total <= 0 || !kinds) return QFS_OK;
+  hipLaunchKernelGGL(k_kind_gates, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s,
+                     seed, start0, starts, L, kinds, fixed, drawn ? 1 : 0, out);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
 }  // namespace qfs

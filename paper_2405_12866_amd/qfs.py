@@ -19,6 +19,7 @@ _lock = threading.Lock()
 QFS_OK, QFS_EINVAL, QFS_ENOMEM, QFS_EDEVICE, QFS_EUNSUPPORTED, QFS_ENUMERIC = range(6)
 QFS_TARGET_DENSE, QFS_TARGET_CIRCUIT, QFS_TARGET_SAMPLES = 0, 1, 2
 QFS_PREC_FP64, QFS_PREC_MIXED = 0, 1
+QFS_GATE_2Q, QFS_GATE_1Q, QFS_GATE_FIXED = 0, 1, 2
 REASONS = {0: "SUCCESS", 1: "PLATEAU", 2: "MAX_ITER", 3: "NOT_GENERALIZED", 4: "TIMEOUT"}
 
 
@@ -31,7 +32,8 @@ class QfsError(RuntimeError):
 
 
 class Template(C.Structure):
-    _fields_ = [("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("pairs", C.POINTER(C.c_int32))]
+    _fields_ = [("n_qubits", C.c_int32), ("n_gates", C.c_int32), ("pairs", C.POINTER(C.c_int32)),
+                ("kinds", C.POINTER(C.c_int32)), ("fixed_gates", C.c_void_p)]
 
 
 class Target(C.Structure):
@@ -102,7 +104,7 @@ def load():
         lib.qfs_dense_apply.argtypes = [I32, I32, P, P, P, P]
         lib.qfs_environment.argtypes = [I32, I32, P, P, I32, I32, P, P]
         lib.qfs_polar_update.argtypes = [I32, P, D, P, P]
-        lib.qfs_sweep.argtypes = [I32, I32, P, I32, P, P, I32, P, I32, D, P, P]
+        lib.qfs_sweep.argtypes = [I32, I32, P, P, I32, P, P, I32, P, I32, D, P, P]
         lib.qfs_state_distance.argtypes = [I32, I32, P, P, C.POINTER(C.c_double), P]
         batch_args = [I32, C.POINTER(Template), C.POINTER(Target), C.POINTER(Params)]
         lib.qfs_label_batch.argtypes = batch_args + [P, C.POINTER(Result)]
@@ -156,6 +158,24 @@ def _pairs(pairs):
     return arr, arr.ctypes.data_as(C.POINTER(C.c_int32))
 
 
+def _template(n, pairs, keep, kinds=None, fixed_gates=None):
+    """A Template for ``pairs``; ``kinds`` (per gate QFS_GATE_*) and ``fixed_gates``
+    (device [L, 4, 4], read at the constant gates) are optional."""
+    import numpy as np
+    arr, pp = _pairs(pairs)
+    keep.append(arr)
+    t = Template(n, arr.shape[0], pp)
+    if kinds is not None:
+        k = np.ascontiguousarray(np.asarray(kinds, dtype=np.int32).reshape(-1))
+        if k.shape[0] != arr.shape[0]:
+            raise ValueError("kinds needs one entry per gate")
+        keep.append(k)
+        t.kinds = k.ctypes.data_as(C.POINTER(C.c_int32))
+    if fixed_gates is not None:
+        t.fixed_gates = _dev_c128(fixed_gates, "fixed_gates")
+    return t
+
+
 def qfs_default_params(**overrides) -> dict:
     p = Params()
     load().qfs_default_params(C.byref(p))
@@ -207,14 +227,13 @@ def _info(res):
     return info
 
 
-def _single(fn_name, n, pairs, params, gates_in, target):
+def _single(fn_name, n, pairs, params, gates_in, target, kinds=None, fixed_gates=None):
     import torch
     lib = load()
-    arr, pp = _pairs(pairs)
-    L = arr.shape[0]
-    tmpl = Template(n, L, pp)
+    keep = []
+    tmpl = _template(n, pairs, keep, kinds, fixed_gates)
+    L = tmpl.n_gates
     tgt = Target()
-    keep = [arr]
     dev = _fill_target(tgt, n, keep, **target)
     par = _params(params)
     out = torch.empty((L, 4, 4), dtype=torch.complex128, device=dev)
@@ -231,14 +250,16 @@ def _single(fn_name, n, pairs, params, gates_in, target):
 
 
 def qfs_instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=None,
-                    phi=None, n_val=0, params=None, gates_in=None):
+                    phi=None, n_val=0, params=None, gates_in=None, kinds=None, fixed_gates=None):
     """QFactor-Sample instantiation on the device. Exactly one target form: dense ``U``
     [N, N]; a circuit (``target_pairs``, ``target_gates`` [Lt, 4, 4]); or samples
-    ``psi``/``phi`` [n_samples, N] whose last ``n_val`` rows validate. Returns
-    (gates [L, 4, 4] complex128 device tensor, result dict)."""
+    ``psi``/``phi`` [n_samples, N] whose last ``n_val`` rows validate. ``kinds`` (per gate
+    QFS_GATE_2Q / QFS_GATE_1Q / QFS_GATE_FIXED) and ``fixed_gates`` (device [L, 4, 4])
+    describe templates with one-qubit and constant gates. Returns (gates [L, 4, 4]
+    complex128 device tensor, result dict)."""
     return _single("qfs_instantiate", n, pairs, params, gates_in,
                    dict(U=U, target_pairs=target_pairs, target_gates=target_gates, psi=psi,
-                        phi=phi, n_val=n_val))
+                        phi=phi, n_val=n_val), kinds, fixed_gates)
 
 
 def qfs_instantiate_learned(n, pairs, *, U=None, target_pairs=None, target_gates=None,
@@ -262,12 +283,10 @@ def _batch(fn_name, problems, params, with_gates=True, per_problem=None):
     tgts = (Target * P)()
     keep, outs = [], []
     for i, pr in enumerate(problems):
-        arr, pp = _pairs(pr["pairs"])
-        keep.append(arr)
-        tmpls[i] = Template(pr["n"], arr.shape[0], pp)
+        tmpls[i] = _template(pr["n"], pr["pairs"], keep, pr.get("kinds"), pr.get("fixed_gates"))
         dev = _fill_target(tgts[i], pr["n"], keep, **{k: pr[k] for k in _TARGET_KEYS if k in pr})
         if with_gates:
-            outs.append(torch.empty((arr.shape[0], 4, 4), dtype=torch.complex128, device=dev))
+            outs.append(torch.empty((tmpls[i].n_gates, 4, 4), dtype=torch.complex128, device=dev))
     res = (Result * P)()
     par = _params(params)
     if with_gates:
@@ -482,13 +501,20 @@ def qfs_polar_update(gamma, beta=0.0, u=None):
     return u
 
 
-def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0):
-    """One sweep of ``gates`` [starts, L, 4, 4] (updated in place); returns c_train list."""
+def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kinds=None):
+    """One sweep of ``gates`` [starts, L, 4, 4] (updated in place); returns c_train list.
+    ``kinds``: per-gate QFS_GATE_* (constant gates are their own entries)."""
     import numpy as np
     arr, pp = _pairs(pairs)
     starts = gates.shape[0]
     c = np.zeros(starts)
-    _check(load().qfs_sweep(n, arr.shape[0], pp, psi.shape[0], _dev_c128(psi, "psi"),
+    kd = None
+    if kinds is not None:
+        kd = np.ascontiguousarray(np.asarray(kinds, dtype=np.int32).reshape(-1))
+        if kd.shape[0] != arr.shape[0]:
+            raise ValueError("kinds needs one entry per gate")
+    _check(load().qfs_sweep(n, arr.shape[0], pp, None if kd is None else kd.ctypes.data_as(C.c_void_p),
+                            psi.shape[0], _dev_c128(psi, "psi"),
                             _dev_c128(phi, "phi"), starts, _dev_c128(gates, "gates"), precision,
                             beta, c.ctypes.data_as(C.c_void_p), _stream()), "qfs_sweep")
     return c

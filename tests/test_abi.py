@@ -71,8 +71,8 @@ def test_invalid_templates_rejected_without_device_work(pairs, n):
     arr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32))
     pp = arr.ctypes.data_as(C.POINTER(C.c_int32))
     c = np.zeros(1)
-    rc = lib.qfs_sweep(n, 1, pp, 1, C.c_void_p(16), C.c_void_p(16), 1, C.c_void_p(16), 0, 0.0,
-                       c.ctypes.data_as(C.c_void_p), None)
+    rc = lib.qfs_sweep(n, 1, pp, None, 1, C.c_void_p(16), C.c_void_p(16), 1, C.c_void_p(16), 0,
+                       0.0, c.ctypes.data_as(C.c_void_p), None)
     assert rc == Q.QFS_EINVAL
     tmpl = Q.Template(n, 1, pp)
     par = Q.Params()
@@ -83,6 +83,46 @@ def test_invalid_templates_rejected_without_device_work(pairs, n):
                              C.byref(res))
     assert rc == Q.QFS_EINVAL
     assert "template" in lib.qfs_last_error_detail().decode()
+
+
+@pytest.mark.parametrize("kinds,fixed", [([0, 3], None), ([0, -1], None), ([1, 2], None)])
+def test_invalid_gate_kinds_rejected_without_device_work(kinds, fixed):
+    """An unknown kind, or a constant gate without fixed_gates, is QFS_EINVAL."""
+    lib = Q.load()
+    arr = np.ascontiguousarray(np.asarray([(0, 1), (1, 2)], dtype=np.int32))
+    kd = np.ascontiguousarray(np.asarray(kinds, dtype=np.int32))
+    tmpl = Q.Template(3, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                      kd.ctypes.data_as(C.POINTER(C.c_int32)), fixed)
+    par = Q.Params()
+    lib.qfs_default_params(C.byref(par))
+    tgt = Q.Target()
+    tgt.kind = Q.QFS_TARGET_DENSE
+    tgt.U = C.c_void_p(16)
+    res = Q.Result()
+    rc = lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), None, C.c_void_p(16),
+                             C.byref(res))
+    assert rc == Q.QFS_EINVAL
+    assert "template" in lib.qfs_last_error_detail().decode()
+
+
+def test_gate_kinds_unsupported_in_batch_and_learned_entries():
+    """The batched engine and the sample-count network take two-qubit templates only."""
+    lib = Q.load()
+    arr = np.ascontiguousarray(np.asarray([(0, 1), (1, 2)], dtype=np.int32))
+    kd = np.ascontiguousarray(np.asarray([1, 0], dtype=np.int32))
+    tmpl = Q.Template(3, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                      kd.ctypes.data_as(C.POINTER(C.c_int32)), None)
+    par = Q.Params()
+    lib.qfs_default_params(C.byref(par))
+    tgt = Q.Target()
+    tgt.kind = Q.QFS_TARGET_DENSE
+    tgt.U = C.c_void_p(16)
+    res = Q.Result()
+    out = (C.c_void_p * 1)(16)
+    assert lib.qfs_instantiate_batch(1, C.byref(tmpl), C.byref(tgt), C.byref(par), out,
+                                     C.byref(res)) == Q.QFS_EUNSUPPORTED
+    f = np.zeros(64, dtype=np.float32)
+    assert lib.qfs_features(C.byref(tmpl), f.ctypes.data_as(C.c_void_p)) == Q.QFS_EUNSUPPORTED
 
 
 def test_invalid_params_rejected():
