@@ -78,15 +78,19 @@ def parse():
                     help="problems of the batched workload also run one by one")
     ap.add_argument("--learned", type=int, default=1024,
                     help="held-out problems for the learned-M comparison (0 skips it)")
+    ap.add_argument("--u3cx", type=int, default=1,
+                    help="1: also time the 12-qubit U3 + CNOT template (one-qubit variable gates "
+                         "around constant CNOTs); 0 skips it")
     ap.add_argument("--learned-large", type=int, default=0,
                     help="10-14 qubit random-pair problems (30-120 gates) for the learned-M "
                          "comparison through qfs_instantiate (0 skips it)")
     return ap.parse_args()
 
 
-def cpu_baseline(w, M, starts):
-    """The FP64 oracle on the host cores: one sweep plus the validation forward pass of
-    each of `cores` starts, one start per thread (a bounded sample of the workload)."""
+def cpu_baseline(w, M, starts, min_seconds=10.0, max_rounds=30):
+    """The FP64 oracle on the host cores: rounds of one sweep plus the validation forward
+    pass of each of `cores` starts, one start per thread, each start continuing from its
+    updated gates, until at least `min_seconds` (a bounded sample of the workload)."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -104,17 +108,77 @@ def cpu_baseline(w, M, starts):
     gates = [I.haar_gates(len(pairs), g) for _ in range(cores)]
 
     def one(s):
-        new, c = O.sweep(n, pairs, psi, phi, gates[s])
-        cv = O.state_distance(n, O.apply_circuit(n, psiv, pairs, new), phiv)
+        gates[s], c = O.sweep(n, pairs, psi, phi, gates[s])
+        cv = O.state_distance(n, O.apply_circuit(n, psiv, pairs, gates[s]), phiv)
         return c, cv
 
+    rounds = 0
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(one, range(cores)))
+        while rounds < max_rounds and (rounds == 0 or time.perf_counter() - t0 < min_seconds):
+            list(ex.map(one, range(cores)))
+            rounds += 1
     dt = time.perf_counter() - t0
-    return {"value": cores / dt, "unit": "start-sweeps/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 sweep + validation forward pass of each of {cores} starts "
-                      f"(one thread each), 12 qubits, 44 gates, M={M}, complex128; {dt:.1f} s"}
+    return {"value": rounds * cores / dt, "unit": "start-sweeps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{rounds} rounds of 1 sweep + validation forward pass of each of {cores} "
+                      f"starts (one thread each), 12 qubits, {len(pairs)} gates, M={M}, complex128; "
+                      f"{dt:.1f} s"}
+
+
+def u3_cnot(dev, M, S, steps, warmup, timing):
+    """The 12-qubit U3 + CNOT template (8 brickwork sublayers: 44 constant CNOTs and 100
+    variable one-qubit gates, 144 gates), Haar one-qubit target gates, M fixed, S lock-step
+    starts, MIXED precision: start-sweeps/s and the per-kernel classes; plus the
+    time-to-distance 1e-8 of the 8-qubit U3 + CNOT template (4 sublayers) with App. A
+    defaults (M from 2, doubling, 16 starts)."""
+    import torch
+
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import qfs as Q
+
+    w = I.workload_u3_cnot(12, 8)
+    n, pairs, kinds = 12, w["pairs"], w["kinds"]
+    tg = torch.as_tensor(w["target_gates"]).to(dev)
+    fx = torch.as_tensor(w["fixed"]).to(dev)
+    base = Q.qfs_default_params(multistarts=S, m_init=M, fixed_m=1, seed=0x5A17 + 8,
+                                precision=Q.QFS_PREC_MIXED, diff_tol_r=0.0, plateau_window=1 << 30)
+    kw = dict(target_pairs=pairs, target_gates=tg, kinds=kinds, fixed_gates=fx)
+    Q.qfs_instantiate(n, pairs, params=dict(base, max_iter=max(1, warmup)), **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = Q.qfs_instantiate(n, pairs, params=dict(base, max_iter=steps), **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L, nvar = len(pairs), int((kinds != I.GATE_FIXED).sum())
+    S_amp = M * (1 << n)
+    # algorithmic bytes per start-sweep: the B list entries before variable gates written
+    # and read once, plus phi, complex64
+    alg = 16.0 * S_amp * nvar + 8.0 * S_amp
+    out = {"workload": f"12q U3+CNOT, 8 sublayers ({L} gates: {nvar} variable one-qubit, "
+                       f"{L - nvar} constant CNOT), M={M} fixed, {S} lock-step starts, MIXED",
+           "start_sweeps_per_s": round(info["start_sweeps"] / dt, 2),
+           "ms_per_step": round(1e3 * dt / steps, 4),
+           "sweep_algorithmic_GBps": round(alg * info["start_sweeps"] / dt / 1e9, 1)}
+    if timing:
+        _, ti = Q.qfs_instantiate(n, pairs, params=dict(base, max_iter=steps, timing=1), **kw)
+        kl, ks, kb = ti["kernel_launches"], ti["kernel_seconds"], ti["kernel_bytes"]
+        out["kernel_classes"] = {
+            name: {"launches": kl[i], "seconds": round(ks[i], 5),
+                   "GBps": round(kb[i] / ks[i] / 1e9, 1) if ks[i] > 0 and kb[i] > 0 else None,
+                   "avg_us": round(1e6 * ks[i] / kl[i], 2) if kl[i] else None}
+            for i, name in enumerate(["bwd_step", "forward", "distance", "env_finalize_polar"])}
+    w8 = I.workload_u3_cnot(8, 4)
+    p = Q.qfs_default_params(multistarts=16, seed=9, max_iter=3000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = Q.qfs_instantiate(8, w8["pairs"], target_pairs=w8["pairs"],
+                             target_gates=torch.as_tensor(w8["target_gates"]).to(dev), params=p,
+                             kinds=w8["kinds"], fixed_gates=torch.as_tensor(w8["fixed"]).to(dev))
+    torch.cuda.synchronize()
+    out["time_to_distance_8q"] = {"seconds": round(time.perf_counter() - t0, 4), "reason": r["reason_name"],
+                                  "m_final": r["m_final"], "sweeps": r["sweeps"], "c_train": r["c_train"],
+                                  "start_sweeps": r["start_sweeps"]}
+    return out
 
 
 def time_to_distance(dev, graphs=0):
@@ -321,6 +385,8 @@ def main():
         "kernel_classes": classes,
         "final_c_train": info["c_train"], "final_c_val": info["c_val"],
     }
+    if args.u3cx:
+        extra["u3_cnot"] = u3_cnot(dev, M, S, args.steps, args.warmup, args.timing)
     if args.batched > 0:
         extra["batched"] = batched(dev, args.batched, args.plain_sample)
     if args.learned > 0 or args.learned_large > 0:
