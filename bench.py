@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--u3cx", type=int, default=1,
                     help="1: also time the 12-qubit U3 + CNOT template (one-qubit variable gates "
                          "around constant CNOTs); 0 skips it")
+    ap.add_argument("--qf", type=str, default="6,8,10,12",
+                    help="qubit counts of U3 + CNOT problems run with full-unitary QFactor and "
+                         "with QFactor-Sample (time to solution); empty skips it")
     ap.add_argument("--learned-large", type=int, default=0,
                     help="10-14 qubit random-pair problems (30-120 gates) for the learned-M "
                          "comparison through qfs_instantiate (0 skips it)")
@@ -179,6 +182,47 @@ def u3_cnot(dev, M, S, steps, warmup, timing):
                                   "m_final": r["m_final"], "sweeps": r["sweeps"], "c_train": r["c_train"],
                                   "start_sweeps": r["start_sweeps"]}
     return out
+
+
+def qf_vs_qfs(dev, sizes):
+    """Time to solution of full-unitary QFactor (params full_unitary: the complete basis,
+    M = 2^n) against QFactor-Sample (M from 2, doubling on the validation cost) on the same
+    MI355X and kernels: U3 + CNOT templates with 4 sublayers, Haar one-qubit target gates,
+    App. A defaults (16 starts, dist_tol 1e-8), MIXED precision, same seed. For the sample
+    method the full distance of the returned gates is measured on the device."""
+    import numpy as np
+    import torch
+
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import qfs as Q
+
+    rows = []
+    for n in sizes:
+        w = I.workload_u3_cnot(n, 4, seed_base=0x5A17 + 9)
+        tg = torch.as_tensor(w["target_gates"]).to(dev)
+        fx = torch.as_tensor(w["fixed"]).to(dev)
+        kw = dict(target_pairs=w["pairs"], target_gates=tg, kinds=w["kinds"], fixed_gates=fx)
+        row = {"n": n, "gates": len(w["pairs"])}
+        for name, full in (("qfs", 0), ("qf", 1)):
+            p = Q.qfs_default_params(seed=11 + n, full_unitary=full, time_budget_s=120.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g, r = Q.qfs_instantiate(n, w["pairs"], params=p, **kw)
+            torch.cuda.synchronize()
+            row[name] = {"seconds": round(time.perf_counter() - t0, 4), "reason": r["reason_name"],
+                         "sweeps": r["sweeps"], "m_final": r["m_final"], "c_train": r["c_train"],
+                         "start_sweeps": r["start_sweeps"]}
+            if not full:
+                N = 1 << n
+                basis = torch.eye(N, dtype=torch.complex128, device=dev)
+                got = Q.qfs_apply_gates(n, basis.clone(), w["pairs"], g)
+                want = Q.qfs_apply_gates(n, basis.clone(), w["pairs"], tg)
+                row[name]["d_full"] = Q.qfs_state_distance(n, got, want)
+        row["speedup"] = round(row["qf"]["seconds"] / row["qfs"]["seconds"], 2)
+        rows.append(row)
+    ok = [r["speedup"] for r in rows if r["qf"]["reason"] == r["qfs"]["reason"] == "SUCCESS"]
+    return {"problems": rows,
+            "mean_speedup_both_succeeded": round(float(np.mean(ok)), 2) if ok else None}
 
 
 def time_to_distance(dev, graphs=0):
@@ -387,6 +431,8 @@ def main():
     }
     if args.u3cx:
         extra["u3_cnot"] = u3_cnot(dev, M, S, args.steps, args.warmup, args.timing)
+    if args.qf:
+        extra["qf_vs_qfs"] = qf_vs_qfs(dev, [int(x) for x in args.qf.split(",") if x])
     if args.batched > 0:
         extra["batched"] = batched(dev, args.batched, args.plain_sample)
     if args.learned > 0 or args.learned_large > 0:

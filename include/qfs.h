@@ -147,6 +147,12 @@ typedef struct {
                                 (re-captured when the running starts, M or the
                                 precision change); 0 (default) launches every
                                 kernel, which measured faster on MI355X / ROCm 7   */
+  int32_t full_unitary;      /* qfs_instantiate: 1 runs full-unitary QFactor
+                                (Sec. 2.1): the training set is the complete
+                                computational basis (M = 2^n, no validation set),
+                                so c_train is the full distance (Eq. 1 / 2^n) and
+                                each sweep is QFactor's; DENSE and CIRCUIT targets
+                                only; m_init, fixed_m and m_val are ignored        */
 } qfs_params;
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,

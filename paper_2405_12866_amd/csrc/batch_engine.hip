@@ -132,6 +132,10 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     set_error_detail("batch: params out of range");
     return QFS_EINVAL;
   }
+  if (p.full_unitary) {
+    set_error_detail("batch: full_unitary is a qfs_instantiate mode");
+    return QFS_EUNSUPPORTED;
+  }
   const int S = p.multistarts;
   if (opts.independent && !p.fixed_m) {
     set_error_detail("batch: independent starts need fixed_m");

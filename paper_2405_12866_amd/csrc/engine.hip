@@ -644,6 +644,8 @@ int Group::run(GroupResult &out, double t_start) {
   }
   M_ = std::max(1, std::min(p_.m_init, m_cap_));
   if (p_.fixed_m) m_cap_ = M_;
+  const bool full_unitary = p_.full_unitary != 0;
+  if (full_unitary) M_ = m_cap_ = (int)N_;
   ldm_ = master_ld(M_);
   fp64_ = p_.precision != QFS_PREC_MIXED;
   timer_.on = p_.timing != 0;
@@ -670,11 +672,18 @@ int Group::run(GroupResult &out, double t_start) {
                                        psi64_.as<c128>(), stream_));
     QFS_TRY(launch_to_internal<double>(n_, M_, ceil_log2(ldm_), 1, reinterpret_cast<const c128 *>(tgt_->phi),
                                        phi64_.as<c128>(), stream_));
+  } else if (full_unitary) {
+    // full-unitary QFactor: the computational basis, so phi holds U's columns
+    QFS_TRY(launch_unit_columns(N_, ldm_, psi64_.as<c128>(), stream_));
+    QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
   } else {
     QFS_TRY(draw_training(0, M_));
     QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
   }
-  QFS_TRY(draw_validation());
+  if (full_unitary)
+    Mv_ = 0;
+  else
+    QFS_TRY(draw_validation());
 
   // initial gates (App. A: random per start from the seed, or given)
   QFS_TRY(arena_.alloc(g64_, sizeof(c128) * 16 * (size_t)L_ * S_));
@@ -1046,6 +1055,7 @@ void qfs_default_params(qfs_params *p) {
   p->batch_sweeps = 0;
   p->batch_threads = 0;
   p->graphs = 0;
+  p->full_unitary = 0;
 }
 
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
@@ -1061,8 +1071,12 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
   if (p.multistarts < 1 || p.m_init < 1 || p.m_init > N || p.max_iter < 1 || p.plateau_window < 1 ||
       !(p.dist_tol >= 0) || !(p.diff_tol_r >= 0) || !(p.overtrain_ratio >= 0) || !(p.beta >= 0) ||
       !(p.beta <= 1) || (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) ||
-      p.m_val < 0 || p.m_val > N) {
+      p.m_val < 0 || p.m_val > N || (p.full_unitary != 0 && p.full_unitary != 1)) {
     set_error_detail("params out of range");
+    return QFS_EINVAL;
+  }
+  if (p.full_unitary && target->kind == QFS_TARGET_SAMPLES) {
+    set_error_detail("full_unitary needs a DENSE or CIRCUIT target");
     return QFS_EINVAL;
   }
   switch (target->kind) {

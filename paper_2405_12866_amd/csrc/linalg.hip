@@ -430,4 +430,19 @@ int launch_zero(void *p, size_t bytes, hipStream_t s) {
   return QFS_OK;
 }
 
+// Columns 0..N-1 of the N x ld matrix A set to the computational basis (A zeroed before):
+// A[i][i] = 1.
+__global__ void k_unit_columns(int64_t N, int64_t ld, c128 *A) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    A[i * ld + i] = cmake(1.0, 0.0);
+}
+
+int launch_unit_columns(int64_t N, int64_t ld, c128 *A, hipStream_t s) {
+  if (N <= 0 || ld < N) return QFS_EINVAL;
+  hipLaunchKernelGGL(k_unit_columns, dim3((unsigned)std::min<int64_t>((N + 255) / 256, 4096)), dim3(256), 0,
+                     s, N, ld, A);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
 }  // namespace qfs

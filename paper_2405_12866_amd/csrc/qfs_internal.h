@@ -168,6 +168,8 @@ template <typename R>
 int launch_from_internal(int n, int64_t M, int logC, const cx<R> *src, c128 *dst, hipStream_t s);
 int launch_narrow(int64_t count, const c128 *src, c64 *dst, hipStream_t s);
 int launch_zero(void *p, size_t bytes, hipStream_t s);
+// A[i][i] = 1 for i < N in an N x ld complex128 matrix (the computational basis as columns).
+int launch_unit_columns(int64_t N, int64_t ld, c128 *A, hipStream_t s);
 
 // ------------------------------------------------------------------ sweep kernels
 // Per-start addressing for the sweep kernels: a buffer of starts is at
