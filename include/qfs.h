@@ -153,6 +153,10 @@ typedef struct {
                                 so c_train is the full distance (Eq. 1 / 2^n) and
                                 each sweep is QFactor's; DENSE and CIRCUIT targets
                                 only; m_init, fixed_m and m_val are ignored        */
+  int32_t beta_normalized;   /* 1: the regularised update (App. A Beta) mixes the
+                                environment divided by the current M with the gate,
+                                polar((1 - beta) Gamma / M + beta u), so beta keeps
+                                its meaning as M changes; 0: the paper's form       */
 } qfs_params;
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,

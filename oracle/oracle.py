@@ -54,6 +54,7 @@ class Params(C.Structure):
         ("seed", C.c_uint64),
         ("fixed_m", C.c_int32),
         ("m_val", C.c_int32),
+        ("beta_normalized", C.c_int32),
     ]
 
 
@@ -88,7 +89,7 @@ def default_params(**kw) -> dict:
     M0 2, overtrain_ratio 0.1, min_iter 6, max_iter 1e4, 16 multistarts, beta 0)."""
     p = dict(dist_tol=1e-8, diff_tol_r=1e-5, plateau_window=5, min_iter=6, max_iter=10000,
              m_init=2, m_max=0, overtrain_ratio=0.1, multistarts=16, beta=0.0, seed=0,
-             fixed_m=0, m_val=0)
+             fixed_m=0, m_val=0, beta_normalized=0)
     p.update(kw)
     return p
 
@@ -124,7 +125,8 @@ def load():
         lib.qo_update_gate1.argtypes = [P, C.c_double, P]
         lib.qo_state_distance.argtypes = [C.c_int, C.c_int, P, P]
         lib.qo_state_distance.restype = C.c_double
-        lib.qo_sweep.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, C.c_double, P, P, P]
+        lib.qo_sweep.argtypes = [C.c_int, C.c_int, P, P, C.c_int, P, P, P, C.c_double, C.c_double,
+                                 P, P, P]
         lib.qo_sweep.restype = C.c_double
         lib.qo_instantiate.argtypes = [C.c_int, C.c_int, P, P, P, C.c_int, P, C.c_int, P, P, P, P,
                                        C.c_int, C.c_int, C.POINTER(Params), P, P,
@@ -282,9 +284,10 @@ def state_distance(n, x, y):
     return load().qo_state_distance(n, xx.shape[0], _p(xx), _p(yy))
 
 
-def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False, kinds=None):
+def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False, kinds=None, gamma_scale=1.0):
     """One sweep; returns (new_gates, c_train) or, with record, also f_before, f_after
-    and the environments. kinds: per-gate GATE_2Q / GATE_1Q / GATE_FIXED (None: all 2Q)."""
+    and the environments. kinds: per-gate GATE_2Q / GATE_1Q / GATE_FIXED (None: all 2Q).
+    gamma_scale multiplies each environment before the beta mix (1/M: normalised)."""
     pr = _pairs(pairs)
     L = pr.shape[0]
     kd = _kinds(kinds, L)
@@ -293,7 +296,8 @@ def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False, kinds=None):
     fb = np.zeros(L) if record else None
     fa = np.zeros(L) if record else None
     gam = np.zeros((L, 4, 4), dtype=np.complex128) if record else None
-    c = load().qo_sweep(n, L, _p(pr), _p(kd), ps.shape[0], _p(ps), _p(ph), _p(g), beta, _p(fb),
+    c = load().qo_sweep(n, L, _p(pr), _p(kd), ps.shape[0], _p(ps), _p(ph), _p(g), beta,
+                        gamma_scale, _p(fb),
                         _p(fa), _p(gam))
     if record:
         return g, c, fb, fa, gam

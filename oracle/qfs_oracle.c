@@ -448,7 +448,7 @@ static double qo_re_tr_gdag_v(const qo_cplx G[4], const qo_cplx u[16]) {
  * updated from its 2x2 environment. */
 double qo_sweep(int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
                 const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
-                double *f_before, double *f_after, qo_cplx *gammas) {
+                double gamma_scale, double *f_before, double *f_after, qo_cplx *gammas) {
   const int64_t N = (int64_t)1 << n;
   const int64_t S = (int64_t)M * N;
   qo_cplx *B = (qo_cplx *)malloc(sizeof(qo_cplx) * S * (size_t)L);
@@ -462,17 +462,19 @@ double qo_sweep(int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
   memcpy(a, phi, sizeof(qo_cplx) * S);
   for (int k = L - 1; k >= 0; --k) {
     const int kind = kinds ? kinds[k] : QO_GATE_2Q;
-    qo_cplx G[16];
+    qo_cplx G[16], Gs[16];
     for (int e = 0; e < 16; ++e) G[e] = 0.0;
     if (kind == QO_GATE_2Q) {
       qo_environment(n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
+      for (int e = 0; e < 16; ++e) Gs[e] = gamma_scale * G[e];
       if (f_before) f_before[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
-      qo_update_gate(G, beta, gates + 16 * k);
+      qo_update_gate(Gs, beta, gates + 16 * k);
       if (f_after) f_after[k] = qo_re_tr_gdag_u(G, gates + 16 * k);
     } else if (kind == QO_GATE_1Q) {
       qo_environment1(n, M, a, B + (size_t)k * S, pairs[2 * k], G);
+      for (int e = 0; e < 4; ++e) Gs[e] = gamma_scale * G[e];
       if (f_before) f_before[k] = qo_re_tr_gdag_v(G, gates + 16 * k);
-      qo_update_gate1(G, beta, gates + 16 * k);
+      qo_update_gate1(Gs, beta, gates + 16 * k);
       if (f_after) f_after[k] = qo_re_tr_gdag_v(G, gates + 16 * k);
     } else {
       if (f_before) f_before[k] = NAN;
@@ -621,7 +623,8 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
     for (int s = 0; s < S; ++s) {
       if (status[s] != ST_RUNNING) continue;
       qo_cplx *g = gates + 16 * (size_t)s * L;
-      c_tr[s] = qo_sweep(n, L, pairs, kinds, M, psi, phi, g, p->beta, NULL, NULL, NULL);
+      c_tr[s] = qo_sweep(n, L, pairs, kinds, M, psi, phi, g, p->beta,
+                         p->beta_normalized ? 1.0 / (double)M : 1.0, NULL, NULL, NULL);
       c_v[s] = Mv > 0 ? qo_forward_cost(n, L, pairs, Mv, psiv, phiv, g) : c_tr[s];
     }
     const int full = (M == (int)N);

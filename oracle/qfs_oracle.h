@@ -68,6 +68,7 @@ typedef struct {
   uint64_t seed;          /* App. A: seed                                      */
   int32_t fixed_m;        /* 1: never double M                                 */
   int32_t m_val;          /* validation-set size; 0 means M                    */
+  int32_t beta_normalized; /* 1: mix the environment divided by M with u       */
 } qo_params;
 
 typedef struct {
@@ -137,12 +138,14 @@ void qo_update_gate1(const qo_cplx G[4], double beta, qo_cplx u[16]);
 double qo_state_distance(int n, int M, const qo_cplx *x, const qo_cplx *y);
 
 /* One sweep (forward B list, right-to-left update). Returns c_train after the sweep.
- * kinds: [L] or NULL (all QO_GATE_2Q). Optional outputs: per gate f = Re Tr(G^dagger u)
+ * kinds: [L] or NULL (all QO_GATE_2Q). gamma_scale multiplies each environment before the
+ * regularised mix (1: the paper's form; 1/M: normalised). Optional outputs: per gate
+ * f = Re Tr(G^dagger u)
  * before/after its update (NaN for a fixed gate), and each environment G ([L][16]; a
  * one-qubit gate's 2x2 in the first 4 entries, a fixed gate's all zero). */
 double qo_sweep(int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
                 const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
-                double *f_before, double *f_after, qo_cplx *gammas);
+                double gamma_scale, double *f_before, double *f_after, qo_cplx *gammas);
 
 /* Full instantiation with the paper's control loop. kinds: [L] or NULL; fixed: [L][16]
  * constant gates (read for QO_GATE_FIXED; replace those slots of gates_in too). */

@@ -58,6 +58,7 @@ struct BParams {
   int64_t max_iter;
   int32_t mixed;
   int32_t independent;  // every start runs to its own stop (no problem-level pause)
+  int32_t beta_normalized;  // mix Gamma / M (effective_beta of the problem's M)
 };
 
 struct BatchArgs {

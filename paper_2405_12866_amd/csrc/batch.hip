@@ -321,6 +321,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
   c128 *g64 = P.g64 + (size_t)J.start * L * 16;
   c128 *vst = P.vst + (size_t)J.start * L * 16;
   const BParams &hp = A.hp;
+  const double beta = effective_beta(hp.beta, hp.beta_normalized != 0, M);
 
   // gate k of this job in R precision: resident in LDS (short templates), or staged
   // from the FP64 master into the slot gl
@@ -433,7 +434,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
       // the new gate k goes to the FP64 master and (state precision) to its LDS slot;
       // the old one has served its last use (B_k above)
       cx<R> *unew = resident ? gates_l + k * 16 : gl;
-      if (threadIdx.x < 64) batch_polar<R>(sh.gam, hp.beta, g64 + k * 16, unew, vst + k * 16, sh.pg, sh.pv, sh.ps);
+      if (threadIdx.x < 64) batch_polar<R>(sh.gam, beta, g64 + k * 16, unew, vst + k * 16, sh.pg, sh.pv, sh.ps);
       __syncthreads();
     }
     // cost of the updated gates: a_0 = u_0^dag a

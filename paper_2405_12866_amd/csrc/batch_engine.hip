@@ -317,6 +317,7 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
   bp.diff_tol_r = p.diff_tol_r;
   bp.overtrain_ratio = p.overtrain_ratio;
   bp.beta = p.beta;
+  bp.beta_normalized = p.beta_normalized != 0;
   bp.refine_below = p.refine_below;
   bp.plateau_window = p.plateau_window;
   bp.min_iter = p.min_iter;

@@ -711,7 +711,7 @@ int Group::run(GroupResult &out, double t_start) {
   c.g64 = g64_.as<c128>();
   c.g32 = g32_.as<c64>();
   c.vstore = vstore_.as<c128>();
-  c.beta = p_.beta;
+  c.beta = effective_beta(p_.beta, p_.beta_normalized != 0, M_);
   c.partials = partials_.as<c128>();
   c.dpart0 = dpart_.as<double>();
   c.dpart1 = dpart_.as<double>() + (size_t)kPcap * S_;
@@ -857,6 +857,7 @@ int Group::run(GroupResult &out, double t_start) {
         QFS_TRY(draw_validation());
       }
       QFS_TRY(setup_working());
+      ctx_.beta = effective_beta(p_.beta, p_.beta_normalized != 0, M_);
       m_total += M_;
       ++restarts;
       active.clear();
@@ -1056,6 +1057,7 @@ void qfs_default_params(qfs_params *p) {
   p->batch_threads = 0;
   p->graphs = 0;
   p->full_unitary = 0;
+  p->beta_normalized = 0;
 }
 
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
@@ -1071,7 +1073,8 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
   if (p.multistarts < 1 || p.m_init < 1 || p.m_init > N || p.max_iter < 1 || p.plateau_window < 1 ||
       !(p.dist_tol >= 0) || !(p.diff_tol_r >= 0) || !(p.overtrain_ratio >= 0) || !(p.beta >= 0) ||
       !(p.beta <= 1) || (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) ||
-      p.m_val < 0 || p.m_val > N || (p.full_unitary != 0 && p.full_unitary != 1)) {
+      p.m_val < 0 || p.m_val > N || (p.full_unitary != 0 && p.full_unitary != 1) ||
+      (p.beta_normalized != 0 && p.beta_normalized != 1)) {
     set_error_detail("params out of range");
     return QFS_EINVAL;
   }

@@ -171,6 +171,16 @@ int launch_zero(void *p, size_t bytes, hipStream_t s);
 // A[i][i] = 1 for i < N in an N x ld complex128 matrix (the computational basis as columns).
 int launch_unit_columns(int64_t N, int64_t ld, c128 *A, hipStream_t s);
 
+// The regularised update with the environment normalised by M, polar((1 - beta) G / M +
+// beta u), is the paper's unnormalised form polar((1 - b) G + b u) at
+// b = beta M / ((1 - beta) + beta M): the two mixes differ by the positive factor
+// (1 - beta) + beta M, and the polar factor ignores a positive scale.
+__host__ __device__ inline double effective_beta(double beta, bool normalized, int M) {
+  if (!normalized || beta <= 0.0 || beta >= 1.0) return beta;
+  const double bm = beta * (double)M;
+  return bm / ((1.0 - beta) + bm);
+}
+
 // ------------------------------------------------------------------ sweep kernels
 // Per-start addressing for the sweep kernels: a buffer of starts is at
 // base + stride * start (elements); stride 0 means shared by all starts.

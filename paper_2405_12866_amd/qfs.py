@@ -51,7 +51,8 @@ class Params(C.Structure):
                 ("refine_below", C.c_double), ("device_mem_budget", C.c_uint64),
                 ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p),
                 ("timing", C.c_int32), ("batch_sweeps", C.c_int32), ("batch_threads", C.c_int32),
-                ("graphs", C.c_int32), ("full_unitary", C.c_int32)]
+                ("graphs", C.c_int32), ("full_unitary", C.c_int32),
+                ("beta_normalized", C.c_int32)]
 
 
 class Result(C.Structure):

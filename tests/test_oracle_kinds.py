@@ -4,9 +4,10 @@ QFactor updates gates of any size directly as unitaries (Sec. 2.1), and the pape
 circuits are U3 + CNOT partitions (Sec. 4). A one-qubit gate v on qubit a is held as
 the 4x4 slot v (x) I_2 on (a, spectator); its environment is the 2x2 contraction over
 the other n-1 qubits and its update the polar factor of that 2x2 (Eq. 2). A constant
-gate is applied and never updated. The checks go through full 2^n x 2^n matrices,
-SciPy's polar decomposition, the full-unitary QFactor sweep of the dense checker,
-closed forms and invariants.
+gate is applied and never updated. Also the regularised update with the environment
+normalised by M (App. A Beta, with E / M in place of E). The checks go through full
+2^n x 2^n matrices, SciPy's polar decomposition, the full-unitary QFactor sweep of the
+dense checker, closed forms and invariants.
 """
 import numpy as np
 import pytest
@@ -213,3 +214,47 @@ def test_u3_cnot_template_is_recovered(n, sub):
     U = D.circuit_matrix(n, w["target_pairs"], w["target_gates"])
     C = D.circuit_matrix(n, w["pairs"], gates)
     assert D.full_distance(U, C) < 1e-9
+
+
+# ------------------------------------------------ beta with the environment normalised by M
+def _beta_problem(seed, kinds=None):
+    n, L, M = 4, 6, 5
+    g = np.random.default_rng(seed)
+    pairs = I.random_pair_template(n, L, g)
+    kinds = np.zeros(L, np.int32) if kinds is None else np.asarray(kinds, np.int32)
+    fixed = np.stack([I.haar_unitary(4, g) for _ in range(L)])
+    tg = I.kinds_target_gates(kinds, fixed, g)
+    psi = I.orthonormal_samples(n, M, g)
+    phi = O.apply_circuit(n, psi, pairs, tg)
+    return n, pairs, kinds, psi, phi, O.initial_gates(seed, 0, kinds, fixed), M
+
+
+def test_normalised_beta_is_scipy_polar_of_scaled_mix():
+    """With the environment divided by M, gate k's update is the unitary factor of
+    (1 - beta) Gamma_k / M + beta u_k (SciPy), Gamma_k taken from the recorded sweep."""
+    n, pairs, kinds, psi, phi, g0, M = _beta_problem(21)
+    beta = 0.4
+    new, _, _, _, gam = O.sweep(n, pairs, psi, phi, g0, beta=beta, record=True, gamma_scale=1.0 / M)
+    for k in range(len(pairs)):
+        old = g0[k]
+        want = scipy.linalg.polar((1 - beta) * gam[k] / M + beta * old, side="right")[0]
+        assert np.allclose(new[k], want, atol=1e-12)
+
+
+def test_normalised_beta_limits_and_effective_beta():
+    """beta = 0: the normalisation changes nothing (the polar factor ignores a positive
+    scale); beta = 1: no update; and for any beta the normalised update equals the paper's
+    unnormalised one at beta' = beta M / ((1 - beta) + beta M), since the two mixes differ
+    by the positive factor (1 - beta) + beta M."""
+    for kinds in (None, [1, 0, 2, 1, 0, 1]):
+        n, pairs, kinds, psi, phi, g0, M = _beta_problem(22, kinds)
+        a, ca = O.sweep(n, pairs, psi, phi, g0, kinds=kinds)
+        b, cb = O.sweep(n, pairs, psi, phi, g0, kinds=kinds, gamma_scale=1.0 / M)
+        assert np.allclose(a, b, atol=1e-12) and abs(ca - cb) < 1e-12
+        c, _ = O.sweep(n, pairs, psi, phi, g0, beta=1.0, kinds=kinds, gamma_scale=1.0 / M)
+        assert np.allclose(c, g0, atol=1e-13)
+        beta = 0.3
+        beta_eff = beta * M / ((1 - beta) + beta * M)
+        d, cd = O.sweep(n, pairs, psi, phi, g0, beta=beta, kinds=kinds, gamma_scale=1.0 / M)
+        e, ce = O.sweep(n, pairs, psi, phi, g0, beta=beta_eff, kinds=kinds)
+        assert np.allclose(d, e, atol=1e-12) and abs(cd - ce) < 1e-12
