@@ -245,8 +245,9 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target,
  *   tmpl, targets: host arrays [P] (targets' device pointers as in qfs_instantiate).
  *   gates_out: host array [P] of device pointers [L_p][4][4] (NULL entries skipped).
  *   res: host [P].
- * Limits: 2 <= n_qubits <= 10 per problem (QFS_EUNSUPPORTED above); two-qubit gates
- * only (QFS_EUNSUPPORTED for a template with other gate kinds). */
+ * Templates may hold one-qubit and constant gates (kinds, fixed_gates as in
+ * qfs_instantiate; initial one-qubit gates drawn the same way).
+ * Limits: 2 <= n_qubits <= 10 per problem (QFS_EUNSUPPORTED above). */
 int qfs_instantiate_batch(int32_t P, const qfs_template *tmpl, const qfs_target *targets,
                           const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res);
 

@@ -30,6 +30,8 @@ struct BProb {
   int32_t n_train;      // SAMPLES: training rows available
   uint64_t seed;
   const int32_t *pairs;   // device [L][2]
+  const int32_t *kinds;   // device [L] gate kinds (nullptr: all two-qubit)
+  const c128 *fixed;      // device [L][16] constant gates (read at QFS_GATE_FIXED)
   const int32_t *tpairs;  // device [Lt][2]
   const c128 *tgates;     // device [Lt][16]
   const c128 *U;          // DENSE target

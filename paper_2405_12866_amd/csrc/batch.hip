@@ -14,6 +14,7 @@
 
 #include "batch.h"
 #include "philox.h"
+#include "polar2.h"
 
 namespace qfs {
 
@@ -386,6 +387,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
     __syncthreads();
     for (int k = L - 1; k >= 0; --k) {
       const int pa = n - 1 - pairs[2 * k], pb = n - 1 - pairs[2 * k + 1];
+      const int kind = P.kinds ? P.kinds[k] : QFS_GATE_2Q;
       if (k < L - 1) {
         const cx<R> *u1 = gate(k + 1);  // already updated
         const int qa = n - 1 - pairs[2 * (k + 1)], qb = n - 1 - pairs[2 * (k + 1) + 1];
@@ -395,6 +397,7 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
       const cx<R> *u0 = gate(k);  // not yet updated
       apply_states<R, NT>(bufB, M, n, pa, pb, u0, true);  // B_k
       __syncthreads();
+      if (kind == QFS_GATE_FIXED) continue;  // applied only, no environment
       // environment of gate k
       cx<R> acc[16];
 #pragma unroll
@@ -434,7 +437,11 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
       // the new gate k goes to the FP64 master and (state precision) to its LDS slot;
       // the old one has served its last use (B_k above)
       cx<R> *unew = resident ? gates_l + k * 16 : gl;
-      if (threadIdx.x < 64) batch_polar<R>(sh.gam, beta, g64 + k * 16, unew, vst + k * 16, sh.pg, sh.pv, sh.ps);
+      if (kind == QFS_GATE_1Q) {
+        if (threadIdx.x == 0) polar2_update<R>(sh.gam, beta, g64 + k * 16, unew);
+      } else if (threadIdx.x < 64) {
+        batch_polar<R>(sh.gam, beta, g64 + k * 16, unew, vst + k * 16, sh.pg, sh.pv, sh.ps);
+      }
       __syncthreads();
     }
     // cost of the updated gates: a_0 = u_0^dag a
@@ -643,6 +650,32 @@ __global__ void k_batch_gates(BProb *probs, const int32_t *prob_of, const int32_
   const BProb &P = probs[pidx];
   const int local = t - first_gate[pidx];
   const int s = local / P.L, k = local % P.L;
+  const int kind = P.kinds ? P.kinds[k] : QFS_GATE_2Q;
+  c128 *u = P.g64 + ((size_t)s * P.L + k) * 16;
+  c128 *v = P.vst + ((size_t)s * P.L + k) * 16;
+  for (int e = 0; e < 16; ++e) v[e] = cmake((e % 5 == 0) ? 1.0 : 0.0, 0.0);
+  if (kind == QFS_GATE_FIXED) {
+    for (int e = 0; e < 16; ++e) u[e] = P.fixed[(size_t)k * 16 + e];
+    return;
+  }
+  if (kind == QFS_GATE_1Q) {
+    // v (x) I_2 with v Haar on U(2) from indices 16 k + 2 col + row of the same stream
+    c128 h[2][2];
+    for (int c = 0; c < 2; ++c)
+      for (int r = 0; r < 2; ++r) h[c][r] = complex_normal(P.seed, 3u, (uint32_t)s, (uint64_t)k * 16u + 2u * c + r);
+    for (int c = 0; c < 2; ++c) {
+      for (int rep = 0; rep < 2; ++rep)
+        for (int o = 0; o < c; ++o) {
+          const c128 d = cconj(h[o][0]) * h[c][0] + cconj(h[o][1]) * h[c][1];
+          for (int r = 0; r < 2; ++r) h[c][r] = h[c][r] - d * h[o][r];
+        }
+      const double inv = 1.0 / sqrt(cabs2(h[c][0]) + cabs2(h[c][1]));
+      for (int r = 0; r < 2; ++r) h[c][r] = cscale(h[c][r], inv);
+    }
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) u[r * 4 + c] = ((r & 1) == (c & 1)) ? h[c >> 1][r >> 1] : cmake(0.0, 0.0);
+    return;
+  }
   c128 q[4][4];
   for (int c = 0; c < 4; ++c)
     for (int r = 0; r < 4; ++r) q[c][r] = complex_normal(P.seed, 3u, (uint32_t)s, (uint64_t)k * 16u + 4u * c + r);
@@ -658,13 +691,8 @@ __global__ void k_batch_gates(BProb *probs, const int32_t *prob_of, const int32_
     const double inv = 1.0 / sqrt(nrm);
     for (int r = 0; r < 4; ++r) q[c][r] = cscale(q[c][r], inv);
   }
-  c128 *u = P.g64 + ((size_t)s * P.L + k) * 16;
-  c128 *v = P.vst + ((size_t)s * P.L + k) * 16;
   for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) {
-      u[r * 4 + c] = q[c][r];
-      v[r * 4 + c] = cmake(r == c ? 1.0 : 0.0, 0.0);
-    }
+    for (int c = 0; c < 4; ++c) u[r * 4 + c] = q[c][r];
 }
 
 }  // namespace

@@ -149,7 +149,8 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
 
   // ---------------------------------------------------------------- validation + sizes
   std::vector<BProb> hp(P);
-  std::vector<size_t> off_psi(P), off_psiv(P), off_coef(P), off_g(P), off_pairs(P), off_tpairs(P);
+  std::vector<size_t> off_psi(P), off_psiv(P), off_coef(P), off_g(P), off_pairs(P), off_tpairs(P),
+      off_kinds(P);
   size_t c128s = 0, ints = 0;
   for (int i = 0; i < P; ++i) {
     const qfs_template &t = tmpl[i];
@@ -164,9 +165,16 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         set_error_detail("batch: problem " + std::to_string(i) + ": invalid qubit pair");
         return QFS_EINVAL;
       }
-      if (t.kinds && t.kinds[k] != QFS_GATE_2Q) {
-        set_error_detail("batch: problem " + std::to_string(i) + ": only two-qubit variable gates");
-        return QFS_EUNSUPPORTED;
+      if (t.kinds) {
+        const int kind = t.kinds[k];
+        if (kind != QFS_GATE_2Q && kind != QFS_GATE_1Q && kind != QFS_GATE_FIXED) {
+          set_error_detail("batch: problem " + std::to_string(i) + ": unknown gate kind");
+          return QFS_EINVAL;
+        }
+        if (kind == QFS_GATE_FIXED && !t.fixed_gates) {
+          set_error_detail("batch: problem " + std::to_string(i) + ": constant gates need fixed_gates");
+          return QFS_EINVAL;
+        }
       }
     }
     const int N = 1 << t.n_qubits;
@@ -231,6 +239,15 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     ints += 2 * (size_t)t.n_gates;
     off_tpairs[i] = ints;
     ints += 2 * (size_t)d.Lt;
+    off_kinds[i] = ints;
+    if (t.kinds) ints += (size_t)t.n_gates;
+  }
+  for (int i = 0; i < P; ++i) {
+    bool any_fixed = false;
+    for (int k = 0; tmpl[i].kinds && k < tmpl[i].n_gates; ++k) any_fixed |= tmpl[i].kinds[k] == QFS_GATE_FIXED;
+    if (any_fixed)
+      QFS_TRY(check_gates_unitary(tmpl[i].fixed_gates, (size_t)tmpl[i].n_gates, tmpl[i].n_gates, tmpl[i].kinds,
+                                  true, "fixed_gates", st));
   }
   // ---------------------------------------------------------------- device memory
   size_t fr = 0, tot = 0;
@@ -261,6 +278,11 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     d.vst = d.g64 + (size_t)S * d.L * 16;
     std::memcpy(hints.data() + off_pairs[i], tmpl[i].pairs, sizeof(int32_t) * 2 * d.L);
     d.pairs = ibase + off_pairs[i];
+    if (tmpl[i].kinds) {
+      std::memcpy(hints.data() + off_kinds[i], tmpl[i].kinds, sizeof(int32_t) * d.L);
+      d.kinds = ibase + off_kinds[i];
+      d.fixed = reinterpret_cast<const c128 *>(tmpl[i].fixed_gates);
+    }
     if (d.kind == QFS_TARGET_CIRCUIT && d.Lt > 0) {
       std::memcpy(hints.data() + off_tpairs[i], targets[i].circuit->pairs, sizeof(int32_t) * 2 * d.Lt);
       d.tpairs = ibase + off_tpairs[i];

@@ -953,6 +953,22 @@ int run_split(const qfs_template *t, const qfs_target *tg, const qfs_params &p,
   return QFS_OK;
 }
 
+// A per-gate (unfused) chunked geometry for the step entry points.
+Geometry api_geometry(int n, int M) {
+  const int logC = choose_log_chunk(n, M, sizeof(double), false, 1, 0);
+  const int C = 1 << logC;
+  return Geometry{n, 1 << n, logC, (M + C - 1) / C, M};
+}
+
+int one_slot(DevBuf &slot, hipStream_t s) {
+  int32_t zero = 0;
+  QFS_TRY(slot.alloc(sizeof(int32_t)));
+  QFS_HIP(hipMemcpyAsync(slot.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  return QFS_OK;
+}
+
+}  // namespace
+
 // Gate slots [count][4][4] (gate index gi % L of the template) must be unitary to 1e-10,
 // and a one-qubit slot must have the form v (x) I_2. fixed_only: check the constant gates
 // only (the template's fixed_gates); else every slot but the constant gates' (gates_in).
@@ -994,21 +1010,6 @@ int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, int L, const in
   return QFS_OK;
 }
 
-// A per-gate (unfused) chunked geometry for the step entry points.
-Geometry api_geometry(int n, int M) {
-  const int logC = choose_log_chunk(n, M, sizeof(double), false, 1, 0);
-  const int C = 1 << logC;
-  return Geometry{n, 1 << n, logC, (M + C - 1) / C, M};
-}
-
-int one_slot(DevBuf &slot, hipStream_t s) {
-  int32_t zero = 0;
-  QFS_TRY(slot.alloc(sizeof(int32_t)));
-  QFS_HIP(hipMemcpyAsync(slot.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  return QFS_OK;
-}
-
-}  // namespace
 }  // namespace qfs
 
 using namespace qfs;

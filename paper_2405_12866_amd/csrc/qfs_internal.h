@@ -171,6 +171,12 @@ int launch_zero(void *p, size_t bytes, hipStream_t s);
 // A[i][i] = 1 for i < N in an N x ld complex128 matrix (the computational basis as columns).
 int launch_unit_columns(int64_t N, int64_t ld, c128 *A, hipStream_t s);
 
+// Host check of gate slots [count][4][4] (gate gi % L of a template with the given kinds):
+// unitary to 1e-10 and, for one-qubit gates, of the form v (x) I_2. fixed_only: only the
+// constant gates; else every gate but those. QFS_EINVAL with a detail naming `what`.
+int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, int L, const int32_t *kinds,
+                        bool fixed_only, const char *what, hipStream_t s);
+
 // The regularised update with the environment normalised by M, polar((1 - beta) G / M +
 // beta u), is the paper's unnormalised form polar((1 - b) G + b u) at
 // b = beta M / ((1 - beta) + beta M): the two mixes differ by the positive factor

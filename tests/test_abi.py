@@ -105,8 +105,9 @@ def test_invalid_gate_kinds_rejected_without_device_work(kinds, fixed):
     assert "template" in lib.qfs_last_error_detail().decode()
 
 
-def test_gate_kinds_unsupported_in_batch_and_learned_entries():
-    """The batched engine and the sample-count network take two-qubit templates only."""
+def test_gate_kinds_unsupported_in_learned_entries():
+    """The sample-count network takes two-qubit templates only; the batched engine checks
+    the kinds before any device work."""
     lib = Q.load()
     arr = np.ascontiguousarray(np.asarray([(0, 1), (1, 2)], dtype=np.int32))
     kd = np.ascontiguousarray(np.asarray([1, 0], dtype=np.int32))
@@ -119,8 +120,11 @@ def test_gate_kinds_unsupported_in_batch_and_learned_entries():
     tgt.U = C.c_void_p(16)
     res = Q.Result()
     out = (C.c_void_p * 1)(16)
-    assert lib.qfs_instantiate_batch(1, C.byref(tmpl), C.byref(tgt), C.byref(par), out,
-                                     C.byref(res)) == Q.QFS_EUNSUPPORTED
+    bad = np.ascontiguousarray(np.asarray([1, 5], dtype=np.int32))
+    tmpl_bad = Q.Template(3, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                          bad.ctypes.data_as(C.POINTER(C.c_int32)), None)
+    assert lib.qfs_instantiate_batch(1, C.byref(tmpl_bad), C.byref(tgt), C.byref(par), out,
+                                     C.byref(res)) == Q.QFS_EINVAL
     f = np.zeros(64, dtype=np.float32)
     assert lib.qfs_features(C.byref(tmpl), f.ctypes.data_as(C.c_void_p)) == Q.QFS_EUNSUPPORTED
 

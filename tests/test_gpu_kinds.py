@@ -209,3 +209,79 @@ def test_full_size_u3_cnot_sweep_sampled_start():
     say("full size U3+CNOT: second sweep")
     c2 = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED, kinds=kinds)
     assert np.all(c2 <= c_gpu + 1e-6 * np.maximum(c_gpu, 1e-3))
+
+
+# ------------------------------------------------------------------ batched engine
+def _kind_problems(count, seed):
+    """U3 + CNOT templates and random mixed-kind templates of 3-6 qubits."""
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = 3 + i % 4
+        if i % 2 == 0:
+            w = I.workload_u3_cnot(n, 1 + i % 3, seed_base=0x5A17 + 80 + i)
+            out.append((n, w["pairs"], w["kinds"], w["fixed"], w["target_gates"]))
+        else:
+            L = 4 + i % 5
+            pairs = I.random_pair_template(n, L, g)
+            kinds = g.integers(0, 3, size=L).astype(np.int32)
+            kinds[0] = I.GATE_1Q
+            fixed = np.stack([I.haar_unitary(4, g) for _ in range(L)])
+            out.append((n, pairs, kinds, fixed, I.kinds_target_gates(kinds, fixed, g)))
+    return out
+
+
+def test_batched_kinds_one_sweep_per_launch_follows_oracle():
+    """FP64 states, one sweep per launch: every problem follows the oracle's control flow
+    (its own seed params.seed + p, initial one-qubit gates drawn as on the oracle)."""
+    say("kinds batched K=1 vs oracle")
+    probs = _kind_problems(6, 90)
+    bp = Q.qfs_default_params(dist_tol=1e-10, multistarts=3, seed=50, max_iter=400,
+                              precision=Q.QFS_PREC_FP64, batch_sweeps=1)
+    dprobs = [dict(n=n, pairs=pr, kinds=k, fixed_gates=dev(f), target_pairs=pr, target_gates=dev(tg))
+              for n, pr, k, f, tg in probs]
+    gates, infos = Q.qfs_instantiate_batch(dprobs, bp)
+    for i, (n, pr, k, f, tg) in enumerate(probs):
+        op = O.default_params(dist_tol=1e-10, multistarts=3, seed=50 + i, max_iter=400)
+        g_ref, ref = O.instantiate(n, pr, target_pairs=pr, target_gates=tg, params=op, kinds=k, fixed=f)
+        got = infos[i]
+        assert (got["reason_name"], got["sweeps"], got["restarts"], got["m_final"]) == \
+            (ref["reason_name"], ref["sweeps"], ref["restarts"], ref["m_final"]), (i, got, ref)
+        if ref["c_train"] > 1e-20:
+            # a unique best start: same start, cost and gates
+            assert got["best_start"] == ref["best_start"], (i, got, ref)
+            assert abs(got["c_train"] - ref["c_train"]) <= 1e-9 * max(ref["c_train"], 1e-12) + 1e-20
+            assert np.max(np.abs(host(gates[i]) - g_ref)) < 1e-8
+        else:
+            # several starts solved the problem exactly in the same sweep and rounding
+            # noise orders them: the returned start must be one of them, its gates a
+            # solution
+            G = host(gates[i])
+            basis = np.eye(1 << n)
+            d = O.state_distance(n, O.apply_circuit(n, basis, pr, G), O.apply_circuit(n, basis, pr, tg))
+            assert got["c_train"] < 1e-20 and d < 1e-20, (i, got["c_train"], d)
+
+
+def test_batched_kinds_mixed_successes_are_solutions():
+    """complex64 states, automatic sweeps per launch, 40 problems: every reported success
+    is a real solution (full distance by the oracle's simulation <= 1e-8 at dist_tol 1e-9),
+    constant gates returned unchanged."""
+    say("kinds batched MIXED successes")
+    probs = _kind_problems(40, 91)
+    bp = Q.qfs_default_params(dist_tol=1e-9, multistarts=8, seed=60, max_iter=3000)
+    dprobs = [dict(n=n, pairs=pr, kinds=k, fixed_gates=dev(f), target_pairs=pr, target_gates=dev(tg))
+              for n, pr, k, f, tg in probs]
+    gates, infos = Q.qfs_instantiate_batch(dprobs, bp)
+    ok = 0
+    for i, (n, pr, k, f, tg) in enumerate(probs):
+        G = host(gates[i])
+        fx = k == I.GATE_FIXED
+        assert np.array_equal(G[fx], f[fx])
+        if infos[i]["reason_name"] != "SUCCESS":
+            continue
+        ok += 1
+        basis = np.eye(1 << n)
+        d = O.state_distance(n, O.apply_circuit(n, basis, pr, G), O.apply_circuit(n, basis, pr, tg))
+        assert d <= 1e-8, (i, d)
+    say(f"  {ok}/40 succeeded")
+    assert ok >= 20
