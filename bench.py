@@ -74,6 +74,8 @@ def parse():
                          "as needed to compare a profiler's per-launch averages with the roofline")
     ap.add_argument("--batched", type=int, default=4096,
                     help="problems in the batched workload (0 skips it)")
+    ap.add_argument("--batched-u3cx", type=int, default=4096,
+                    help="U3 + CNOT problems in a second batched workload (0 skips it)")
     ap.add_argument("--plain-sample", type=int, default=48,
                     help="problems of the batched workload also run one by one")
     ap.add_argument("--learned", type=int, default=1024,
@@ -309,6 +311,55 @@ def batched(dev, count, plain_sample):
     return out
 
 
+def batched_u3cx(dev, count, plain_sample):
+    """Batched U3 + CNOT workload: `count` problems (n ~ U{3..7}, 1-4 brickwork sublayers
+    of CNOT blocks with one-qubit gates, Haar one-qubit targets), 16 starts, M0 =
+    2^(n-1), App. A rules, MIXED, automatic sweeps per launch; compared with plain
+    qfs_instantiate calls on the first `plain_sample` problems, extrapolated."""
+    import numpy as np
+    import torch
+
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import qfs as Q
+
+    probs = I.batched_u3_cnot_problems(count)
+    dprobs = [dict(n=p["n"], pairs=p["pairs"], kinds=p["kinds"],
+                   fixed_gates=torch.as_tensor(p["fixed"]).to(dev), target_pairs=p["target_pairs"],
+                   target_gates=torch.as_tensor(p["target_gates"]).to(dev)) for p in probs]
+    m0 = np.array([1 << (p["n"] - 1) for p in probs], dtype=np.int32)
+    params = Q.qfs_default_params(multistarts=16, seed=0x5A17 + 10, batch_sweeps=0,
+                                  precision=Q.QFS_PREC_MIXED)
+    warm = min(128, count)
+    Q.qfs_instantiate_batch_ex(dprobs[:warm], params, m_init=m0[:warm])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos = Q.qfs_instantiate_batch_ex(dprobs, params, m_init=m0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    job_sweeps = sum(r["start_sweeps"] for r in infos)
+    out = {"problems": count, "starts": 16, "wall_s": round(dt, 3), "problems_per_s": round(count / dt, 1),
+           "successes": sum(r["reason_name"] == "SUCCESS" for r in infos), "job_sweeps": job_sweeps,
+           "job_sweeps_per_s": round(job_sweeps / dt, 1)}
+    k = min(plain_sample, count)
+    if k > 0:
+        t_plain, ok_plain = 0.0, 0
+        for i in range(k):
+            p = dict(params, seed=params["seed"] + i, m_init=int(m0[i]))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, r = Q.qfs_instantiate(probs[i]["n"], probs[i]["pairs"], target_pairs=probs[i]["pairs"],
+                                     target_gates=dprobs[i]["target_gates"], params=p,
+                                     kinds=probs[i]["kinds"], fixed_gates=dprobs[i]["fixed_gates"])
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t1
+            ok_plain += r["reason_name"] == "SUCCESS"
+        est = t_plain / k * count
+        out["plain_loop"] = {"sample": k, "sample_s": round(t_plain, 3), "sample_successes": ok_plain,
+                             "batched_successes_on_sample": sum(infos[i]["reason_name"] == "SUCCESS" for i in range(k)),
+                             "extrapolated_s": round(est, 2), "batched_speedup": round(est / dt, 1)}
+    return out
+
+
 def learned(dev, count, large):
     """Learned initial M and start pruning against the plain method (M from 2, doubling,
     16 starts, App. A rules, MIXED), both batched, on `count` held-out problems drawn like
@@ -440,6 +491,8 @@ def main():
         extra["qf_vs_qfs"] = qf_vs_qfs(dev, [int(x) for x in args.qf.split(",") if x])
     if args.batched > 0:
         extra["batched"] = batched(dev, args.batched, args.plain_sample)
+    if args.batched_u3cx > 0:
+        extra["batched_u3cx"] = batched_u3cx(dev, args.batched_u3cx, args.plain_sample)
     if args.learned > 0 or args.learned_large > 0:
         extra["learned"] = learned(dev, args.learned, args.learned_large)
     if not args.no_ttd:

@@ -193,6 +193,20 @@ def workload_u3_cnot(n: int, sublayers: int, seed_base: int = 0x5A17 + 6, proble
                 target_gates=kinds_target_gates(kinds, fixed, g))
 
 
+def batched_u3_cnot_problems(count: int, seed_base: int = 0x5A17 + 10, n_range=(3, 7), sub_range=(1, 4)):
+    """Uneven U3 + CNOT problem set: n ~ U{3..7}, brickwork sublayers ~ U{1..4}
+    (u3_cnot_template), target = the template with Haar one-qubit gates and the same CNOTs."""
+    probs = []
+    for pid in range(count):
+        g = rng(derive_seed(seed_base, pid, ROLE_TARGET))
+        n = int(g.integers(n_range[0], n_range[1] + 1))
+        sub = int(g.integers(sub_range[0], sub_range[1] + 1))
+        pairs, kinds, fixed = u3_cnot_template(n, sub)
+        probs.append(dict(n=n, pairs=pairs, kinds=kinds, fixed=fixed, target_pairs=pairs,
+                          target_gates=kinds_target_gates(kinds, fixed, g)))
+    return probs
+
+
 def batched_problems(count: int, seed_base: int = 0x5A17 + 4, n_range=(3, 7), L_range=(2, 20)):
     """Uneven problem set: n ~ U{3..7}, L ~ U{2..20}, random distinct pairs, target =
     the template with Haar gates."""
