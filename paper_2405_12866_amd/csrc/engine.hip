@@ -189,6 +189,7 @@ struct SweepCtx {
   const int32_t *pairs_host = nullptr;
   const int32_t *pairs_dev = nullptr;
   const int32_t *kinds = nullptr;  // host [L] gate kinds, or nullptr: all two-qubit
+  const int32_t *kinds_dev = nullptr;  // the same on the device
   Geometry g{}, gv{};  // training / validation sets (gv.M == 0: no validation)
   bool fused = false;
   const int32_t *slots = nullptr;
@@ -242,8 +243,11 @@ int sweep_forward(SweepCtx &c, bool with_c0) {
     QFS_TRY(T.begin(c.stream));
     QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
                                     with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
-                                    c.nslots, c.stream));
-    const double bytes = set_bytes<R>(c, c.g) * (c.L + (with_c0 ? 1 : 0)) +
+                                    c.nslots, c.kinds_dev, c.stream));
+    // load Psi, store the B list entries some environment reads, read U Psi for c_0
+    int stored = c.L - 1;
+    for (int k = 1; c.kinds && k < c.L; ++k) stored -= c.kinds[k] == QFS_GATE_FIXED;
+    const double bytes = set_bytes<R>(c, c.g) * (1 + stored + (with_c0 ? 1 : 0)) +
                          (val ? 2.0 * set_bytes<R>(c, c.gv) : 0.0);
     QFS_TRY(T.end(c.stream, kClsForward, bytes));
     if (val) QFS_TRY(launch_dist_finalize(c.gv.nch, c.dpart1, c.slots, c.nslots, c.gv.M, c.costs + c.S, c.stream));
@@ -707,6 +711,7 @@ int Group::run(GroupResult &out, double t_start) {
 
   SweepCtx &c = ctx_;
   c.kinds = kinds_.empty() ? nullptr : kinds_.data();
+  c.kinds_dev = kinds_.empty() ? nullptr : kinds_dev_.as<int32_t>();
   c.slots = slots_.as<int32_t>();
   c.g64 = g64_.as<c128>();
   c.g32 = g32_.as<c64>();
@@ -1320,6 +1325,12 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
   c.L = L;
   c.pairs_host = pairs;
   c.kinds = kinds;
+  DevBuf kdev;
+  if (kinds) {
+    QFS_TRY(kdev.alloc(sizeof(int32_t) * L));
+    QFS_HIP(hipMemcpyAsync(kdev.ptr, kinds, sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
+    c.kinds_dev = kdev.as<int32_t>();
+  }
   c.g = Geometry{n, 1 << n, logC, (M + C - 1) / C, M};
   c.gv = Geometry{n, 1 << n, logC, 1, 0};
   c.fused = fused;

@@ -230,13 +230,15 @@ int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef 
 // Fused forward pass for every slot: B list (B_{k+1} at list index k, k < L-1) from
 // psi; optionally the Eq. 9 distance of the full circuit against phi_ref (block
 // partials [S][g.nch]); optionally the validation set through all L gates with its
-// distance partials [S][gv->nch]. pairs_dev: device [L][2].
+// distance partials [S][gv->nch]. pairs_dev: device [L][2]. kinds_dev: device [L] gate
+// kinds or nullptr; the B list entry before a constant gate is not stored (no environment
+// reads it).
 template <typename R>
 int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *pairs_dev, int L,
                          GateRef gates, const cx<R> *psi, cx<R> *blist, int64_t bstride,
                          const cx<R> *phi_ref, double *c0_partials, const cx<R> *psiv,
                          const cx<R> *phiv, double *val_partials, const int32_t *slot_to_start,
-                         int nslots, hipStream_t s);
+                         int nslots, const int32_t *kinds_dev, hipStream_t s);
 
 template <typename R>
 int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, hipStream_t s);

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
                                                              int logC, const int32_t *pairs,
                                                              const cx<R> *gates, int32_t gstride,
                                                              const int32_t *slot_to_start,
-                                                             int coalesce_b) {
+                                                             int coalesce_b, const int32_t *kinds) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
   __shared__ double red[FB / 64];
@@ -426,7 +426,8 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
     const uint32_t ma = 1u << pa, mb = 1u << pb;
     cx<R> u[16];
     load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, false);
-    const bool store = k < sg.kstore;
+    // B_{k+1} serves only the environment of gate k+1: none for a constant gate
+    const bool store = k < sg.kstore && !(kinds && kinds[k + 1] == QFS_GATE_FIXED);
     cx<R> *dst = store ? sg.blist + sg.bstride * s + sg.sN * k + cbase : nullptr;
     const bool late = store && coalesce_b && ((sizeof(cx<R>) << (logC + min(pa, pb))) < 128);
     for (uint32_t g = threadIdx.x; g < groups; g += FB) {
@@ -980,7 +981,7 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
                          GateRef gates, const cx<R> *psi, cx<R> *blist, int64_t bstride,
                          const cx<R> *phi_ref, double *c0_partials, const cx<R> *psiv,
                          const cx<R> *phiv, double *val_partials, const int32_t *slot_to_start,
-                         int nslots, hipStream_t s) {
+                         int nslots, const int32_t *kinds_dev, hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   FwdSeg<R> a{}, b{};
   a.src = psi;
@@ -1030,7 +1031,8 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
       attr_bytes = lds;
     }
     hipLaunchKernelGGL(kernel, dim3(gx, nslots, nz), dim3(threads), lds, s, a, b, g.n, g.logC, pairs_dev,
-                       static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, coalesce_b);
+                       static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, coalesce_b,
+                       kinds_dev);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   };
@@ -1279,7 +1281,8 @@ int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipSt
   template int launch_forward_fused<R>(const Geometry &, const Geometry *, const int32_t *,   \
                                        int, GateRef, const cx<R> *, cx<R> *, int64_t,         \
                                        const cx<R> *, double *, const cx<R> *, const cx<R> *, \
-                                       double *, const int32_t *, int, hipStream_t);          \
+                                       double *, const int32_t *, int, const int32_t *,       \
+                                       hipStream_t);                                          \
   template int launch_pack<R>(const Geometry &, int64_t, const c128 *, cx<R> *, hipStream_t);
 QFS_INST(float)
 QFS_INST(double)
