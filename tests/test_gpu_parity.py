@@ -319,6 +319,37 @@ def test_full_size_sweep_sampled_starts():
     assert np.all(c2 <= c_gpu + 1e-6 * np.maximum(c_gpu, 1e-3))
 
 
+@pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
+def test_full_size_instantiate_in_bench_configuration(precision):
+    """The timed call of the benchmark, shortened to two sweeps: 12-qubit brickwork (44
+    gates), M = 256 fixed, 16 starts, the two streams of the backward pass, sample sets and
+    initial gates drawn on the device; the oracle runs the same call in FP64 from its own
+    draws (same seed). FP64 states: the same best start, c_train and c_val to 1e-10
+    relative. complex64 states (the bench's precision): 1e-4 relative; two free-running
+    sweeps far from the solution (c near 2, so f = M (1 - c/2) is about 5 while the
+    environment sums terms of total size about M = 256) amplify the FP32 rounding of the
+    partial sums about 50-fold. The best start must agree when the runner-up is not within
+    that tolerance of it."""
+    say(f"full size: qfs_instantiate in the bench configuration (2 sweeps), precision={precision}")
+    w = I.workload_12q()
+    kw = dict(multistarts=16, m_init=256, fixed_m=1, seed=0x5A17 + 3, max_iter=2, diff_tol_r=0.0,
+              plateau_window=1 << 30)
+    _, got = Q.qfs_instantiate(12, w["pairs"], target_pairs=w["pairs"], target_gates=dev(w["target_gates"]),
+                               params=Q.qfs_default_params(precision=precision, **kw))
+    say("full size: oracle of the same call")
+    _, ref = O.instantiate(12, w["pairs"], target_pairs=w["pairs"], target_gates=w["target_gates"],
+                           params=O.default_params(**kw), trace_capacity=64)
+    assert got["reason_name"] == ref["reason_name"] == "MAX_ITER" and got["sweeps"] == 2
+    assert got["m_final"] == 256 and got["start_sweeps"] == 32
+    tol = 1e-10 if precision == Q.QFS_PREC_FP64 else 1e-4
+    tr = ref["trace"]
+    last = np.sort(tr["c_train"][tr["sweep"] == 2])
+    assert abs(got["c_train"] - ref["c_train"]) <= tol * ref["c_train"], (got["c_train"], ref["c_train"])
+    if last[1] - last[0] > 2 * tol * last[0]:
+        assert got["best_start"] == ref["best_start"]
+        assert abs(got["c_val"] - ref["c_val"]) <= tol * ref["c_val"], (got["c_val"], ref["c_val"])
+
+
 # ------------------------------------------------------------------ graph replay
 @pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
 def test_graph_replay_matches_eager(precision):
