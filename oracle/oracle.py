@@ -132,6 +132,17 @@ def load():
                                        C.c_int, C.c_int, C.POINTER(Params), P, P,
                                        C.POINTER(Result), C.POINTER(Trace)]
         lib.qo_instantiate.restype = C.c_int
+        lib.qd_apply_gate.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_int, C.c_int, P, C.c_int]
+        lib.qd_environment.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int, P]
+        lib.qd_svd.argtypes = [C.c_int, P, P, P, P]
+        lib.qd_update_gate.argtypes = [C.c_int, P, C.c_double, P]
+        lib.qd_haar_gate.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        lib.qd_sweep.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_int, P, P, P, C.c_double,
+                                 C.c_double, P, P]
+        lib.qd_sweep.restype = C.c_double
+        lib.qd_instantiate.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_int, C.c_int,
+                                       C.POINTER(Params), P, P, C.POINTER(Result), C.POINTER(Trace)]
+        lib.qd_instantiate.restype = C.c_int
         _lib = lib
         return lib
 
@@ -364,11 +375,87 @@ def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=N
     return out, info
 
 
+# ------------------------------------------------------------------------ qudits
+def qd_apply_gate(d, n, states, qa, qb, u, dagger=False):
+    st = _c128(states).copy()
+    load().qd_apply_gate(d, n, st.shape[0], _p(st), qa, qb, _p(_c128(u)), 1 if dagger else 0)
+    return st
+
+
+def qd_apply_circuit(d, n, states, pairs, gates):
+    st = _c128(states).copy()
+    for (a, b), u in zip(_pairs(pairs), _c128(gates)):
+        load().qd_apply_gate(d, n, st.shape[0], _p(st), int(a), int(b), _p(_c128(u)), 0)
+    return st
+
+
+def qd_environment(d, n, a, b, qa, qb):
+    aa, bb = _c128(a), _c128(b)
+    G = np.zeros((d * d, d * d), dtype=np.complex128)
+    load().qd_environment(d, n, aa.shape[0], _p(aa), _p(bb), qa, qb, _p(G))
+    return G
+
+
+def qd_svd(G):
+    g = _c128(G)
+    D = g.shape[0]
+    W = np.zeros((D, D), dtype=np.complex128)
+    V = np.zeros((D, D), dtype=np.complex128)
+    s = np.zeros(D)
+    load().qd_svd(D, _p(g), _p(W), _p(s), _p(V))
+    return W, s, V
+
+
+def qd_update_gate(G, beta=0.0, u=None):
+    g = _c128(G)
+    D = g.shape[0]
+    uu = np.zeros((D, D), dtype=np.complex128) if u is None else _c128(u).copy()
+    load().qd_update_gate(D, _p(g), beta, _p(uu))
+    return uu
+
+
+def qd_haar_gate(d, seed, start, gate):
+    u = np.zeros((d * d, d * d), dtype=np.complex128)
+    load().qd_haar_gate(d, seed, start, gate, _p(u))
+    return u
+
+
+def qd_sweep(d, n, pairs, psi, phi, gates, beta=0.0, gamma_scale=1.0, record=False):
+    pr = _pairs(pairs)
+    L = pr.shape[0]
+    g = _c128(gates).copy()
+    ps, ph = _c128(psi), _c128(phi)
+    fb = np.zeros(L) if record else None
+    fa = np.zeros(L) if record else None
+    c = load().qd_sweep(d, n, L, _p(pr), ps.shape[0], _p(ps), _p(ph), _p(g), beta, gamma_scale,
+                        _p(fb), _p(fa))
+    return (g, c, fb, fa) if record else (g, c)
+
+
+def qd_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None):
+    """Qudit instantiation on a fixed sample set (the last n_val rows validate)."""
+    pr = _pairs(pairs)
+    L = pr.shape[0]
+    par = Params(**(params or default_params()))
+    ps, ph = _c128(psi), _c128(phi)
+    gi = None if gates_in is None else _c128(gates_in)
+    out = np.zeros((L, d * d, d * d), dtype=np.complex128)
+    res = Result()
+    rc = load().qd_instantiate(d, n, L, _p(pr), _p(ps), _p(ph), ps.shape[0], n_val, C.byref(par),
+                               _p(gi), _p(out), C.byref(res), None)
+    if rc != 0:
+        raise ValueError(f"qd_instantiate failed: {rc}")
+    info = {f: getattr(res, f) for f, _ in Result._fields_}
+    info["reason_name"] = REASONS[res.reason]
+    return out, info
+
+
 __all__ = [
     "Params", "Result", "ROLE_TRAIN", "ROLE_VAL", "ROLE_INIT", "REASONS", "default_params",
     "philox4x32_10", "cgauss", "ginibre", "orthonormalize", "draw_states", "haar_gate",
     "haar_gate2", "initial_gates", "kron_i2", "GATE_2Q", "GATE_1Q", "GATE_FIXED",
     "apply_gate", "apply_circuit", "dense_apply", "environment", "environment1", "svd4",
-    "update_gate", "update_gate1",
+    "update_gate", "update_gate1", "qd_apply_gate", "qd_apply_circuit", "qd_environment",
+    "qd_svd", "qd_update_gate", "qd_haar_gate", "qd_sweep", "qd_instantiate",
     "state_distance", "sweep", "instantiate",
 ]

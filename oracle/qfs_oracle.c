@@ -502,6 +502,255 @@ static double qo_forward_cost(int n, int L, const int32_t *pairs, int M, const q
 }
 
 /* ------------------------------------------------------------------------------------
+ * Qudits (Sec. 5: the method applies unchanged to d-level gates, where a sweep costs
+ * O(M d^n) instead of QFactor's O(d^{2n})). n qudits of dimension d, N = d^n; qudit 0 is
+ * the most significant base-d digit of the amplitude index (stride d^{n-1-q}); a
+ * two-qudit gate on (qa, qb) is a D x D unitary, D = d^2, row-major u[q][p], with local
+ * index d * digit(qa) + digit(qb). With d = 2 every function below computes what the
+ * qubit functions above compute.
+ * ---------------------------------------------------------------------------------- */
+static int64_t qd_pow(int d, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= d;
+  return r;
+}
+
+/* Amplitude indices of the D-group of base index i (digits of qa and qb zero). */
+static void qd_group(int d, int n, int qa, int qb, int64_t i, int64_t *idx) {
+  const int64_t sa = qd_pow(d, n - 1 - qa), sb = qd_pow(d, n - 1 - qb);
+  for (int x = 0; x < d; ++x)
+    for (int y = 0; y < d; ++y) idx[x * d + y] = i + x * sa + y * sb;
+}
+
+static int qd_is_base(int d, int n, int qa, int qb, int64_t i) {
+  return (i / qd_pow(d, n - 1 - qa)) % d == 0 && (i / qd_pow(d, n - 1 - qb)) % d == 0;
+}
+
+/* st <- u st (or u^dagger st) on qudits (qa, qb), every sample. */
+void qd_apply_gate(int d, int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx *u, int dagger) {
+  const int D = d * d;
+  const int64_t N = qd_pow(d, n);
+  int64_t idx[16];
+  qo_cplx in[16];
+  for (int64_t j = 0; j < M; ++j)
+    for (int64_t i = 0; i < N; ++i) {
+      if (!qd_is_base(d, n, qa, qb, i)) continue;
+      qd_group(d, n, qa, qb, i, idx);
+      for (int p = 0; p < D; ++p) in[p] = st[j * N + idx[p]];
+      for (int q = 0; q < D; ++q) {
+        qo_cplx acc = 0.0;
+        for (int p = 0; p < D; ++p) acc += (dagger ? conj(u[p * D + q]) : u[q * D + p]) * in[p];
+        st[j * N + idx[q]] = acc;
+      }
+    }
+}
+
+/* Environment of a two-qudit gate: G[q][p] = sum_j sum_r a_j(q, r) conj(b_j(p, r)) over the
+ * other n-2 qudits (the qubit environment above with base-d digits). */
+void qd_environment(int d, int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, int qb,
+                    qo_cplx *G) {
+  const int D = d * d;
+  const int64_t N = qd_pow(d, n);
+  int64_t idx[16];
+  for (int e = 0; e < D * D; ++e) G[e] = 0.0;
+  for (int64_t j = 0; j < M; ++j)
+    for (int64_t i = 0; i < N; ++i) {
+      if (!qd_is_base(d, n, qa, qb, i)) continue;
+      qd_group(d, n, qa, qb, i, idx);
+      for (int q = 0; q < D; ++q)
+        for (int p = 0; p < D; ++p) G[q * D + p] += a[j * N + idx[q]] * conj(b[j * N + idx[p]]);
+    }
+}
+
+/* D x D complex SVD G = W diag(s) V^dagger (D <= 16) by one-sided Jacobi, the same
+ * rotations as qo_svd4 on D columns; s in decreasing order, W completed to a unitary
+ * where singular values are negligible. */
+void qd_svd(int D, const qo_cplx *Gin, qo_cplx *W, double *s, qo_cplx *V) {
+  qo_cplx g[16][16], v[16][16]; /* [column][row] */
+  for (int c = 0; c < D; ++c)
+    for (int r = 0; r < D; ++r) {
+      g[c][r] = Gin[r * D + c];
+      v[c][r] = (r == c) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    int rotated = 0;
+    for (int p = 0; p < D - 1; ++p)
+      for (int q = p + 1; q < D; ++q) {
+        double alpha = 0.0, beta = 0.0;
+        qo_cplx gamma = 0.0;
+        for (int r = 0; r < D; ++r) {
+          alpha += creal(g[p][r] * conj(g[p][r]));
+          beta += creal(g[q][r] * conj(g[q][r]));
+          gamma += conj(g[p][r]) * g[q][r];
+        }
+        double ag = cabs(gamma);
+        if (ag == 0.0 || ag <= 1e-15 * sqrt(alpha * beta)) continue;
+        rotated = 1;
+        qo_cplx e = gamma / ag;
+        double tau = (beta - alpha) / (2.0 * ag);
+        double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        double c = 1.0 / sqrt(1.0 + t * t);
+        double sn = c * t;
+        for (int r = 0; r < D; ++r) {
+          qo_cplx gp = g[p][r], gq = g[q][r];
+          g[p][r] = c * gp - sn * conj(e) * gq;
+          g[q][r] = sn * gp + c * conj(e) * gq;
+          qo_cplx vp = v[p][r], vq = v[q][r];
+          v[p][r] = c * vp - sn * conj(e) * vq;
+          v[q][r] = sn * vp + c * conj(e) * vq;
+        }
+      }
+    if (!rotated) break;
+  }
+  double nrm[16];
+  int order[16];
+  for (int c = 0; c < D; ++c) {
+    double acc = 0.0;
+    for (int r = 0; r < D; ++r) acc += creal(g[c][r] * conj(g[c][r]));
+    nrm[c] = sqrt(acc);
+    order[c] = c;
+  }
+  for (int a = 0; a < D; ++a)
+    for (int b = a + 1; b < D; ++b)
+      if (nrm[order[b]] > nrm[order[a]]) {
+        int tmp = order[a]; order[a] = order[b]; order[b] = tmp;
+      }
+  double smax = nrm[order[0]];
+  qo_cplx w[16][16];
+  for (int k = 0; k < D; ++k) {
+    int c = order[k];
+    s[k] = nrm[c];
+    for (int r = 0; r < D; ++r) V[r * D + k] = v[c][r];
+    qo_cplx x[16];
+    int ok = 0;
+    if (nrm[c] > 1e-13 * smax && nrm[c] > 0.0) {
+      for (int r = 0; r < D; ++r) x[r] = g[c][r] / nrm[c];
+      for (int pass = 0; pass < 2; ++pass)
+        for (int m = 0; m < k; ++m) {
+          qo_cplx dd = 0.0;
+          for (int r = 0; r < D; ++r) dd += conj(w[m][r]) * x[r];
+          for (int r = 0; r < D; ++r) x[r] -= dd * w[m][r];
+        }
+      double l = 0.0;
+      for (int r = 0; r < D; ++r) l += creal(x[r] * conj(x[r]));
+      l = sqrt(l);
+      if (l > 0.5) {
+        for (int r = 0; r < D; ++r) x[r] /= l;
+        ok = 1;
+      }
+    }
+    if (!ok) {
+      double best = -1.0;
+      qo_cplx bx[16];
+      for (int e = 0; e < D; ++e) {
+        qo_cplx y[16];
+        for (int r = 0; r < D; ++r) y[r] = (r == e) ? 1.0 : 0.0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int m = 0; m < k; ++m) {
+            qo_cplx dd = 0.0;
+            for (int r = 0; r < D; ++r) dd += conj(w[m][r]) * y[r];
+            for (int r = 0; r < D; ++r) y[r] -= dd * w[m][r];
+          }
+        double l = 0.0;
+        for (int r = 0; r < D; ++r) l += creal(y[r] * conj(y[r]));
+        if (l > best) {
+          best = l;
+          for (int r = 0; r < D; ++r) bx[r] = y[r];
+        }
+      }
+      best = sqrt(best);
+      for (int r = 0; r < D; ++r) x[r] = bx[r] / best;
+    }
+    for (int r = 0; r < D; ++r) w[k][r] = x[r];
+  }
+  for (int k = 0; k < D; ++k)
+    for (int r = 0; r < D; ++r) W[r * D + k] = w[k][r];
+}
+
+/* u <- W V^dagger for (1 - beta) G + beta u = W S V^dagger (Eq. 2, App. A Beta). */
+void qd_update_gate(int D, const qo_cplx *G, double beta, qo_cplx *u) {
+  qo_cplx X[256], Wm[256], Vm[256];
+  double sv[16];
+  for (int e = 0; e < D * D; ++e) X[e] = (1.0 - beta) * G[e] + beta * u[e];
+  qd_svd(D, X, Wm, sv, Vm);
+  for (int q = 0; q < D; ++q)
+    for (int p = 0; p < D; ++p) {
+      qo_cplx acc = 0.0;
+      for (int k = 0; k < D; ++k) acc += Wm[q * D + k] * conj(Vm[p * D + k]);
+      u[q * D + p] = acc;
+    }
+}
+
+/* Initial two-qudit gate: Haar on U(D) from a D x D Ginibre block of the start's
+ * initial-gate stream (indices 256 gate + D col + row), orthonormalised by columns. */
+void qd_haar_gate(int d, uint64_t seed, uint32_t start, uint32_t gate, qo_cplx *u) {
+  const int D = d * d;
+  qo_cplx cols[256];
+  for (int j = 0; j < D; ++j)
+    for (int i = 0; i < D; ++i)
+      cols[j * D + i] = qo_cgauss(seed, QO_ROLE_INIT, start, (uint64_t)gate * 256u + (uint64_t)(j * D + i));
+  qo_gram_schmidt_columns(D, 0, D, cols);
+  for (int q = 0; q < D; ++q)
+    for (int p = 0; p < D; ++p) u[q * D + p] = cols[p * D + q];
+}
+
+static double qd_re_tr(int D, const qo_cplx *G, const qo_cplx *u) {
+  double acc = 0.0;
+  for (int e = 0; e < D * D; ++e) acc += creal(conj(G[e]) * u[e]);
+  return acc;
+}
+
+/* One sweep on qudits (the qubit sweep with D x D gates). */
+double qd_sweep(int d, int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
+                const qo_cplx *phi, qo_cplx *gates, double beta, double gamma_scale,
+                double *f_before, double *f_after) {
+  const int D = d * d, GS = D * D;
+  const int64_t S = (int64_t)M * qd_pow(d, n);
+  qo_cplx *B = (qo_cplx *)malloc(sizeof(qo_cplx) * S * (size_t)L);
+  qo_cplx *a = (qo_cplx *)malloc(sizeof(qo_cplx) * S);
+  qo_cplx G[256], Gs[256];
+  memcpy(B, psi, sizeof(qo_cplx) * S);
+  for (int k = 1; k < L; ++k) {
+    memcpy(B + (size_t)k * S, B + (size_t)(k - 1) * S, sizeof(qo_cplx) * S);
+    qd_apply_gate(d, n, M, B + (size_t)k * S, pairs[2 * (k - 1)], pairs[2 * (k - 1) + 1],
+                  gates + GS * (k - 1), 0);
+  }
+  memcpy(a, phi, sizeof(qo_cplx) * S);
+  for (int k = L - 1; k >= 0; --k) {
+    qd_environment(d, n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
+    if (f_before) f_before[k] = qd_re_tr(D, G, gates + GS * k);
+    for (int e = 0; e < GS; ++e) Gs[e] = gamma_scale * G[e];
+    qd_update_gate(D, Gs, beta, gates + GS * k);
+    if (f_after) f_after[k] = qd_re_tr(D, G, gates + GS * k);
+    qd_apply_gate(d, n, M, a, pairs[2 * k], pairs[2 * k + 1], gates + GS * k, 1);
+  }
+  double c = 0.0;
+  for (int64_t e = 0; e < S; ++e) {
+    qo_cplx x = a[e] - psi[e];
+    c += creal(x * conj(x));
+  }
+  free(a);
+  free(B);
+  return c / (double)M;
+}
+
+static double qd_forward_cost(int d, int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
+                              const qo_cplx *phi, const qo_cplx *gates) {
+  const int GS = d * d * d * d;
+  const int64_t S = (int64_t)M * qd_pow(d, n);
+  qo_cplx *x = (qo_cplx *)malloc(sizeof(qo_cplx) * S);
+  memcpy(x, psi, sizeof(qo_cplx) * S);
+  for (int k = 0; k < L; ++k) qd_apply_gate(d, n, M, x, pairs[2 * k], pairs[2 * k + 1], gates + GS * k, 0);
+  double c = 0.0;
+  for (int64_t e = 0; e < S; ++e) {
+    qo_cplx y = x[e] - phi[e];
+    c += creal(y * conj(y));
+  }
+  free(x);
+  return c / (double)M;
+}
+
+/* ------------------------------------------------------------------------------------
  * The control loop (Sec. 3 "on-the-fly" generalisation check and double-and-restart;
  * the success relations of Eq. 12; App. A plateau test Eq. 13, min_iter, max_iter,
  * multistarts). Readings where the paper is silent are listed in the design notes:
@@ -529,7 +778,7 @@ static void qo_targets(int n, int kind, const qo_cplx *U, int Lt, const int32_t 
   }
 }
 
-int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
+static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int32_t *kinds,
                    const qo_cplx *fixed, int target_kind, const qo_cplx *U,
                    int Lt, const int32_t *tpairs, const qo_cplx *tgates,
                    const qo_cplx *samples_psi, const qo_cplx *samples_phi, int n_samples,
@@ -537,13 +786,15 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
                    qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
   const double t0 = qo_now();
   if (n < 2 || n > 24 || L < 1 || !p || !gates_out || !res) return -1;
+  if (d != 2 && (kinds || target_kind != QO_TARGET_SAMPLES)) return -1;
+  const int GS = d * d * d * d; /* entries of one gate */
   for (int k = 0; k < L; ++k) {
     int a = pairs[2 * k], b = pairs[2 * k + 1];
     if (a < 0 || b < 0 || a >= n || b >= n || a == b) return -1;
     if (kinds && (kinds[k] < QO_GATE_2Q || kinds[k] > QO_GATE_FIXED)) return -1;
     if (kinds && kinds[k] == QO_GATE_FIXED && !fixed) return -1;
   }
-  const int64_t N = (int64_t)1 << n;
+  const int64_t N = qd_pow(d, n);
   const int S = p->multistarts > 0 ? p->multistarts : 1;
   int m_cap = (p->m_max > 0 && p->m_max < N) ? p->m_max : (int)N;
   int n_train = 0;
@@ -586,18 +837,23 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
     qo_targets(n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
   }
 
-  qo_cplx *gates = (qo_cplx *)malloc(sizeof(qo_cplx) * 16 * (size_t)L * S);
+  qo_cplx *gates = (qo_cplx *)malloc(sizeof(qo_cplx) * GS * (size_t)L * S);
   for (int s = 0; s < S; ++s)
     for (int k = 0; k < L; ++k) {
       const int kind = kinds ? kinds[k] : QO_GATE_2Q;
-      qo_cplx *u = gates + 16 * ((size_t)s * L + k);
+      qo_cplx *u = gates + GS * ((size_t)s * L + k);
       if (kind == QO_GATE_FIXED)
         memcpy(u, fixed + 16 * (size_t)k, sizeof(qo_cplx) * 16);
       else if (gates_in)
-        memcpy(u, gates_in + 16 * ((size_t)s * L + k), sizeof(qo_cplx) * 16);
+        memcpy(u, gates_in + GS * ((size_t)s * L + k), sizeof(qo_cplx) * GS);
+      else if (d != 2)
+        qd_haar_gate(d, p->seed, (uint32_t)s, (uint32_t)k, u);
       else
         qo_initial_gate(p->seed, (uint32_t)s, (uint32_t)k, kind, fixed, u);
     }
+#define FWD_COST(MM, PS, PH, G)                                                  \
+  (d == 2 ? qo_forward_cost(n, L, pairs, (MM), (PS), (PH), (G))                  \
+          : qd_forward_cost(d, n, L, pairs, (MM), (PS), (PH), (G)))
 
   int *status = (int *)calloc(S, sizeof(int));
   int *reason = (int *)calloc(S, sizeof(int));
@@ -611,10 +867,9 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
 
 #pragma omp parallel for schedule(dynamic)
   for (int s = 0; s < S; ++s) {
-    c_prev[s] = qo_forward_cost(n, L, pairs, M, psi, phi, gates + 16 * (size_t)s * L);
+    c_prev[s] = FWD_COST(M, psi, phi, gates + GS * (size_t)s * L);
     c_tr[s] = c_prev[s];
-    c_v[s] = Mv > 0 ? qo_forward_cost(n, L, pairs, Mv, psiv, phiv, gates + 16 * (size_t)s * L)
-                    : c_tr[s];
+    c_v[s] = Mv > 0 ? FWD_COST(Mv, psiv, phiv, gates + GS * (size_t)s * L) : c_tr[s];
   }
 
   int restarts = 0, m_total = M, chosen = -1;
@@ -622,10 +877,14 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
 #pragma omp parallel for schedule(dynamic)
     for (int s = 0; s < S; ++s) {
       if (status[s] != ST_RUNNING) continue;
-      qo_cplx *g = gates + 16 * (size_t)s * L;
-      c_tr[s] = qo_sweep(n, L, pairs, kinds, M, psi, phi, g, p->beta,
-                         p->beta_normalized ? 1.0 / (double)M : 1.0, NULL, NULL, NULL);
-      c_v[s] = Mv > 0 ? qo_forward_cost(n, L, pairs, Mv, psiv, phiv, g) : c_tr[s];
+      qo_cplx *g = gates + GS * (size_t)s * L;
+      if (d == 2)
+        c_tr[s] = qo_sweep(n, L, pairs, kinds, M, psi, phi, g, p->beta,
+                           p->beta_normalized ? 1.0 / (double)M : 1.0, NULL, NULL, NULL);
+      else
+        c_tr[s] = qd_sweep(d, n, L, pairs, M, psi, phi, g, p->beta,
+                           p->beta_normalized ? 1.0 / (double)M : 1.0, NULL, NULL);
+      c_v[s] = Mv > 0 ? FWD_COST(Mv, psiv, phiv, g) : c_tr[s];
     }
     const int full = (M == (int)N);
     int any_success = 0, any_over = 0, any_running = 0;
@@ -713,7 +972,7 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
         status[s] = ST_RUNNING;
         iter[s] = 0;
         zcount[s] = 0;
-        c_prev[s] = qo_forward_cost(n, L, pairs, M, psi, phi, gates + 16 * (size_t)s * L);
+        c_prev[s] = FWD_COST(M, psi, phi, gates + GS * (size_t)s * L);
       }
       continue;
     }
@@ -730,7 +989,8 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
     }
   }
 
-  memcpy(gates_out, gates + 16 * (size_t)chosen * L, sizeof(qo_cplx) * 16 * (size_t)L);
+#undef FWD_COST
+  memcpy(gates_out, gates + GS * (size_t)chosen * L, sizeof(qo_cplx) * GS * (size_t)L);
   res->reason = reason[chosen];
   res->m_final = M;
   res->sweeps = (int32_t)total[chosen];
@@ -745,4 +1005,23 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,
   free(c_prev); free(c_tr); free(c_v); free(success);
   free(gates); free(psi); free(phi); free(psiv); free(phiv);
   return 0;
+}
+
+int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds, const qo_cplx *fixed,
+                   int target_kind, const qo_cplx *U, int Lt, const int32_t *tpairs,
+                   const qo_cplx *tgates, const qo_cplx *samples_psi, const qo_cplx *samples_phi,
+                   int n_samples, int n_val, const qo_params *p, const qo_cplx *gates_in,
+                   qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
+  return instantiate_impl(2, n, L, pairs, kinds, fixed, target_kind, U, Lt, tpairs, tgates,
+                          samples_psi, samples_phi, n_samples, n_val, p, gates_in, gates_out, res,
+                          trace);
+}
+
+int qd_instantiate(int d, int n, int L, const int32_t *pairs, const qo_cplx *samples_psi,
+                   const qo_cplx *samples_phi, int n_samples, int n_val, const qo_params *p,
+                   const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
+  if (d < 2 || d > 4) return -1;
+  return instantiate_impl(d, n, L, pairs, NULL, NULL, QO_TARGET_SAMPLES, NULL, 0, NULL, NULL,
+                          samples_psi, samples_phi, n_samples, n_val, p, gates_in, gates_out, res,
+                          trace);
 }

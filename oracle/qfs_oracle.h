@@ -147,6 +147,25 @@ double qo_sweep(int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
                 const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
                 double gamma_scale, double *f_before, double *f_after, qo_cplx *gammas);
 
+/* Qudits (n of dimension d, 2 <= d <= 4; N = d^n, qudit 0 the most significant base-d
+ * digit; a two-qudit gate on (qa, qb) is D x D, D = d^2, local index d digit(qa) +
+ * digit(qb)). With d = 2 these compute what the qubit functions compute. */
+void qd_apply_gate(int d, int n, int M, qo_cplx *st, int qa, int qb, const qo_cplx *u, int dagger);
+void qd_environment(int d, int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, int qb,
+                    qo_cplx *G /* [D][D] */);
+void qd_svd(int D, const qo_cplx *G, qo_cplx *W, double *s, qo_cplx *V);
+void qd_update_gate(int D, const qo_cplx *G, double beta, qo_cplx *u);
+/* Haar D x D initial gate from indices 256 gate + D col + row of the start's stream. */
+void qd_haar_gate(int d, uint64_t seed, uint32_t start, uint32_t gate, qo_cplx *u);
+double qd_sweep(int d, int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
+                const qo_cplx *phi, qo_cplx *gates, double beta, double gamma_scale,
+                double *f_before, double *f_after);
+/* Instantiation on a fixed sample set (rows 0 .. n_samples - n_val - 1 train, the last
+ * n_val validate), the same control loop as qo_instantiate. */
+int qd_instantiate(int d, int n, int L, const int32_t *pairs, const qo_cplx *samples_psi,
+                   const qo_cplx *samples_phi, int n_samples, int n_val, const qo_params *p,
+                   const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res, qo_trace *trace);
+
 /* Full instantiation with the paper's control loop. kinds: [L] or NULL; fixed: [L][16]
  * constant gates (read for QO_GATE_FIXED; replace those slots of gates_in too). */
 int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,

@@ -102,3 +102,59 @@ def dense_qfactor_sweep(n, pairs, gates, U, kinds=None):
         X, d, Yh = np.linalg.svd(E)
         g[k] = Yh.conj().T @ X.conj().T
     return np.stack(g)
+
+
+# ------------------------------------------------------------------------ qudits
+def apply_gate_tensor_d(d, n, states, a, b, u):
+    """Apply the d^2 x d^2 gate u on ordered qudits (a, b) to [M][d^n] states via tensor
+    axes (qudit 0 first)."""
+    M = states.shape[0]
+    t = states.reshape((M,) + (d,) * n)
+    t = np.moveaxis(t, (1 + a, 1 + b), (1, 2))
+    shp = t.shape
+    t = t.reshape(M, d * d, -1)
+    t = np.einsum("qp,mpr->mqr", u, t)
+    t = t.reshape(shp)
+    t = np.moveaxis(t, (1, 2), (1 + a, 1 + b))
+    return t.reshape(M, -1)
+
+
+def gate_matrix_d(d, n, a, b, u):
+    N = d ** n
+    return apply_gate_tensor_d(d, n, np.eye(N, dtype=np.complex128), a, b, u).T
+
+
+def circuit_matrix_d(d, n, pairs, gates):
+    C = np.eye(d ** n, dtype=np.complex128)
+    for (a, b), u in zip(np.asarray(pairs).reshape(-1, 2), gates):
+        C = gate_matrix_d(d, n, int(a), int(b), u) @ C
+    return C
+
+
+def partial_trace_env_d(d, n, a, b, X):
+    """E[p][q] = sum_r X[(p,r),(q,r)] with qudits (a, b) as the local index."""
+    N = d ** n
+    T = X.reshape((d,) * (2 * n))
+    rest = [q for q in range(n) if q not in (a, b)]
+    order = [a, b] + rest + [n + a, n + b] + [n + q for q in rest]
+    T = np.transpose(T, order).reshape(d * d, N // (d * d), d * d, N // (d * d))
+    return np.einsum("prqr->pq", T)
+
+
+def dense_qfactor_sweep_d(d, n, pairs, gates, U):
+    """Full-unitary QFactor sweep on qudits (as dense_qfactor_sweep, base-d axes)."""
+    pairs = np.asarray(pairs).reshape(-1, 2)
+    g = [np.array(x, dtype=np.complex128) for x in gates]
+    L = len(g)
+    N = d ** n
+    for k in range(L - 1, -1, -1):
+        A = np.eye(N, dtype=np.complex128)
+        for j in range(k + 1, L):
+            A = gate_matrix_d(d, n, int(pairs[j][0]), int(pairs[j][1]), g[j]) @ A
+        B = np.eye(N, dtype=np.complex128)
+        for j in range(k):
+            B = gate_matrix_d(d, n, int(pairs[j][0]), int(pairs[j][1]), g[j]) @ B
+        E = partial_trace_env_d(d, n, int(pairs[k][0]), int(pairs[k][1]), B @ U.conj().T @ A)
+        X, _, Yh = np.linalg.svd(E)
+        g[k] = Yh.conj().T @ X.conj().T
+    return np.stack(g)
