@@ -350,6 +350,36 @@ int qfs_instantiate_samples(const qfs_template *tmpl, const qfs_c128 *psi,
                             const qfs_c128 *phi, int32_t M, double tol,
                             qfs_c128 *gates_out, double *cost_out);
 
+/* ------------------------------------------------------------------ qudits */
+/* QFactor-Sample on n qudits of dimension d (Sec. 5: the method applies unchanged to
+ * d-level gates; a sweep costs O(M d^n) where QFactor's costs O(d^{2n})). Qudit 0 is the
+ * most significant base-d digit of the amplitude index (N = d^n); tmpl->n_qubits is the
+ * qudit count, tmpl->pairs the ordered qudit pairs; a gate is a D x D unitary, D = d^2,
+ * row-major u[q][p] with local index d digit(a) + digit(b). d = 2 or 3; d^n <= 2^24;
+ * tmpl->kinds must be NULL (QFS_EUNSUPPORTED otherwise).
+ *
+ * Instantiation on a fixed sample set with the paper's control loop (Sec. 3, App. A), the
+ * SAMPLES semantics of qfs_instantiate: psi, phi device [n_samples][N] (phi = U psi);
+ * rows 0 .. n_samples - n_val - 1 train (M from params->m_init, doubling takes more rows,
+ * capped by m_max), the last n_val rows validate (n_val = 0: no generalisation test).
+ * gates_in: device [multistarts][L][D][D] or NULL for Haar-random D x D initial gates
+ * drawn from params->seed (role 3, stream = start, index 256 gate + D col + row of a
+ * column-major Ginibre block). gates_out: device [L][D][D]. Precision FP64 or MIXED
+ * (complex64 states, complex128 sweeps once the best running c_train < refine_below).
+ * params->timing and full_unitary are not supported here (full_unitary: QFS_EINVAL).
+ * Errors: QFS_EINVAL, QFS_EUNSUPPORTED, QFS_ENOMEM, QFS_EDEVICE. */
+int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi,
+                          const qfs_c128 *phi, int32_t n_samples, int32_t n_val,
+                          const qfs_params *params, const qfs_c128 *gates_in,
+                          qfs_c128 *gates_out, qfs_result *res);
+
+/* One qudit sweep for `starts` starts sharing a training set, as qfs_sweep: psi, phi
+ * device [M][N]; gates device [starts][L][D][D] updated in place; c_train host [starts]
+ * (Eq. 9 cost of the updated gates). */
+int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32_t M,
+                    const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates,
+                    int32_t precision, double beta, double *c_train, void *hip_stream);
+
 /* ------------------------------------------------- steps of the method (device) */
 /* M orthonormal Haar states (Sec. 3; App. A: columns of a Haar unitary): the Q of the
  * QR factorisation, with real positive diag(R), of the N x M complex Ginibre matrix

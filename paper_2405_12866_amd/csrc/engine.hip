@@ -377,7 +377,6 @@ struct GroupResult {
   std::vector<qfs_c128> gates;  // [L][16] of the chosen start (host copy)
 };
 
-enum { ST_RUN = 0, ST_STOP = 1, ST_OVER = 2 };
 
 // One independent QFactor-Sample run over starts [start0, start0 + S).
 class Group {
@@ -777,45 +776,10 @@ int Group::run(GroupResult &out, double t_start) {
     for (int s : active) {
       ct[s] = nct[s];
       cv[s] = Mv_ > 0 ? ncv[s] : nct[s];
-      iter[s] += 1;
-      total[s] += 1;
-      const bool improved = std::fabs(c_prev[s]) - std::fabs(ct[s]) > p_.diff_tol_r * std::fabs(ct[s]);
-      z[s] = improved ? 0 : z[s] + 1;
-      c_prev[s] = ct[s];
-      const bool gen_ok = full || Mv_ == 0 || cv[s] <= (1.0 + p_.overtrain_ratio) * ct[s];
-      if (ct[s] < p_.dist_tol && gen_ok) {
-        status[s] = ST_STOP;
-        reason[s] = QFS_SUCCESS;
-        any_success = true;
-        continue;
-      }
-      if (iter[s] >= p_.min_iter && !gen_ok) {
-        if (M_ < m_cap_) {
-          status[s] = ST_OVER;
-          any_over = true;
-          continue;
-        }
-        if (ct[s] < p_.dist_tol) {
-          status[s] = ST_STOP;
-          reason[s] = QFS_NOT_GENERALIZED;
-          continue;
-        }
-      }
-      if (iter[s] >= p_.min_iter && z[s] >= p_.plateau_window) {
-        status[s] = ST_STOP;
-        reason[s] = QFS_PLATEAU;
-        continue;
-      }
-      if (total[s] >= p_.max_iter) {
-        status[s] = ST_STOP;
-        reason[s] = QFS_MAX_ITER;
-        continue;
-      }
-      if (timed_out) {
-        status[s] = ST_STOP;
-        reason[s] = QFS_TIMEOUT;
-        continue;
-      }
+      status[s] = control_step(p_, ct[s], cv[s], full || Mv_ == 0, M_ < m_cap_, timed_out, iter[s], z[s],
+                               total[s], c_prev[s], reason[s]);
+      any_success |= status[s] == ST_STOP && reason[s] == QFS_SUCCESS;
+      any_over |= status[s] == ST_OVER;
     }
     if (any_success) {
       double best = INFINITY;

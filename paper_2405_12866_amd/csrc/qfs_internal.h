@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -176,6 +177,31 @@ int launch_unit_columns(int64_t N, int64_t ld, c128 *A, hipStream_t s);
 // constant gates; else every gate but those. QFS_EINVAL with a detail naming `what`.
 int check_gates_unitary(const qfs_c128 *gates_dev, size_t count, int L, const int32_t *kinds,
                         bool fixed_only, const char *what, hipStream_t s);
+
+// Control of one running start after a sweep (Sec. 3 success relations, Eq. 12; App. A:
+// plateau test Eq. 13 over plateau_window sweeps after min_iter, max_iter, time budget).
+// ct, cv: training and validation cost after the sweep; no_gen_test: the training set is
+// the full basis or there is no validation set; can_double: M may still grow. Updates the
+// counters and returns ST_STOP (reason set), ST_OVER (overtrained, M may double) or ST_RUN.
+enum { ST_RUN = 0, ST_STOP = 1, ST_OVER = 2 };
+inline int control_step(const qfs_params &p, double ct, double cv, bool no_gen_test, bool can_double,
+                        bool timed_out, int &iter, int &z, int64_t &total, double &c_prev, int &reason) {
+  iter += 1;
+  total += 1;
+  const bool improved = std::fabs(c_prev) - std::fabs(ct) > p.diff_tol_r * std::fabs(ct);
+  z = improved ? 0 : z + 1;
+  c_prev = ct;
+  const bool gen_ok = no_gen_test || cv <= (1.0 + p.overtrain_ratio) * ct;
+  if (ct < p.dist_tol && gen_ok) return reason = QFS_SUCCESS, ST_STOP;
+  if (iter >= p.min_iter && !gen_ok) {
+    if (can_double) return ST_OVER;
+    if (ct < p.dist_tol) return reason = QFS_NOT_GENERALIZED, ST_STOP;
+  }
+  if (iter >= p.min_iter && z >= p.plateau_window) return reason = QFS_PLATEAU, ST_STOP;
+  if (total >= p.max_iter) return reason = QFS_MAX_ITER, ST_STOP;
+  if (timed_out) return reason = QFS_TIMEOUT, ST_STOP;
+  return ST_RUN;
+}
 
 // The regularised update with the environment normalised by M, polar((1 - beta) G / M +
 // beta u), is the paper's unnormalised form polar((1 - b) G + b u) at

@@ -1,0 +1,862 @@
+// QFactor-Sample on qudits (Sec. 5: the method carries over unchanged to d-level gates,
+// where a sweep costs O(M d^n) against QFactor's O(d^{2n})).
+//
+// n qudits of dimension d, N = d^n amplitudes, qudit 0 the most significant base-d
+// digit; a two-qudit gate on (a, b) is a D x D unitary, D = d^2, row-major u[q][p], local
+// index d digit(a) + digit(b). State sets are amplitude-major: element (i, j) (amplitude
+// i of sample j) at i * M + j, so the D amplitudes of a gate group are D rows of M
+// consecutive samples, read and written as runs whatever qudits the gate acts on.
+// Kernels are templated on the state precision R and on d; the environment partials,
+// the polar update and the costs are FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "philox.h"
+#include "qfs_internal.h"
+
+namespace qfs {
+namespace {
+
+constexpr int kQdBlock = 256;
+constexpr int kQdMaxP = 64;  // environment partial blocks per (start, row group)
+
+// Position of a gate group: items are (group r, sample j), j fastest.
+struct QdGeom {
+  int32_t M;        // samples in the set (row length)
+  int64_t groups;   // N / D
+  int64_t s_lo;     // d^(lower digit position of the two gate qudits)
+  int64_t mid;      // d^(digits strictly between the two positions)
+  int64_t sa, sb;   // strides of the gate's first and second qudit
+};
+
+template <int d>
+__device__ __forceinline__ int64_t qd_base(const QdGeom &g, int64_t r) {
+  const int64_t r_lo = r % g.s_lo;
+  const int64_t t = r / g.s_lo;
+  const int64_t r_mid = t % g.mid, r_hi = t / g.mid;
+  // digits: r_hi | 0 (upper gate qudit) | r_mid | 0 (lower gate qudit) | r_lo
+  return r_hi * d * g.mid * d * g.s_lo + r_mid * d * g.s_lo + r_lo;
+}
+
+QdGeom qd_geom(int d, int n, int M, int qa, int qb) {
+  auto pw = [&](int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= d;
+    return r;
+  };
+  const int pa = n - 1 - qa, pb = n - 1 - qb;
+  const int lo = std::min(pa, pb), hi = std::max(pa, pb);
+  QdGeom g;
+  g.M = M;
+  g.groups = pw(n) / (d * d);
+  g.s_lo = pw(lo);
+  g.mid = pw(hi - lo - 1);
+  g.sa = pw(pa);
+  g.sb = pw(pb);
+  return g;
+}
+
+// dst = u_k src (dagger: u_k^dagger src) for every active start; the gate (FP64 master)
+// goes through LDS in the state precision.
+template <typename R, int d>
+__global__ __launch_bounds__(kQdBlock) void k_qd_apply(const cx<R> *src, int64_t src_stride, cx<R> *dst,
+                                                       int64_t dst_stride, const c128 *gates,
+                                                       int32_t gstride, int32_t k, int32_t dagger,
+                                                       QdGeom g, const int32_t *slots) {
+  constexpr int D = d * d;
+  __shared__ cx<R> u[D * D];
+  const int s = slots[blockIdx.y];
+  const c128 *gk = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  for (int e = threadIdx.x; e < D * D; e += kQdBlock) {
+    const int q = e / D, p = e % D;
+    const c128 v = dagger ? cconj(gk[p * D + q]) : gk[e];
+    u[e] = cmake<R>((R)v.re, (R)v.im);
+  }
+  __syncthreads();
+  const cx<R> *x = src + (int64_t)s * src_stride;
+  cx<R> *y = dst + (int64_t)s * dst_stride;
+  const int64_t items = g.groups * g.M;
+  for (int64_t it = blockIdx.x * (int64_t)kQdBlock + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * kQdBlock) {
+    const int64_t j = it % g.M, r = it / g.M;
+    const int64_t base = qd_base<d>(g, r);
+    int64_t off[D];
+    cx<R> in[D];
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        off[a * d + b] = (base + a * g.sa + b * g.sb) * g.M + j;
+        in[a * d + b] = x[off[a * d + b]];
+      }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      cx<R> acc = cmake<R>(0, 0);
+#pragma unroll
+      for (int p = 0; p < D; ++p) cfma(acc, u[q * D + p], in[p]);
+      y[off[q]] = acc;
+    }
+  }
+}
+
+// Environment partials: block (row group xg, partial blk, start) accumulates rows
+// q = d xg + y (y < d) of Gamma[q][p] = sum a(q) conj(b(p)) over its items in FP64 and
+// writes them to partials[s][blk][q][p].
+template <typename R, int d>
+__global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_stride, const cx<R> *b,
+                                                     int64_t b_stride, QdGeom g, int32_t P,
+                                                     c128 *partials, const int32_t *slots) {
+  constexpr int D = d * d;
+  constexpr int W = kQdBlock / 64;
+  __shared__ c128 red[W][d * D];
+  const int s = slots[blockIdx.y];
+  const int xg = blockIdx.x % d, blk = blockIdx.x / d;
+  const cx<R> *as = a + (int64_t)s * a_stride;
+  const cx<R> *bs = b + (int64_t)s * b_stride;
+  c128 acc[d][D];
+#pragma unroll
+  for (int y = 0; y < d; ++y)
+#pragma unroll
+    for (int p = 0; p < D; ++p) acc[y][p] = cmake(0.0, 0.0);
+  const int64_t items = g.groups * g.M;
+  for (int64_t it = blk * (int64_t)kQdBlock + threadIdx.x; it < items; it += (int64_t)P * kQdBlock) {
+    const int64_t j = it % g.M, r = it / g.M;
+    const int64_t base = qd_base<d>(g, r);
+    c128 bv[D], av[d];
+#pragma unroll
+    for (int x = 0; x < d; ++x)
+#pragma unroll
+      for (int y = 0; y < d; ++y) {
+        const cx<R> v = bs[(base + x * g.sa + y * g.sb) * g.M + j];
+        bv[x * d + y] = cmake((double)v.re, (double)v.im);
+      }
+#pragma unroll
+    for (int y = 0; y < d; ++y) {
+      const cx<R> v = as[(base + xg * g.sa + y * g.sb) * g.M + j];
+      av[y] = cmake((double)v.re, (double)v.im);
+    }
+#pragma unroll
+    for (int y = 0; y < d; ++y)
+#pragma unroll
+      for (int p = 0; p < D; ++p) cfma_conj(acc[y][p], av[y], bv[p]);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int y = 0; y < d; ++y)
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      double re = acc[y][p].re, im = acc[y][p].im;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        re += __shfl_xor(re, o);
+        im += __shfl_xor(im, o);
+      }
+      if (lane == 0) red[w][y * D + p] = cmake(re, im);
+    }
+  __syncthreads();
+  if (threadIdx.x < d * D) {
+    c128 t = red[0][threadIdx.x];
+    for (int ww = 1; ww < W; ++ww) t = t + red[ww][threadIdx.x];
+    const int y = threadIdx.x / D, p = threadIdx.x % D;
+    const int q = xg * d + y;
+    partials[(((int64_t)s * P + blk) * D + q) * D + p] = t;
+  }
+}
+
+// Per start (one block): fixed-order sum of the partials, then u_k <- W V^dagger for
+// (1 - beta) Gamma + beta u_k = W S V^dagger by one-sided Jacobi on one wave: lane r holds
+// row r of the working matrix and of V; for each column pair the three Gram entries are
+// wave sums over the rows, so every lane derives the same rotation.
+template <int d>
+__global__ __launch_bounds__(kQdBlock) void k_qd_finalize(const c128 *partials, int32_t P,
+                                                          const int32_t *slots, double beta,
+                                                          c128 *gates, int32_t gstride, int32_t k) {
+  constexpr int D = d * d;
+  __shared__ c128 G[D * D];
+  __shared__ c128 Vs[D * D];
+  __shared__ c128 Gc[D * D];
+  __shared__ double sig[D];
+  const int s = slots[blockIdx.x];
+  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  for (int e = threadIdx.x; e < D * D; e += kQdBlock) {
+    const c128 *src = partials + (int64_t)s * P * D * D + e;
+    c128 a0 = cmake(0.0, 0.0), a1 = cmake(0.0, 0.0);
+    int blk = 0;
+    for (; blk + 1 < P; blk += 2) {
+      a0 = a0 + src[(int64_t)blk * D * D];
+      a1 = a1 + src[(int64_t)(blk + 1) * D * D];
+    }
+    if (blk < P) a0 = a0 + src[(int64_t)blk * D * D];
+    const c128 gm = a0 + a1;
+    G[e] = beta != 0.0 ? cmake((1.0 - beta) * gm.re + beta * u[e].re, (1.0 - beta) * gm.im + beta * u[e].im)
+                       : gm;
+  }
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int r = threadIdx.x;
+  const bool act = r < D;
+  c128 g[D], v[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    g[c] = act ? G[r * D + c] : cmake(0.0, 0.0);
+    v[c] = cmake(act && r == c ? 1.0 : 0.0, 0.0);
+  }
+  auto wsum = [](double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+  };
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+#pragma unroll
+    for (int p = 0; p < D - 1; ++p)
+#pragma unroll
+      for (int q = p + 1; q < D; ++q) {
+        const double al = wsum(cabs2(g[p])), be = wsum(cabs2(g[q]));
+        const double gr = wsum(g[p].re * g[q].re + g[p].im * g[q].im);
+        const double gi = wsum(g[p].re * g[q].im - g[p].im * g[q].re);
+        const double ag = sqrt(gr * gr + gi * gi);
+        if (ag > 0.0 && ag > 1e-15 * sqrt(al * be)) {
+          rotated = 1;
+          const c128 ec = cmake(gr / ag, -gi / ag);  // conj(gamma) / |gamma|
+          const double tau = (be - al) / (2.0 * ag);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          const c128 egq = ec * g[q], evq = ec * v[q];
+          const c128 gp = g[p], vp = v[p];
+          g[p] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+          g[q] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+          v[p] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+          v[q] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+        }
+      }
+    if (!rotated) break;
+  }
+  // singular values; W columns g / sigma; V rows to LDS
+  double smax = 0.0, smin = INFINITY;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const double sc = sqrt(wsum(cabs2(g[c])));
+    smax = fmax(smax, sc);
+    smin = fmin(smin, sc);
+    if (r == 0) sig[c] = sc;
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      Vs[r * D + c] = v[c];
+      Gc[r * D + c] = g[c];
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (smin > 1e-200 && smin > 1e-13 * smax) {
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        c128 acc = cmake(0.0, 0.0);
+#pragma unroll
+        for (int kk = 0; kk < D; ++kk) cfma_conj(acc, cscale(g[kk], 1.0 / sig[kk]), Vs[c * D + kk]);
+        u[r * D + c] = acc;
+      }
+    }
+    return;
+  }
+  // a (near) singular environment: left vectors in decreasing-sigma order, orthonormalised
+  // and completed with unit vectors (any such completion attains the maximum)
+  if (r == 0) {
+    int ord[D];
+    for (int c = 0; c < D; ++c) ord[c] = c;
+    for (int a = 0; a < D; ++a)
+      for (int b2 = a + 1; b2 < D; ++b2)
+        if (sig[ord[b2]] > sig[ord[a]]) {
+          const int t = ord[a];
+          ord[a] = ord[b2];
+          ord[b2] = t;
+        }
+    c128 w[D][D];
+    for (int kk = 0; kk < D; ++kk) {
+      const int cc = ord[kk];
+      c128 x[D];
+      bool ok = sig[cc] > 0.0 && sig[cc] > 1e-13 * smax;
+      if (ok) {
+        for (int rr = 0; rr < D; ++rr) x[rr] = cscale(Gc[rr * D + cc], 1.0 / sig[cc]);
+        for (int rep = 0; rep < 2; ++rep)
+          for (int o = 0; o < kk; ++o) {
+            c128 dd = cmake(0.0, 0.0);
+            for (int rr = 0; rr < D; ++rr) cfma(dd, cconj(w[o][rr]), x[rr]);
+            for (int rr = 0; rr < D; ++rr) x[rr] = x[rr] - dd * w[o][rr];
+          }
+        double nn = 0.0;
+        for (int rr = 0; rr < D; ++rr) nn += cabs2(x[rr]);
+        nn = sqrt(nn);
+        if (nn > 0.5)
+          for (int rr = 0; rr < D; ++rr) x[rr] = cscale(x[rr], 1.0 / nn);
+        else
+          ok = false;
+      }
+      if (!ok) {
+        double best = -1.0;
+        c128 bx[D];
+        for (int e = 0; e < D; ++e) {
+          c128 yv[D];
+          for (int rr = 0; rr < D; ++rr) yv[rr] = cmake(rr == e ? 1.0 : 0.0, 0.0);
+          for (int rep = 0; rep < 2; ++rep)
+            for (int o = 0; o < kk; ++o) {
+              c128 dd = cmake(0.0, 0.0);
+              for (int rr = 0; rr < D; ++rr) cfma(dd, cconj(w[o][rr]), yv[rr]);
+              for (int rr = 0; rr < D; ++rr) yv[rr] = yv[rr] - dd * w[o][rr];
+            }
+          double nn = 0.0;
+          for (int rr = 0; rr < D; ++rr) nn += cabs2(yv[rr]);
+          if (nn > best) {
+            best = nn;
+            for (int rr = 0; rr < D; ++rr) bx[rr] = yv[rr];
+          }
+        }
+        const double inv = 1.0 / sqrt(best);
+        for (int rr = 0; rr < D; ++rr) x[rr] = cscale(bx[rr], inv);
+      }
+      for (int rr = 0; rr < D; ++rr) w[kk][rr] = x[rr];
+    }
+    for (int q = 0; q < D; ++q)
+      for (int p = 0; p < D; ++p) {
+        c128 acc = cmake(0.0, 0.0);
+        for (int kk = 0; kk < D; ++kk) cfma_conj(acc, w[kk][q], Vs[p * D + ord[kk]]);
+        u[q * D + p] = acc;
+      }
+  }
+}
+
+// sum |x - ref|^2 over a set, per block, FP64 (partials[s][blk]).
+template <typename R>
+__global__ __launch_bounds__(kQdBlock) void k_qd_dist(const cx<R> *x, int64_t x_stride, const cx<R> *ref,
+                                                      int64_t ref_stride, int64_t count, double *partials,
+                                                      const int32_t *slots) {
+  __shared__ double red[kQdBlock / 64];
+  const int s = slots[blockIdx.y];
+  const cx<R> *xs = x + (int64_t)s * x_stride;
+  const cx<R> *rs = ref + (int64_t)s * ref_stride;
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)kQdBlock + threadIdx.x; e < count; e += (int64_t)gridDim.x * kQdBlock) {
+    const double dr = (double)xs[e].re - (double)rs[e].re, di = (double)xs[e].im - (double)rs[e].im;
+    acc += dr * dr + di * di;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kQdBlock / 64; ++w) t += red[w];
+    partials[(int64_t)s * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Sample-major [rows][N] complex128 (rows row0 .. row0 + M - 1 of src) to amplitude-major
+// [N][M] in precision R.
+template <typename R>
+__global__ void k_qd_pack(const c128 *src, int64_t N, int64_t row0, int32_t M, cx<R> *dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N * M; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / M, j = e % M;
+    const c128 v = src[(row0 + j) * N + i];
+    dst[e] = cmake<R>((R)v.re, (R)v.im);
+  }
+}
+
+// Haar D x D initial gates: Ginibre block at indices 256 gate + D col + row of the start's
+// initial-gate stream, orthonormalised column by column (positive diag(R)).
+template <int d>
+__global__ void k_qd_haar(uint64_t seed, int32_t start0, int32_t starts, int32_t L, c128 *out) {
+  constexpr int D = d * d;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)starts * L) return;
+  const int s = (int)(t / L), k = (int)(t % L);
+  c128 q[D][D];  // [col][row]
+  for (int c = 0; c < D; ++c)
+    for (int r = 0; r < D; ++r)
+      q[c][r] = complex_normal(seed, 3u, (uint32_t)(start0 + s), (uint64_t)k * 256u + (uint64_t)(c * D + r));
+  for (int c = 0; c < D; ++c) {
+    for (int rep = 0; rep < 2; ++rep)
+      for (int o = 0; o < c; ++o) {
+        c128 dd = cmake(0.0, 0.0);
+        for (int r = 0; r < D; ++r) cfma(dd, cconj(q[o][r]), q[c][r]);
+        for (int r = 0; r < D; ++r) q[c][r] = q[c][r] - dd * q[o][r];
+      }
+    double nn = 0.0;
+    for (int r = 0; r < D; ++r) nn += cabs2(q[c][r]);
+    const double inv = 1.0 / sqrt(nn);
+    for (int r = 0; r < D; ++r) q[c][r] = cscale(q[c][r], inv);
+  }
+  c128 *u = out + t * D * D;
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) u[r * D + c] = q[c][r];
+}
+
+double qd_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t qd_pow(int d, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= d;
+  return r;
+}
+
+int qd_grid(int64_t items) { return (int)std::min<int64_t>((items + kQdBlock - 1) / kQdBlock, 4096); }
+
+// One problem's device state: the sweep machinery over `S` starts for state precision R.
+template <typename R>
+struct QdSweeper {
+  int d = 0, n = 0, L = 0, S = 0;
+  int64_t N = 0;
+  const int32_t *pairs = nullptr;  // host [L][2]
+  hipStream_t st = nullptr;
+  int M = 0, Mv = 0;
+  DevBuf psi, phi, psiv, phiv;  // working sets [N][M] in R (shared by the starts)
+  DevBuf blist, astate, vstate, partials, dpart, costs, slots;
+  c128 *g64 = nullptr;  // [S][L][D][D]
+  double beta = 0.0;
+  int nslots = 0;
+
+  int D() const { return d * d; }
+  int64_t set() const { return N * M; }
+
+  template <int dd>
+  int apply_t(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows) {
+    const int qa = pairs[2 * k], qb = pairs[2 * k + 1];
+    const QdGeom g = qd_geom(dd, n, Mrows, qa, qb);
+    hipLaunchKernelGGL((k_qd_apply<R, dd>), dim3(qd_grid(g.groups * Mrows), nslots), dim3(kQdBlock), 0, st, src, ss,
+                       dst, ds, g64, L * dd * dd * dd * dd, k, dagger ? 1 : 0, g, slots.as<int32_t>());
+    QFS_HIP(hipGetLastError());
+    return QFS_OK;
+  }
+  int apply(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows) {
+    return d == 2 ? apply_t<2>(src, ss, dst, ds, k, dagger, Mrows) : apply_t<3>(src, ss, dst, ds, k, dagger, Mrows);
+  }
+  template <int dd>
+  int env_t(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k) {
+    const QdGeom g = qd_geom(dd, n, M, pairs[2 * k], pairs[2 * k + 1]);
+    const int P = (int)std::max<int64_t>(1, std::min<int64_t>(kQdMaxP, (g.groups * M + kQdBlock - 1) / kQdBlock));
+    hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * P, nslots), dim3(kQdBlock), 0, st, a, as, b, bs, g, P,
+                       partials.as<c128>(), slots.as<int32_t>());
+    QFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(nslots), dim3(kQdBlock), 0, st, partials.as<c128>(), P,
+                       slots.as<int32_t>(), beta, g64, L * dd * dd * dd * dd, k);
+    QFS_HIP(hipGetLastError());
+    return QFS_OK;
+  }
+  int env(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k) {
+    return d == 2 ? env_t<2>(a, as, b, bs, k) : env_t<3>(a, as, b, bs, k);
+  }
+  int dist(const cx<R> *x, int64_t xs, const cx<R> *ref, int64_t rs, int64_t count, int Mrows, double *out) {
+    const int P = (int)std::min<int64_t>(kQdMaxP * 4, (count + kQdBlock - 1) / kQdBlock);
+    hipLaunchKernelGGL((k_qd_dist<R>), dim3(P, nslots), dim3(kQdBlock), 0, st, x, xs, ref, rs, count,
+                       dpart.as<double>(), slots.as<int32_t>());
+    QFS_HIP(hipGetLastError());
+    return launch_dist_finalize(P, dpart.as<double>(), slots.as<int32_t>(), nslots, Mrows, out, st);
+  }
+
+  int alloc(int Mnew, int Mvnew) {
+    M = Mnew;
+    Mv = Mvnew;
+    const size_t cb = sizeof(cx<R>);
+    QFS_TRY(psi.alloc(cb * set()));
+    QFS_TRY(phi.alloc(cb * set()));
+    QFS_TRY(blist.alloc(cb * set() * (size_t)std::max(L - 1, 1) * S));
+    QFS_TRY(astate.alloc(cb * set() * S));
+    if (Mv > 0) {
+      QFS_TRY(psiv.alloc(cb * N * Mv));
+      QFS_TRY(phiv.alloc(cb * N * Mv));
+      QFS_TRY(vstate.alloc(cb * N * Mv * S));
+    }
+    QFS_TRY(partials.alloc(sizeof(c128) * (size_t)S * kQdMaxP * 256));
+    QFS_TRY(dpart.alloc(sizeof(double) * (size_t)S * kQdMaxP * 4));
+    if (!costs.ptr) QFS_TRY(costs.alloc(sizeof(double) * 3 * S));
+    if (!slots.ptr) QFS_TRY(slots.alloc(sizeof(int32_t) * S));
+    return QFS_OK;
+  }
+
+  // forward: B list from the current gates; with_c0: cost of the current gates
+  // (costs[2S + s]); validation cost (costs[S + s]) when Mv > 0
+  int forward(bool with_c0) {
+    cx<R> *P0 = psi.as<cx<R>>(), *B = blist.as<cx<R>>();
+    const int64_t sN = set(), bstride = sN * std::max(L - 1, 1);
+    for (int k = 0; k < L - 1; ++k)
+      QFS_TRY(apply(k == 0 ? P0 : B + (k - 1) * sN, k == 0 ? 0 : bstride, B + k * sN, bstride, k, false, M));
+    if (with_c0) {
+      cx<R> *A = astate.as<cx<R>>();
+      QFS_TRY(apply(L == 1 ? P0 : B + (L - 2) * sN, L == 1 ? 0 : bstride, A, sN, L - 1, false, M));
+      QFS_TRY(dist(A, sN, phi.as<cx<R>>(), 0, sN, M, costs.as<double>() + 2 * S));
+    }
+    if (Mv > 0) {
+      cx<R> *V = vstate.as<cx<R>>();
+      const int64_t vN = N * Mv;
+      for (int k = 0; k < L; ++k)
+        QFS_TRY(apply(k == 0 ? psiv.as<cx<R>>() : V, k == 0 ? 0 : vN, V, vN, k, false, Mv));
+      QFS_TRY(dist(V, vN, phiv.as<cx<R>>(), 0, vN, Mv, costs.as<double>() + S));
+    }
+    return QFS_OK;
+  }
+
+  // right to left: a <- u_{k+1}^dagger a, Gamma_k against B_k, u_k <- polar; then the
+  // Eq. 9 cost of the updated gates (costs[s])
+  int backward() {
+    cx<R> *P0 = psi.as<cx<R>>(), *F = phi.as<cx<R>>(), *B = blist.as<cx<R>>(), *A = astate.as<cx<R>>();
+    const int64_t sN = set(), bstride = sN * std::max(L - 1, 1);
+    for (int k = L - 1; k >= 0; --k) {
+      if (k < L - 1) QFS_TRY(apply(k == L - 2 ? F : A, k == L - 2 ? 0 : sN, A, sN, k + 1, true, M));
+      const cx<R> *a = k == L - 1 ? F : A;
+      const int64_t as = k == L - 1 ? 0 : sN;
+      QFS_TRY(env(a, as, k == 0 ? P0 : B + (k - 1) * sN, k == 0 ? 0 : bstride, k));
+    }
+    QFS_TRY(apply(L == 1 ? F : A, L == 1 ? 0 : sN, A, sN, 0, true, M));
+    QFS_TRY(dist(A, sN, P0, 0, sN, M, costs.as<double>()));
+    return QFS_OK;
+  }
+
+  int set_slots(const std::vector<int> &active) {
+    nslots = (int)active.size();
+    if (nslots == 0) return QFS_OK;
+    QFS_HIP(hipMemcpyAsync(slots.ptr, active.data(), sizeof(int32_t) * nslots, hipMemcpyHostToDevice, st));
+    return QFS_OK;
+  }
+};
+
+// Host check that count D x D gates (device) are unitary to 1e-10.
+int check_gates_unitary_n(const qfs_c128 *gates_dev, size_t count, int D, const char *what, hipStream_t s) {
+  std::vector<qfs_c128> h(count * D * D);
+  QFS_HIP(hipMemcpyAsync(h.data(), gates_dev, sizeof(qfs_c128) * h.size(), hipMemcpyDeviceToHost, s));
+  QFS_HIP(hipStreamSynchronize(s));
+  for (size_t gi = 0; gi < count; ++gi) {
+    const qfs_c128 *u = h.data() + gi * D * D;
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) {
+        double re = (i == j) ? -1.0 : 0.0, im = 0.0;
+        for (int k = 0; k < D; ++k) {
+          const qfs_c128 a = u[k * D + i], b = u[k * D + j];  // conj(u[k][i]) u[k][j]
+          re += a.re * b.re + a.im * b.im;
+          im += a.re * b.im - a.im * b.re;
+        }
+        if (!std::isfinite(re) || !std::isfinite(im) || std::fabs(re) > 1e-10 || std::fabs(im) > 1e-10) {
+          set_error_detail(std::string(what) + ": gate " + std::to_string(gi) + " is not unitary to 1e-10");
+          return QFS_EINVAL;
+        }
+      }
+  }
+  return QFS_OK;
+}
+
+int qd_validate(int d, const qfs_template *t) {
+  if (d != 2 && d != 3) {
+    set_error_detail("qudits: d must be 2 or 3");
+    return QFS_EUNSUPPORTED;
+  }
+  if (!t || t->n_qubits < 2 || t->n_gates < 1 || !t->pairs || qd_pow(d, t->n_qubits) > (int64_t(1) << 24)) {
+    set_error_detail("qudits: need n >= 2, d^n <= 2^24, n_gates >= 1, pairs");
+    return QFS_EINVAL;
+  }
+  if (t->kinds) {
+    set_error_detail("qudits: gate kinds are not supported");
+    return QFS_EUNSUPPORTED;
+  }
+  for (int k = 0; k < t->n_gates; ++k) {
+    const int a = t->pairs[2 * k], b = t->pairs[2 * k + 1];
+    if (a < 0 || b < 0 || a >= t->n_qubits || b >= t->n_qubits || a == b) {
+      set_error_detail("qudits: gate " + std::to_string(k) + " has an invalid qudit pair");
+      return QFS_EINVAL;
+    }
+  }
+  return QFS_OK;
+}
+
+// Load rows [row0, row0 + M) of a sample-major complex128 set into an amplitude-major R set.
+template <typename R>
+int qd_pack(const qfs_c128 *src, int64_t N, int row0, int M, DevBuf &dst, hipStream_t st) {
+  if (M <= 0) return QFS_OK;
+  hipLaunchKernelGGL(k_qd_pack<R>, dim3(qd_grid(N * M)), dim3(kQdBlock), 0, st, reinterpret_cast<const c128 *>(src),
+                     N, (int64_t)row0, M, dst.as<cx<R>>());
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+template <typename R>
+int qd_load_sets(QdSweeper<R> &w, const qfs_c128 *psi, const qfs_c128 *phi, int n_train, int n_val) {
+  QFS_TRY(qd_pack<R>(psi, w.N, 0, w.M, w.psi, w.st));
+  QFS_TRY(qd_pack<R>(phi, w.N, 0, w.M, w.phi, w.st));
+  if (w.Mv > 0) {
+    QFS_TRY(qd_pack<R>(psi, w.N, n_train, n_val, w.psiv, w.st));
+    QFS_TRY(qd_pack<R>(phi, w.N, n_train, n_val, w.phiv, w.st));
+  }
+  return QFS_OK;
+}
+
+// The App. A control loop on a fixed sample set, for one precision; returns when every
+// start has stopped, a start succeeded, or the precision switch is due (refine = true).
+struct QdState {
+  std::vector<int> status, reason, iter, z;
+  std::vector<int64_t> total;
+  std::vector<double> c_prev, ct, cv;
+  int M = 0, m_cap = 0, restarts = 0, m_total = 0, chosen = -1;
+  bool need_c0 = true;
+  int64_t start_sweeps = 0;
+  double amp_updates = 0.0, sweep_seconds = 0.0;
+};
+
+template <typename R>
+int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *phi, int n_train, int n_val,
+           const qfs_params &p, c128 *g64, int S, QdState &cs, double t0, bool &refine) {
+  QdSweeper<R> w;
+  w.d = d;
+  w.n = t->n_qubits;
+  w.L = t->n_gates;
+  w.S = S;
+  w.N = qd_pow(d, w.n);
+  w.pairs = t->pairs;
+  w.st = static_cast<hipStream_t>(p.hip_stream);
+  w.g64 = g64;
+  w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
+  QFS_TRY(w.alloc(cs.M, n_val));
+  QFS_TRY(qd_load_sets<R>(w, psi, phi, n_train, n_val));
+  std::vector<int> active;
+  for (int s = 0; s < S; ++s)
+    if (cs.status[s] != ST_STOP) active.push_back(s);
+  QFS_TRY(w.set_slots(active));
+  std::vector<double> h(3 * S);
+  auto read = [&]() -> int {
+    QFS_HIP(hipMemcpyAsync(h.data(), w.costs.ptr, sizeof(double) * 3 * S, hipMemcpyDeviceToHost, w.st));
+    QFS_HIP(hipStreamSynchronize(w.st));
+    return QFS_OK;
+  };
+  hipEvent_t e0, e1;
+  QFS_HIP(hipEventCreate(&e0));
+  QFS_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  QFS_TRY(w.forward(cs.need_c0));
+  QFS_TRY(read());
+  if (cs.need_c0) {
+    for (int s : active) cs.c_prev[s] = h[2 * S + s];
+    cs.need_c0 = false;
+  }
+  const int64_t N = w.N;
+  for (;;) {
+    QFS_HIP(hipEventRecord(e0, w.st));
+    QFS_TRY(w.backward());
+    QFS_TRY(w.forward(false));
+    QFS_HIP(hipEventRecord(e1, w.st));
+    QFS_TRY(read());
+    float ms = 0.f;
+    QFS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    cs.sweep_seconds += 1e-3 * ms;
+    cs.start_sweeps += (int64_t)active.size();
+    cs.amp_updates += (double)active.size() * (double)(cs.M + n_val) * (double)N * (double)w.L;
+    const bool full = (int64_t)cs.M == N;
+    const bool timed_out = p.time_budget_s > 0 && qd_now() - t0 > p.time_budget_s;
+    bool any_success = false, any_over = false;
+    for (int s : active) {
+      cs.ct[s] = h[s];
+      cs.cv[s] = n_val > 0 ? h[S + s] : h[s];
+      cs.status[s] = control_step(p, cs.ct[s], cs.cv[s], full || n_val == 0, cs.M < cs.m_cap, timed_out, cs.iter[s],
+                                  cs.z[s], cs.total[s], cs.c_prev[s], cs.reason[s]);
+      any_success |= cs.status[s] == ST_STOP && cs.reason[s] == QFS_SUCCESS;
+      any_over |= cs.status[s] == ST_OVER;
+    }
+    if (any_success) {
+      double best = INFINITY;
+      for (int s : active)
+        if (cs.status[s] == ST_STOP && cs.reason[s] == QFS_SUCCESS && cs.ct[s] < best) {
+          best = cs.ct[s];
+          cs.chosen = s;
+        }
+      return QFS_OK;
+    }
+    if (any_over) {
+      // double-and-restart: more rows of the sample set, every gate kept (App. A)
+      cs.M = std::min(2 * cs.M, cs.m_cap);
+      cs.m_total += cs.M;
+      ++cs.restarts;
+      active.clear();
+      for (int s = 0; s < S; ++s)
+        if (cs.status[s] != ST_STOP) {
+          cs.status[s] = ST_RUN;
+          cs.iter[s] = 0;
+          cs.z[s] = 0;
+          active.push_back(s);
+        }
+      QFS_HIP(hipStreamSynchronize(w.st));
+      QFS_TRY(w.alloc(cs.M, n_val));
+      w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
+      QFS_TRY(qd_load_sets<R>(w, psi, phi, n_train, n_val));
+      QFS_TRY(w.set_slots(active));
+      QFS_TRY(w.forward(true));
+      QFS_TRY(read());
+      for (int s : active) cs.c_prev[s] = h[2 * S + s];
+      continue;
+    }
+    std::vector<int> next;
+    for (int s : active)
+      if (cs.status[s] == ST_RUN) next.push_back(s);
+    if (next.empty()) return QFS_OK;
+    if (sizeof(R) == 4) {
+      double best = INFINITY;
+      for (int s : next) best = std::min(best, cs.ct[s]);
+      if (best < p.refine_below) {
+        refine = true;  // complex128 sweeps from here, same gates and counters
+        return QFS_OK;
+      }
+    }
+    if (next.size() != active.size()) {
+      // the forward pass of this sweep already holds the survivors' B lists (per start)
+      active = next;
+      QFS_TRY(w.set_slots(active));
+    }
+  }
+}
+
+}  // namespace
+}  // namespace qfs
+
+using namespace qfs;
+
+extern "C" {
+
+int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi, const qfs_c128 *phi,
+                          int32_t n_samples, int32_t n_val, const qfs_params *params,
+                          const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res) {
+  const double t0 = qd_now();
+  QFS_TRY(qd_validate(d, tmpl));
+  if (!params || !psi || !phi || !gates_out || !res) {
+    set_error_detail("qudits: null argument");
+    return QFS_EINVAL;
+  }
+  const qfs_params &p = *params;
+  const int n = tmpl->n_qubits, L = tmpl->n_gates, D = d * d;
+  const int64_t N = qd_pow(d, n);
+  const int n_train = n_samples - n_val;
+  if (n_val < 0 || n_train < 1 || n_train > N || p.multistarts < 1 || p.m_init < 1 || p.max_iter < 1 ||
+      p.plateau_window < 1 || !(p.beta >= 0 && p.beta <= 1) ||
+      (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) || p.full_unitary) {
+    set_error_detail("qudits: bad sample counts or params");
+    return QFS_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(p.hip_stream);
+  const int S = p.multistarts;
+  if (gates_in)
+    QFS_TRY(check_gates_unitary_n(gates_in, (size_t)S * L, D, "gates_in", st));
+  DevBuf gates;
+  QFS_TRY(gates.alloc(sizeof(c128) * (size_t)S * L * D * D));
+  if (gates_in) {
+    QFS_HIP(hipMemcpyAsync(gates.ptr, gates_in, sizeof(c128) * (size_t)S * L * D * D, hipMemcpyDeviceToDevice, st));
+  } else {
+    const int64_t tot = (int64_t)S * L;
+    if (d == 2)
+      hipLaunchKernelGGL(k_qd_haar<2>, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, st, p.seed, 0, S, L,
+                         gates.as<c128>());
+    else
+      hipLaunchKernelGGL(k_qd_haar<3>, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, st, p.seed, 0, S, L,
+                         gates.as<c128>());
+    QFS_HIP(hipGetLastError());
+  }
+  QdState cs;
+  cs.status.assign(S, ST_RUN);
+  cs.reason.assign(S, QFS_MAX_ITER);
+  cs.iter.assign(S, 0);
+  cs.z.assign(S, 0);
+  cs.total.assign(S, 0);
+  cs.c_prev.assign(S, 0.0);
+  cs.ct.assign(S, INFINITY);
+  cs.cv.assign(S, INFINITY);
+  cs.m_cap = (p.m_max > 0 && p.m_max < N) ? p.m_max : (int)N;
+  cs.m_cap = std::min(cs.m_cap, n_train);
+  cs.M = std::max(1, std::min(p.m_init, cs.m_cap));
+  if (p.fixed_m) cs.m_cap = cs.M;
+  cs.m_total = cs.M;
+  bool refine = false;
+  int refined = 0;
+  if (p.precision == QFS_PREC_MIXED) {
+    QFS_TRY(qd_run<float>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), S, cs, t0, refine));
+    if (refine) {
+      refined = 1;
+      QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), S, cs, t0, refine));
+    }
+  } else {
+    QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), S, cs, t0, refine));
+  }
+  if (cs.chosen < 0) {
+    double best = INFINITY;
+    for (int s = 0; s < S; ++s)
+      if (cs.ct[s] < best || cs.chosen < 0) {
+        best = cs.ct[s];
+        cs.chosen = s;
+      }
+  }
+  const int c = cs.chosen;
+  QFS_HIP(hipMemcpyAsync(gates_out, gates.as<c128>() + (size_t)c * L * D * D, sizeof(c128) * (size_t)L * D * D,
+                         hipMemcpyDeviceToDevice, st));
+  QFS_HIP(hipStreamSynchronize(st));
+  std::memset(res, 0, sizeof(*res));
+  res->reason = cs.reason[c];
+  res->m_final = cs.M;
+  res->sweeps = (int32_t)cs.total[c];
+  res->restarts = cs.restarts;
+  res->best_start = c;
+  res->m_total = cs.m_total;
+  res->start_groups = 1;
+  res->refined = refined;
+  res->c_train = cs.ct[c];
+  res->c_val = cs.cv[c];
+  res->start_sweeps = cs.start_sweeps;
+  res->sweep_seconds = cs.sweep_seconds;
+  res->amp_updates = cs.amp_updates;
+  res->seconds = qd_now() - t0;
+  return QFS_OK;
+}
+
+int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c128 *psi,
+                    const qfs_c128 *phi, int32_t starts, qfs_c128 *gates, int32_t precision, double beta,
+                    double *c_train, void *hip_stream) {
+  qfs_template t{n, L, pairs, nullptr, nullptr};
+  QFS_TRY(qd_validate(d, &t));
+  const int64_t N = qd_pow(d, n);
+  if (M < 1 || M > N || starts < 1 || !psi || !phi || !gates || !c_train ||
+      (precision != QFS_PREC_FP64 && precision != QFS_PREC_MIXED) || !(beta >= 0 && beta <= 1)) {
+    set_error_detail("qudits: bad sweep arguments");
+    return QFS_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  std::vector<int> all(starts);
+  for (int s = 0; s < starts; ++s) all[s] = s;
+  auto run = [&](auto tag) -> int {
+    using R = decltype(tag);
+    QdSweeper<R> w;
+    w.d = d;
+    w.n = n;
+    w.L = L;
+    w.S = starts;
+    w.N = N;
+    w.pairs = pairs;
+    w.st = st;
+    w.g64 = reinterpret_cast<c128 *>(gates);
+    w.beta = beta;
+    QFS_TRY(w.alloc(M, 0));
+    QFS_TRY(qd_load_sets<R>(w, psi, phi, M, 0));
+    QFS_TRY(w.set_slots(all));
+    QFS_TRY(w.forward(false));
+    QFS_TRY(w.backward());
+    QFS_HIP(hipMemcpyAsync(c_train, w.costs.ptr, sizeof(double) * starts, hipMemcpyDeviceToHost, st));
+    QFS_HIP(hipStreamSynchronize(st));
+    return QFS_OK;
+  };
+  return precision == QFS_PREC_MIXED ? run(float{}) : run(double{});
+}
+
+}  // extern "C"

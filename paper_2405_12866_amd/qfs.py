@@ -73,7 +73,7 @@ EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_
            "qfs_mlp_num_params", "qfs_mlp_init", "qfs_mlp_get", "qfs_mlp_set", "qfs_mlp_save",
            "qfs_mlp_load", "qfs_mlp_forward", "qfs_mlp_grad", "qfs_mlp_train", "qfs_predict_m",
            "qfs_predict_batch", "qfs_instantiate_learned", "qfs_instantiate_batch_learned",
-           "qfs_instantiate_batch_ex"]
+           "qfs_instantiate_batch_ex", "qfs_qudit_instantiate", "qfs_qudit_sweep"]
 
 
 def load():
@@ -126,6 +126,9 @@ def load():
         lib.qfs_mlp_train.argtypes = [I32, P, P, I32, I32, C.c_float, U64, P, P]
         lib.qfs_predict_m.argtypes = [C.POINTER(Template), C.POINTER(Params), P, P]
         lib.qfs_predict_batch.argtypes = [I32, C.POINTER(Template), C.POINTER(Params), P, P]
+        lib.qfs_qudit_instantiate.argtypes = [I32, C.POINTER(Template), P, P, I32, I32,
+                                              C.POINTER(Params), P, P, C.POINTER(Result)]
+        lib.qfs_qudit_sweep.argtypes = [I32, I32, I32, P, I32, P, P, I32, P, I32, D, P, P]
         for name in EXPORTS:
             if name not in ("qfs_strerror", "qfs_last_error_detail", "qfs_version",
                             "qfs_default_params"):
@@ -519,6 +522,34 @@ def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kind
                             _dev_c128(phi, "phi"), starts, _dev_c128(gates, "gates"), precision,
                             beta, c.ctypes.data_as(C.c_void_p), _stream()), "qfs_sweep")
     return c
+
+
+def qfs_qudit_sweep(d, n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0):
+    """One qudit sweep of ``gates`` [starts, L, d^2, d^2] (in place); returns c_train."""
+    import numpy as np
+    arr, pp = _pairs(pairs)
+    starts = gates.shape[0]
+    c = np.zeros(starts)
+    _check(load().qfs_qudit_sweep(d, n, arr.shape[0], pp, psi.shape[0], _dev_c128(psi, "psi"),
+                                  _dev_c128(phi, "phi"), starts, _dev_c128(gates, "gates"), precision,
+                                  beta, c.ctypes.data_as(C.c_void_p), _stream()), "qfs_qudit_sweep")
+    return c
+
+
+def qfs_qudit_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None):
+    """Qudit instantiation on a fixed sample set ``psi``/``phi`` [n_samples, d^n] whose last
+    ``n_val`` rows validate. Returns (gates [L, d^2, d^2] device tensor, result dict)."""
+    import torch
+    keep = []
+    tmpl = _template(n, pairs, keep)
+    out = torch.empty((tmpl.n_gates, d * d, d * d), dtype=torch.complex128, device=psi.device)
+    par = _params(params)
+    res = Result()
+    gi = _dev_c128(gates_in, "gates_in") if gates_in is not None else None
+    _check(load().qfs_qudit_instantiate(d, C.byref(tmpl), _dev_c128(psi, "psi"), _dev_c128(phi, "phi"),
+                                        psi.shape[0], n_val, C.byref(par), gi,
+                                        C.c_void_p(out.data_ptr()), C.byref(res)), "qfs_qudit_instantiate")
+    return out, _info(res)
 
 
 def qfs_state_distance(n, x, y):
