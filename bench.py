@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--qf", type=str, default="6,8,10,12",
                     help="qubit counts of U3 + CNOT problems run with full-unitary QFactor and "
                          "with QFactor-Sample (time to solution); empty skips it")
+    ap.add_argument("--qudits", type=int, default=1,
+                    help="1: time qutrit sweeps and QFactor vs QFactor-Sample on qutrits; 0 skips it")
     ap.add_argument("--learned-large", type=int, default=0,
                     help="10-14 qubit random-pair problems (30-120 gates) for the learned-M "
                          "comparison through qfs_instantiate (0 skips it)")
@@ -229,6 +231,70 @@ def qf_vs_qfs(dev, sizes):
     for key, name in (("speedup", "qfs"), ("speedup_m32", "qfs_m32")):
         ok = [r[key] for r in rows if r["qf"]["reason"] == r[name]["reason"] == "SUCCESS"]
         out[f"mean_{key}_both_succeeded"] = round(float(np.mean(ok)), 2) if ok else None
+    return out
+
+
+def qudits_leg(dev, steps):
+    """Qutrits (d = 3, Sec. 5). (a) Sweeps: 7 qutrits (2187 amplitudes), brickwork of 4
+    sublayers (12 two-qutrit gates, 9 x 9), Haar target gates, M = 64 fixed samples, 16
+    lock-step starts, MIXED: start-sweeps/s and algorithmic GB/s (each call also converts
+    the sets to the internal layout). (b) Time to solution of full-unitary QFactor (the
+    complete basis as the sample set, M = 3^n, no validation set) against the sample method
+    (M from 9, doubling up to 36 against 9 validation samples) on 6 and 7 qutrits
+    (brickwork, 4 sublayers), 16 starts, App. A rules, MIXED, same seed."""
+    import numpy as np
+    import torch
+
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import qfs as Q
+
+    out = {}
+    g = I.rng(I.derive_seed(0x5A17 + 11))
+    n, M, S = 7, 64, 16
+    pairs = I.qudit_brickwork(n, 4)
+    L = len(pairs)
+    tg = np.stack([I.haar_unitary(9, g) for _ in range(L)])
+    N = 3 ** n
+    psi = I.orthonormal_states(N, M, g)
+    phi = I.qudit_circuit_apply(3, n, psi, pairs, tg)
+    dpsi, dphi = torch.as_tensor(psi).to(dev), torch.as_tensor(phi).to(dev)
+    base = Q.qfs_default_params(multistarts=S, m_init=M, fixed_m=1, seed=0x5A17 + 11, diff_tol_r=0.0,
+                                plateau_window=1 << 30)
+    Q.qfs_qudit_instantiate(3, n, pairs, dpsi, dphi, params=dict(base, max_iter=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = Q.qfs_qudit_instantiate(3, n, pairs, dpsi, dphi, params=dict(base, max_iter=steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S_amp = M * N
+    alg = 16.0 * S_amp * L + 8.0 * S_amp
+    out["sweeps_7qutrits"] = {"workload": f"7 qutrits, {L} two-qutrit gates, M={M} fixed, {S} lock-step starts, "
+                                          f"MIXED, one qfs_qudit_instantiate call of {steps} sweeps",
+                              "start_sweeps_per_s": round(r["start_sweeps"] / dt, 1),
+                              "ms_per_step": round(1e3 * dt / steps, 3),
+                              "sweep_algorithmic_GBps": round(alg * r["start_sweeps"] / dt / 1e9, 1)}
+    rows = []
+    for n in (6, 7):
+        N = 3 ** n
+        pairs = I.qudit_brickwork(n, 4)
+        tg = np.stack([I.haar_unitary(9, g) for _ in pairs])
+        basis = np.eye(N, dtype=np.complex128)
+        samples = I.orthonormal_states(N, 45, g)
+        row = {"n": n, "gates": len(pairs)}
+        for name, ps, m0, nv in (("qf", basis, N, 0), ("qfs", samples, 9, 9)):
+            ph = I.qudit_circuit_apply(3, n, ps, pairs, tg)
+            p = Q.qfs_default_params(seed=31 + n, m_init=m0, time_budget_s=120.0)
+            dps, dph = torch.as_tensor(ps).to(dev), torch.as_tensor(ph).to(dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, r = Q.qfs_qudit_instantiate(3, n, pairs, dps, dph, n_val=nv, params=p)
+            torch.cuda.synchronize()
+            row[name] = {"seconds": round(time.perf_counter() - t1, 4), "reason": r["reason_name"],
+                         "m_final": r["m_final"], "sweeps": r["sweeps"], "c_train": r["c_train"],
+                         "c_val": r["c_val"]}
+        row["speedup"] = round(row["qf"]["seconds"] / row["qfs"]["seconds"], 2)
+        rows.append(row)
+    out["qf_vs_qfs_qutrits"] = rows
     return out
 
 
@@ -487,6 +553,8 @@ def main():
     }
     if args.u3cx:
         extra["u3_cnot"] = u3_cnot(dev, M, S, args.steps, args.warmup, args.timing)
+    if args.qudits:
+        extra["qudits"] = qudits_leg(dev, args.steps)
     if args.qf:
         extra["qf_vs_qfs"] = qf_vs_qfs(dev, [int(x) for x in args.qf.split(",") if x])
     if args.batched > 0:

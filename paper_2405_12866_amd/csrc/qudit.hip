@@ -22,6 +22,10 @@ namespace {
 
 constexpr int kQdBlock = 256;
 constexpr int kQdMaxP = 64;  // environment partial blocks per (start, row group)
+// Jacobi stops when every column pair has |g_p^dagger g_q| <= tol |g_p| |g_q|. The Gram
+// entry of D-long columns carries a rounding error of about D eps |g_p| |g_q| (1e-15 for
+// D = 9), so the threshold sits above it; the polar factor is then accurate to ~1e-14.
+constexpr double kQdJacobiTol = 1e-14;
 
 // Position of a gate group: items are (group r, sample j), j fastest.
 struct QdGeom {
@@ -166,21 +170,15 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_s
   }
 }
 
-// Per start (one block): fixed-order sum of the partials, then u_k <- W V^dagger for
-// (1 - beta) Gamma + beta u_k = W S V^dagger by one-sided Jacobi on one wave: lane r holds
-// row r of the working matrix and of V; for each column pair the three Gram entries are
-// wave sums over the rows, so every lane derives the same rotation.
+// Fixed-order sum of the environment partials of every active start into gam [S][D][D]
+// (mixed with the gate when beta != 0).
 template <int d>
-__global__ __launch_bounds__(kQdBlock) void k_qd_finalize(const c128 *partials, int32_t P,
-                                                          const int32_t *slots, double beta,
-                                                          c128 *gates, int32_t gstride, int32_t k) {
+__global__ __launch_bounds__(kQdBlock) void k_qd_envsum(const c128 *partials, int32_t P, const int32_t *slots,
+                                                        double beta, const c128 *gates, int32_t gstride,
+                                                        int32_t k, c128 *gam) {
   constexpr int D = d * d;
-  __shared__ c128 G[D * D];
-  __shared__ c128 Vs[D * D];
-  __shared__ c128 Gc[D * D];
-  __shared__ double sig[D];
   const int s = slots[blockIdx.x];
-  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  const c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
   for (int e = threadIdx.x; e < D * D; e += kQdBlock) {
     const c128 *src = partials + (int64_t)s * P * D * D + e;
     c128 a0 = cmake(0.0, 0.0), a1 = cmake(0.0, 0.0);
@@ -191,143 +189,233 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_finalize(const c128 *partials, 
     }
     if (blk < P) a0 = a0 + src[(int64_t)blk * D * D];
     const c128 gm = a0 + a1;
-    G[e] = beta != 0.0 ? cmake((1.0 - beta) * gm.re + beta * u[e].re, (1.0 - beta) * gm.im + beta * u[e].im)
-                       : gm;
+    gam[(int64_t)s * D * D + e] =
+        beta != 0.0 ? cmake((1.0 - beta) * gm.re + beta * u[e].re, (1.0 - beta) * gm.im + beta * u[e].im) : gm;
+  }
+}
+
+// Per start (one wave): u_k <- W V^dagger for the mixed environment gam =
+// (1 - beta) Gamma + beta u_k = W S V^dagger by one-sided Jacobi on one wave. The working
+// matrix G and V live in LDS, lane r owning row r, so a rotation touches only the lane's own
+// row and the only cross-lane steps are the wave sums of the three Gram entries of a
+// column pair. Pairs are rotated in round-robin rounds (circle method on D rounded up to
+// even, a ghost column when D is odd): the pairs of a round are disjoint, so their sums are
+// formed together. Warm start: Jacobi begins from G V_prev with V_prev, the right singular
+// vectors this gate had after its previous update (vst, made unitary to rounding by one
+// Newton-Schulz step V (3I - V^dagger V) / 2), so a sweep of small changes converges in a
+// few Jacobi sweeps; the new V is stored back.
+template <int d>
+__global__ __launch_bounds__(64) void k_qd_finalize(const c128 *gam, const int32_t *slots, c128 *gates,
+                                                    c128 *vstore, int32_t gstride, int32_t k) {
+  constexpr int D = d * d;
+  constexpr int PL = (D + 1) / 2 * 2;  // players of the round-robin schedule
+  constexpr int NP = PL / 2;
+  __shared__ c128 Gm[D * D];
+  __shared__ c128 Vs[D * D];
+  __shared__ c128 Tm[D * D];
+  __shared__ double sig[D];
+  __shared__ double part[4 * NP][D];  // per-row Gram contributions of a round's pairs
+  __shared__ double gram[4 * NP];
+  __shared__ double rot[NP][4];       // per pair: cos, sin, Re and Im of conj(gamma)/|gamma|
+  __shared__ int any_rot;
+  const int s = slots[blockIdx.x];
+  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  c128 *vst = vstore + (int64_t)s * gstride + (int64_t)k * D * D;
+  for (int e = threadIdx.x; e < D * D; e += 64) {
+    Tm[e] = gam[(int64_t)s * D * D + e];
+    Vs[e] = vst[e];
   }
   __syncthreads();
-  if (threadIdx.x >= 64) return;
   const int r = threadIdx.x;
   const bool act = r < D;
-  c128 g[D], v[D];
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    g[c] = act ? G[r * D + c] : cmake(0.0, 0.0);
-    v[c] = cmake(act && r == c ? 1.0 : 0.0, 0.0);
-  }
+  auto wsync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  };
   auto wsum = [](double x) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
     return x;
   };
+  // Newton-Schulz on V_prev (row r of V^dagger V into Gm), then V <- V (3I - V^dagger V)/2
+  if (act)
+    for (int j = 0; j < D; ++j) {
+      c128 acc = cmake(0.0, 0.0);
+      for (int kk = 0; kk < D; ++kk) cfma(acc, cconj(Vs[kk * D + r]), Vs[kk * D + j]);
+      Gm[r * D + j] = acc;
+    }
+  wsync();
+  c128 row[D];
+  if (act)
+    for (int j = 0; j < D; ++j) {
+      c128 acc = cmake(0.0, 0.0);
+      for (int kk = 0; kk < D; ++kk) {
+        const c128 t = Gm[kk * D + j];
+        cfma(acc, Vs[r * D + kk], cmake((kk == j ? 3.0 : 0.0) - t.re, -t.im));
+      }
+      row[j] = cscale(acc, 0.5);
+    }
+  wsync();
+  if (act)
+    for (int j = 0; j < D; ++j) Vs[r * D + j] = row[j];
+  wsync();
+  // G <- Gamma V (Gamma in Tm)
+  if (act)
+    for (int j = 0; j < D; ++j) {
+      c128 acc = cmake(0.0, 0.0);
+      for (int kk = 0; kk < D; ++kk) cfma(acc, Tm[r * D + kk], Vs[kk * D + j]);
+      Gm[r * D + j] = acc;
+    }
+  c128 *gr_ = Gm + (act ? r : 0) * D;
+  c128 *vr_ = Vs + (act ? r : 0) * D;
   for (int sweep = 0; sweep < 60; ++sweep) {
     int rotated = 0;
+    for (int rd = 0; rd < PL - 1; ++rd) {
+      int pp[NP], qq[NP];
+      // Gram entries of the round's pairs: each row's contributions to LDS, lane e
+      // (< 4 NP) sums entry e over the rows in row order, lane i (< NP) turns pair i's
+      // entries into its rotation, and every row applies the rotations of the round
 #pragma unroll
-    for (int p = 0; p < D - 1; ++p)
-#pragma unroll
-      for (int q = p + 1; q < D; ++q) {
-        const double al = wsum(cabs2(g[p])), be = wsum(cabs2(g[q]));
-        const double gr = wsum(g[p].re * g[q].re + g[p].im * g[q].im);
-        const double gi = wsum(g[p].re * g[q].im - g[p].im * g[q].re);
-        const double ag = sqrt(gr * gr + gi * gi);
-        if (ag > 0.0 && ag > 1e-15 * sqrt(al * be)) {
-          rotated = 1;
-          const c128 ec = cmake(gr / ag, -gi / ag);  // conj(gamma) / |gamma|
-          const double tau = (be - al) / (2.0 * ag);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          const c128 egq = ec * g[q], evq = ec * v[q];
-          const c128 gp = g[p], vp = v[p];
-          g[p] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
-          g[q] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
-          v[p] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
-          v[q] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+      for (int i = 0; i < NP; ++i) {
+        pp[i] = i == 0 ? 0 : (rd + i) % (PL - 1) + 1;
+        qq[i] = i == 0 ? rd % (PL - 1) + 1 : (rd - i + PL - 1) % (PL - 1) + 1;
+        if (act && pp[i] < D && qq[i] < D) {
+          const c128 gp = gr_[pp[i]], gq = gr_[qq[i]];
+          part[4 * i][r] = cabs2(gp);
+          part[4 * i + 1][r] = cabs2(gq);
+          part[4 * i + 2][r] = gp.re * gq.re + gp.im * gq.im;
+          part[4 * i + 3][r] = gp.re * gq.im - gp.im * gq.re;
         }
       }
+      if (r == 0) any_rot = 0;
+      wsync();
+      if (r < 4 * NP) {
+        const int i = r >> 2;
+        const int pi = i == 0 ? 0 : (rd + i) % (PL - 1) + 1;
+        const int qi = i == 0 ? rd % (PL - 1) + 1 : (rd - i + PL - 1) % (PL - 1) + 1;
+        double t = 0.0;
+        if (pi < D && qi < D)
+          for (int rr = 0; rr < D; ++rr) t += part[r][rr];
+        gram[r] = t;
+      }
+      wsync();
+      if (r < NP) {
+        const double al = gram[4 * r], be = gram[4 * r + 1], gre = gram[4 * r + 2], gim = gram[4 * r + 3];
+        const double ag = sqrt(gre * gre + gim * gim);
+        const int pr = r == 0 ? 0 : (rd + r) % (PL - 1) + 1;
+        const int qr = r == 0 ? rd % (PL - 1) + 1 : (rd - r + PL - 1) % (PL - 1) + 1;
+        const bool pair_ok = pr < D && qr < D;
+        if (pair_ok && ag > 0.0 && ag > kQdJacobiTol * sqrt(al * be)) {
+          const double tau = (be - al) / (2.0 * ag);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          rot[r][0] = cs;
+          rot[r][1] = cs * t;
+          rot[r][2] = gre / ag;
+          rot[r][3] = -gim / ag;
+          any_rot = 1;
+        } else {
+          rot[r][0] = 1.0;
+          rot[r][1] = 0.0;
+          rot[r][2] = 1.0;
+          rot[r][3] = 0.0;
+        }
+      }
+      wsync();
+      if (any_rot) rotated = 1;
+      if (act) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          if (pp[i] >= D || qq[i] >= D) continue;
+          const double cs = rot[i][0], sn = rot[i][1];
+          if (sn == 0.0 && cs == 1.0) continue;
+          const c128 ec = cmake(rot[i][2], rot[i][3]);
+          const c128 gp = gr_[pp[i]], egq = ec * gr_[qq[i]];
+          const c128 vp = vr_[pp[i]], evq = ec * vr_[qq[i]];
+          gr_[pp[i]] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+          gr_[qq[i]] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+          vr_[pp[i]] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+          vr_[qq[i]] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+        }
+      }
+      wsync();
+    }
     if (!rotated) break;
   }
-  // singular values; W columns g / sigma; V rows to LDS
+  // singular values; W columns g / sigma; V stored back
   double smax = 0.0, smin = INFINITY;
-#pragma unroll
   for (int c = 0; c < D; ++c) {
-    const double sc = sqrt(wsum(cabs2(g[c])));
+    const double sc = sqrt(wsum(act ? cabs2(gr_[c]) : 0.0));
     smax = fmax(smax, sc);
     smin = fmin(smin, sc);
     if (r == 0) sig[c] = sc;
   }
-  if (act) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      Vs[r * D + c] = v[c];
-      Gc[r * D + c] = g[c];
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  if (act)
+    for (int c = 0; c < D; ++c) vst[r * D + c] = vr_[c];
+  wsync();
   if (smin > 1e-200 && smin > 1e-13 * smax) {
-    if (act) {
-#pragma unroll
+    if (act)
       for (int c = 0; c < D; ++c) {
         c128 acc = cmake(0.0, 0.0);
-#pragma unroll
-        for (int kk = 0; kk < D; ++kk) cfma_conj(acc, cscale(g[kk], 1.0 / sig[kk]), Vs[c * D + kk]);
+        for (int kk = 0; kk < D; ++kk) cfma_conj(acc, cscale(gr_[kk], 1.0 / sig[kk]), Vs[c * D + kk]);
         u[r * D + c] = acc;
       }
-    }
     return;
   }
   // a (near) singular environment: left vectors in decreasing-sigma order, orthonormalised
-  // and completed with unit vectors (any such completion attains the maximum)
-  if (r == 0) {
-    int ord[D];
-    for (int c = 0; c < D; ++c) ord[c] = c;
-    for (int a = 0; a < D; ++a)
-      for (int b2 = a + 1; b2 < D; ++b2)
-        if (sig[ord[b2]] > sig[ord[a]]) {
-          const int t = ord[a];
-          ord[a] = ord[b2];
-          ord[b2] = t;
-        }
-    c128 w[D][D];
-    for (int kk = 0; kk < D; ++kk) {
-      const int cc = ord[kk];
-      c128 x[D];
-      bool ok = sig[cc] > 0.0 && sig[cc] > 1e-13 * smax;
-      if (ok) {
-        for (int rr = 0; rr < D; ++rr) x[rr] = cscale(Gc[rr * D + cc], 1.0 / sig[cc]);
-        for (int rep = 0; rep < 2; ++rep)
-          for (int o = 0; o < kk; ++o) {
-            c128 dd = cmake(0.0, 0.0);
-            for (int rr = 0; rr < D; ++rr) cfma(dd, cconj(w[o][rr]), x[rr]);
-            for (int rr = 0; rr < D; ++rr) x[rr] = x[rr] - dd * w[o][rr];
-          }
-        double nn = 0.0;
-        for (int rr = 0; rr < D; ++rr) nn += cabs2(x[rr]);
-        nn = sqrt(nn);
-        if (nn > 0.5)
-          for (int rr = 0; rr < D; ++rr) x[rr] = cscale(x[rr], 1.0 / nn);
-        else
-          ok = false;
+  // in place in LDS (columns of Gm) and completed with unit vectors (any such completion
+  // attains the maximum); lane 0 alone
+  if (r != 0) return;
+  int ord[D];
+  for (int c = 0; c < D; ++c) ord[c] = c;
+  for (int a = 0; a < D; ++a)
+    for (int b2 = a + 1; b2 < D; ++b2)
+      if (sig[ord[b2]] > sig[ord[a]]) {
+        const int t = ord[a];
+        ord[a] = ord[b2];
+        ord[b2] = t;
       }
-      if (!ok) {
-        double best = -1.0;
-        c128 bx[D];
-        for (int e = 0; e < D; ++e) {
-          c128 yv[D];
-          for (int rr = 0; rr < D; ++rr) yv[rr] = cmake(rr == e ? 1.0 : 0.0, 0.0);
-          for (int rep = 0; rep < 2; ++rep)
-            for (int o = 0; o < kk; ++o) {
-              c128 dd = cmake(0.0, 0.0);
-              for (int rr = 0; rr < D; ++rr) cfma(dd, cconj(w[o][rr]), yv[rr]);
-              for (int rr = 0; rr < D; ++rr) yv[rr] = yv[rr] - dd * w[o][rr];
-            }
-          double nn = 0.0;
-          for (int rr = 0; rr < D; ++rr) nn += cabs2(yv[rr]);
-          if (nn > best) {
-            best = nn;
-            for (int rr = 0; rr < D; ++rr) bx[rr] = yv[rr];
-          }
-        }
-        const double inv = 1.0 / sqrt(best);
-        for (int rr = 0; rr < D; ++rr) x[rr] = cscale(bx[rr], inv);
+  // W column kk goes to Tm[. * D + kk]
+  for (int kk = 0; kk < D; ++kk) {
+    const int cc = ord[kk];
+    bool ok = sig[cc] > 0.0 && sig[cc] > 1e-13 * smax;
+    for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = ok ? cscale(Gm[rr * D + cc], 1.0 / sig[cc]) : cmake(0.0, 0.0);
+    for (int attempt = 0; attempt <= D; ++attempt) {
+      if (attempt > 0) {  // complete with unit vector e = attempt - 1
+        if (ok) break;
+        for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = cmake(rr == attempt - 1 ? 1.0 : 0.0, 0.0);
       }
-      for (int rr = 0; rr < D; ++rr) w[kk][rr] = x[rr];
+      for (int rep = 0; rep < 2; ++rep)
+        for (int o = 0; o < kk; ++o) {
+          c128 dd = cmake(0.0, 0.0);
+          for (int rr = 0; rr < D; ++rr) cfma(dd, cconj(Tm[rr * D + o]), Tm[rr * D + kk]);
+          for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = Tm[rr * D + kk] - dd * Tm[rr * D + o];
+        }
+      double nn = 0.0;
+      for (int rr = 0; rr < D; ++rr) nn += cabs2(Tm[rr * D + kk]);
+      nn = sqrt(nn);
+      if (nn > 0.5) {
+        for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = cscale(Tm[rr * D + kk], 1.0 / nn);
+        ok = true;
+        break;
+      }
+      ok = false;
     }
-    for (int q = 0; q < D; ++q)
-      for (int p = 0; p < D; ++p) {
-        c128 acc = cmake(0.0, 0.0);
-        for (int kk = 0; kk < D; ++kk) cfma_conj(acc, w[kk][q], Vs[p * D + ord[kk]]);
-        u[q * D + p] = acc;
-      }
+  }
+  for (int q = 0; q < D; ++q)
+    for (int p = 0; p < D; ++p) {
+      c128 acc = cmake(0.0, 0.0);
+      for (int kk = 0; kk < D; ++kk) cfma_conj(acc, Tm[q * D + kk], Vs[p * D + ord[kk]]);
+      u[q * D + p] = acc;
+    }
+}
+
+// count D x D identity matrices (the initial warm-start V).
+__global__ void k_qd_identity(int64_t count, int D, c128 *v) {
+  const int64_t tot = count * D * D;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = e % ((int64_t)D * D);
+    v[e] = cmake((w / D == w % D) ? 1.0 : 0.0, 0.0);
   }
 }
 
@@ -417,8 +505,9 @@ struct QdSweeper {
   hipStream_t st = nullptr;
   int M = 0, Mv = 0;
   DevBuf psi, phi, psiv, phiv;  // working sets [N][M] in R (shared by the starts)
-  DevBuf blist, astate, vstate, partials, dpart, costs, slots;
+  DevBuf blist, astate, vstate, partials, dpart, costs, slots, gam;
   c128 *g64 = nullptr;  // [S][L][D][D]
+  c128 *vst = nullptr;  // [S][L][D][D] Jacobi warm start
   double beta = 0.0;
   int nslots = 0;
 
@@ -444,8 +533,11 @@ struct QdSweeper {
     hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * P, nslots), dim3(kQdBlock), 0, st, a, as, b, bs, g, P,
                        partials.as<c128>(), slots.as<int32_t>());
     QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(nslots), dim3(kQdBlock), 0, st, partials.as<c128>(), P,
-                       slots.as<int32_t>(), beta, g64, L * dd * dd * dd * dd, k);
+    hipLaunchKernelGGL((k_qd_envsum<dd>), dim3(nslots), dim3(kQdBlock), 0, st, partials.as<c128>(), P,
+                       slots.as<int32_t>(), beta, g64, L * dd * dd * dd * dd, k, gam.as<c128>());
+    QFS_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(nslots), dim3(64), 0, st, gam.as<c128>(), slots.as<int32_t>(), g64,
+                       vst, L * dd * dd * dd * dd, k);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   }
@@ -474,6 +566,7 @@ struct QdSweeper {
       QFS_TRY(vstate.alloc(cb * N * Mv * S));
     }
     QFS_TRY(partials.alloc(sizeof(c128) * (size_t)S * kQdMaxP * 256));
+    QFS_TRY(gam.alloc(sizeof(c128) * (size_t)S * 256));
     QFS_TRY(dpart.alloc(sizeof(double) * (size_t)S * kQdMaxP * 4));
     if (!costs.ptr) QFS_TRY(costs.alloc(sizeof(double) * 3 * S));
     if (!slots.ptr) QFS_TRY(slots.alloc(sizeof(int32_t) * S));
@@ -608,7 +701,7 @@ struct QdState {
 
 template <typename R>
 int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *phi, int n_train, int n_val,
-           const qfs_params &p, c128 *g64, int S, QdState &cs, double t0, bool &refine) {
+           const qfs_params &p, c128 *g64, c128 *vst, int S, QdState &cs, double t0, bool &refine) {
   QdSweeper<R> w;
   w.d = d;
   w.n = t->n_qubits;
@@ -618,6 +711,7 @@ int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *ph
   w.pairs = t->pairs;
   w.st = static_cast<hipStream_t>(p.hip_stream);
   w.g64 = g64;
+  w.vst = vst;
   w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
   QFS_TRY(w.alloc(cs.M, n_val));
   QFS_TRY(qd_load_sets<R>(w, psi, phi, n_train, n_val));
@@ -766,6 +860,11 @@ int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *p
                          gates.as<c128>());
     QFS_HIP(hipGetLastError());
   }
+  DevBuf vstore;
+  QFS_TRY(vstore.alloc(sizeof(c128) * (size_t)S * L * D * D));
+  hipLaunchKernelGGL(k_qd_identity, dim3(qd_grid((int64_t)S * L * D * D)), dim3(kQdBlock), 0, st, (int64_t)S * L, D,
+                     vstore.as<c128>());
+  QFS_HIP(hipGetLastError());
   QdState cs;
   cs.status.assign(S, ST_RUN);
   cs.reason.assign(S, QFS_MAX_ITER);
@@ -783,13 +882,13 @@ int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *p
   bool refine = false;
   int refined = 0;
   if (p.precision == QFS_PREC_MIXED) {
-    QFS_TRY(qd_run<float>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), S, cs, t0, refine));
+    QFS_TRY(qd_run<float>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
     if (refine) {
       refined = 1;
-      QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), S, cs, t0, refine));
+      QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
     }
   } else {
-    QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), S, cs, t0, refine));
+    QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
   }
   if (cs.chosen < 0) {
     double best = INFINITY;
@@ -835,6 +934,12 @@ int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   std::vector<int> all(starts);
   for (int s = 0; s < starts; ++s) all[s] = s;
+  const int D = d * d;
+  DevBuf vst;
+  QFS_TRY(vst.alloc(sizeof(c128) * (size_t)starts * L * D * D));
+  hipLaunchKernelGGL(k_qd_identity, dim3(qd_grid((int64_t)starts * L * D * D)), dim3(kQdBlock), 0, st,
+                     (int64_t)starts * L, D, vst.as<c128>());
+  QFS_HIP(hipGetLastError());
   auto run = [&](auto tag) -> int {
     using R = decltype(tag);
     QdSweeper<R> w;
@@ -846,6 +951,7 @@ int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32
     w.pairs = pairs;
     w.st = st;
     w.g64 = reinterpret_cast<c128 *>(gates);
+    w.vst = vst.as<c128>();
     w.beta = beta;
     QFS_TRY(w.alloc(M, 0));
     QFS_TRY(qd_load_sets<R>(w, psi, phi, M, 0));

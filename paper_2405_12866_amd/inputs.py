@@ -99,6 +99,32 @@ def orthonormal_samples(n: int, M: int, g: np.random.Generator):
     return np.ascontiguousarray(q.T)
 
 
+def orthonormal_states(N: int, M: int, g: np.random.Generator):
+    """M orthonormal states of N amplitudes, [M][N] (numpy QR of a complex Ginibre
+    matrix), for qudit sample sets."""
+    z = (g.standard_normal((N, M)) + 1j * g.standard_normal((N, M))) / np.sqrt(2.0)
+    q, _ = np.linalg.qr(z)
+    return np.ascontiguousarray(q.T)
+
+
+def qudit_brickwork(n: int, sublayers: int):
+    """Brickwork pairs of n qudits (as brickwork_template)."""
+    return brickwork_template(n, sublayers)
+
+
+def qudit_circuit_apply(d: int, n: int, states, pairs, gates):
+    """Apply d^2 x d^2 gates in order to [M][d^n] states through base-d tensor axes (qudit
+    0 first). Input construction only (target sample sets)."""
+    out = np.array(states, dtype=np.complex128, copy=True)
+    M = out.shape[0]
+    for (a, b), u in zip(np.asarray(pairs).reshape(-1, 2), gates):
+        t = np.moveaxis(out.reshape((M,) + (d,) * n), (1 + int(a), 1 + int(b)), (1, 2))
+        shp = t.shape
+        t = np.einsum("qp,mpr->mqr", u, t.reshape(M, d * d, -1)).reshape(shp)
+        out = np.moveaxis(t, (1, 2), (1 + int(a), 1 + int(b))).reshape(M, -1)
+    return out
+
+
 def circuit_unitary_columns(n: int, pairs, gates, states):
     """Apply a gate list to [M][N] states by explicit 2^n x 2^n Kronecker embedding.
     Input construction only (used to build fixed target samples); O(4^n) per gate."""
