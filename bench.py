@@ -240,7 +240,7 @@ def qudits_leg(dev, steps):
     lock-step starts, MIXED: start-sweeps/s and algorithmic GB/s (each call also converts
     the sets to the internal layout). (b) Time to solution of full-unitary QFactor (the
     complete basis as the sample set, M = 3^n, no validation set) against the sample method
-    (M from 9, doubling up to 36 against 9 validation samples) on 6 and 7 qutrits
+    (M from 9, doubling up to 144 against 9 validation samples) on 6 and 7 qutrits
     (brickwork, 4 sublayers), 16 starts, App. A rules, MIXED, same seed."""
     import numpy as np
     import torch
@@ -279,7 +279,7 @@ def qudits_leg(dev, steps):
         pairs = I.qudit_brickwork(n, 4)
         tg = np.stack([I.haar_unitary(9, g) for _ in pairs])
         basis = np.eye(N, dtype=np.complex128)
-        samples = I.orthonormal_states(N, 45, g)
+        samples = I.orthonormal_states(N, 9 + 144, g)
         row = {"n": n, "gates": len(pairs)}
         for name, ps, m0, nv in (("qf", basis, N, 0), ("qfs", samples, 9, 9)):
             ph = I.qudit_circuit_apply(3, n, ps, pairs, tg)
