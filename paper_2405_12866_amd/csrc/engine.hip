@@ -37,7 +37,6 @@ namespace {
 
 enum { kRoleTrain = 1, kRoleVal = 2 };
 enum { kClsStep = 0, kClsForward = 1, kClsDist = 2, kClsPolar = 3, kClasses = 4 };
-constexpr int kPcap = 4096;  // capacity of per-start block partials
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();

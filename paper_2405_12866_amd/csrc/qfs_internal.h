@@ -213,6 +213,11 @@ __host__ __device__ inline double effective_beta(double beta, bool normalized, i
   return bm / ((1.0 - beta) + bm);
 }
 
+// Capacity, in blocks, of the per-start environment partials of a backward step: start s
+// owns blocks [s kPcap, s kPcap + P) whatever the block count P of a launch, so launches on
+// different streams over different start sets (with different P) never share partials.
+constexpr int kPcap = 4096;
+
 // ------------------------------------------------------------------ sweep kernels
 // Per-start addressing for the sweep kernels: a buffer of starts is at
 // base + stride * start (elements); stride 0 means shared by all starts.
@@ -271,8 +276,8 @@ int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, h
 
 // Backward step: optionally a_s <- u_s[k_apply]^dagger a_s (qubits of k_apply), then
 // the environment of gate k_env from a_s and b_s as per-block FP64 partial sums
-// [S][P][16] (P returned). launch_env_finalize (one wave per start) reduces them in a
-// fixed order and writes u_s[k_env] <- polar((1-beta) Gamma + beta u) to both gate
+// [S][kPcap][16] (blocks 0 .. P-1 of each start; P returned). launch_env_finalize (one
+// wave per start) reduces them in a fixed order and writes u_s[k_env] <- polar((1-beta) Gamma + beta u) to both gate
 // copies (kind QFS_GATE_1Q: the one-qubit update of a v (x) I_2 slot); optionally stores
 // Gamma (FP64) to gamma_out[s].
 template <typename R>

@@ -502,7 +502,7 @@ struct StepArgs {
   const cx<R> *gR;      // gates in state precision
   int32_t gstride;
   int32_t k_apply;
-  c128 *partials;       // [S][P][16]
+  c128 *partials;       // [S][kPcap][16], blocks 0 .. P-1 used
   const int32_t *slot_to_start;
   StepGeom geo;
 };
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   if (threadIdx.x < 16) {
     c128 sum = red[0][threadIdx.x];
     for (int w = 1; w < kWaves; ++w) sum = sum + red[w][threadIdx.x];
-    A.partials[((int64_t)s * P + blockIdx.x) * 16 + threadIdx.x] = sum;
+    A.partials[((int64_t)s * kPcap + blockIdx.x) * 16 + threadIdx.x] = sum;
   }
 }
 
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
   if (threadIdx.x < 16) {
     c128 sum = red[0][threadIdx.x];
     for (int w = 1; w < kLdsWaves; ++w) sum = sum + red[w][threadIdx.x];
-    A.partials[((int64_t)s * P + blockIdx.x) * 16 + threadIdx.x] = sum;
+    A.partials[((int64_t)s * kPcap + blockIdx.x) * 16 + threadIdx.x] = sum;
   }
 }
 
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(kFinBlock) void k_env_finalize(const c128 *partials
   const int s = slot_to_start[blockIdx.x];
   const int e = threadIdx.x & 15, grp = threadIdx.x >> 4;
   constexpr int G = kFinBlock / 16;
-  const c128 *src = partials + (int64_t)s * P * 16 + e;
+  const c128 *src = partials + (int64_t)s * kPcap * 16 + e;
   c128 acc[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
   int blk = grp;
   for (; blk + 3 * G < P; blk += 4 * G) {

@@ -350,6 +350,28 @@ def test_full_size_instantiate_in_bench_configuration(precision):
         assert abs(got["c_val"] - ref["c_val"]) <= tol * ref["c_val"], (got["c_val"], ref["c_val"])
 
 
+@pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
+def test_backward_split_deterministic_when_starts_stop_unevenly(precision):
+    """The backward pass runs the two halves of the running starts on two streams. Once
+    starts stop at different sweeps the halves differ in size (and in blocks per start),
+    which must not let their environment partials meet: repeated calls of a 12-qubit U3 +
+    CNOT instantiation (16 starts, M = 32, starts stopping one by one) agree bit for bit."""
+    say(f"split backward determinism, precision={precision}")
+    w = I.workload_u3_cnot(12, 4, seed_base=0x5A17 + 9)
+    tg, fx = dev(w["target_gates"]), dev(w["fixed"])
+    outs = []
+    for _ in range(3):
+        p = Q.qfs_default_params(seed=23, m_init=32, precision=precision)
+        g, r = Q.qfs_instantiate(12, w["pairs"], target_pairs=w["pairs"], target_gates=tg, params=p,
+                                 kinds=w["kinds"], fixed_gates=fx)
+        outs.append((host(g), r["reason_name"], r["sweeps"], r["best_start"], r["c_train"], r["start_sweeps"]))
+    for o in outs[1:]:
+        assert o[1:] == outs[0][1:], (o[1:], outs[0][1:])
+        assert np.array_equal(o[0], outs[0][0])
+    # starts did stop unevenly: fewer start-sweeps than 16 x the returned start's sweeps
+    assert outs[0][5] < 16 * outs[0][2]
+
+
 # ------------------------------------------------------------------ graph replay
 @pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
 def test_graph_replay_matches_eager(precision):
