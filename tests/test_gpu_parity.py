@@ -375,7 +375,7 @@ def test_backward_split_deterministic_when_starts_stop_unevenly(precision):
 # ------------------------------------------------------------------ graph replay
 @pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
 def test_graph_replay_matches_eager(precision):
-    """Each sweep replayed from a captured HIP graph (the default) gives bit-identical
+    """Each sweep replayed from a captured HIP graph (params.graphs = 1) gives bit-identical
     results to launching every kernel: many replays with host decisions and copies in
     between, re-captures after starts stop, after doublings and after the switch to
     complex128 refinement."""
