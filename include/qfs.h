@@ -219,7 +219,8 @@ void qfs_default_params(qfs_params *p);
  *              + row of a column-major 4x4 Ginibre block; a one-qubit gate takes
  *              v (x) I_2 with v from the 2x2 block at indices 16*gate + 2*col + row).
  *              Constant gates always come from tmpl->fixed_gates; a one-qubit gate's
- *              entry must have the form v (x) I_2 (to 1e-10).
+ *              entry must have the form v (x) I_2 (to 1e-10) and is used as exactly
+ *              that form, v taken from its entries (2i, 2j).
  *   gates_out: device [L][4][4]: the returned start's gates (complex128).
  *   res:       host.
  * Errors: QFS_EINVAL (invalid template/target/params, or gates_in not unitary to
@@ -423,7 +424,9 @@ int qfs_polar_update(int32_t count, const qfs_c128 *gamma, double beta, qfs_c128
  * environment, polar update, and backward propagation through the updated gate;
  * returns the Eq. 9 cost of the updated gates per start.
  *   kinds:     host [L] gate kinds, or NULL (every gate QFS_GATE_2Q); constant gates
- *              are the gates' own entries and are left unchanged.
+ *              are the gates' own entries and are left unchanged; a one-qubit
+ *              gate's entry must have the form v (x) I_2 exactly (the forward pass
+ *              skips the products with its zero entries).
  *   psi, phi:  device [M][N] (training states and U psi).
  *   gates:     device [starts][L][4][4], updated in place (complex128 master).
  *   precision: QFS_PREC_FP64 or QFS_PREC_MIXED (complex64 states).

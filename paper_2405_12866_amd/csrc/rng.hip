@@ -70,7 +70,8 @@ int launch_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L, 
 
 // Gate kinds after the 4x4 draw (or copy) of every slot: a one-qubit gate of a drawn
 // start becomes v (x) I_2 with v Haar on U(2) from the 2x2 Ginibre block at indices
-// 16*gate + 2*col + row of the same stream; a constant gate is copied from fixed[gate].
+// 16*gate + 2*col + row of the same stream (a copied one is projected onto that form);
+// a constant gate is copied from fixed[gate].
 // One thread per (start, gate).
 __global__ void k_kind_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L,
                              const int32_t *kinds, const c128 *fixed, int32_t drawn, c128 *out) {
@@ -83,7 +84,17 @@ __global__ void k_kind_gates(uint64_t seed, int32_t start0, int32_t starts, int3
     for (int e = 0; e < 16; ++e) u[e] = fixed[(int64_t)k * 16 + e];
     return;
   }
-  if (kind != QFS_GATE_1Q || !drawn) return;
+  if (kind != QFS_GATE_1Q) return;
+  if (!drawn) {
+    // a supplied one-qubit slot (checked to be within 1e-10 of v (x) I_2) is made exactly
+    // v (x) I_2, v from its entries (2i, 2j), so every kernel may rely on that form
+    c128 v[4];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) v[i * 2 + j] = u[(2 * i) * 4 + 2 * j];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) u[r * 4 + c] = ((r & 1) == (c & 1)) ? v[(r >> 1) * 2 + (c >> 1)] : cmake(0.0, 0.0);
+    return;
+  }
   c128 q[2][2];  // [col][row]
   for (int c = 0; c < 2; ++c)
     for (int r = 0; r < 2; ++r)

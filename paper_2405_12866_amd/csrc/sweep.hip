@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "polar2.h"
 #include "qfs_internal.h"
@@ -399,17 +400,23 @@ struct FwdSeg {
 // A gate on the lowest amplitude bits makes a thread's four outputs rows 32 or 64 bytes
 // apart; for such gates (when coalesce_b is set) B_k leaves LDS in a second, contiguous
 // pass instead of straight from registers.
+//
+// With two segments (training and validation sets) blockIdx.x alternates between them
+// (even: seg0 chunk x/2, odd: seg1 chunk x/2), so the store-bound training chunks and the
+// arithmetic-bound validation chunks (which store nothing) are dispatched side by side
+// and overlap, instead of one phase of the grid after the other.
 template <typename R, int FB>
-__global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int n,
-                                                             int logC, const int32_t *pairs,
-                                                             const cx<R> *gates, int32_t gstride,
-                                                             const int32_t *slot_to_start,
-                                                             int coalesce_b, const int32_t *kinds) {
+__global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int nseg, int n,
+                                                             int logC, const int32_t *__restrict__ pairs,
+                                                             const cx<R> *__restrict__ gates, int32_t gstride,
+                                                             const int32_t *__restrict__ slot_to_start,
+                                                             int coalesce_b, const int32_t *__restrict__ kinds) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
   __shared__ double red[FB / 64];
-  const FwdSeg<R> sg = blockIdx.z == 0 ? seg0 : seg1;
-  const int q = blockIdx.x;
+  const bool second = nseg == 2 && (blockIdx.x & 1);
+  const FwdSeg<R> sg = second ? seg1 : seg0;
+  const int q = nseg == 2 ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
   if (q >= sg.nch) return;
   const int s = slot_to_start[blockIdx.y];
   constexpr int V = Pk<R>::V, LOGV = Pk<R>::LOGV;
@@ -430,31 +437,42 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
     const bool store = k < sg.kstore && !(kinds && kinds[k + 1] == QFS_GATE_FIXED);
     cx<R> *dst = store ? sg.blist + sg.bstride * s + sg.sN * k + cbase : nullptr;
     const bool late = store && coalesce_b && ((sizeof(cx<R>) << (logC + min(pa, pb))) < 128);
-    for (uint32_t g = threadIdx.x; g < groups; g += FB) {
-      const uint32_t jv = g & ((1u << logJ) - 1u);
-      const uint32_t i0 = deposit(g >> logJ, sorted, 2);
-      uint32_t o[4];
-      o[0] = (i0 << logC) + jv * V;
-      o[1] = ((i0 + mb) << logC) + jv * V;
-      o[2] = ((i0 + ma) << logC) + jv * V;
-      o[3] = ((i0 + ma + mb) << logC) + jv * V;
-      Pk<R> x[4];
+    // a one-qubit slot is v (x) I_2: output 2i + j mixes inputs j and 2 + j only, so half
+    // of the products (those with the slot's exact zeros) are skipped; the remaining ones
+    // are accumulated in the same order, so the result is that of the full product
+    auto apply = [&](auto one_qubit) {
+      constexpr bool ONEQ = decltype(one_qubit)::value;
+      for (uint32_t g = threadIdx.x; g < groups; g += FB) {
+        const uint32_t jv = g & ((1u << logJ) - 1u);
+        const uint32_t i0 = deposit(g >> logJ, sorted, 2);
+        uint32_t o[4];
+        o[0] = (i0 << logC) + jv * V;
+        o[1] = ((i0 + mb) << logC) + jv * V;
+        o[2] = ((i0 + ma) << logC) + jv * V;
+        o[3] = ((i0 + ma + mb) << logC) + jv * V;
+        Pk<R> x[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) x[p] = ld_pk(lds + o[p]);
+        for (int p = 0; p < 4; ++p) x[p] = ld_pk(lds + o[p]);
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) {
-        Pk<R> y;
+        for (int qq = 0; qq < 4; ++qq) {
+          Pk<R> y;
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          cx<R> acc = cmake<R>(0, 0);
+          for (int e = 0; e < V; ++e) {
+            cx<R> acc = cmake<R>(0, 0);
 #pragma unroll
-          for (int p = 0; p < 4; ++p) cfma(acc, u[qq * 4 + p], x[p].v[e]);
-          y.v[e] = acc;
+            for (int p = 0; p < 4; ++p)
+              if (!ONEQ || (p & 1) == (qq & 1)) cfma(acc, u[qq * 4 + p], x[p].v[e]);
+            y.v[e] = acc;
+          }
+          st_pk(lds + o[qq], y);
+          if (store && !late) st_pk(dst + o[qq], y);
         }
-        st_pk(lds + o[qq], y);
-        if (store && !late) st_pk(dst + o[qq], y);
       }
-    }
+    };
+    if (kinds && kinds[k] == QFS_GATE_1Q)
+      apply(std::true_type{});
+    else
+      apply(std::false_type{});
     __syncthreads();
     if (late) {
       for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(dst + e, ld_pk(lds + e));
@@ -536,6 +554,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
     Pk<R> a[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) a[l] = ld_pk(a_in + base + ((int64_t)G.off[l] << logC));
+    // keep the NL loads of the super group together (one memory round trip per item): left
+    // to itself the scheduler folds each packet into the product as it arrives and waits
+    // for every load in turn
+    __builtin_amdgcn_sched_barrier(0);
     if (APPLY) {
 #pragma unroll
       for (int rho = 0; rho < NS; ++rho) {
@@ -556,19 +578,21 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
 #pragma unroll
       for (int l = 0; l < NL; ++l) st_pk(a_out + base + ((int64_t)G.off[l] << logC), a[l]);
     }
+    // the item's B_k packets, likewise in one batch (issued after the stores: loading them
+    // together with the state costs an occupancy step and measured no faster)
+    Pk<R> bl[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) bl[l] = ld_pk(b + base + ((int64_t)G.off[l] << logC));
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) {
-      Pk<R> bb[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-        bb[p] = ld_pk(b + base + ((int64_t)G.off[env_index<VAR>(p, sg)] << logC));
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
         const Pk<R> &aq = a[env_index<VAR>(qq, sg)];
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int e = 0; e < V; ++e) cfma_conj(acc[qq * 4 + p], aq.v[e], bb[p].v[e]);
+          for (int e = 0; e < V; ++e) cfma_conj(acc[qq * 4 + p], aq.v[e], bl[env_index<VAR>(p, sg)].v[e]);
       }
     }
   }
@@ -702,11 +726,16 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
               lds_get<R>(lds, lds_slot(((uint32_t)l << Lg.W) + rlow, jv, Lg.logJ)));
     }
     wave_sync();
-    // the box of B_k, same way
+    // the box of B_k, same way (all NL loads issued before the first LDS write, so they
+    // share one memory round trip)
+    {
+      Pk<R> bl[NL];
 #pragma unroll
-    for (int l = 0; l < NL; ++l)
-      lds_put<R>(lds, lds_slot(((uint32_t)l << Lg.W) + rlow, jv, Lg.logJ),
-                 ld_pk(b + gbase + ((int64_t)Lg.segoff[l] << logC)));
+      for (int l = 0; l < NL; ++l) bl[l] = ld_pk(b + gbase + ((int64_t)Lg.segoff[l] << logC));
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int l = 0; l < NL; ++l) lds_put<R>(lds, lds_slot(((uint32_t)l << Lg.W) + rlow, jv, Lg.logJ), bl[l]);
+    }
     wave_sync();
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) {
@@ -1024,13 +1053,16 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
   const int64_t groups = int64_t(1) << (g.n - 2 + g.logC - (sizeof(R) == 4 ? 1 : 0));
   const int fwd_threads = fwd_env == 512 || fwd_env == 1024 ? fwd_env : (groups >= 2048 ? 1024 : 512);
   auto go = [&](auto kernel, int threads) -> int {
-    static size_t attr_bytes = 0;  // dynamic LDS above 64 KB must be requested per kernel
-    if (lds > 64 * 1024 && lds > attr_bytes) {
+    // dynamic LDS above 64 KB must be requested per kernel (one entry per block size:
+    // both sizes share this lambda's instantiation)
+    static size_t attr_bytes[2] = {0, 0};
+    size_t &ab = attr_bytes[threads == 1024 ? 1 : 0];
+    if (lds > 64 * 1024 && lds > ab) {
       QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      attr_bytes = lds;
+      ab = lds;
     }
-    hipLaunchKernelGGL(kernel, dim3(gx, nslots, nz), dim3(threads), lds, s, a, b, g.n, g.logC, pairs_dev,
+    hipLaunchKernelGGL(kernel, dim3(gx * nz, nslots, 1), dim3(threads), lds, s, a, b, nz, g.n, g.logC, pairs_dev,
                        static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, coalesce_b,
                        kinds_dev);
     QFS_HIP(hipGetLastError());
