@@ -319,32 +319,53 @@ int sweep_backward(SweepCtx &c) {
     QFS_HIP(hipEventRecord(c.fork, c.stream));
     QFS_HIP(hipStreamWaitEvent(c.side, c.fork, 0));
   }
+  auto kind_of = [&](int k) { return c.kinds ? c.kinds[k] : QFS_GATE_2Q; };
+  auto same_qubits = [&](int i, int j) {
+    const int32_t *p = c.pairs_host;
+    return (p[2 * i] == p[2 * j] && p[2 * i + 1] == p[2 * j + 1]) ||
+           (p[2 * i] == p[2 * j + 1] && p[2 * i + 1] == p[2 * j]);
+  };
+  bool a_written = false;  // A holds the backward state (else it is still phi)
+  int fold = -1;           // gate whose u^dag the next step applies first (folded step)
   for (int k = c.L - 1; k >= 0; --k) {
     const int k_apply = (k == c.L - 1) ? -1 : k + 1;
-    const int kind = c.kinds ? c.kinds[k] : QFS_GATE_2Q;
-    SBuf<R> a_in = (k >= c.L - 2) ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
+    const int kind = kind_of(k);
+    SBuf<R> a_in = a_written ? SBuf<R>{A, sN} : SBuf<R>{phi, 0};
     SBuf<R> b = k == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (k - 1) * sN, bstride};
-    for (int h = 0; h < halves; ++h) {
-      if (kind == QFS_GATE_FIXED) {
-        // a constant gate has no environment: only move the backward state through
-        // the gate after it (nothing to do for the last gate)
-        if (k_apply < 0) continue;
+    if (kind == QFS_GATE_FIXED) {
+      // a constant gate has no environment: only move the backward state through the
+      // gate after it (nothing to do for the last gate). When the gate before it has an
+      // environment and the gate after it acts on the same two qubits (a U3 + CNOT
+      // block), that move is folded into the next step, which then applies
+      // u_k^dag u_{k+1}^dag with one pass over the state instead of two.
+      if (k_apply < 0) continue;
+      if (k >= 1 && kind_of(k - 1) != QFS_GATE_FIXED && same_qubits(k, k + 1)) {
+        fold = k + 1;
+        continue;
+      }
+      for (int h = 0; h < halves; ++h) {
         QFS_TRY(T.begin(hs[h]));
         QFS_TRY(launch_apply<R>(c.g, c.pairs_host[2 * k_apply], c.pairs_host[2 * k_apply + 1], k_apply,
                                 true, gr, a_in, SBuf<R>{A, sN}, hslots[h], hn[h], hs[h]));
         QFS_TRY(T.end(hs[h], kClsStep, 2.0 * set_bytes<R>(c, c.g) * hn[h] / c.nslots));
-        continue;
       }
+      a_written = true;
+      continue;
+    }
+    const int k_apply2 = fold;
+    fold = -1;
+    for (int h = 0; h < halves; ++h) {
       int P = 0;
       QFS_TRY(T.begin(hs[h]));
       QFS_TRY(launch_bwd_step<R>(c.g, c.pairs_host, k_apply, k, gr, a_in, SBuf<R>{A, sN}, b, hslots[h],
-                                 hn[h], c.partials, &P, hs[h]));
+                                 hn[h], c.partials, &P, hs[h], k_apply2));
       QFS_TRY(T.end(hs[h], kClsStep, (k_apply < 0 ? 2.0 : 3.0) * set_bytes<R>(c, c.g) * hn[h] / c.nslots));
       QFS_TRY(T.begin(hs[h]));
       QFS_TRY(launch_env_finalize(P, c.partials, hslots[h], hn[h], nullptr, true, c.beta, c.g64,
                                   sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, k, c.vstore, kind, hs[h]));
       QFS_TRY(T.end(hs[h], kClsPolar, (double)P * 256.0 * hn[h]));
     }
+    if (k_apply >= 0) a_written = true;
   }
   if (split) {
     QFS_HIP(hipEventRecord(c.join, c.side));
@@ -353,7 +374,7 @@ int sweep_backward(SweepCtx &c) {
   int P = 0;
   QFS_TRY(T.begin(c.stream));
   QFS_TRY(launch_apply_dist<R>(c.g, c.pairs_host[0], c.pairs_host[1], 0, true, gr,
-                               c.L == 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN}, SBuf<R>{psi, 0}, c.slots,
+                               a_written ? SBuf<R>{A, sN} : SBuf<R>{phi, 0}, SBuf<R>{psi, 0}, c.slots,
                                c.nslots, c.dpart0, &P, c.stream));
   QFS_TRY(T.end(c.stream, kClsDist, 2.0 * set_bytes<R>(c, c.g)));
   QFS_TRY(launch_dist_finalize(P, c.dpart0, c.slots, c.nslots, c.g.M, c.costs, c.stream));

@@ -274,8 +274,10 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
 template <typename R>
 int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, hipStream_t s);
 
-// Backward step: optionally a_s <- u_s[k_apply]^dagger a_s (qubits of k_apply), then
-// the environment of gate k_env from a_s and b_s as per-block FP64 partial sums
+// Backward step: optionally a_s <- u_s[k_apply]^dagger a_s (qubits of k_apply; with
+// k_apply2 >= 0, a gate on the same two qubits, a_s <- u_s[k_apply]^dagger
+// u_s[k_apply2]^dagger a_s), then the environment of gate k_env from a_s and b_s as
+// per-block FP64 partial sums
 // [S][kPcap][16] (blocks 0 .. P-1 of each start; P returned). launch_env_finalize (one
 // wave per start) reduces them in a fixed order and writes u_s[k_env] <- polar((1-beta) Gamma + beta u) to both gate
 // copies (kind QFS_GATE_1Q: the one-qubit update of a v (x) I_2 slot); optionally stores
@@ -284,7 +286,7 @@ template <typename R>
 int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
                     GateRef gates, SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b,
                     const int32_t *slot_to_start, int nslots, c128 *partials, int *P_out,
-                    hipStream_t s);
+                    hipStream_t s, int k_apply2 = -1);
 // vstore (nullable, [S][L][16]): right singular vectors of each gate's last update,
 // used to warm-start the Jacobi iteration and updated in place.
 int launch_env_finalize(int P, const c128 *partials, const int32_t *slot_to_start, int nslots,

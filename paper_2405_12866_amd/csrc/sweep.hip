@@ -125,6 +125,39 @@ __device__ __forceinline__ void load_gate(const cx<R> *src, cx<R> (&u)[16], bool
     for (int p = 0; p < 4; ++p) u[q * 4 + p] = dagger ? cconj(src[p * 4 + q]) : src[q * 4 + p];
 }
 
+// u^dag of gate k_apply, or u_{k_apply}^dag u_{k_apply2}^dag when a second gate on the same
+// two qubits goes first (a constant gate's backward step folded into the next one); the
+// second gate is taken into the first one's local basis (indices 1 and 2 exchanged when
+// it names the qubits in the opposite order)
+template <typename R>
+__device__ __forceinline__ void load_step_gate(const cx<R> *g, int k_apply, int k_apply2, int swap2,
+                                               cx<R> (&ud)[16]) {
+  load_gate<R>(g + k_apply * 16, ud, true);
+  if (k_apply2 < 0) return;
+  cx<R> u2[16];
+  load_gate<R>(g + k_apply2 * 16, u2, true);
+  if (swap2) {
+    constexpr int pm[4] = {0, 2, 1, 3};
+    cx<R> t[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t[e] = u2[pm[e >> 2] * 4 + pm[e & 3]];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u2[e] = t[e];
+  }
+  cx<R> m[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      cx<R> acc = cmake<R>(0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cfma(acc, ud[q * 4 + r], u2[r * 4 + p]);
+      m[q * 4 + p] = acc;
+    }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) ud[e] = m[e];
+}
+
 // ------------------------------------------------------------------ FP64 4x4 polar
 // One-sided (Hestenes) Jacobi on one wave: lane l = 4c + r (of each 16-lane group)
 // holds column c, row r of the working matrix G and of V. Each round rotates the two
@@ -520,6 +553,8 @@ struct StepArgs {
   const cx<R> *gR;      // gates in state precision
   int32_t gstride;
   int32_t k_apply;
+  int32_t k_apply2;     // >= 0: apply u^dag of this gate first (same qubits as k_apply)
+  int32_t swap2;        // k_apply2 names the two qubits in the opposite order
   c128 *partials;       // [S][kPcap][16], blocks 0 .. P-1 used
   const int32_t *slot_to_start;
   StepGeom geo;
@@ -536,7 +571,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
   cx<R> ud[16];
-  if (APPLY) load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k_apply * 16, ud, true);
+  if (APPLY) load_step_gate<R>(A.gR + (int64_t)s * A.gstride, A.k_apply, A.k_apply2, A.swap2, ud);
   const cx<R> *a_in = A.a_in + A.a_in_stride * s;
   cx<R> *a_out = A.a_out + A.a_out_stride * s;
   const cx<R> *b = A.b + A.b_stride * s;
@@ -673,7 +708,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
   cx<R> ud[16];
-  if (APPLY) load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k_apply * 16, ud, true);
+  if (APPLY) load_step_gate<R>(A.gR + (int64_t)s * A.gstride, A.k_apply, A.k_apply2, A.swap2, ud);
   const cx<R> *a_in = A.a_in + A.a_in_stride * s;
   cx<R> *a_out = A.a_out + A.a_out_stride * s;
   const cx<R> *b = A.b + A.b_stride * s;
@@ -1180,8 +1215,18 @@ template <typename R>
 int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, int k_env,
                     GateRef gates, SBuf<R> a_in, SBuf<R> a_out, SBuf<R> b,
                     const int32_t *slot_to_start, int nslots, c128 *partials, int *P_out,
-                    hipStream_t s) {
+                    hipStream_t s, int k_apply2) {
   if (nslots <= 0) return QFS_OK;
+  int swap2 = 0;
+  if (k_apply2 >= 0) {
+    const int a0 = pairs_host[2 * k_apply], a1 = pairs_host[2 * k_apply + 1];
+    const int b0 = pairs_host[2 * k_apply2], b1 = pairs_host[2 * k_apply2 + 1];
+    if (k_apply < 0 || !((a0 == b0 && a1 == b1) || (a0 == b1 && a1 == b0))) {
+      set_error_detail("backward step: the folded gate must act on the same two qubits");
+      return QFS_EINVAL;
+    }
+    swap2 = a0 == b1 ? 1 : 0;
+  }
   int32_t tq[4];
   int t = 0;
   const int var = classify_step(pairs_host, k_apply, k_env, tq, &t);
@@ -1195,6 +1240,8 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
   a.gR = static_cast<const cx<R> *>(gates.gR);
   a.gstride = gates.gstride;
   a.k_apply = k_apply;
+  a.k_apply2 = k_apply2;
+  a.swap2 = swap2;
   a.partials = partials;
   a.slot_to_start = slot_to_start;
   StepGeom &G = a.geo;
@@ -1306,7 +1353,7 @@ int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipSt
                                SBuf<R>, const int32_t *, int, hipStream_t);                   \
   template int launch_bwd_step<R>(const Geometry &, const int32_t *, int, int, GateRef,       \
                                   SBuf<R>, SBuf<R>, SBuf<R>, const int32_t *, int, c128 *,    \
-                                  int *, hipStream_t);                                       \
+                                  int *, hipStream_t, int);                                  \
   template int launch_apply_dist<R>(const Geometry &, int, int, int, bool, GateRef, SBuf<R>,  \
                                     SBuf<R>, const int32_t *, int, double *, int *,           \
                                     hipStream_t);                                            \

@@ -80,6 +80,52 @@ def test_fp64_lock_step_with_kinds(n, L, M, starts, ends_fixed):
             assert np.max(np.abs(got[:, k] - np.stack([np.kron(x, np.eye(2)) for x in v]))) < 1e-15
 
 
+def _folding_template():
+    """n = 5: constant gates whose backward step folds into the next one (the gate after
+    them on the same two qubits, in the same or the opposite order), and constant gates
+    that cannot fold (different qubits after them, a constant gate before them, the last
+    gate, the first gate)."""
+    pairs = [(0, 1), (1, 2), (1, 2), (3, 4), (2, 3), (3, 2), (0, 4), (0, 1), (1, 0), (2, 4),
+             (2, 4), (4, 1), (3, 1), (3, 0)]
+    kinds = [I.GATE_FIXED, I.GATE_2Q, I.GATE_FIXED, I.GATE_2Q, I.GATE_FIXED, I.GATE_1Q,
+             I.GATE_2Q, I.GATE_FIXED, I.GATE_2Q, I.GATE_FIXED, I.GATE_FIXED, I.GATE_1Q,
+             I.GATE_2Q, I.GATE_FIXED]
+    return np.asarray(pairs, dtype=np.int32), np.asarray(kinds, dtype=np.int32)
+
+
+@pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
+def test_folded_constant_steps_follow_oracle(precision):
+    """The backward step of a constant gate is folded into the next step when the gate
+    after it acts on the same two qubits (the device applies u_k^dag u_{k+1}^dag in one
+    pass, the oracle one gate at a time). FP64: 20 sweeps in lock step to 1e-10;
+    complex64 states: teacher-forced to 1e-6 max(c, c_initial)."""
+    say(f"folded constant steps, precision={precision}")
+    n, M, starts = 5, 7, 2
+    pairs, kinds = _folding_template()
+    L = len(pairs)
+    g = np.random.default_rng(77)
+    fixed = np.stack([I.haar_unitary(4, g) for _ in range(L)])
+    tg = I.kinds_target_gates(kinds, fixed, g)
+    psi = I.orthonormal_samples(n, M, g)
+    phi = O.apply_circuit(n, psi, pairs, tg)
+    gates = np.stack([O.initial_gates(5, s, kinds, fixed) for s in range(starts)])
+    dg, dpsi, dphi = dev(gates), dev(psi), dev(phi)
+    ref = gates.copy()
+    c_init = max(O.sweep(n, pairs, psi, phi, gates[0].copy(), kinds=kinds)[1], 1e-3)
+    for sweep in range(20 if precision == Q.QFS_PREC_FP64 else 6):
+        start = host(dg).copy()
+        c_gpu = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=precision, kinds=kinds)
+        for s in range(starts):
+            if precision == Q.QFS_PREC_FP64:
+                ref[s], c_ref = O.sweep(n, pairs, psi, phi, ref[s], kinds=kinds)
+                assert abs(c_gpu[s] - c_ref) <= 1e-10 * max(c_ref, 1e-3), (sweep, s, c_gpu[s], c_ref)
+            else:
+                _, c_ref = O.sweep(n, pairs, psi, phi, start[s].copy(), kinds=kinds)
+                assert abs(c_gpu[s] - c_ref) <= 1e-6 * max(c_ref, c_init), (sweep, s, c_gpu[s], c_ref)
+        if precision == Q.QFS_PREC_FP64:
+            assert np.max(np.abs(host(dg) - ref)) < 1e-10
+
+
 def test_mixed_u3_cnot_teacher_forced():
     """complex64 states on an 8-qubit U3 + CNOT template (4 sublayers, 14 CNOTs and 36
     one-qubit gates): each sweep from the device's own FP64 gates on both sides."""
