@@ -117,12 +117,26 @@ __device__ __forceinline__ void split_item(uint32_t it, const ChunkGeom &cg, uin
   q = rest >> cg.logG;
 }
 
-template <typename R>
-__device__ __forceinline__ void load_gate(const cx<R> *src, cx<R> (&u)[16], bool dagger) {
+// Read-only kernel inputs through the constant address space: uniform loads from it are
+// scalar loads (counted by lgkmcnt), so reading the next gate never waits for the vector
+// stores still in flight, however the surrounding code looks to alias analysis.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
+
+template <typename R, typename P>
+__device__ __forceinline__ void load_gate(P src, cx<R> (&u)[16], bool dagger) {
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int p = 0; p < 4; ++p) u[q * 4 + p] = dagger ? cconj(src[p * 4 + q]) : src[q * 4 + p];
+    for (int p = 0; p < 4; ++p) {
+      const int i = dagger ? p * 4 + q : q * 4 + p;
+      const cx<R> x = cmake<R>(src[i].re, src[i].im);  // (also from the constant address space)
+      u[q * 4 + p] = dagger ? cconj(x) : x;
+    }
 }
 
 // u^dag of gate k_apply, or u_{k_apply}^dag u_{k_apply2}^dag when a second gate on the same
@@ -430,6 +444,80 @@ struct FwdSeg {
   int32_t kstore;       // outputs stored for gates 0 .. kstore-1
 };
 
+// One LDS pass over gates k0 .. k0 + run - 1, all on the qubits of gate k0 (in either
+// order). Each gate is taken into gate k0's local basis (indices 1 and 2 exchanged when
+// it names the qubits the other way round); a one-qubit slot v (x) I_2 skips its zero
+// products (on the first local bit in its own order, so on the second one when
+// exchanged). B_{k+1} is stored from registers after gate k when some environment reads
+// it (bit j of store_mask: after gate k0 + j; blist: this chunk's entry 0 of the start,
+// entries sN apart).
+template <typename R>
+__device__ __forceinline__ void forward_run(cx<R> *lds, uint32_t groups, int logJ, int logC,
+                                            const int (&sorted)[2], uint32_t ma, uint32_t mb,
+                                            cptr<int32_t> pairs, cptr<cx<R>> g, cptr<int32_t> kinds,
+                                            int k0, int run, uint32_t store_mask, cx<R> *blist,
+                                            int64_t sN) {
+  constexpr int V = Pk<R>::V;
+  const int FB = blockDim.x;
+  for (uint32_t gi = threadIdx.x; gi < groups; gi += FB) {
+    const uint32_t jv = gi & ((1u << logJ) - 1u);
+    const uint32_t i0 = deposit(gi >> logJ, sorted, 2);
+    uint32_t o[4];
+    o[0] = (i0 << logC) + jv * V;
+    o[1] = ((i0 + mb) << logC) + jv * V;
+    o[2] = ((i0 + ma) << logC) + jv * V;
+    o[3] = ((i0 + ma + mb) << logC) + jv * V;
+    Pk<R> x[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) x[p] = ld_pk(lds + o[p]);
+    for (int j = 0; j < run; ++j) {
+      const int k = k0 + j;
+      const bool swapped = pairs[2 * k] != pairs[2 * k0];
+      cx<R> u[16];
+      load_gate<R>(g + k * 16, u, false);
+      if (swapped) {
+        constexpr int pm[4] = {0, 2, 1, 3};
+        cx<R> t[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) t[e] = u[pm[e >> 2] * 4 + pm[e & 3]];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) u[e] = t[e];
+      }
+      const int mode = (kinds && kinds[k] == QFS_GATE_1Q) ? (swapped ? 2 : 1) : 0;
+      Pk<R> y[4];
+      auto product = [&](auto m) {
+        constexpr int MODE = decltype(m)::value;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            cx<R> acc = cmake<R>(0, 0);
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+              if (MODE == 0 || (MODE == 1 ? (p & 1) == (qq & 1) : (p >> 1) == (qq >> 1)))
+                cfma(acc, u[qq * 4 + p], x[p].v[e]);
+            y[qq].v[e] = acc;
+          }
+      };
+      if (mode == 0)
+        product(std::integral_constant<int, 0>{});
+      else if (mode == 1)
+        product(std::integral_constant<int, 1>{});
+      else
+        product(std::integral_constant<int, 2>{});
+      if (blist && ((store_mask >> j) & 1u)) {
+        cx<R> *dst = blist + sN * k;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) st_pk(dst + o[qq], y[qq]);
+      }
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) x[qq] = y[qq];
+    }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) st_pk(lds + o[qq], x[qq]);
+  }
+}
+
 // A gate on the lowest amplitude bits makes a thread's four outputs rows 32 or 64 bytes
 // apart; for such gates (when coalesce_b is set) B_k leaves LDS in a second, contiguous
 // pass instead of straight from registers.
@@ -440,10 +528,13 @@ struct FwdSeg {
 // and overlap, instead of one phase of the grid after the other.
 template <typename R, int FB>
 __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> seg1, int nseg, int n,
-                                                             int logC, const int32_t *__restrict__ pairs,
-                                                             const cx<R> *__restrict__ gates, int32_t gstride,
-                                                             const int32_t *__restrict__ slot_to_start,
-                                                             int coalesce_b, const int32_t *__restrict__ kinds) {
+                                                             int logC, const int32_t *pairs_in,
+                                                             const cx<R> *gates_in, int32_t gstride,
+                                                             const int32_t *slot_to_start,
+                                                             int coalesce_b, const int32_t *kinds_in) {
+  const cptr<int32_t> pairs = as_const(pairs_in);
+  const cptr<int32_t> kinds = kinds_in ? as_const(kinds_in) : (cptr<int32_t>)nullptr;
+  const cptr<cx<R>> gates = as_const(gates_in);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
   __shared__ double red[FB / 64];
@@ -460,10 +551,37 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
   for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(lds + e, ld_pk(src + e));
   __syncthreads();
   const uint32_t groups = 1u << (n - 2 + logJ);
-  for (int k = 0; k < sg.kapply; ++k) {
+  for (int k = 0; k < sg.kapply;) {
     const int pa = n - 1 - pairs[2 * k], pb = n - 1 - pairs[2 * k + 1];
     const int sorted[2] = {min(pa, pb), max(pa, pb)};
     const uint32_t ma = 1u << pa, mb = 1u << pb;
+    // the gates after k on the same two qubits (a U3 + CNOT block) join this pass: each
+    // group of four amplitudes goes through all of them in registers, with their B list
+    // entries stored on the way, and LDS is read and written once. Not for gates on the
+    // lowest amplitude bits when B entries are stored (those leave LDS in a second pass).
+    int run = 1;
+    if (sg.kstore == 0 || !(coalesce_b && ((sizeof(cx<R>) << (logC + min(pa, pb))) < 128))) {
+      while (k + run < sg.kapply && run < 32) {
+        const int c0 = pairs[2 * (k + run)], c1 = pairs[2 * (k + run) + 1];
+        const int a0 = pairs[2 * k], a1 = pairs[2 * k + 1];
+        if (!((c0 == a0 && c1 == a1) || (c0 == a1 && c1 == a0))) break;
+        ++run;
+      }
+    }
+    run = __builtin_amdgcn_readfirstlane(run);
+    if (run > 1) {
+      // which gates of the run are followed by a B entry some environment reads (none
+      // before a constant gate); uniform, worked out before the per-thread loop
+      uint32_t mask = 0;
+      for (int j = 0; j < run; ++j)
+        if (k + j < sg.kstore && !(kinds && kinds[k + j + 1] == QFS_GATE_FIXED)) mask |= 1u << j;
+      mask = __builtin_amdgcn_readfirstlane(mask);
+      forward_run<R>(lds, groups, logJ, logC, sorted, ma, mb, pairs, gates + (int64_t)s * gstride, kinds, k,
+                     run, mask, sg.blist ? sg.blist + sg.bstride * s + cbase : nullptr, sg.sN);
+      __syncthreads();
+      k += run;
+      continue;
+    }
     cx<R> u[16];
     load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, false);
     // B_{k+1} serves only the environment of gate k+1: none for a constant gate
@@ -511,6 +629,7 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
       for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(dst + e, ld_pk(lds + e));
       __syncthreads();
     }
+    ++k;
   }
   if (sg.ref) {
     const cx<R> *ref = sg.ref + cbase;
@@ -560,7 +679,9 @@ struct StepArgs {
   StepGeom geo;
 };
 
-template <typename R, int VAR, bool APPLY>
+// EXTRA: the step may fold a second gate into its apply (k_apply2); a separate
+// instantiation, so the common step keeps its registers.
+template <typename R, int VAR, bool APPLY, bool EXTRA>
 __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   constexpr int t = var_bits<VAR>();
   constexpr int NL = 1 << t;
@@ -571,7 +692,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
   cx<R> ud[16];
-  if (APPLY) load_step_gate<R>(A.gR + (int64_t)s * A.gstride, A.k_apply, A.k_apply2, A.swap2, ud);
+  if (APPLY) {
+    if (EXTRA)
+      load_step_gate<R>(A.gR + (int64_t)s * A.gstride, A.k_apply, A.k_apply2, A.swap2, ud);
+    else
+      load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k_apply * 16, ud, true);
+  }
   const cx<R> *a_in = A.a_in + A.a_in_stride * s;
   cx<R> *a_out = A.a_out + A.a_out_stride * s;
   const cx<R> *b = A.b + A.b_stride * s;
@@ -693,7 +819,7 @@ __device__ __forceinline__ Pk<R> lds_get(const float4 *lds, int slot) {
   return *reinterpret_cast<const Pk<R> *>(&x);
 }
 
-template <typename R, int VAR, bool APPLY>
+template <typename R, int VAR, bool APPLY, bool EXTRA>
 __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGeom Lg) {
   constexpr int t = var_bits<VAR>();
   constexpr int NL = 1 << t;
@@ -708,7 +834,12 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
   cx<R> ud[16];
-  if (APPLY) load_step_gate<R>(A.gR + (int64_t)s * A.gstride, A.k_apply, A.k_apply2, A.swap2, ud);
+  if (APPLY) {
+    if (EXTRA)
+      load_step_gate<R>(A.gR + (int64_t)s * A.gstride, A.k_apply, A.k_apply2, A.swap2, ud);
+    else
+      load_gate<R>(A.gR + (int64_t)s * A.gstride + A.k_apply * 16, ud, true);
+  }
   const cx<R> *a_in = A.a_in + A.a_in_stride * s;
   cx<R> *a_out = A.a_out + A.a_out_stride * s;
   const cx<R> *b = A.b + A.b_stride * s;
@@ -1147,13 +1278,31 @@ static int classify_step(const int32_t *pairs, int k_apply, int k_env, int32_t t
   return 6;
 }
 
-template <typename R, int VAR, bool APPLY>
+template <typename R, int VAR, bool APPLY, bool EXTRA>
 static void launch_step_kernel(dim3 grid, const StepArgs<R> &a, const LdsGeom *lg, hipStream_t s) {
   if (lg) {
     const size_t lds = (size_t)kLdsWaves * (1 << var_bits<VAR>()) * 72 * 16;
-    hipLaunchKernelGGL((k_bwd_step_lds<R, VAR, APPLY>), grid, dim3(kLdsBlock), lds, s, a, *lg);
+    hipLaunchKernelGGL((k_bwd_step_lds<R, VAR, APPLY, EXTRA>), grid, dim3(kLdsBlock), lds, s, a, *lg);
   } else {
-    hipLaunchKernelGGL((k_bwd_step<R, VAR, APPLY>), grid, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_bwd_step<R, VAR, APPLY, EXTRA>), grid, dim3(kBlock), 0, s, a);
+  }
+}
+
+template <typename R, bool EXTRA>
+static void launch_step_var(int var, bool apply, dim3 grid, const StepArgs<R> &a, const LdsGeom *lg,
+                            hipStream_t s) {
+  if (!apply) {
+    launch_step_kernel<R, 0, false, EXTRA>(grid, a, lg, s);
+    return;
+  }
+  switch (var) {
+    case 0: launch_step_kernel<R, 0, true, EXTRA>(grid, a, lg, s); break;
+    case 1: launch_step_kernel<R, 1, true, EXTRA>(grid, a, lg, s); break;
+    case 2: launch_step_kernel<R, 2, true, EXTRA>(grid, a, lg, s); break;
+    case 3: launch_step_kernel<R, 3, true, EXTRA>(grid, a, lg, s); break;
+    case 4: launch_step_kernel<R, 4, true, EXTRA>(grid, a, lg, s); break;
+    case 5: launch_step_kernel<R, 5, true, EXTRA>(grid, a, lg, s); break;
+    default: launch_step_kernel<R, 6, true, EXTRA>(grid, a, lg, s); break;
   }
 }
 
@@ -1271,19 +1420,10 @@ int launch_bwd_step(const Geometry &g, const int32_t *pairs_host, int k_apply, i
   }
   *P_out = P;
   dim3 grid(P, nslots);
-  if (k_apply < 0) {
-    launch_step_kernel<R, 0, false>(grid, a, lgp, s);
-  } else {
-    switch (var) {
-      case 0: launch_step_kernel<R, 0, true>(grid, a, lgp, s); break;
-      case 1: launch_step_kernel<R, 1, true>(grid, a, lgp, s); break;
-      case 2: launch_step_kernel<R, 2, true>(grid, a, lgp, s); break;
-      case 3: launch_step_kernel<R, 3, true>(grid, a, lgp, s); break;
-      case 4: launch_step_kernel<R, 4, true>(grid, a, lgp, s); break;
-      case 5: launch_step_kernel<R, 5, true>(grid, a, lgp, s); break;
-      default: launch_step_kernel<R, 6, true>(grid, a, lgp, s); break;
-    }
-  }
+  if (k_apply2 >= 0)
+    launch_step_var<R, true>(var, k_apply >= 0, grid, a, lgp, s);
+  else
+    launch_step_var<R, false>(var, k_apply >= 0, grid, a, lgp, s);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
