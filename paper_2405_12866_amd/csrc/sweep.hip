@@ -82,6 +82,39 @@ __device__ __forceinline__ R wave_sum(R x) {
   return x;
 }
 
+// Wave sums of the 16 complex entries of a 4x4 environment (32 reals) by recursive
+// halving: at the exchange with lane ^ m (m = 32 .. 2) each lane keeps half of its values
+// (the upper half when its bit m is set) and adds its partner's copy of that half, so 31
+// exchanges replace 6 per value; a last exchange with lane ^ 1 completes the sums. Lane l
+// returns the wave sum of real value l >> 1 (entry (l >> 2), real part when bit 1 of l is
+// clear).
+template <int C, typename R>
+__device__ __forceinline__ void halve_level(R (&v)[32], int lane) {
+  const bool hi = (lane & (2 * C)) != 0;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const R give = hi ? v[i] : v[C + i];
+    const R keep = hi ? v[C + i] : v[i];
+    v[i] = keep + __shfl_xor(give, 2 * C);
+  }
+}
+template <typename R>
+__device__ __forceinline__ R wave_sum_env(const cx<R> (&acc)[16]) {
+  const int lane = threadIdx.x & 63;
+  R v[32];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    v[2 * e] = acc[e].re;
+    v[2 * e + 1] = acc[e].im;
+  }
+  halve_level<16>(v, lane);
+  halve_level<8>(v, lane);
+  halve_level<4>(v, lane);
+  halve_level<2>(v, lane);
+  halve_level<1>(v, lane);
+  return v[0] + __shfl_xor(v[0], 1);
+}
+
 // Local index of the environment gate's (q, sigma) inside a super group, per variant
 // (see host-side classify_step for how the canonical bit order is built).
 template <int VAR>
@@ -687,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
   constexpr int NL = 1 << t;
   constexpr int NS = NL / 4;
   constexpr int V = Pk<R>::V;
-  __shared__ c128 red[kWaves][16];
+  __shared__ double red[kWaves][32];
 
   const int s = A.slot_to_start[blockIdx.y];
   const int P = gridDim.x;
@@ -760,16 +793,13 @@ __global__ __launch_bounds__(kBlock) void k_bwd_step(StepArgs<R> A) {
 
   // thread -> wave -> block partial (FP64 across waves)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const R re = wave_sum<R>(acc[e].re);
-    const R im = wave_sum<R>(acc[e].im);
-    if (lane == 0) red[wv][e] = cmake<double>(re, im);
-  }
+  const R ws = wave_sum_env<R>(acc);
+  if ((lane & 1) == 0) red[wv][lane >> 1] = (double)ws;
   __syncthreads();
   if (threadIdx.x < 16) {
-    c128 sum = red[0][threadIdx.x];
-    for (int w = 1; w < kWaves; ++w) sum = sum + red[w][threadIdx.x];
+    const int e = threadIdx.x;
+    c128 sum = cmake(red[0][2 * e], red[0][2 * e + 1]);
+    for (int w = 1; w < kWaves; ++w) sum = sum + cmake(red[w][2 * e], red[w][2 * e + 1]);
     A.partials[((int64_t)s * kPcap + blockIdx.x) * 16 + threadIdx.x] = sum;
   }
 }
@@ -827,7 +857,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
   constexpr int V = Pk<R>::V;
   constexpr int kSlots = NL * 72;  // 64 packets per segment + padding
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  __shared__ c128 red[kLdsWaves][16];
+  __shared__ double red[kLdsWaves][32];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float4 *lds = reinterpret_cast<float4 *>(lds_raw) + wv * kSlots;
 
@@ -921,16 +951,13 @@ __global__ __launch_bounds__(kLdsBlock) void k_bwd_step_lds(StepArgs<R> A, LdsGe
     wave_sync();
   }
 
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const R re = wave_sum<R>(acc[e].re);
-    const R im = wave_sum<R>(acc[e].im);
-    if (lane == 0) red[wv][e] = cmake<double>(re, im);
-  }
+  const R ws = wave_sum_env<R>(acc);
+  if ((lane & 1) == 0) red[wv][lane >> 1] = (double)ws;
   __syncthreads();
   if (threadIdx.x < 16) {
-    c128 sum = red[0][threadIdx.x];
-    for (int w = 1; w < kLdsWaves; ++w) sum = sum + red[w][threadIdx.x];
+    const int e = threadIdx.x;
+    c128 sum = cmake(red[0][2 * e], red[0][2 * e + 1]);
+    for (int w = 1; w < kLdsWaves; ++w) sum = sum + cmake(red[w][2 * e], red[w][2 * e + 1]);
     A.partials[((int64_t)s * kPcap + blockIdx.x) * 16 + threadIdx.x] = sum;
   }
 }
