@@ -33,6 +33,38 @@ __device__ __forceinline__ uint32_t deposit2(uint32_t r, int lo, int hi) {
   return r;
 }
 
+// Wave sums of the 16 complex entries of a 4x4 environment (32 reals, FP64) by recursive
+// halving: at the exchange with lane ^ 2C each lane keeps half of its values (the upper
+// half when that lane bit is set) and adds its partner's copy of that half; a last
+// exchange with lane ^ 1 completes the sums. Lane l returns the wave sum of real value
+// l >> 1 (value 2e is entry e's real part, 2e + 1 its imaginary part).
+template <int C>
+__device__ __forceinline__ void bhalve(double (&v)[32], int lane) {
+  const bool hi = (lane & (2 * C)) != 0;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const double give = hi ? v[i] : v[C + i];
+    const double keep = hi ? v[C + i] : v[i];
+    v[i] = keep + __shfl_xor(give, 2 * C);
+  }
+}
+template <typename R>
+__device__ __forceinline__ double bwave_sum_env(const cx<R> (&acc)[16]) {
+  const int lane = threadIdx.x & 63;
+  double v[32];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    v[2 * e] = (double)acc[e].re;
+    v[2 * e + 1] = (double)acc[e].im;
+  }
+  bhalve<16>(v, lane);
+  bhalve<8>(v, lane);
+  bhalve<4>(v, lane);
+  bhalve<2>(v, lane);
+  bhalve<1>(v, lane);
+  return v[0] + __shfl_xor(v[0], 1);
+}
+
 // Sum over the work-group; result valid in every thread. `red` holds NT/64 values.
 template <int NT>
 __device__ __forceinline__ double block_sum(double x, double *red) {
@@ -421,11 +453,10 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
           for (int p = 0; p < 4; ++p) cfma_conj(acc[q * 4 + p], av[q], bv[p]);
       }
       const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const double re = bwave_sum<double>((double)acc[e].re);
-        const double im = bwave_sum<double>((double)acc[e].im);
-        if (lane == 0) sh.wred[w][e] = cmake(re, im);
+      {
+        const double ws = bwave_sum_env<R>(acc);
+        // (value 2e + part lands on the real or imaginary half of entry e)
+        if ((lane & 1) == 0) reinterpret_cast<double *>(&sh.wred[w][0])[lane >> 1] = ws;
       }
       __syncthreads();
       if (threadIdx.x < 16) {

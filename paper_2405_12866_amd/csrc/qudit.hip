@@ -106,6 +106,35 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_apply(const cx<R> *src, int64_t
   }
 }
 
+// Wave sums of NV values (NV = 16, 32 or 64; FP64) by recursive halving: at the exchange
+// with lane ^ MASK each lane keeps C of its 2C values (the upper ones when that lane bit is
+// set) and adds its partner's copy; the lane bits left over are summed plainly. Lane l
+// returns the wave sum of value l >> (6 - log2 NV).
+template <int C, int MASK, int NV>
+__device__ __forceinline__ void qhalve(double (&v)[NV], int lane) {
+  const bool hi = (lane & MASK) != 0;
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const double give = hi ? v[i] : v[C + i];
+    const double keep = hi ? v[C + i] : v[i];
+    v[i] = keep + __shfl_xor(give, MASK);
+  }
+}
+template <int NV>
+__device__ __forceinline__ double qwave_sum(double (&v)[NV]) {
+  static_assert(NV == 16 || NV == 32 || NV == 64, "16, 32 or 64 values");
+  const int lane = threadIdx.x & 63;
+  qhalve<NV / 2, 32>(v, lane);
+  qhalve<NV / 4, 16>(v, lane);
+  qhalve<NV / 8, 8>(v, lane);
+  qhalve<NV / 16, 4>(v, lane);
+  if constexpr (NV >= 32) qhalve<NV / 32, 2>(v, lane);
+  else v[0] += __shfl_xor(v[0], 2);
+  if constexpr (NV >= 64) qhalve<1, 1>(v, lane);
+  else v[0] += __shfl_xor(v[0], 1);
+  return v[0];
+}
+
 // Environment partials: block (row group xg, partial blk, start) accumulates rows
 // q = d xg + y (y < d) of Gamma[q][p] = sum a(q) conj(b(p)) over its items in FP64 and
 // writes them to partials[s][blk][q][p].
@@ -148,18 +177,26 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_s
       for (int p = 0; p < D; ++p) cfma_conj(acc[y][p], av[y], bv[p]);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  {
+    // the 2 d D reals (value 2 (y D + p) + part), padded with zeros to a power of two
+    constexpr int NR = 2 * d * D;
+    constexpr int NV = NR <= 16 ? 16 : (NR <= 32 ? 32 : 64);
+    static_assert(NR <= 64, "d <= 3");
+    double v[NV];
 #pragma unroll
-  for (int y = 0; y < d; ++y)
+    for (int y = 0; y < d; ++y)
 #pragma unroll
-    for (int p = 0; p < D; ++p) {
-      double re = acc[y][p].re, im = acc[y][p].im;
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        re += __shfl_xor(re, o);
-        im += __shfl_xor(im, o);
+      for (int p = 0; p < D; ++p) {
+        v[2 * (y * D + p)] = acc[y][p].re;
+        v[2 * (y * D + p) + 1] = acc[y][p].im;
       }
-      if (lane == 0) red[w][y * D + p] = cmake(re, im);
-    }
+#pragma unroll
+    for (int i = NR; i < NV; ++i) v[i] = 0.0;
+    const double ws = qwave_sum<NV>(v);
+    constexpr int SH = NV == 16 ? 2 : (NV == 32 ? 1 : 0);
+    const int idx = lane >> SH;
+    if ((lane & ((1 << SH) - 1)) == 0 && idx < NR) reinterpret_cast<double *>(&red[w][0])[idx] = ws;
+  }
   __syncthreads();
   if (threadIdx.x < d * D) {
     c128 t = red[0][threadIdx.x];
