@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -547,39 +548,63 @@ struct QdSweeper {
   c128 *vst = nullptr;  // [S][L][D][D] Jacobi warm start
   double beta = 0.0;
   int nslots = 0;
+  // second stream of the backward pass (default priority) and its fork/join events: the
+  // two halves of the running starts go on two streams, so one half's environment
+  // reduction and polar update overlap the other half's propagation and reduction
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+
+  QdSweeper() = default;
+  QdSweeper(const QdSweeper &) = delete;
+  QdSweeper &operator=(const QdSweeper &) = delete;
+  ~QdSweeper() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
 
   int D() const { return d * d; }
   int64_t set() const { return N * M; }
 
+  // (sl, ns, s: the starts a launch covers and its stream; the partial-sum block count
+  // P depends on the geometry only, and partials and gam are indexed by start, so
+  // launches over disjoint start sets never share them)
   template <int dd>
-  int apply_t(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows) {
+  int apply_t(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows,
+              const int32_t *sl, int ns, hipStream_t s) {
     const int qa = pairs[2 * k], qb = pairs[2 * k + 1];
     const QdGeom g = qd_geom(dd, n, Mrows, qa, qb);
-    hipLaunchKernelGGL((k_qd_apply<R, dd>), dim3(qd_grid(g.groups * Mrows), nslots), dim3(kQdBlock), 0, st, src, ss,
-                       dst, ds, g64, L * dd * dd * dd * dd, k, dagger ? 1 : 0, g, slots.as<int32_t>());
+    hipLaunchKernelGGL((k_qd_apply<R, dd>), dim3(qd_grid(g.groups * Mrows), ns), dim3(kQdBlock), 0, s, src, ss,
+                       dst, ds, g64, L * dd * dd * dd * dd, k, dagger ? 1 : 0, g, sl);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
+  }
+  int apply_on(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows,
+               const int32_t *sl, int ns, hipStream_t s) {
+    return d == 2 ? apply_t<2>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s)
+                  : apply_t<3>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s);
   }
   int apply(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows) {
-    return d == 2 ? apply_t<2>(src, ss, dst, ds, k, dagger, Mrows) : apply_t<3>(src, ss, dst, ds, k, dagger, Mrows);
+    return apply_on(src, ss, dst, ds, k, dagger, Mrows, slots.as<int32_t>(), nslots, st);
   }
   template <int dd>
-  int env_t(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k) {
+  int env_t(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k, const int32_t *sl, int ns,
+            hipStream_t s) {
     const QdGeom g = qd_geom(dd, n, M, pairs[2 * k], pairs[2 * k + 1]);
     const int P = (int)std::max<int64_t>(1, std::min<int64_t>(kQdMaxP, (g.groups * M + kQdBlock - 1) / kQdBlock));
-    hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * P, nslots), dim3(kQdBlock), 0, st, a, as, b, bs, g, P,
-                       partials.as<c128>(), slots.as<int32_t>());
+    hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * P, ns), dim3(kQdBlock), 0, s, a, as, b, bs, g, P,
+                       partials.as<c128>(), sl);
     QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_qd_envsum<dd>), dim3(nslots), dim3(kQdBlock), 0, st, partials.as<c128>(), P,
-                       slots.as<int32_t>(), beta, g64, L * dd * dd * dd * dd, k, gam.as<c128>());
+    hipLaunchKernelGGL((k_qd_envsum<dd>), dim3(ns), dim3(kQdBlock), 0, s, partials.as<c128>(), P, sl, beta, g64,
+                       L * dd * dd * dd * dd, k, gam.as<c128>());
     QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(nslots), dim3(64), 0, st, gam.as<c128>(), slots.as<int32_t>(), g64,
-                       vst, L * dd * dd * dd * dd, k);
+    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(ns), dim3(64), 0, s, gam.as<c128>(), sl, g64, vst,
+                       L * dd * dd * dd * dd, k);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   }
-  int env(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k) {
-    return d == 2 ? env_t<2>(a, as, b, bs, k) : env_t<3>(a, as, b, bs, k);
+  int env_on(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k, const int32_t *sl, int ns,
+             hipStream_t s) {
+    return d == 2 ? env_t<2>(a, as, b, bs, k, sl, ns, s) : env_t<3>(a, as, b, bs, k, sl, ns, s);
   }
   int dist(const cx<R> *x, int64_t xs, const cx<R> *ref, int64_t rs, int64_t count, int Mrows, double *out) {
     const int P = (int)std::min<int64_t>(kQdMaxP * 4, (count + kQdBlock - 1) / kQdBlock);
@@ -637,11 +662,36 @@ struct QdSweeper {
   int backward() {
     cx<R> *P0 = psi.as<cx<R>>(), *F = phi.as<cx<R>>(), *B = blist.as<cx<R>>(), *A = astate.as<cx<R>>();
     const int64_t sN = set(), bstride = sN * std::max(L - 1, 1);
+    static const bool split_ok = [] {
+      const char *e = std::getenv("QFS_BWD_SPLIT");  // 0: one stream for the backward pass
+      return !(e && std::atoi(e) == 0);
+    }();
+    const bool split = split_ok && nslots >= 2;
+    if (split && !side) {
+      QFS_TRY(pool_stream(2, &side));
+      QFS_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+      QFS_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    }
+    const int halves = split ? 2 : 1, h0 = split ? nslots / 2 : nslots;
+    const int32_t *hsl[2] = {slots.as<int32_t>(), slots.as<int32_t>() + h0};
+    const int hn[2] = {h0, nslots - h0};
+    hipStream_t hst[2] = {st, side};
+    if (split) {
+      QFS_HIP(hipEventRecord(fork, st));
+      QFS_HIP(hipStreamWaitEvent(side, fork, 0));
+    }
     for (int k = L - 1; k >= 0; --k) {
-      if (k < L - 1) QFS_TRY(apply(k == L - 2 ? F : A, k == L - 2 ? 0 : sN, A, sN, k + 1, true, M));
       const cx<R> *a = k == L - 1 ? F : A;
       const int64_t as = k == L - 1 ? 0 : sN;
-      QFS_TRY(env(a, as, k == 0 ? P0 : B + (k - 1) * sN, k == 0 ? 0 : bstride, k));
+      for (int h = 0; h < halves; ++h) {
+        if (k < L - 1)
+          QFS_TRY(apply_on(k == L - 2 ? F : A, k == L - 2 ? 0 : sN, A, sN, k + 1, true, M, hsl[h], hn[h], hst[h]));
+        QFS_TRY(env_on(a, as, k == 0 ? P0 : B + (k - 1) * sN, k == 0 ? 0 : bstride, k, hsl[h], hn[h], hst[h]));
+      }
+    }
+    if (split) {
+      QFS_HIP(hipEventRecord(join, side));
+      QFS_HIP(hipStreamWaitEvent(st, join, 0));
     }
     QFS_TRY(apply(L == 1 ? F : A, L == 1 ? 0 : sN, A, sN, 0, true, M));
     QFS_TRY(dist(A, sN, P0, 0, sN, M, costs.as<double>()));
