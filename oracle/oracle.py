@@ -81,7 +81,23 @@ class Trace(C.Structure):
         ("m", C.POINTER(C.c_int32)),
         ("c_train", C.POINTER(C.c_double)),
         ("c_val", C.POINTER(C.c_double)),
+        ("iter", C.POINTER(C.c_int32)),
+        ("event", C.POINTER(C.c_int32)),
+        ("dbl_capacity", C.c_int32),
+        ("dbl_count", C.c_int32),
+        ("dbl_rows", C.c_int32),
+        ("dbl_m_old", C.POINTER(C.c_int32)),
+        ("dbl_m_new", C.POINTER(C.c_int32)),
+        ("dbl_gates_before", C.c_void_p),
+        ("dbl_gates_after", C.c_void_p),
+        ("dbl_psi", C.c_void_p),
+        ("dbl_phi", C.c_void_p),
+        ("dbl_c_prev", C.POINTER(C.c_double)),
     ]
+
+
+# control decision recorded per trace row (trace["event"])
+EV_RUN, EV_SUCCESS, EV_OVERTRAINED, EV_NOT_GEN, EV_PLATEAU, EV_MAX_ITER = range(6)
 
 
 def default_params(**kw) -> dict:
@@ -315,14 +331,61 @@ def sweep(n, pairs, psi, phi, gates, beta=0.0, record=False, kinds=None, gamma_s
     return g, c
 
 
+def _int_ptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _dbl_ptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _make_trace(capacity, dbl_capacity, starts, L, gate_entries, n_amp):
+    """Trace buffers (numpy) and the ctypes struct pointing at them. Doubling records
+    hold every start's gates before/after, the training set (up to n_amp rows of n_amp
+    amplitudes) and the plateau reference of each start on the new set."""
+    bufs = dict(start=np.zeros(capacity, np.int32), sweep=np.zeros(capacity, np.int32),
+                m=np.zeros(capacity, np.int32), c_train=np.zeros(capacity),
+                c_val=np.zeros(capacity), iter=np.zeros(capacity, np.int32),
+                event=np.full(capacity, -1, np.int32))
+    dcap = max(int(dbl_capacity), 0)
+    dbl = dict(m_old=np.zeros(max(dcap, 1), np.int32), m_new=np.zeros(max(dcap, 1), np.int32),
+               gates_before=np.zeros((max(dcap, 1), starts, L, gate_entries), np.complex128),
+               gates_after=np.zeros((max(dcap, 1), starts, L, gate_entries), np.complex128),
+               psi=np.zeros((max(dcap, 1), n_amp, n_amp), np.complex128),
+               phi=np.zeros((max(dcap, 1), n_amp, n_amp), np.complex128),
+               c_prev=np.zeros((max(dcap, 1), starts)))
+    tr = Trace(capacity, 0, _int_ptr(bufs["start"]), _int_ptr(bufs["sweep"]), _int_ptr(bufs["m"]),
+               _dbl_ptr(bufs["c_train"]), _dbl_ptr(bufs["c_val"]), _int_ptr(bufs["iter"]),
+               _int_ptr(bufs["event"]), dcap, 0, n_amp, _int_ptr(dbl["m_old"]),
+               _int_ptr(dbl["m_new"]), dbl["gates_before"].ctypes.data,
+               dbl["gates_after"].ctypes.data, dbl["psi"].ctypes.data, dbl["phi"].ctypes.data,
+               _dbl_ptr(dbl["c_prev"]))
+    return tr, bufs, dbl
+
+
+def _read_trace(tr, bufs, dbl):
+    out = {key: v[:tr.count].copy() for key, v in bufs.items()}
+    k = tr.dbl_count
+    out["doublings"] = [
+        dict(m_old=int(dbl["m_old"][i]), m_new=int(dbl["m_new"][i]),
+             gates_before=dbl["gates_before"][i].copy(), gates_after=dbl["gates_after"][i].copy(),
+             psi=dbl["psi"][i, :dbl["m_new"][i]].copy(), phi=dbl["phi"][i, :dbl["m_new"][i]].copy(),
+             c_prev=dbl["c_prev"][i].copy())
+        for i in range(k)]
+    return out
+
+
 def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=None,
                 phi=None, n_val=0, params=None, gates_in=None, trace_capacity=0, kinds=None,
-                fixed=None):
+                fixed=None, doubling_capacity=0):
     """Full QFactor-Sample instantiation. Exactly one target form: dense ``U``, a target
     circuit (``target_pairs`` + ``target_gates``), or fixed samples ``psi``/``phi``
     whose last ``n_val`` rows are the validation set. ``kinds`` and ``fixed`` ([L][4][4],
     read for fixed gates) describe a template with one-qubit and constant gates.
-    Returns (gates, result dict)."""
+    With ``trace_capacity`` the result holds a per-sweep trace (costs, sweep index since
+    the last restart, control decision) and, with ``doubling_capacity``, a record of each
+    doubling (gates of every start before and after it, the new training set, the
+    plateau reference on it). Returns (gates, result dict)."""
     lib = load()
     pr = _pairs(pairs)
     L = pr.shape[0]
@@ -353,16 +416,9 @@ def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=N
     out = np.zeros((L, 4, 4), dtype=np.complex128)
     res = Result()
     tr = None
-    if trace_capacity:
-        bufs = dict(start=np.zeros(trace_capacity, np.int32), sweep=np.zeros(trace_capacity, np.int32),
-                    m=np.zeros(trace_capacity, np.int32), c_train=np.zeros(trace_capacity),
-                    c_val=np.zeros(trace_capacity))
-        tr = Trace(trace_capacity, 0,
-                   bufs["start"].ctypes.data_as(C.POINTER(C.c_int32)),
-                   bufs["sweep"].ctypes.data_as(C.POINTER(C.c_int32)),
-                   bufs["m"].ctypes.data_as(C.POINTER(C.c_int32)),
-                   bufs["c_train"].ctypes.data_as(C.POINTER(C.c_double)),
-                   bufs["c_val"].ctypes.data_as(C.POINTER(C.c_double)))
+    if trace_capacity or doubling_capacity:
+        tr, bufs, dbl = _make_trace(max(trace_capacity, 1), doubling_capacity, par.multistarts
+                                    if par.multistarts > 0 else 1, L, 16, 1 << n)
     rc = lib.qo_instantiate(n, L, _p(pr), _p(kd), _p(fx), kind, *args, C.byref(par), _p(gi), _p(out),
                             C.byref(res), C.byref(tr) if tr is not None else None)
     if rc != 0:
@@ -370,8 +426,7 @@ def instantiate(n, pairs, *, U=None, target_pairs=None, target_gates=None, psi=N
     info = {f: getattr(res, f) for f, _ in Result._fields_}
     info["reason_name"] = REASONS[res.reason]
     if tr is not None:
-        k = tr.count
-        info["trace"] = {key: v[:k].copy() for key, v in bufs.items()}
+        info["trace"] = _read_trace(tr, bufs, dbl)
     return out, info
 
 
@@ -457,5 +512,6 @@ __all__ = [
     "apply_gate", "apply_circuit", "dense_apply", "environment", "environment1", "svd4",
     "update_gate", "update_gate1", "qd_apply_gate", "qd_apply_circuit", "qd_environment",
     "qd_svd", "qd_update_gate", "qd_haar_gate", "qd_sweep", "qd_instantiate",
-    "state_distance", "sweep", "instantiate",
+    "state_distance", "sweep", "instantiate", "EV_RUN", "EV_SUCCESS", "EV_OVERTRAINED",
+    "EV_NOT_GEN", "EV_PLATEAU", "EV_MAX_ITER",
 ]

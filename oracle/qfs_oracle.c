@@ -892,14 +892,17 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
       if (status[s] != ST_RUNNING) continue;
       iter[s] += 1;
       total[s] += 1;
+      int t = -1;
       if (trace && trace->count < trace->capacity) {
-        int t = trace->count++;
+        t = trace->count++;
         trace->start[t] = s;
         trace->sweep[t] = (int32_t)total[s];
         trace->m[t] = M;
         trace->c_train[t] = c_tr[s];
         trace->c_val[t] = c_v[s];
+        if (trace->iter) trace->iter[t] = iter[s];
       }
+      int ev = QO_EV_RUN;
       /* App. A, Eq. 13: relative improvement test over consecutive iterations. */
       int improved = fabs(c_prev[s]) - fabs(c_tr[s]) > p->diff_tol_r * fabs(c_tr[s]);
       zcount[s] = improved ? 0 : zcount[s] + 1;
@@ -911,30 +914,25 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
         reason[s] = QO_SUCCESS;
         success[s] = 1;
         any_success = 1;
-        continue;
-      }
-      if (iter[s] >= p->min_iter && !gen_ok) {
-        if (M < m_cap) {
-          status[s] = ST_OVERTRAINED;
-          any_over = 1;
-          continue;
-        }
-        if (c_tr[s] < p->dist_tol) {
-          status[s] = ST_STOPPED;
-          reason[s] = QO_NOT_GENERALIZED;
-          continue;
-        }
-      }
-      if (iter[s] >= p->min_iter && zcount[s] >= p->plateau_window) {
+        ev = QO_EV_SUCCESS;
+      } else if (iter[s] >= p->min_iter && !gen_ok && M < m_cap) {
+        status[s] = ST_OVERTRAINED;
+        any_over = 1;
+        ev = QO_EV_OVERTRAINED;
+      } else if (iter[s] >= p->min_iter && !gen_ok && c_tr[s] < p->dist_tol) {
+        status[s] = ST_STOPPED;
+        reason[s] = QO_NOT_GENERALIZED;
+        ev = QO_EV_NOT_GEN;
+      } else if (iter[s] >= p->min_iter && zcount[s] >= p->plateau_window) {
         status[s] = ST_STOPPED;
         reason[s] = QO_PLATEAU;
-        continue;
-      }
-      if (total[s] >= p->max_iter) {
+        ev = QO_EV_PLATEAU;
+      } else if (total[s] >= p->max_iter) {
         status[s] = ST_STOPPED;
         reason[s] = QO_MAX_ITER;
-        continue;
+        ev = QO_EV_MAX_ITER;
       }
+      if (t >= 0 && trace->event) trace->event[t] = ev;
     }
     if (any_success) {
       double best = INFINITY;
@@ -948,6 +946,14 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
     if (any_over) {
       /* double-and-restart: extend the training set, keep every gate (App. A) */
       int M_new = 2 * M < m_cap ? 2 * M : m_cap;
+      const int rec = trace && trace->dbl_count < trace->dbl_capacity ? trace->dbl_count++ : -1;
+      const size_t all_gates = GS * (size_t)L * S;
+      if (rec >= 0) {
+        trace->dbl_m_old[rec] = M;
+        trace->dbl_m_new[rec] = M_new;
+        if (trace->dbl_gates_before)
+          memcpy(trace->dbl_gates_before + rec * all_gates, gates, sizeof(qo_cplx) * all_gates);
+      }
       if (target_kind == QO_TARGET_SAMPLES) {
         memcpy(psi, samples_psi, sizeof(qo_cplx) * (size_t)M_new * N);
         memcpy(phi, samples_phi, sizeof(qo_cplx) * (size_t)M_new * N);
@@ -973,6 +979,17 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
         iter[s] = 0;
         zcount[s] = 0;
         c_prev[s] = FWD_COST(M, psi, phi, gates + GS * (size_t)s * L);
+      }
+      if (rec >= 0) {
+        if (trace->dbl_gates_after)
+          memcpy(trace->dbl_gates_after + rec * all_gates, gates, sizeof(qo_cplx) * all_gates);
+        const int rows = M < trace->dbl_rows ? M : trace->dbl_rows;
+        const size_t stride = (size_t)trace->dbl_rows * N;
+        if (trace->dbl_psi) memcpy(trace->dbl_psi + rec * stride, psi, sizeof(qo_cplx) * (size_t)rows * N);
+        if (trace->dbl_phi) memcpy(trace->dbl_phi + rec * stride, phi, sizeof(qo_cplx) * (size_t)rows * N);
+        if (trace->dbl_c_prev)
+          for (int s = 0; s < S; ++s)
+            trace->dbl_c_prev[(size_t)rec * S + s] = status[s] == ST_STOPPED ? NAN : c_prev[s];
       }
       continue;
     }

@@ -83,7 +83,18 @@ typedef struct {
   double seconds;
 } qo_result;
 
-/* Optional per-sweep trace: one row per (start, sweep). */
+/* Control decision taken for a start after one of its sweeps (trace->event). */
+enum {
+  QO_EV_RUN = 0,         /* keeps running                                         */
+  QO_EV_SUCCESS = 1,     /* success relations of Sec. 3 hold                      */
+  QO_EV_OVERTRAINED = 2, /* generalisation test failed while M may still grow     */
+  QO_EV_NOT_GEN = 3,     /* generalisation test failed at the M cap below dist_tol */
+  QO_EV_PLATEAU = 4,
+  QO_EV_MAX_ITER = 5
+};
+
+/* Optional per-sweep trace: one row per (start, sweep). Every array except the first
+ * five may be NULL. */
 typedef struct {
   int32_t capacity;
   int32_t count;
@@ -92,6 +103,22 @@ typedef struct {
   int32_t *m;         /* [capacity] */
   double *c_train;    /* [capacity] */
   double *c_val;      /* [capacity] */
+  int32_t *iter;      /* [capacity] sweep index since the last restart (1-based)   */
+  int32_t *event;     /* [capacity] QO_EV_* decision taken after that sweep        */
+  /* Record of each double-and-restart (Sec. 3; App. A), up to dbl_capacity of them.
+   * gates: [dbl_capacity][multistarts][L][D*D] (D = d^2); states: [dbl_capacity]
+   * [dbl_rows][N] (the first min(M_new, dbl_rows) rows are written). */
+  int32_t dbl_capacity;
+  int32_t dbl_count;
+  int32_t dbl_rows;
+  int32_t *dbl_m_old;         /* [dbl_capacity] M before the doubling               */
+  int32_t *dbl_m_new;         /* [dbl_capacity] M after it                          */
+  qo_cplx *dbl_gates_before;  /* every start's gates when the doubling is decided   */
+  qo_cplx *dbl_gates_after;   /* every start's gates when the new set's sweeps begin */
+  qo_cplx *dbl_psi;           /* training states after the doubling                 */
+  qo_cplx *dbl_phi;           /* U psi of those states                              */
+  double *dbl_c_prev;         /* [dbl_capacity][multistarts] plateau reference c_0 on
+                                 the new set (NaN for a start that had stopped)     */
 } qo_trace;
 
 /* Counter-based generator Philox4x32-10 (Salmon et al., SC'11). */
