@@ -337,7 +337,9 @@ struct SweepShared {
   c128 pg[16], pv[16];
   double ps[4];
   double red[NW];
-  int flag;
+  int flag;   // control decision after a sweep
+  int pause;  // pause at the top of a sweep (a separate word: waves may still be reading
+              // flag from the previous sweep's decision when thread 0 writes this one)
 };
 
 // Jobs with at most kGatesInLds gates keep all their gates (state precision) in LDS for
@@ -379,6 +381,9 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
   auto forward = [&](double *c0) {
     load_states<R, NT>(bufB, P.psi, M, n);
     if (Mv > 0) load_states<R, NT>(bufA, P.psiv, Mv, n);
+    // the loads fill one element per thread while a gate reads groups of four written by
+    // other waves (and gate(k) returns without a barrier when the gates are resident)
+    __syncthreads();
     for (int k = 0; k < L; ++k) {
       const cx<R> *u = gate(k);
       const int pa = n - 1 - pairs[2 * k], pb = n - 1 - pairs[2 * k + 1];
@@ -392,8 +397,11 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
 
   const int Kmax = A.sweeps_per_launch;
   double c0 = 0.0;
-  double cval = forward(J.need_c0 ? &c0 : nullptr);
-  if (J.need_c0) {
+  // read once: thread 0 clears the flag below, and every wave must take the same branch
+  // to the barrier inside it
+  const bool need_c0 = J.need_c0 != 0;
+  double cval = forward(need_c0 ? &c0 : nullptr);
+  if (need_c0) {
     if (threadIdx.x == 0) {
       J.c_prev = c0;
       J.c_train = c0;
@@ -407,10 +415,10 @@ __device__ void run_job(const BatchArgs &A, int jid, cx<R> *bufA, cx<R> *bufB,
     if (threadIdx.x == 0) {
       const int ds = __hip_atomic_load(&P.done_sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int os = __hip_atomic_load(&P.over_sweep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      sh.flag = (!hp.independent && (J.total >= ds || J.total >= os)) ? 1 : 0;
+      sh.pause = (!hp.independent && (J.total >= ds || J.total >= os)) ? 1 : 0;
     }
     __syncthreads();
-    if (sh.flag) {
+    if (sh.pause) {
       if (threadIdx.x == 0) J.status = BJ_PAUSED;
       return;
     }

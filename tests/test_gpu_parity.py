@@ -319,17 +319,54 @@ def test_full_size_sweep_sampled_starts():
     assert np.all(c2 <= c_gpu + 1e-6 * np.maximum(c_gpu, 1e-3))
 
 
+def test_full_size_teacher_forced_all_starts():
+    """The parity contract at the bench's full size (12-qubit brickwork, 44 gates,
+    M = 256, 16 starts, complex64 states with FP64 environment sums, polar update and
+    cost): the bench's inputs (training states and initial gates drawn from its seed,
+    U psi of its target) and five sweeps of all 16 starts on the device, each one
+    teacher-forced: the oracle re-runs every start's sweep in FP64 from the device's
+    FP64 gates before that sweep, and |dc| <= 1e-6 max(c, c_init) for every start and
+    sweep. (qfs_sweep runs the sweep kernels of the bench's qfs_instantiate call.)"""
+    from concurrent.futures import ThreadPoolExecutor
+    import os
+    n, M, S, seed = 12, 256, 16, 0x5A17 + 3
+    w = I.workload_12q()
+    pairs = w["pairs"]
+    say("full size teacher-forced: drawing the bench's states and initial gates (oracle)")
+    psi = O.draw_states(n, M, seed=seed)
+    phi = O.apply_circuit(n, psi, pairs, w["target_gates"])
+    gates = np.stack([np.stack([O.haar_gate(seed, s, k) for k in range(len(pairs))]) for s in range(S)])
+    dpsi, dphi, dg = dev(psi), dev(phi), dev(gates)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    pool = ThreadPoolExecutor(max_workers=workers)
+    c_init = np.array(list(pool.map(
+        lambda s: O.state_distance(n, O.apply_circuit(n, psi, pairs, gates[s]), phi), range(S))))
+    for t in range(5):
+        before = host(dg)
+        say(f"full size teacher-forced: device sweep {t + 1} (16 starts)")
+        c_dev = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED)
+        say(f"full size teacher-forced: oracle sweep {t + 1} of 16 starts on {workers} threads")
+        c_ref = np.array(list(pool.map(lambda s: O.sweep(n, pairs, psi, phi, before[s])[1], range(S))))
+        bound = 1e-6 * np.maximum(c_ref, c_init)
+        ratio = np.abs(c_dev - c_ref) / bound
+        say(f"  sweep {t + 1}: c in [{c_ref.min():.6f}, {c_ref.max():.6f}], max |dc| "
+            f"{np.max(np.abs(c_dev - c_ref)):.2e}, max |dc| / bound {ratio.max():.3f}")
+        assert np.all(ratio <= 1.0), (t, ratio)
+    pool.shutdown()
+
+
 @pytest.mark.parametrize("precision", [Q.QFS_PREC_FP64, Q.QFS_PREC_MIXED])
 def test_full_size_instantiate_in_bench_configuration(precision):
     """The timed call of the benchmark, shortened to two sweeps: 12-qubit brickwork (44
     gates), M = 256 fixed, 16 starts, the two streams of the backward pass, sample sets and
     initial gates drawn on the device; the oracle runs the same call in FP64 from its own
-    draws (same seed). FP64 states: the same best start, c_train and c_val to 1e-10
-    relative. complex64 states (the bench's precision): 1e-4 relative; two free-running
-    sweeps far from the solution (c near 2, so f = M (1 - c/2) is about 5 while the
-    environment sums terms of total size about M = 256) amplify the FP32 rounding of the
-    partial sums about 50-fold. The best start must agree when the runner-up is not within
-    that tolerance of it."""
+    draws (same seed). FP64 states: parity, the same best start, c_train and c_val to
+    1e-10 relative. complex64 states (the bench's precision): not the parity contract
+    (that is checked teacher-forced above) but a bound on how far two free-running
+    sweeps drift apart: 1e-4 relative. Far from the solution (c near 2, so f = M (1 - c/2)
+    is about 5 while the environment sums terms of total size about M = 256) the FP32
+    rounding of the partial sums is amplified about 50-fold, and the two sweeps compound
+    it. The best start must agree when the runner-up is not within that tolerance."""
     say(f"full size: qfs_instantiate in the bench configuration (2 sweeps), precision={precision}")
     w = I.workload_12q()
     kw = dict(multistarts=16, m_init=256, fixed_m=1, seed=0x5A17 + 3, max_iter=2, diff_tol_r=0.0,

@@ -307,8 +307,8 @@ RECOVERY_TEMPLATES = [
 def test_recovery_three_qubits(pairs):
     """Pin P12: a target built from the template is recovered (d_full from the dense
     8x8 product below 1e-10) by the best of 16 starts, with the on-the-fly doubling
-    from M = 2. (The 6-gate linear template converges too, but its last decades take
-    thousands of sweeps; it is exercised by the GPU parity tests instead.)"""
+    from M = 2. (The 6-gate linear template of the 3-qubit workload is run by
+    tests/test_gpu_c1.py, on the device and by this oracle side by side.)"""
     g = np.random.default_rng(5)
     tg = I.haar_gates(len(pairs), g)
     p = O.default_params(dist_tol=1e-11, multistarts=16, seed=3, max_iter=3000, diff_tol_r=1e-7)
