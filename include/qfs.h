@@ -157,7 +157,20 @@ typedef struct {
                                 environment divided by the current M with the gate,
                                 polar((1 - beta) Gamma / M + beta u), so beta keeps
                                 its meaning as M changes; 0: the paper's form       */
+  int32_t backward_mode;     /* QFS_BWD_GROUPED (default): consecutive gates whose
+                                qubits fit in four share one pass over the backward
+                                state (Sec. 3 right-to-left update, Fig.
+                                env_calc_tensor): the pass reduces one 16 x 16
+                                second-moment matrix of the state entering the group
+                                and the forward state before it, and every gate's
+                                environment follows from it in order; the forward
+                                pass stores one B list entry per group.
+                                QFS_BWD_PER_GATE: one pass per gate. Both give the
+                                same gates to rounding; templates on fewer than 3
+                                qubits always take the per-gate passes.             */
 } qfs_params;
+
+enum { QFS_BWD_GROUPED = 0, QFS_BWD_PER_GATE = 1 };
 
 /* Termination reasons (the paper's run outcomes: success, distance not reached,
  * timeout). */
@@ -430,10 +443,12 @@ int qfs_polar_update(int32_t count, const qfs_c128 *gamma, double beta, qfs_c128
  *   psi, phi:  device [M][N] (training states and U psi).
  *   gates:     device [starts][L][4][4], updated in place (complex128 master).
  *   precision: QFS_PREC_FP64 or QFS_PREC_MIXED (complex64 states).
+ *   backward_mode: QFS_BWD_GROUPED or QFS_BWD_PER_GATE (as qfs_params.backward_mode).
  *   c_train:   host [starts]. */
 int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, int32_t M,
               const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates,
-              int32_t precision, double beta, double *c_train, void *hip_stream);
+              int32_t precision, double beta, int32_t backward_mode, double *c_train,
+              void *hip_stream);
 
 /* (1/M) sum_j ||x_j - y_j||^2 accumulated in FP64 (Sec. 3, Eq. 9). x, y: device
  * [M][N]; result: host. */

@@ -210,6 +210,14 @@ struct SweepCtx {
   // polar update overlap the other half's backward step.
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  // Grouped backward pass (group.hip): groups from the last gate down, the device mask
+  // of the B list entries they read, and the second-moment partials [S][kGPcap][256].
+  bool grouped = false;
+  const std::vector<GateGroup> *groups = nullptr;
+  const int32_t *bneed_dev = nullptr;
+  c128 *gpartials = nullptr;
+  int gpstride = 0;
+  c128 *vop = nullptr;  // [S][256]: the last finalized group's operator
 };
 
 template <typename R>
@@ -242,10 +250,15 @@ int sweep_forward(SweepCtx &c, bool with_c0) {
     QFS_TRY(T.begin(c.stream));
     QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
                                     with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
-                                    c.nslots, c.kinds_dev, c.stream));
-    // load Psi, store the B list entries some environment reads, read U Psi for c_0
-    int stored = c.L - 1;
-    for (int k = 1; c.kinds && k < c.L; ++k) stored -= c.kinds[k] == QFS_GATE_FIXED;
+                                    c.nslots, c.kinds_dev, c.stream, c.grouped ? c.bneed_dev : nullptr));
+    // load Psi, store the B list entries the backward pass reads, read U Psi for c_0
+    int stored = 0;
+    if (c.grouped) {
+      for (const GateGroup &gg : *c.groups) stored += gg.k_lo >= 1 && gg.nvar > 0;
+    } else {
+      stored = c.L - 1;
+      for (int k = 1; c.kinds && k < c.L; ++k) stored -= c.kinds[k] == QFS_GATE_FIXED;
+    }
     const double bytes = set_bytes<R>(c, c.g) * (1 + stored + (with_c0 ? 1 : 0)) +
                          (val ? 2.0 * set_bytes<R>(c, c.gv) : 0.0);
     QFS_TRY(T.end(c.stream, kClsForward, bytes));
@@ -292,12 +305,82 @@ int sweep_forward(SweepCtx &c, bool with_c0) {
   return QFS_OK;
 }
 
+// Right-to-left update with gate groups (Sec. 3; Fig. env_calc_tensor): for each group
+// from the last one down, one pass moves the backward state through the previous group's
+// just-updated gates and reduces the group's second-moment matrix against the B entry
+// before the group; the finalize updates the group's gates in order. Then the Eq. 9 cost
+// of the updated gates from a_0 = C^dagger U psi (the last group's gates applied on the
+// way). The halves of the starts run on two streams as in the per-gate pass.
+template <typename R>
+int sweep_backward_grouped(SweepCtx &c) {
+  const GateRef gr = gate_ref<R>(c);
+  cx<R> *psi = static_cast<cx<R> *>(c.psi), *phi = static_cast<cx<R> *>(c.phi);
+  cx<R> *B = static_cast<cx<R> *>(c.blist), *A = static_cast<cx<R> *>(c.astate);
+  const int64_t sN = c.g.elems();
+  const int64_t bstride = sN * std::max(c.L - 1, 1);
+  KernelTimer &T = *c.timer;
+  const bool split = !T.on && c.side && c.nslots >= 2 &&
+                     (int64_t)(c.nslots / 2) * c.g.elems() >= (int64_t(1) << 20);
+  const int halves = split ? 2 : 1;
+  const int h0 = split ? c.nslots / 2 : c.nslots;
+  const int32_t *hslots[2] = {c.slots, c.slots + h0};
+  const int hn[2] = {h0, c.nslots - h0};
+  hipStream_t hs[2] = {c.stream, c.side};
+  if (split) {
+    QFS_HIP(hipEventRecord(c.fork, c.stream));
+    QFS_HIP(hipStreamWaitEvent(c.side, c.fork, 0));
+  }
+  const std::vector<GateGroup> &G = *c.groups;
+  const double set = set_bytes<R>(c, c.g);
+  for (size_t gi = 0; gi < G.size(); ++gi) {
+    const GateGroup &cur = G[gi];
+    const GateGroup *prev = gi ? &G[gi - 1] : nullptr;
+    if (!prev && cur.nvar == 0) {  // nothing to reduce: only the group's operator
+      for (int h = 0; h < halves; ++h)
+        QFS_TRY(launch_group_finalize(0, c.gpartials, c.gpstride, hslots[h], hn[h], cur, c.pairs_host, c.kinds,
+                                      c.beta, c.g64, sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, c.vstore,
+                                      c.vop, hs[h]));
+      continue;
+    }
+    // the state entering group gi: U psi through groups 0 .. gi-1 (written from gi = 1 on)
+    const SBuf<R> a_in = gi <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
+    const SBuf<R> a_out = prev ? SBuf<R>{A, sN} : SBuf<R>{nullptr, 0};
+    const SBuf<R> b = cur.k_lo == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (cur.k_lo - 1) * sN, bstride};
+    const double moved = set * ((prev ? 2.0 : 1.0) + (cur.nvar > 0 ? 1.0 : 0.0));
+    for (int h = 0; h < halves; ++h) {
+      int P = 0;
+      QFS_TRY(T.begin(hs[h]));
+      QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, prev, &cur, false, c.vop, a_in, a_out, b, hslots[h],
+                                   hn[h], c.gpartials, c.gpstride, nullptr, &P, hs[h]));
+      QFS_TRY(T.end(hs[h], kClsStep, moved * hn[h] / c.nslots));
+      QFS_TRY(T.begin(hs[h]));
+      QFS_TRY(launch_group_finalize(cur.nvar > 0 ? P : 0, c.gpartials, c.gpstride, hslots[h], hn[h], cur,
+                                    c.pairs_host, c.kinds, c.beta, c.g64, sizeof(R) == 4 ? c.g32 : nullptr,
+                                    c.L * 16, c.vstore, c.vop, hs[h]));
+      QFS_TRY(T.end(hs[h], kClsPolar, (double)P * 4096.0 * hn[h]));
+    }
+  }
+  if (split) {
+    QFS_HIP(hipEventRecord(c.join, c.side));
+    QFS_HIP(hipStreamWaitEvent(c.stream, c.join, 0));
+  }
+  int P = 0;
+  QFS_TRY(T.begin(c.stream));
+  QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, &G.back(), nullptr, true, c.vop,
+                               G.size() <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN}, SBuf<R>{nullptr, 0},
+                               SBuf<R>{psi, 0}, c.slots, c.nslots, nullptr, kGPcap, c.dpart0, &P, c.stream));
+  QFS_TRY(T.end(c.stream, kClsDist, 2.0 * set));
+  QFS_TRY(launch_dist_finalize(P, c.dpart0, c.slots, c.nslots, c.g.M, c.costs, c.stream));
+  return QFS_OK;
+}
+
 // Right-to-left update (Sec. 3; Fig. env_calc_tensor): for k = L-1 .. 0 the backward
 // state is moved through the just-updated gate k+1, the environment of gate k is
 // reduced against B_k, and gate k is replaced by its polar factor. Then the Eq. 9
 // cost of the updated gates from a_0 = C^dagger U psi.
 template <typename R>
 int sweep_backward(SweepCtx &c) {
+  if (c.grouped) return sweep_backward_grouped<R>(c);
   const GateRef gr = gate_ref<R>(c);
   cx<R> *psi = static_cast<cx<R> *>(c.psi), *phi = static_cast<cx<R> *>(c.phi);
   cx<R> *B = static_cast<cx<R> *>(c.blist), *A = static_cast<cx<R> *>(c.astate);
@@ -459,6 +542,9 @@ class Group {
   DevBuf blist_, astate_, vstate_;
   DevBuf g64_, g32_, vstore_, pairs_dev_, kinds_dev_;
   DevBuf partials_, dpart_, costs_, slots_, work_;
+  std::vector<GateGroup> groups_;  // grouped backward pass (backward_mode GROUPED)
+  DevBuf bneed_dev_, gpartials_, vop_;
+  int gpstride_ = 0;
   double *h_costs_ = nullptr;  // pinned [3 S]: c_train, c_val, c_0
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   KernelTimer timer_;
@@ -561,6 +647,33 @@ int Group::setup_working() {
   c.g = Geometry{n_, (int32_t)N_, logC, (M_ + C - 1) / C, M_};
   c.gv = Geometry{n_, (int32_t)N_, logC, std::max(1, (Mv_ + C - 1) / C), Mv_};
   c.fused = fused;
+  c.grouped = p_.backward_mode == QFS_BWD_GROUPED && group_path_supported(c.g, rb);
+  if (c.grouped) {
+    // the partials grow with the chunk count (M); reallocated only when a larger stride is needed
+    const int stride = group_partials_stride(c.g, rb);
+    if (stride > gpstride_) {
+      QFS_TRY(arena_.alloc(gpartials_, sizeof(c128) * 256 * (size_t)stride * S_));
+      gpstride_ = stride;
+    }
+    if (!vop_.ptr) QFS_TRY(arena_.alloc(vop_, sizeof(c128) * 256 * (size_t)S_));
+    if (!bneed_dev_.ptr) {
+      std::vector<int32_t> need(L_, 0);
+      for (const GateGroup &gg : groups_)
+        if (gg.k_lo >= 1 && gg.nvar > 0) need[gg.k_lo] = 1;
+      QFS_TRY(arena_.alloc(bneed_dev_, sizeof(int32_t) * (size_t)L_));
+      QFS_HIP(hipMemcpyAsync(bneed_dev_.ptr, need.data(), sizeof(int32_t) * L_, hipMemcpyHostToDevice,
+                             stream_));
+    }
+  }
+  if (!c.grouped && !partials_.ptr) {  // environment partials of the per-gate pass
+    QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)kPcap * S_));
+    c.partials = partials_.as<c128>();
+  }
+  c.gpstride = gpstride_;
+  c.vop = vop_.as<c128>();
+  c.groups = &groups_;
+  c.bneed_dev = bneed_dev_.as<int32_t>();
+  c.gpartials = gpartials_.as<c128>();
   const size_t set = (size_t)c.g.elems() * cb, vset = (size_t)c.gv.elems() * cb;
   QFS_TRY(arena_.alloc(psiw_, set));
   QFS_TRY(arena_.alloc(phiw_, set));
@@ -677,7 +790,6 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_costs_), sizeof(double) * 3 * S_));
   QFS_HIP(hipEventCreate(&ev0_));
   QFS_HIP(hipEventCreate(&ev1_));
-  QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)kPcap * S_));
   QFS_TRY(arena_.alloc(dpart_, sizeof(double) * 2 * (size_t)kPcap * S_));
   QFS_TRY(arena_.alloc(costs_, sizeof(double) * 3 * S_));
   QFS_TRY(arena_.alloc(slots_, sizeof(int32_t) * S_));
@@ -728,6 +840,7 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_TRY(arena_.alloc(vstore_, sizeof(c128) * 16 * (size_t)L_ * S_));
   QFS_TRY(launch_identity4((int64_t)L_ * S_, vstore_.as<c128>(), stream_));
 
+  groups_ = plan_gate_groups(L_, pairs_.data(), kinds_.empty() ? nullptr : kinds_.data());
   SweepCtx &c = ctx_;
   c.kinds = kinds_.empty() ? nullptr : kinds_.data();
   c.kinds_dev = kinds_.empty() ? nullptr : kinds_dev_.as<int32_t>();
@@ -1048,6 +1161,7 @@ void qfs_default_params(qfs_params *p) {
   p->graphs = 0;
   p->full_unitary = 0;
   p->beta_normalized = 0;
+  p->backward_mode = QFS_BWD_GROUPED;
 }
 
 int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
@@ -1064,7 +1178,8 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
       !(p.dist_tol >= 0) || !(p.diff_tol_r >= 0) || !(p.overtrain_ratio >= 0) || !(p.beta >= 0) ||
       !(p.beta <= 1) || (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) ||
       p.m_val < 0 || p.m_val > N || (p.full_unitary != 0 && p.full_unitary != 1) ||
-      (p.beta_normalized != 0 && p.beta_normalized != 1)) {
+      (p.beta_normalized != 0 && p.beta_normalized != 1) ||
+      (p.backward_mode != QFS_BWD_GROUPED && p.backward_mode != QFS_BWD_PER_GATE)) {
     set_error_detail("params out of range");
     return QFS_EINVAL;
   }
@@ -1284,7 +1399,8 @@ int qfs_state_distance(int32_t n, int32_t M, const qfs_c128 *x, const qfs_c128 *
 
 int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, int32_t M,
               const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates,
-              int32_t precision, double beta, double *c_train, void *hip_stream) {
+              int32_t precision, double beta, int32_t backward_mode, double *c_train,
+              void *hip_stream) {
   // constant gates are the gates' own entries here: validate the kinds without them
   std::vector<int32_t> kv;
   if (kinds) {
@@ -1295,7 +1411,8 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
   qfs_template t{n, L, pairs, kinds ? kv.data() : nullptr, nullptr};
   QFS_TRY(validate_template(&t));
   if (M < 1 || (int64_t)M > (int64_t(1) << n) || starts < 1 || !psi || !phi || !gates || !c_train ||
-      (precision != QFS_PREC_FP64 && precision != QFS_PREC_MIXED) || !(beta >= 0 && beta <= 1))
+      (precision != QFS_PREC_FP64 && precision != QFS_PREC_MIXED) || !(beta >= 0 && beta <= 1) ||
+      (backward_mode != QFS_BWD_GROUPED && backward_mode != QFS_BWD_PER_GATE))
     return QFS_EINVAL;
   hipStream_t s = as_stream(hip_stream);
   const bool f32 = precision == QFS_PREC_MIXED;
@@ -1360,6 +1477,24 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
   c.dpart0 = dpart.as<double>();
   c.dpart1 = dpart.as<double>() + (size_t)kPcap * starts;
   c.costs = costs.as<double>();
+  std::vector<GateGroup> groups;
+  DevBuf gpart, bneed, vopb;
+  c.grouped = backward_mode == QFS_BWD_GROUPED && group_path_supported(c.g, rb);
+  if (c.grouped) {
+    groups = plan_gate_groups(L, pairs, kinds);
+    std::vector<int32_t> need(L, 0);
+    for (const GateGroup &gg : groups)
+      if (gg.k_lo >= 1 && gg.nvar > 0) need[gg.k_lo] = 1;
+    c.gpstride = group_partials_stride(c.g, rb);
+    QFS_TRY(gpart.alloc(sizeof(c128) * 256 * (size_t)c.gpstride * starts));
+    QFS_TRY(vopb.alloc(sizeof(c128) * 256 * (size_t)starts));
+    c.vop = vopb.as<c128>();
+    QFS_TRY(bneed.alloc(sizeof(int32_t) * L));
+    QFS_HIP(hipMemcpyAsync(bneed.ptr, need.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, s));
+    c.groups = &groups;
+    c.bneed_dev = bneed.as<int32_t>();
+    c.gpartials = gpart.as<c128>();
+  }
   if (f32) {
     QFS_TRY(sweep_forward<float>(c, false));
     QFS_TRY(sweep_backward<float>(c));

@@ -1,0 +1,683 @@
+// Grouped backward pass of QFactor-Sample (Sec. 3; Fig. env_calc_tensor; Fig. pre-comp).
+//
+// The right-to-left update visits the gates one at a time: gate k's environment
+//   Gamma_k[q][p] = sum_j sum_r a_k,j(q, r) conj(B_k,j(p, r))
+// pairs the backward state a_k (every later gate already updated) with the forward state
+// B_k (the gates before k, as they were before the sweep), and u_k <- polar(Gamma_k) must be
+// known before a_{k-1} = u_k^dag a_k exists. A pass per gate therefore reads and writes the
+// whole backward state once per gate.
+//
+// Here consecutive gates whose qubits fit in four slots form a group k_lo .. k_hi and share
+// one pass. The pass reduces the 16 x 16 second-moment matrix
+//   G[z][y] = sum_j sum_r a_{k_hi},j(z, r) conj(B_{k_lo},j(y, r))
+// (z, y: the values of the four slots; r: every other amplitude bit). Every environment of
+// the group follows from G exactly: inside the group the backward state is
+// a_k = V_k a_{k_hi} with V_k the daggers of the group's already-updated gates above k, and
+// the forward state is B_k = W_k B_{k_lo} with W_k the group's pre-sweep gates below k, so
+//   H_k = V_k G W_k^dag,   Gamma_k[q][p] = sum_s H_k[(q, s)][(p, s)],
+//   H_{k-1} = u_k^dag H_k u_{k-1}   (u_k updated, u_{k-1} as before the sweep),
+// the partial trace running over the two slots outside gate k. The state thus makes one
+// round trip per group instead of one per gate, and the forward pass stores one B entry
+// per group. G is a (16 x K)(K x 16)^H product with K = M 2^(n-4) per start: it runs on the
+// matrix cores (16x16x4 MFMA; FP32 products for complex64 states, FP64 for complex128), over
+// tiles of the state staged in LDS. The 16 x 16 algebra and the polar updates run in FP64 in
+// one work-group per start.
+//
+// Tiles: a tile is a set of nT bits of the chunk-local element index (see the chunked layout
+// in qfs_internal.h) that contains the packet bits, the qubits of the gates applied in the
+// pass and the four slots, filled with the lowest remaining bits so that every tile read is
+// a run of whole 128-byte lines. A work-group loads a tile of the state and the same tile of
+// the B entry into LDS, applies the previous group's updated gates (u^dag, in order) in LDS,
+// writes the state back, and feeds the MFMA from LDS.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
+#include "polar2.h"
+#include "polar4.h"
+#include "qfs_internal.h"
+#include "stream_common.h"
+
+namespace qfs {
+
+namespace {
+
+constexpr int kGBlock = 256;
+constexpr int kGWaves = kGBlock / 64;
+constexpr int kMaxBits = 28;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 matrix-core product per precision: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator entry v of lane l is D[row(l, v)][l % 16].
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using acc_t = f32x4;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct Mfma<double> {
+  using acc_t = f64x4;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+template <typename R>
+struct GroupArgs {
+  const cx<R> *a_in;     // backward state (or U psi), nullptr: none
+  int64_t a_in_stride;
+  cx<R> *a_out;          // updated state, nullptr: not stored
+  int64_t a_out_stride;
+  const cx<R> *b;        // forward state B_{k_lo} (or psi in the distance mode)
+  int64_t b_stride;
+  const c128 *vop;       // [S][256]: the previous group's operator (16 x 16 over its four
+                         // slots, the u^dag of its gates in order), nullptr: none
+  c128 *partials;        // [S][pstride][256]: second-moment block partials
+  double *dpartials;     // [S][P]: distance block partials
+  const int32_t *slot_to_start;
+  int32_t pstride;       // blocks per start in the partials (>= gridDim.x)
+  int32_t n, logC;
+  int32_t nT;            // tile bits of the chunk-local index (packet bits included)
+  int32_t nX;            // chunk-local bits outside the tile
+  int32_t nch;
+  int32_t lowP;          // packet bits of the tile that sit at their own position
+  int32_t tpos[kMaxBits];  // chunk-local position of tile bit i (ascending)
+  int32_t xpos[kMaxBits];  // chunk-local positions outside the tile (ascending)
+  int32_t apos[4];         // tile packet-bit positions of the operator's four slots
+  int32_t cpos[kMaxBits];  // the other tile packet bits (ascending): the operator's columns
+  int32_t env;             // reduce the second-moment matrix
+  int32_t zpos[4];         // tile packet-bit positions of the four slots of the reduction
+  int32_t nK;              // packet bits of the reduction index
+  int32_t kpos[kMaxBits];  // their tile packet-bit positions (ascending)
+  int32_t dist;            // distance mode: sum |a - b|^2 after the operator
+};
+
+__device__ __forceinline__ uint32_t spread_bits(uint32_t x, const int32_t *pos, int nb) {
+  uint32_t r = 0;
+  for (int i = 0; i < nb; ++i) r |= ((x >> i) & 1u) << pos[i];
+  return r;
+}
+
+__device__ __forceinline__ int lds_slot16(uint32_t pk) { return (int)(pk + (pk >> 4)); }
+
+template <typename R>
+__device__ __forceinline__ Pk<R> lds_pk(const float4 *lds, uint32_t pk) {
+  const float4 x = lds[lds_slot16(pk)];
+  return *reinterpret_cast<const Pk<R> *>(&x);
+}
+
+// One complex element (sample e of packet pk) of a staged tile.
+__device__ __forceinline__ c64 lds_elem(const float4 *lds, uint32_t pk, int e, float) {
+  const float2 x = reinterpret_cast<const float2 *>(lds)[2 * lds_slot16(pk) + e];
+  return cmake(x.x, x.y);
+}
+__device__ __forceinline__ c128 lds_elem(const float4 *lds, uint32_t pk, int, double) {
+  const double2 x = reinterpret_cast<const double2 *>(lds)[lds_slot16(pk)];
+  return cmake(x.x, x.y);
+}
+__device__ __forceinline__ void lds_elem_put(float4 *lds, uint32_t pk, int e, c64 v) {
+  reinterpret_cast<float2 *>(lds)[2 * lds_slot16(pk) + e] = make_float2(v.re, v.im);
+}
+__device__ __forceinline__ void lds_elem_put(float4 *lds, uint32_t pk, int, c128 v) {
+  reinterpret_cast<double2 *>(lds)[lds_slot16(pk)] = make_double2(v.re, v.im);
+}
+
+// Packets per thread and set of one tile (tiles of at most 2048 packets).
+constexpr int kMaxPkt = 8;
+
+template <typename R>
+__global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
+  constexpr int V = Pk<R>::V, LOGV = Pk<R>::LOGV;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc_t;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int nP = A.nT - LOGV;
+  const uint32_t npk = 1u << nP;
+  const uint32_t nslot = npk + (npk >> 4);
+  float4 *la = reinterpret_cast<float4 *>(lds_raw);
+  float4 *lb = la + nslot;
+
+  const int s = A.slot_to_start[blockIdx.y];
+  const int P = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const cx<R> *a_in = A.a_in ? A.a_in + A.a_in_stride * s : nullptr;
+  cx<R> *a_out = A.a_out ? A.a_out + A.a_out_stride * s : nullptr;
+  const cx<R> *bsrc = A.b + A.b_stride * s;
+  const int n = A.n, logC = A.logC, nX = A.nX;
+
+  // chunk-local element offset of packet tid + 256 u of a tile: the bits are disjoint, so
+  // the offset of the thread's bits and of u's bits are ORed
+  const uint32_t lowmask = (1u << A.lowP) - 1u;
+  const int nhi = nP - A.lowP;
+  const int32_t *hipos = A.tpos + LOGV + A.lowP;
+  auto elem_off = [&](uint32_t pk) __attribute__((always_inline)) -> uint32_t {
+    return ((pk & lowmask) << LOGV) | spread_bits(pk >> A.lowP, hipos, nhi);
+  };
+  uint32_t eo[kMaxPkt];
+  const uint32_t eo_t = elem_off((uint32_t)tid & (npk - 1u));
+#pragma unroll
+  for (int u = 0; u < kMaxPkt; ++u) eo[u] = eo_t | elem_off(((uint32_t)u * kGBlock) & (npk - 1u));
+
+  // the previous group's operator as the A operand of the apply: V[l % 16][4 t + l / 16]
+  const bool apply = A.vop != nullptr;
+  R vre[4], vim[4], vnim[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) vre[t] = vim[t] = vnim[t] = R(0);
+  uint32_t rd_off[4], wr_off[4];
+  const int ncb = nP - 4;
+  const uint32_t ncols = (1u << ncb) << LOGV;
+  const uint32_t nblk = ncols >= 16 ? ncols >> 4 : 1u;
+  if (apply) {
+    const c128 *vs = A.vop + (int64_t)s * 256;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const c128 x = vs[(lane & 15) * 16 + 4 * t + (lane >> 4)];
+      vre[t] = (R)x.re;
+      vim[t] = (R)x.im;
+      vnim[t] = -(R)x.im;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rr = 4 * t + (lane >> 4), rw = MF::row(lane, t);
+      rd_off[t] = wr_off[t] = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        rd_off[t] |= (uint32_t)((rr >> i) & 1) << A.apos[i];
+        wr_off[t] |= (uint32_t)((rw >> i) & 1) << A.apos[i];
+      }
+    }
+  }
+
+  // reduction lanes: slot index z = lane % 16 (rows of A, columns of B), K quad lane kk
+  const int zl = lane & 15, kk = lane >> 4;
+  uint32_t zoff = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) zoff |= (uint32_t)((zl >> i) & 1) << A.zpos[i];
+  const int nK = A.nK;
+  uint32_t kkoff = 0;
+  if (nK >= 1) kkoff |= (uint32_t)(kk & 1) << A.kpos[0];
+  if (nK >= 2) kkoff |= (uint32_t)((kk >> 1) & 1) << A.kpos[1];
+  const bool kk_ok = kk < (1 << min(nK, 2));
+  const uint32_t nkq = nK >= 2 ? 1u << (nK - 2) : 1u;
+  double gre[4] = {0.0, 0.0, 0.0, 0.0}, gim[4] = {0.0, 0.0, 0.0, 0.0};
+  double dacc = 0.0;
+
+  const uint32_t tiles = (uint32_t)A.nch << nX;
+  auto tile_base = [&](uint32_t t) __attribute__((always_inline)) -> int64_t {
+    const uint32_t q = t >> nX, e = t & ((1u << nX) - 1u);
+    return ((int64_t)q << (n + logC)) + spread_bits(e, A.xpos, nX);
+  };
+  // the next tile's packets are loaded into registers while the current tile is worked on
+  // (packets beyond a small tile re-read packet tid: every load is unconditional, so the
+  // registers are never partly written)
+  const int npt = npk >= kGBlock ? (int)(npk / kGBlock) : 1;
+#pragma unroll
+  for (int u = 0; u < kMaxPkt; ++u)
+    if (u >= npt || (uint32_t)(tid + u * kGBlock) >= npk) eo[u] = eo_t;
+  const cx<R> *a_rd = a_in ? a_in : bsrc;
+  // (native vectors: HIP's float4 struct is copied through memcpy, which keeps an array
+  // of it out of registers)
+  f32x4 ra[kMaxPkt], rb[kMaxPkt];
+  auto fetch = [&](uint32_t t) __attribute__((always_inline)) {
+    const int64_t base = tile_base(t);
+#pragma unroll
+    for (int u = 0; u < kMaxPkt; ++u) {
+      ra[u] = *reinterpret_cast<const f32x4 *>(a_rd + base + eo[u]);
+      rb[u] = *reinterpret_cast<const f32x4 *>(bsrc + base + eo[u]);
+    }
+  };
+  uint32_t tau = blockIdx.x;
+  if (tau < tiles) fetch(tau);
+  for (; tau < tiles; tau += P) {
+    const int64_t base = tile_base(tau);
+#pragma unroll
+    for (int u = 0; u < kMaxPkt; ++u) {
+      const uint32_t pk = tid + u * kGBlock;
+      if (pk < npk) {
+        if (a_in) reinterpret_cast<f32x4 *>(la)[lds_slot16(pk)] = ra[u];
+        reinterpret_cast<f32x4 *>(lb)[lds_slot16(pk)] = rb[u];
+      }
+    }
+    __syncthreads();
+    if (tau + P < tiles) fetch(tau + P);
+    if (apply) {
+      // a <- V a on the operator's slots: (16 x 16) x (16 x 16-column block) products on the
+      // matrix cores, each wave on its own column blocks, results written back in place
+      for (uint32_t blk = wv; blk < nblk; blk += kGWaves) {
+        const uint32_t j = blk * 16 + (lane & 15);
+        const bool ok = j < ncols;
+        const int e = (int)(j & (V - 1));
+        const uint32_t cofs = spread_bits(j >> LOGV, A.cpos, ncb);
+        acc_t dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          cx<R> x = cmake<R>(0, 0);
+          if (ok) x = lds_elem(la, rd_off[t] | cofs, e, R(0));
+          dre = MF::mma(vre[t], x.re, dre);
+          dre = MF::mma(vnim[t], x.im, dre);
+          dim = MF::mma(vre[t], x.im, dim);
+          dim = MF::mma(vim[t], x.re, dim);
+        }
+        if (ok) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) lds_elem_put(la, wr_off[v] | cofs, e, cmake<R>(dre[v], dim[v]));
+        }
+      }
+      __syncthreads();
+    }
+    if (a_out) {
+#pragma unroll
+      for (int u = 0; u < kMaxPkt; ++u) {
+        const uint32_t pk = tid + u * kGBlock;
+        if (pk < npk) *reinterpret_cast<float4 *>(a_out + base + eo[u]) = la[lds_slot16(pk)];
+      }
+    }
+    if (A.env) {
+      acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ir = {0, 0, 0, 0}, ri = {0, 0, 0, 0};
+      for (uint32_t j = wv; j < nkq; j += kGWaves) {
+        const uint32_t pk = zoff | kkoff | (nK > 2 ? spread_bits(j, A.kpos + 2, nK - 2) : 0u);
+        Pk<R> av, bv;
+        if (kk_ok) {
+          av = lds_pk<R>(la, pk);
+          bv = lds_pk<R>(lb, pk);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) av.v[v] = bv.v[v] = cmake<R>(0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          rr = MF::mma(av.v[v].re, bv.v[v].re, rr);
+          ii = MF::mma(av.v[v].im, bv.v[v].im, ii);
+          ir = MF::mma(av.v[v].im, bv.v[v].re, ir);
+          ri = MF::mma(av.v[v].re, bv.v[v].im, ri);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        gre[v] += (double)rr[v] + (double)ii[v];
+        gim[v] += (double)ir[v] - (double)ri[v];
+      }
+    }
+    if (A.dist) {
+#pragma unroll
+      for (int u = 0; u < kMaxPkt; ++u) {
+        const uint32_t pk = tid + u * kGBlock;
+        if (pk < npk) {
+          const Pk<R> x = lds_pk<R>(la, pk), y = lds_pk<R>(lb, pk);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const R dr = x.v[v].re - y.v[v].re, di = x.v[v].im - y.v[v].im;
+            dacc += (double)dr * (double)dr + (double)di * (double)di;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (A.env) {
+    // wave matrices -> block partial, summed over the waves in order in FP64
+    double2 *red = reinterpret_cast<double2 *>(lds_raw);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv * 256 + MF::row(lane, v) * 16 + zl] = make_double2(gre[v], gim[v]);
+    __syncthreads();
+    double2 acc = red[tid];
+#pragma unroll
+    for (int w = 1; w < kGWaves; ++w) {
+      acc.x += red[w * 256 + tid].x;
+      acc.y += red[w * 256 + tid].y;
+    }
+    A.partials[((int64_t)s * A.pstride + blockIdx.x) * 256 + tid] = cmake(acc.x, acc.y);
+  }
+  if (A.dist) {
+    __shared__ double dred[kGWaves];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dacc += __shfl_xor(dacc, o);
+    if (lane == 0) dred[wv] = dacc;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = dred[0];
+      for (int w = 1; w < kGWaves; ++w) sum += dred[w];
+      A.dpartials[(int64_t)s * P + blockIdx.x] = sum;
+    }
+  }
+}
+
+struct GroupFin {
+  int32_t k_hi, k_lo, nvar;
+  int32_t sa[kGroupMaxGates], sb[kGroupMaxGates];  // slots of gate k_lo + i's qubits
+  int32_t kind[kGroupMaxGates];
+};
+
+// Per start: fixed-order FP64 sum of the block partials of G, then the group's gates from
+// the top down: Gamma_k by partial trace of H_k, u_k <- polar((1 - beta) Gamma_k + beta u_k)
+// (one wave; one-qubit slots by the closed-form 2x2 update), H_{k-1} = u_k^dag H_k u_{k-1}.
+// Also the group's operator Vop = u_{k_lo}^dag ... u_{k_hi}^dag over its four slots (the
+// updated gates), which the next pass applies to the backward state.
+__global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, int P, int pstride,
+                                                        const int32_t *slot_to_start, GroupFin F,
+                                                        double beta, c128 *g64, c64 *g32,
+                                                        int32_t gstride, c128 *vstore, c128 *vop) {
+  __shared__ c128 H[256], Vm[256];
+  __shared__ c128 gam[16], ug[16];
+  __shared__ c128 pg[16], pv[16];
+  __shared__ double psig[4];
+  const int s = slot_to_start[blockIdx.x];
+  const int t = threadIdx.x;
+  const int z = t >> 4, y = t & 15;
+  if (F.nvar > 0) {
+    const c128 *src = partials + (int64_t)s * pstride * 256 + t;
+    c128 acc[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
+    int p = 0;
+    for (; p + 3 < P; p += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = acc[u] + src[(int64_t)(p + u) * 256];
+    }
+    if (p < P) acc[0] = acc[0] + src[(int64_t)p * 256];
+    if (p + 1 < P) acc[1] = acc[1] + src[(int64_t)(p + 1) * 256];
+    if (p + 2 < P) acc[2] = acc[2] + src[(int64_t)(p + 2) * 256];
+    H[t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+  Vm[t] = cmake(z == y ? 1.0 : 0.0, 0.0);
+  c128 *gs = g64 + (int64_t)s * gstride;
+  auto load_u = [&](int k) {
+    __syncthreads();
+    if (t < 16) ug[t] = gs[k * 16 + t];
+    __syncthreads();
+  };
+  // X <- X op(u) with u on slots (a, b) of the column index; op(u) = u^dag or u
+  auto right = [&](c128 *X, int a, int b, bool dag) {
+    const int ly = 2 * ((y >> a) & 1) + ((y >> b) & 1);
+    const int yb = y & ~((1 << a) | (1 << b));
+    c128 v = cmake(0.0, 0.0);
+#pragma unroll
+    for (int p2 = 0; p2 < 4; ++p2) {
+      const int yy = yb | ((p2 >> 1) << a) | ((p2 & 1) << b);
+      const c128 m = dag ? cconj(ug[ly * 4 + p2]) : ug[p2 * 4 + ly];
+      cfma(v, X[z * 16 + yy], m);
+    }
+    __syncthreads();
+    X[t] = v;
+    __syncthreads();
+  };
+  // X <- u^dag X with u on slots (a, b) of the row index
+  auto left_dag = [&](c128 *X, int a, int b) {
+    const int lz = 2 * ((z >> a) & 1) + ((z >> b) & 1);
+    const int zb = z & ~((1 << a) | (1 << b));
+    c128 v = cmake(0.0, 0.0);
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2) {
+      const int zz = zb | ((q2 >> 1) << a) | ((q2 & 1) << b);
+      cfma(v, cconj(ug[q2 * 4 + lz]), X[zz * 16 + y]);
+    }
+    __syncthreads();
+    X[t] = v;
+    __syncthreads();
+  };
+  __syncthreads();
+  // H_{k_hi} = G W^dag, W = u_{k_hi - 1} ... u_{k_lo} (pre-sweep gates)
+  if (F.nvar > 0)
+    for (int k = F.k_lo; k < F.k_hi; ++k) {
+      load_u(k);
+      right(H, F.sa[k - F.k_lo], F.sb[k - F.k_lo], true);
+    }
+  for (int k = F.k_hi; k >= F.k_lo; --k) {
+    const int i = k - F.k_lo;
+    const int a = F.sa[i], b = F.sb[i];
+    if (F.kind[i] != QFS_GATE_FIXED) {
+      if (t < 16) {
+        // Gamma[q][p] = sum over the two other slots o0 < o1 of H[(q, o)][(p, o)]
+        const int om = 15 & ~((1 << a) | (1 << b));
+        const int o0 = __ffs(om) - 1, o1 = __ffs(om & (om - 1)) - 1;
+        const int qq = t >> 2, pp = t & 3;
+        const int zq = ((qq >> 1) << a) | ((qq & 1) << b), zp = ((pp >> 1) << a) | ((pp & 1) << b);
+        c128 g = cmake(0.0, 0.0);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const int zo = ((s2 >> 1) << o0) | ((s2 & 1) << o1);
+          g = g + H[(zq | zo) * 16 + (zp | zo)];
+        }
+        gam[t] = g;
+        ug[t] = gs[k * 16 + t];
+      }
+      __syncthreads();
+      if (t < 64) {
+        if (F.kind[i] == QFS_GATE_1Q) {
+          if (t == 0) polar2_update<float>(gam, beta, ug, nullptr);
+        } else {
+          polar4_wave(gam, beta, gs + k * 16, ug, nullptr, pg, pv, psig,
+                      vstore ? vstore + (int64_t)s * gstride + k * 16 : nullptr);
+        }
+      }
+      __syncthreads();
+      if (t < 16) {
+        gs[k * 16 + t] = ug[t];
+        if (g32) g32[(int64_t)s * gstride + k * 16 + t] = cmake<float>((float)ug[t].re, (float)ug[t].im);
+      }
+    } else {
+      load_u(k);
+    }
+    left_dag(Vm, a, b);
+    if (F.nvar > 0) {
+      left_dag(H, a, b);
+      if (k > F.k_lo) {
+        load_u(k - 1);
+        right(H, F.sa[i - 1], F.sb[i - 1], false);
+      }
+    }
+  }
+  vop[(int64_t)s * 256 + t] = Vm[t];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+std::vector<GateGroup> plan_gate_groups(int L, const int32_t *pairs, const int32_t *kinds) {
+  std::vector<GateGroup> out;
+  int k = L - 1;
+  while (k >= 0) {
+    GateGroup gg{};
+    gg.k_hi = k;
+    gg.nq = 0;
+    gg.nvar = 0;
+    auto slot_of = [&](int q) {
+      for (int i = 0; i < gg.nq; ++i)
+        if (gg.q[i] == q) return i;
+      return -1;
+    };
+    while (k >= 0 && gg.k_hi - k < kGroupMaxGates) {
+      const int a = pairs[2 * k], b = pairs[2 * k + 1];
+      const int need = (slot_of(a) < 0) + (slot_of(b) < 0);
+      if (gg.nq + need > 4) break;
+      if (slot_of(a) < 0) gg.q[gg.nq++] = a;
+      if (slot_of(b) < 0) gg.q[gg.nq++] = b;
+      if (!(kinds && kinds[k] == QFS_GATE_FIXED)) ++gg.nvar;
+      --k;
+    }
+    gg.k_lo = k + 1;
+    out.push_back(gg);
+  }
+  return out;
+}
+
+bool group_path_supported(const Geometry &g, size_t rbytes) {
+  const int logV = rbytes == 4 ? 1 : 0;
+  return g.n >= 3 && g.n + g.logC - logV >= 4 && g.n + g.logC <= 24;
+}
+
+static int tile_bits_for(size_t rbytes) {
+  static const int tb = [] {
+    const char *e = std::getenv("QFS_GROUP_TILE_BITS");  // tuning aid (complex64 value)
+    return e ? std::atoi(e) : 12;
+  }();
+  return rbytes == 4 ? tb : tb - 1;
+}
+
+static int target_blocks() {
+  static const int tb = [] {
+    const char *e = std::getenv("QFS_GROUP_BLOCKS");  // tuning aid: work-groups per pass
+    return e ? std::max(1, std::atoi(e)) : 512;
+  }();
+  return tb;
+}
+
+int group_partials_stride(const Geometry &g, size_t rbytes) {
+  const int logV = rbytes == 4 ? 1 : 0;
+  const int nC = g.n + g.logC;
+  // every pass's tile has at least min(nC, tile bits) bits, so at most this many tiles
+  const int nT = std::max(std::min(nC, tile_bits_for(rbytes)), logV + 4);
+  const int64_t tiles = (int64_t)g.nch << std::max(0, nC - nT);
+  return (int)std::max<int64_t>(1, std::min<int64_t>({tiles, (int64_t)kGPcap, (int64_t)target_blocks()}));
+}
+
+template <typename R>
+int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *prev,
+                      const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
+                      SBuf<R> b, const int32_t *slot_to_start, int nslots, c128 *gpartials,
+                      int pstride, double *dpartials, int *P_out, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  constexpr int LOGV = Pk<R>::LOGV;
+  const int nC = g.n + g.logC;
+  GroupArgs<R> A;
+  std::memset(&A, 0, sizeof(A));
+  A.a_in = a_in.base;
+  A.a_in_stride = a_in.stride;
+  A.a_out = a_out.base;
+  A.a_out_stride = a_out.stride;
+  A.b = b.base;
+  A.b_stride = b.stride;
+  A.vop = prev ? vop : nullptr;
+  A.partials = gpartials;
+  A.dpartials = dpartials;
+  A.slot_to_start = slot_to_start;
+  A.pstride = pstride;
+  A.n = g.n;
+  A.logC = g.logC;
+  A.nch = g.nch;
+  auto qpos = [&](int qubit) { return g.logC + (g.n - 1 - qubit); };
+  // tile: packet bits, the previous group's qubits, the slots' qubits, then the lowest others
+  bool in_t[kMaxBits] = {};
+  for (int i = 0; i < LOGV; ++i) in_t[i] = true;
+  if (prev)
+    for (int i = 0; i < prev->nq; ++i) in_t[qpos(prev->q[i])] = true;
+  if (cur && !dist)
+    for (int i = 0; i < cur->nq; ++i) in_t[qpos(cur->q[i])] = true;
+  int nT = 0;
+  for (int p = 0; p < nC; ++p) nT += in_t[p];
+  const int want = std::max(std::min(nC, tile_bits_for(sizeof(R))), LOGV + 4);
+  for (int p = 0; p < nC && nT < want; ++p)
+    if (!in_t[p]) {
+      in_t[p] = true;
+      ++nT;
+    }
+  if (nT - LOGV < 4 || nT - LOGV > 11) {
+    set_error_detail("grouped backward pass: tile geometry out of range");
+    return QFS_EUNSUPPORTED;
+  }
+  int tix[kMaxBits];  // tile bit index of a chunk-local position (-1: outside)
+  A.nT = 0;
+  A.nX = 0;
+  for (int p = 0; p < nC; ++p) {
+    if (in_t[p]) {
+      tix[p] = A.nT;
+      A.tpos[A.nT++] = p;
+    } else {
+      tix[p] = -1;
+      A.xpos[A.nX++] = p;
+    }
+  }
+  A.lowP = 0;
+  while (A.lowP < A.nT - LOGV && A.tpos[LOGV + A.lowP] == LOGV + A.lowP) ++A.lowP;
+  auto ppos = [&](int qubit) { return tix[qpos(qubit)] - LOGV; };  // tile packet-bit position
+  const int nP = A.nT - LOGV;
+  // four slots over the given qubits, completed with the lowest other packet bits
+  auto slots4 = [&](const GateGroup &gg, int32_t (&pos)[4], bool (&used)[kMaxBits]) {
+    for (int i = 0; i < gg.nq; ++i) {
+      pos[i] = ppos(gg.q[i]);
+      used[pos[i]] = true;
+    }
+    for (int i = gg.nq, p = 0; i < 4; ++i) {
+      while (used[p]) ++p;
+      pos[i] = p;
+      used[p] = true;
+    }
+  };
+  if (prev) {
+    bool used[kMaxBits] = {};
+    slots4(*prev, A.apos, used);
+    for (int p = 0, c = 0; p < nP; ++p)
+      if (!used[p]) A.cpos[c++] = p;
+  }
+  A.dist = dist ? 1 : 0;
+  A.env = (!dist && cur && cur->nvar > 0) ? 1 : 0;
+  if (A.env) {
+    bool used[kMaxBits] = {};
+    slots4(*cur, A.zpos, used);
+    A.nK = 0;
+    for (int p = 0; p < nP; ++p)
+      if (!used[p]) A.kpos[A.nK++] = p;
+  }
+  const uint32_t npk = 1u << (A.nT - LOGV);
+  const size_t lds = std::max<size_t>(2 * (size_t)(npk + (npk >> 4)) * 16, (size_t)kGWaves * 256 * 16);
+  static size_t attr[2] = {0, 0};
+  size_t &ab = attr[sizeof(R) == 4 ? 0 : 1];
+  if (lds > 64 * 1024 && lds > ab) {
+    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_bwd_group<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    ab = lds;
+  }
+  const int64_t tiles = (int64_t)g.nch << A.nX;
+  const int P = (int)std::min<int64_t>({tiles, (int64_t)std::max(1, pstride),
+                                         std::max<int64_t>(1, target_blocks() / std::max(1, nslots))});
+  *P_out = P;
+  hipLaunchKernelGGL(k_bwd_group<R>, dim3(P, nslots), dim3(kGBlock), lds, s, A);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32_t *slot_to_start,
+                          int nslots,
+                          const GateGroup &cur, const int32_t *pairs, const int32_t *kinds,
+                          double beta, c128 *g64, c64 *g32, int32_t gstride, c128 *vstore,
+                          c128 *vop, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  GroupFin F;
+  std::memset(&F, 0, sizeof(F));
+  F.k_hi = cur.k_hi;
+  F.k_lo = cur.k_lo;
+  F.nvar = cur.nvar;
+  auto slot = [&](int q) {
+    for (int i = 0; i < cur.nq; ++i)
+      if (cur.q[i] == q) return i;
+    return -1;
+  };
+  for (int k = cur.k_lo; k <= cur.k_hi; ++k) {
+    F.sa[k - cur.k_lo] = slot(pairs[2 * k]);
+    F.sb[k - cur.k_lo] = slot(pairs[2 * k + 1]);
+    F.kind[k - cur.k_lo] = kinds ? kinds[k] : QFS_GATE_2Q;
+  }
+  hipLaunchKernelGGL(k_group_finalize, dim3(nslots), dim3(256), 0, s, gpartials, P, pstride, slot_to_start, F,
+                     beta, g64, g32, gstride, vstore, vop);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
+#define QFS_GINST(R)                                                                          \
+  template int launch_group_pass<R>(const Geometry &, const int32_t *, const GateGroup *,      \
+                                    const GateGroup *, bool, const c128 *, SBuf<R>, SBuf<R>,   \
+                                    SBuf<R>, const int32_t *, int, c128 *, int, double *,      \
+                                    int *,                                                     \
+                                    hipStream_t);
+QFS_GINST(float)
+QFS_GINST(double)
+#undef QFS_GINST
+
+}  // namespace qfs

@@ -1,0 +1,215 @@
+// FP64 4x4 unitary polar factor on one wave, shared by the per-gate and the grouped
+// backward passes (sweep.hip, group.hip).
+#pragma once
+
+#include "qfs_internal.h"
+
+namespace qfs {
+
+// ------------------------------------------------------------------ FP64 4x4 polar
+// One-sided (Hestenes) Jacobi on one wave: lane l = 4c + r (of each 16-lane group)
+// holds column c, row r of the working matrix G and of V. Each round rotates the two
+// disjoint column pairs c <-> c ^ (m >> 2), m in {4, 8, 12}; the pair's Gram entries
+// are summed over the four rows of a quad, so both columns' lanes compute bitwise
+// equal rotations. Then W = normalised columns of G (re-orthonormalised and completed
+// when a singular value is negligible) and u = W V^dagger.
+//
+// Warm start (vstore != nullptr): Jacobi starts from G V_prev and V_prev, the right
+// singular vectors this gate had after its previous update (the environment changes
+// little between sweeps), so it converges in one or two sweeps instead of ~6. V_prev is
+// first made unitary to rounding by one Newton-Schulz step V (3I - V^dag V) / 2, so no
+// error accumulates across sweeps; the new V is stored back.
+__device__ __forceinline__ c128 shfl_c(c128 x, int src) {
+  return cmake(__shfl(x.re, src), __shfl(x.im, src));
+}
+__device__ __forceinline__ c128 quad_sum(c128 x) {
+  x.re += __shfl_xor(x.re, 1);
+  x.im += __shfl_xor(x.im, 1);
+  x.re += __shfl_xor(x.re, 2);
+  x.im += __shfl_xor(x.im, 2);
+  return x;
+}
+
+__device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
+                            c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s,
+                            c128 *vstore = nullptr) {
+  const int lane = threadIdx.x & 63;
+  const int l = lane & 15, c = l >> 2, r = l & 3, base = lane & ~15;
+  auto gm = [&](int row, int col) {
+    c128 x = G[row * 4 + col];
+    if (beta != 0.0) {
+      const c128 up = u_prev[row * 4 + col];
+      x = cmake((1.0 - beta) * x.re + beta * up.re, (1.0 - beta) * x.im + beta * up.im);
+    }
+    return x;
+  };
+  c128 g, v;
+  if (vstore) {
+    // lane 4c + r holds X[r][c]; Y[a][c] = sum_k conj(X[k][a]) X[k][c] (quad c);
+    // Z[r][c] = (3 X[r][c] - sum_a X[r][a] Y[a][c]) / 2
+    const c128 x = vstore[r * 4 + c];
+    c128 acc = cmake(0.0, 0.0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const c128 xca = shfl_c(x, base + 4 * a + r);  // X[r][a]
+      const c128 yac = quad_sum(cconj(xca) * x);     // Y[a][c]
+      cfma(acc, xca, yac);
+    }
+    v = cmake(0.5 * (3.0 * x.re - acc.re), 0.5 * (3.0 * x.im - acc.im));
+    g = cmake(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cfma(g, gm(r, k), shfl_c(v, base + 4 * c + k));  // (G V)[r][c]
+  } else {
+    g = gm(r, c);
+    v = cmake(r == c ? 1.0 : 0.0, 0.0);
+  }
+  bool converged = false;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    int rotated = 0;
+#pragma unroll
+    for (int m = 4; m <= 12; m += 4) {
+      const c128 go = cmake(__shfl_xor(g.re, m), __shfl_xor(g.im, m));
+      const c128 vo = cmake(__shfl_xor(v.re, m), __shfl_xor(v.im, m));
+      const bool is_p = (l ^ m) > l;
+      const c128 gp = is_p ? g : go, gq = is_p ? go : g;
+      const c128 vp = is_p ? v : vo, vq = is_p ? vo : v;
+      double al = cabs2(gp), be = cabs2(gq);
+      double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) * gq
+      double gi = gp.re * gq.im - gp.im * gq.re;
+#pragma unroll
+      for (int o = 1; o <= 2; o <<= 1) {
+        al += __shfl_xor(al, o);
+        be += __shfl_xor(be, o);
+        gr += __shfl_xor(gr, o);
+        gi += __shfl_xor(gi, o);
+      }
+      const double ag = sqrt(gr * gr + gi * gi);
+      if (ag > 0.0 && ag > 1e-15 * sqrt(al * be)) {
+        rotated = 1;
+        const c128 ec = cmake(gr / ag, -gi / ag);  // conj(e^{i phi})
+        const double tau = (be - al) / (2.0 * ag);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+        const c128 egq = ec * gq, evq = ec * vq;
+        if (is_p) {
+          g = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+          v = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+        } else {
+          g = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+          v = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+        }
+      }
+    }
+    if (!__any(rotated)) {
+      converged = true;
+      break;
+    }
+  }
+  double s2 = cabs2(g);
+  s2 += __shfl_xor(s2, 1);
+  s2 += __shfl_xor(s2, 2);
+  const double sig = sqrt(s2);
+  double smin = sig, smax = sig;
+  smin = fmin(smin, __shfl_xor(smin, 4));
+  smin = fmin(smin, __shfl_xor(smin, 8));
+  smax = fmax(smax, __shfl_xor(smax, 4));
+  smax = fmax(smax, __shfl_xor(smax, 8));
+  if (converged && smin > 1e-200 && smin > 1e-15 * smax) {
+    // W = G diag(1/sigma) is unitary to the Jacobi tolerance; u = W V^dagger with
+    // lane 4q + p computing u[q][p] = sum_k W[q][k] conj(V[p][k]); W[q][k] and V[p][k]
+    // live on lanes 4k + q and 4k + p.
+    const c128 w = cscale(g, 1.0 / sig);
+    const int q = l >> 2, p = l & 3, base = lane & ~15;
+    c128 acc = cmake(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int lw = base + 4 * k + q, lv = base + 4 * k + p;
+      const c128 wk = cmake(__shfl(w.re, lw), __shfl(w.im, lw));
+      const c128 vk = cmake(__shfl(v.re, lv), __shfl(v.im, lv));
+      cfma_conj(acc, wk, vk);
+    }
+    if (lane < 16) {
+      out64[l] = acc;
+      if (out32) out32[l] = cmake<float>((float)acc.re, (float)acc.im);
+      if (vstore) vstore[r * 4 + c] = v;
+    }
+    return;
+  }
+  // Rank-deficient (or unconverged) case: lane 0 orders the columns by singular value,
+  // re-orthonormalises them and completes W with unit vectors where sigma vanishes.
+  if (lane < 16) {
+    lds_g[c * 4 + r] = g;
+    lds_v[c * 4 + r] = v;
+    if (r == 0) lds_s[c] = sig;
+    if (vstore) vstore[r * 4 + c] = v;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    int ord[4] = {0, 1, 2, 3};
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (lds_s[ord[b]] > lds_s[ord[a]]) {
+          const int tmp = ord[a];
+          ord[a] = ord[b];
+          ord[b] = tmp;
+        }
+    const double sm = lds_s[ord[0]];
+    c128 w[4][4];  // [k][row]
+    for (int k = 0; k < 4; ++k) {
+      const int cc = ord[k];
+      const double sk = lds_s[cc];
+      c128 x[4];
+      bool ok = sk > 0.0 && sk > 1e-13 * sm;
+      if (ok) {
+        for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(lds_g[cc * 4 + rr], 1.0 / sk);
+        for (int rep = 0; rep < 2; ++rep)
+          for (int o = 0; o < k; ++o) {
+            c128 d = cmake(0.0, 0.0);
+            for (int rr = 0; rr < 4; ++rr) cfma(d, cconj(w[o][rr]), x[rr]);
+            for (int rr = 0; rr < 4; ++rr) x[rr] = x[rr] - d * w[o][rr];
+          }
+        double nn = 0.0;
+        for (int rr = 0; rr < 4; ++rr) nn += cabs2(x[rr]);
+        nn = sqrt(nn);
+        if (nn > 0.5)
+          for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(x[rr], 1.0 / nn);
+        else
+          ok = false;
+      }
+      if (!ok) {  // complete with the unit vector of largest orthogonal remainder
+        double best = -1.0;
+        c128 bx[4];
+        for (int e = 0; e < 4; ++e) {
+          c128 y[4];
+          for (int rr = 0; rr < 4; ++rr) y[rr] = cmake(rr == e ? 1.0 : 0.0, 0.0);
+          for (int rep = 0; rep < 2; ++rep)
+            for (int o = 0; o < k; ++o) {
+              c128 d = cmake(0.0, 0.0);
+              for (int rr = 0; rr < 4; ++rr) cfma(d, cconj(w[o][rr]), y[rr]);
+              for (int rr = 0; rr < 4; ++rr) y[rr] = y[rr] - d * w[o][rr];
+            }
+          double nn = 0.0;
+          for (int rr = 0; rr < 4; ++rr) nn += cabs2(y[rr]);
+          if (nn > best) {
+            best = nn;
+            for (int rr = 0; rr < 4; ++rr) bx[rr] = y[rr];
+          }
+        }
+        const double inv = 1.0 / sqrt(best);
+        for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(bx[rr], inv);
+      }
+      for (int rr = 0; rr < 4; ++rr) w[k][rr] = x[rr];
+    }
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < 4; ++p) {
+        c128 acc = cmake(0.0, 0.0);
+        for (int k = 0; k < 4; ++k) cfma_conj(acc, w[k][q], lds_v[ord[k] * 4 + p]);
+        out64[q * 4 + p] = acc;
+        if (out32) out32[q * 4 + p] = cmake<float>((float)acc.re, (float)acc.im);
+      }
+  }
+}
+
+
+}  // namespace qfs

@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/qfs.h"
 
@@ -263,13 +264,15 @@ int launch_apply(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef 
 // partials [S][g.nch]); optionally the validation set through all L gates with its
 // distance partials [S][gv->nch]. pairs_dev: device [L][2]. kinds_dev: device [L] gate
 // kinds or nullptr; the B list entry before a constant gate is not stored (no environment
-// reads it).
+// reads it). bneed_dev: device [L], when given B_j is stored iff bneed_dev[j] != 0 (the
+// grouped backward pass reads one entry per group).
 template <typename R>
 int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *pairs_dev, int L,
                          GateRef gates, const cx<R> *psi, cx<R> *blist, int64_t bstride,
                          const cx<R> *phi_ref, double *c0_partials, const cx<R> *psiv,
                          const cx<R> *phiv, double *val_partials, const int32_t *slot_to_start,
-                         int nslots, const int32_t *kinds_dev, hipStream_t s);
+                         int nslots, const int32_t *kinds_dev, hipStream_t s,
+                         const int32_t *bneed_dev = nullptr);
 
 template <typename R>
 int launch_pack(const Geometry &g, int64_t ld, const c128 *master, cx<R> *dst, hipStream_t s);
@@ -306,5 +309,43 @@ int launch_dist_finalize(int P, const double *partials, const int32_t *slot_to_s
 
 // Batched polar update on device (count problems).
 int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipStream_t s);
+
+// ------------------------------------------------------------------ grouped backward pass
+// Consecutive gates whose qubits fit in four slots share one pass over the backward state
+// (group.hip): the pass reduces a 16 x 16 second-moment matrix of the state entering the
+// group and the forward state before it, and a finalize kernel derives every environment
+// of the group from it and updates the gates in order.
+constexpr int kGroupMaxGates = 16;
+// Most blocks per start of a grouped pass (second-moment partials [S][stride][256] c128,
+// stride = group_partials_stride(g) <= kGPcap).
+constexpr int kGPcap = 512;
+struct GateGroup {
+  int32_t k_hi, k_lo;  // gates k_lo .. k_hi
+  int32_t nq;          // distinct qubits of the group (<= 4)
+  int32_t q[4];        // those qubits: slots 0 .. nq-1 of the second-moment index
+  int32_t nvar;        // variable (updated) gates in the group
+};
+// Groups from the last gate down, each as long as its qubits fit in four (fewest groups).
+std::vector<GateGroup> plan_gate_groups(int L, const int32_t *pairs, const int32_t *kinds);
+bool group_path_supported(const Geometry &g, size_t rbytes);
+// Blocks per start any grouped pass over geometry g uses at most (the partials' stride).
+int group_partials_stride(const Geometry &g, size_t rbytes);
+// One pass: a_in <- Vop a_in with prev's operator (vop [S][256], from prev's finalize; when
+// prev), stored to a_out (when given), then either the second-moment block partials of cur
+// against b (gpartials) or, with dist, the block partials of sum |a - b|^2 ([S][P] in
+// dpartials). P returned.
+template <typename R>
+int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *prev,
+                      const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
+                      SBuf<R> b, const int32_t *slot_to_start, int nslots, c128 *gpartials,
+                      int pstride, double *dpartials, int *P_out, hipStream_t s);
+// Per start: sum the P partials in a fixed order and update cur's variable gates from the top
+// down (both gate copies, warm-start vectors as launch_env_finalize); then write cur's
+// operator Vop = u_{k_lo}^dag ... u_{k_hi}^dag over its four slots to vop [S][256].
+int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32_t *slot_to_start,
+                          int nslots,
+                          const GateGroup &cur, const int32_t *pairs, const int32_t *kinds,
+                          double beta, c128 *g64, c64 *g32, int32_t gstride, c128 *vstore,
+                          c128 *vop, hipStream_t s);
 
 }  // namespace qfs

@@ -20,6 +20,8 @@
 #include <type_traits>
 
 #include "polar2.h"
+#include "polar4.h"
+#include "stream_common.h"
 #include "qfs_internal.h"
 
 namespace qfs {
@@ -29,51 +31,6 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kFwdBlock = 512;
-
-template <typename R>
-struct Pk;  // 16-byte packet of samples
-template <>
-struct Pk<float> {
-  static constexpr int V = 2;
-  static constexpr int LOGV = 1;
-  c64 v[2];
-};
-template <>
-struct Pk<double> {
-  static constexpr int V = 1;
-  static constexpr int LOGV = 0;
-  c128 v[1];
-};
-
-__device__ __forceinline__ Pk<float> ld_pk(const c64 *p) {
-  const float4 x = *reinterpret_cast<const float4 *>(p);
-  Pk<float> r;
-  r.v[0] = cmake(x.x, x.y);
-  r.v[1] = cmake(x.z, x.w);
-  return r;
-}
-__device__ __forceinline__ Pk<double> ld_pk(const c128 *p) {
-  const double2 x = *reinterpret_cast<const double2 *>(p);
-  Pk<double> r;
-  r.v[0] = cmake(x.x, x.y);
-  return r;
-}
-__device__ __forceinline__ void st_pk(c64 *p, const Pk<float> &r) {
-  *reinterpret_cast<float4 *>(p) = make_float4(r.v[0].re, r.v[0].im, r.v[1].re, r.v[1].im);
-}
-__device__ __forceinline__ void st_pk(c128 *p, const Pk<double> &r) {
-  *reinterpret_cast<double2 *>(p) = make_double2(r.v[0].re, r.v[0].im);
-}
-
-// Insert a zero bit at each of the t ascending positions.
-__device__ __forceinline__ uint32_t deposit(uint32_t r, const int *sorted_pos, int t) {
-  for (int m = 0; m < t; ++m) {
-    const int p = sorted_pos[m];
-    const uint32_t low = r & ((1u << p) - 1u);
-    r = ((r >> p) << (p + 1)) | low;
-  }
-  return r;
-}
 
 template <typename R>
 __device__ __forceinline__ R wave_sum(R x) {
@@ -150,28 +107,6 @@ __device__ __forceinline__ void split_item(uint32_t it, const ChunkGeom &cg, uin
   q = rest >> cg.logG;
 }
 
-// Read-only kernel inputs through the constant address space: uniform loads from it are
-// scalar loads (counted by lgkmcnt), so reading the next gate never waits for the vector
-// stores still in flight, however the surrounding code looks to alias analysis.
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-template <typename T>
-__device__ __forceinline__ cptr<T> as_const(const T *p) {
-  return (cptr<T>)p;
-}
-
-template <typename R, typename P>
-__device__ __forceinline__ void load_gate(P src, cx<R> (&u)[16], bool dagger) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int i = dagger ? p * 4 + q : q * 4 + p;
-      const cx<R> x = cmake<R>(src[i].re, src[i].im);  // (also from the constant address space)
-      u[q * 4 + p] = dagger ? cconj(x) : x;
-    }
-}
-
 // u^dag of gate k_apply, or u_{k_apply}^dag u_{k_apply2}^dag when a second gate on the same
 // two qubits goes first (a constant gate's backward step folded into the next one); the
 // second gate is taken into the first one's local basis (indices 1 and 2 exchanged when
@@ -203,211 +138,6 @@ __device__ __forceinline__ void load_step_gate(const cx<R> *g, int k_apply, int 
     }
 #pragma unroll
   for (int e = 0; e < 16; ++e) ud[e] = m[e];
-}
-
-// ------------------------------------------------------------------ FP64 4x4 polar
-// One-sided (Hestenes) Jacobi on one wave: lane l = 4c + r (of each 16-lane group)
-// holds column c, row r of the working matrix G and of V. Each round rotates the two
-// disjoint column pairs c <-> c ^ (m >> 2), m in {4, 8, 12}; the pair's Gram entries
-// are summed over the four rows of a quad, so both columns' lanes compute bitwise
-// equal rotations. Then W = normalised columns of G (re-orthonormalised and completed
-// when a singular value is negligible) and u = W V^dagger.
-//
-// Warm start (vstore != nullptr): Jacobi starts from G V_prev and V_prev, the right
-// singular vectors this gate had after its previous update (the environment changes
-// little between sweeps), so it converges in one or two sweeps instead of ~6. V_prev is
-// first made unitary to rounding by one Newton-Schulz step V (3I - V^dag V) / 2, so no
-// error accumulates across sweeps; the new V is stored back.
-__device__ __forceinline__ c128 shfl_c(c128 x, int src) {
-  return cmake(__shfl(x.re, src), __shfl(x.im, src));
-}
-__device__ __forceinline__ c128 quad_sum(c128 x) {
-  x.re += __shfl_xor(x.re, 1);
-  x.im += __shfl_xor(x.im, 1);
-  x.re += __shfl_xor(x.re, 2);
-  x.im += __shfl_xor(x.im, 2);
-  return x;
-}
-
-__device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
-                            c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s,
-                            c128 *vstore = nullptr) {
-  const int lane = threadIdx.x & 63;
-  const int l = lane & 15, c = l >> 2, r = l & 3, base = lane & ~15;
-  auto gm = [&](int row, int col) {
-    c128 x = G[row * 4 + col];
-    if (beta != 0.0) {
-      const c128 up = u_prev[row * 4 + col];
-      x = cmake((1.0 - beta) * x.re + beta * up.re, (1.0 - beta) * x.im + beta * up.im);
-    }
-    return x;
-  };
-  c128 g, v;
-  if (vstore) {
-    // lane 4c + r holds X[r][c]; Y[a][c] = sum_k conj(X[k][a]) X[k][c] (quad c);
-    // Z[r][c] = (3 X[r][c] - sum_a X[r][a] Y[a][c]) / 2
-    const c128 x = vstore[r * 4 + c];
-    c128 acc = cmake(0.0, 0.0);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const c128 xca = shfl_c(x, base + 4 * a + r);  // X[r][a]
-      const c128 yac = quad_sum(cconj(xca) * x);     // Y[a][c]
-      cfma(acc, xca, yac);
-    }
-    v = cmake(0.5 * (3.0 * x.re - acc.re), 0.5 * (3.0 * x.im - acc.im));
-    g = cmake(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cfma(g, gm(r, k), shfl_c(v, base + 4 * c + k));  // (G V)[r][c]
-  } else {
-    g = gm(r, c);
-    v = cmake(r == c ? 1.0 : 0.0, 0.0);
-  }
-  bool converged = false;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    int rotated = 0;
-#pragma unroll
-    for (int m = 4; m <= 12; m += 4) {
-      const c128 go = cmake(__shfl_xor(g.re, m), __shfl_xor(g.im, m));
-      const c128 vo = cmake(__shfl_xor(v.re, m), __shfl_xor(v.im, m));
-      const bool is_p = (l ^ m) > l;
-      const c128 gp = is_p ? g : go, gq = is_p ? go : g;
-      const c128 vp = is_p ? v : vo, vq = is_p ? vo : v;
-      double al = cabs2(gp), be = cabs2(gq);
-      double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) * gq
-      double gi = gp.re * gq.im - gp.im * gq.re;
-#pragma unroll
-      for (int o = 1; o <= 2; o <<= 1) {
-        al += __shfl_xor(al, o);
-        be += __shfl_xor(be, o);
-        gr += __shfl_xor(gr, o);
-        gi += __shfl_xor(gi, o);
-      }
-      const double ag = sqrt(gr * gr + gi * gi);
-      if (ag > 0.0 && ag > 1e-15 * sqrt(al * be)) {
-        rotated = 1;
-        const c128 ec = cmake(gr / ag, -gi / ag);  // conj(e^{i phi})
-        const double tau = (be - al) / (2.0 * ag);
-        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        const c128 egq = ec * gq, evq = ec * vq;
-        if (is_p) {
-          g = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
-          v = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
-        } else {
-          g = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
-          v = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
-        }
-      }
-    }
-    if (!__any(rotated)) {
-      converged = true;
-      break;
-    }
-  }
-  double s2 = cabs2(g);
-  s2 += __shfl_xor(s2, 1);
-  s2 += __shfl_xor(s2, 2);
-  const double sig = sqrt(s2);
-  double smin = sig, smax = sig;
-  smin = fmin(smin, __shfl_xor(smin, 4));
-  smin = fmin(smin, __shfl_xor(smin, 8));
-  smax = fmax(smax, __shfl_xor(smax, 4));
-  smax = fmax(smax, __shfl_xor(smax, 8));
-  if (converged && smin > 1e-200 && smin > 1e-15 * smax) {
-    // W = G diag(1/sigma) is unitary to the Jacobi tolerance; u = W V^dagger with
-    // lane 4q + p computing u[q][p] = sum_k W[q][k] conj(V[p][k]); W[q][k] and V[p][k]
-    // live on lanes 4k + q and 4k + p.
-    const c128 w = cscale(g, 1.0 / sig);
-    const int q = l >> 2, p = l & 3, base = lane & ~15;
-    c128 acc = cmake(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int lw = base + 4 * k + q, lv = base + 4 * k + p;
-      const c128 wk = cmake(__shfl(w.re, lw), __shfl(w.im, lw));
-      const c128 vk = cmake(__shfl(v.re, lv), __shfl(v.im, lv));
-      cfma_conj(acc, wk, vk);
-    }
-    if (lane < 16) {
-      out64[l] = acc;
-      if (out32) out32[l] = cmake<float>((float)acc.re, (float)acc.im);
-      if (vstore) vstore[r * 4 + c] = v;
-    }
-    return;
-  }
-  // Rank-deficient (or unconverged) case: lane 0 orders the columns by singular value,
-  // re-orthonormalises them and completes W with unit vectors where sigma vanishes.
-  if (lane < 16) {
-    lds_g[c * 4 + r] = g;
-    lds_v[c * 4 + r] = v;
-    if (r == 0) lds_s[c] = sig;
-    if (vstore) vstore[r * 4 + c] = v;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0) {
-    int ord[4] = {0, 1, 2, 3};
-    for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b)
-        if (lds_s[ord[b]] > lds_s[ord[a]]) {
-          const int tmp = ord[a];
-          ord[a] = ord[b];
-          ord[b] = tmp;
-        }
-    const double sm = lds_s[ord[0]];
-    c128 w[4][4];  // [k][row]
-    for (int k = 0; k < 4; ++k) {
-      const int cc = ord[k];
-      const double sk = lds_s[cc];
-      c128 x[4];
-      bool ok = sk > 0.0 && sk > 1e-13 * sm;
-      if (ok) {
-        for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(lds_g[cc * 4 + rr], 1.0 / sk);
-        for (int rep = 0; rep < 2; ++rep)
-          for (int o = 0; o < k; ++o) {
-            c128 d = cmake(0.0, 0.0);
-            for (int rr = 0; rr < 4; ++rr) cfma(d, cconj(w[o][rr]), x[rr]);
-            for (int rr = 0; rr < 4; ++rr) x[rr] = x[rr] - d * w[o][rr];
-          }
-        double nn = 0.0;
-        for (int rr = 0; rr < 4; ++rr) nn += cabs2(x[rr]);
-        nn = sqrt(nn);
-        if (nn > 0.5)
-          for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(x[rr], 1.0 / nn);
-        else
-          ok = false;
-      }
-      if (!ok) {  // complete with the unit vector of largest orthogonal remainder
-        double best = -1.0;
-        c128 bx[4];
-        for (int e = 0; e < 4; ++e) {
-          c128 y[4];
-          for (int rr = 0; rr < 4; ++rr) y[rr] = cmake(rr == e ? 1.0 : 0.0, 0.0);
-          for (int rep = 0; rep < 2; ++rep)
-            for (int o = 0; o < k; ++o) {
-              c128 d = cmake(0.0, 0.0);
-              for (int rr = 0; rr < 4; ++rr) cfma(d, cconj(w[o][rr]), y[rr]);
-              for (int rr = 0; rr < 4; ++rr) y[rr] = y[rr] - d * w[o][rr];
-            }
-          double nn = 0.0;
-          for (int rr = 0; rr < 4; ++rr) nn += cabs2(y[rr]);
-          if (nn > best) {
-            best = nn;
-            for (int rr = 0; rr < 4; ++rr) bx[rr] = y[rr];
-          }
-        }
-        const double inv = 1.0 / sqrt(best);
-        for (int rr = 0; rr < 4; ++rr) x[rr] = cscale(bx[rr], inv);
-      }
-      for (int rr = 0; rr < 4; ++rr) w[k][rr] = x[rr];
-    }
-    for (int q = 0; q < 4; ++q)
-      for (int p = 0; p < 4; ++p) {
-        c128 acc = cmake(0.0, 0.0);
-        for (int k = 0; k < 4; ++k) cfma_conj(acc, w[k][q], lds_v[ord[k] * 4 + p]);
-        out64[q * 4 + p] = acc;
-        if (out32) out32[q * 4 + p] = cmake<float>((float)acc.re, (float)acc.im);
-      }
-  }
 }
 
 
@@ -564,9 +294,14 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
                                                              int logC, const int32_t *pairs_in,
                                                              const cx<R> *gates_in, int32_t gstride,
                                                              const int32_t *slot_to_start,
-                                                             int coalesce_b, const int32_t *kinds_in) {
+                                                             int coalesce_b, const int32_t *kinds_in,
+                                                             const int32_t *bneed_in) {
   const cptr<int32_t> pairs = as_const(pairs_in);
   const cptr<int32_t> kinds = kinds_in ? as_const(kinds_in) : (cptr<int32_t>)nullptr;
+  const cptr<int32_t> bneed = bneed_in ? as_const(bneed_in) : (cptr<int32_t>)nullptr;
+  // B_j is read by the backward pass: the given mask, else every entry but those before a
+  // constant gate
+  auto needed = [&](int j) { return bneed ? bneed[j] != 0 : !(kinds && kinds[j] == QFS_GATE_FIXED); };
   const cptr<cx<R>> gates = as_const(gates_in);
   extern __shared__ __align__(16) unsigned char lds_raw[];
   cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
@@ -607,7 +342,7 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
       // before a constant gate); uniform, worked out before the per-thread loop
       uint32_t mask = 0;
       for (int j = 0; j < run; ++j)
-        if (k + j < sg.kstore && !(kinds && kinds[k + j + 1] == QFS_GATE_FIXED)) mask |= 1u << j;
+        if (k + j < sg.kstore && needed(k + j + 1)) mask |= 1u << j;
       mask = __builtin_amdgcn_readfirstlane(mask);
       forward_run<R>(lds, groups, logJ, logC, sorted, ma, mb, pairs, gates + (int64_t)s * gstride, kinds, k,
                      run, mask, sg.blist ? sg.blist + sg.bstride * s + cbase : nullptr, sg.sN);
@@ -618,7 +353,7 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
     cx<R> u[16];
     load_gate<R>(gates + (int64_t)s * gstride + k * 16, u, false);
     // B_{k+1} serves only the environment of gate k+1: none for a constant gate
-    const bool store = k < sg.kstore && !(kinds && kinds[k + 1] == QFS_GATE_FIXED);
+    const bool store = k < sg.kstore && needed(k + 1);
     cx<R> *dst = store ? sg.blist + sg.bstride * s + sg.sN * k + cbase : nullptr;
     const bool late = store && coalesce_b && ((sizeof(cx<R>) << (logC + min(pa, pb))) < 128);
     // a one-qubit slot is v (x) I_2: output 2i + j mixes inputs j and 2 + j only, so half
@@ -1203,7 +938,8 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
                          GateRef gates, const cx<R> *psi, cx<R> *blist, int64_t bstride,
                          const cx<R> *phi_ref, double *c0_partials, const cx<R> *psiv,
                          const cx<R> *phiv, double *val_partials, const int32_t *slot_to_start,
-                         int nslots, const int32_t *kinds_dev, hipStream_t s) {
+                         int nslots, const int32_t *kinds_dev, hipStream_t s,
+                         const int32_t *bneed_dev) {
   if (nslots <= 0) return QFS_OK;
   FwdSeg<R> a{}, b{};
   a.src = psi;
@@ -1257,7 +993,7 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
     }
     hipLaunchKernelGGL(kernel, dim3(gx * nz, nslots, 1), dim3(threads), lds, s, a, b, nz, g.n, g.logC, pairs_dev,
                        static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, coalesce_b,
-                       kinds_dev);
+                       kinds_dev, bneed_dev);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   };
@@ -1528,7 +1264,7 @@ int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipSt
                                        int, GateRef, const cx<R> *, cx<R> *, int64_t,         \
                                        const cx<R> *, double *, const cx<R> *, const cx<R> *, \
                                        double *, const int32_t *, int, const int32_t *,       \
-                                       hipStream_t);                                          \
+                                       hipStream_t, const int32_t *);                         \
   template int launch_pack<R>(const Geometry &, int64_t, const c128 *, cx<R> *, hipStream_t);
 QFS_INST(float)
 QFS_INST(double)

@@ -20,6 +20,7 @@ QFS_OK, QFS_EINVAL, QFS_ENOMEM, QFS_EDEVICE, QFS_EUNSUPPORTED, QFS_ENUMERIC = ra
 QFS_TARGET_DENSE, QFS_TARGET_CIRCUIT, QFS_TARGET_SAMPLES = 0, 1, 2
 QFS_PREC_FP64, QFS_PREC_MIXED = 0, 1
 QFS_GATE_2Q, QFS_GATE_1Q, QFS_GATE_FIXED = 0, 1, 2
+QFS_BWD_GROUPED, QFS_BWD_PER_GATE = 0, 1
 REASONS = {0: "SUCCESS", 1: "PLATEAU", 2: "MAX_ITER", 3: "NOT_GENERALIZED", 4: "TIMEOUT"}
 
 
@@ -52,7 +53,7 @@ class Params(C.Structure):
                 ("time_budget_s", C.c_double), ("hip_stream", C.c_void_p),
                 ("timing", C.c_int32), ("batch_sweeps", C.c_int32), ("batch_threads", C.c_int32),
                 ("graphs", C.c_int32), ("full_unitary", C.c_int32),
-                ("beta_normalized", C.c_int32)]
+                ("beta_normalized", C.c_int32), ("backward_mode", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -105,7 +106,7 @@ def load():
         lib.qfs_dense_apply.argtypes = [I32, I32, P, P, P, P]
         lib.qfs_environment.argtypes = [I32, I32, P, P, I32, I32, P, P]
         lib.qfs_polar_update.argtypes = [I32, P, D, P, P]
-        lib.qfs_sweep.argtypes = [I32, I32, P, P, I32, P, P, I32, P, I32, D, P, P]
+        lib.qfs_sweep.argtypes = [I32, I32, P, P, I32, P, P, I32, P, I32, D, I32, P, P]
         lib.qfs_state_distance.argtypes = [I32, I32, P, P, C.POINTER(C.c_double), P]
         batch_args = [I32, C.POINTER(Template), C.POINTER(Target), C.POINTER(Params)]
         lib.qfs_label_batch.argtypes = batch_args + [P, C.POINTER(Result)]
@@ -505,9 +506,11 @@ def qfs_polar_update(gamma, beta=0.0, u=None):
     return u
 
 
-def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kinds=None):
+def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kinds=None,
+              backward=None):
     """One sweep of ``gates`` [starts, L, 4, 4] (updated in place); returns c_train list.
-    ``kinds``: per-gate QFS_GATE_* (constant gates are their own entries)."""
+    ``kinds``: per-gate QFS_GATE_* (constant gates are their own entries). ``backward``:
+    QFS_BWD_GROUPED (default) or QFS_BWD_PER_GATE."""
     import numpy as np
     arr, pp = _pairs(pairs)
     starts = gates.shape[0]
@@ -520,7 +523,8 @@ def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kind
     _check(load().qfs_sweep(n, arr.shape[0], pp, None if kd is None else kd.ctypes.data_as(C.c_void_p),
                             psi.shape[0], _dev_c128(psi, "psi"),
                             _dev_c128(phi, "phi"), starts, _dev_c128(gates, "gates"), precision,
-                            beta, c.ctypes.data_as(C.c_void_p), _stream()), "qfs_sweep")
+                            beta, QFS_BWD_GROUPED if backward is None else backward,
+                            c.ctypes.data_as(C.c_void_p), _stream()), "qfs_sweep")
     return c
 
 

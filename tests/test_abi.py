@@ -72,7 +72,7 @@ def test_invalid_templates_rejected_without_device_work(pairs, n):
     pp = arr.ctypes.data_as(C.POINTER(C.c_int32))
     c = np.zeros(1)
     rc = lib.qfs_sweep(n, 1, pp, None, 1, C.c_void_p(16), C.c_void_p(16), 1, C.c_void_p(16), 0,
-                       0.0, c.ctypes.data_as(C.c_void_p), None)
+                       0.0, 0, c.ctypes.data_as(C.c_void_p), None)
     assert rc == Q.QFS_EINVAL
     tmpl = Q.Template(n, 1, pp)
     par = Q.Params()

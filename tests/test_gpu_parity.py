@@ -269,8 +269,22 @@ def test_memory_split_matches_unsplit_run():
                                 fixed_m=1, precision=Q.QFS_PREC_FP64, diff_tol_r=0.0,
                                 plateau_window=100)
     g1, i1 = Q.qfs_instantiate(5, pairs, target_pairs=pairs, target_gates=dev(tg), params=base)
-    small = dict(base, device_mem_budget=1_200_000)
-    g2, i2 = Q.qfs_instantiate(5, pairs, target_pairs=pairs, target_gates=dev(tg), params=small)
+    # the largest budget (in steps of 0.8 from 4 MB) under which the starts no longer fit
+    # together: the run splits them and must still succeed
+    g2 = i2 = None
+    budget = 4_000_000.0
+    while budget > 20_000 and g2 is None:
+        try:
+            g, i = Q.qfs_instantiate(5, pairs, target_pairs=pairs, target_gates=dev(tg),
+                                     params=dict(base, device_mem_budget=int(budget)))
+            if i["start_groups"] > 1:
+                g2, i2 = g, i
+        except Q.QfsError as e:
+            assert e.code == Q.QFS_ENOMEM
+            break
+        budget *= 0.8
+    say(f"memory split at a budget of {int(budget)} bytes")
+    assert g2 is not None, "no budget split the starts"
     assert i1["start_groups"] == 1 and i2["start_groups"] > 1
     assert i2["best_start"] == i1["best_start"] and abs(i2["c_train"] - i1["c_train"]) < 1e-14
     assert np.max(np.abs(host(g1) - host(g2))) < 1e-14
