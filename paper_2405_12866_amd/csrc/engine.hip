@@ -218,6 +218,14 @@ struct SweepCtx {
   c128 *gpartials = nullptr;
   int gpstride = 0;
   c128 *vop = nullptr;  // [S][256]: the last finalized group's operator
+  // Grouped sweeps run the starts in up to nparts parts (2 by default: on MI355X more
+  // parts measured no faster, their kernels slowing each other down), part p on
+  // pstream[p] (pstream[0] is the call's stream), each part's forward pass right after its
+  // own backward pass.
+  static constexpr int kParts = 4;
+  int nparts = 1;
+  hipStream_t pstream[kParts] = {};
+  hipEvent_t pfork = nullptr, pjoin[kParts] = {};
 };
 
 template <typename R>
@@ -305,72 +313,107 @@ int sweep_forward(SweepCtx &c, bool with_c0) {
   return QFS_OK;
 }
 
-// Right-to-left update with gate groups (Sec. 3; Fig. env_calc_tensor): for each group
-// from the last one down, one pass moves the backward state through the previous group's
-// just-updated gates and reduces the group's second-moment matrix against the B entry
-// before the group; the finalize updates the group's gates in order. Then the Eq. 9 cost
-// of the updated gates from a_0 = C^dagger U psi (the last group's gates applied on the
-// way). The halves of the starts run on two streams as in the per-gate pass.
+// Right-to-left update with gate groups (Sec. 3; Fig. env_calc_tensor), issued group by
+// group for the starts slots[0 .. n) on stream st. Item gi < ng: one pass moves the backward
+// state through the previous group's just-updated gates and reduces group gi's
+// second-moment matrix against the B entry before the group, then the finalize updates the
+// group's gates in order. Item ng: the Eq. 9 cost of the updated gates from
+// a_0 = C^dagger U psi (the last group's operator applied on the way). Item ng + 1: the
+// forward pass of the updated gates and their validation cost.
 template <typename R>
-int sweep_backward_grouped(SweepCtx &c) {
-  const GateRef gr = gate_ref<R>(c);
+int grouped_item(SweepCtx &c, const int32_t *slots, int n, hipStream_t st, int item) {
   cx<R> *psi = static_cast<cx<R> *>(c.psi), *phi = static_cast<cx<R> *>(c.phi);
   cx<R> *B = static_cast<cx<R> *>(c.blist), *A = static_cast<cx<R> *>(c.astate);
   const int64_t sN = c.g.elems();
   const int64_t bstride = sN * std::max(c.L - 1, 1);
   KernelTimer &T = *c.timer;
-  const bool split = !T.on && c.side && c.nslots >= 2 &&
-                     (int64_t)(c.nslots / 2) * c.g.elems() >= (int64_t(1) << 20);
-  const int halves = split ? 2 : 1;
-  const int h0 = split ? c.nslots / 2 : c.nslots;
-  const int32_t *hslots[2] = {c.slots, c.slots + h0};
-  const int hn[2] = {h0, c.nslots - h0};
-  hipStream_t hs[2] = {c.stream, c.side};
-  if (split) {
-    QFS_HIP(hipEventRecord(c.fork, c.stream));
-    QFS_HIP(hipStreamWaitEvent(c.side, c.fork, 0));
-  }
   const std::vector<GateGroup> &G = *c.groups;
-  const double set = set_bytes<R>(c, c.g);
-  for (size_t gi = 0; gi < G.size(); ++gi) {
-    const GateGroup &cur = G[gi];
-    const GateGroup *prev = gi ? &G[gi - 1] : nullptr;
-    if (!prev && cur.nvar == 0) {  // nothing to reduce: only the group's operator
-      for (int h = 0; h < halves; ++h)
-        QFS_TRY(launch_group_finalize(0, c.gpartials, c.gpstride, hslots[h], hn[h], cur, c.pairs_host, c.kinds,
-                                      c.beta, c.g64, sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16, c.vstore,
-                                      c.vop, hs[h]));
-      continue;
+  const int ng = (int)G.size();
+  const double set = set_bytes<R>(c, c.g) * n / c.nslots;
+  if (item < ng) {
+    const GateGroup &cur = G[item];
+    const GateGroup *prev = item ? &G[item - 1] : nullptr;
+    int P = 0;
+    if (prev || cur.nvar > 0) {
+      // the state entering group item: U psi through groups 0 .. item-1 (written from 1 on)
+      const SBuf<R> a_in = item <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
+      const SBuf<R> a_out = prev ? SBuf<R>{A, sN} : SBuf<R>{nullptr, 0};
+      const SBuf<R> b = cur.k_lo == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (cur.k_lo - 1) * sN, bstride};
+      QFS_TRY(T.begin(st));
+      QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, prev, &cur, false, c.vop, a_in, a_out, b, slots, n,
+                                   group_blocks_per_start(c.nslots), c.gpartials, c.gpstride, nullptr, &P,
+                                   st));
+      QFS_TRY(T.end(st, kClsStep, set * ((prev ? 2.0 : 1.0) + (cur.nvar > 0 ? 1.0 : 0.0))));
     }
-    // the state entering group gi: U psi through groups 0 .. gi-1 (written from gi = 1 on)
-    const SBuf<R> a_in = gi <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
-    const SBuf<R> a_out = prev ? SBuf<R>{A, sN} : SBuf<R>{nullptr, 0};
-    const SBuf<R> b = cur.k_lo == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (cur.k_lo - 1) * sN, bstride};
-    const double moved = set * ((prev ? 2.0 : 1.0) + (cur.nvar > 0 ? 1.0 : 0.0));
-    for (int h = 0; h < halves; ++h) {
-      int P = 0;
-      QFS_TRY(T.begin(hs[h]));
-      QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, prev, &cur, false, c.vop, a_in, a_out, b, hslots[h],
-                                   hn[h], c.gpartials, c.gpstride, nullptr, &P, hs[h]));
-      QFS_TRY(T.end(hs[h], kClsStep, moved * hn[h] / c.nslots));
-      QFS_TRY(T.begin(hs[h]));
-      QFS_TRY(launch_group_finalize(cur.nvar > 0 ? P : 0, c.gpartials, c.gpstride, hslots[h], hn[h], cur,
-                                    c.pairs_host, c.kinds, c.beta, c.g64, sizeof(R) == 4 ? c.g32 : nullptr,
-                                    c.L * 16, c.vstore, c.vop, hs[h]));
-      QFS_TRY(T.end(hs[h], kClsPolar, (double)P * 4096.0 * hn[h]));
+    // (a group with nothing to reduce still forms its operator for the next pass)
+    QFS_TRY(T.begin(st));
+    QFS_TRY(launch_group_finalize(cur.nvar > 0 ? P : 0, c.gpartials, c.gpstride, slots, n, cur, c.pairs_host,
+                                  c.kinds, c.beta, c.g64, sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16,
+                                  c.vstore, c.vop, st));
+    QFS_TRY(T.end(st, kClsPolar, (double)P * 4096.0 * n));
+    return QFS_OK;
+  }
+  if (item == ng) {
+    int P = 0;
+    QFS_TRY(T.begin(st));
+    QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, &G.back(), nullptr, true, c.vop,
+                                 ng <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN}, SBuf<R>{nullptr, 0},
+                                 SBuf<R>{psi, 0}, slots, n, group_blocks_per_start(c.nslots), nullptr, kGPcap,
+                                 c.dpart0, &P, st));
+    QFS_TRY(T.end(st, kClsDist, 2.0 * set));
+    return launch_dist_finalize(P, c.dpart0, slots, n, c.g.M, c.costs, st, kGPcap);
+  }
+  SweepCtx sub = c;
+  sub.slots = slots;
+  sub.nslots = n;
+  sub.stream = st;
+  return sweep_forward<R>(sub, false);
+}
+
+// One grouped sweep of the running starts: backward pass and cost, then (with_forward)
+// the forward pass of the updated gates, which also gives their validation cost. Without
+// timing, and when every part still streams at least 2^20 amplitudes per pass, the starts
+// run in up to four parts on their own streams (see SweepCtx::pstream); the host issues the
+// parts' items round robin, part p `lag` items behind part p - 1, so the parts' chains of
+// dependent launches advance together and the arithmetic-bound forward pass of one part
+// runs beside the bandwidth-bound passes of the others.
+template <typename R>
+int sweep_grouped(SweepCtx &c, bool with_forward) {
+  KernelTimer &T = *c.timer;
+  const int ng = (int)c.groups->size();
+  const int items = ng + 1 + (with_forward ? 1 : 0);
+  int parts = T.on ? 1 : std::min(c.nparts, c.nslots);
+  while (parts > 1 && (int64_t)(c.nslots / parts) * c.g.elems() < (int64_t(1) << 20)) --parts;
+  if (parts <= 1) {
+    for (int i = 0; i < items; ++i) QFS_TRY(grouped_item<R>(c, c.slots, c.nslots, c.stream, i));
+    return QFS_OK;
+  }
+  static const int lag_env = [] {
+    const char *e = std::getenv("QFS_PART_LAG");  // tuning aid: items between part starts
+    return e ? std::atoi(e) : -1;
+  }();
+  const int lag = lag_env >= 0 ? std::min(lag_env, items) : std::max(1, ng / (2 * parts));
+  QFS_HIP(hipEventRecord(c.pfork, c.stream));
+  const int32_t *pslots[SweepCtx::kParts];
+  int pn[SweepCtx::kParts];
+  hipStream_t pst[SweepCtx::kParts];
+  const int base = c.nslots / parts, extra = c.nslots % parts;
+  for (int p = 0, off = 0; p < parts; ++p) {
+    pn[p] = base + (p < extra ? 1 : 0);
+    pslots[p] = c.slots + off;
+    off += pn[p];
+    pst[p] = p == 0 ? c.stream : c.pstream[p];
+    if (p > 0) QFS_HIP(hipStreamWaitEvent(pst[p], c.pfork, 0));
+  }
+  for (int t = 0; t < items + lag * (parts - 1); ++t)
+    for (int p = 0; p < parts; ++p) {
+      const int i = t - p * lag;
+      if (i >= 0 && i < items) QFS_TRY(grouped_item<R>(c, pslots[p], pn[p], pst[p], i));
     }
+  for (int p = 1; p < parts; ++p) {
+    QFS_HIP(hipEventRecord(c.pjoin[p], pst[p]));
+    QFS_HIP(hipStreamWaitEvent(c.stream, c.pjoin[p], 0));
   }
-  if (split) {
-    QFS_HIP(hipEventRecord(c.join, c.side));
-    QFS_HIP(hipStreamWaitEvent(c.stream, c.join, 0));
-  }
-  int P = 0;
-  QFS_TRY(T.begin(c.stream));
-  QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, &G.back(), nullptr, true, c.vop,
-                               G.size() <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN}, SBuf<R>{nullptr, 0},
-                               SBuf<R>{psi, 0}, c.slots, c.nslots, nullptr, kGPcap, c.dpart0, &P, c.stream));
-  QFS_TRY(T.end(c.stream, kClsDist, 2.0 * set));
-  QFS_TRY(launch_dist_finalize(P, c.dpart0, c.slots, c.nslots, c.g.M, c.costs, c.stream));
   return QFS_OK;
 }
 
@@ -380,7 +423,7 @@ int sweep_backward_grouped(SweepCtx &c) {
 // cost of the updated gates from a_0 = C^dagger U psi.
 template <typename R>
 int sweep_backward(SweepCtx &c) {
-  if (c.grouped) return sweep_backward_grouped<R>(c);
+  if (c.grouped) return sweep_grouped<R>(c, false);
   const GateRef gr = gate_ref<R>(c);
   cx<R> *psi = static_cast<cx<R> *>(c.psi), *phi = static_cast<cx<R> *>(c.phi);
   cx<R> *B = static_cast<cx<R> *>(c.blist), *A = static_cast<cx<R> *>(c.astate);
@@ -503,6 +546,9 @@ class Group {
     if (ev1_) (void)hipEventDestroy(ev1_);
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
+    if (ctx_.pfork) (void)hipEventDestroy(ctx_.pfork);
+    for (int p = 0; p < SweepCtx::kParts; ++p)
+      if (ctx_.pjoin[p]) (void)hipEventDestroy(ctx_.pjoin[p]);
 
     if (gexec_) (void)hipGraphExecDestroy(gexec_);
     if (gfork_) (void)hipEventDestroy(gfork_);
@@ -711,6 +757,7 @@ int Group::setup_working() {
 
 int Group::sweep_once() {
   if (!p_.graphs || timer_.on) {
+    if (ctx_.grouped) return fp64_ ? sweep_grouped<double>(ctx_, true) : sweep_grouped<float>(ctx_, true);
     QFS_TRY(backward_any());
     return forward_any(false);
   }
@@ -730,8 +777,13 @@ int Group::sweep_once() {
     ctx_.stream = cap_;
     hipGraph_t graph = nullptr;
     QFS_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
-    int rc = backward_any();
-    if (rc == QFS_OK) rc = forward_any(false);
+    int rc;
+    if (ctx_.grouped) {
+      rc = fp64_ ? sweep_grouped<double>(ctx_, true) : sweep_grouped<float>(ctx_, true);
+    } else {
+      rc = backward_any();
+      if (rc == QFS_OK) rc = forward_any(false);
+    }
     const hipError_t e = hipStreamEndCapture(cap_, &graph);
     ctx_.stream = stream_;
     if (rc != QFS_OK) {
@@ -867,6 +919,15 @@ int Group::run(GroupResult &out, double t_start) {
     c.side = side_;
     c.fork = fork_;
     c.join = join_;
+    static const int parts_env = [] {
+      const char *e = std::getenv("QFS_PARTS");  // tuning aid: most stream parts of a sweep
+      return e ? std::max(1, std::min(SweepCtx::kParts, std::atoi(e))) : 2;
+    }();
+    c.nparts = parts_env;
+    c.pstream[1] = side_;
+    for (int p = 2; p < SweepCtx::kParts; ++p) QFS_TRY(pool_stream(p + 1, &c.pstream[p]));
+    QFS_HIP(hipEventCreateWithFlags(&c.pfork, hipEventDisableTiming));
+    for (int p = 0; p < SweepCtx::kParts; ++p) QFS_HIP(hipEventCreateWithFlags(&c.pjoin[p], hipEventDisableTiming));
   }
   QFS_TRY(setup_working());
 

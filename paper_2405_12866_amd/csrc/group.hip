@@ -42,7 +42,7 @@ namespace qfs {
 
 namespace {
 
-constexpr int kGBlock = 256;
+constexpr int kGBlock = 512;
 constexpr int kGWaves = kGBlock / 64;
 constexpr int kMaxBits = 28;
 
@@ -81,9 +81,9 @@ struct GroupArgs {
   const c128 *vop;       // [S][256]: the previous group's operator (16 x 16 over its four
                          // slots, the u^dag of its gates in order), nullptr: none
   c128 *partials;        // [S][pstride][256]: second-moment block partials
-  double *dpartials;     // [S][P]: distance block partials
+  double *dpartials;     // [S][pstride]: distance block partials
   const int32_t *slot_to_start;
-  int32_t pstride;       // blocks per start in the partials (>= gridDim.x)
+  int32_t pstride;       // blocks per start in either partials (>= gridDim.x)
   int32_t n, logC;
   int32_t nT;            // tile bits of the chunk-local index (packet bits included)
   int32_t nX;            // chunk-local bits outside the tile
@@ -131,7 +131,7 @@ __device__ __forceinline__ void lds_elem_put(float4 *lds, uint32_t pk, int, c128
 }
 
 // Packets per thread and set of one tile (tiles of at most 2048 packets).
-constexpr int kMaxPkt = 8;
+constexpr int kMaxPkt = 2048 / kGBlock;
 
 template <typename R>
 __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
@@ -329,13 +329,15 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wv * 256 + MF::row(lane, v) * 16 + zl] = make_double2(gre[v], gim[v]);
     __syncthreads();
-    double2 acc = red[tid];
+    if (tid < 256) {
+      double2 acc = red[tid];
 #pragma unroll
-    for (int w = 1; w < kGWaves; ++w) {
-      acc.x += red[w * 256 + tid].x;
-      acc.y += red[w * 256 + tid].y;
+      for (int w = 1; w < kGWaves; ++w) {
+        acc.x += red[w * 256 + tid].x;
+        acc.y += red[w * 256 + tid].y;
+      }
+      A.partials[((int64_t)s * A.pstride + blockIdx.x) * 256 + tid] = cmake(acc.x, acc.y);
     }
-    A.partials[((int64_t)s * A.pstride + blockIdx.x) * 256 + tid] = cmake(acc.x, acc.y);
   }
   if (A.dist) {
     __shared__ double dred[kGWaves];
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
     if (tid == 0) {
       double sum = dred[0];
       for (int w = 1; w < kGWaves; ++w) sum += dred[w];
-      A.dpartials[(int64_t)s * P + blockIdx.x] = sum;
+      A.dpartials[(int64_t)s * A.pstride + blockIdx.x] = sum;
     }
   }
 }
@@ -367,68 +369,76 @@ __global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, in
                                                         double beta, c128 *g64, c64 *g32,
                                                         int32_t gstride, c128 *vstore, c128 *vop) {
   __shared__ c128 H[256], Vm[256];
-  __shared__ c128 gam[16], ug[16];
+  __shared__ c128 ug[kGroupMaxGates][16];  // the group's gates (pre-sweep, then updated)
+  __shared__ c128 gam[16];
   __shared__ c128 pg[16], pv[16];
   __shared__ double psig[4];
   const int s = slot_to_start[blockIdx.x];
   const int t = threadIdx.x;
   const int z = t >> 4, y = t & 15;
+  const int ngate = F.k_hi - F.k_lo + 1;
+  c128 *gs = g64 + (int64_t)s * gstride;
+  if (t < 16 * ngate) ug[t >> 4][t & 15] = gs[(F.k_lo + (t >> 4)) * 16 + (t & 15)];
   if (F.nvar > 0) {
+    // fixed-order sum of the block partials: eight interleaved accumulators, each batch of
+    // eight loads in flight together
     const c128 *src = partials + (int64_t)s * pstride * 256 + t;
-    c128 acc[4] = {cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0), cmake(0.0, 0.0)};
-    int p = 0;
-    for (; p + 3 < P; p += 4) {
+    c128 acc[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = acc[u] + src[(int64_t)(p + u) * 256];
+    for (int u = 0; u < 8; ++u) acc[u] = cmake(0.0, 0.0);
+    int p = 0;
+    for (; p + 7 < P; p += 8) {
+      c128 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(p + u) * 256];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = acc[u] + v[u];
     }
-    if (p < P) acc[0] = acc[0] + src[(int64_t)p * 256];
-    if (p + 1 < P) acc[1] = acc[1] + src[(int64_t)(p + 1) * 256];
-    if (p + 2 < P) acc[2] = acc[2] + src[(int64_t)(p + 2) * 256];
-    H[t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+      if (p + u < P) acc[u] = acc[u] + src[(int64_t)(p + u) * 256];
+    H[t] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
   Vm[t] = cmake(z == y ? 1.0 : 0.0, 0.0);
-  c128 *gs = g64 + (int64_t)s * gstride;
-  auto load_u = [&](int k) {
-    __syncthreads();
-    if (t < 16) ug[t] = gs[k * 16 + t];
-    __syncthreads();
-  };
   // X <- X op(u) with u on slots (a, b) of the column index; op(u) = u^dag or u
-  auto right = [&](c128 *X, int a, int b, bool dag) {
+  auto right = [&](c128 *X, const c128 *u, int a, int b, bool dag) {
     const int ly = 2 * ((y >> a) & 1) + ((y >> b) & 1);
     const int yb = y & ~((1 << a) | (1 << b));
     c128 v = cmake(0.0, 0.0);
 #pragma unroll
     for (int p2 = 0; p2 < 4; ++p2) {
       const int yy = yb | ((p2 >> 1) << a) | ((p2 & 1) << b);
-      const c128 m = dag ? cconj(ug[ly * 4 + p2]) : ug[p2 * 4 + ly];
+      const c128 m = dag ? cconj(u[ly * 4 + p2]) : u[p2 * 4 + ly];
       cfma(v, X[z * 16 + yy], m);
     }
     __syncthreads();
     X[t] = v;
     __syncthreads();
   };
-  // X <- u^dag X with u on slots (a, b) of the row index
-  auto left_dag = [&](c128 *X, int a, int b) {
+  // X <- u^dag X (and Y <- u^dag Y when given) with u on slots (a, b) of the row index
+  auto left_dag = [&](c128 *X, c128 *Y, const c128 *u, int a, int b) {
     const int lz = 2 * ((z >> a) & 1) + ((z >> b) & 1);
     const int zb = z & ~((1 << a) | (1 << b));
-    c128 v = cmake(0.0, 0.0);
+    c128 v = cmake(0.0, 0.0), w = cmake(0.0, 0.0);
 #pragma unroll
     for (int q2 = 0; q2 < 4; ++q2) {
       const int zz = zb | ((q2 >> 1) << a) | ((q2 & 1) << b);
-      cfma(v, cconj(ug[q2 * 4 + lz]), X[zz * 16 + y]);
+      const c128 m = cconj(u[q2 * 4 + lz]);
+      cfma(v, m, X[zz * 16 + y]);
+      if (Y) cfma(w, m, Y[zz * 16 + y]);
     }
     __syncthreads();
     X[t] = v;
+    if (Y) Y[t] = w;
     __syncthreads();
   };
   __syncthreads();
   // H_{k_hi} = G W^dag, W = u_{k_hi - 1} ... u_{k_lo} (pre-sweep gates)
   if (F.nvar > 0)
-    for (int k = F.k_lo; k < F.k_hi; ++k) {
-      load_u(k);
-      right(H, F.sa[k - F.k_lo], F.sb[k - F.k_lo], true);
-    }
+    for (int k = F.k_lo; k < F.k_hi; ++k) right(H, ug[k - F.k_lo], F.sa[k - F.k_lo], F.sb[k - F.k_lo], true);
+  // the variable gate lowest in the group: H is not needed below it
+  int k_last = F.k_lo;
+  while (k_last < F.k_hi && F.kind[k_last - F.k_lo] == QFS_GATE_FIXED) ++k_last;
   for (int k = F.k_hi; k >= F.k_lo; --k) {
     const int i = k - F.k_lo;
     const int a = F.sa[i], b = F.sb[i];
@@ -446,33 +456,25 @@ __global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, in
           g = g + H[(zq | zo) * 16 + (zp | zo)];
         }
         gam[t] = g;
-        ug[t] = gs[k * 16 + t];
       }
       __syncthreads();
       if (t < 64) {
         if (F.kind[i] == QFS_GATE_1Q) {
-          if (t == 0) polar2_update<float>(gam, beta, ug, nullptr);
+          if (t == 0) polar2_update<float>(gam, beta, ug[i], nullptr);
         } else {
-          polar4_wave(gam, beta, gs + k * 16, ug, nullptr, pg, pv, psig,
+          polar4_wave(gam, beta, gs + k * 16, ug[i], nullptr, pg, pv, psig,
                       vstore ? vstore + (int64_t)s * gstride + k * 16 : nullptr);
         }
       }
       __syncthreads();
       if (t < 16) {
-        gs[k * 16 + t] = ug[t];
-        if (g32) g32[(int64_t)s * gstride + k * 16 + t] = cmake<float>((float)ug[t].re, (float)ug[t].im);
-      }
-    } else {
-      load_u(k);
-    }
-    left_dag(Vm, a, b);
-    if (F.nvar > 0) {
-      left_dag(H, a, b);
-      if (k > F.k_lo) {
-        load_u(k - 1);
-        right(H, F.sa[i - 1], F.sb[i - 1], false);
+        gs[k * 16 + t] = ug[i][t];
+        if (g32) g32[(int64_t)s * gstride + k * 16 + t] = cmake<float>((float)ug[i][t].re, (float)ug[i][t].im);
       }
     }
+    const bool more = F.nvar > 0 && k > k_last;
+    left_dag(Vm, more ? H : nullptr, ug[i], a, b);
+    if (more) right(H, ug[i - 1], F.sa[i - 1], F.sb[i - 1], false);
   }
   vop[(int64_t)s * 256 + t] = Vm[t];
 }
@@ -529,6 +531,10 @@ static int target_blocks() {
   return tb;
 }
 
+int group_blocks_per_start(int running_starts) {
+  return std::max(1, target_blocks() / std::max(1, running_starts));
+}
+
 int group_partials_stride(const Geometry &g, size_t rbytes) {
   const int logV = rbytes == 4 ? 1 : 0;
   const int nC = g.n + g.logC;
@@ -541,8 +547,8 @@ int group_partials_stride(const Geometry &g, size_t rbytes) {
 template <typename R>
 int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *prev,
                       const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
-                      SBuf<R> b, const int32_t *slot_to_start, int nslots, c128 *gpartials,
-                      int pstride, double *dpartials, int *P_out, hipStream_t s) {
+                      SBuf<R> b, const int32_t *slot_to_start, int nslots, int blocks_per_start,
+                      c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   constexpr int LOGV = Pk<R>::LOGV;
   const int nC = g.n + g.logC;
@@ -636,7 +642,7 @@ int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *
   }
   const int64_t tiles = (int64_t)g.nch << A.nX;
   const int P = (int)std::min<int64_t>({tiles, (int64_t)std::max(1, pstride),
-                                         std::max<int64_t>(1, target_blocks() / std::max(1, nslots))});
+                                         (int64_t)std::max(1, blocks_per_start)});
   *P_out = P;
   hipLaunchKernelGGL(k_bwd_group<R>, dim3(P, nslots), dim3(kGBlock), lds, s, A);
   QFS_HIP(hipGetLastError());
@@ -673,7 +679,7 @@ int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32
 #define QFS_GINST(R)                                                                          \
   template int launch_group_pass<R>(const Geometry &, const int32_t *, const GateGroup *,      \
                                     const GateGroup *, bool, const c128 *, SBuf<R>, SBuf<R>,   \
-                                    SBuf<R>, const int32_t *, int, c128 *, int, double *,      \
+                                    SBuf<R>, const int32_t *, int, int, c128 *, int, double *, \
                                     int *,                                                     \
                                     hipStream_t);
 QFS_GINST(float)

@@ -299,13 +299,14 @@ int launch_env_finalize(int P, const c128 *partials, const int32_t *slot_to_star
 int launch_identity4(int64_t count, c128 *v, hipStream_t s);
 
 // Block partials of sum ||op(u_s[k]) x_s - ref_s||^2 (k < 0: no gate), P returned;
-// launch_dist_finalize writes out[s] = (1/M) * (fixed-order sum).
+// launch_dist_finalize writes out[s] = (1/M) * (fixed-order sum of partials[s stride + b],
+// b < P; stride 0 means P).
 template <typename R>
 int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, GateRef gates,
                       SBuf<R> x, SBuf<R> ref, const int32_t *slot_to_start, int nslots,
                       double *partials, int *P_out, hipStream_t s);
 int launch_dist_finalize(int P, const double *partials, const int32_t *slot_to_start, int nslots,
-                         int M, double *out, hipStream_t s);
+                         int M, double *out, hipStream_t s, int stride = 0);
 
 // Batched polar update on device (count problems).
 int launch_polar_batch(int count, const c128 *gamma, double beta, c128 *u, hipStream_t s);
@@ -337,8 +338,11 @@ int group_partials_stride(const Geometry &g, size_t rbytes);
 template <typename R>
 int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *prev,
                       const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
-                      SBuf<R> b, const int32_t *slot_to_start, int nslots, c128 *gpartials,
-                      int pstride, double *dpartials, int *P_out, hipStream_t s);
+                      SBuf<R> b, const int32_t *slot_to_start, int nslots, int blocks_per_start,
+                      c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s);
+// Work-groups per start of a grouped pass when `running_starts` starts sweep together
+// (whatever streams they are split over).
+int group_blocks_per_start(int running_starts);
 // Per start: sum the P partials in a fixed order and update cur's variable gates from the top
 // down (both gate copies, warm-start vectors as launch_env_finalize); then write cur's
 // operator Vop = u_{k_lo}^dag ... u_{k_hi}^dag over its four slots to vop [S][256].

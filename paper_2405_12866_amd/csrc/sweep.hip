@@ -825,12 +825,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_dist(DistArgs<R> A) {
 }
 
 // Per start (one wave): fixed-order sum of the P block partials, divided by M.
-__global__ __launch_bounds__(64) void k_dist_finalize(const double *partials, int P,
+__global__ __launch_bounds__(64) void k_dist_finalize(const double *partials, int P, int stride,
                                                       const int32_t *slot_to_start, double inv_m,
                                                       double *out) {
   const int s = slot_to_start[blockIdx.x];
   double sum = 0.0;
-  for (int blk = threadIdx.x; blk < P; blk += 64) sum += partials[(int64_t)s * P + blk];
+  for (int blk = threadIdx.x; blk < P; blk += 64) sum += partials[(int64_t)s * stride + blk];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_down(sum, o);
   if (threadIdx.x == 0) out[s] = sum * inv_m;
@@ -1228,10 +1228,10 @@ int launch_apply_dist(const Geometry &g, int qa, int qb, int k, bool dagger, Gat
 }
 
 int launch_dist_finalize(int P, const double *partials, const int32_t *slot_to_start, int nslots,
-                         int M, double *out, hipStream_t s) {
+                         int M, double *out, hipStream_t s, int stride) {
   if (nslots <= 0) return QFS_OK;
-  hipLaunchKernelGGL(k_dist_finalize, dim3(nslots), dim3(64), 0, s, partials, P, slot_to_start,
-                     1.0 / (double)M, out);
+  hipLaunchKernelGGL(k_dist_finalize, dim3(nslots), dim3(64), 0, s, partials, P, stride > 0 ? stride : P,
+                     slot_to_start, 1.0 / (double)M, out);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
