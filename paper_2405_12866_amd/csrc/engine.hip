@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <vector>
+#include <type_traits>
 
 #include "qfs_internal.h"
 
@@ -218,6 +219,9 @@ struct SweepCtx {
   c128 *gpartials = nullptr;
   int gpstride = 0;
   c128 *vop = nullptr;  // [S][256]: the last finalized group's operator
+  // forward pass by groups (complex64, fused): device plan, per-gate slots, group count
+  const int32_t *fplan = nullptr, *fgslot = nullptr;
+  int fngroups = 0;
   // Grouped sweeps run the starts in up to nparts parts (2 by default: on MI355X more
   // parts measured no faster, their kernels slowing each other down), part p on
   // pstream[p] (pstream[0] is the call's stream), each part's forward pass right after its
@@ -256,9 +260,21 @@ int sweep_forward(SweepCtx &c, bool with_c0) {
   KernelTimer &T = *c.timer;
   if (c.fused) {
     QFS_TRY(T.begin(c.stream));
-    QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
-                                    with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
-                                    c.nslots, c.kinds_dev, c.stream, c.grouped ? c.bneed_dev : nullptr));
+    if constexpr (std::is_same<R, float>::value) {
+      if (c.grouped && c.fplan) {
+        QFS_TRY(launch_forward_groups<float>(c.g, val ? &c.gv : nullptr, c.L, gr, psi, B, bstride,
+                                             with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
+                                             c.nslots, c.fplan, c.fngroups, c.fgslot, c.stream));
+      } else {
+        QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
+                                        with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
+                                        c.nslots, c.kinds_dev, c.stream, c.grouped ? c.bneed_dev : nullptr));
+      }
+    } else {
+      QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
+                                      with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
+                                      c.nslots, c.kinds_dev, c.stream, c.grouped ? c.bneed_dev : nullptr));
+    }
     // load Psi, store the B list entries the backward pass reads, read U Psi for c_0
     int stored = 0;
     if (c.grouped) {
@@ -589,7 +605,8 @@ class Group {
   DevBuf g64_, g32_, vstore_, pairs_dev_, kinds_dev_;
   DevBuf partials_, dpart_, costs_, slots_, work_;
   std::vector<GateGroup> groups_;  // grouped backward pass (backward_mode GROUPED)
-  DevBuf bneed_dev_, gpartials_, vop_;
+  DevBuf bneed_dev_, gpartials_, vop_, fplan_dev_, fgslot_dev_;
+  std::vector<int32_t> bneed_h_, fplan_h_, fgslot_h_;
   int gpstride_ = 0;
   double *h_costs_ = nullptr;  // pinned [3 S]: c_train, c_val, c_0
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
@@ -703,13 +720,29 @@ int Group::setup_working() {
     }
     if (!vop_.ptr) QFS_TRY(arena_.alloc(vop_, sizeof(c128) * 256 * (size_t)S_));
     if (!bneed_dev_.ptr) {
-      std::vector<int32_t> need(L_, 0);
+      bneed_h_.assign(L_, 0);
       for (const GateGroup &gg : groups_)
-        if (gg.k_lo >= 1 && gg.nvar > 0) need[gg.k_lo] = 1;
+        if (gg.k_lo >= 1 && gg.nvar > 0) bneed_h_[gg.k_lo] = 1;
       QFS_TRY(arena_.alloc(bneed_dev_, sizeof(int32_t) * (size_t)L_));
-      QFS_HIP(hipMemcpyAsync(bneed_dev_.ptr, need.data(), sizeof(int32_t) * L_, hipMemcpyHostToDevice,
+      QFS_HIP(hipMemcpyAsync(bneed_dev_.ptr, bneed_h_.data(), sizeof(int32_t) * L_, hipMemcpyHostToDevice,
                              stream_));
     }
+  }
+  // the forward pass by groups (complex64 states, whole chunks in LDS); the plan follows the
+  // chunk width
+  c.fplan = c.fgslot = nullptr;
+  c.fngroups = 0;
+  if (c.grouped && fused && !fp64_ && build_forward_plan(c.g, L_, pairs_.data(), groups_, bneed_h_.data(),
+                                                         fplan_h_, fgslot_h_) == QFS_OK) {
+    if (!fplan_dev_.ptr) QFS_TRY(arena_.alloc(fplan_dev_, sizeof(int32_t) * fplan_h_.size()));
+    if (!fgslot_dev_.ptr) QFS_TRY(arena_.alloc(fgslot_dev_, sizeof(int32_t) * fgslot_h_.size()));
+    QFS_HIP(hipMemcpyAsync(fplan_dev_.ptr, fplan_h_.data(), sizeof(int32_t) * fplan_h_.size(),
+                           hipMemcpyHostToDevice, stream_));
+    QFS_HIP(hipMemcpyAsync(fgslot_dev_.ptr, fgslot_h_.data(), sizeof(int32_t) * fgslot_h_.size(),
+                           hipMemcpyHostToDevice, stream_));
+    c.fplan = fplan_dev_.as<int32_t>();
+    c.fgslot = fgslot_dev_.as<int32_t>();
+    c.fngroups = (int)groups_.size();
   }
   if (!c.grouped && !partials_.ptr) {  // environment partials of the per-gate pass
     QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)kPcap * S_));
@@ -1539,11 +1572,12 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
   c.dpart1 = dpart.as<double>() + (size_t)kPcap * starts;
   c.costs = costs.as<double>();
   std::vector<GateGroup> groups;
-  DevBuf gpart, bneed, vopb;
+  std::vector<int32_t> need, fplan_h, fgslot_h;
+  DevBuf gpart, bneed, vopb, fplan_d, fgslot_d;
   c.grouped = backward_mode == QFS_BWD_GROUPED && group_path_supported(c.g, rb);
   if (c.grouped) {
     groups = plan_gate_groups(L, pairs, kinds);
-    std::vector<int32_t> need(L, 0);
+    need.assign(L, 0);
     for (const GateGroup &gg : groups)
       if (gg.k_lo >= 1 && gg.nvar > 0) need[gg.k_lo] = 1;
     c.gpstride = group_partials_stride(c.g, rb);
@@ -1555,6 +1589,16 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
     c.groups = &groups;
     c.bneed_dev = bneed.as<int32_t>();
     c.gpartials = gpart.as<c128>();
+    if (f32 && fused && build_forward_plan(c.g, L, pairs, groups, need.data(), fplan_h, fgslot_h) == QFS_OK) {
+      QFS_TRY(fplan_d.alloc(sizeof(int32_t) * fplan_h.size()));
+      QFS_TRY(fgslot_d.alloc(sizeof(int32_t) * fgslot_h.size()));
+      QFS_HIP(hipMemcpyAsync(fplan_d.ptr, fplan_h.data(), sizeof(int32_t) * fplan_h.size(), hipMemcpyHostToDevice, s));
+      QFS_HIP(hipMemcpyAsync(fgslot_d.ptr, fgslot_h.data(), sizeof(int32_t) * fgslot_h.size(),
+                             hipMemcpyHostToDevice, s));
+      c.fplan = fplan_d.as<int32_t>();
+      c.fgslot = fgslot_d.as<int32_t>();
+      c.fngroups = (int)groups.size();
+    }
   }
   if (f32) {
     QFS_TRY(sweep_forward<float>(c, false));

@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "polar2.h"
 #include "polar4.h"
@@ -479,6 +480,194 @@ __global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, in
   vop[(int64_t)s * 256 + t] = Vm[t];
 }
 
+// ------------------------------------------------------------------ grouped forward pass
+// The forward pass (Fig. pre-comp) with the same gate groups: a work-group holds one chunk
+// of samples in LDS (see the chunked layout in qfs_internal.h) and applies the gates one
+// group at a time, each thread taking a 16-element item (the values of the group's four slot
+// bits, for fixed other bits and sample) into registers, applying every gate of the group
+// there (complex64: the 4x4x1 matrix-core product on the lane's own four amplitudes per
+// pair of slots; complex128: FMA), and writing it back: one LDS round trip per group instead
+// of one per gate. The B list entry before a group, when the backward pass reads it, is
+// stored from the registers on the way in.
+template <typename R>
+struct FwdGroupSeg {
+  const cx<R> *src;     // initial states (shared by all starts), chunked
+  cx<R> *blist;         // B list (B_{k+1} at list index k) or nullptr
+  int64_t bstride;      // per start
+  int64_t sN;           // per list entry
+  const cx<R> *ref;     // states to compare against after the last gate, or nullptr
+  double *partials;     // [S][nch] distance partials
+  int32_t nch;
+  int32_t kapply;       // gates applied: 0 .. kapply-1 (whole groups)
+};
+
+// Plan entry of a group (forward order): k_lo, k_hi, the chunk-local positions of its four
+// slots (qubits first, then fillers), store flag (the entry B_{k_lo} is read); per gate k:
+// the slots of its two qubits at gslot[2k], gslot[2k + 1].
+constexpr int kFwdPlan = 8;
+
+template <int SA, int SB, typename R>
+__device__ __forceinline__ void item_gate(cx<R> (&x)[16], const cx<R> (&u)[16], const Gate4 &G4) {
+  constexpr int o0 = (0 != SA && 0 != SB) ? 0 : (1 != SA && 1 != SB) ? 1 : 2;
+  constexpr int o1 = (3 != SA && 3 != SB) ? 3 : (2 != SA && 2 != SB && 2 != o0) ? 2 : 1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int cb = ((c >> 1) << o0) | ((c & 1) << o1);
+    int idx[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) idx[l] = cb | ((l >> 1) << SA) | ((l & 1) << SB);
+    if constexpr (std::is_same<R, float>::value) {
+      c64 xi[4], yo[4];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) xi[l] = x[idx[l]];
+      gate4_apply(G4, xi, yo);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) x[idx[l]] = yo[l];
+    } else {
+      cx<R> yo[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cx<R> acc = cmake<R>(0, 0);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) cfma(acc, u[q * 4 + p], x[idx[p]]);
+        yo[q] = acc;
+      }
+#pragma unroll
+      for (int l = 0; l < 4; ++l) x[idx[l]] = yo[l];
+    }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void item_gate_slots(int sa, int sb, cx<R> (&x)[16], const cx<R> (&u)[16],
+                                                const Gate4 &G4) {
+  switch (sa * 4 + sb) {
+    case 1: item_gate<0, 1, R>(x, u, G4); break;
+    case 2: item_gate<0, 2, R>(x, u, G4); break;
+    case 3: item_gate<0, 3, R>(x, u, G4); break;
+    case 4: item_gate<1, 0, R>(x, u, G4); break;
+    case 6: item_gate<1, 2, R>(x, u, G4); break;
+    case 7: item_gate<1, 3, R>(x, u, G4); break;
+    case 8: item_gate<2, 0, R>(x, u, G4); break;
+    case 9: item_gate<2, 1, R>(x, u, G4); break;
+    case 11: item_gate<2, 3, R>(x, u, G4); break;
+    case 12: item_gate<3, 0, R>(x, u, G4); break;
+    case 13: item_gate<3, 1, R>(x, u, G4); break;
+    default: item_gate<3, 2, R>(x, u, G4); break;
+  }
+}
+
+template <typename R, int FB>
+__global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdGroupSeg<R> seg1, int nseg,
+                                                       int n, int logC, const int32_t *plan_in, int ngroups,
+                                                       const int32_t *gslot_in, const cx<R> *gates_in,
+                                                       int32_t gstride, const int32_t *slot_to_start, int L,
+                                                       int gates_in_lds) {
+  constexpr int V = Pk<R>::V;
+  const cptr<int32_t> plan = as_const(plan_in);
+  const cptr<int32_t> gslot = as_const(gslot_in);
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  cx<R> *lds = reinterpret_cast<cx<R> *>(lds_raw);
+  __shared__ double red[FB / 64];
+  const bool second = nseg == 2 && (blockIdx.x & 1);
+  const FwdGroupSeg<R> sg = second ? seg1 : seg0;
+  const int q = nseg == 2 ? (int)(blockIdx.x >> 1) : (int)blockIdx.x;
+  if (q >= sg.nch) return;
+  const int s = slot_to_start[blockIdx.y];
+  const cx<R> *gates = gates_in + (int64_t)s * gstride;
+  const cptr<cx<R>> gates_c = as_const(gates);
+  const uint32_t chunk = 1u << (n + logC);  // elements per chunk
+  const int64_t cbase = (int64_t)q << (n + logC);
+  const cx<R> *src = sg.src + cbase;
+  for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(lds + e, ld_pk(src + e));
+  // the start's gates behind the chunk, so reading a gate row never waits on memory
+  cx<R> *lgates = lds + chunk;
+  if (gates_in_lds)
+    for (int e = threadIdx.x; e < 16 * L; e += FB) lgates[e] = gates[e];
+  __syncthreads();
+  cx<R> *bl = sg.blist ? sg.blist + sg.bstride * s + cbase : nullptr;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nitems = chunk >> 4;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const cptr<int32_t> pg = plan + gi * kFwdPlan;
+    const int k_lo = pg[0], k_hi = pg[1];
+    const bool store = bl && pg[6] && k_lo - 1 < sg.kapply;
+    const bool apply = k_hi < sg.kapply;
+    if (!store && !apply) break;  // (groups come in forward order)
+    int sp[4], srt[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) srt[i] = sp[i] = pg[2 + i];
+    // ascending slot positions for the item index
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (srt[j] > srt[j + 1]) {
+          const int t = srt[j];
+          srt[j] = srt[j + 1];
+          srt[j + 1] = t;
+        }
+    uint32_t ro[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      ro[r] = ((uint32_t)(r & 1) << sp[0]) | ((uint32_t)((r >> 1) & 1) << sp[1]) |
+              ((uint32_t)((r >> 2) & 1) << sp[2]) | ((uint32_t)((r >> 3) & 1) << sp[3]);
+    cx<R> *dst = store ? bl + sg.sN * (k_lo - 1) : nullptr;
+    // (wave-uniform trip count: every lane of a wave runs the matrix-core products)
+    for (uint32_t ib = threadIdx.x - lane; ib < nitems; ib += FB) {
+      const uint32_t it = ib + lane;
+      const bool ok = it < nitems;
+      const uint32_t base = deposit(it, srt, 4);
+      cx<R> x[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) x[r] = ok ? lds[base + ro[r]] : cmake<R>(0, 0);
+      if (store && ok) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dst[base + ro[r]] = x[r];
+      }
+      if (!apply) continue;
+      for (int k = k_lo; k <= k_hi; ++k) {
+        const int sa = gslot[2 * k], sb = gslot[2 * k + 1];
+        Gate4 G4;
+        cx<R> u[16];
+        if constexpr (std::is_same<R, float>::value) {
+          G4 = gates_in_lds ? gate4_row(lgates + k * 16, false) : gate4_row(gates_c + k * 16, false);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) u[e] = cmake<R>(gates_c[k * 16 + e].re, gates_c[k * 16 + e].im);
+        }
+        item_gate_slots<R>(sa, sb, x, u, G4);
+      }
+      if (ok) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds[base + ro[r]] = x[r];
+      }
+    }
+    __syncthreads();
+  }
+  if (sg.ref) {
+    const cx<R> *ref = sg.ref + cbase;
+    double acc = 0.0;
+    for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) {
+      const Pk<R> a = ld_pk(lds + e), b = ld_pk(ref + e);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const R dr = a.v[v].re - b.v[v].re, di = a.v[v].im - b.v[v].im;
+        acc += (double)dr * (double)dr + (double)di * (double)di;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < FB / 64; ++w) tot += red[w];
+      sg.partials[(int64_t)s * sg.nch + q] = tot;
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -675,6 +864,106 @@ int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
+
+
+// ------------------------------------------------------------------ grouped forward, host
+int build_forward_plan(const Geometry &g, int L, const int32_t *pairs, const std::vector<GateGroup> &groups,
+                       const int32_t *bneed_host, std::vector<int32_t> &plan, std::vector<int32_t> &gslot) {
+  const int nC = g.n + g.logC;
+  if (nC < 4) return QFS_EUNSUPPORTED;
+  plan.assign(groups.size() * kFwdPlan, 0);
+  gslot.assign(2 * (size_t)L, 0);
+  const int ng = (int)groups.size();
+  for (int fi = 0; fi < ng; ++fi) {
+    const GateGroup &gg = groups[ng - 1 - fi];  // forward order
+    int32_t *pe = &plan[fi * kFwdPlan];
+    pe[0] = gg.k_lo;
+    pe[1] = gg.k_hi;
+    bool used[32] = {};
+    for (int i = 0; i < gg.nq; ++i) {
+      pe[2 + i] = g.logC + (g.n - 1 - gg.q[i]);
+      used[pe[2 + i]] = true;
+    }
+    // fillers: the highest free positions, so the lanes of an item run over the low bits
+    for (int i = gg.nq, p = nC - 1; i < 4; ++i) {
+      while (used[p]) --p;
+      pe[2 + i] = p;
+      used[p] = true;
+    }
+    pe[6] = (gg.k_lo >= 1 && bneed_host && bneed_host[gg.k_lo]) ? 1 : 0;
+    auto slot = [&](int q) {
+      for (int i = 0; i < gg.nq; ++i)
+        if (gg.q[i] == q) return i;
+      return -1;
+    };
+    for (int k = gg.k_lo; k <= gg.k_hi; ++k) {
+      gslot[2 * k] = slot(pairs[2 * k]);
+      gslot[2 * k + 1] = slot(pairs[2 * k + 1]);
+    }
+  }
+  return QFS_OK;
+}
+
+template <typename R>
+int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef gates, const cx<R> *psi,
+                          cx<R> *blist, int64_t bstride, const cx<R> *phi_ref, double *c0_partials,
+                          const cx<R> *psiv, const cx<R> *phiv, double *val_partials,
+                          const int32_t *slot_to_start, int nslots, const int32_t *plan_dev, int ngroups,
+                          const int32_t *gslot_dev, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  FwdGroupSeg<R> a{}, b{};
+  a.src = psi;
+  a.blist = blist;
+  a.bstride = bstride;
+  a.sN = (int64_t)g.nch * ((int64_t)g.N << g.logC);
+  a.ref = phi_ref;
+  a.partials = c0_partials;
+  a.nch = g.nch;
+  a.kapply = phi_ref ? L : L - 1;
+  int nz = 1;
+  if (gv) {
+    if (gv->logC != g.logC) {
+      set_error_detail("grouped forward: training and validation chunk widths differ");
+      return QFS_EINVAL;
+    }
+    b.src = psiv;
+    b.ref = phiv;
+    b.partials = val_partials;
+    b.nch = gv->nch;
+    b.kapply = L;
+    nz = 2;
+  }
+  const int gx = std::max(a.nch, gv ? b.nch : 0);
+  const size_t chunk_bytes = (size_t(1) << (g.n + g.logC)) * sizeof(cx<R>);
+  const size_t gate_bytes = (size_t)16 * L * sizeof(cx<R>);
+  const int gates_in_lds = chunk_bytes + gate_bytes <= 160 * 1024 ? 1 : 0;
+  const size_t lds = chunk_bytes + (gates_in_lds ? gate_bytes : 0);
+  const int64_t items = int64_t(1) << (g.n + g.logC - 4);
+  const int threads = items >= 1024 ? 1024 : 512;
+  auto go = [&](auto kernel) -> int {
+    static size_t attr = 0;
+    if (lds > 64 * 1024 && lds > attr) {
+      QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      attr = lds;
+    }
+    hipLaunchKernelGGL(kernel, dim3(gx * nz, nslots, 1), dim3(threads), lds, s, a, b, nz, g.n, g.logC, plan_dev,
+                       ngroups, gslot_dev, static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, L,
+                       gates_in_lds);
+    QFS_HIP(hipGetLastError());
+    return QFS_OK;
+  };
+  if (threads == 1024) return go(k_forward_groups<R, 1024>);
+  return go(k_forward_groups<R, 512>);
+}
+
+#define QFS_FINST(R)                                                                              \
+  template int launch_forward_groups<R>(const Geometry &, const Geometry *, int, GateRef, const cx<R> *, \
+                                        cx<R> *, int64_t, const cx<R> *, double *, const cx<R> *,  \
+                                        const cx<R> *, double *, const int32_t *, int,            \
+                                        const int32_t *, int, const int32_t *, hipStream_t);
+QFS_FINST(float)
+#undef QFS_FINST
 
 #define QFS_GINST(R)                                                                          \
   template int launch_group_pass<R>(const Geometry &, const int32_t *, const GateGroup *,      \

@@ -63,9 +63,12 @@ __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c1
     g = gm(r, c);
     v = cmake(r == c ? 1.0 : 0.0, 0.0);
   }
+  // Cyclic Jacobi converges quadratically: a sweep whose rotations all started from a
+  // relative off-diagonal Gram entry below 1e-7 leaves them at the 1e-14 level, so the
+  // iteration stops after it instead of running a further sweep that rotates nothing.
   bool converged = false;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    int rotated = 0;
+    int large = 0;
 #pragma unroll
     for (int m = 4; m <= 12; m += 4) {
       const c128 go = cmake(__shfl_xor(g.re, m), __shfl_xor(g.im, m));
@@ -84,10 +87,12 @@ __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c1
         gi += __shfl_xor(gi, o);
       }
       const double ag = sqrt(gr * gr + gi * gi);
-      if (ag > 0.0 && ag > 1e-15 * sqrt(al * be)) {
-        rotated = 1;
-        const c128 ec = cmake(gr / ag, -gi / ag);  // conj(e^{i phi})
-        const double tau = (be - al) / (2.0 * ag);
+      const double gsc = sqrt(al * be);
+      if (ag > 0.0 && ag > 1e-15 * gsc) {
+        large |= ag > 1e-7 * gsc;
+        const double rag = 1.0 / ag;
+        const c128 ec = cmake(gr * rag, -gi * rag);  // conj(e^{i phi})
+        const double tau = (be - al) * (0.5 * rag);
         const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
         const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
         const c128 egq = ec * gq, evq = ec * vq;
@@ -100,7 +105,7 @@ __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c1
         }
       }
     }
-    if (!__any(rotated)) {
+    if (!__any(large)) {
       converged = true;
       break;
     }

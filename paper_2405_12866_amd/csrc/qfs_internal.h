@@ -340,6 +340,18 @@ int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *
                       const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
                       SBuf<R> b, const int32_t *slot_to_start, int nslots, int blocks_per_start,
                       c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s);
+// Forward pass by gate groups (the groups in forward order, one LDS round trip per group;
+// complex64 states, the products on the matrix cores):
+// plan [ngroups][8] and per-gate slots [L][2] from build_forward_plan (host; bneed_host
+// [L] marks the B entries the backward pass reads), copied to the device by the caller.
+int build_forward_plan(const Geometry &g, int L, const int32_t *pairs, const std::vector<GateGroup> &groups,
+                       const int32_t *bneed_host, std::vector<int32_t> &plan, std::vector<int32_t> &gslot);
+template <typename R>
+int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef gates, const cx<R> *psi,
+                          cx<R> *blist, int64_t bstride, const cx<R> *phi_ref, double *c0_partials,
+                          const cx<R> *psiv, const cx<R> *phiv, double *val_partials,
+                          const int32_t *slot_to_start, int nslots, const int32_t *plan_dev, int ngroups,
+                          const int32_t *gslot_dev, hipStream_t s);
 // Work-groups per start of a grouped pass when `running_starts` starts sweep together
 // (whatever streams they are split over).
 int group_blocks_per_start(int running_starts);

@@ -73,4 +73,47 @@ __device__ __forceinline__ void load_gate(P src, cx<R> (&u)[16], bool dagger) {
     }
 }
 
+// A 4x4 complex64 gate applied by the matrix cores to each lane's own four amplitudes.
+// The 16-block 4x4x1 FP32 MFMA forms, in block b (lanes 4b .. 4b+3), D[i][j] += a_i b_j with
+// a_i, b_j supplied by lanes 4b + i and 4b + j and D[i][j] returned in lane 4b + j,
+// register i. With lane 4b + i supplying u[i][p] and every lane its own x[p], the four
+// K-steps p give every lane its own (u x)[i]: the per-thread matrix-vector product of the
+// vector ALU at twice its FP32 rate, in the same data layout. All 64 lanes must execute it.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+struct Gate4 {
+  float re[4], im[4], nim[4];  // row (lane % 4) of the gate, column p
+};
+
+// Row lane % 4 of gate src (row-major 4x4), in the local basis with indices 1 and 2
+// exchanged when swapped.
+template <typename P>
+__device__ __forceinline__ Gate4 gate4_row(P src, bool swapped) {
+  constexpr int pm[4] = {0, 2, 1, 3};
+  const int r = threadIdx.x & 3;
+  const int rr = swapped ? pm[r] : r;
+  Gate4 G;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int pp = swapped ? pm[p] : p;
+    const float re = (float)src[rr * 4 + pp].re, im = (float)src[rr * 4 + pp].im;
+    G.re[p] = re;
+    G.im[p] = im;
+    G.nim[p] = -im;
+  }
+  return G;
+}
+
+__device__ __forceinline__ void gate4_apply(const Gate4 &G, const c64 (&x)[4], c64 (&y)[4]) {
+  f32x4_t dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    dr = __builtin_amdgcn_mfma_f32_4x4x1f32(G.re[p], x[p].re, dr, 0, 0, 0);
+    dr = __builtin_amdgcn_mfma_f32_4x4x1f32(G.nim[p], x[p].im, dr, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f32_4x4x1f32(G.re[p], x[p].im, di, 0, 0, 0);
+    di = __builtin_amdgcn_mfma_f32_4x4x1f32(G.im[p], x[p].re, di, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) y[i] = cmake(dr[i], di[i]);
+}
+
 }  // namespace qfs

@@ -221,8 +221,13 @@ __device__ __forceinline__ void forward_run(cx<R> *lds, uint32_t groups, int log
                                             int k0, int run, uint32_t store_mask, cx<R> *blist,
                                             int64_t sN) {
   constexpr int V = Pk<R>::V;
+  constexpr bool MF = std::is_same<R, float>::value;  // complex64: products on the matrix cores
   const int FB = blockDim.x;
-  for (uint32_t gi = threadIdx.x; gi < groups; gi += FB) {
+  const uint32_t lane = threadIdx.x & 63u;
+  // (wave-uniform trip count: every lane of a wave runs the matrix-core products)
+  for (uint32_t gb = threadIdx.x - lane; gb < groups; gb += FB) {
+    const uint32_t gi = gb + lane;
+    const bool ok = gi < groups;
     const uint32_t jv = gi & ((1u << logJ) - 1u);
     const uint32_t i0 = deposit(gi >> logJ, sorted, 2);
     uint32_t o[4];
@@ -232,10 +237,38 @@ __device__ __forceinline__ void forward_run(cx<R> *lds, uint32_t groups, int log
     o[3] = ((i0 + ma + mb) << logC) + jv * V;
     Pk<R> x[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) x[p] = ld_pk(lds + o[p]);
+    for (int p = 0; p < 4; ++p) {
+      if (ok) {
+        x[p] = ld_pk(lds + o[p]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[p].v[e] = cmake<R>(0, 0);
+      }
+    }
     for (int j = 0; j < run; ++j) {
       const int k = k0 + j;
       const bool swapped = pairs[2 * k] != pairs[2 * k0];
+      if constexpr (MF) {
+        const Gate4 G4 = gate4_row(g + k * 16, swapped);
+        Pk<R> y[4];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          c64 xe[4], ye[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) xe[p] = x[p].v[e];
+          gate4_apply(G4, xe, ye);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) y[p].v[e] = ye[p];
+        }
+        if (ok && blist && ((store_mask >> j) & 1u)) {
+          cx<R> *dst = blist + sN * k;
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) st_pk(dst + o[qq], y[qq]);
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) x[qq] = y[qq];
+        continue;
+      }
       cx<R> u[16];
       load_gate<R>(g + k * 16, u, false);
       if (swapped) {
@@ -268,7 +301,7 @@ __device__ __forceinline__ void forward_run(cx<R> *lds, uint32_t groups, int log
         product(std::integral_constant<int, 1>{});
       else
         product(std::integral_constant<int, 2>{});
-      if (blist && ((store_mask >> j) & 1u)) {
+      if (ok && blist && ((store_mask >> j) & 1u)) {
         cx<R> *dst = blist + sN * k;
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) st_pk(dst + o[qq], y[qq]);
@@ -276,8 +309,10 @@ __device__ __forceinline__ void forward_run(cx<R> *lds, uint32_t groups, int log
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) x[qq] = y[qq];
     }
+    if (ok) {
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) st_pk(lds + o[qq], x[qq]);
+      for (int qq = 0; qq < 4; ++qq) st_pk(lds + o[qq], x[qq]);
+    }
   }
 }
 
@@ -359,6 +394,48 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
     // a one-qubit slot is v (x) I_2: output 2i + j mixes inputs j and 2 + j only, so half
     // of the products (those with the slot's exact zeros) are skipped; the remaining ones
     // are accumulated in the same order, so the result is that of the full product
+    if constexpr (std::is_same<R, float>::value) {
+      // complex64: the products on the matrix cores (wave-uniform trip count)
+      const Gate4 G4 = gate4_row(gates + (int64_t)s * gstride + k * 16, false);
+      const uint32_t lane = threadIdx.x & 63u;
+      for (uint32_t gb = threadIdx.x - lane; gb < groups; gb += FB) {
+        const uint32_t g = gb + lane;
+        const bool ok = g < groups;
+        const uint32_t jv = g & ((1u << logJ) - 1u);
+        const uint32_t i0 = deposit(g >> logJ, sorted, 2);
+        uint32_t o[4];
+        o[0] = (i0 << logC) + jv * V;
+        o[1] = ((i0 + mb) << logC) + jv * V;
+        o[2] = ((i0 + ma) << logC) + jv * V;
+        o[3] = ((i0 + ma + mb) << logC) + jv * V;
+        Pk<R> x[4], y[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          if (ok) {
+            x[p] = ld_pk(lds + o[p]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) x[p].v[e] = cmake<R>(0, 0);
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          c64 xe[4], ye[4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) xe[p] = x[p].v[e];
+          gate4_apply(G4, xe, ye);
+#pragma unroll
+          for (int p = 0; p < 4; ++p) y[p].v[e] = ye[p];
+        }
+        if (ok) {
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            st_pk(lds + o[qq], y[qq]);
+            if (store && !late) st_pk(dst + o[qq], y[qq]);
+          }
+        }
+      }
+    }
     auto apply = [&](auto one_qubit) {
       constexpr bool ONEQ = decltype(one_qubit)::value;
       for (uint32_t g = threadIdx.x; g < groups; g += FB) {
@@ -388,10 +465,12 @@ __global__ __launch_bounds__(FB) void k_forward_fused(FwdSeg<R> seg0, FwdSeg<R> 
         }
       }
     };
-    if (kinds && kinds[k] == QFS_GATE_1Q)
-      apply(std::true_type{});
-    else
-      apply(std::false_type{});
+    if constexpr (!std::is_same<R, float>::value) {
+      if (kinds && kinds[k] == QFS_GATE_1Q)
+        apply(std::true_type{});
+      else
+        apply(std::false_type{});
+    }
     __syncthreads();
     if (late) {
       for (uint32_t e = threadIdx.x * V; e < chunk; e += FB * V) st_pk(dst + e, ld_pk(lds + e));
