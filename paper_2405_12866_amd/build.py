@@ -24,6 +24,12 @@ FLAGS = [
 ]
 
 
+# Per-source flags. group.hip: common-code sinking off, so the switch over a gate's item
+# slots keeps one body per case and the 16-element items stay in registers (merged cases
+# select between array elements, which moves the items to scratch memory).
+SOURCE_FLAGS = {"group.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every source (always, even when a library exists) and link."""
     objdir = os.path.join(HERE, "_build")
@@ -32,7 +38,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc", *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

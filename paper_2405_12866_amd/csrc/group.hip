@@ -34,6 +34,12 @@
 #include <cstring>
 #include <type_traits>
 
+// complex64 forward products: 1 on the matrix cores (4x4x1 MFMA), 0 on the vector ALU (the
+// two measured within 7 % of each other on MI355X, the matrix cores ahead)
+#ifndef QFS_FWD_MFMA
+#define QFS_FWD_MFMA 1
+#endif
+
 #include "polar2.h"
 #include "polar4.h"
 #include "qfs_internal.h"
@@ -506,54 +512,66 @@ struct FwdGroupSeg {
 // the slots of its two qubits at gslot[2k], gslot[2k + 1].
 constexpr int kFwdPlan = 8;
 
-template <int SA, int SB, typename R>
-__device__ __forceinline__ void item_gate(cx<R> (&x)[16], const cx<R> (&u)[16], const Gate4 &G4) {
+// Gate on item slots (SA, SB) applied to the four amplitudes whose other two slots take the
+// value C; every index is a compile-time constant, so the item stays in registers.
+template <int SA, int SB, int C, typename R, bool MF>
+__device__ __forceinline__ void item_quad(cx<R> (&x)[16], const cx<R> (&u)[16], const Gate4 &G4) {
   constexpr int o0 = (0 != SA && 0 != SB) ? 0 : (1 != SA && 1 != SB) ? 1 : 2;
   constexpr int o1 = (3 != SA && 3 != SB) ? 3 : (2 != SA && 2 != SB && 2 != o0) ? 2 : 1;
+  constexpr int cb = ((C >> 1) << o0) | ((C & 1) << o1);
+  constexpr int i0 = cb, i1 = cb | (1 << SB), i2 = cb | (1 << SA), i3 = cb | (1 << SA) | (1 << SB);
+  if constexpr (std::is_same<R, float>::value && MF) {
+    const c64 xi[4] = {x[i0], x[i1], x[i2], x[i3]};
+    c64 yo[4];
+    gate4_apply(G4, xi, yo);
+    x[i0] = yo[0];
+    x[i1] = yo[1];
+    x[i2] = yo[2];
+    x[i3] = yo[3];
+  } else {
+    const cx<R> xi[4] = {x[i0], x[i1], x[i2], x[i3]};
+    cx<R> yo[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int cb = ((c >> 1) << o0) | ((c & 1) << o1);
-    int idx[4];
+    for (int q = 0; q < 4; ++q) {
+      cx<R> acc = cmake<R>(0, 0);
 #pragma unroll
-    for (int l = 0; l < 4; ++l) idx[l] = cb | ((l >> 1) << SA) | ((l & 1) << SB);
-    if constexpr (std::is_same<R, float>::value) {
-      c64 xi[4], yo[4];
-#pragma unroll
-      for (int l = 0; l < 4; ++l) xi[l] = x[idx[l]];
-      gate4_apply(G4, xi, yo);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) x[idx[l]] = yo[l];
-    } else {
-      cx<R> yo[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cx<R> acc = cmake<R>(0, 0);
-#pragma unroll
-        for (int p = 0; p < 4; ++p) cfma(acc, u[q * 4 + p], x[idx[p]]);
-        yo[q] = acc;
-      }
-#pragma unroll
-      for (int l = 0; l < 4; ++l) x[idx[l]] = yo[l];
+      for (int p = 0; p < 4; ++p) cfma(acc, u[q * 4 + p], xi[p]);
+      yo[q] = acc;
     }
+    x[i0] = yo[0];
+    x[i1] = yo[1];
+    x[i2] = yo[2];
+    x[i3] = yo[3];
   }
 }
 
-template <typename R>
+template <int SA, int SB, typename R, bool MF>
+__device__ __forceinline__ void item_gate(cx<R> (&x)[16], const cx<R> (&u)[16], const Gate4 &G4) {
+  // (a convergent no-op keeps the compiler from merging the twelve slot cases into one body
+  // that selects between array elements, which would move the item out of registers)
+  __builtin_amdgcn_wave_barrier();
+  item_quad<SA, SB, 0, R, MF>(x, u, G4);
+  item_quad<SA, SB, 1, R, MF>(x, u, G4);
+  item_quad<SA, SB, 2, R, MF>(x, u, G4);
+  item_quad<SA, SB, 3, R, MF>(x, u, G4);
+}
+
+template <typename R, bool MF>
 __device__ __forceinline__ void item_gate_slots(int sa, int sb, cx<R> (&x)[16], const cx<R> (&u)[16],
                                                 const Gate4 &G4) {
   switch (sa * 4 + sb) {
-    case 1: item_gate<0, 1, R>(x, u, G4); break;
-    case 2: item_gate<0, 2, R>(x, u, G4); break;
-    case 3: item_gate<0, 3, R>(x, u, G4); break;
-    case 4: item_gate<1, 0, R>(x, u, G4); break;
-    case 6: item_gate<1, 2, R>(x, u, G4); break;
-    case 7: item_gate<1, 3, R>(x, u, G4); break;
-    case 8: item_gate<2, 0, R>(x, u, G4); break;
-    case 9: item_gate<2, 1, R>(x, u, G4); break;
-    case 11: item_gate<2, 3, R>(x, u, G4); break;
-    case 12: item_gate<3, 0, R>(x, u, G4); break;
-    case 13: item_gate<3, 1, R>(x, u, G4); break;
-    default: item_gate<3, 2, R>(x, u, G4); break;
+    case 1: item_gate<0, 1, R, MF>(x, u, G4); break;
+    case 2: item_gate<0, 2, R, MF>(x, u, G4); break;
+    case 3: item_gate<0, 3, R, MF>(x, u, G4); break;
+    case 4: item_gate<1, 0, R, MF>(x, u, G4); break;
+    case 6: item_gate<1, 2, R, MF>(x, u, G4); break;
+    case 7: item_gate<1, 3, R, MF>(x, u, G4); break;
+    case 8: item_gate<2, 0, R, MF>(x, u, G4); break;
+    case 9: item_gate<2, 1, R, MF>(x, u, G4); break;
+    case 11: item_gate<2, 3, R, MF>(x, u, G4); break;
+    case 12: item_gate<3, 0, R, MF>(x, u, G4); break;
+    case 13: item_gate<3, 1, R, MF>(x, u, G4); break;
+    default: item_gate<3, 2, R, MF>(x, u, G4); break;
   }
 }
 
@@ -588,6 +606,9 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
   cx<R> *bl = sg.blist ? sg.blist + sg.bstride * s + cbase : nullptr;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nitems = chunk >> 4;
+  // complex64: the products on the matrix cores (splitting the waves between the matrix
+  // cores and the vector ALU measured slower)
+  const bool mf = std::is_same<R, float>::value && QFS_FWD_MFMA;
   for (int gi = 0; gi < ngroups; ++gi) {
     const cptr<int32_t> pg = plan + gi * kFwdPlan;
     const int k_lo = pg[0], k_hi = pg[1];
@@ -630,13 +651,19 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
         const int sa = gslot[2 * k], sb = gslot[2 * k + 1];
         Gate4 G4;
         cx<R> u[16];
-        if constexpr (std::is_same<R, float>::value) {
+        if (mf) {
           G4 = gates_in_lds ? gate4_row(lgates + k * 16, false) : gate4_row(gates_c + k * 16, false);
+          item_gate_slots<R, true>(sa, sb, x, u, G4);
         } else {
+          if (gates_in_lds) {
 #pragma unroll
-          for (int e = 0; e < 16; ++e) u[e] = cmake<R>(gates_c[k * 16 + e].re, gates_c[k * 16 + e].im);
+            for (int e = 0; e < 16; ++e) u[e] = lgates[k * 16 + e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) u[e] = cmake<R>(gates_c[k * 16 + e].re, gates_c[k * 16 + e].im);
+          }
+          item_gate_slots<R, false>(sa, sb, x, u, G4);
         }
-        item_gate_slots<R>(sa, sb, x, u, G4);
       }
       if (ok) {
 #pragma unroll
