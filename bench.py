@@ -28,13 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "instantiation sweeps/s + time-to-dist 1e-8 (12q, HBM GB/s); batched vs plain"
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_bwd_step_12q_M256_S16_pmc.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_12866_amd", "csrc", "sweep.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_bwd_group_12q_M256_S16_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_12866_amd", "csrc", "group.hip")
 
 
 def measured_traffic():
-    """HBM bytes per k_bwd_step launch from the committed PMC summary, when it was taken
-    on the current kernel source (sha256 of sweep.hip recorded there); else None."""
+    """HBM bytes per k_bwd_group launch from the committed PMC summary, when it was taken
+    on the current kernel source (sha256 of group.hip recorded there); else None."""
     import hashlib
     try:
         with open(PMC_SUMMARY) as f:
@@ -616,13 +616,16 @@ def main():
                                      params=dict(base, max_iter=args.steps, timing=1))
         kl, ks, kb = tinfo["kernel_launches"], tinfo["kernel_seconds"], tinfo["kernel_bytes"]
         if kl[0] > 0:
-            # algorithmic bytes of a backward step (the method's minimum: B_k written once
-            # by the forward pass and read once here, the running state kept on chip): b S
-            # per start per step, plus U psi read once per sweep (b = 8, complex64). With
-            # timing on, every step launch covers all running starts (one stream), and the
-            # bench disables the plateau stop, so every launch covers all S starts.
+            # algorithmic bytes of the backward pass (the method's minimum: every B_k
+            # written once by the forward pass and read once here, the running state kept
+            # on chip): b S per start for each of the L gates, plus U psi read once per
+            # sweep (b = 8, complex64). The grouped passes cover a group of gates per
+            # launch, so per launch this is (L + 1) b S per start-sweep over the passes of
+            # a sweep. With timing on, every launch covers all running starts (one
+            # stream), and the bench disables the plateau stop, so every launch covers all
+            # S starts.
             sweeps = tinfo["start_sweeps"] / S
-            alg = (kl[0] + sweeps) * S * 8.0 * S_amp
+            alg = sweeps * S * (L + 1) * 8.0 * S_amp
             achieved = alg / ks[0] / 1e9
             kernel_moved = kb[0] / ks[0] / 1e9  # what the kernel itself reads and writes
             traffic = measured_traffic()
@@ -631,9 +634,11 @@ def main():
                     "traffic": traffic,
                     "traffic_source": ("rocprofv3 --pmc FETCH_SIZE + WRITE_SIZE of this kernel, from the "
                                        "committed summary taken on the current kernel source "
-                                       "(profiles/k_bwd_step_12q_M256_S16_pmc.md), calibrated on a "
+                                       "(profiles/k_bwd_group_12q_M256_S16_pmc.md), calibrated on a "
                                        "256 MiB device copy") if traffic else None,
-                    "kernel": "k_bwd_step (apply u^dag + environment partial sums)",
+                    "kernel": ("k_bwd_group (one pass per gate group: the previous group's 16x16 "
+                               "operator and the group's 16x16 second-moment matrix on the matrix cores)"),
+                    "launches_per_sweep": round(kl[0] / sweeps, 2),
                     "avg_launch_us": round(1e6 * ks[0] / kl[0], 2),
                     "algorithmic_bytes_per_launch": alg / kl[0],
                     "kernel_moved_bytes_per_launch": kb[0] / kl[0],

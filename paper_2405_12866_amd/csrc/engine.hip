@@ -139,28 +139,26 @@ class KernelTimer {
   bool on = false;
   int begin(hipStream_t s) {
     if (!on) return QFS_OK;
-    if (ev_.size() < 2 * (used_ + 1)) {
-      hipEvent_t a, b;
-      QFS_HIP(hipEventCreate(&a));
-      QFS_HIP(hipEventCreate(&b));
-      ev_.push_back(a);
-      ev_.push_back(b);
-    }
+    QFS_TRY(reserve());
     QFS_HIP(hipEventRecord(ev_[2 * used_], s));
     return QFS_OK;
   }
   int end(hipStream_t s, int cls, double bytes) {
     if (!on) return QFS_OK;
     QFS_HIP(hipEventRecord(ev_[2 * used_ + 1], s));
-    if (cls_.size() <= used_) {
-      cls_.resize(used_ + 1);
-      bytes_.resize(used_ + 1);
-    }
-    cls_[used_] = cls;
-    bytes_[used_] = bytes;
-    ++used_;
+    return count(cls, bytes);
+  }
+  // The next pair of events for a launch that records them itself (LaunchEvents, null
+  // when timing is off); ext_end books it like end().
+  int ext_begin(LaunchEvents *le) {
+    *le = LaunchEvents{};
+    if (!on) return QFS_OK;
+    QFS_TRY(reserve());
+    le->start = ev_[2 * used_];
+    le->stop = ev_[2 * used_ + 1];
     return QFS_OK;
   }
+  int ext_end(int cls, double bytes) { return on ? count(cls, bytes) : QFS_OK; }
   // Call only after the stream has been synchronised.
   int flush(Counters &r) {
     for (size_t i = 0; i < used_; ++i) {
@@ -175,6 +173,26 @@ class KernelTimer {
   }
 
  private:
+  int reserve() {
+    if (ev_.size() < 2 * (used_ + 1)) {
+      hipEvent_t a, b;
+      QFS_HIP(hipEventCreate(&a));
+      QFS_HIP(hipEventCreate(&b));
+      ev_.push_back(a);
+      ev_.push_back(b);
+    }
+    return QFS_OK;
+  }
+  int count(int cls, double bytes) {
+    if (cls_.size() <= used_) {
+      cls_.resize(used_ + 1);
+      bytes_.resize(used_ + 1);
+    }
+    cls_[used_] = cls;
+    bytes_[used_] = bytes;
+    ++used_;
+    return QFS_OK;
+  }
   std::vector<hipEvent_t> ev_;
   std::vector<int> cls_;
   std::vector<double> bytes_;
@@ -346,6 +364,7 @@ int grouped_item(SweepCtx &c, const int32_t *slots, int n, hipStream_t st, int i
   const std::vector<GateGroup> &G = *c.groups;
   const int ng = (int)G.size();
   const double set = set_bytes<R>(c, c.g) * n / c.nslots;
+  LaunchEvents le;
   if (item < ng) {
     const GateGroup &cur = G[item];
     const GateGroup *prev = item ? &G[item - 1] : nullptr;
@@ -355,28 +374,28 @@ int grouped_item(SweepCtx &c, const int32_t *slots, int n, hipStream_t st, int i
       const SBuf<R> a_in = item <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN};
       const SBuf<R> a_out = prev ? SBuf<R>{A, sN} : SBuf<R>{nullptr, 0};
       const SBuf<R> b = cur.k_lo == 0 ? SBuf<R>{psi, 0} : SBuf<R>{B + (cur.k_lo - 1) * sN, bstride};
-      QFS_TRY(T.begin(st));
+      QFS_TRY(T.ext_begin(&le));
       QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, prev, &cur, false, c.vop, a_in, a_out, b, slots, n,
                                    group_blocks_per_start(c.nslots), c.gpartials, c.gpstride, nullptr, &P,
-                                   st));
-      QFS_TRY(T.end(st, kClsStep, set * ((prev ? 2.0 : 1.0) + (cur.nvar > 0 ? 1.0 : 0.0))));
+                                   st, le));
+      QFS_TRY(T.ext_end(kClsStep, set * ((prev ? 2.0 : 1.0) + (cur.nvar > 0 ? 1.0 : 0.0))));
     }
     // (a group with nothing to reduce still forms its operator for the next pass)
-    QFS_TRY(T.begin(st));
+    QFS_TRY(T.ext_begin(&le));
     QFS_TRY(launch_group_finalize(cur.nvar > 0 ? P : 0, c.gpartials, c.gpstride, slots, n, cur, c.pairs_host,
                                   c.kinds, c.beta, c.g64, sizeof(R) == 4 ? c.g32 : nullptr, c.L * 16,
-                                  c.vstore, c.vop, st));
-    QFS_TRY(T.end(st, kClsPolar, (double)P * 4096.0 * n));
+                                  c.vstore, c.vop, st, le));
+    QFS_TRY(T.ext_end(kClsPolar, (double)P * 4096.0 * n));
     return QFS_OK;
   }
   if (item == ng) {
     int P = 0;
-    QFS_TRY(T.begin(st));
+    QFS_TRY(T.ext_begin(&le));
     QFS_TRY(launch_group_pass<R>(c.g, c.pairs_host, &G.back(), nullptr, true, c.vop,
                                  ng <= 1 ? SBuf<R>{phi, 0} : SBuf<R>{A, sN}, SBuf<R>{nullptr, 0},
                                  SBuf<R>{psi, 0}, slots, n, group_blocks_per_start(c.nslots), nullptr, kGPcap,
-                                 c.dpart0, &P, st));
-    QFS_TRY(T.end(st, kClsDist, 2.0 * set));
+                                 c.dpart0, &P, st, le));
+    QFS_TRY(T.ext_end(kClsDist, 2.0 * set));
     return launch_dist_finalize(P, c.dpart0, slots, n, c.g.M, c.costs, st, kGPcap);
   }
   SweepCtx sub = c;
@@ -386,20 +405,39 @@ int grouped_item(SweepCtx &c, const int32_t *slots, int n, hipStream_t st, int i
   return sweep_forward<R>(sub, false);
 }
 
+// The parts a grouped sweep of the running starts runs in: without timing, and while every
+// part still streams at least 2^20 amplitudes per pass, up to nparts consecutive ranges of
+// the slot list, part p on pstream[p] (part 0 on the call's stream). off[p] is the part's
+// first slot; returns the number of parts.
+int sweep_parts(const SweepCtx &c, int off[], int pn[], hipStream_t pst[]) {
+  int parts = c.timer->on ? 1 : std::min(c.nparts, c.nslots);
+  while (parts > 1 && (int64_t)(c.nslots / parts) * c.g.elems() < (int64_t(1) << 20)) --parts;
+  parts = std::max(parts, 1);
+  const int base = c.nslots / parts, extra = c.nslots % parts;
+  for (int p = 0, o = 0; p < parts; ++p) {
+    pn[p] = base + (p < extra ? 1 : 0);
+    off[p] = o;
+    o += pn[p];
+    pst[p] = p == 0 ? c.stream : c.pstream[p];
+  }
+  return parts;
+}
+
 // One grouped sweep of the running starts: backward pass and cost, then (with_forward)
-// the forward pass of the updated gates, which also gives their validation cost. Without
-// timing, and when every part still streams at least 2^20 amplitudes per pass, the starts
-// run in up to four parts on their own streams (see SweepCtx::pstream); the host issues the
-// parts' items round robin, part p `lag` items behind part p - 1, so the parts' chains of
-// dependent launches advance together and the arithmetic-bound forward pass of one part
-// runs beside the bandwidth-bound passes of the others.
+// the forward pass of the updated gates, which also gives their validation cost, in the
+// parts of sweep_parts. The host issues the parts' items round robin, part p `lag` items
+// behind part p - 1, so the parts' chains of dependent launches advance together and the
+// arithmetic-bound forward pass of one part runs beside the bandwidth-bound passes of the
+// others. The part streams are forked from and joined to the call's stream around the
+// sweep, unless `ordered` says the caller already ordered them (the control loop keeps
+// them running from one sweep into the next).
 template <typename R>
-int sweep_grouped(SweepCtx &c, bool with_forward) {
-  KernelTimer &T = *c.timer;
+int sweep_grouped(SweepCtx &c, bool with_forward, bool ordered = false) {
   const int ng = (int)c.groups->size();
   const int items = ng + 1 + (with_forward ? 1 : 0);
-  int parts = T.on ? 1 : std::min(c.nparts, c.nslots);
-  while (parts > 1 && (int64_t)(c.nslots / parts) * c.g.elems() < (int64_t(1) << 20)) --parts;
+  int off[SweepCtx::kParts], pn[SweepCtx::kParts];
+  hipStream_t pst[SweepCtx::kParts];
+  const int parts = sweep_parts(c, off, pn, pst);
   if (parts <= 1) {
     for (int i = 0; i < items; ++i) QFS_TRY(grouped_item<R>(c, c.slots, c.nslots, c.stream, i));
     return QFS_OK;
@@ -409,27 +447,20 @@ int sweep_grouped(SweepCtx &c, bool with_forward) {
     return e ? std::atoi(e) : -1;
   }();
   const int lag = lag_env >= 0 ? std::min(lag_env, items) : std::max(1, ng / (2 * parts));
-  QFS_HIP(hipEventRecord(c.pfork, c.stream));
-  const int32_t *pslots[SweepCtx::kParts];
-  int pn[SweepCtx::kParts];
-  hipStream_t pst[SweepCtx::kParts];
-  const int base = c.nslots / parts, extra = c.nslots % parts;
-  for (int p = 0, off = 0; p < parts; ++p) {
-    pn[p] = base + (p < extra ? 1 : 0);
-    pslots[p] = c.slots + off;
-    off += pn[p];
-    pst[p] = p == 0 ? c.stream : c.pstream[p];
-    if (p > 0) QFS_HIP(hipStreamWaitEvent(pst[p], c.pfork, 0));
+  if (!ordered) {
+    QFS_HIP(hipEventRecord(c.pfork, c.stream));
+    for (int p = 1; p < parts; ++p) QFS_HIP(hipStreamWaitEvent(pst[p], c.pfork, 0));
   }
   for (int t = 0; t < items + lag * (parts - 1); ++t)
     for (int p = 0; p < parts; ++p) {
       const int i = t - p * lag;
-      if (i >= 0 && i < items) QFS_TRY(grouped_item<R>(c, pslots[p], pn[p], pst[p], i));
+      if (i >= 0 && i < items) QFS_TRY(grouped_item<R>(c, c.slots + off[p], pn[p], pst[p], i));
     }
-  for (int p = 1; p < parts; ++p) {
-    QFS_HIP(hipEventRecord(c.pjoin[p], pst[p]));
-    QFS_HIP(hipStreamWaitEvent(c.stream, c.pjoin[p], 0));
-  }
+  if (!ordered)
+    for (int p = 1; p < parts; ++p) {
+      QFS_HIP(hipEventRecord(c.pjoin[p], pst[p]));
+      QFS_HIP(hipStreamWaitEvent(c.stream, c.pjoin[p], 0));
+    }
   return QFS_OK;
 }
 
@@ -558,8 +589,10 @@ class Group {
   }
   ~Group() {
     if (h_costs_) (void)hipHostFree(h_costs_);
-    if (ev0_) (void)hipEventDestroy(ev0_);
-    if (ev1_) (void)hipEventDestroy(ev1_);
+    if (seg0_) (void)hipEventDestroy(seg0_);
+    for (auto &d : done_)
+      for (hipEvent_t e : d)
+        if (e) (void)hipEventDestroy(e);
     if (fork_) (void)hipEventDestroy(fork_);
     if (join_) (void)hipEventDestroy(join_);
     if (ctx_.pfork) (void)hipEventDestroy(ctx_.pfork);
@@ -608,8 +641,31 @@ class Group {
   DevBuf bneed_dev_, gpartials_, vop_, fplan_dev_, fgslot_dev_;
   std::vector<int32_t> bneed_h_, fplan_h_, fgslot_h_;
   int gpstride_ = 0;
-  double *h_costs_ = nullptr;  // pinned [3 S]: c_train, c_val, c_0
-  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  // pinned [1 + 2 kParts][3 S] (c_train, c_val, c_0): read_costs's copy, then one copy per
+  // sweep parity and part, written on the part's stream right after its sweep
+  double *h_costs_ = nullptr;
+  double *cost_buf(int par, int part) { return h_costs_ + (size_t)(1 + par * SweepCtx::kParts + part) * 3 * S_; }
+  // The control loop's sweeps: run-ahead (spec_), per sweep parity the starts and parts it
+  // was issued with and an event per part at its end (timing reference seg0_), and the
+  // snapshot of every start's gates after the sweep ([2][S][g64, g32, vstore]).
+  struct Issued {
+    std::vector<int> starts;
+    int parts = 1;
+    int off[SweepCtx::kParts] = {}, pn[SweepCtx::kParts] = {};
+  };
+  bool spec_ = false;
+  Issued issued_[2];
+  hipEvent_t done_[2][SweepCtx::kParts] = {};
+  hipEvent_t seg0_ = nullptr;
+  double seg_prev_ms_ = 0.0;
+  DevBuf snap_, rslots_;
+  size_t snap_bytes_per_start() const { return (size_t)L_ * 16 * (2 * sizeof(c128) + sizeof(c64)); }
+  SlotCopy snap_copy(int par, bool restore);
+  int begin_segment(bool new_ref);
+  int end_segment();
+  int issue_sweep(int par, const std::vector<int> &active);
+  int wait_sweep(int par, std::vector<double> &ct, std::vector<double> &cv, double &seconds);
+  int restore_gates(const std::vector<int> &starts, int par);
   KernelTimer timer_;
   SweepCtx ctx_;
   GroupResult *res_ = nullptr;
@@ -844,6 +900,111 @@ int Group::set_slots(const std::vector<int> &active) {
   return QFS_OK;
 }
 
+// Snapshot copies of every start's gates (both precisions) and Jacobi warm starts, to or
+// from the buffers of sweep parity par.
+SlotCopy Group::snap_copy(int par, bool restore) {
+  SlotCopy sc;
+  const size_t per = snap_bytes_per_start();
+  unsigned char *base = static_cast<unsigned char *>(snap_.ptr) + (size_t)par * per * S_;
+  const size_t b64 = sizeof(c128) * 16 * (size_t)L_ * S_, b32 = sizeof(c64) * 16 * (size_t)L_ * S_;
+  const void *live[3] = {g64_.ptr, g32_.ptr, vstore_.ptr};
+  const void *copy[3] = {base, base + b64, base + b64 + b32};
+  const int64_t units[3] = {(int64_t)L_ * 16, (int64_t)L_ * 8, (int64_t)L_ * 16};
+  for (int b = 0; b < 3; ++b) {
+    sc.src[b] = static_cast<const uint4 *>(restore ? copy[b] : live[b]);
+    sc.dst[b] = const_cast<uint4 *>(static_cast<const uint4 *>(restore ? live[b] : copy[b]));
+    sc.units[b] = units[b];
+  }
+  return sc;
+}
+
+// Order the part streams after the call's stream (and, with new_ref, restart the clock of
+// the sweeps that follow).
+int Group::begin_segment(bool new_ref) {
+  if (new_ref) {
+    QFS_HIP(hipEventRecord(seg0_, stream_));
+    seg_prev_ms_ = 0.0;
+  }
+  if (!ctx_.pfork) return QFS_OK;
+  QFS_HIP(hipEventRecord(ctx_.pfork, stream_));
+  for (int p = 1; p < SweepCtx::kParts; ++p)
+    if (ctx_.pstream[p]) QFS_HIP(hipStreamWaitEvent(ctx_.pstream[p], ctx_.pfork, 0));
+  return QFS_OK;
+}
+
+// Order the call's stream after everything issued on the part streams.
+int Group::end_segment() {
+  for (int p = 1; p < SweepCtx::kParts; ++p)
+    if (ctx_.pstream[p] && ctx_.pjoin[p]) {
+      QFS_HIP(hipEventRecord(ctx_.pjoin[p], ctx_.pstream[p]));
+      QFS_HIP(hipStreamWaitEvent(stream_, ctx_.pjoin[p], 0));
+    }
+  return QFS_OK;
+}
+
+// One sweep of the running starts (parity par). A grouped sweep without timing or graphs
+// runs its parts on their streams with no join, each part going on into its next sweep;
+// after each part: the snapshot of its gates (run-ahead only), its costs to the host and
+// its end event.
+int Group::issue_sweep(int par, const std::vector<int> &active) {
+  Issued &is = issued_[par];
+  is.starts = active;
+  hipStream_t pst[SweepCtx::kParts];
+  if (ctx_.grouped && !p_.graphs && !timer_.on) {
+    is.parts = sweep_parts(ctx_, is.off, is.pn, pst);
+    QFS_TRY(fp64_ ? sweep_grouped<double>(ctx_, true, true) : sweep_grouped<float>(ctx_, true, true));
+  } else {
+    is.parts = 1;
+    is.off[0] = 0;
+    is.pn[0] = ctx_.nslots;
+    pst[0] = stream_;
+    QFS_TRY(sweep_once());
+  }
+  for (int p = 0; p < is.parts; ++p) {
+    if (spec_) QFS_TRY(launch_copy_slots(ctx_.slots + is.off[p], is.pn[p], snap_copy(par, false), pst[p]));
+    QFS_HIP(hipMemcpyAsync(cost_buf(par, p), costs_.ptr, sizeof(double) * 3 * S_, hipMemcpyDeviceToHost, pst[p]));
+    QFS_HIP(hipEventRecord(done_[par][p], pst[p]));
+  }
+  return QFS_OK;
+}
+
+// Wait for sweep parity par and read its costs (each start from its part's copy); seconds
+// grows by the device time since the previous sweep's end.
+int Group::wait_sweep(int par, std::vector<double> &ct, std::vector<double> &cv, double &seconds) {
+  const Issued &is = issued_[par];
+  float end_ms = 0.f;
+  for (int p = 0; p < is.parts; ++p) {
+    QFS_HIP(hipEventSynchronize(done_[par][p]));
+    float ms = 0.f;
+    QFS_HIP(hipEventElapsedTime(&ms, seg0_, done_[par][p]));
+    end_ms = std::max(end_ms, ms);
+  }
+  seconds += 1e-3 * std::max(0.0, (double)end_ms - seg_prev_ms_);
+  seg_prev_ms_ = std::max(seg_prev_ms_, (double)end_ms);
+  if (res_ && timer_.on) {
+    QFS_HIP(hipStreamSynchronize(stream_));
+    QFS_TRY(timer_.flush(res_->k));
+  }
+  for (int p = 0; p < is.parts; ++p) {
+    const double *h = cost_buf(par, p);
+    for (int i = is.off[p]; i < is.off[p] + is.pn[p]; ++i) {
+      const int s = is.starts[i];
+      ct[s] = h[s];
+      cv[s] = h[S_ + s];
+    }
+  }
+  return QFS_OK;
+}
+
+// Gates and warm starts of the given starts back to the snapshot of sweep parity par, on
+// the call's stream (after end_segment).
+int Group::restore_gates(const std::vector<int> &starts, int par) {
+  if (starts.empty()) return QFS_OK;
+  QFS_HIP(hipMemcpyAsync(rslots_.ptr, starts.data(), sizeof(int32_t) * starts.size(), hipMemcpyHostToDevice,
+                         stream_));
+  return launch_copy_slots(rslots_.as<int32_t>(), (int)starts.size(), snap_copy(par, true), stream_);
+}
+
 int Group::read_costs(std::vector<double> &ct, std::vector<double> &cv, std::vector<double> *c0) {
   QFS_HIP(hipMemcpyAsync(h_costs_, costs_.ptr, sizeof(double) * 3 * S_, hipMemcpyDeviceToHost, stream_));
   QFS_HIP(hipStreamSynchronize(stream_));
@@ -872,9 +1033,11 @@ int Group::run(GroupResult &out, double t_start) {
   timer_.on = p_.timing != 0;
   res_ = &out;
 
-  QFS_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_costs_), sizeof(double) * 3 * S_));
-  QFS_HIP(hipEventCreate(&ev0_));
-  QFS_HIP(hipEventCreate(&ev1_));
+  QFS_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_costs_),
+                        sizeof(double) * 3 * S_ * (1 + 2 * SweepCtx::kParts)));
+  QFS_HIP(hipEventCreate(&seg0_));
+  for (auto &d : done_)
+    for (hipEvent_t &e : d) QFS_HIP(hipEventCreate(&e));
   QFS_TRY(arena_.alloc(dpart_, sizeof(double) * 2 * (size_t)kPcap * S_));
   QFS_TRY(arena_.alloc(costs_, sizeof(double) * 3 * S_));
   QFS_TRY(arena_.alloc(slots_, sizeof(int32_t) * S_));
@@ -981,18 +1144,28 @@ int Group::run(GroupResult &out, double t_start) {
     if (Mv_ == 0) cv[s] = ct[s];
   }
 
+  // Run-ahead: sweep t + 1 of the running starts is issued before the costs of sweep t are
+  // read, so the device never waits for the host's decisions. Its results are kept when
+  // every start continues (the usual case); a start that stops at sweep t gets the gates it
+  // had after sweep t back from the snapshot taken then, and a decision for all starts
+  // (success, over-training, the switch to complex128) undoes sweep t + 1 of every start
+  // before it acts, so the trajectory is that of one sweep at a time.
+  static const bool run_ahead_env = [] {
+    const char *e = std::getenv("QFS_RUN_AHEAD");  // tuning aid: 0 decides after every sweep
+    return !(e && std::atoi(e) == 0);
+  }();
+  spec_ = run_ahead_env && !timer_.on;
+  if (spec_) QFS_TRY(arena_.alloc(snap_, 2 * snap_bytes_per_start() * (size_t)S_));
+  QFS_TRY(arena_.alloc(rslots_, sizeof(int32_t) * S_));
   int chosen = -1;
+  int par = 0;  // parity of the sweep decided next (its snapshot and cost buffers)
+  QFS_TRY(begin_segment(true));
+  QFS_TRY(issue_sweep(par, active));
+  std::vector<double> nct(S_), ncv(S_);
   for (;;) {
-    // one sweep of every running start, then the next forward pass (which also gives
-    // the validation cost of the post-sweep gates)
-    QFS_HIP(hipEventRecord(ev0_, stream_));
-    QFS_TRY(sweep_once());
-    QFS_HIP(hipEventRecord(ev1_, stream_));
-    std::vector<double> nct(S_), ncv(S_);
-    QFS_TRY(read_costs(nct, ncv, nullptr));
-    float ms = 0.f;
-    QFS_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
-    out.sweep_seconds += 1e-3 * ms;
+    const bool ahead = spec_;
+    if (ahead) QFS_TRY(issue_sweep(par ^ 1, active));
+    QFS_TRY(wait_sweep(par, nct, ncv, out.sweep_seconds));
     ++round;
     out.start_sweeps += (int64_t)active.size();
     out.amp_updates += (double)active.size() * (double)(M_ + Mv_) * (double)N_ * (double)L_;
@@ -1007,6 +1180,40 @@ int Group::run(GroupResult &out, double t_start) {
                                total[s], c_prev[s], reason[s]);
       any_success |= status[s] == ST_STOP && reason[s] == QFS_SUCCESS;
       any_over |= status[s] == ST_OVER;
+    }
+    std::vector<int> next;
+    for (int s : active)
+      if (status[s] == ST_RUN) next.push_back(s);
+    // precision policy: complex128 refinement once the best running start is close
+    bool switch_now = false;
+    if (!fp64_ && !any_success && !any_over && !next.empty()) {
+      double best = INFINITY;
+      for (int s : next) best = std::min(best, ct[s]);
+      switch_now = best < p_.refine_below;
+    }
+    const bool all_continue = !any_success && !any_over && !switch_now && next.size() == active.size();
+    if (all_continue) {
+      if (!ahead) QFS_TRY(issue_sweep(par ^ 1, active));
+      par ^= 1;
+      continue;
+    }
+    // something changes: order the call's stream after every part, then undo sweep t + 1
+    // where its result is not kept. The survivors' sweep t + 1 is kept when only some starts
+    // stopped and the survivors' passes split their sums as they would have if issued now
+    // (grouped passes, same blocks per start), so that the result does not depend on the
+    // run-ahead, bit for bit.
+    const bool keep = ahead && !any_success && !any_over && !switch_now && !next.empty() && ctx_.grouped &&
+                      group_blocks_per_start((int)next.size()) == group_blocks_per_start((int)active.size());
+    QFS_TRY(end_segment());
+    if (ahead) {
+      if (keep) {
+        std::vector<int> stopped;
+        for (int s : active)
+          if (status[s] != ST_RUN) stopped.push_back(s);
+        QFS_TRY(restore_gates(stopped, par));
+      } else {
+        QFS_TRY(restore_gates(active, par));
+      }
     }
     if (any_success) {
       double best = INFINITY;
@@ -1068,11 +1275,11 @@ int Group::run(GroupResult &out, double t_start) {
       QFS_TRY(forward_any(true));
       QFS_TRY(read_costs(nct, ncv, &c0));
       for (int s : active) c_prev[s] = c0[s];
+      par = 0;
+      QFS_TRY(begin_segment(true));
+      QFS_TRY(issue_sweep(par, active));
       continue;
     }
-    std::vector<int> next;
-    for (int s : active)
-      if (status[s] == ST_RUN) next.push_back(s);
     if (next.empty()) {
       double best = INFINITY;
       for (int s = 0; s < S_; ++s)
@@ -1082,25 +1289,28 @@ int Group::run(GroupResult &out, double t_start) {
         }
       break;
     }
-    // precision policy: complex128 refinement once the best running start is close
-    bool switch_now = false;
-    if (!fp64_) {
-      double best = INFINITY;
-      for (int s : next) best = std::min(best, ct[s]);
-      switch_now = best < p_.refine_below;
-    }
-    if (next.size() != active.size()) {
-      // the forward pass just run already holds valid B lists for the survivors
-      active = next;
-      QFS_TRY(set_slots(active));
-    }
+    // the forward pass just run (in sweep t, or in sweep t + 1 when it is kept) holds valid
+    // B lists for the survivors
+    active = next;
+    QFS_TRY(set_slots(active));
     if (switch_now) {
       QFS_HIP(hipStreamSynchronize(stream_));
       fp64_ = true;
       out.refined = 1;
       QFS_TRY(setup_working());
       QFS_TRY(forward_any(false));  // B lists again, in complex128, from the FP64 gates
+      par = 0;
+      QFS_TRY(begin_segment(true));
+      QFS_TRY(issue_sweep(par, active));
+      continue;
     }
+    // some starts stopped, the others go on: sweep t + 1 of the survivors, when kept, is the
+    // next to decide (in the old parts; later sweeps use the new ones); else it is issued
+    // now, after a forward pass that rebuilds the B lists from the restored gates
+    if (ahead && !keep) QFS_TRY(forward_any(false));
+    QFS_TRY(begin_segment(false));
+    if (!keep) QFS_TRY(issue_sweep(par ^ 1, active));
+    par ^= 1;
   }
 
   out.best = start0_ + chosen;

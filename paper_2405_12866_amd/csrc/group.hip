@@ -104,7 +104,6 @@ struct GroupArgs {
   int32_t zpos[4];         // tile packet-bit positions of the four slots of the reduction
   int32_t nK;              // packet bits of the reduction index
   int32_t kpos[kMaxBits];  // their tile packet-bit positions (ascending)
-  int32_t dist;            // distance mode: sum |a - b|^2 after the operator
 };
 
 __device__ __forceinline__ uint32_t spread_bits(uint32_t x, const int32_t *pos, int nb) {
@@ -140,7 +139,10 @@ __device__ __forceinline__ void lds_elem_put(float4 *lds, uint32_t pk, int, c128
 // Packets per thread and set of one tile (tiles of at most 2048 packets).
 constexpr int kMaxPkt = 2048 / kGBlock;
 
-template <typename R>
+// DIST selects the distance pass (the last group's operator applied to the state, then
+// sum |a - b|^2) instead of the environment pass; each has its own kernel, so neither
+// carries the other's registers.
+template <typename R, bool DIST>
 __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
   constexpr int V = Pk<R>::V, LOGV = Pk<R>::LOGV;
   using MF = Mfma<R>;
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
         if (pk < npk) *reinterpret_cast<float4 *>(a_out + base + eo[u]) = la[lds_slot16(pk)];
       }
     }
-    if (A.env) {
+    if (!DIST && A.env) {
       acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ir = {0, 0, 0, 0}, ri = {0, 0, 0, 0};
       for (uint32_t j = wv; j < nkq; j += kGWaves) {
         const uint32_t pk = zoff | kkoff | (nK > 2 ? spread_bits(j, A.kpos + 2, nK - 2) : 0u);
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
         gim[v] += (double)ir[v] - (double)ri[v];
       }
     }
-    if (A.dist) {
+    if (DIST) {
 #pragma unroll
       for (int u = 0; u < kMaxPkt; ++u) {
         const uint32_t pk = tid + u * kGBlock;
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
     __syncthreads();
   }
 
-  if (A.env) {
+  if (!DIST && A.env) {
     // wave matrices -> block partial, summed over the waves in order in FP64
     double2 *red = reinterpret_cast<double2 *>(lds_raw);
 #pragma unroll
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
       A.partials[((int64_t)s * A.pstride + blockIdx.x) * 256 + tid] = cmake(acc.x, acc.y);
     }
   }
-  if (A.dist) {
+  if (DIST) {
     __shared__ double dred[kGWaves];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) dacc += __shfl_xor(dacc, o);
@@ -748,7 +750,11 @@ static int target_blocks() {
 }
 
 int group_blocks_per_start(int running_starts) {
-  return std::max(1, target_blocks() / std::max(1, running_starts));
+  // a power of two of starts, so that the split of the sums changes only when the number
+  // of running starts crosses one
+  int r = 1;
+  while (r < running_starts) r *= 2;
+  return std::max(1, target_blocks() / r);
 }
 
 int group_partials_stride(const Geometry &g, size_t rbytes) {
@@ -764,7 +770,8 @@ template <typename R>
 int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *prev,
                       const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
                       SBuf<R> b, const int32_t *slot_to_start, int nslots, int blocks_per_start,
-                      c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s) {
+                      c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s,
+                      LaunchEvents ev) {
   if (nslots <= 0) return QFS_OK;
   constexpr int LOGV = Pk<R>::LOGV;
   const int nC = g.n + g.logC;
@@ -838,7 +845,6 @@ int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *
     for (int p = 0, c = 0; p < nP; ++p)
       if (!used[p]) A.cpos[c++] = p;
   }
-  A.dist = dist ? 1 : 0;
   A.env = (!dist && cur && cur->nvar > 0) ? 1 : 0;
   if (A.env) {
     bool used[kMaxBits] = {};
@@ -849,18 +855,24 @@ int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *
   }
   const uint32_t npk = 1u << (A.nT - LOGV);
   const size_t lds = std::max<size_t>(2 * (size_t)(npk + (npk >> 4)) * 16, (size_t)kGWaves * 256 * 16);
-  static size_t attr[2] = {0, 0};
-  size_t &ab = attr[sizeof(R) == 4 ? 0 : 1];
+  static size_t attr[2][2] = {{0, 0}, {0, 0}};
+  size_t &ab = attr[sizeof(R) == 4 ? 0 : 1][dist ? 1 : 0];
+  const void *fn = dist ? reinterpret_cast<const void *>(k_bwd_group<R, true>)
+                        : reinterpret_cast<const void *>(k_bwd_group<R, false>);
   if (lds > 64 * 1024 && lds > ab) {
-    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_bwd_group<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    QFS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     ab = lds;
   }
   const int64_t tiles = (int64_t)g.nch << A.nX;
   const int P = (int)std::min<int64_t>({tiles, (int64_t)std::max(1, pstride),
                                          (int64_t)std::max(1, blocks_per_start)});
   *P_out = P;
-  hipLaunchKernelGGL(k_bwd_group<R>, dim3(P, nslots), dim3(kGBlock), lds, s, A);
+  if (dist)
+    hipExtLaunchKernelGGL((k_bwd_group<R, true>), dim3(P, nslots), dim3(kGBlock), lds, s, ev.start, ev.stop, 0,
+                          A);
+  else
+    hipExtLaunchKernelGGL((k_bwd_group<R, false>), dim3(P, nslots), dim3(kGBlock), lds, s, ev.start, ev.stop,
+                          0, A);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
@@ -869,7 +881,7 @@ int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32
                           int nslots,
                           const GateGroup &cur, const int32_t *pairs, const int32_t *kinds,
                           double beta, c128 *g64, c64 *g32, int32_t gstride, c128 *vstore,
-                          c128 *vop, hipStream_t s) {
+                          c128 *vop, hipStream_t s, LaunchEvents ev) {
   if (nslots <= 0) return QFS_OK;
   GroupFin F;
   std::memset(&F, 0, sizeof(F));
@@ -886,8 +898,8 @@ int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32
     F.sb[k - cur.k_lo] = slot(pairs[2 * k + 1]);
     F.kind[k - cur.k_lo] = kinds ? kinds[k] : QFS_GATE_2Q;
   }
-  hipLaunchKernelGGL(k_group_finalize, dim3(nslots), dim3(256), 0, s, gpartials, P, pstride, slot_to_start, F,
-                     beta, g64, g32, gstride, vstore, vop);
+  hipExtLaunchKernelGGL(k_group_finalize, dim3(nslots), dim3(256), 0, s, ev.start, ev.stop, 0, gpartials, P,
+                        pstride, slot_to_start, F, beta, g64, g32, gstride, vstore, vop);
   QFS_HIP(hipGetLastError());
   return QFS_OK;
 }
@@ -996,8 +1008,7 @@ QFS_FINST(float)
   template int launch_group_pass<R>(const Geometry &, const int32_t *, const GateGroup *,      \
                                     const GateGroup *, bool, const c128 *, SBuf<R>, SBuf<R>,   \
                                     SBuf<R>, const int32_t *, int, int, c128 *, int, double *, \
-                                    int *,                                                     \
-                                    hipStream_t);
+                                    int *, hipStream_t, LaunchEvents);
 QFS_GINST(float)
 QFS_GINST(double)
 #undef QFS_GINST

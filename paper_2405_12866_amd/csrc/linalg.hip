@@ -410,6 +410,29 @@ int launch_narrow(int64_t count, const c128 *src, c64 *dst, hipStream_t s) {
   return QFS_OK;
 }
 
+__global__ void k_copy_slots(const int32_t *slots, SlotCopy c) {
+  const int64_t s = slots[blockIdx.y];
+  for (int b = 0; b < SlotCopy::kBufs; ++b) {
+    const int64_t u = c.units[b];
+    if (u == 0) continue;
+    const uint4 *src = c.src[b] + s * u;
+    uint4 *dst = c.dst[b] + s * u;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < u; e += (int64_t)gridDim.x * blockDim.x)
+      dst[e] = src[e];
+  }
+}
+
+int launch_copy_slots(const int32_t *slots, int nslots, const SlotCopy &c, hipStream_t s) {
+  if (nslots <= 0) return QFS_OK;
+  int64_t umax = 0;
+  for (int b = 0; b < SlotCopy::kBufs; ++b) umax = std::max(umax, c.units[b]);
+  if (umax == 0) return QFS_OK;
+  const unsigned bx = (unsigned)std::min<int64_t>((umax + 255) / 256, 64);
+  hipLaunchKernelGGL(k_copy_slots, dim3(bx, (unsigned)nslots), dim3(256), 0, s, slots, c);
+  QFS_HIP(hipGetLastError());
+  return QFS_OK;
+}
+
 // Fill with zeros by a kernel (safe inside captured graphs).
 __global__ void k_zero(uint4 *p, int64_t n16) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n16;

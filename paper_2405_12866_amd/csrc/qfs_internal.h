@@ -8,6 +8,7 @@
 // whatever qubits the gate acts on.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -169,6 +170,16 @@ int launch_to_internal(int n, int64_t M, int logC, int64_t nch, const c128 *src,
 template <typename R>
 int launch_from_internal(int n, int64_t M, int logC, const cx<R> *src, c128 *dst, hipStream_t s);
 int launch_narrow(int64_t count, const c128 *src, c64 *dst, hipStream_t s);
+// Per-start copies between buffers of layout [S][units] (16-byte units; src and dst 16-byte
+// aligned), for the starts slots[0 .. nslots) (device list): up to kBufs buffers per launch,
+// units 0 for an unused one.
+struct SlotCopy {
+  static constexpr int kBufs = 3;
+  const uint4 *src[kBufs] = {};
+  uint4 *dst[kBufs] = {};
+  int64_t units[kBufs] = {};
+};
+int launch_copy_slots(const int32_t *slots, int nslots, const SlotCopy &c, hipStream_t s);
 int launch_zero(void *p, size_t bytes, hipStream_t s);
 // A[i][i] = 1 for i < N in an N x ld complex128 matrix (the computational basis as columns).
 int launch_unit_columns(int64_t N, int64_t ld, c128 *A, hipStream_t s);
@@ -327,6 +338,10 @@ struct GateGroup {
   int32_t nvar;        // variable (updated) gates in the group
 };
 // Groups from the last gate down, each as long as its qubits fit in four (fewest groups).
+// Start/stop events recorded by a launch itself (see launch_group_pass).
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
 std::vector<GateGroup> plan_gate_groups(int L, const int32_t *pairs, const int32_t *kinds);
 bool group_path_supported(const Geometry &g, size_t rbytes);
 // Blocks per start any grouped pass over geometry g uses at most (the partials' stride).
@@ -335,11 +350,14 @@ int group_partials_stride(const Geometry &g, size_t rbytes);
 // prev), stored to a_out (when given), then either the second-moment block partials of cur
 // against b (gpartials) or, with dist, the block partials of sum |a - b|^2 ([S][P] in
 // dpartials). P returned.
+// (ev: start/stop events the launch records itself, hipExtLaunchKernelGGL, so that they
+// bracket the kernel's own execution; both null: a plain launch.)
 template <typename R>
 int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *prev,
                       const GateGroup *cur, bool dist, const c128 *vop, SBuf<R> a_in, SBuf<R> a_out,
                       SBuf<R> b, const int32_t *slot_to_start, int nslots, int blocks_per_start,
-                      c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s);
+                      c128 *gpartials, int pstride, double *dpartials, int *P_out, hipStream_t s,
+                      LaunchEvents ev = {});
 // Forward pass by gate groups (the groups in forward order, one LDS round trip per group;
 // complex64 states, the products on the matrix cores):
 // plan [ngroups][8] and per-gate slots [L][2] from build_forward_plan (host; bneed_host
@@ -362,6 +380,6 @@ int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32
                           int nslots,
                           const GateGroup &cur, const int32_t *pairs, const int32_t *kinds,
                           double beta, c128 *g64, c64 *g32, int32_t gstride, c128 *vstore,
-                          c128 *vop, hipStream_t s);
+                          c128 *vop, hipStream_t s, LaunchEvents ev = {});
 
 }  // namespace qfs
