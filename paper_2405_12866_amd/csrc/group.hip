@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
         reinterpret_cast<f32x4 *>(lb)[lds_slot16(pk)] = rb[u];
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (tau + P < tiles) fetch(tau + P);
     if (apply) {
       // a <- V a on the operator's slots: (16 x 16) x (16 x 16-column block) products on the
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
           for (int v = 0; v < 4; ++v) lds_elem_put(la, wr_off[v] | cofs, e, cmake<R>(dre[v], dim[v]));
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     if (a_out) {
 #pragma unroll
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   if (!DIST && A.env) {
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
   cx<R> *lgates = lds + chunk;
   if (gates_in_lds)
     for (int e = threadIdx.x; e < 16 * L; e += FB) lgates[e] = gates[e];
-  __syncthreads();
+  lds_barrier();
   cx<R> *bl = sg.blist ? sg.blist + sg.bstride * s + cbase : nullptr;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nitems = chunk >> 4;
@@ -672,7 +672,7 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
         for (int r = 0; r < 16; ++r) lds[base + ro[r]] = x[r];
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (sg.ref) {
     const cx<R> *ref = sg.ref + cbase;

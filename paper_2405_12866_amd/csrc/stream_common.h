@@ -6,6 +6,12 @@
 
 namespace qfs {
 
+// Work-group barrier for hand-offs through LDS only: it waits for the wave's own LDS
+// operations, not for its global loads and stores (which __syncthreads also drains), so
+// prefetches and stores stay in flight across it. The memory clobber keeps the compiler
+// from moving memory operations across it.
+__device__ __forceinline__ void lds_barrier() { __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <typename R>
 struct Pk;  // 16-byte packet of samples
 template <>
