@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--shares", type=str, default="2,4,8",
                     help="GPU counts G: time the 12-qubit workload at M / G samples, one GPU's "
                          "share of a sample-sharded run (empty skips it)")
+    ap.add_argument("--sec8d", type=int, default=1,
+                    help="measurement rows C1, C2, C3 (every M, 1 and 16 starts) and errors against the oracle")
     ap.add_argument("--learned-large", type=int, default=0,
                     help="10-14 qubit random-pair problems (30-120 gates) for the learned-M "
                          "comparison through qfs_instantiate (0 skips it)")
@@ -409,6 +411,147 @@ def time_to_distance(dev, graphs=0):
     return out
 
 
+def _sweep_bytes(n, M, L, b=8):
+    """Algorithmic bytes of one sweep of one start: every B_k written once and read once,
+    the running state on chip, U psi read once: 2 b S L + b S with S = M 2^n."""
+    S = M * (1 << n)
+    return 2.0 * b * S * L + b * S
+
+
+def _timed_call(Q, torch, n, pairs, tg, params):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, info = Q.qfs_instantiate(n, pairs, target_pairs=pairs, target_gates=tg, params=params)
+    torch.cuda.synchronize()
+    return g, info, time.perf_counter() - t0
+
+
+def _teacher_forced(Q, torch, dev, n, pairs, tg_host, M, starts, sweeps, check_starts, check_sweeps, seed):
+    """Error of the device's complex64 sweeps against the FP64 oracle: `sweeps` MIXED sweeps of
+    `starts` starts from Haar gates on fixed sample sets; before each sweep in check_sweeps the
+    oracle runs one sweep of each start in check_starts from the device's FP64 gates (both sides
+    from the same gates), and |c_gpu - c_oracle| / max(c_oracle, c_initial) is recorded."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle as O
+    from paper_2405_12866_amd import inputs as I
+
+    g = np.random.default_rng(seed)
+    psi = I.orthonormal_samples(n, M, g)
+    phi = O.apply_circuit(n, psi, pairs, tg_host)
+    gates = np.stack([I.haar_gates(len(pairs), g) for _ in range(starts)])
+    dpsi = torch.as_tensor(psi).to(dev)
+    dphi = torch.as_tensor(phi).to(dev)
+    dg = torch.as_tensor(gates).to(dev)
+    worst, c_init, rows = 0.0, None, []
+    with cf.ThreadPoolExecutor(max_workers=len(check_starts)) as ex:
+        for sw in range(sweeps):
+            start = None
+            if sw in check_sweeps:
+                torch.cuda.synchronize()
+                start = dg.cpu().numpy().copy()
+            c_gpu = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED)
+            if start is None:
+                continue
+            refs = list(ex.map(lambda s: O.sweep(n, pairs, psi, phi, start[s].copy())[1], check_starts))
+            if c_init is None:
+                c_init = max(refs)
+            for s, c_ref in zip(check_starts, refs):
+                e = abs(c_gpu[s] - c_ref) / max(c_ref, c_init)
+                worst = max(worst, e)
+                rows.append({"sweep": sw, "start": s, "c_gpu": c_gpu[s], "c_oracle": c_ref, "rel_err": e})
+    return {"worst_rel_err": worst, "contract": 1e-6, "checks": rows,
+            "what": f"{n} qubits, {len(pairs)} gates, M={M}, {starts} starts, complex64 sweeps (qfs_sweep) "
+                    f"checked teacher-forced against the FP64 oracle at sweeps {list(check_sweeps)} for "
+                    f"starts {list(check_starts)}"}
+
+
+def sec8d(dev, ttd_max_iter=400):
+    """Measurement rows: C1 against the oracle, C2's serial chain, C3 at every M with 1 and 16
+    starts (throughput and time to distance), and the teacher-forced error of complex64 sweeps
+    against the FP64 oracle at the C2 and full C3 sizes."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2405_12866_amd import inputs as I
+    from paper_2405_12866_amd import qfs as Q
+
+    out = {}
+    # C1: 3 qubits, (0,1),(1,2) x 3, M = 4 with doubling, complex128, to 1e-10 or 200 sweeps
+    w = I.workload_3q()
+    tg = torch.as_tensor(w["target_gates"]).to(dev)
+    c1 = {}
+    for starts in (1, 16):
+        kw = dict(dist_tol=1e-10, multistarts=starts, seed=0x5A17 + 1, max_iter=200, m_init=4)
+        g, info, dt = _timed_call(Q, torch, 3, w["pairs"], tg, Q.qfs_default_params(precision=Q.QFS_PREC_FP64, **kw))
+        t0 = time.perf_counter()
+        g_ref, ref = O.instantiate(3, w["pairs"], target_pairs=w["pairs"], target_gates=w["target_gates"],
+                                   params=O.default_params(**kw))
+        dt_o = time.perf_counter() - t0
+        same = all(info[k] == ref[k] for k in ("reason_name", "sweeps", "best_start", "restarts", "m_final"))
+        c1[f"starts{starts}"] = {
+            "gpu_s": round(dt, 4), "oracle_s_one_thread": round(dt_o, 4), "reason": info["reason_name"],
+            "sweeps": info["sweeps"], "doublings": info["restarts"], "m_final": info["m_final"],
+            "c_train": info["c_train"],
+            "vs_oracle": {"same_start_reason_sweeps_doublings": bool(same),
+                          "c_train_abs_err": abs(info["c_train"] - ref["c_train"]),
+                          "gates_max_abs_err": float(np.max(np.abs(g.cpu().numpy() - g_ref)))}}
+    out["C1_3q_L6_M4_c128"] = c1
+    # C2: 8 qubits, 21 gates, M = 32, one start (plain): the serial chain per gate step
+    w8 = I.workload_8q()
+    tg8 = torch.as_tensor(w8["target_gates"]).to(dev)
+    L8 = len(w8["pairs"])
+    base = dict(multistarts=1, m_init=32, fixed_m=1, seed=5, precision=Q.QFS_PREC_MIXED, diff_tol_r=0.0,
+                plateau_window=1 << 30, dist_tol=0.0)
+    _timed_call(Q, torch, 8, w8["pairs"], tg8, Q.qfs_default_params(max_iter=5, **base))
+    _, info, dt = _timed_call(Q, torch, 8, w8["pairs"], tg8, Q.qfs_default_params(max_iter=200, **base))
+    sw = info["start_sweeps"]
+    out["C2_8q_L21_M32_1start"] = {
+        "sweeps": sw, "wall_us_per_sweep": round(1e6 * dt / sw, 2),
+        "device_us_per_sweep": round(1e6 * info["sweep_seconds"] / sw, 2),
+        "device_us_per_gate_step": round(1e6 * info["sweep_seconds"] / sw / L8, 3),
+        "algorithmic_GBps": round(_sweep_bytes(8, 32, L8) * sw / dt / 1e9, 2),
+        "error_vs_oracle": _teacher_forced(Q, torch, dev, 8, w8["pairs"], w8["target_gates"], 32, 1, 6, [0],
+                                           (0, 5), seed=81)}
+    # C3: 12 qubits, 44 gates, every M with 1 and 16 starts
+    w12 = I.workload_12q()
+    tg12 = torch.as_tensor(w12["target_gates"]).to(dev)
+    L12 = len(w12["pairs"])
+    thr, ttd = [], []
+    for M in (8, 16, 32, 64, 128, 256):
+        for starts in (1, 16):
+            base = dict(multistarts=starts, m_init=M, fixed_m=1, seed=0x5A17 + 3, precision=Q.QFS_PREC_MIXED,
+                        diff_tol_r=0.0, plateau_window=1 << 30, dist_tol=0.0)
+            _timed_call(Q, torch, 12, w12["pairs"], tg12, Q.qfs_default_params(max_iter=3, **base))
+            k = 40 if M * starts <= 512 else 20
+            _, info, dt = _timed_call(Q, torch, 12, w12["pairs"], tg12, Q.qfs_default_params(max_iter=k, **base))
+            sw = info["start_sweeps"]
+            ab = _sweep_bytes(12, M, L12) * sw
+            thr.append({"M": M, "starts": starts, "start_sweeps": sw,
+                        "start_sweeps_per_s": round(sw / dt, 1),
+                        "device_ms_per_sweep": round(1e3 * info["sweep_seconds"] / info["sweeps"], 4),
+                        "algorithmic_GBps_wall": round(ab / dt / 1e9, 1),
+                        "algorithmic_GBps_device": round(ab / info["sweep_seconds"] / 1e9, 1)})
+        p = Q.qfs_default_params(multistarts=16, m_init=M, fixed_m=1, seed=0x5A17 + 3, precision=Q.QFS_PREC_MIXED,
+                                 max_iter=ttd_max_iter)
+        _, info, dt = _timed_call(Q, torch, 12, w12["pairs"], tg12, p)
+        ttd.append({"M": M, "starts": 16, "reason": info["reason_name"],
+                    "reached_1e-8": info["reason_name"] == "SUCCESS", "sweeps": info["sweeps"],
+                    "c_train": info["c_train"], "c_val": info["c_val"], "seconds": round(dt, 3)})
+    out["C3_12q_L44_throughput"] = thr
+    out["C3_12q_L44_time_to_distance"] = {
+        "rows": ttd,
+        "note": ("fixed M, App. A stopping rules (plateau 1e-5 over 5 sweeps), at most "
+                 f"{ttd_max_iter} sweeps; this brickwork with Haar-random target gates stalls far above 1e-8 "
+                 "(in the oracle as well), so the rows report where it stops")}
+    out["C3_12q_M256_error_vs_oracle"] = _teacher_forced(Q, torch, dev, 12, w12["pairs"], w12["target_gates"],
+                                                         256, 16, 5, [0, 9], (0, 4), seed=83)
+    return out
+
+
 def batched(dev, count, plain_sample):
     """Batched workload: `count` problems (n ~ U{3..7}, L ~ U{2..20} random pairs, Haar
     target from the template), 16 starts each, M0 = 2^(n-1) with doubling to 2^n,
@@ -436,11 +579,19 @@ def batched(dev, count, plain_sample):
     dt = time.perf_counter() - t0
     ok = sum(r["reason_name"] == "SUCCESS" for r in infos)
     job_sweeps = sum(r["start_sweeps"] for r in infos)
+    # algorithmic bytes (2 b S L + b S per job-sweep, b = 8) from the amplitude-gate updates
+    # of each problem's sweeps, (M + M_val) 2^n L with M_val = M: the training half
+    alg = 0.0
+    for p, r in zip(probs, infos):
+        train = 0.5 * r["amp_updates"]
+        alg += 2.0 * 8 * train + 8.0 * train / len(p["pairs"])
     out = {"problems": count, "starts": 16, "wall_s": round(dt, 3),
            "problems_per_s": round(count / dt, 1), "successes": ok,
            "job_sweeps": job_sweeps, "job_sweeps_per_s": round(job_sweeps / dt, 1),
            "doublings": sum(r["restarts"] for r in infos),
-           "device_s": round(infos[0]["sweep_seconds"], 3)}
+           "device_s": round(infos[0]["sweep_seconds"], 3),
+           "algorithmic_GBps": round(alg / dt / 1e9, 1),
+           "algorithmic_note": "complex64 bytes for every sweep (the final complex128 sweeps counted at 8 B)"}
     k = min(plain_sample, count)
     if k > 0:
         t_plain, ok_plain, ok_batch = 0.0, 0, 0
@@ -657,6 +808,8 @@ def main():
         "kernel_classes": classes,
         "final_c_train": info["c_train"], "final_c_val": info["c_val"],
     }
+    if args.sec8d:
+        extra["measurement_rows"] = sec8d(dev)
     if args.u3cx:
         extra["u3_cnot"] = u3_cnot(dev, M, S, args.steps, args.warmup, args.timing)
     if args.shares:
