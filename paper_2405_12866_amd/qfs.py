@@ -86,6 +86,14 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                               "(hipcc --offload-arch=gfx950) first")
+        # The library and PyTorch must share one HIP runtime (the library's arguments are
+        # torch's device pointers): load torch's first, so that the library's dependency on
+        # libamdhip64 resolves to it. Loaded the other way round, the second runtime finds
+        # no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(LIB_PATH)
         P, I32, U32, U64, D = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64, C.c_double
         lib.qfs_strerror.restype = C.c_char_p
