@@ -22,12 +22,79 @@ namespace qfs {
 __device__ __forceinline__ c128 shfl_c(c128 x, int src) {
   return cmake(__shfl(x.re, src), __shfl(x.im, src));
 }
+
+// Exchange between the lanes of a 16-lane row by DPP moves (no trip through the LDS
+// crossbar): lane i receives lane i ^ M's value, M in {1, 2, 4, 8, 12}. xor 1 and 2 are quad
+// permutations, xor 8 the rotation of the row by 8, xor 4 the reversal of each half row
+// followed by the reversal of each quad.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int M>
+__device__ __forceinline__ double xor_lane(double x) {
+  if constexpr (M == 1) {
+    return dpp_move<0xB1>(x);  // quad_perm [1, 0, 3, 2]
+  } else if constexpr (M == 2) {
+    return dpp_move<0x4E>(x);  // quad_perm [2, 3, 0, 1]
+  } else if constexpr (M == 8) {
+    return dpp_move<0x128>(x);  // row_ror:8
+  } else if constexpr (M == 4) {
+    return dpp_move<0x1B>(dpp_move<0x141>(x));  // row_half_mirror, then quad_perm [3, 2, 1, 0]
+  } else {
+    static_assert(M == 12, "lane exchange within a row");
+    return xor_lane<8>(xor_lane<4>(x));
+  }
+}
+
 __device__ __forceinline__ c128 quad_sum(c128 x) {
-  x.re += __shfl_xor(x.re, 1);
-  x.im += __shfl_xor(x.im, 1);
-  x.re += __shfl_xor(x.re, 2);
-  x.im += __shfl_xor(x.im, 2);
+  x.re += xor_lane<1>(x.re);
+  x.im += xor_lane<1>(x.im);
+  x.re += xor_lane<2>(x.re);
+  x.im += xor_lane<2>(x.im);
   return x;
+}
+
+// One round of the one-sided Jacobi below: the column pairs c <-> c ^ (M >> 2).
+template <int M>
+__device__ __forceinline__ void jacobi_round(int l, c128 &g, c128 &v, int &large) {
+  const c128 go = cmake(xor_lane<M>(g.re), xor_lane<M>(g.im));
+  const c128 vo = cmake(xor_lane<M>(v.re), xor_lane<M>(v.im));
+  const bool is_p = (l ^ M) > l;
+  const c128 gp = is_p ? g : go, gq = is_p ? go : g;
+  const c128 vp = is_p ? v : vo, vq = is_p ? vo : v;
+  double al = cabs2(gp), be = cabs2(gq);
+  double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) * gq
+  double gi = gp.re * gq.im - gp.im * gq.re;
+  al += xor_lane<1>(al);
+  be += xor_lane<1>(be);
+  gr += xor_lane<1>(gr);
+  gi += xor_lane<1>(gi);
+  al += xor_lane<2>(al);
+  be += xor_lane<2>(be);
+  gr += xor_lane<2>(gr);
+  gi += xor_lane<2>(gi);
+  const double ag = sqrt(gr * gr + gi * gi);
+  const double gsc = sqrt(al * be);
+  if (ag > 0.0 && ag > 1e-15 * gsc) {
+    large |= ag > 1e-7 * gsc;
+    const double rag = 1.0 / ag;
+    const c128 ec = cmake(gr * rag, -gi * rag);  // conj(e^{i phi})
+    const double tau = (be - al) * (0.5 * rag);
+    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+    const c128 egq = ec * gq, evq = ec * vq;
+    if (is_p) {
+      g = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+      v = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+    } else {
+      g = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+      v = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+    }
+  }
 }
 
 __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
@@ -69,56 +136,23 @@ __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c1
   bool converged = false;
   for (int sweep = 0; sweep < 40; ++sweep) {
     int large = 0;
-#pragma unroll
-    for (int m = 4; m <= 12; m += 4) {
-      const c128 go = cmake(__shfl_xor(g.re, m), __shfl_xor(g.im, m));
-      const c128 vo = cmake(__shfl_xor(v.re, m), __shfl_xor(v.im, m));
-      const bool is_p = (l ^ m) > l;
-      const c128 gp = is_p ? g : go, gq = is_p ? go : g;
-      const c128 vp = is_p ? v : vo, vq = is_p ? vo : v;
-      double al = cabs2(gp), be = cabs2(gq);
-      double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) * gq
-      double gi = gp.re * gq.im - gp.im * gq.re;
-#pragma unroll
-      for (int o = 1; o <= 2; o <<= 1) {
-        al += __shfl_xor(al, o);
-        be += __shfl_xor(be, o);
-        gr += __shfl_xor(gr, o);
-        gi += __shfl_xor(gi, o);
-      }
-      const double ag = sqrt(gr * gr + gi * gi);
-      const double gsc = sqrt(al * be);
-      if (ag > 0.0 && ag > 1e-15 * gsc) {
-        large |= ag > 1e-7 * gsc;
-        const double rag = 1.0 / ag;
-        const c128 ec = cmake(gr * rag, -gi * rag);  // conj(e^{i phi})
-        const double tau = (be - al) * (0.5 * rag);
-        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        const c128 egq = ec * gq, evq = ec * vq;
-        if (is_p) {
-          g = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
-          v = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
-        } else {
-          g = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
-          v = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
-        }
-      }
-    }
+    jacobi_round<4>(l, g, v, large);
+    jacobi_round<8>(l, g, v, large);
+    jacobi_round<12>(l, g, v, large);
     if (!__any(large)) {
       converged = true;
       break;
     }
   }
   double s2 = cabs2(g);
-  s2 += __shfl_xor(s2, 1);
-  s2 += __shfl_xor(s2, 2);
+  s2 += xor_lane<1>(s2);
+  s2 += xor_lane<2>(s2);
   const double sig = sqrt(s2);
   double smin = sig, smax = sig;
-  smin = fmin(smin, __shfl_xor(smin, 4));
-  smin = fmin(smin, __shfl_xor(smin, 8));
-  smax = fmax(smax, __shfl_xor(smax, 4));
-  smax = fmax(smax, __shfl_xor(smax, 8));
+  smin = fmin(smin, xor_lane<4>(smin));
+  smin = fmin(smin, xor_lane<8>(smin));
+  smax = fmax(smax, xor_lane<4>(smax));
+  smax = fmax(smax, xor_lane<8>(smax));
   if (converged && smin > 1e-200 && smin > 1e-15 * smax) {
     // W = G diag(1/sigma) is unitary to the Jacobi tolerance; u = W V^dagger with
     // lane 4q + p computing u[q][p] = sum_k W[q][k] conj(V[p][k]); W[q][k] and V[p][k]
