@@ -425,6 +425,17 @@ int qfs_dense_apply(int32_t n, int32_t M, const qfs_c128 *U, const qfs_c128 *psi
 int qfs_environment(int32_t n, int32_t M, const qfs_c128 *a, const qfs_c128 *b,
                     int32_t qa, int32_t qb, qfs_c128 *gamma, void *hip_stream);
 
+/* qfs_environment for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same Gamma, computed
+ * from the row-major states directly, with its work-group partial sums in a fixed array of
+ * this library (256 KiB per GPU, held until the process ends); no allocation, no
+ * memset, no synchronisation (gamma is ready in stream order). Limit: M 2^(n-2) <= 2^28,
+ * else QFS_EINVAL. Every call on a GPU shares that array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller. a, b: device
+ * [M][N]; gamma: device [4][4]. */
+int qfs_environment_noalloc(int32_t n, int32_t M, const qfs_c128 *a, const qfs_c128 *b,
+                            int32_t qa, int32_t qb, qfs_c128 *gamma, void *hip_stream);
+
 /* Gate update (Sec. 2.1, Eq. 2; App. A Beta): u <- W V^dagger where
  * (1 - beta) Gamma + beta u = W S V^dagger (FP64 one-sided Jacobi SVD). count
  * independent 4x4 problems; gamma: device [count][4][4]; u: device [count][4][4]

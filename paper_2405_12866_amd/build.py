@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqfs_hip.so")
 SOURCES = ["rng.hip", "linalg.hip", "sweep.hip", "group.hip", "engine.hip", "batch.hip",
-           "batch_engine.hip", "mlp.hip", "learned.hip", "qudit.hip"]
+           "batch_engine.hip", "mlp.hip", "learned.hip", "qudit.hip", "noalloc.hip"]
 ARCH = os.environ.get("QFS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -69,7 +69,8 @@ class Result(C.Structure):
 
 EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",
            "qfs_instantiate", "qfs_instantiate_batch", "qfs_instantiate_samples", "qfs_draw_states", "qfs_haar_gates",
-           "qfs_apply_gates", "qfs_dense_apply", "qfs_environment", "qfs_polar_update",
+           "qfs_apply_gates", "qfs_dense_apply", "qfs_environment", "qfs_environment_noalloc",
+           "qfs_polar_update",
            "qfs_sweep", "qfs_state_distance", "qfs_label_batch", "qfs_features",
            "qfs_mlp_num_params", "qfs_mlp_init", "qfs_mlp_get", "qfs_mlp_set", "qfs_mlp_save",
            "qfs_mlp_load", "qfs_mlp_forward", "qfs_mlp_grad", "qfs_mlp_train", "qfs_predict_m",
@@ -113,6 +114,7 @@ def load():
         lib.qfs_apply_gates.argtypes = [I32, I32, P, I32, P, P, I32, P]
         lib.qfs_dense_apply.argtypes = [I32, I32, P, P, P, P]
         lib.qfs_environment.argtypes = [I32, I32, P, P, I32, I32, P, P]
+        lib.qfs_environment_noalloc.argtypes = [I32, I32, P, P, I32, I32, P, P]
         lib.qfs_polar_update.argtypes = [I32, P, D, P, P]
         lib.qfs_sweep.argtypes = [I32, I32, P, P, I32, P, P, I32, P, I32, D, I32, P, P]
         lib.qfs_state_distance.argtypes = [I32, I32, P, P, C.POINTER(C.c_double), P]
@@ -501,6 +503,14 @@ def qfs_environment(n, a, b, qa, qb):
     _check(load().qfs_environment(n, a.shape[0], _dev_c128(a, "a"), _dev_c128(b, "b"), qa, qb,
                                   C.c_void_p(g.data_ptr()), _stream()), "qfs_environment")
     return g
+
+
+def qfs_environment_noalloc(n, a, b, qa, qb, gamma):
+    """Into the caller's device tensor ``gamma`` [4, 4] complex128 (the library allocates
+    nothing); stream-ordered on the current stream."""
+    _check(load().qfs_environment_noalloc(n, a.shape[0], _dev_c128(a, "a"), _dev_c128(b, "b"), qa, qb,
+                                          _dev_c128(gamma, "gamma"), _stream()), "qfs_environment_noalloc")
+    return gamma
 
 
 def qfs_polar_update(gamma, beta=0.0, u=None):
