@@ -1163,7 +1163,11 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_TRY(issue_sweep(par, active));
   std::vector<double> nct(S_), ncv(S_);
   for (;;) {
-    const bool ahead = spec_;
+    // (not past max_iter: when sweep t is the last every running start may make, nothing is
+    // issued ahead of it)
+    bool last = true;
+    for (int s : active) last = last && total[s] + 1 >= p_.max_iter;
+    const bool ahead = spec_ && !last;
     if (ahead) QFS_TRY(issue_sweep(par ^ 1, active));
     QFS_TRY(wait_sweep(par, nct, ncv, out.sweep_seconds));
     ++round;
