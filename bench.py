@@ -76,7 +76,7 @@ def parse():
                     help="problems in the batched workload (0 skips it)")
     ap.add_argument("--batched-u3cx", type=int, default=4096,
                     help="U3 + CNOT problems in a second batched workload (0 skips it)")
-    ap.add_argument("--plain-sample", type=int, default=48,
+    ap.add_argument("--plain-sample", type=int, default=128,
                     help="problems of the batched workload also run one by one")
     ap.add_argument("--learned", type=int, default=1024,
                     help="held-out problems for the learned-M comparison (0 skips it)")
