@@ -379,6 +379,7 @@ __global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, in
                                                         int32_t gstride, c128 *vstore, c128 *vop) {
   __shared__ c128 H[256], Vm[256];
   __shared__ c128 ug[kGroupMaxGates][16];  // the group's gates (pre-sweep, then updated)
+  __shared__ c128 vw[kGroupMaxGates][16];  // their Jacobi warm starts
   __shared__ c128 gam[16];
   __shared__ c128 pg[16], pv[16];
   __shared__ double psig[4];
@@ -387,7 +388,10 @@ __global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, in
   const int z = t >> 4, y = t & 15;
   const int ngate = F.k_hi - F.k_lo + 1;
   c128 *gs = g64 + (int64_t)s * gstride;
-  if (t < 16 * ngate) ug[t >> 4][t & 15] = gs[(F.k_lo + (t >> 4)) * 16 + (t & 15)];
+  if (t < 16 * ngate) {
+    ug[t >> 4][t & 15] = gs[(F.k_lo + (t >> 4)) * 16 + (t & 15)];
+    if (vstore) vw[t >> 4][t & 15] = vstore[(int64_t)s * gstride + (F.k_lo + (t >> 4)) * 16 + (t & 15)];
+  }
   if (F.nvar > 0) {
     // fixed-order sum of the block partials: eight interleaved accumulators, each batch of
     // eight loads in flight together
@@ -472,7 +476,7 @@ __global__ __launch_bounds__(256) void k_group_finalize(const c128 *partials, in
           if (t == 0) polar2_update<float>(gam, beta, ug[i], nullptr);
         } else {
           polar4_wave(gam, beta, gs + k * 16, ug[i], nullptr, pg, pv, psig,
-                      vstore ? vstore + (int64_t)s * gstride + k * 16 : nullptr);
+                      vstore ? vstore + (int64_t)s * gstride + k * 16 : nullptr, vw[i]);
         }
       }
       __syncthreads();

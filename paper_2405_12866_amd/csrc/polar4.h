@@ -18,7 +18,8 @@ namespace qfs {
 // singular vectors this gate had after its previous update (the environment changes
 // little between sweeps), so it converges in one or two sweeps instead of ~6. V_prev is
 // first made unitary to rounding by one Newton-Schulz step V (3I - V^dag V) / 2, so no
-// error accumulates across sweeps; the new V is stored back.
+// error accumulates across sweeps; the new V is stored back. vstart, when given, holds a
+// copy of the stored V_prev (in LDS) to read instead.
 __device__ __forceinline__ c128 shfl_c(c128 x, int src) {
   return cmake(__shfl(x.re, src), __shfl(x.im, src));
 }
@@ -58,6 +59,24 @@ __device__ __forceinline__ c128 quad_sum(c128 x) {
   return x;
 }
 
+// 1/sqrt(x) and 1/x from the hardware estimates, each refined by two Newton steps (about
+// one ulp; the rotations below need cs^2 + sn^2 = 1 and |e| = 1 to rounding, not the
+// correctly rounded values, and the estimates shorten their dependent chain).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 // One round of the one-sided Jacobi below: the column pairs c <-> c ^ (M >> 2).
 template <int M>
 __device__ __forceinline__ void jacobi_round(int l, c128 &g, c128 &v, int &large) {
@@ -77,15 +96,17 @@ __device__ __forceinline__ void jacobi_round(int l, c128 &g, c128 &v, int &large
   be += xor_lane<2>(be);
   gr += xor_lane<2>(gr);
   gi += xor_lane<2>(gi);
-  const double ag = sqrt(gr * gr + gi * gi);
-  const double gsc = sqrt(al * be);
-  if (ag > 0.0 && ag > 1e-15 * gsc) {
-    large |= ag > 1e-7 * gsc;
-    const double rag = 1.0 / ag;
+  // |Gram_pq|^2 against the product of the column norms squared: rotate when |Gram_pq| >
+  // 1e-15 sqrt(al be), and count the round as large above 1e-7 sqrt(al be)
+  const double x2 = gr * gr + gi * gi, ab = al * be;
+  if (x2 > 1e-30 * ab) {
+    large |= x2 > 1e-14 * ab;
+    const double rag = rsq_nr(x2);  // 1 / |Gram_pq|
     const c128 ec = cmake(gr * rag, -gi * rag);  // conj(e^{i phi})
     const double tau = (be - al) * (0.5 * rag);
-    const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+    const double t1 = fma(tau, tau, 1.0);
+    const double tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + t1 * rsq_nr(t1));
+    const double cs = rsq_nr(fma(tt, tt, 1.0)), sn = cs * tt;
     const c128 egq = ec * gq, evq = ec * vq;
     if (is_p) {
       g = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
@@ -99,7 +120,7 @@ __device__ __forceinline__ void jacobi_round(int l, c128 &g, c128 &v, int &large
 
 __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c128 *u_prev, c128 *out64,
                             c64 *out32, c128 *lds_g, c128 *lds_v, double *lds_s,
-                            c128 *vstore = nullptr) {
+                            c128 *vstore = nullptr, const c128 *vstart = nullptr) {
   const int lane = threadIdx.x & 63;
   const int l = lane & 15, c = l >> 2, r = l & 3, base = lane & ~15;
   auto gm = [&](int row, int col) {
@@ -114,7 +135,7 @@ __device__ __forceinline__ void polar4_wave(const c128 *G, double beta, const c1
   if (vstore) {
     // lane 4c + r holds X[r][c]; Y[a][c] = sum_k conj(X[k][a]) X[k][c] (quad c);
     // Z[r][c] = (3 X[r][c] - sum_a X[r][a] Y[a][c]) / 2
-    const c128 x = vstore[r * 4 + c];
+    const c128 x = (vstart ? vstart : vstore)[r * 4 + c];
     c128 acc = cmake(0.0, 0.0);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
