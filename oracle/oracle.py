@@ -159,6 +159,13 @@ def load():
         lib.qd_instantiate.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_int, C.c_int,
                                        C.POINTER(Params), P, P, C.POINTER(Result), C.POINTER(Trace)]
         lib.qd_instantiate.restype = C.c_int
+        lib.qd_draw_states.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
+                                       P]
+        lib.qd_draw_states.restype = C.c_int
+        lib.qd_instantiate_target.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_int, P, C.c_int, P, P,
+                                              C.POINTER(Params), P, P, C.POINTER(Result),
+                                              C.POINTER(Trace)]
+        lib.qd_instantiate_target.restype = C.c_int
         _lib = lib
         return lib
 
@@ -505,6 +512,54 @@ def qd_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None):
     return out, info
 
 
+def qd_draw_states(d, n, M, seed, role, stream):
+    """M orthonormal Haar states on d^n amplitudes ([M][d^n], the qubit draw's streams)."""
+    out = np.zeros((M, d ** n), dtype=np.complex128)
+    rc = load().qd_draw_states(d, n, M, seed, role, stream, _p(out))
+    if rc != 0:
+        raise ValueError(f"qd_draw_states failed: {rc}")
+    return out
+
+
+def qd_instantiate_target(d, n, pairs, *, U=None, target_pairs=None, target_gates=None,
+                          params=None, gates_in=None, trace_capacity=0, doubling_capacity=0):
+    """Qudit instantiation against a dense target ``U`` ([d^n][d^n]) or a target circuit
+    (``target_pairs`` + ``target_gates`` [Lt][d^2][d^2]), with drawn training and validation
+    states. Returns (gates, result dict), with the trace as in ``instantiate``."""
+    lib = load()
+    pr = _pairs(pairs)
+    L, D = pr.shape[0], d * d
+    par = Params(**(params or default_params()))
+    keep = []
+    if U is not None:
+        kind = TARGET_DENSE
+        Uc = _c128(U)
+        keep.append(Uc)
+        args = (_p(Uc), 0, None, None)
+    else:
+        kind = TARGET_CIRCUIT
+        tp = _pairs(target_pairs)
+        tg = _c128(target_gates)
+        keep += [tp, tg]
+        args = (None, tp.shape[0], _p(tp), _p(tg))
+    gi = None if gates_in is None else _c128(gates_in)
+    out = np.zeros((L, D, D), dtype=np.complex128)
+    res = Result()
+    tr = None
+    if trace_capacity or doubling_capacity:
+        tr, bufs, dbl = _make_trace(max(trace_capacity, 1), doubling_capacity, par.multistarts
+                                    if par.multistarts > 0 else 1, L, D * D, d ** n)
+    rc = lib.qd_instantiate_target(d, n, L, _p(pr), kind, *args, C.byref(par), _p(gi), _p(out),
+                                   C.byref(res), C.byref(tr) if tr is not None else None)
+    if rc != 0:
+        raise ValueError(f"qd_instantiate_target failed: {rc}")
+    info = {f: getattr(res, f) for f, _ in Result._fields_}
+    info["reason_name"] = REASONS[res.reason]
+    if tr is not None:
+        info["trace"] = _read_trace(tr, bufs, dbl)
+    return out, info
+
+
 __all__ = [
     "Params", "Result", "ROLE_TRAIN", "ROLE_VAL", "ROLE_INIT", "REASONS", "default_params",
     "philox4x32_10", "cgauss", "ginibre", "orthonormalize", "draw_states", "haar_gate",
@@ -512,6 +567,7 @@ __all__ = [
     "apply_gate", "apply_circuit", "dense_apply", "environment", "environment1", "svd4",
     "update_gate", "update_gate1", "qd_apply_gate", "qd_apply_circuit", "qd_environment",
     "qd_svd", "qd_update_gate", "qd_haar_gate", "qd_sweep", "qd_instantiate",
+    "qd_draw_states", "qd_instantiate_target",
     "state_distance", "sweep", "instantiate", "EV_RUN", "EV_SUCCESS", "EV_OVERTRAINED",
     "EV_NOT_GEN", "EV_PLATEAU", "EV_MAX_ITER",
 ]

@@ -778,6 +778,59 @@ static void qo_targets(int n, int kind, const qo_cplx *U, int Lt, const int32_t 
   }
 }
 
+/* The same three steps on n qudits (Sec. 5: states and targets are those of the qubit
+ * method with N = d^n amplitudes). States: column j of the N x M Ginibre matrix from
+ * Philox index j N + i, orthonormalised in column order, so an extension draws the next
+ * columns of the same stream. Targets: phi_j = U psi_j for a dense N x N target, or the
+ * target circuit's D x D gates applied to psi_j in list order. */
+int qd_draw_states(int d, int n, int M, uint64_t seed, uint32_t role, uint32_t stream,
+                   qo_cplx *out) {
+  const int64_t N = qd_pow(d, n);
+  qo_ginibre(N, M, seed, role, stream, out);
+  return qo_gram_schmidt_columns(N, 0, M, out);
+}
+
+static int qd_extend_states(int d, int n, int m_old, int m_new, uint64_t seed, qo_cplx *psi) {
+  const int64_t N = qd_pow(d, n);
+  for (int64_t j = m_old; j < m_new; ++j)
+    for (int64_t i = 0; i < N; ++i)
+      psi[j * N + i] = qo_cgauss(seed, QO_ROLE_TRAIN, 0, (uint64_t)(j * N + i));
+  return qo_gram_schmidt_columns(N, m_old, m_new, psi);
+}
+
+static void qd_targets(int d, int n, int kind, const qo_cplx *U, int Lt, const int32_t *tpairs,
+                       const qo_cplx *tgates, int M, const qo_cplx *psi, qo_cplx *phi) {
+  const int64_t N = qd_pow(d, n);
+  const int GS = d * d * d * d;
+  if (kind == QO_TARGET_DENSE) {
+    for (int64_t j = 0; j < M; ++j)
+      for (int64_t r = 0; r < N; ++r) {
+        qo_cplx acc = 0.0;
+        for (int64_t c = 0; c < N; ++c) acc += U[r * N + c] * psi[j * N + c];
+        phi[j * N + r] = acc;
+      }
+  } else {
+    memcpy(phi, psi, sizeof(qo_cplx) * (size_t)M * N);
+    for (int k = 0; k < Lt; ++k)
+      qd_apply_gate(d, n, M, phi, tpairs[2 * k], tpairs[2 * k + 1], tgates + (size_t)GS * k, 0);
+  }
+}
+
+/* Draws, extension and targets for either case: the qubit functions when d = 2. */
+static int any_draw(int d, int n, int M, uint64_t seed, uint32_t role, uint32_t stream, qo_cplx *out) {
+  return d == 2 ? qo_draw_states(n, M, seed, role, stream, out) : qd_draw_states(d, n, M, seed, role, stream, out);
+}
+static int any_extend(int d, int n, int m_old, int m_new, uint64_t seed, qo_cplx *psi) {
+  return d == 2 ? qo_extend_states(n, m_old, m_new, seed, psi) : qd_extend_states(d, n, m_old, m_new, seed, psi);
+}
+static void any_targets(int d, int n, int kind, const qo_cplx *U, int Lt, const int32_t *tpairs,
+                        const qo_cplx *tgates, int M, const qo_cplx *psi, qo_cplx *phi) {
+  if (d == 2)
+    qo_targets(n, kind, U, Lt, tpairs, tgates, M, psi, phi);
+  else
+    qd_targets(d, n, kind, U, Lt, tpairs, tgates, M, psi, phi);
+}
+
 static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int32_t *kinds,
                    const qo_cplx *fixed, int target_kind, const qo_cplx *U,
                    int Lt, const int32_t *tpairs, const qo_cplx *tgates,
@@ -786,7 +839,7 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
                    qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
   const double t0 = qo_now();
   if (n < 2 || n > 24 || L < 1 || !p || !gates_out || !res) return -1;
-  if (d != 2 && (kinds || target_kind != QO_TARGET_SAMPLES)) return -1;
+  if (d != 2 && kinds) return -1;
   const int GS = d * d * d * d; /* entries of one gate */
   for (int k = 0; k < L; ++k) {
     int a = pairs[2 * k], b = pairs[2 * k + 1];
@@ -817,8 +870,8 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
     memcpy(psi, samples_psi, sizeof(qo_cplx) * (size_t)M * N);
     memcpy(phi, samples_phi, sizeof(qo_cplx) * (size_t)M * N);
   } else {
-    if (qo_draw_states(n, M, p->seed, QO_ROLE_TRAIN, 0, psi) != 0) return -2;
-    qo_targets(n, target_kind, U, Lt, tpairs, tgates, M, psi, phi);
+    if (any_draw(d, n, M, p->seed, QO_ROLE_TRAIN, 0, psi) != 0) return -2;
+    any_targets(d, n, target_kind, U, Lt, tpairs, tgates, M, psi, phi);
   }
   /* validation set */
   if (target_kind == QO_TARGET_SAMPLES) {
@@ -833,8 +886,8 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
     Mv = p->m_val > 0 ? p->m_val : M;
     psiv = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)Mv * N);
     phiv = (qo_cplx *)malloc(sizeof(qo_cplx) * (size_t)Mv * N);
-    if (qo_draw_states(n, Mv, p->seed, QO_ROLE_VAL, (uint32_t)generation, psiv) != 0) return -2;
-    qo_targets(n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
+    if (any_draw(d, n, Mv, p->seed, QO_ROLE_VAL, (uint32_t)generation, psiv) != 0) return -2;
+    any_targets(d, n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
   }
 
   qo_cplx *gates = (qo_cplx *)malloc(sizeof(qo_cplx) * GS * (size_t)L * S);
@@ -958,16 +1011,16 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
         memcpy(psi, samples_psi, sizeof(qo_cplx) * (size_t)M_new * N);
         memcpy(phi, samples_phi, sizeof(qo_cplx) * (size_t)M_new * N);
       } else {
-        if (qo_extend_states(n, M, M_new, p->seed, psi) != 0) return -2;
-        qo_targets(n, target_kind, U, Lt, tpairs, tgates, M_new - M, psi + (size_t)M * N,
-                   phi + (size_t)M * N);
+        if (any_extend(d, n, M, M_new, p->seed, psi) != 0) return -2;
+        any_targets(d, n, target_kind, U, Lt, tpairs, tgates, M_new - M, psi + (size_t)M * N,
+                    phi + (size_t)M * N);
         ++generation;
         Mv = p->m_val > 0 ? p->m_val : M_new;
         psiv = (qo_cplx *)realloc(psiv, sizeof(qo_cplx) * (size_t)Mv * N);
         phiv = (qo_cplx *)realloc(phiv, sizeof(qo_cplx) * (size_t)Mv * N);
-        if (qo_draw_states(n, Mv, p->seed, QO_ROLE_VAL, (uint32_t)generation, psiv) != 0)
+        if (any_draw(d, n, Mv, p->seed, QO_ROLE_VAL, (uint32_t)generation, psiv) != 0)
           return -2;
-        qo_targets(n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
+        any_targets(d, n, target_kind, U, Lt, tpairs, tgates, Mv, psiv, phiv);
       }
       M = M_new;
       m_total += M;
@@ -1032,6 +1085,23 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds, con
   return instantiate_impl(2, n, L, pairs, kinds, fixed, target_kind, U, Lt, tpairs, tgates,
                           samples_psi, samples_phi, n_samples, n_val, p, gates_in, gates_out, res,
                           trace);
+}
+
+int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, int target_kind,
+                          const qo_cplx *U, int Lt, const int32_t *tpairs, const qo_cplx *tgates,
+                          const qo_params *p, const qo_cplx *gates_in, qo_cplx *gates_out,
+                          qo_result *res, qo_trace *trace) {
+  if (d < 2 || d > 4 || (target_kind != QO_TARGET_DENSE && target_kind != QO_TARGET_CIRCUIT)) return -1;
+  if (target_kind == QO_TARGET_DENSE && !U) return -1;
+  if (target_kind == QO_TARGET_CIRCUIT) {
+    if (Lt < 0 || (Lt > 0 && (!tpairs || !tgates))) return -1;
+    for (int k = 0; k < Lt; ++k) {
+      const int a = tpairs[2 * k], b = tpairs[2 * k + 1];
+      if (a < 0 || b < 0 || a >= n || b >= n || a == b) return -1;
+    }
+  }
+  return instantiate_impl(d, n, L, pairs, NULL, NULL, target_kind, U, Lt, tpairs, tgates, NULL, NULL,
+                          0, 0, p, gates_in, gates_out, res, trace);
 }
 
 int qd_instantiate(int d, int n, int L, const int32_t *pairs, const qo_cplx *samples_psi,

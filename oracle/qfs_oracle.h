@@ -193,6 +193,20 @@ int qd_instantiate(int d, int n, int L, const int32_t *pairs, const qo_cplx *sam
                    const qo_cplx *samples_phi, int n_samples, int n_val, const qo_params *p,
                    const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res, qo_trace *trace);
 
+/* M orthonormal Haar states on N = d^n amplitudes, drawn as qo_draw_states draws them for
+ * N = 2^n (column j of the Ginibre matrix from Philox index j N + i, orthonormalised in
+ * column order). out: [M][N]. */
+int qd_draw_states(int d, int n, int M, uint64_t seed, uint32_t role, uint32_t stream,
+                   qo_cplx *out);
+/* Instantiation against a dense target U ([N][N] row-major) or a target circuit
+ * of Lt two-qudit gates (tpairs [Lt][2], tgates [Lt][D][D]) with states drawn as in
+ * qo_instantiate (N = d^n amplitudes, the same Philox roles, streams and indices),
+ * the same control loop. */
+int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, int target_kind,
+                          const qo_cplx *U, int Lt, const int32_t *tpairs, const qo_cplx *tgates,
+                          const qo_params *p, const qo_cplx *gates_in, qo_cplx *gates_out,
+                          qo_result *res, qo_trace *trace);
+
 /* Full instantiation with the paper's control loop. kinds: [L] or NULL; fixed: [L][16]
  * constant gates (read for QO_GATE_FIXED; replace those slots of gates_in too). */
 int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds,

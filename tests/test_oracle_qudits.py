@@ -183,3 +183,78 @@ def test_qutrit_target_recovered():
     assert info["m_final"] == 18
     C = D.circuit_matrix_d(3, n, pairs, gates)
     assert np.linalg.norm(U - C) ** 2 / 27 < 1e-9
+
+
+# ------------------------------------------------------------- drawn states and targets
+def _lapack_q(A_cols):
+    """Q of the QR factorisation of the N x M matrix whose columns are the rows of A_cols,
+    with diag(R) made real positive (LAPACK Householder, phases fixed after)."""
+    q, r = np.linalg.qr(A_cols.T)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return (q * ph).T
+
+
+@pytest.mark.parametrize("d,n,M", [(3, 3, 5), (4, 2, 7), (3, 4, 12), (2, 5, 6)])
+def test_qudit_draw_is_qr_of_the_ginibre_stream(d, n, M):
+    """Sec. 3 / App. A: the states are the columns of a Haar unitary, here the Q of the
+    N x M Ginibre matrix (Philox index j N + i) with positive diag(R): equal to LAPACK's
+    QR with its phases fixed; the first rows of a larger draw are the smaller draw (what
+    the extension on doubling relies on); d = 2 is the qubit draw."""
+    N = d ** n
+    A = O.ginibre(N, M, 11, O.ROLE_TRAIN, 0)
+    st = O.qd_draw_states(d, n, M, 11, O.ROLE_TRAIN, 0)
+    assert np.allclose(st, _lapack_q(A), atol=1e-12)
+    assert np.allclose(st.conj() @ st.T, np.eye(M), atol=1e-13)
+    big = O.qd_draw_states(d, n, M + 3, 11, O.ROLE_TRAIN, 0)
+    assert np.array_equal(big[:M], st)
+    other = O.qd_draw_states(d, n, M, 11, O.ROLE_VAL, 1)
+    assert np.max(np.abs(other - st)) > 0.1
+    if d == 2:
+        assert np.array_equal(st, O.draw_states(n, M, 11, O.ROLE_TRAIN, 0))
+
+
+def _qudit_problem(d, n, pairs, seed):
+    g = np.random.default_rng(seed)
+    tg = np.stack([I.haar_unitary(d * d, g) for _ in pairs])
+    return tg, D.circuit_matrix_d(d, n, pairs, tg)
+
+
+def test_qudit_dense_and_circuit_targets_agree_and_double():
+    """A target circuit and its dense unitary (built independently by Kronecker
+    products) give the same training pairs, hence the same run: same reason, start,
+    sweeps and doublings, costs to rounding. (M d^(n-2) >= d^2 from the first sweep, so
+    every environment has full rank and each update is unique: with fewer samples the
+    polar factor's completion follows rounding.) The doubling record shows the Sec. 3
+    double-and-restart on drawn states: the new training set is the larger draw (old
+    states kept, new ones orthonormal to them), phi = U psi on it, every gate kept."""
+    d, n = 3, 3
+    pairs = [(0, 1), (1, 2), (0, 1), (1, 2)]
+    tg, U = _qudit_problem(d, n, pairs, 30)
+    p = O.default_params(multistarts=2, m_init=3, seed=9, dist_tol=1e-10, max_iter=300, min_iter=3)
+    ga, ia = O.qd_instantiate_target(d, n, pairs, U=U, params=p, doubling_capacity=4)
+    gb, ib = O.qd_instantiate_target(d, n, pairs, target_pairs=pairs, target_gates=tg, params=p)
+    for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final"):
+        assert ia[k] == ib[k], (k, ia[k], ib[k])
+    assert ia["reason_name"] == "SUCCESS"
+    assert abs(ia["c_train"] - ib["c_train"]) <= 1e-8 * ib["c_train"] + 1e-18
+    assert ia["restarts"] >= 1, ia
+    rec = ia["trace"]["doublings"][0]
+    m_old, m_new = rec["m_old"], rec["m_new"]
+    assert m_new == 2 * m_old
+    draw = O.qd_draw_states(d, n, m_new, 9, O.ROLE_TRAIN, 0)
+    assert np.allclose(rec["psi"], draw, atol=1e-14)
+    assert np.allclose(rec["phi"], rec["psi"] @ U.T, atol=1e-12)
+    assert np.array_equal(rec["gates_before"], rec["gates_after"])
+
+
+@pytest.mark.parametrize("d,n,pairs", [(3, 3, [(0, 1), (1, 2), (0, 1)]), (4, 2, [(0, 1)]),
+                                       (4, 3, [(0, 1), (1, 2)])])
+def test_qudit_reachable_target_recovered_from_drawn_states(d, n, pairs):
+    """A target built from the template is recovered: SUCCESS, and the returned gates
+    reproduce the target unitary (full distance, Eq. 1, from Kronecker products)."""
+    tg, U = _qudit_problem(d, n, pairs, 40 + d + n)
+    p = O.default_params(multistarts=4, m_init=d * d, seed=4, dist_tol=1e-11, max_iter=3000)
+    gates, info = O.qd_instantiate_target(d, n, pairs, target_pairs=pairs, target_gates=tg, params=p)
+    assert info["reason_name"] == "SUCCESS", info
+    C = D.circuit_matrix_d(d, n, pairs, gates)
+    assert np.linalg.norm(U - C) ** 2 / d ** n < 1e-8
