@@ -369,7 +369,7 @@ int qfs_instantiate_samples(const qfs_template *tmpl, const qfs_c128 *psi,
  * d-level gates; a sweep costs O(M d^n) where QFactor's costs O(d^{2n})). Qudit 0 is the
  * most significant base-d digit of the amplitude index (N = d^n); tmpl->n_qubits is the
  * qudit count, tmpl->pairs the ordered qudit pairs; a gate is a D x D unitary, D = d^2,
- * row-major u[q][p] with local index d digit(a) + digit(b). d = 2 or 3; d^n <= 2^24;
+ * row-major u[q][p] with local index d digit(a) + digit(b). d = 2, 3 or 4; d^n <= 2^24;
  * tmpl->kinds must be NULL (QFS_EUNSUPPORTED otherwise).
  *
  * Instantiation on a fixed sample set with the paper's control loop (Sec. 3, App. A), the
@@ -386,6 +386,21 @@ int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *p
                           const qfs_c128 *phi, int32_t n_samples, int32_t n_val,
                           const qfs_params *params, const qfs_c128 *gates_in,
                           qfs_c128 *gates_out, qfs_result *res);
+
+/* The same with a target as for qfs_instantiate: DENSE (U device [N][N] row-major,
+ * N = d^n <= 2^16) or CIRCUIT (target->circuit a host template on the same n qudits, its
+ * kinds ignored; target->circuit_gates device [Lt][D][D]), with the training and
+ * validation states drawn on the device as qfs_instantiate draws them for qubits (Sec. 3,
+ * App. A: columns of a Haar unitary; Philox role 1 stream 0 for training, role 2 stream =
+ * generation for validation, index j N + i; M_val = params->m_val or M, capped at N), the
+ * targets formed on the device (U psi by the dense product, or the target circuit's
+ * gates applied in order); a doubling extends the training set by the next columns of
+ * its stream, orthonormal to the earlier ones, keeps every gate, and draws the next
+ * validation generation. SAMPLES forwards to qfs_qudit_instantiate. Errors as there, plus
+ * QFS_ENUMERIC when a drawn set fails to orthonormalise. */
+int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_target *target,
+                                 const qfs_params *params, const qfs_c128 *gates_in,
+                                 qfs_c128 *gates_out, qfs_result *res);
 
 /* One qudit sweep for `starts` starts sharing a training set, as qfs_sweep: psi, phi
  * device [M][N]; gates device [starts][L][D][D] updated in place; c_train host [starts]

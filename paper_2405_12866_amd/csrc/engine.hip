@@ -36,7 +36,6 @@ int pool_stream(int index, hipStream_t *out) {
 
 namespace {
 
-enum { kRoleTrain = 1, kRoleVal = 2 };
 enum { kClsStep = 0, kClsForward = 1, kClsDist = 2, kClsPolar = 3, kClasses = 4 };
 
 double now_s() {

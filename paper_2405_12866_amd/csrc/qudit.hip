@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kQdBlock = 256;
 constexpr int kQdMaxP = 64;  // environment partial blocks per (start, row group)
+constexpr int kQdMaxDD = 256;  // entries of the largest gate (d = 4: 16 x 16)
 // Jacobi stops when every column pair has |g_p^dagger g_q| <= tol |g_p| |g_q|. The Gram
 // entry of D-long columns carries a rounding error of about D eps |g_p| |g_q| (1e-15 for
 // D = 9), so the threshold sits above it; the polar factor is then accurate to ~1e-14.
@@ -97,7 +98,10 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_apply(const cx<R> *src, int64_t
         off[a * d + b] = (base + a * g.sa + b * g.sb) * g.M + j;
         in[a * d + b] = x[off[a * d + b]];
       }
-#pragma unroll
+    // (d > 2: output rows d at a time, so the compiler does not hold the whole gate in
+    // registers across the item loop)
+    constexpr int UQ = d == 2 ? D : d;
+#pragma unroll UQ
     for (int q = 0; q < D; ++q) {
       cx<R> acc = cmake<R>(0, 0);
 #pragma unroll
@@ -136,30 +140,39 @@ __device__ __forceinline__ double qwave_sum(double (&v)[NV]) {
   return v[0];
 }
 
-// Environment partials: block (row group xg, partial blk, start) accumulates rows
-// q = d xg + y (y < d) of Gamma[q][p] = sum a(q) conj(b(p)) over its items in FP64 and
+// Rows of the environment one block accumulates: d (one value of the first gate qudit's
+// digit) for d <= 3, two for d = 4, where d rows would hold 128 FP64 accumulators a thread.
+template <int d>
+constexpr int qd_env_rows() {
+  return d <= 3 ? d : 2;
+}
+
+// Environment partials: block (row set xg, partial blk, start) accumulates rows
+// q = RY xg + y (y < RY) of Gamma[q][p] = sum a(q) conj(b(p)) over its items in FP64 and
 // writes them to partials[s][blk][q][p].
 template <typename R, int d>
 __global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_stride, const cx<R> *b,
                                                      int64_t b_stride, QdGeom g, int32_t P,
                                                      c128 *partials, const int32_t *slots) {
   constexpr int D = d * d;
+  constexpr int RY = qd_env_rows<d>();
+  constexpr int NX = D / RY;  // row sets
   constexpr int W = kQdBlock / 64;
-  __shared__ c128 red[W][d * D];
+  __shared__ c128 red[W][RY * D];
   const int s = slots[blockIdx.y];
-  const int xg = blockIdx.x % d, blk = blockIdx.x / d;
+  const int xg = blockIdx.x % NX, blk = blockIdx.x / NX;
   const cx<R> *as = a + (int64_t)s * a_stride;
   const cx<R> *bs = b + (int64_t)s * b_stride;
-  c128 acc[d][D];
+  c128 acc[RY][D];
 #pragma unroll
-  for (int y = 0; y < d; ++y)
+  for (int y = 0; y < RY; ++y)
 #pragma unroll
     for (int p = 0; p < D; ++p) acc[y][p] = cmake(0.0, 0.0);
   const int64_t items = g.groups * g.M;
   for (int64_t it = blk * (int64_t)kQdBlock + threadIdx.x; it < items; it += (int64_t)P * kQdBlock) {
     const int64_t j = it % g.M, r = it / g.M;
     const int64_t base = qd_base<d>(g, r);
-    c128 bv[D], av[d];
+    c128 bv[D], av[RY];
 #pragma unroll
     for (int x = 0; x < d; ++x)
 #pragma unroll
@@ -168,24 +181,25 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_s
         bv[x * d + y] = cmake((double)v.re, (double)v.im);
       }
 #pragma unroll
-    for (int y = 0; y < d; ++y) {
-      const cx<R> v = as[(base + xg * g.sa + y * g.sb) * g.M + j];
+    for (int y = 0; y < RY; ++y) {
+      const int q = xg * RY + y;  // local row: digits q / d (first qudit), q % d (second)
+      const cx<R> v = as[(base + (q / d) * g.sa + (q % d) * g.sb) * g.M + j];
       av[y] = cmake((double)v.re, (double)v.im);
     }
 #pragma unroll
-    for (int y = 0; y < d; ++y)
+    for (int y = 0; y < RY; ++y)
 #pragma unroll
       for (int p = 0; p < D; ++p) cfma_conj(acc[y][p], av[y], bv[p]);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   {
-    // the 2 d D reals (value 2 (y D + p) + part), padded with zeros to a power of two
-    constexpr int NR = 2 * d * D;
+    // the 2 RY D reals (value 2 (y D + p) + part), padded with zeros to a power of two
+    constexpr int NR = 2 * RY * D;
     constexpr int NV = NR <= 16 ? 16 : (NR <= 32 ? 32 : 64);
-    static_assert(NR <= 64, "d <= 3");
+    static_assert(NR <= 64, "at most 64 reals a lane");
     double v[NV];
 #pragma unroll
-    for (int y = 0; y < d; ++y)
+    for (int y = 0; y < RY; ++y)
 #pragma unroll
       for (int p = 0; p < D; ++p) {
         v[2 * (y * D + p)] = acc[y][p].re;
@@ -199,11 +213,11 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_s
     if ((lane & ((1 << SH) - 1)) == 0 && idx < NR) reinterpret_cast<double *>(&red[w][0])[idx] = ws;
   }
   __syncthreads();
-  if (threadIdx.x < d * D) {
+  if (threadIdx.x < RY * D) {
     c128 t = red[0][threadIdx.x];
     for (int ww = 1; ww < W; ++ww) t = t + red[ww][threadIdx.x];
     const int y = threadIdx.x / D, p = threadIdx.x % D;
-    const int q = xg * d + y;
+    const int q = xg * RY + y;
     partials[(((int64_t)s * P + blk) * D + q) * D + p] = t;
   }
 }
@@ -504,7 +518,7 @@ __global__ void k_qd_haar(uint64_t seed, int32_t start0, int32_t starts, int32_t
   c128 q[D][D];  // [col][row]
   for (int c = 0; c < D; ++c)
     for (int r = 0; r < D; ++r)
-      q[c][r] = complex_normal(seed, 3u, (uint32_t)(start0 + s), (uint64_t)k * 256u + (uint64_t)(c * D + r));
+      q[c][r] = complex_normal(seed, kRoleInit, (uint32_t)(start0 + s), (uint64_t)k * 256u + (uint64_t)(c * D + r));
   for (int c = 0; c < D; ++c) {
     for (int rep = 0; rep < 2; ++rep)
       for (int o = 0; o < c; ++o) {
@@ -580,8 +594,9 @@ struct QdSweeper {
   }
   int apply_on(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows,
                const int32_t *sl, int ns, hipStream_t s) {
-    return d == 2 ? apply_t<2>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s)
-                  : apply_t<3>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s);
+    return d == 2   ? apply_t<2>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s)
+           : d == 3 ? apply_t<3>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s)
+                    : apply_t<4>(src, ss, dst, ds, k, dagger, Mrows, sl, ns, s);
   }
   int apply(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows) {
     return apply_on(src, ss, dst, ds, k, dagger, Mrows, slots.as<int32_t>(), nslots, st);
@@ -591,7 +606,8 @@ struct QdSweeper {
             hipStream_t s) {
     const QdGeom g = qd_geom(dd, n, M, pairs[2 * k], pairs[2 * k + 1]);
     const int P = (int)std::max<int64_t>(1, std::min<int64_t>(kQdMaxP, (g.groups * M + kQdBlock - 1) / kQdBlock));
-    hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * P, ns), dim3(kQdBlock), 0, s, a, as, b, bs, g, P,
+    hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * dd / qd_env_rows<dd>() * P, ns), dim3(kQdBlock), 0, s, a, as,
+                       b, bs, g, P,
                        partials.as<c128>(), sl);
     QFS_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_qd_envsum<dd>), dim3(ns), dim3(kQdBlock), 0, s, partials.as<c128>(), P, sl, beta, g64,
@@ -604,7 +620,9 @@ struct QdSweeper {
   }
   int env_on(const cx<R> *a, int64_t as, const cx<R> *b, int64_t bs, int k, const int32_t *sl, int ns,
              hipStream_t s) {
-    return d == 2 ? env_t<2>(a, as, b, bs, k, sl, ns, s) : env_t<3>(a, as, b, bs, k, sl, ns, s);
+    return d == 2   ? env_t<2>(a, as, b, bs, k, sl, ns, s)
+           : d == 3 ? env_t<3>(a, as, b, bs, k, sl, ns, s)
+                    : env_t<4>(a, as, b, bs, k, sl, ns, s);
   }
   int dist(const cx<R> *x, int64_t xs, const cx<R> *ref, int64_t rs, int64_t count, int Mrows, double *out) {
     const int P = (int)std::min<int64_t>(kQdMaxP * 4, (count + kQdBlock - 1) / kQdBlock);
@@ -627,8 +645,8 @@ struct QdSweeper {
       QFS_TRY(phiv.alloc(cb * N * Mv));
       QFS_TRY(vstate.alloc(cb * N * Mv * S));
     }
-    QFS_TRY(partials.alloc(sizeof(c128) * (size_t)S * kQdMaxP * 256));
-    QFS_TRY(gam.alloc(sizeof(c128) * (size_t)S * 256));
+    QFS_TRY(partials.alloc(sizeof(c128) * (size_t)S * kQdMaxP * kQdMaxDD));
+    QFS_TRY(gam.alloc(sizeof(c128) * (size_t)S * kQdMaxDD));
     QFS_TRY(dpart.alloc(sizeof(double) * (size_t)S * kQdMaxP * 4));
     if (!costs.ptr) QFS_TRY(costs.alloc(sizeof(double) * 3 * S));
     if (!slots.ptr) QFS_TRY(slots.alloc(sizeof(int32_t) * S));
@@ -731,8 +749,8 @@ int check_gates_unitary_n(const qfs_c128 *gates_dev, size_t count, int D, const 
 }
 
 int qd_validate(int d, const qfs_template *t) {
-  if (d != 2 && d != 3) {
-    set_error_detail("qudits: d must be 2 or 3");
+  if (d < 2 || d > 4) {
+    set_error_detail("qudits: d must be 2, 3 or 4");
     return QFS_EUNSUPPORTED;
   }
   if (!t || t->n_qubits < 2 || t->n_gates < 1 || !t->pairs || qd_pow(d, t->n_qubits) > (int64_t(1) << 24)) {
@@ -774,6 +792,127 @@ int qd_load_sets(QdSweeper<R> &w, const qfs_c128 *psi, const qfs_c128 *phi, int 
   return QFS_OK;
 }
 
+// FP64 amplitude-major master [N][M] into a working set in precision R.
+template <typename R>
+int qd_from_master(const DevBuf &src, int64_t count, DevBuf &dst, hipStream_t st) {
+  if (count <= 0) return QFS_OK;
+  if constexpr (sizeof(R) == 8) {
+    QFS_HIP(hipMemcpyAsync(dst.ptr, src.ptr, sizeof(c128) * (size_t)count, hipMemcpyDeviceToDevice, st));
+    return QFS_OK;
+  } else {
+    return launch_narrow(count, src.as<c128>(), dst.as<c64>(), st);
+  }
+}
+
+// x <- u_k x for k = 0 .. Lt-1 (gates [Lt][D][D], FP64) on an amplitude-major FP64 set of
+// `cols` samples: the target circuit's output states.
+template <int dd>
+int qd_apply_circuit(int n, int cols, c128 *x, const qfs_template *ct, const c128 *gates, const int32_t *slot0,
+                     hipStream_t st) {
+  for (int k = 0; k < ct->n_gates; ++k) {
+    const QdGeom g = qd_geom(dd, n, cols, ct->pairs[2 * k], ct->pairs[2 * k + 1]);
+    hipLaunchKernelGGL((k_qd_apply<double, dd>), dim3(qd_grid(g.groups * cols), 1), dim3(kQdBlock), 0, st, x,
+                       (int64_t)0, x, (int64_t)0, gates, 0, k, 0, g, slot0);
+    QFS_HIP(hipGetLastError());
+  }
+  return QFS_OK;
+}
+
+// Where the sample pairs come from: the caller's fixed set (sample-major rows; the last
+// n_val rows validate), or states drawn here (Sec. 3, App. A: columns of a Haar unitary;
+// Philox roles, streams and indices as for qubits with N = d^n amplitudes) with their
+// target outputs formed here, kept as FP64 amplitude-major masters [N][M]. A doubling
+// extends the drawn training set by the next columns of its stream, orthonormalised
+// against the earlier ones, and draws a new validation set (the next generation).
+struct QdData {
+  int d = 0, n = 0;
+  int64_t N = 0;
+  hipStream_t st = nullptr;
+  const qfs_c128 *psi = nullptr, *phi = nullptr;  // fixed sets
+  int n_train = 0, n_val = 0;
+  const qfs_target *tgt = nullptr;  // drawn sets: DENSE or CIRCUIT target
+  uint64_t seed = 0;
+  int m_val = 0;
+  int M = 0, Mv = 0, generation = 0;
+  DevBuf tpsi, tphi, vpsi, vphi, work, slot0;
+
+  bool drawn() const { return tgt != nullptr; }
+  int val_rows() const { return drawn() ? Mv : n_val; }
+
+  // dst = target applied to the `cols` states of src (both [N][cols])
+  int targets(const DevBuf &src, DevBuf &dst, int cols) {
+    if (tgt->kind == QFS_TARGET_DENSE) {
+      return launch_zgemm(false, (int)N, cols, (int)N, cmake(1.0, 0.0), reinterpret_cast<const c128 *>(tgt->U),
+                          (int)N, src.as<c128>(), cols, cmake(0.0, 0.0), dst.as<c128>(), cols, st);
+    }
+    QFS_HIP(hipMemcpyAsync(dst.ptr, src.ptr, sizeof(c128) * (size_t)N * cols, hipMemcpyDeviceToDevice, st));
+    if (!slot0.ptr) {
+      const int32_t zero = 0;
+      QFS_TRY(slot0.alloc(sizeof(int32_t)));
+      QFS_HIP(hipMemcpyAsync(slot0.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, st));
+      QFS_HIP(hipStreamSynchronize(st));
+    }
+    const c128 *tg = reinterpret_cast<const c128 *>(tgt->circuit_gates);
+    c128 *x = dst.as<c128>();
+    const int32_t *s0 = slot0.as<int32_t>();
+    return d == 2   ? qd_apply_circuit<2>(n, cols, x, tgt->circuit, tg, s0, st)
+           : d == 3 ? qd_apply_circuit<3>(n, cols, x, tgt->circuit, tg, s0, st)
+                    : qd_apply_circuit<4>(n, cols, x, tgt->circuit, tg, s0, st);
+  }
+  // columns [c0, c1) of the [N][c1] set A: Ginibre draw, orthonormalised against columns
+  // [0, c0) and among themselves
+  int draw(DevBuf &A, int c0, int c1, uint32_t role, uint32_t stream) {
+    QFS_TRY(launch_ginibre(N, c0, c1, c1, seed, role, stream, A.as<c128>(), st));
+    QFS_TRY(work.alloc(work_bytes_orth(N, c1)));
+    QFS_TRY(orthonormalize_columns(N, c1, c0, c1, A.as<c128>(), work.ptr, st));
+    work.release();
+    return QFS_OK;
+  }
+  int draw_validation(int Mtrain) {
+    Mv = (int)std::min<int64_t>(m_val > 0 ? m_val : Mtrain, N);
+    QFS_TRY(vpsi.alloc(sizeof(c128) * (size_t)N * Mv));
+    QFS_TRY(vphi.alloc(sizeof(c128) * (size_t)N * Mv));
+    QFS_TRY(draw(vpsi, 0, Mv, kRoleVal, (uint32_t)generation));
+    return targets(vpsi, vphi, Mv);
+  }
+  int init(int M0) {
+    if (!drawn()) return QFS_OK;
+    M = M0;
+    QFS_TRY(tpsi.alloc(sizeof(c128) * (size_t)N * M));
+    QFS_TRY(tphi.alloc(sizeof(c128) * (size_t)N * M));
+    QFS_TRY(draw(tpsi, 0, M, kRoleTrain, 0));
+    QFS_TRY(targets(tpsi, tphi, M));
+    return draw_validation(M);
+  }
+  int grow(int Mnew) {
+    if (!drawn() || Mnew == M) return QFS_OK;
+    DevBuf np, nf;
+    QFS_TRY(np.alloc(sizeof(c128) * (size_t)N * Mnew));
+    QFS_TRY(nf.alloc(sizeof(c128) * (size_t)N * Mnew));
+    QFS_HIP(hipMemcpy2DAsync(np.ptr, sizeof(c128) * Mnew, tpsi.ptr, sizeof(c128) * M, sizeof(c128) * M, N,
+                             hipMemcpyDeviceToDevice, st));
+    QFS_TRY(draw(np, M, Mnew, kRoleTrain, 0));
+    QFS_TRY(targets(np, nf, Mnew));  // each column's output depends on that column alone
+    QFS_HIP(hipStreamSynchronize(st));
+    std::swap(tpsi.ptr, np.ptr);
+    std::swap(tpsi.bytes, np.bytes);
+    std::swap(tphi.ptr, nf.ptr);
+    std::swap(tphi.bytes, nf.bytes);
+    M = Mnew;
+    ++generation;
+    return draw_validation(M);
+  }
+  template <typename R>
+  int load(QdSweeper<R> &w) {
+    if (!drawn()) return qd_load_sets<R>(w, psi, phi, n_train, n_val);
+    QFS_TRY(qd_from_master<R>(tpsi, N * w.M, w.psi, st));
+    QFS_TRY(qd_from_master<R>(tphi, N * w.M, w.phi, st));
+    QFS_TRY(qd_from_master<R>(vpsi, N * w.Mv, w.psiv, st));
+    QFS_TRY(qd_from_master<R>(vphi, N * w.Mv, w.phiv, st));
+    return QFS_OK;
+  }
+};
+
 // The App. A control loop on a fixed sample set, for one precision; returns when every
 // start has stopped, a start succeeded, or the precision switch is due (refine = true).
 struct QdState {
@@ -787,8 +926,9 @@ struct QdState {
 };
 
 template <typename R>
-int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *phi, int n_train, int n_val,
-           const qfs_params &p, c128 *g64, c128 *vst, int S, QdState &cs, double t0, bool &refine) {
+int qd_run(int d, const qfs_template *t, QdData &data, const qfs_params &p, c128 *g64, c128 *vst, int S,
+           QdState &cs, double t0, bool &refine) {
+  int n_val = data.val_rows();
   QdSweeper<R> w;
   w.d = d;
   w.n = t->n_qubits;
@@ -801,7 +941,7 @@ int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *ph
   w.vst = vst;
   w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
   QFS_TRY(w.alloc(cs.M, n_val));
-  QFS_TRY(qd_load_sets<R>(w, psi, phi, n_train, n_val));
+  QFS_TRY(data.load<R>(w));
   std::vector<int> active;
   for (int s = 0; s < S; ++s)
     if (cs.status[s] != ST_STOP) active.push_back(s);
@@ -874,9 +1014,11 @@ int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *ph
           active.push_back(s);
         }
       QFS_HIP(hipStreamSynchronize(w.st));
+      QFS_TRY(data.grow(cs.M));
+      n_val = data.val_rows();
       QFS_TRY(w.alloc(cs.M, n_val));
       w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
-      QFS_TRY(qd_load_sets<R>(w, psi, phi, n_train, n_val));
+      QFS_TRY(data.load<R>(w));
       QFS_TRY(w.set_slots(active));
       QFS_TRY(w.forward(true));
       QFS_TRY(read());
@@ -903,33 +1045,22 @@ int qd_run(int d, const qfs_template *t, const qfs_c128 *psi, const qfs_c128 *ph
   }
 }
 
-}  // namespace
-}  // namespace qfs
-
-using namespace qfs;
-
-extern "C" {
-
-int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi, const qfs_c128 *phi,
-                          int32_t n_samples, int32_t n_val, const qfs_params *params,
-                          const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res) {
-  const double t0 = qd_now();
-  QFS_TRY(qd_validate(d, tmpl));
-  if (!params || !psi || !phi || !gates_out || !res) {
-    set_error_detail("qudits: null argument");
-    return QFS_EINVAL;
-  }
-  const qfs_params &p = *params;
+// Multistart instantiation from initial gates (given or Haar-drawn) on the samples of
+// `data`, FP64 or MIXED with refinement.
+int qd_instantiate_impl(int d, const qfs_template *tmpl, QdData &data, const qfs_params &p,
+                        const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res, double t0) {
   const int n = tmpl->n_qubits, L = tmpl->n_gates, D = d * d;
   const int64_t N = qd_pow(d, n);
-  const int n_train = n_samples - n_val;
-  if (n_val < 0 || n_train < 1 || n_train > N || p.multistarts < 1 || p.m_init < 1 || p.max_iter < 1 ||
-      p.plateau_window < 1 || !(p.beta >= 0 && p.beta <= 1) ||
+  if (p.multistarts < 1 || p.m_init < 1 || p.max_iter < 1 || p.plateau_window < 1 || !(p.beta >= 0 && p.beta <= 1) ||
       (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) || p.full_unitary) {
-    set_error_detail("qudits: bad sample counts or params");
+    set_error_detail("qudits: bad params");
     return QFS_EINVAL;
   }
   hipStream_t st = static_cast<hipStream_t>(p.hip_stream);
+  data.d = d;
+  data.n = n;
+  data.N = N;
+  data.st = st;
   const int S = p.multistarts;
   if (gates_in)
     QFS_TRY(check_gates_unitary_n(gates_in, (size_t)S * L, D, "gates_in", st));
@@ -939,12 +1070,13 @@ int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *p
     QFS_HIP(hipMemcpyAsync(gates.ptr, gates_in, sizeof(c128) * (size_t)S * L * D * D, hipMemcpyDeviceToDevice, st));
   } else {
     const int64_t tot = (int64_t)S * L;
+    const dim3 grid((unsigned)((tot + 63) / 64));
     if (d == 2)
-      hipLaunchKernelGGL(k_qd_haar<2>, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, st, p.seed, 0, S, L,
-                         gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_haar<2>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
+    else if (d == 3)
+      hipLaunchKernelGGL(k_qd_haar<3>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
     else
-      hipLaunchKernelGGL(k_qd_haar<3>, dim3((unsigned)((tot + 63) / 64)), dim3(64), 0, st, p.seed, 0, S, L,
-                         gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_haar<4>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
     QFS_HIP(hipGetLastError());
   }
   DevBuf vstore;
@@ -962,20 +1094,21 @@ int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *p
   cs.ct.assign(S, INFINITY);
   cs.cv.assign(S, INFINITY);
   cs.m_cap = (p.m_max > 0 && p.m_max < N) ? p.m_max : (int)N;
-  cs.m_cap = std::min(cs.m_cap, n_train);
+  if (!data.drawn()) cs.m_cap = std::min(cs.m_cap, data.n_train);
   cs.M = std::max(1, std::min(p.m_init, cs.m_cap));
   if (p.fixed_m) cs.m_cap = cs.M;
   cs.m_total = cs.M;
+  QFS_TRY(data.init(cs.M));
   bool refine = false;
   int refined = 0;
   if (p.precision == QFS_PREC_MIXED) {
-    QFS_TRY(qd_run<float>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
+    QFS_TRY(qd_run<float>(d, tmpl, data, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
     if (refine) {
       refined = 1;
-      QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
+      QFS_TRY(qd_run<double>(d, tmpl, data, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
     }
   } else {
-    QFS_TRY(qd_run<double>(d, tmpl, psi, phi, n_train, n_val, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
+    QFS_TRY(qd_run<double>(d, tmpl, data, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
   }
   if (cs.chosen < 0) {
     double best = INFINITY;
@@ -1005,6 +1138,83 @@ int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *p
   res->amp_updates = cs.amp_updates;
   res->seconds = qd_now() - t0;
   return QFS_OK;
+}
+
+}  // namespace
+}  // namespace qfs
+
+using namespace qfs;
+
+extern "C" {
+
+int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi, const qfs_c128 *phi,
+                          int32_t n_samples, int32_t n_val, const qfs_params *params,
+                          const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res) {
+  const double t0 = qd_now();
+  QFS_TRY(qd_validate(d, tmpl));
+  if (!params || !psi || !phi || !gates_out || !res) {
+    set_error_detail("qudits: null argument");
+    return QFS_EINVAL;
+  }
+  const int64_t N = qd_pow(d, tmpl->n_qubits);
+  const int n_train = n_samples - n_val;
+  if (n_val < 0 || n_train < 1 || n_train > N) {
+    set_error_detail("qudits: bad sample counts");
+    return QFS_EINVAL;
+  }
+  QdData data;
+  data.psi = psi;
+  data.phi = phi;
+  data.n_train = n_train;
+  data.n_val = n_val;
+  return qd_instantiate_impl(d, tmpl, data, *params, gates_in, gates_out, res, t0);
+}
+
+int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_target *target,
+                                 const qfs_params *params, const qfs_c128 *gates_in, qfs_c128 *gates_out,
+                                 qfs_result *res) {
+  const double t0 = qd_now();
+  if (!target) {
+    set_error_detail("qudits: null target");
+    return QFS_EINVAL;
+  }
+  if (target->kind == QFS_TARGET_SAMPLES)
+    return qfs_qudit_instantiate(d, tmpl, target->psi, target->phi, target->n_samples, target->n_val, params,
+                                 gates_in, gates_out, res);
+  QFS_TRY(qd_validate(d, tmpl));
+  if (!params || !gates_out || !res) {
+    set_error_detail("qudits: null argument");
+    return QFS_EINVAL;
+  }
+  const int n = tmpl->n_qubits;
+  const int64_t N = qd_pow(d, n);
+  if (target->kind == QFS_TARGET_DENSE) {
+    if (!target->U || N > (int64_t(1) << 16)) {
+      set_error_detail("qudits: a dense target needs U and d^n <= 2^16");
+      return QFS_EINVAL;
+    }
+  } else if (target->kind == QFS_TARGET_CIRCUIT) {
+    const qfs_template *ct = target->circuit;
+    if (!ct || ct->n_qubits != n || ct->n_gates < 0 || (ct->n_gates > 0 && (!ct->pairs || !target->circuit_gates))) {
+      set_error_detail("qudits: a circuit target needs a template on the same qudits and its gates");
+      return QFS_EINVAL;
+    }
+    for (int k = 0; k < ct->n_gates; ++k) {
+      const int a = ct->pairs[2 * k], b = ct->pairs[2 * k + 1];
+      if (a < 0 || b < 0 || a >= n || b >= n || a == b) {
+        set_error_detail("qudits: target gate " + std::to_string(k) + " has an invalid qudit pair");
+        return QFS_EINVAL;
+      }
+    }
+  } else {
+    set_error_detail("qudits: unknown target kind");
+    return QFS_EINVAL;
+  }
+  QdData data;
+  data.tgt = target;
+  data.seed = params->seed;
+  data.m_val = params->m_val;
+  return qd_instantiate_impl(d, tmpl, data, *params, gates_in, gates_out, res, t0);
 }
 
 int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c128 *psi,

@@ -75,7 +75,8 @@ EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_
            "qfs_mlp_num_params", "qfs_mlp_init", "qfs_mlp_get", "qfs_mlp_set", "qfs_mlp_save",
            "qfs_mlp_load", "qfs_mlp_forward", "qfs_mlp_grad", "qfs_mlp_train", "qfs_predict_m",
            "qfs_predict_batch", "qfs_instantiate_learned", "qfs_instantiate_batch_learned",
-           "qfs_instantiate_batch_ex", "qfs_qudit_instantiate", "qfs_qudit_sweep"]
+           "qfs_instantiate_batch_ex", "qfs_qudit_instantiate", "qfs_qudit_instantiate_target",
+           "qfs_qudit_sweep"]
 
 
 def load():
@@ -139,6 +140,8 @@ def load():
         lib.qfs_predict_batch.argtypes = [I32, C.POINTER(Template), C.POINTER(Params), P, P]
         lib.qfs_qudit_instantiate.argtypes = [I32, C.POINTER(Template), P, P, I32, I32,
                                               C.POINTER(Params), P, P, C.POINTER(Result)]
+        lib.qfs_qudit_instantiate_target.argtypes = [I32, C.POINTER(Template), C.POINTER(Target),
+                                                     C.POINTER(Params), P, P, C.POINTER(Result)]
         lib.qfs_qudit_sweep.argtypes = [I32, I32, I32, P, I32, P, P, I32, P, I32, D, P, P]
         for name in EXPORTS:
             if name not in ("qfs_strerror", "qfs_last_error_detail", "qfs_version",
@@ -571,6 +574,27 @@ def qfs_qudit_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=
     _check(load().qfs_qudit_instantiate(d, C.byref(tmpl), _dev_c128(psi, "psi"), _dev_c128(phi, "phi"),
                                         psi.shape[0], n_val, C.byref(par), gi,
                                         C.c_void_p(out.data_ptr()), C.byref(res)), "qfs_qudit_instantiate")
+    return out, _info(res)
+
+
+def qfs_qudit_instantiate_target(d, n, pairs, *, U=None, target_pairs=None, target_gates=None,
+                                 psi=None, phi=None, n_val=0, params=None, gates_in=None):
+    """Qudit instantiation with one target form: dense ``U`` [d^n, d^n] or a circuit
+    (``target_pairs``, ``target_gates`` [Lt, d^2, d^2]) with states drawn on the device, or
+    samples ``psi``/``phi``. Returns (gates [L, d^2, d^2] device tensor, result dict)."""
+    import torch
+    keep = []
+    tmpl = _template(n, pairs, keep)
+    tgt = Target()
+    dev = _fill_target(tgt, n, keep, U=U, target_pairs=target_pairs, target_gates=target_gates,
+                       psi=psi, phi=phi, n_val=n_val)
+    out = torch.empty((tmpl.n_gates, d * d, d * d), dtype=torch.complex128, device=dev)
+    par = _params(params)
+    res = Result()
+    gi = _dev_c128(gates_in, "gates_in") if gates_in is not None else None
+    _check(load().qfs_qudit_instantiate_target(d, C.byref(tmpl), C.byref(tgt), C.byref(par), gi,
+                                               C.c_void_p(out.data_ptr()), C.byref(res)),
+           "qfs_qudit_instantiate_target")
     return out, _info(res)
 
 

@@ -145,3 +145,48 @@ def test_invalid_params_rejected():
         rc = lib.qfs_instantiate(C.byref(tmpl), C.byref(tgt), C.byref(par), None, C.c_void_p(16),
                                  C.byref(res))
         assert rc == Q.QFS_EINVAL, field
+
+
+def test_qudit_target_arguments_rejected_without_device_work():
+    """qfs_qudit_instantiate_target checks d, the template, the target and the params on
+    the host before any device call."""
+    lib = Q.load()
+    arr = np.ascontiguousarray(np.asarray([(0, 1), (1, 2)], dtype=np.int32))
+    tmpl = Q.Template(3, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)))
+    other = Q.Template(4, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)))
+    bad_pairs = np.ascontiguousarray(np.asarray([(0, 3)], dtype=np.int32))
+    bad_circ = Q.Template(3, 1, bad_pairs.ctypes.data_as(C.POINTER(C.c_int32)))
+    par = Q.Params()
+    lib.qfs_default_params(C.byref(par))
+    res = Q.Result()
+    out = C.c_void_p(16)
+
+    def call(d, tmpl_, tgt, p=par):
+        return lib.qfs_qudit_instantiate_target(d, C.byref(tmpl_), C.byref(tgt), C.byref(p), None, out,
+                                                C.byref(res))
+
+    dense = Q.Target()
+    dense.kind = Q.QFS_TARGET_DENSE
+    dense.U = C.c_void_p(16)
+    assert call(5, tmpl, dense) == Q.QFS_EUNSUPPORTED
+    assert call(1, tmpl, dense) == Q.QFS_EUNSUPPORTED
+    no_u = Q.Target()
+    no_u.kind = Q.QFS_TARGET_DENSE
+    assert call(3, tmpl, no_u) == Q.QFS_EINVAL
+    big = Q.Template(9, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)))  # 4^9 > 2^16 amplitudes
+    assert call(4, big, dense) == Q.QFS_EINVAL
+    for ct in (other, bad_circ):
+        circ = Q.Target()
+        circ.kind = Q.QFS_TARGET_CIRCUIT
+        circ.circuit = C.pointer(ct)
+        circ.circuit_gates = C.c_void_p(16)
+        assert call(3, tmpl, circ) == Q.QFS_EINVAL
+    unknown = Q.Target()
+    unknown.kind = 7
+    assert call(3, tmpl, unknown) == Q.QFS_EINVAL
+    for field, bad in [("multistarts", 0), ("beta", 1.5), ("precision", 7), ("max_iter", 0),
+                       ("full_unitary", 1)]:
+        p = Q.Params()
+        lib.qfs_default_params(C.byref(p))
+        setattr(p, field, bad)
+        assert call(3, tmpl, dense, p) == Q.QFS_EINVAL, field

@@ -1,9 +1,10 @@
 """GPU parity of the qudit path (Sec. 5: the method on d-level gates) against the FP64
 oracle's qudit functions, through the C ABI.
 
-d = 2 must reproduce the qubit path; d = 3 (qutrits) runs in lock step with the oracle
-(FP64: cost and gates 1e-10 over 10 sweeps; complex64 states teacher-forced,
-|dc| <= 1e-6 max(c, c_initial)), follows its control flow, and handles a rank-deficient
+d = 2 must reproduce the qubit path; d = 3 (qutrits) and d = 4 run in lock step with the
+oracle (FP64: cost and gates 1e-10 over 10 sweeps; complex64 states teacher-forced,
+|dc| <= 1e-6 max(c, c_initial)), follow its control flow on fixed sample sets and on
+dense and circuit targets with states drawn on each side, and handle a rank-deficient
 environment (several optimal gates: the cost, which depends only on the sum of singular
 values, is compared).
 """
@@ -156,11 +157,159 @@ def test_qutrit_instantiate_mixed_reaches_target():
 
 def test_qudit_entries_reject_bad_arguments():
     say("qudit argument checks")
-    psi = dev(np.eye(16)[:2])
+    psi = dev(np.eye(25)[:2])
     with pytest.raises(Q.QfsError) as e:
-        Q.qfs_qudit_instantiate(4, 2, [(0, 1)], psi, psi, params=Q.qfs_default_params())
+        Q.qfs_qudit_instantiate(5, 2, [(0, 1)], psi, psi, params=Q.qfs_default_params())
     assert e.value.code == Q.QFS_EUNSUPPORTED
     psi = dev(np.eye(9)[:2])
     with pytest.raises(Q.QfsError) as e:
         Q.qfs_qudit_instantiate(3, 2, [(0, 0)], psi, psi, params=Q.qfs_default_params())
     assert e.value.code == Q.QFS_EINVAL
+
+
+@pytest.mark.parametrize("n,L,M,starts", [(2, 1, 17, 1), (2, 3, 16, 2), (3, 4, 7, 2), (4, 5, 3, 3)])
+def test_d4_fp64_lock_step(n, L, M, starts):
+    """d = 4: 16 x 16 gates (environment rows two per block, the 16 x 16 Jacobi polar).
+    M 4^(n-2) >= 16, so every environment has full rank and the updated gates are unique."""
+    say(f"d=4 fp64 lock-step n={n} L={L} M={M} starts={starts}")
+    pairs, psi, phi, gates, _ = _problem(4, n, L, M, starts, seed=100 + 10 * n + L)
+    dg, dpsi, dphi = dev(gates), dev(psi), dev(phi)
+    ref = gates.copy()
+    for sweep in range(10):
+        c = Q.qfs_qudit_sweep(4, n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_FP64)
+        for s in range(starts):
+            ref[s], cr = O.qd_sweep(4, n, pairs, psi, phi, ref[s])
+            assert abs(c[s] - cr) <= 1e-10 * max(cr, 1e-3), (sweep, s, c[s], cr)
+        assert np.max(np.abs(host(dg) - ref)) < 1e-10
+
+
+def test_d4_rank_deficient_environment():
+    """n = 2 ququarts, M = 5: each 16 x 16 environment has rank 5, so the polar factor is
+    not unique; the gates must stay unitary and each sweep's cost must match the oracle's
+    from the same gates (it depends only on the singular values)."""
+    say("d=4 rank-deficient environment")
+    pairs, psi, phi, gates, _ = _problem(4, 2, 3, 5, 2, seed=130)
+    dg, dpsi, dphi = dev(gates), dev(psi), dev(phi)
+    for sweep in range(4):
+        start = host(dg).copy()
+        c = Q.qfs_qudit_sweep(4, 2, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_FP64)
+        for s in range(2):
+            _, cr = O.qd_sweep(4, 2, pairs, psi, phi, start[s])
+            assert abs(c[s] - cr) <= 1e-10 * max(cr, 1e-3), (sweep, s, c[s], cr)
+            for u in host(dg)[s]:
+                assert np.max(np.abs(u.conj().T @ u - np.eye(16))) < 1e-12
+
+
+def test_d4_mixed_teacher_forced():
+    say("d=4 mixed teacher-forced n=4")
+    n, L, M = 4, 6, 12
+    pairs, psi, phi, gates, _ = _problem(4, n, L, M, 2, seed=71)
+    dpsi, dphi, dg = dev(psi), dev(phi), dev(gates)
+    c_init = max(O.qd_sweep(4, n, pairs, psi, phi, gates[0])[1], 1e-3)
+    for sweep in range(4):
+        start = host(dg).copy()
+        c = Q.qfs_qudit_sweep(4, n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED)
+        new = host(dg)
+        for s in range(2):
+            _, cr = O.qd_sweep(4, n, pairs, psi, phi, start[s])
+            assert abs(c[s] - cr) <= 1e-6 * max(cr, c_init), (sweep, s, c[s], cr)
+            for u in new[s]:
+                assert np.max(np.abs(u.conj().T @ u - np.eye(16))) < 1e-12
+
+
+def test_d4_instantiate_follows_oracle():
+    """FP64 on a fixed set of 3 ququarts (N = 64): same reason, start, sweeps, doublings,
+    final M and cost as the oracle."""
+    say("d=4 instantiate vs oracle n=3")
+    n = 3
+    g = np.random.default_rng(23)
+    pairs = [(0, 1), (1, 2)]
+    tg = np.stack([I.haar_unitary(16, g) for _ in pairs])
+    psi = _samples(4, n, 64, g)
+    phi = O.qd_apply_circuit(4, n, psi, pairs, tg)
+    p = O.default_params(multistarts=2, m_init=4, seed=8, dist_tol=1e-11, max_iter=400)
+    g_ref, ref = O.qd_instantiate(4, n, pairs, psi, phi, n_val=16, params=p)
+    g_gpu, got = Q.qfs_qudit_instantiate(4, n, pairs, dev(psi), dev(phi), n_val=16,
+                                         params=dict(p, precision=Q.QFS_PREC_FP64))
+    for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final"):
+        assert got[k] == ref[k], (k, got, ref)
+    assert abs(got["c_train"] - ref["c_train"]) <= 1e-9 * max(ref["c_train"], 1e-12) + 1e-20
+    assert np.max(np.abs(host(g_gpu) - g_ref)) < 1e-8
+
+
+def _target_case(d, n, pairs, seed):
+    g = np.random.default_rng(seed)
+    tg = np.stack([I.haar_unitary(d * d, g) for _ in pairs])
+    return tg
+
+
+@pytest.mark.parametrize("d,n,pairs,form,m_init,starts", [
+    (3, 3, [(0, 1), (1, 2), (0, 1), (1, 2)], "dense", 3, 2),
+    (3, 3, [(0, 1), (1, 2), (0, 1), (1, 2)], "circuit", 3, 2),
+    (3, 4, [(0, 1), (2, 3), (1, 2), (0, 1)], "circuit", 2, 2),
+    (4, 3, [(0, 1), (1, 2)], "circuit", 4, 1),
+])
+def test_qudit_target_instantiate_follows_oracle(d, n, pairs, form, m_init, starts):
+    """States drawn on each side (device: Philox + CholeskyQR2; oracle: Philox +
+    Gram-Schmidt), targets formed on each side, FP64: same reason, start, sweeps,
+    doublings and final M, cost and gates to rounding. Every environment has full rank
+    (M d^(n-2) >= d^2), so each update is unique. (The d = 4 case runs one start: there
+    every start reaches the exact target, cost ~1e-30, so the pick among starts that
+    succeed in the same sweep is decided by rounding.)"""
+    say(f"qudit target instantiate d={d} n={n} {form} m_init={m_init} starts={starts}")
+    tg = _target_case(d, n, pairs, 50 + d + n)
+    p = O.default_params(multistarts=starts, m_init=m_init, seed=9, dist_tol=1e-10, max_iter=300, min_iter=3)
+    if form == "dense":
+        # row c of the circuit applied to the basis rows is column c of its unitary
+        U = O.qd_apply_circuit(d, n, np.eye(d ** n, dtype=np.complex128), pairs, tg).T.copy()
+        g_ref, ref = O.qd_instantiate_target(d, n, pairs, U=U, params=p)
+        g_gpu, got = Q.qfs_qudit_instantiate_target(d, n, pairs, U=dev(U),
+                                                    params=dict(p, precision=Q.QFS_PREC_FP64))
+    else:
+        g_ref, ref = O.qd_instantiate_target(d, n, pairs, target_pairs=pairs, target_gates=tg, params=p)
+        g_gpu, got = Q.qfs_qudit_instantiate_target(d, n, pairs, target_pairs=pairs, target_gates=dev(tg),
+                                                    params=dict(p, precision=Q.QFS_PREC_FP64))
+    say(f"  oracle {ref['reason_name']} sweeps={ref['sweeps']} restarts={ref['restarts']} "
+        f"c={ref['c_train']:.3e}; device {got['reason_name']} sweeps={got['sweeps']} c={got['c_train']:.3e}")
+    for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final"):
+        assert got[k] == ref[k], (k, got, ref)
+    assert ref["restarts"] >= 1
+    assert abs(got["c_train"] - ref["c_train"]) <= 1e-8 * ref["c_train"] + 1e-18
+    assert abs(got["c_val"] - ref["c_val"]) <= 1e-8 * ref["c_val"] + 1e-18
+    assert np.max(np.abs(host(g_gpu) - g_ref)) < 1e-7
+
+
+def test_qutrit_circuit_target_mixed_reaches_target():
+    """complex64 states with complex128 refinement, 5 qutrits, drawn states with doubling:
+    success, and the returned gates reproduce the target on fresh states."""
+    say("qutrit circuit target mixed n=5")
+    n = 5
+    pairs = [(0, 1), (2, 3), (1, 2), (3, 4)]
+    tg = _target_case(3, n, pairs, 61)
+    p = Q.qfs_default_params(multistarts=8, m_init=3, seed=6, dist_tol=1e-9, max_iter=3000)
+    gates, info = Q.qfs_qudit_instantiate_target(3, n, pairs, target_pairs=pairs, target_gates=dev(tg),
+                                                 params=p)
+    say(f"  {info['reason_name']} m_final={info['m_final']} restarts={info['restarts']} refined={info['refined']}")
+    assert info["reason_name"] == "SUCCESS", info
+    fresh = _samples(3, n, 12, np.random.default_rng(62))
+    a = O.qd_apply_circuit(3, n, fresh, pairs, host(gates))
+    b = O.qd_apply_circuit(3, n, fresh, pairs, tg)
+    assert np.sum(np.abs(a - b) ** 2) / 12 < 1e-7
+
+
+def test_qudit_target_samples_form_forwards():
+    """The SAMPLES form of the target entry is qfs_qudit_instantiate."""
+    say("qudit target samples form")
+    n = 3
+    g = np.random.default_rng(24)
+    pairs = [(0, 1), (1, 2)]
+    tg = np.stack([I.haar_unitary(9, g) for _ in pairs])
+    psi = _samples(3, n, 27, g)
+    phi = O.qd_apply_circuit(3, n, psi, pairs, tg)
+    p = Q.qfs_default_params(multistarts=2, m_init=9, seed=3, dist_tol=1e-11, max_iter=200,
+                             precision=Q.QFS_PREC_FP64)
+    ga, ia = Q.qfs_qudit_instantiate(3, n, pairs, dev(psi), dev(phi), n_val=0, params=p)
+    gb, ib = Q.qfs_qudit_instantiate_target(3, n, pairs, psi=dev(psi), phi=dev(phi), n_val=0, params=p)
+    for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final", "c_train"):
+        assert ia[k] == ib[k], k
+    assert torch.equal(ga, gb)
