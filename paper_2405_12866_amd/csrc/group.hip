@@ -175,11 +175,12 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
 #pragma unroll
   for (int u = 0; u < kMaxPkt; ++u) eo[u] = eo_t | elem_off(((uint32_t)u * kGBlock) & (npk - 1u));
 
-  // the previous group's operator as the A operand of the apply: V[l % 16][4 t + l / 16]
+  // the previous group's operator as the A operand of the apply: V[l % 16][4 t + l / 16],
+  // as Re V, Re V + Im V and Im V - Re V for the three-product complex multiply
   const bool apply = A.vop != nullptr;
-  R vre[4], vim[4], vnim[4];
+  R vre[4], vsum[4], vdif[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) vre[t] = vim[t] = vnim[t] = R(0);
+  for (int t = 0; t < 4; ++t) vre[t] = vsum[t] = vdif[t] = R(0);
   uint32_t rd_off[4], wr_off[4];
   const int ncb = nP - 4;
   const uint32_t ncols = (1u << ncb) << LOGV;
@@ -190,8 +191,8 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
     for (int t = 0; t < 4; ++t) {
       const c128 x = vs[(lane & 15) * 16 + 4 * t + (lane >> 4)];
       vre[t] = (R)x.re;
-      vim[t] = (R)x.im;
-      vnim[t] = -(R)x.im;
+      vsum[t] = (R)x.re + (R)x.im;
+      vdif[t] = (R)x.im - (R)x.re;
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -259,25 +260,26 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
     if (tau + P < tiles) fetch(tau + P);
     if (apply) {
       // a <- V a on the operator's slots: (16 x 16) x (16 x 16-column block) products on the
-      // matrix cores, each wave on its own column blocks, results written back in place
+      // matrix cores, each wave on its own column blocks, results written back in place.
+      // Three real products per complex one: T1 = Re V (Re x + Im x), T2 = (Re V + Im V) Im x,
+      // T3 = (Im V - Re V) Re x; Re(V x) = T1 - T2, Im(V x) = T1 + T3.
       for (uint32_t blk = wv; blk < nblk; blk += kGWaves) {
         const uint32_t j = blk * 16 + (lane & 15);
         const bool ok = j < ncols;
         const int e = (int)(j & (V - 1));
         const uint32_t cofs = spread_bits(j >> LOGV, A.cpos, ncb);
-        acc_t dre = {0, 0, 0, 0}, dim = {0, 0, 0, 0};
+        acc_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           cx<R> x = cmake<R>(0, 0);
           if (ok) x = lds_elem(la, rd_off[t] | cofs, e, R(0));
-          dre = MF::mma(vre[t], x.re, dre);
-          dre = MF::mma(vnim[t], x.im, dre);
-          dim = MF::mma(vre[t], x.im, dim);
-          dim = MF::mma(vim[t], x.re, dim);
+          t1 = MF::mma(vre[t], x.re + x.im, t1);
+          t2 = MF::mma(vsum[t], x.im, t2);
+          t3 = MF::mma(vdif[t], x.re, t3);
         }
         if (ok) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) lds_elem_put(la, wr_off[v] | cofs, e, cmake<R>(dre[v], dim[v]));
+          for (int v = 0; v < 4; ++v) lds_elem_put(la, wr_off[v] | cofs, e, cmake<R>(t1[v] - t2[v], t1[v] + t3[v]));
         }
       }
       lds_barrier();
@@ -290,7 +292,9 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
       }
     }
     if (!DIST && A.env) {
-      acc_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ir = {0, 0, 0, 0}, ri = {0, 0, 0, 0};
+      // G += a b^H by three real products: T1 = (Re a + Im a)(Re b + Im b)^T,
+      // T2 = Re a Im b^T, T3 = Im a Re b^T; Re G = T1 - T2 - T3, Im G = T3 - T2
+      acc_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
       for (uint32_t j = wv; j < nkq; j += kGWaves) {
         const uint32_t pk = zoff | kkoff | (nK > 2 ? spread_bits(j, A.kpos + 2, nK - 2) : 0u);
         Pk<R> av, bv;
@@ -303,16 +307,15 @@ __global__ __launch_bounds__(kGBlock) void k_bwd_group(GroupArgs<R> A) {
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          rr = MF::mma(av.v[v].re, bv.v[v].re, rr);
-          ii = MF::mma(av.v[v].im, bv.v[v].im, ii);
-          ir = MF::mma(av.v[v].im, bv.v[v].re, ir);
-          ri = MF::mma(av.v[v].re, bv.v[v].im, ri);
+          t1 = MF::mma(av.v[v].re + av.v[v].im, bv.v[v].re + bv.v[v].im, t1);
+          t2 = MF::mma(av.v[v].re, bv.v[v].im, t2);
+          t3 = MF::mma(av.v[v].im, bv.v[v].re, t3);
         }
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        gre[v] += (double)rr[v] + (double)ii[v];
-        gim[v] += (double)ir[v] - (double)ri[v];
+        gre[v] += ((double)t1[v] - (double)t2[v]) - (double)t3[v];
+        gim[v] += (double)t3[v] - (double)t2[v];
       }
     }
     if (DIST) {
