@@ -752,8 +752,10 @@ int Group::setup_working() {
   const size_t lds = lds_max_bytes();
   const bool fused = forward_fusable(n_, rb, lds);
   static const int logc_cap = [] {
-    const char *e = std::getenv("QFS_LOGC_MAX");  // tuning aid: cap the chunk width 2^logC
-    return e ? std::max(0, std::atoi(e)) : 30;
+    // tuning aid: cap the chunk width 2^logC (at least two samples: a complex64 packet
+    // holds two samples of one amplitude)
+    const char *e = std::getenv("QFS_LOGC_MAX");
+    return e ? std::max(1, std::atoi(e)) : 30;
   }();
   const int logC = std::min(logc_cap, choose_log_chunk(n_, M_, rb, fused, S_, lds));
   const int C = 1 << logC;
