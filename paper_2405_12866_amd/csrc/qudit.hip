@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "philox.h"
+#include "polar4.h"
 #include "qfs_internal.h"
 
 namespace qfs {
@@ -222,231 +223,66 @@ __global__ __launch_bounds__(kQdBlock) void k_qd_env(const cx<R> *a, int64_t a_s
   }
 }
 
-// Fixed-order sum of the environment partials of every active start into gam [S][D][D]
-// (mixed with the gate when beta != 0).
-template <int d>
-__global__ __launch_bounds__(kQdBlock) void k_qd_envsum(const c128 *partials, int32_t P, const int32_t *slots,
-                                                        double beta, const c128 *gates, int32_t gstride,
-                                                        int32_t k, c128 *gam) {
-  constexpr int D = d * d;
-  const int s = slots[blockIdx.x];
-  const c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
-  for (int e = threadIdx.x; e < D * D; e += kQdBlock) {
-    const c128 *src = partials + (int64_t)s * P * D * D + e;
-    c128 a0 = cmake(0.0, 0.0), a1 = cmake(0.0, 0.0);
-    int blk = 0;
-    for (; blk + 1 < P; blk += 2) {
-      a0 = a0 + src[(int64_t)blk * D * D];
-      a1 = a1 + src[(int64_t)(blk + 1) * D * D];
-    }
-    if (blk < P) a0 = a0 + src[(int64_t)blk * D * D];
-    const c128 gm = a0 + a1;
-    gam[(int64_t)s * D * D + e] =
-        beta != 0.0 ? cmake((1.0 - beta) * gm.re + beta * u[e].re, (1.0 - beta) * gm.im + beta * u[e].im) : gm;
-  }
-}
-
-// Per start (one wave): u_k <- W V^dagger for the mixed environment gam =
-// (1 - beta) Gamma + beta u_k = W S V^dagger by one-sided Jacobi on one wave. The working
-// matrix G and V live in LDS, lane r owning row r, so a rotation touches only the lane's own
-// row and the only cross-lane steps are the wave sums of the three Gram entries of a
-// column pair. Pairs are rotated in round-robin rounds (circle method on D rounded up to
-// even, a ghost column when D is odd): the pairs of a round are disjoint, so their sums are
-// formed together. Warm start: Jacobi begins from G V_prev with V_prev, the right singular
-// vectors this gate had after its previous update (vst, made unitary to rounding by one
-// Newton-Schulz step V (3I - V^dagger V) / 2), so a sweep of small changes converges in a
-// few Jacobi sweeps; the new V is stored back.
-template <int d>
-__global__ __launch_bounds__(64) void k_qd_finalize(const c128 *gam, const int32_t *slots, c128 *gates,
-                                                    c128 *vstore, int32_t gstride, int32_t k) {
-  constexpr int D = d * d;
-  constexpr int PL = (D + 1) / 2 * 2;  // players of the round-robin schedule
-  constexpr int NP = PL / 2;
-  __shared__ c128 Gm[D * D];
-  __shared__ c128 Vs[D * D];
-  __shared__ c128 Tm[D * D];
-  __shared__ double sig[D];
-  __shared__ double part[4 * NP][D];  // per-row Gram contributions of a round's pairs
-  __shared__ double gram[4 * NP];
-  __shared__ double rot[NP][4];       // per pair: cos, sin, Re and Im of conj(gamma)/|gamma|
-  __shared__ int any_rot;
-  const int s = slots[blockIdx.x];
-  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
-  c128 *vst = vstore + (int64_t)s * gstride + (int64_t)k * D * D;
-  for (int e = threadIdx.x; e < D * D; e += 64) {
-    Tm[e] = gam[(int64_t)s * D * D + e];
-    Vs[e] = vst[e];
-  }
-  __syncthreads();
-  const int r = threadIdx.x;
-  const bool act = r < D;
-  auto wsync = [] {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  };
-  auto wsum = [](double x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-  };
-  // Newton-Schulz on V_prev (row r of V^dagger V into Gm), then V <- V (3I - V^dagger V)/2
-  if (act)
-    for (int j = 0; j < D; ++j) {
-      c128 acc = cmake(0.0, 0.0);
-      for (int kk = 0; kk < D; ++kk) cfma(acc, cconj(Vs[kk * D + r]), Vs[kk * D + j]);
-      Gm[r * D + j] = acc;
-    }
-  wsync();
-  c128 row[D];
-  if (act)
-    for (int j = 0; j < D; ++j) {
-      c128 acc = cmake(0.0, 0.0);
-      for (int kk = 0; kk < D; ++kk) {
-        const c128 t = Gm[kk * D + j];
-        cfma(acc, Vs[r * D + kk], cmake((kk == j ? 3.0 : 0.0) - t.re, -t.im));
-      }
-      row[j] = cscale(acc, 0.5);
-    }
-  wsync();
-  if (act)
-    for (int j = 0; j < D; ++j) Vs[r * D + j] = row[j];
-  wsync();
-  // G <- Gamma V (Gamma in Tm)
-  if (act)
-    for (int j = 0; j < D; ++j) {
-      c128 acc = cmake(0.0, 0.0);
-      for (int kk = 0; kk < D; ++kk) cfma(acc, Tm[r * D + kk], Vs[kk * D + j]);
-      Gm[r * D + j] = acc;
-    }
-  c128 *gr_ = Gm + (act ? r : 0) * D;
-  c128 *vr_ = Vs + (act ? r : 0) * D;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    int rotated = 0;
-    for (int rd = 0; rd < PL - 1; ++rd) {
-      int pp[NP], qq[NP];
-      // Gram entries of the round's pairs: each row's contributions to LDS, lane e
-      // (< 4 NP) sums entry e over the rows in row order, lane i (< NP) turns pair i's
-      // entries into its rotation, and every row applies the rotations of the round
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        pp[i] = i == 0 ? 0 : (rd + i) % (PL - 1) + 1;
-        qq[i] = i == 0 ? rd % (PL - 1) + 1 : (rd - i + PL - 1) % (PL - 1) + 1;
-        if (act && pp[i] < D && qq[i] < D) {
-          const c128 gp = gr_[pp[i]], gq = gr_[qq[i]];
-          part[4 * i][r] = cabs2(gp);
-          part[4 * i + 1][r] = cabs2(gq);
-          part[4 * i + 2][r] = gp.re * gq.re + gp.im * gq.im;
-          part[4 * i + 3][r] = gp.re * gq.im - gp.im * gq.re;
-        }
-      }
-      if (r == 0) any_rot = 0;
-      wsync();
-      if (r < 4 * NP) {
-        const int i = r >> 2;
-        const int pi = i == 0 ? 0 : (rd + i) % (PL - 1) + 1;
-        const int qi = i == 0 ? rd % (PL - 1) + 1 : (rd - i + PL - 1) % (PL - 1) + 1;
-        double t = 0.0;
-        if (pi < D && qi < D)
-          for (int rr = 0; rr < D; ++rr) t += part[r][rr];
-        gram[r] = t;
-      }
-      wsync();
-      if (r < NP) {
-        const double al = gram[4 * r], be = gram[4 * r + 1], gre = gram[4 * r + 2], gim = gram[4 * r + 3];
-        const double ag = sqrt(gre * gre + gim * gim);
-        const int pr = r == 0 ? 0 : (rd + r) % (PL - 1) + 1;
-        const int qr = r == 0 ? rd % (PL - 1) + 1 : (rd - r + PL - 1) % (PL - 1) + 1;
-        const bool pair_ok = pr < D && qr < D;
-        if (pair_ok && ag > 0.0 && ag > kQdJacobiTol * sqrt(al * be)) {
-          const double tau = (be - al) / (2.0 * ag);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
-          rot[r][0] = cs;
-          rot[r][1] = cs * t;
-          rot[r][2] = gre / ag;
-          rot[r][3] = -gim / ag;
-          any_rot = 1;
-        } else {
-          rot[r][0] = 1.0;
-          rot[r][1] = 0.0;
-          rot[r][2] = 1.0;
-          rot[r][3] = 0.0;
-        }
-      }
-      wsync();
-      if (any_rot) rotated = 1;
-      if (act) {
-#pragma unroll
-        for (int i = 0; i < NP; ++i) {
-          if (pp[i] >= D || qq[i] >= D) continue;
-          const double cs = rot[i][0], sn = rot[i][1];
-          if (sn == 0.0 && cs == 1.0) continue;
-          const c128 ec = cmake(rot[i][2], rot[i][3]);
-          const c128 gp = gr_[pp[i]], egq = ec * gr_[qq[i]];
-          const c128 vp = vr_[pp[i]], evq = ec * vr_[qq[i]];
-          gr_[pp[i]] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
-          gr_[qq[i]] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
-          vr_[pp[i]] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
-          vr_[qq[i]] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
-        }
-      }
-      wsync();
-    }
-    if (!rotated) break;
-  }
-  // singular values; W columns g / sigma; V stored back
-  double smax = 0.0, smin = INFINITY;
-  for (int c = 0; c < D; ++c) {
-    const double sc = sqrt(wsum(act ? cabs2(gr_[c]) : 0.0));
-    smax = fmax(smax, sc);
-    smin = fmin(smin, sc);
-    if (r == 0) sig[c] = sc;
-  }
-  if (act)
-    for (int c = 0; c < D; ++c) vst[r * D + c] = vr_[c];
-  wsync();
-  if (smin > 1e-200 && smin > 1e-13 * smax) {
-    if (act)
-      for (int c = 0; c < D; ++c) {
-        c128 acc = cmake(0.0, 0.0);
-        for (int kk = 0; kk < D; ++kk) cfma_conj(acc, cscale(gr_[kk], 1.0 / sig[kk]), Vs[c * D + kk]);
-        u[r * D + c] = acc;
-      }
-    return;
-  }
-  // a (near) singular environment: left vectors in decreasing-sigma order, orthonormalised
-  // in place in LDS (columns of Gm) and completed with unit vectors (any such completion
-  // attains the maximum); lane 0 alone
-  if (r != 0) return;
+// Per start: the environment Gamma_k as the fixed-order sum of its work-group partials
+// (partial i in running sum i mod 8), then u_k <- W V^dagger for the mixed
+// environment (1 - beta) Gamma_k + beta u_k = W S V^dagger by one-sided (Hestenes) Jacobi. The working
+// matrix G and V are kept by columns in LDS (rows padded to 16 with zeros; a zero ghost
+// column when D is odd). Pairs are rotated in round-robin rounds (circle method on the PL
+// columns): the pairs of a round are disjoint, and pair i of the round is worked by the
+// 16 lanes of row i of the block's waves (lane r holds row r of both columns of G and V),
+// which sum the pair's three Gram entries by DPP moves within their row, so each lane
+// computes the same rotation and applies it to its own row. Zero rows and ghost columns
+// contribute nothing and never rotate. Warm start: Jacobi begins from G V_prev with
+// V_prev, the right singular vectors this gate had after its previous update (vst, made
+// unitary to rounding by one Newton-Schulz step V (3I - V^dagger V) / 2), so a sweep of
+// small changes converges in a few Jacobi sweeps; the new V is stored back.
+// u for a (near) singular environment: left vectors in decreasing-sigma order,
+// orthonormalised in place in LDS (W column kk in Tm[. * D + kk]) and completed with unit
+// vectors (any such completion attains the maximum); one thread.
+template <int D, int PL>
+__device__ __noinline__ void qd_polar_singular(const c128 (*Gc)[16], const c128 (*Vc)[16], c128 *Tm,
+                                               const double *sig, double smax, c128 *u) {
   int ord[D];
+#pragma unroll 1
   for (int c = 0; c < D; ++c) ord[c] = c;
+#pragma unroll 1
   for (int a = 0; a < D; ++a)
+#pragma unroll 1
     for (int b2 = a + 1; b2 < D; ++b2)
       if (sig[ord[b2]] > sig[ord[a]]) {
-        const int t = ord[a];
+        const int tmp = ord[a];
         ord[a] = ord[b2];
-        ord[b2] = t;
+        ord[b2] = tmp;
       }
-  // W column kk goes to Tm[. * D + kk]
+#pragma unroll 1
   for (int kk = 0; kk < D; ++kk) {
     const int cc = ord[kk];
     bool ok = sig[cc] > 0.0 && sig[cc] > 1e-13 * smax;
-    for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = ok ? cscale(Gm[rr * D + cc], 1.0 / sig[cc]) : cmake(0.0, 0.0);
+#pragma unroll 1
+    for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = ok ? cscale(Gc[cc][rr], 1.0 / sig[cc]) : cmake(0.0, 0.0);
+#pragma unroll 1
     for (int attempt = 0; attempt <= D; ++attempt) {
       if (attempt > 0) {  // complete with unit vector e = attempt - 1
         if (ok) break;
+#pragma unroll 1
         for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = cmake(rr == attempt - 1 ? 1.0 : 0.0, 0.0);
       }
+#pragma unroll 1
       for (int rep = 0; rep < 2; ++rep)
+#pragma unroll 1
         for (int o = 0; o < kk; ++o) {
           c128 dd = cmake(0.0, 0.0);
+#pragma unroll 1
           for (int rr = 0; rr < D; ++rr) cfma(dd, cconj(Tm[rr * D + o]), Tm[rr * D + kk]);
+#pragma unroll 1
           for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = Tm[rr * D + kk] - dd * Tm[rr * D + o];
         }
       double nn = 0.0;
+#pragma unroll 1
       for (int rr = 0; rr < D; ++rr) nn += cabs2(Tm[rr * D + kk]);
       nn = sqrt(nn);
       if (nn > 0.5) {
+#pragma unroll 1
         for (int rr = 0; rr < D; ++rr) Tm[rr * D + kk] = cscale(Tm[rr * D + kk], 1.0 / nn);
         ok = true;
         break;
@@ -454,12 +290,165 @@ __global__ __launch_bounds__(64) void k_qd_finalize(const c128 *gam, const int32
       ok = false;
     }
   }
+#pragma unroll 1
   for (int q = 0; q < D; ++q)
-    for (int p = 0; p < D; ++p) {
+#pragma unroll 1
+    for (int p2 = 0; p2 < D; ++p2) {
       c128 acc = cmake(0.0, 0.0);
-      for (int kk = 0; kk < D; ++kk) cfma_conj(acc, Tm[q * D + kk], Vs[p * D + ord[kk]]);
-      u[q * D + p] = acc;
+#pragma unroll 1
+      for (int kk = 0; kk < D; ++kk) cfma_conj(acc, Tm[q * D + kk], Vc[ord[kk]][p2]);
+      u[q * D + p2] = acc;
     }
+}
+
+constexpr int kQdFinBlock = 128;  // eight 16-lane rows: one column pair each (D <= 16)
+
+template <int d>
+__global__ __launch_bounds__(kQdFinBlock) void k_qd_finalize(const c128 *partials, int32_t P, double beta,
+                                                             const int32_t *slots, c128 *gates, c128 *vstore,
+                                                             int32_t gstride, int32_t k) {
+  constexpr int D = d * d;
+  constexpr int PL = (D + 1) / 2 * 2;  // players of the round-robin schedule
+  constexpr int NP = PL / 2;           // pairs per round
+  static_assert(D <= 16 && NP * 16 <= kQdFinBlock, "one 16-lane row per pair");
+  __shared__ c128 Gc[PL][16];  // G by columns: Gc[c][r] = G[r][c]
+  __shared__ c128 Vc[PL][16];  // V by columns
+  __shared__ c128 Tm[D * D];   // Gamma (row-major), then W in the singular case
+  __shared__ c128 Vs[D * D];   // V_prev (row-major)
+  __shared__ c128 Nm[D * D];   // V_prev^dagger V_prev
+  __shared__ double sig[D];
+  const int s = slots[blockIdx.x];
+  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  c128 *vst = vstore + (int64_t)s * gstride + (int64_t)k * D * D;
+  const int t = threadIdx.x;
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    // eight interleaved running sums, each batch of eight loads in flight together
+    const c128 *src = partials + (int64_t)s * P * D * D + e;
+    c128 acc[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[v] = cmake(0.0, 0.0);
+    int blk = 0;
+    for (; blk + 7 < P; blk += 8) {
+      c128 x[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) x[v] = src[(int64_t)(blk + v) * D * D];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) acc[v] = acc[v] + x[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 7; ++v)
+      if (blk + v < P) acc[v] = acc[v] + src[(int64_t)(blk + v) * D * D];
+    const c128 gm = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    Tm[e] = beta != 0.0 ? cmake((1.0 - beta) * gm.re + beta * u[e].re, (1.0 - beta) * gm.im + beta * u[e].im) : gm;
+    Vs[e] = vst[e];
+  }
+  for (int e = t; e < PL * 16; e += kQdFinBlock) {
+    Gc[e >> 4][e & 15] = cmake(0.0, 0.0);
+    Vc[e >> 4][e & 15] = cmake(0.0, 0.0);
+  }
+  __syncthreads();
+  // Newton-Schulz on V_prev: N = V^dagger V, then V <- V (3I - N) / 2 (into Vc by columns)
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    const int i = e / D, j = e % D;
+    c128 acc = cmake(0.0, 0.0);
+    for (int kk = 0; kk < D; ++kk) cfma(acc, cconj(Vs[kk * D + i]), Vs[kk * D + j]);
+    Nm[e] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    const int i = e / D, j = e % D;
+    c128 acc = cmake(0.0, 0.0);
+    for (int kk = 0; kk < D; ++kk) {
+      const c128 x = Nm[kk * D + j];
+      cfma(acc, Vs[i * D + kk], cmake((kk == j ? 3.0 : 0.0) - x.re, -x.im));
+    }
+    Vc[j][i] = cscale(acc, 0.5);
+  }
+  __syncthreads();
+  // G <- Gamma V
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    const int i = e / D, j = e % D;
+    c128 acc = cmake(0.0, 0.0);
+    for (int kk = 0; kk < D; ++kk) cfma(acc, Tm[i * D + kk], Vc[j][kk]);
+    Gc[j][i] = acc;
+  }
+  __syncthreads();
+  const int pi = t >> 4, r = t & 15;  // pair (row of 16 lanes) and matrix row of this lane
+  const bool worker = pi < NP;
+  // rotate when |Gram_pq| > tol sqrt(al be), compared squared
+  constexpr double kTol2 = kQdJacobiTol * kQdJacobiTol;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    int rotated = 0;
+#pragma unroll 1
+    for (int rd = 0; rd < PL - 1; ++rd) {
+      if (worker) {
+        const int p = pi == 0 ? 0 : (rd + pi) % (PL - 1) + 1;
+        const int q = pi == 0 ? rd % (PL - 1) + 1 : (rd - pi + PL - 1) % (PL - 1) + 1;
+        const c128 gp = Gc[p][r], gq = Gc[q][r], vp = Vc[p][r], vq = Vc[q][r];
+        double al = cabs2(gp), be = cabs2(gq);
+        double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) gq
+        double gi = gp.re * gq.im - gp.im * gq.re;
+        al += xor_lane<1>(al);
+        be += xor_lane<1>(be);
+        gr += xor_lane<1>(gr);
+        gi += xor_lane<1>(gi);
+        al += xor_lane<2>(al);
+        be += xor_lane<2>(be);
+        gr += xor_lane<2>(gr);
+        gi += xor_lane<2>(gi);
+        al += xor_lane<4>(al);
+        be += xor_lane<4>(be);
+        gr += xor_lane<4>(gr);
+        gi += xor_lane<4>(gi);
+        al += xor_lane<8>(al);
+        be += xor_lane<8>(be);
+        gr += xor_lane<8>(gr);
+        gi += xor_lane<8>(gi);
+        const double x2 = gr * gr + gi * gi, ab = al * be;
+        if (x2 > 0.0 && x2 > kTol2 * ab) {
+          rotated = 1;
+          const double rag = rsq_nr(x2);               // 1 / |Gram_pq|
+          const c128 ec = cmake(gr * rag, -gi * rag);  // conj(Gram_pq) / |Gram_pq|
+          const double tau = (be - al) * (0.5 * rag);
+          const double t1 = fma(tau, tau, 1.0);
+          const double tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + t1 * rsq_nr(t1));
+          const double cs = rsq_nr(fma(tt, tt, 1.0)), sn = cs * tt;
+          const c128 egq = ec * gq, evq = ec * vq;
+          Gc[p][r] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+          Gc[q][r] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+          Vc[p][r] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+          Vc[q][r] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+  // singular values (column norms of G), V stored back
+  if (t < D) {
+    double a = 0.0;
+    for (int rr = 0; rr < D; ++rr) a += cabs2(Gc[t][rr]);
+    sig[t] = sqrt(a);
+  }
+  for (int e = t; e < D * D; e += kQdFinBlock) vst[e] = Vc[e % D][e / D];
+  __syncthreads();
+  double smax = 0.0, smin = INFINITY;
+  for (int c = 0; c < D; ++c) {
+    smax = fmax(smax, sig[c]);
+    smin = fmin(smin, sig[c]);
+  }
+  if (smin > 1e-200 && smin > 1e-13 * smax) {
+    // u = W V^dagger with W = G diag(1 / sigma)
+    for (int e = t; e < D * D; e += kQdFinBlock) {
+      const int i = e / D, c = e % D;
+      c128 acc = cmake(0.0, 0.0);
+      for (int kk = 0; kk < D; ++kk) cfma_conj(acc, cscale(Gc[kk][i], 1.0 / sig[kk]), Vc[kk][c]);
+      u[e] = acc;
+    }
+    return;
+  }
+  // a (near) singular environment: thread 0 alone
+  if (t == 0) qd_polar_singular<D, PL>(Gc, Vc, Tm, sig, smax, u);
 }
 
 // count D x D identity matrices (the initial warm-start V).
@@ -557,7 +546,7 @@ struct QdSweeper {
   hipStream_t st = nullptr;
   int M = 0, Mv = 0;
   DevBuf psi, phi, psiv, phiv;  // working sets [N][M] in R (shared by the starts)
-  DevBuf blist, astate, vstate, partials, dpart, costs, slots, gam;
+  DevBuf blist, astate, vstate, partials, dpart, costs, slots;
   c128 *g64 = nullptr;  // [S][L][D][D]
   c128 *vst = nullptr;  // [S][L][D][D] Jacobi warm start
   double beta = 0.0;
@@ -580,7 +569,7 @@ struct QdSweeper {
   int64_t set() const { return N * M; }
 
   // (sl, ns, s: the starts a launch covers and its stream; the partial-sum block count
-  // P depends on the geometry only, and partials and gam are indexed by start, so
+  // P depends on the geometry only, and the partials are indexed by start, so
   // launches over disjoint start sets never share them)
   template <int dd>
   int apply_t(const cx<R> *src, int64_t ss, cx<R> *dst, int64_t ds, int k, bool dagger, int Mrows,
@@ -607,14 +596,10 @@ struct QdSweeper {
     const QdGeom g = qd_geom(dd, n, M, pairs[2 * k], pairs[2 * k + 1]);
     const int P = (int)std::max<int64_t>(1, std::min<int64_t>(kQdMaxP, (g.groups * M + kQdBlock - 1) / kQdBlock));
     hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * dd / qd_env_rows<dd>() * P, ns), dim3(kQdBlock), 0, s, a, as,
-                       b, bs, g, P,
-                       partials.as<c128>(), sl);
+                       b, bs, g, P, partials.as<c128>(), sl);
     QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_qd_envsum<dd>), dim3(ns), dim3(kQdBlock), 0, s, partials.as<c128>(), P, sl, beta, g64,
-                       L * dd * dd * dd * dd, k, gam.as<c128>());
-    QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(ns), dim3(64), 0, s, gam.as<c128>(), sl, g64, vst,
-                       L * dd * dd * dd * dd, k);
+    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(ns), dim3(kQdFinBlock), 0, s, partials.as<c128>(), P, beta, sl, g64,
+                       vst, L * dd * dd * dd * dd, k);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   }
@@ -646,7 +631,6 @@ struct QdSweeper {
       QFS_TRY(vstate.alloc(cb * N * Mv * S));
     }
     QFS_TRY(partials.alloc(sizeof(c128) * (size_t)S * kQdMaxP * kQdMaxDD));
-    QFS_TRY(gam.alloc(sizeof(c128) * (size_t)S * kQdMaxDD));
     QFS_TRY(dpart.alloc(sizeof(double) * (size_t)S * kQdMaxP * 4));
     if (!costs.ptr) QFS_TRY(costs.alloc(sizeof(double) * 3 * S));
     if (!slots.ptr) QFS_TRY(slots.alloc(sizeof(int32_t) * S));
