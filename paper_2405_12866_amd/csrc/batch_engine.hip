@@ -384,7 +384,7 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
     }
     // Size classes are launched concurrently on side streams (each with its own queue
     // segment, queue head and scratch region); a class whose work-group size is not
-    // known yet is first autotuned on the call's stream: its jobs are split in three
+    // known yet is first autotuned on the call's stream: its jobs are dealt to three
     // parts run with 64, 128 and 256 threads, one after the other.
     struct Launch {
       ClassKey key;
@@ -414,15 +414,18 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
         if (it != g_tune.end()) chosen = it->second;
       }
       if (!chosen && ids.size() >= 3 * 64) {
-        // autotune on the call's stream
+        // autotune on the call's stream: the class's jobs (longest first) dealt round robin
+        // to three parts of like size mix, run with 64, 128 and 256 threads one after the
+        // other; a part's rate is the work its jobs did in the launch (their own work
+        // counters, so jobs that stop early count what they ran) per millisecond
         const int cands[3] = {64, 128, 256};
-        double best_rate = -1.0;
-        int best_threads = 64;
+        std::vector<int32_t> part_ids[3];
+        for (size_t q = 0; q < ids.size(); ++q) part_ids[q % 3].push_back(ids[q]);
+        float part_ms[3] = {0.f, 0.f, 0.f};
         for (int part = 0; part < 3; ++part) {
-          const size_t lo = ids.size() * part / 3, hi = ids.size() * (part + 1) / 3;
-          const int nj = (int)(hi - lo);
+          const int nj = (int)part_ids[part].size();
           const int threads = cands[part];
-          QFS_HIP(hipMemcpyAsync(dqueue.ptr, ids.data() + lo, sizeof(int32_t) * nj, hipMemcpyHostToDevice, st));
+          QFS_HIP(hipMemcpyAsync(dqueue.ptr, part_ids[part].data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice, st));
           QFS_TRY(launch_zero(dhead.ptr, 16, st));
           const int grid = grid_for(lds, threads, nj);
           BatchArgs a;
@@ -439,21 +442,24 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
           QFS_TRY(launch_batch_sweep(a, key.fp64 != 0, threads, grid, lds, st));
           QFS_HIP(hipEventRecord(e1, st));
           QFS_HIP(hipEventSynchronize(e1));
-          float ms = 0.f;
-          QFS_HIP(hipEventElapsedTime(&ms, e0, e1));
-          kernel_seconds += 1e-3 * ms;
+          QFS_HIP(hipEventElapsedTime(&part_ms[part], e0, e1));
+          kernel_seconds += 1e-3 * part_ms[part];
           if (batch_trace())
             std::fprintf(stderr, "qfs batch: tune fp64=%d state_bytes<=%zu threads=%d jobs=%d grid=%d %.3f ms\n",
-                         key.fp64, key.bucket, threads, nj, grid, ms);
+                         key.fp64, key.bucket, threads, nj, grid, part_ms[part]);
+        }
+        std::vector<BJob> after(njobs_all);
+        QFS_HIP(hipMemcpyAsync(after.data(), djobs.ptr, sizeof(BJob) * njobs_all, hipMemcpyDeviceToHost, st));
+        QFS_HIP(hipStreamSynchronize(st));
+        double best_rate = -1.0;
+        int best_threads = 64;
+        for (int part = 0; part < 3; ++part) {
           double work = 0.0;
-          for (size_t q = lo; q < hi; ++q) {
-            const BProb &d = hp[jobs[ids[q]].prob];
-            work += (double)d.L * ((double)d.M + d.Mv) * (1 << d.n);
-          }
-          const double rate = work / std::max(1e-9, (double)ms);
+          for (int32_t j : part_ids[part]) work += after[j].work - jobs[j].work;
+          const double rate = work / std::max(1e-6, (double)part_ms[part]);
           if (rate > best_rate) {
             best_rate = rate;
-            best_threads = threads;
+            best_threads = cands[part];
           }
         }
         std::lock_guard<std::mutex> lk(g_tune_mu);
