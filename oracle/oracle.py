@@ -153,16 +153,19 @@ def load():
         lib.qd_svd.argtypes = [C.c_int, P, P, P, P]
         lib.qd_update_gate.argtypes = [C.c_int, P, C.c_double, P]
         lib.qd_haar_gate.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, P]
-        lib.qd_sweep.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_int, P, P, P, C.c_double,
+        lib.qd_sweep.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P, P, P, C.c_double,
                                  C.c_double, P, P]
         lib.qd_sweep.restype = C.c_double
-        lib.qd_instantiate.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_int, C.c_int,
+        lib.qd_instantiate.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, C.c_int, C.c_int,
                                        C.POINTER(Params), P, P, C.POINTER(Result), C.POINTER(Trace)]
         lib.qd_instantiate.restype = C.c_int
         lib.qd_draw_states.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, C.c_uint32,
                                        P]
         lib.qd_draw_states.restype = C.c_int
-        lib.qd_instantiate_target.argtypes = [C.c_int, C.c_int, C.c_int, P, C.c_int, P, C.c_int, P, P,
+        lib.qd_environment1.argtypes = [C.c_int, C.c_int, C.c_int, P, P, C.c_int, P]
+        lib.qd_update_gate1.argtypes = [C.c_int, P, C.c_double, P]
+        lib.qd_haar_gate1.argtypes = [C.c_int, C.c_uint64, C.c_uint32, C.c_uint32, P]
+        lib.qd_instantiate_target.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_int, P, C.c_int, P, P,
                                               C.POINTER(Params), P, P, C.POINTER(Result),
                                               C.POINTER(Trace)]
         lib.qd_instantiate_target.restype = C.c_int
@@ -482,29 +485,53 @@ def qd_haar_gate(d, seed, start, gate):
     return u
 
 
-def qd_sweep(d, n, pairs, psi, phi, gates, beta=0.0, gamma_scale=1.0, record=False):
+def qd_sweep(d, n, pairs, psi, phi, gates, beta=0.0, gamma_scale=1.0, record=False, kinds=None):
     pr = _pairs(pairs)
     L = pr.shape[0]
+    kd = _kinds(kinds, L)
     g = _c128(gates).copy()
     ps, ph = _c128(psi), _c128(phi)
     fb = np.zeros(L) if record else None
     fa = np.zeros(L) if record else None
-    c = load().qd_sweep(d, n, L, _p(pr), ps.shape[0], _p(ps), _p(ph), _p(g), beta, gamma_scale,
+    c = load().qd_sweep(d, n, L, _p(pr), _p(kd), ps.shape[0], _p(ps), _p(ph), _p(g), beta, gamma_scale,
                         _p(fb), _p(fa))
     return (g, c, fb, fa) if record else (g, c)
 
 
-def qd_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None):
-    """Qudit instantiation on a fixed sample set (the last n_val rows validate)."""
+def qd_environment1(d, n, a, b, qa):
+    aa, bb = _c128(a), _c128(b)
+    G = np.zeros((d, d), dtype=np.complex128)
+    load().qd_environment1(d, n, aa.shape[0], _p(aa), _p(bb), qa, _p(G))
+    return G
+
+
+def qd_update_gate1(d, G1, beta=0.0, u=None):
+    """v <- polar((1 - beta) G1 + beta v) on the slot u = v (x) I_d (identity slot if None)."""
+    uu = np.eye(d * d, dtype=np.complex128) if u is None else _c128(u).copy()
+    load().qd_update_gate1(d, _p(_c128(G1)), beta, _p(uu))
+    return uu
+
+
+def qd_haar_gate1(d, seed, start, gate):
+    u = np.zeros((d * d, d * d), dtype=np.complex128)
+    load().qd_haar_gate1(d, seed, start, gate, _p(u))
+    return u
+
+
+def qd_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None, kinds=None, fixed=None):
+    """Qudit instantiation on a fixed sample set (the last n_val rows validate); kinds and
+    fixed ([L][d^2][d^2], read for constant gates) as for ``instantiate``."""
     pr = _pairs(pairs)
     L = pr.shape[0]
+    kd = _kinds(kinds, L)
+    fx = None if fixed is None else _c128(fixed)
     par = Params(**(params or default_params()))
     ps, ph = _c128(psi), _c128(phi)
     gi = None if gates_in is None else _c128(gates_in)
     out = np.zeros((L, d * d, d * d), dtype=np.complex128)
     res = Result()
-    rc = load().qd_instantiate(d, n, L, _p(pr), _p(ps), _p(ph), ps.shape[0], n_val, C.byref(par),
-                               _p(gi), _p(out), C.byref(res), None)
+    rc = load().qd_instantiate(d, n, L, _p(pr), _p(kd), _p(fx), _p(ps), _p(ph), ps.shape[0], n_val,
+                               C.byref(par), _p(gi), _p(out), C.byref(res), None)
     if rc != 0:
         raise ValueError(f"qd_instantiate failed: {rc}")
     info = {f: getattr(res, f) for f, _ in Result._fields_}
@@ -522,7 +549,8 @@ def qd_draw_states(d, n, M, seed, role, stream):
 
 
 def qd_instantiate_target(d, n, pairs, *, U=None, target_pairs=None, target_gates=None,
-                          params=None, gates_in=None, trace_capacity=0, doubling_capacity=0):
+                          params=None, gates_in=None, trace_capacity=0, doubling_capacity=0,
+                          kinds=None, fixed=None):
     """Qudit instantiation against a dense target ``U`` ([d^n][d^n]) or a target circuit
     (``target_pairs`` + ``target_gates`` [Lt][d^2][d^2]), with drawn training and validation
     states. Returns (gates, result dict), with the trace as in ``instantiate``."""
@@ -549,8 +577,10 @@ def qd_instantiate_target(d, n, pairs, *, U=None, target_pairs=None, target_gate
     if trace_capacity or doubling_capacity:
         tr, bufs, dbl = _make_trace(max(trace_capacity, 1), doubling_capacity, par.multistarts
                                     if par.multistarts > 0 else 1, L, D * D, d ** n)
-    rc = lib.qd_instantiate_target(d, n, L, _p(pr), kind, *args, C.byref(par), _p(gi), _p(out),
-                                   C.byref(res), C.byref(tr) if tr is not None else None)
+    kd = _kinds(kinds, L)
+    fx = None if fixed is None else _c128(fixed)
+    rc = lib.qd_instantiate_target(d, n, L, _p(pr), _p(kd), _p(fx), kind, *args, C.byref(par), _p(gi),
+                                   _p(out), C.byref(res), C.byref(tr) if tr is not None else None)
     if rc != 0:
         raise ValueError(f"qd_instantiate_target failed: {rc}")
     info = {f: getattr(res, f) for f, _ in Result._fields_}
@@ -567,7 +597,7 @@ __all__ = [
     "apply_gate", "apply_circuit", "dense_apply", "environment", "environment1", "svd4",
     "update_gate", "update_gate1", "qd_apply_gate", "qd_apply_circuit", "qd_environment",
     "qd_svd", "qd_update_gate", "qd_haar_gate", "qd_sweep", "qd_instantiate",
-    "qd_draw_states", "qd_instantiate_target",
+    "qd_draw_states", "qd_instantiate_target", "qd_environment1", "qd_update_gate1", "qd_haar_gate1",
     "state_distance", "sweep", "instantiate", "EV_RUN", "EV_SUCCESS", "EV_OVERTRAINED",
     "EV_NOT_GEN", "EV_PLATEAU", "EV_MAX_ITER",
 ]

@@ -694,16 +694,63 @@ void qd_haar_gate(int d, uint64_t seed, uint32_t start, uint32_t gate, qo_cplx *
     for (int p = 0; p < D; ++p) u[q * D + p] = cols[p * D + q];
 }
 
+/* Environment of a one-qudit gate on qudit qa: the sum over every sample j and every
+ * index r of the other n-1 qudits of a_j(x, r) conj(b_j(y, r)), d x d. */
+void qd_environment1(int d, int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, qo_cplx *G) {
+  const int64_t N = qd_pow(d, n), sa = qd_pow(d, n - 1 - qa);
+  for (int e = 0; e < d * d; ++e) G[e] = 0.0;
+  for (int64_t j = 0; j < M; ++j)
+    for (int64_t i = 0; i < N; ++i) {
+      if ((i / sa) % d != 0) continue;
+      for (int x = 0; x < d; ++x)
+        for (int y = 0; y < d; ++y) G[x * d + y] += a[j * N + i + x * sa] * conj(b[j * N + i + y * sa]);
+    }
+}
+
+/* v (x) I_d in the local basis d digit(qa) + digit(qb): entry (d x + z, d y + w) is v[x][y]
+ * when z = w, else 0. */
+static void qd_kron_id(int d, const qo_cplx *v, qo_cplx *u) {
+  const int D = d * d;
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) u[r * D + c] = (r % d == c % d) ? v[(r / d) * d + c / d] : 0.0;
+}
+
+/* Update of a one-qudit gate held as the slot v (x) I_d: v <- polar((1 - beta) G1 + beta v)
+ * with the d x d environment G1 (the two-qudit rule on the gate's own d levels); the slot
+ * keeps its form. */
+void qd_update_gate1(int d, const qo_cplx *G1, double beta, qo_cplx *u) {
+  const int D = d * d;
+  qo_cplx v[16];
+  for (int x = 0; x < d; ++x)
+    for (int y = 0; y < d; ++y) v[x * d + y] = u[(d * x) * D + d * y];
+  qd_update_gate(d, G1, beta, v);
+  qd_kron_id(d, v, u);
+}
+
+/* Initial one-qudit gate: Haar on U(d) from the d x d Ginibre block at indices
+ * 256 gate + d col + row of the start's initial-gate stream, as the slot v (x) I_d. */
+void qd_haar_gate1(int d, uint64_t seed, uint32_t start, uint32_t gate, qo_cplx *u) {
+  qo_cplx cols[16], v[16];
+  for (int j = 0; j < d; ++j)
+    for (int i = 0; i < d; ++i)
+      cols[j * d + i] = qo_cgauss(seed, QO_ROLE_INIT, start, (uint64_t)gate * 256u + (uint64_t)(j * d + i));
+  qo_gram_schmidt_columns(d, 0, d, cols);
+  for (int q = 0; q < d; ++q)
+    for (int p = 0; p < d; ++p) v[q * d + p] = cols[p * d + q];
+  qd_kron_id(d, v, u);
+}
+
 static double qd_re_tr(int D, const qo_cplx *G, const qo_cplx *u) {
   double acc = 0.0;
   for (int e = 0; e < D * D; ++e) acc += creal(conj(G[e]) * u[e]);
   return acc;
 }
 
-/* One sweep on qudits (the qubit sweep with D x D gates). */
-double qd_sweep(int d, int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
-                const qo_cplx *phi, qo_cplx *gates, double beta, double gamma_scale,
-                double *f_before, double *f_after) {
+/* One sweep on qudits (the qubit sweep with D x D gates): a constant gate is applied in
+ * both passes and never updated; a one-qudit gate is updated from its d x d environment. */
+double qd_sweep(int d, int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
+                const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
+                double gamma_scale, double *f_before, double *f_after) {
   const int D = d * d, GS = D * D;
   const int64_t S = (int64_t)M * qd_pow(d, n);
   qo_cplx *B = (qo_cplx *)malloc(sizeof(qo_cplx) * S * (size_t)L);
@@ -717,11 +764,27 @@ double qd_sweep(int d, int n, int L, const int32_t *pairs, int M, const qo_cplx 
   }
   memcpy(a, phi, sizeof(qo_cplx) * S);
   for (int k = L - 1; k >= 0; --k) {
-    qd_environment(d, n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
-    if (f_before) f_before[k] = qd_re_tr(D, G, gates + GS * k);
-    for (int e = 0; e < GS; ++e) Gs[e] = gamma_scale * G[e];
-    qd_update_gate(D, Gs, beta, gates + GS * k);
-    if (f_after) f_after[k] = qd_re_tr(D, G, gates + GS * k);
+    const int kind = kinds ? kinds[k] : QO_GATE_2Q;
+    if (kind == QO_GATE_2Q) {
+      qd_environment(d, n, M, a, B + (size_t)k * S, pairs[2 * k], pairs[2 * k + 1], G);
+      if (f_before) f_before[k] = qd_re_tr(D, G, gates + GS * k);
+      for (int e = 0; e < GS; ++e) Gs[e] = gamma_scale * G[e];
+      qd_update_gate(D, Gs, beta, gates + GS * k);
+      if (f_after) f_after[k] = qd_re_tr(D, G, gates + GS * k);
+    } else if (kind == QO_GATE_1Q) {
+      qd_environment1(d, n, M, a, B + (size_t)k * S, pairs[2 * k], G);
+      qo_cplx Gk[256];
+      for (int e = 0; e < GS; ++e) Gk[e] = 0.0;
+      for (int x = 0; x < d; ++x)
+        for (int y = 0; y < d; ++y) Gk[(d * x) * D + d * y] = G[x * d + y];
+      if (f_before) f_before[k] = qd_re_tr(D, Gk, gates + GS * k);
+      for (int e = 0; e < d * d; ++e) Gs[e] = gamma_scale * G[e];
+      qd_update_gate1(d, Gs, beta, gates + GS * k);
+      if (f_after) f_after[k] = qd_re_tr(D, Gk, gates + GS * k);
+    } else {
+      if (f_before) f_before[k] = NAN;
+      if (f_after) f_after[k] = NAN;
+    }
     qd_apply_gate(d, n, M, a, pairs[2 * k], pairs[2 * k + 1], gates + GS * k, 1);
   }
   double c = 0.0;
@@ -839,7 +902,6 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
                    qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
   const double t0 = qo_now();
   if (n < 2 || n > 24 || L < 1 || !p || !gates_out || !res) return -1;
-  if (d != 2 && kinds) return -1;
   const int GS = d * d * d * d; /* entries of one gate */
   for (int k = 0; k < L; ++k) {
     int a = pairs[2 * k], b = pairs[2 * k + 1];
@@ -896,9 +958,11 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
       const int kind = kinds ? kinds[k] : QO_GATE_2Q;
       qo_cplx *u = gates + GS * ((size_t)s * L + k);
       if (kind == QO_GATE_FIXED)
-        memcpy(u, fixed + 16 * (size_t)k, sizeof(qo_cplx) * 16);
+        memcpy(u, fixed + GS * (size_t)k, sizeof(qo_cplx) * GS);
       else if (gates_in)
         memcpy(u, gates_in + GS * ((size_t)s * L + k), sizeof(qo_cplx) * GS);
+      else if (d != 2 && kind == QO_GATE_1Q)
+        qd_haar_gate1(d, p->seed, (uint32_t)s, (uint32_t)k, u);
       else if (d != 2)
         qd_haar_gate(d, p->seed, (uint32_t)s, (uint32_t)k, u);
       else
@@ -935,7 +999,7 @@ static int instantiate_impl(int d, int n, int L, const int32_t *pairs, const int
         c_tr[s] = qo_sweep(n, L, pairs, kinds, M, psi, phi, g, p->beta,
                            p->beta_normalized ? 1.0 / (double)M : 1.0, NULL, NULL, NULL);
       else
-        c_tr[s] = qd_sweep(d, n, L, pairs, M, psi, phi, g, p->beta,
+        c_tr[s] = qd_sweep(d, n, L, pairs, kinds, M, psi, phi, g, p->beta,
                            p->beta_normalized ? 1.0 / (double)M : 1.0, NULL, NULL);
       c_v[s] = Mv > 0 ? FWD_COST(Mv, psiv, phiv, g) : c_tr[s];
     }
@@ -1087,10 +1151,11 @@ int qo_instantiate(int n, int L, const int32_t *pairs, const int32_t *kinds, con
                           trace);
 }
 
-int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, int target_kind,
-                          const qo_cplx *U, int Lt, const int32_t *tpairs, const qo_cplx *tgates,
-                          const qo_params *p, const qo_cplx *gates_in, qo_cplx *gates_out,
-                          qo_result *res, qo_trace *trace) {
+int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, const int32_t *kinds,
+                          const qo_cplx *fixed, int target_kind, const qo_cplx *U, int Lt,
+                          const int32_t *tpairs, const qo_cplx *tgates, const qo_params *p,
+                          const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res,
+                          qo_trace *trace) {
   if (d < 2 || d > 4 || (target_kind != QO_TARGET_DENSE && target_kind != QO_TARGET_CIRCUIT)) return -1;
   if (target_kind == QO_TARGET_DENSE && !U) return -1;
   if (target_kind == QO_TARGET_CIRCUIT) {
@@ -1100,15 +1165,16 @@ int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, int target_
       if (a < 0 || b < 0 || a >= n || b >= n || a == b) return -1;
     }
   }
-  return instantiate_impl(d, n, L, pairs, NULL, NULL, target_kind, U, Lt, tpairs, tgates, NULL, NULL,
+  return instantiate_impl(d, n, L, pairs, kinds, fixed, target_kind, U, Lt, tpairs, tgates, NULL, NULL,
                           0, 0, p, gates_in, gates_out, res, trace);
 }
 
-int qd_instantiate(int d, int n, int L, const int32_t *pairs, const qo_cplx *samples_psi,
-                   const qo_cplx *samples_phi, int n_samples, int n_val, const qo_params *p,
-                   const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
+int qd_instantiate(int d, int n, int L, const int32_t *pairs, const int32_t *kinds,
+                   const qo_cplx *fixed, const qo_cplx *samples_psi, const qo_cplx *samples_phi,
+                   int n_samples, int n_val, const qo_params *p, const qo_cplx *gates_in,
+                   qo_cplx *gates_out, qo_result *res, qo_trace *trace) {
   if (d < 2 || d > 4) return -1;
-  return instantiate_impl(d, n, L, pairs, NULL, NULL, QO_TARGET_SAMPLES, NULL, 0, NULL, NULL,
+  return instantiate_impl(d, n, L, pairs, kinds, fixed, QO_TARGET_SAMPLES, NULL, 0, NULL, NULL,
                           samples_psi, samples_phi, n_samples, n_val, p, gates_in, gates_out, res,
                           trace);
 }

@@ -184,14 +184,25 @@ void qd_svd(int D, const qo_cplx *G, qo_cplx *W, double *s, qo_cplx *V);
 void qd_update_gate(int D, const qo_cplx *G, double beta, qo_cplx *u);
 /* Haar D x D initial gate from indices 256 gate + D col + row of the start's stream. */
 void qd_haar_gate(int d, uint64_t seed, uint32_t start, uint32_t gate, qo_cplx *u);
-double qd_sweep(int d, int n, int L, const int32_t *pairs, int M, const qo_cplx *psi,
-                const qo_cplx *phi, qo_cplx *gates, double beta, double gamma_scale,
-                double *f_before, double *f_after);
+/* Gate kinds on qudits (the qubit kinds with d levels): a one-qudit gate v on qa with qb a
+ * spectator is held as the D x D slot v (x) I_d (entry (d x + z, d y + w) = v[x][y] when
+ * z = w), updated from its d x d environment; a constant gate is applied, never updated.
+ * qd_environment1: G[x][y] = sum_j sum_r a_j(x, r) conj(b_j(y, r)) over the other n-1
+ * qudits. qd_haar_gate1: Haar on U(d) from the d x d Ginibre block at indices
+ * 256 gate + d col + row of the start's stream, as a slot. */
+void qd_environment1(int d, int n, int M, const qo_cplx *a, const qo_cplx *b, int qa, qo_cplx *G);
+void qd_update_gate1(int d, const qo_cplx *G1, double beta, qo_cplx *u);
+void qd_haar_gate1(int d, uint64_t seed, uint32_t start, uint32_t gate, qo_cplx *u);
+/* kinds: [L] or NULL (all QO_GATE_2Q); f_before/f_after as for qo_sweep. */
+double qd_sweep(int d, int n, int L, const int32_t *pairs, const int32_t *kinds, int M,
+                const qo_cplx *psi, const qo_cplx *phi, qo_cplx *gates, double beta,
+                double gamma_scale, double *f_before, double *f_after);
 /* Instantiation on a fixed sample set (rows 0 .. n_samples - n_val - 1 train, the last
  * n_val validate), the same control loop as qo_instantiate. */
-int qd_instantiate(int d, int n, int L, const int32_t *pairs, const qo_cplx *samples_psi,
-                   const qo_cplx *samples_phi, int n_samples, int n_val, const qo_params *p,
-                   const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res, qo_trace *trace);
+int qd_instantiate(int d, int n, int L, const int32_t *pairs, const int32_t *kinds,
+                   const qo_cplx *fixed, const qo_cplx *samples_psi, const qo_cplx *samples_phi,
+                   int n_samples, int n_val, const qo_params *p, const qo_cplx *gates_in,
+                   qo_cplx *gates_out, qo_result *res, qo_trace *trace);
 
 /* M orthonormal Haar states on N = d^n amplitudes, drawn as qo_draw_states draws them for
  * N = 2^n (column j of the Ginibre matrix from Philox index j N + i, orthonormalised in
@@ -201,11 +212,13 @@ int qd_draw_states(int d, int n, int M, uint64_t seed, uint32_t role, uint32_t s
 /* Instantiation against a dense target U ([N][N] row-major) or a target circuit
  * of Lt two-qudit gates (tpairs [Lt][2], tgates [Lt][D][D]) with states drawn as in
  * qo_instantiate (N = d^n amplitudes, the same Philox roles, streams and indices),
- * the same control loop. */
-int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, int target_kind,
-                          const qo_cplx *U, int Lt, const int32_t *tpairs, const qo_cplx *tgates,
-                          const qo_params *p, const qo_cplx *gates_in, qo_cplx *gates_out,
-                          qo_result *res, qo_trace *trace);
+ * the same control loop. kinds and fixed ([L][D][D], read for QO_GATE_FIXED) as for
+ * qo_instantiate. */
+int qd_instantiate_target(int d, int n, int L, const int32_t *pairs, const int32_t *kinds,
+                          const qo_cplx *fixed, int target_kind, const qo_cplx *U, int Lt,
+                          const int32_t *tpairs, const qo_cplx *tgates, const qo_params *p,
+                          const qo_cplx *gates_in, qo_cplx *gates_out, qo_result *res,
+                          qo_trace *trace);
 
 /* Full instantiation with the paper's control loop. kinds: [L] or NULL; fixed: [L][16]
  * constant gates (read for QO_GATE_FIXED; replace those slots of gates_in too). */

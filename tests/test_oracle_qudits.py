@@ -258,3 +258,114 @@ def test_qudit_reachable_target_recovered_from_drawn_states(d, n, pairs):
     assert info["reason_name"] == "SUCCESS", info
     C = D.circuit_matrix_d(d, n, pairs, gates)
     assert np.linalg.norm(U - C) ** 2 / d ** n < 1e-8
+
+
+# ------------------------------------------------------------------ qudit gate kinds
+def _csum(d):
+    """Constant two-qudit gate |x, y> -> |x, y + x mod d> (local index d x + y)."""
+    D = d * d
+    U = np.zeros((D, D), dtype=np.complex128)
+    for x in range(d):
+        for y in range(d):
+            U[d * x + (y + x) % d, d * x + y] = 1.0
+    return U
+
+
+def _kind_slots(d, kinds, g):
+    D = d * d
+    out = []
+    for k in kinds:
+        if k == O.GATE_1Q:
+            out.append(np.kron(I.haar_unitary(d, g), np.eye(d)))
+        elif k == O.GATE_FIXED:
+            out.append(_csum(d))
+        else:
+            out.append(I.haar_unitary(D, g))
+    return np.stack(out)
+
+
+def test_d2_kinds_sweep_is_the_qubit_kinds_sweep():
+    n = 4
+    g = np.random.default_rng(31)
+    pairs = [(0, 1), (1, 2), (2, 3), (3, 0), (1, 3), (2, 0)]
+    kinds = [O.GATE_1Q, O.GATE_FIXED, O.GATE_2Q, O.GATE_1Q, O.GATE_2Q, O.GATE_FIXED]
+    gates = _kind_slots(2, kinds, g)
+    psi = I.orthonormal_samples(n, 5, g)
+    phi = O.apply_circuit(n, psi, pairs, I.haar_gates(6, g))
+    x, cx = O.qd_sweep(2, n, pairs, psi, phi, gates, kinds=kinds)
+    y, cy = O.sweep(n, pairs, psi, phi, gates, kinds=kinds)
+    assert np.allclose(x, y, atol=1e-12) and abs(cx - cy) < 1e-13
+
+
+@pytest.mark.parametrize("qa,qb", [(0, 1), (1, 2), (2, 0)])
+def test_qutrit_one_qudit_update_is_polar_of_its_contraction(qa, qb):
+    """L = 1, one one-qutrit gate on qa (spectator qb): its environment is the contraction
+    of phi against psi over every digit but qa (numpy), and the sweep sets the slot to
+    polar(G1) (x) I_3 (SciPy), whatever the spectator."""
+    n, M = 3, 4
+    g = np.random.default_rng(40 + qa)
+    psi, phi = _samples(3, n, M, g), _rand_c(g, M, 27)
+    a = phi.reshape((M,) + (3,) * n)
+    b = psi.reshape((M,) + (3,) * n)
+    G1 = np.tensordot(np.moveaxis(a, 1 + qa, 1), np.moveaxis(b, 1 + qa, 1).conj(),
+                      axes=([0] + list(range(2, n + 1)), [0] + list(range(2, n + 1))))
+    assert np.allclose(O.qd_environment1(3, n, phi, psi, qa), G1, atol=1e-12)
+    slot = np.kron(I.haar_unitary(3, g), np.eye(3))
+    new, _ = O.qd_sweep(3, n, [(qa, qb)], psi, phi, slot[None], kinds=[O.GATE_1Q])
+    v = scipy.linalg.polar(G1, side="right")[0]
+    assert np.allclose(new[0], np.kron(v, np.eye(3)), atol=1e-12)
+
+
+def test_qutrit_kinds_sweep_keeps_forms_and_descends():
+    """Constant gates stay as given, one-qudit slots keep the form v (x) I_3 with v unitary,
+    and the Eq. 9 cost never rises over the sweeps."""
+    n, M = 4, 6
+    g = np.random.default_rng(32)
+    pairs = [(0, 1), (1, 2), (2, 3), (3, 1), (0, 2), (2, 1), (1, 0)]
+    kinds = [O.GATE_1Q, O.GATE_FIXED, O.GATE_2Q, O.GATE_1Q, O.GATE_FIXED, O.GATE_1Q, O.GATE_2Q]
+    gates = _kind_slots(3, kinds, g)
+    psi = _samples(3, n, M, g)
+    phi = O.qd_apply_circuit(3, n, psi, pairs, _kind_slots(3, kinds, g))
+    c_prev = np.inf
+    for _ in range(6):
+        gates, c = O.qd_sweep(3, n, pairs, psi, phi, gates, kinds=kinds)
+        assert c <= c_prev + 1e-12
+        c_prev = c
+        for k, kind in enumerate(kinds):
+            if kind == O.GATE_FIXED:
+                assert np.array_equal(gates[k], _csum(3))
+            elif kind == O.GATE_1Q:
+                v = gates[k][::3, ::3]
+                assert np.allclose(gates[k], np.kron(v, np.eye(3)), atol=1e-14)
+                assert np.allclose(v.conj().T @ v, np.eye(3), atol=1e-12)
+
+
+def test_qd_haar_gate1_is_a_unitary_slot():
+    for s in range(3):
+        for k in range(5):
+            u = O.qd_haar_gate1(3, 9, s, k)
+            v = u[::3, ::3]
+            assert np.allclose(u, np.kron(v, np.eye(3)), atol=0)
+            assert np.allclose(v.conj().T @ v, np.eye(3), atol=1e-13)
+
+
+def test_qutrit_kinds_target_recovered():
+    """3 qutrits: one-qutrit gates around constant CSUM gates; a target from the same
+    template with other one-qutrit gates is recovered from drawn states (SUCCESS, full
+    distance from Kronecker products)."""
+    n = 3
+    pairs = [(0, 1), (1, 2), (0, 1), (1, 0), (2, 1), (0, 1), (1, 2)]
+    kinds = [O.GATE_1Q, O.GATE_1Q, O.GATE_FIXED, O.GATE_1Q, O.GATE_1Q, O.GATE_FIXED, O.GATE_1Q]
+    g = np.random.default_rng(33)
+    tg = _kind_slots(3, kinds, g)
+    fixed = np.stack([_csum(3)] * len(pairs))
+    U = D.circuit_matrix_d(3, n, pairs, tg)
+    p = O.default_params(multistarts=8, m_init=3, seed=5, dist_tol=1e-11, max_iter=2000)
+    gates, info = O.qd_instantiate_target(3, n, pairs, target_pairs=pairs, target_gates=tg, params=p,
+                                          kinds=kinds, fixed=fixed)
+    assert info["reason_name"] == "SUCCESS", info
+    for k, kind in enumerate(kinds):
+        if kind == O.GATE_FIXED:
+            assert np.array_equal(gates[k], _csum(3))
+    C = D.circuit_matrix_d(3, n, pairs, gates)
+    assert np.linalg.norm(U - C) ** 2 / 27 < 1e-8
