@@ -369,8 +369,14 @@ int qfs_instantiate_samples(const qfs_template *tmpl, const qfs_c128 *psi,
  * d-level gates; a sweep costs O(M d^n) where QFactor's costs O(d^{2n})). Qudit 0 is the
  * most significant base-d digit of the amplitude index (N = d^n); tmpl->n_qubits is the
  * qudit count, tmpl->pairs the ordered qudit pairs; a gate is a D x D unitary, D = d^2,
- * row-major u[q][p] with local index d digit(a) + digit(b). d = 2, 3 or 4; d^n <= 2^24;
- * tmpl->kinds must be NULL (QFS_EUNSUPPORTED otherwise).
+ * row-major u[q][p] with local index d digit(a) + digit(b). d = 2, 3 or 4; d^n <= 2^24.
+ * Gate kinds as for qubits (tmpl->kinds, NULL: every gate QFS_GATE_2Q): a QFS_GATE_1Q gate
+ * v on qudit a (b a spectator) is held as the slot v (x) I_d (entry (d x + z, d y + w) is
+ * v[x][y] when z = w) and updated to polar((1 - beta) G1 + beta v) of its d x d
+ * environment G1[x][y] = sum_z Gamma[d x + z][d y + z]; a QFS_GATE_FIXED gate takes
+ * tmpl->fixed_gates (device [L][D][D], read for those entries; they replace the same slots
+ * of gates_in) and is never updated. Drawn one-qudit gates are Haar on U(d) from the d x d
+ * Ginibre block at indices 256 gate + d col + row of the start's stream.
  *
  * Instantiation on a fixed sample set with the paper's control loop (Sec. 3, App. A), the
  * SAMPLES semantics of qfs_instantiate: psi, phi device [n_samples][N] (phi = U psi);
@@ -403,11 +409,13 @@ int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_
                                  qfs_c128 *gates_out, qfs_result *res);
 
 /* One qudit sweep for `starts` starts sharing a training set, as qfs_sweep: psi, phi
- * device [M][N]; gates device [starts][L][D][D] updated in place; c_train host [starts]
- * (Eq. 9 cost of the updated gates). */
-int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32_t M,
-                    const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates,
-                    int32_t precision, double beta, double *c_train, void *hip_stream);
+ * device [M][N]; kinds host [L] or NULL (constant gates are the gates' own slots, applied
+ * and kept); gates device [starts][L][D][D] updated in place; c_train host [starts] (Eq. 9
+ * cost of the updated gates). */
+int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds,
+                    int32_t M, const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts,
+                    qfs_c128 *gates, int32_t precision, double beta, double *c_train,
+                    void *hip_stream);
 
 /* ------------------------------------------------- steps of the method (device) */
 /* M orthonormal Haar states (Sec. 3; App. A: columns of a Haar unitary): the Q of the

@@ -301,76 +301,57 @@ __device__ __noinline__ void qd_polar_singular(const c128 (*Gc)[16], const c128 
     }
 }
 
-constexpr int kQdFinBlock = 128;  // eight 16-lane rows: one column pair each (D <= 16)
+constexpr int kQdFinBlock = 128;  // eight 16-lane rows: one column pair each (DM <= 16)
 
-template <int d>
-__global__ __launch_bounds__(kQdFinBlock) void k_qd_finalize(const c128 *partials, int32_t P, double beta,
-                                                             const int32_t *slots, c128 *gates, c128 *vstore,
-                                                             int32_t gstride, int32_t k) {
-  constexpr int D = d * d;
-  constexpr int PL = (D + 1) / 2 * 2;  // players of the round-robin schedule
-  constexpr int NP = PL / 2;           // pairs per round
-  static_assert(D <= 16 && NP * 16 <= kQdFinBlock, "one 16-lane row per pair");
-  __shared__ c128 Gc[PL][16];  // G by columns: Gc[c][r] = G[r][c]
-  __shared__ c128 Vc[PL][16];  // V by columns
-  __shared__ c128 Tm[D * D];   // Gamma (row-major), then W in the singular case
-  __shared__ c128 Vs[D * D];   // V_prev (row-major)
-  __shared__ c128 Nm[D * D];   // V_prev^dagger V_prev
-  __shared__ double sig[D];
-  const int s = slots[blockIdx.x];
-  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
-  c128 *vst = vstore + (int64_t)s * gstride + (int64_t)k * D * D;
+// LDS workspace of one DM x DM polar update.
+template <int DM>
+struct QdPolarLds {
+  static constexpr int PL = (DM + 1) / 2 * 2;  // players of the round-robin schedule
+  c128 Gc[PL][16];   // G by columns: Gc[c][r] = G[r][c]
+  c128 Vc[PL][16];   // V by columns
+  c128 Tm[DM * DM];  // the mixed environment (row-major), then W in the singular case
+  c128 Vs[DM * DM];  // V_prev (row-major) in, the new V out
+  c128 Nm[DM * DM];  // V_prev^dagger V_prev
+  c128 Pu[DM * DM];  // the polar factor (row-major) out
+  double sig[DM];
+};
+
+// The whole block: Pu <- the unitary polar factor of Tm, started from V_prev in Vs, and the
+// new right singular vectors into Vs (Tm and Vs filled and a barrier passed by the caller).
+template <int DM>
+__device__ void qd_polar_block(QdPolarLds<DM> &W) {
+  constexpr int PL = QdPolarLds<DM>::PL;
+  constexpr int NP = PL / 2;  // pairs per round
+  static_assert(DM <= 16 && NP * 16 <= kQdFinBlock, "one 16-lane row per pair");
   const int t = threadIdx.x;
-  for (int e = t; e < D * D; e += kQdFinBlock) {
-    // eight interleaved running sums, each batch of eight loads in flight together
-    const c128 *src = partials + (int64_t)s * P * D * D + e;
-    c128 acc[8];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) acc[v] = cmake(0.0, 0.0);
-    int blk = 0;
-    for (; blk + 7 < P; blk += 8) {
-      c128 x[8];
-#pragma unroll
-      for (int v = 0; v < 8; ++v) x[v] = src[(int64_t)(blk + v) * D * D];
-#pragma unroll
-      for (int v = 0; v < 8; ++v) acc[v] = acc[v] + x[v];
-    }
-#pragma unroll
-    for (int v = 0; v < 7; ++v)
-      if (blk + v < P) acc[v] = acc[v] + src[(int64_t)(blk + v) * D * D];
-    const c128 gm = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    Tm[e] = beta != 0.0 ? cmake((1.0 - beta) * gm.re + beta * u[e].re, (1.0 - beta) * gm.im + beta * u[e].im) : gm;
-    Vs[e] = vst[e];
-  }
   for (int e = t; e < PL * 16; e += kQdFinBlock) {
-    Gc[e >> 4][e & 15] = cmake(0.0, 0.0);
-    Vc[e >> 4][e & 15] = cmake(0.0, 0.0);
+    W.Gc[e >> 4][e & 15] = cmake(0.0, 0.0);
+    W.Vc[e >> 4][e & 15] = cmake(0.0, 0.0);
   }
-  __syncthreads();
   // Newton-Schulz on V_prev: N = V^dagger V, then V <- V (3I - N) / 2 (into Vc by columns)
-  for (int e = t; e < D * D; e += kQdFinBlock) {
-    const int i = e / D, j = e % D;
+  for (int e = t; e < DM * DM; e += kQdFinBlock) {
+    const int i = e / DM, j = e % DM;
     c128 acc = cmake(0.0, 0.0);
-    for (int kk = 0; kk < D; ++kk) cfma(acc, cconj(Vs[kk * D + i]), Vs[kk * D + j]);
-    Nm[e] = acc;
+    for (int kk = 0; kk < DM; ++kk) cfma(acc, cconj(W.Vs[kk * DM + i]), W.Vs[kk * DM + j]);
+    W.Nm[e] = acc;
   }
   __syncthreads();
-  for (int e = t; e < D * D; e += kQdFinBlock) {
-    const int i = e / D, j = e % D;
+  for (int e = t; e < DM * DM; e += kQdFinBlock) {
+    const int i = e / DM, j = e % DM;
     c128 acc = cmake(0.0, 0.0);
-    for (int kk = 0; kk < D; ++kk) {
-      const c128 x = Nm[kk * D + j];
-      cfma(acc, Vs[i * D + kk], cmake((kk == j ? 3.0 : 0.0) - x.re, -x.im));
+    for (int kk = 0; kk < DM; ++kk) {
+      const c128 x = W.Nm[kk * DM + j];
+      cfma(acc, W.Vs[i * DM + kk], cmake((kk == j ? 3.0 : 0.0) - x.re, -x.im));
     }
-    Vc[j][i] = cscale(acc, 0.5);
+    W.Vc[j][i] = cscale(acc, 0.5);
   }
   __syncthreads();
   // G <- Gamma V
-  for (int e = t; e < D * D; e += kQdFinBlock) {
-    const int i = e / D, j = e % D;
+  for (int e = t; e < DM * DM; e += kQdFinBlock) {
+    const int i = e / DM, j = e % DM;
     c128 acc = cmake(0.0, 0.0);
-    for (int kk = 0; kk < D; ++kk) cfma(acc, Tm[i * D + kk], Vc[j][kk]);
-    Gc[j][i] = acc;
+    for (int kk = 0; kk < DM; ++kk) cfma(acc, W.Tm[i * DM + kk], W.Vc[j][kk]);
+    W.Gc[j][i] = acc;
   }
   __syncthreads();
   const int pi = t >> 4, r = t & 15;  // pair (row of 16 lanes) and matrix row of this lane
@@ -384,7 +365,7 @@ __global__ __launch_bounds__(kQdFinBlock) void k_qd_finalize(const c128 *partial
       if (worker) {
         const int p = pi == 0 ? 0 : (rd + pi) % (PL - 1) + 1;
         const int q = pi == 0 ? rd % (PL - 1) + 1 : (rd - pi + PL - 1) % (PL - 1) + 1;
-        const c128 gp = Gc[p][r], gq = Gc[q][r], vp = Vc[p][r], vq = Vc[q][r];
+        const c128 gp = W.Gc[p][r], gq = W.Gc[q][r], vp = W.Vc[p][r], vq = W.Vc[q][r];
         double al = cabs2(gp), be = cabs2(gq);
         double gr = gp.re * gq.re + gp.im * gq.im;  // conj(gp) gq
         double gi = gp.re * gq.im - gp.im * gq.re;
@@ -414,41 +395,123 @@ __global__ __launch_bounds__(kQdFinBlock) void k_qd_finalize(const c128 *partial
           const double tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + t1 * rsq_nr(t1));
           const double cs = rsq_nr(fma(tt, tt, 1.0)), sn = cs * tt;
           const c128 egq = ec * gq, evq = ec * vq;
-          Gc[p][r] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
-          Gc[q][r] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
-          Vc[p][r] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
-          Vc[q][r] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
+          W.Gc[p][r] = cmake(cs * gp.re - sn * egq.re, cs * gp.im - sn * egq.im);
+          W.Gc[q][r] = cmake(sn * gp.re + cs * egq.re, sn * gp.im + cs * egq.im);
+          W.Vc[p][r] = cmake(cs * vp.re - sn * evq.re, cs * vp.im - sn * evq.im);
+          W.Vc[q][r] = cmake(sn * vp.re + cs * evq.re, sn * vp.im + cs * evq.im);
         }
       }
       __syncthreads();
     }
     if (!__syncthreads_or(rotated)) break;
   }
-  // singular values (column norms of G), V stored back
-  if (t < D) {
+  // singular values (column norms of G); the new V by rows
+  if (t < DM) {
     double a = 0.0;
-    for (int rr = 0; rr < D; ++rr) a += cabs2(Gc[t][rr]);
-    sig[t] = sqrt(a);
+    for (int rr = 0; rr < DM; ++rr) a += cabs2(W.Gc[t][rr]);
+    W.sig[t] = sqrt(a);
   }
-  for (int e = t; e < D * D; e += kQdFinBlock) vst[e] = Vc[e % D][e / D];
+  for (int e = t; e < DM * DM; e += kQdFinBlock) W.Vs[e] = W.Vc[e % DM][e / DM];
   __syncthreads();
   double smax = 0.0, smin = INFINITY;
-  for (int c = 0; c < D; ++c) {
-    smax = fmax(smax, sig[c]);
-    smin = fmin(smin, sig[c]);
+  for (int c = 0; c < DM; ++c) {
+    smax = fmax(smax, W.sig[c]);
+    smin = fmin(smin, W.sig[c]);
   }
   if (smin > 1e-200 && smin > 1e-13 * smax) {
     // u = W V^dagger with W = G diag(1 / sigma)
-    for (int e = t; e < D * D; e += kQdFinBlock) {
-      const int i = e / D, c = e % D;
+    for (int e = t; e < DM * DM; e += kQdFinBlock) {
+      const int i = e / DM, c = e % DM;
       c128 acc = cmake(0.0, 0.0);
-      for (int kk = 0; kk < D; ++kk) cfma_conj(acc, cscale(Gc[kk][i], 1.0 / sig[kk]), Vc[kk][c]);
-      u[e] = acc;
+      for (int kk = 0; kk < DM; ++kk) cfma_conj(acc, cscale(W.Gc[kk][i], 1.0 / W.sig[kk]), W.Vc[kk][c]);
+      W.Pu[e] = acc;
     }
-    return;
+  } else if (t == 0) {
+    // a (near) singular environment: thread 0 alone
+    qd_polar_singular<DM, PL>(W.Gc, W.Vc, W.Tm, W.sig, smax, W.Pu);
   }
-  // a (near) singular environment: thread 0 alone
-  if (t == 0) qd_polar_singular<D, PL>(Gc, Vc, Tm, sig, smax, u);
+  __syncthreads();
+}
+
+// Fixed-order sum of the work-group partials of entry e of a start's environment (partial
+// i in running sum i mod 8, each batch of eight loads in flight together).
+template <int D>
+__device__ __forceinline__ c128 qd_partial_sum(const c128 *partials, int32_t P, int s, int e) {
+  const c128 *src = partials + (int64_t)s * P * D * D + e;
+  c128 acc[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) acc[v] = cmake(0.0, 0.0);
+  int blk = 0;
+  for (; blk + 7 < P; blk += 8) {
+    c128 x[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) x[v] = src[(int64_t)(blk + v) * D * D];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[v] = acc[v] + x[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 7; ++v)
+    if (blk + v < P) acc[v] = acc[v] + src[(int64_t)(blk + v) * D * D];
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+__device__ __forceinline__ c128 qd_mix(c128 g, c128 u, double beta) {
+  return beta != 0.0 ? cmake((1.0 - beta) * g.re + beta * u.re, (1.0 - beta) * g.im + beta * u.im) : g;
+}
+
+template <int d>
+__global__ __launch_bounds__(kQdFinBlock) void k_qd_finalize(const c128 *partials, int32_t P, double beta,
+                                                             const int32_t *slots, c128 *gates, c128 *vstore,
+                                                             int32_t gstride, int32_t k) {
+  constexpr int D = d * d;
+  __shared__ QdPolarLds<D> W;
+  const int s = slots[blockIdx.x];
+  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  c128 *vst = vstore + (int64_t)s * gstride + (int64_t)k * D * D;
+  const int t = threadIdx.x;
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    W.Tm[e] = qd_mix(qd_partial_sum<D>(partials, P, s, e), u[e], beta);
+    W.Vs[e] = vst[e];
+  }
+  __syncthreads();
+  qd_polar_block<D>(W);
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    u[e] = W.Pu[e];
+    vst[e] = W.Vs[e];
+  }
+}
+
+// A one-qudit gate v on the slot's first qudit, held as v (x) I_d: its d x d environment is
+// the trace of the slot's D x D environment over the spectator digit,
+// G1[x][y] = sum_z G[d x + z][d y + z]; v <- polar((1 - beta) G1 + beta v), written back as
+// v (x) I_d. Its warm-start V (d x d) sits at the slot positions (d x, d y) of the stored V.
+template <int d>
+__global__ __launch_bounds__(kQdFinBlock) void k_qd_finalize1(const c128 *partials, int32_t P, double beta,
+                                                              const int32_t *slots, c128 *gates, c128 *vstore,
+                                                              int32_t gstride, int32_t k) {
+  constexpr int D = d * d;
+  __shared__ QdPolarLds<d> W;
+  __shared__ c128 Gf[D * D];
+  const int s = slots[blockIdx.x];
+  c128 *u = gates + (int64_t)s * gstride + (int64_t)k * D * D;
+  c128 *vst = vstore + (int64_t)s * gstride + (int64_t)k * D * D;
+  const int t = threadIdx.x;
+  for (int e = t; e < D * D; e += kQdFinBlock) Gf[e] = qd_partial_sum<D>(partials, P, s, e);
+  __syncthreads();
+  for (int e = t; e < d * d; e += kQdFinBlock) {
+    const int x = e / d, y = e % d;
+    c128 g1 = cmake(0.0, 0.0);
+    for (int z = 0; z < d; ++z) g1 = g1 + Gf[(d * x + z) * D + d * y + z];
+    W.Tm[e] = qd_mix(g1, u[(d * x) * D + d * y], beta);
+    W.Vs[e] = vst[(d * x) * D + d * y];
+  }
+  __syncthreads();
+  qd_polar_block<d>(W);
+  for (int e = t; e < D * D; e += kQdFinBlock) {
+    const int r = e / D, c = e % D;
+    u[e] = (r % d == c % d) ? W.Pu[(r / d) * d + c / d] : cmake(0.0, 0.0);
+  }
+  for (int e = t; e < d * d; e += kQdFinBlock) vst[(d * (e / d)) * D + d * (e % d)] = W.Vs[e];
 }
 
 // count D x D identity matrices (the initial warm-start V).
@@ -525,6 +588,41 @@ __global__ void k_qd_haar(uint64_t seed, int32_t start0, int32_t starts, int32_t
     for (int c = 0; c < D; ++c) u[r * D + c] = q[c][r];
 }
 
+// Gate kinds of the initial slots: a constant gate's slot takes the template's gate (every
+// start); with drawn gates, a one-qudit gate's slot becomes v (x) I_d with v Haar on U(d)
+// from the d x d Ginibre block at indices 256 gate + d col + row of the start's stream.
+template <int d>
+__global__ void k_qd_kinds(uint64_t seed, int32_t starts, int32_t L, const int32_t *kinds, const c128 *fixed,
+                           int32_t drawn, c128 *out) {
+  constexpr int D = d * d;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)starts * L) return;
+  const int s = (int)(t / L), k = (int)(t % L);
+  c128 *u = out + t * D * D;
+  if (kinds[k] == QFS_GATE_FIXED) {
+    for (int e = 0; e < D * D; ++e) u[e] = fixed[(int64_t)k * D * D + e];
+    return;
+  }
+  if (kinds[k] != QFS_GATE_1Q || !drawn) return;
+  c128 q[d][d];  // [col][row]
+  for (int c = 0; c < d; ++c)
+    for (int r = 0; r < d; ++r) q[c][r] = complex_normal(seed, kRoleInit, (uint32_t)s, (uint64_t)k * 256u + (uint64_t)(c * d + r));
+  for (int c = 0; c < d; ++c) {
+    for (int rep = 0; rep < 2; ++rep)
+      for (int o = 0; o < c; ++o) {
+        c128 dd = cmake(0.0, 0.0);
+        for (int r = 0; r < d; ++r) cfma(dd, cconj(q[o][r]), q[c][r]);
+        for (int r = 0; r < d; ++r) q[c][r] = q[c][r] - dd * q[o][r];
+      }
+    double nn = 0.0;
+    for (int r = 0; r < d; ++r) nn += cabs2(q[c][r]);
+    const double inv = 1.0 / sqrt(nn);
+    for (int r = 0; r < d; ++r) q[c][r] = cscale(q[c][r], inv);
+  }
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) u[r * D + c] = (r % d == c % d) ? q[c / d][r / d] : cmake(0.0, 0.0);
+}
+
 double qd_now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -543,6 +641,7 @@ struct QdSweeper {
   int d = 0, n = 0, L = 0, S = 0;
   int64_t N = 0;
   const int32_t *pairs = nullptr;  // host [L][2]
+  const int32_t *kinds = nullptr;  // host [L] or nullptr (every gate QFS_GATE_2Q)
   hipStream_t st = nullptr;
   int M = 0, Mv = 0;
   DevBuf psi, phi, psiv, phiv;  // working sets [N][M] in R (shared by the starts)
@@ -598,8 +697,12 @@ struct QdSweeper {
     hipLaunchKernelGGL((k_qd_env<R, dd>), dim3(dd * dd / qd_env_rows<dd>() * P, ns), dim3(kQdBlock), 0, s, a, as,
                        b, bs, g, P, partials.as<c128>(), sl);
     QFS_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(ns), dim3(kQdFinBlock), 0, s, partials.as<c128>(), P, beta, sl, g64,
-                       vst, L * dd * dd * dd * dd, k);
+    if (kinds && kinds[k] == QFS_GATE_1Q)
+      hipLaunchKernelGGL((k_qd_finalize1<dd>), dim3(ns), dim3(kQdFinBlock), 0, s, partials.as<c128>(), P, beta, sl,
+                         g64, vst, L * dd * dd * dd * dd, k);
+    else
+      hipLaunchKernelGGL((k_qd_finalize<dd>), dim3(ns), dim3(kQdFinBlock), 0, s, partials.as<c128>(), P, beta, sl,
+                         g64, vst, L * dd * dd * dd * dd, k);
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   }
@@ -688,7 +791,8 @@ struct QdSweeper {
       for (int h = 0; h < halves; ++h) {
         if (k < L - 1)
           QFS_TRY(apply_on(k == L - 2 ? F : A, k == L - 2 ? 0 : sN, A, sN, k + 1, true, M, hsl[h], hn[h], hst[h]));
-        QFS_TRY(env_on(a, as, k == 0 ? P0 : B + (k - 1) * sN, k == 0 ? 0 : bstride, k, hsl[h], hn[h], hst[h]));
+        if (!(kinds && kinds[k] == QFS_GATE_FIXED))  // a constant gate has no environment
+          QFS_TRY(env_on(a, as, k == 0 ? P0 : B + (k - 1) * sN, k == 0 ? 0 : bstride, k, hsl[h], hn[h], hst[h]));
       }
     }
     if (split) {
@@ -741,14 +845,14 @@ int qd_validate(int d, const qfs_template *t) {
     set_error_detail("qudits: need n >= 2, d^n <= 2^24, n_gates >= 1, pairs");
     return QFS_EINVAL;
   }
-  if (t->kinds) {
-    set_error_detail("qudits: gate kinds are not supported");
-    return QFS_EUNSUPPORTED;
-  }
   for (int k = 0; k < t->n_gates; ++k) {
     const int a = t->pairs[2 * k], b = t->pairs[2 * k + 1];
     if (a < 0 || b < 0 || a >= t->n_qubits || b >= t->n_qubits || a == b) {
       set_error_detail("qudits: gate " + std::to_string(k) + " has an invalid qudit pair");
+      return QFS_EINVAL;
+    }
+    if (t->kinds && (t->kinds[k] < QFS_GATE_2Q || t->kinds[k] > QFS_GATE_FIXED)) {
+      set_error_detail("qudits: gate " + std::to_string(k) + " has an unknown kind");
       return QFS_EINVAL;
     }
   }
@@ -920,6 +1024,7 @@ int qd_run(int d, const qfs_template *t, QdData &data, const qfs_params &p, c128
   w.S = S;
   w.N = qd_pow(d, w.n);
   w.pairs = t->pairs;
+  w.kinds = t->kinds;
   w.st = static_cast<hipStream_t>(p.hip_stream);
   w.g64 = g64;
   w.vst = vst;
@@ -1063,6 +1168,31 @@ int qd_instantiate_impl(int d, const qfs_template *tmpl, QdData &data, const qfs
       hipLaunchKernelGGL(k_qd_haar<4>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
     QFS_HIP(hipGetLastError());
   }
+  DevBuf dkinds;
+  if (tmpl->kinds) {
+    bool any_fixed = false;
+    for (int k = 0; k < L; ++k) any_fixed |= tmpl->kinds[k] == QFS_GATE_FIXED;
+    if (any_fixed && !tmpl->fixed_gates) {
+      set_error_detail("qudits: constant gates need tmpl->fixed_gates");
+      return QFS_EINVAL;
+    }
+    QFS_TRY(dkinds.alloc(sizeof(int32_t) * L));
+    QFS_HIP(hipMemcpyAsync(dkinds.ptr, tmpl->kinds, sizeof(int32_t) * L, hipMemcpyHostToDevice, st));
+    const int64_t tot = (int64_t)S * L;
+    const dim3 grid((unsigned)((tot + 63) / 64));
+    const c128 *fx = reinterpret_cast<const c128 *>(tmpl->fixed_gates);
+    const int drawn = gates_in ? 0 : 1;
+    if (d == 2)
+      hipLaunchKernelGGL(k_qd_kinds<2>, grid, dim3(64), 0, st, p.seed, S, L, dkinds.as<int32_t>(), fx, drawn,
+                         gates.as<c128>());
+    else if (d == 3)
+      hipLaunchKernelGGL(k_qd_kinds<3>, grid, dim3(64), 0, st, p.seed, S, L, dkinds.as<int32_t>(), fx, drawn,
+                         gates.as<c128>());
+    else
+      hipLaunchKernelGGL(k_qd_kinds<4>, grid, dim3(64), 0, st, p.seed, S, L, dkinds.as<int32_t>(), fx, drawn,
+                         gates.as<c128>());
+    QFS_HIP(hipGetLastError());
+  }
   DevBuf vstore;
   QFS_TRY(vstore.alloc(sizeof(c128) * (size_t)S * L * D * D));
   hipLaunchKernelGGL(k_qd_identity, dim3(qd_grid((int64_t)S * L * D * D)), dim3(kQdBlock), 0, st, (int64_t)S * L, D,
@@ -1201,10 +1331,10 @@ int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_
   return qd_instantiate_impl(d, tmpl, data, *params, gates_in, gates_out, res, t0);
 }
 
-int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32_t M, const qfs_c128 *psi,
-                    const qfs_c128 *phi, int32_t starts, qfs_c128 *gates, int32_t precision, double beta,
-                    double *c_train, void *hip_stream) {
-  qfs_template t{n, L, pairs, nullptr, nullptr};
+int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, int32_t M,
+                    const qfs_c128 *psi, const qfs_c128 *phi, int32_t starts, qfs_c128 *gates, int32_t precision,
+                    double beta, double *c_train, void *hip_stream) {
+  qfs_template t{n, L, pairs, kinds, nullptr};
   QFS_TRY(qd_validate(d, &t));
   const int64_t N = qd_pow(d, n);
   if (M < 1 || M > N || starts < 1 || !psi || !phi || !gates || !c_train ||
@@ -1230,6 +1360,7 @@ int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, int32
     w.S = starts;
     w.N = N;
     w.pairs = pairs;
+    w.kinds = kinds;
     w.st = st;
     w.g64 = reinterpret_cast<c128 *>(gates);
     w.vst = vst.as<c128>();

@@ -142,7 +142,7 @@ def load():
                                               C.POINTER(Params), P, P, C.POINTER(Result)]
         lib.qfs_qudit_instantiate_target.argtypes = [I32, C.POINTER(Template), C.POINTER(Target),
                                                      C.POINTER(Params), P, P, C.POINTER(Result)]
-        lib.qfs_qudit_sweep.argtypes = [I32, I32, I32, P, I32, P, P, I32, P, I32, D, P, P]
+        lib.qfs_qudit_sweep.argtypes = [I32, I32, I32, P, P, I32, P, P, I32, P, I32, D, P, P]
         for name in EXPORTS:
             if name not in ("qfs_strerror", "qfs_last_error_detail", "qfs_version",
                             "qfs_default_params"):
@@ -549,24 +549,33 @@ def qfs_sweep(n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kind
     return c
 
 
-def qfs_qudit_sweep(d, n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0):
-    """One qudit sweep of ``gates`` [starts, L, d^2, d^2] (in place); returns c_train."""
+def qfs_qudit_sweep(d, n, pairs, psi, phi, gates, precision=QFS_PREC_FP64, beta=0.0, kinds=None):
+    """One qudit sweep of ``gates`` [starts, L, d^2, d^2] (in place); returns c_train.
+    ``kinds``: per-gate QFS_GATE_* (constant gates are their own entries)."""
     import numpy as np
     arr, pp = _pairs(pairs)
     starts = gates.shape[0]
     c = np.zeros(starts)
-    _check(load().qfs_qudit_sweep(d, n, arr.shape[0], pp, psi.shape[0], _dev_c128(psi, "psi"),
+    kd = None
+    if kinds is not None:
+        kd = np.ascontiguousarray(np.asarray(kinds, dtype=np.int32).reshape(-1))
+        if kd.shape[0] != arr.shape[0]:
+            raise ValueError("kinds needs one entry per gate")
+    _check(load().qfs_qudit_sweep(d, n, arr.shape[0], pp, None if kd is None else kd.ctypes.data_as(C.c_void_p),
+                                  psi.shape[0], _dev_c128(psi, "psi"),
                                   _dev_c128(phi, "phi"), starts, _dev_c128(gates, "gates"), precision,
                                   beta, c.ctypes.data_as(C.c_void_p), _stream()), "qfs_qudit_sweep")
     return c
 
 
-def qfs_qudit_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None):
+def qfs_qudit_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=None, kinds=None,
+                          fixed_gates=None):
     """Qudit instantiation on a fixed sample set ``psi``/``phi`` [n_samples, d^n] whose last
-    ``n_val`` rows validate. Returns (gates [L, d^2, d^2] device tensor, result dict)."""
+    ``n_val`` rows validate; ``kinds`` and ``fixed_gates`` (device [L, d^2, d^2]) as for
+    qubits. Returns (gates [L, d^2, d^2] device tensor, result dict)."""
     import torch
     keep = []
-    tmpl = _template(n, pairs, keep)
+    tmpl = _template(n, pairs, keep, kinds, fixed_gates)
     out = torch.empty((tmpl.n_gates, d * d, d * d), dtype=torch.complex128, device=psi.device)
     par = _params(params)
     res = Result()
@@ -578,13 +587,15 @@ def qfs_qudit_instantiate(d, n, pairs, psi, phi, n_val=0, params=None, gates_in=
 
 
 def qfs_qudit_instantiate_target(d, n, pairs, *, U=None, target_pairs=None, target_gates=None,
-                                 psi=None, phi=None, n_val=0, params=None, gates_in=None):
+                                 psi=None, phi=None, n_val=0, params=None, gates_in=None, kinds=None,
+                                 fixed_gates=None):
     """Qudit instantiation with one target form: dense ``U`` [d^n, d^n] or a circuit
     (``target_pairs``, ``target_gates`` [Lt, d^2, d^2]) with states drawn on the device, or
-    samples ``psi``/``phi``. Returns (gates [L, d^2, d^2] device tensor, result dict)."""
+    samples ``psi``/``phi``; ``kinds`` and ``fixed_gates`` as for qubits. Returns (gates
+    [L, d^2, d^2] device tensor, result dict)."""
     import torch
     keep = []
-    tmpl = _template(n, pairs, keep)
+    tmpl = _template(n, pairs, keep, kinds, fixed_gates)
     tgt = Target()
     dev = _fill_target(tgt, n, keep, U=U, target_pairs=target_pairs, target_gates=target_gates,
                        psi=psi, phi=phi, n_val=n_val)

@@ -313,3 +313,135 @@ def test_qudit_target_samples_form_forwards():
     for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final", "c_train"):
         assert ia[k] == ib[k], k
     assert torch.equal(ga, gb)
+
+
+# ------------------------------------------------------------------ qudit gate kinds
+def _csum(d):
+    D = d * d
+    U = np.zeros((D, D), dtype=np.complex128)
+    for x in range(d):
+        for y in range(d):
+            U[d * x + (y + x) % d, d * x + y] = 1.0
+    return U
+
+
+def _kind_slots(d, kinds, g):
+    out = []
+    for k in kinds:
+        if k == Q.QFS_GATE_1Q:
+            out.append(np.kron(I.haar_unitary(d, g), np.eye(d)))
+        elif k == Q.QFS_GATE_FIXED:
+            out.append(_csum(d))
+        else:
+            out.append(I.haar_unitary(d * d, g))
+    return np.stack(out)
+
+
+KIND_PAIRS = [(0, 1), (1, 2), (2, 0), (1, 0), (0, 2), (2, 1), (1, 2)]
+KINDS = [1, 2, 0, 1, 2, 1, 0]  # QFS_GATE_1Q, QFS_GATE_FIXED, QFS_GATE_2Q, ...
+
+
+def test_d2_qudit_kinds_sweep_equals_qubit_kinds_sweep():
+    say("qudit d=2 kinds vs qubit kinds sweep")
+    g = np.random.default_rng(81)
+    n, M = 4, 6
+    pairs = [(0, 1), (1, 2), (2, 3), (3, 0), (1, 3), (2, 0)]
+    kinds = [1, 2, 0, 1, 0, 2]
+    gates = np.stack([_kind_slots(2, kinds, g) for _ in range(2)])
+    psi = _samples(2, n, M, g)
+    phi = O.apply_circuit(n, psi, pairs, I.haar_gates(6, g))
+    a, b = dev(gates), dev(gates)
+    for _ in range(4):
+        ca = Q.qfs_qudit_sweep(2, n, pairs, dev(psi), dev(phi), a, precision=Q.QFS_PREC_FP64, kinds=kinds)
+        cb = Q.qfs_sweep(n, pairs, dev(psi), dev(phi), b, precision=Q.QFS_PREC_FP64, kinds=kinds)
+        assert np.max(np.abs(np.asarray(ca) - np.asarray(cb))) <= 1e-12 * max(np.max(cb), 1e-3)
+    assert np.max(np.abs(host(a) - host(b))) < 1e-11
+
+
+@pytest.mark.parametrize("d,n,M,starts", [(3, 3, 4, 2), (3, 5, 3, 2), (4, 3, 4, 1)])
+def test_qudit_kinds_fp64_lock_step(d, n, M, starts):
+    """One-qudit, constant and two-qudit gates: FP64 lock step with the oracle for 10 sweeps
+    (cost and gates 1e-10); constant slots stay bitwise as given, one-qudit slots keep
+    the form v (x) I_d."""
+    say(f"qudit kinds lock-step d={d} n={n} M={M}")
+    g = np.random.default_rng(90 + 10 * d + n)
+    pairs = KIND_PAIRS
+    gates = np.stack([_kind_slots(d, KINDS, g) for _ in range(starts)])
+    psi = _samples(d, n, M, g)
+    phi = O.qd_apply_circuit(d, n, psi, pairs, _kind_slots(d, KINDS, g))
+    dg, dpsi, dphi = dev(gates), dev(psi), dev(phi)
+    ref = gates.copy()
+    for sweep in range(10):
+        c = Q.qfs_qudit_sweep(d, n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_FP64, kinds=KINDS)
+        for s in range(starts):
+            ref[s], cr = O.qd_sweep(d, n, pairs, psi, phi, ref[s], kinds=KINDS)
+            assert abs(c[s] - cr) <= 1e-10 * max(cr, 1e-3), (sweep, s, c[s], cr)
+        got = host(dg)
+        assert np.max(np.abs(got - ref)) < 1e-10
+    for s in range(starts):
+        for k, kind in enumerate(KINDS):
+            if kind == Q.QFS_GATE_FIXED:
+                assert np.array_equal(got[s, k], _csum(d))
+            elif kind == Q.QFS_GATE_1Q:
+                v = got[s, k][::d, ::d]
+                assert np.array_equal(got[s, k], np.kron(v, np.eye(d)))
+
+
+def test_qutrit_kinds_mixed_teacher_forced():
+    say("qutrit kinds mixed teacher-forced n=5")
+    n, M = 5, 8
+    g = np.random.default_rng(95)
+    pairs = KIND_PAIRS + [(3, 4), (4, 2)]
+    kinds = KINDS + [Q.QFS_GATE_2Q, Q.QFS_GATE_1Q]
+    gates = np.stack([_kind_slots(3, kinds, g) for _ in range(2)])
+    psi = _samples(3, n, M, g)
+    phi = O.qd_apply_circuit(3, n, psi, pairs, _kind_slots(3, kinds, g))
+    dpsi, dphi, dg = dev(psi), dev(phi), dev(gates)
+    c_init = max(O.qd_sweep(3, n, pairs, psi, phi, gates[0], kinds=kinds)[1], 1e-3)
+    for sweep in range(4):
+        start = host(dg).copy()
+        c = Q.qfs_qudit_sweep(3, n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED, kinds=kinds)
+        for s in range(2):
+            _, cr = O.qd_sweep(3, n, pairs, psi, phi, start[s], kinds=kinds)
+            assert abs(c[s] - cr) <= 1e-6 * max(cr, c_init), (sweep, s, c[s], cr)
+
+
+def test_qutrit_kinds_instantiate_follows_oracle():
+    """Initial gates drawn on each side (one-qutrit Haar slots, CSUM constants), states
+    drawn on each side, a circuit target from the same template: same reason, sweeps,
+    doublings and final M as the oracle, cost to rounding; the constants kept. One start:
+    the target is exactly reachable, so starts that succeed in the same sweep all end at
+    the rounding floor (~1e-30) and the pick among them is decided by rounding."""
+    say("qutrit kinds instantiate vs oracle")
+    n = 3
+    g = np.random.default_rng(96)
+    tg = _kind_slots(3, KINDS, g)
+    fixed = np.stack([_csum(3)] * len(KINDS))
+    p = O.default_params(multistarts=1, m_init=3, seed=12, dist_tol=1e-10, max_iter=400, min_iter=3)
+    g_ref, ref = O.qd_instantiate_target(3, n, KIND_PAIRS, target_pairs=KIND_PAIRS, target_gates=tg,
+                                         params=p, kinds=KINDS, fixed=fixed)
+    g_gpu, got = Q.qfs_qudit_instantiate_target(3, n, KIND_PAIRS, target_pairs=KIND_PAIRS,
+                                                target_gates=dev(tg), params=dict(p, precision=Q.QFS_PREC_FP64),
+                                                kinds=KINDS, fixed_gates=dev(fixed))
+    say(f"  oracle {ref['reason_name']} start={ref['best_start']} sweeps={ref['sweeps']} "
+        f"restarts={ref['restarts']} c={ref['c_train']:.3e}; device {got['reason_name']} "
+        f"start={got['best_start']} sweeps={got['sweeps']} c={got['c_train']:.3e}")
+    for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final"):
+        assert got[k] == ref[k], (k, got, ref)
+    assert abs(got["c_train"] - ref["c_train"]) <= 1e-8 * ref["c_train"] + 1e-18
+    out = host(g_gpu)
+    assert np.max(np.abs(out - g_ref)) < 1e-7
+    for k, kind in enumerate(KINDS):
+        if kind == Q.QFS_GATE_FIXED:
+            assert np.array_equal(out[k], _csum(3))
+
+
+def test_qudit_kinds_rejected_when_malformed():
+    say("qudit kinds argument checks")
+    psi = dev(np.eye(27)[:3])
+    with pytest.raises(Q.QfsError) as e:  # constant gates without their matrices
+        Q.qfs_qudit_instantiate(3, 3, KIND_PAIRS, psi, psi, params=Q.qfs_default_params(), kinds=KINDS)
+    assert e.value.code == Q.QFS_EINVAL
+    with pytest.raises(Q.QfsError) as e:
+        Q.qfs_qudit_instantiate(3, 3, [(0, 1)], psi, psi, params=Q.qfs_default_params(), kinds=[7])
+    assert e.value.code == Q.QFS_EINVAL
