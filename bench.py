@@ -278,7 +278,9 @@ def qudits_leg(dev, steps):
     the sets to the internal layout). (b) Time to solution of full-unitary QFactor (the
     complete basis as the sample set, M = 3^n, no validation set) against the sample method
     (M from 9, doubling up to 144 against 9 validation samples) on 6 and 7 qutrits
-    (brickwork, 4 sublayers), 16 starts, App. A rules, MIXED, same seed."""
+    (brickwork, 4 sublayers), 16 starts, App. A rules, MIXED, same seed. (c) Sweeps of 5
+    ququarts (d = 4, 16 x 16 gates), as (a). (d) Gate kinds: time to 1e-8 of a 6-qutrit
+    template of one-qutrit gates around constant CSUM gates, states drawn on the device."""
     import numpy as np
     import torch
 
@@ -332,6 +334,58 @@ def qudits_leg(dev, steps):
         row["speedup"] = round(row["qf"]["seconds"] / row["qfs"]["seconds"], 2)
         rows.append(row)
     out["qf_vs_qfs_qutrits"] = rows
+    # (c) d = 4: 5 ququarts (1024 amplitudes), the same brickwork, M = 64, 16 starts
+    n, d, M = 5, 4, 64
+    pairs = I.qudit_brickwork(n, 4)
+    L = len(pairs)
+    tg = np.stack([I.haar_unitary(16, g) for _ in range(L)])
+    N = d ** n
+    psi = I.orthonormal_states(N, M, g)
+    phi = I.qudit_circuit_apply(d, n, psi, pairs, tg)
+    dpsi, dphi = torch.as_tensor(psi).to(dev), torch.as_tensor(phi).to(dev)
+    Q.qfs_qudit_instantiate(d, n, pairs, dpsi, dphi, params=dict(base, max_iter=2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = Q.qfs_qudit_instantiate(d, n, pairs, dpsi, dphi, params=dict(base, max_iter=steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S_amp = M * N
+    alg = 16.0 * S_amp * L + 8.0 * S_amp
+    out["sweeps_5ququarts"] = {"workload": f"5 ququarts (d = 4), {L} two-ququart gates (16 x 16), M={M} fixed, "
+                                           f"{S} lock-step starts, MIXED, one qfs_qudit_instantiate call of {steps} sweeps",
+                               "start_sweeps_per_s": round(r["start_sweeps"] / dt, 1),
+                               "ms_per_step": round(1e3 * dt / steps, 3),
+                               "sweep_algorithmic_GBps": round(alg * r["start_sweeps"] / dt / 1e9, 1)}
+    # (d) gate kinds: 6 qutrits, one-qutrit gates around constant CSUM gates (a qutrit
+    # counterpart of the U3 + CNOT partitions), time to 1e-8 from drawn states against a
+    # target from the same template
+    n = 6
+    pairs, kinds = [], []
+    for layer in range(4):
+        for a in range(layer % 2, n - 1, 2):
+            pairs += [(a, a + 1), (a + 1, a), (a, a + 1)]
+            kinds += [Q.QFS_GATE_1Q, Q.QFS_GATE_1Q, Q.QFS_GATE_FIXED]
+    csum = np.zeros((9, 9), dtype=np.complex128)
+    for x in range(3):
+        for y in range(3):
+            csum[3 * x + (y + x) % 3, 3 * x + y] = 1.0
+    slots = []
+    for k in kinds:
+        slots.append(csum if k == Q.QFS_GATE_FIXED else np.kron(I.haar_unitary(3, g), np.eye(3)))
+    tg = np.stack(slots)
+    fixed = torch.as_tensor(np.stack([csum] * len(kinds))).to(dev)
+    p = Q.qfs_default_params(seed=41, m_init=9, time_budget_s=60.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, r = Q.qfs_qudit_instantiate_target(3, n, pairs, target_pairs=pairs, target_gates=torch.as_tensor(tg).to(dev),
+                                          params=p, kinds=kinds, fixed_gates=fixed)
+    torch.cuda.synchronize()
+    out["kinds_6qutrits_csum"] = {"workload": f"6 qutrits, {len(kinds)} gates ({kinds.count(Q.QFS_GATE_1Q)} one-qutrit, "
+                                              f"{kinds.count(Q.QFS_GATE_FIXED)} constant CSUM), target from the same "
+                                              "template, states drawn on the device, 16 starts, MIXED, App. A rules",
+                                  "seconds": round(time.perf_counter() - t0, 4), "reason": r["reason_name"],
+                                  "m_final": r["m_final"], "sweeps": r["sweeps"], "c_train": r["c_train"],
+                                  "c_val": r["c_val"]}
     return out
 
 
