@@ -184,6 +184,10 @@ def test_qudit_target_arguments_rejected_without_device_work():
     unknown = Q.Target()
     unknown.kind = 7
     assert call(3, tmpl, unknown) == Q.QFS_EINVAL
+    bad_kinds = np.ascontiguousarray(np.asarray([0, 7], dtype=np.int32))
+    tmpl_k = Q.Template(3, 2, arr.ctypes.data_as(C.POINTER(C.c_int32)),
+                        bad_kinds.ctypes.data_as(C.POINTER(C.c_int32)))
+    assert call(3, tmpl_k, dense) == Q.QFS_EINVAL
     for field, bad in [("multistarts", 0), ("beta", 1.5), ("precision", 7), ("max_iter", 0),
                        ("full_unitary", 1)]:
         p = Q.Params()
