@@ -755,6 +755,34 @@ def learned(dev, count, large):
         rows["time_to_solution_speedup"] = round(rows["plain"]["wall_s"] / rows["learned"]["wall_s"], 2)
         rows["work_ratio"] = round(rows["learned"]["amp_updates"] / max(1.0, rows["plain"]["amp_updates"]), 3)
         out["held_out"] = rows
+        # one problem at a time (no batch tail): a stratified sample of the same problems,
+        # three quarters from the 3-7 qubit part and one quarter from the 8-10 qubit part
+        small = count - count // 4
+        pick = list(range(min(48, small))) + list(range(small, min(small + 16, count)))
+        one = {"plain": {"seconds": 0.0, "successes": 0, "amp_updates": 0.0, "doublings": 0},
+               "learned": {"seconds": 0.0, "successes": 0, "amp_updates": 0.0, "doublings": 0, "fallbacks": 0}}
+        for name, fn in (("plain", Q.qfs_instantiate), ("learned", Q.qfs_instantiate_learned)):
+            for i in pick[:2]:  # code objects
+                fn(dprobs[i]["n"], dprobs[i]["pairs"], target_pairs=dprobs[i]["target_pairs"],
+                   target_gates=dprobs[i]["target_gates"], params=params)
+            for i in pick:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, r = fn(dprobs[i]["n"], dprobs[i]["pairs"], target_pairs=dprobs[i]["target_pairs"],
+                          target_gates=dprobs[i]["target_gates"], params=params)
+                torch.cuda.synchronize()
+                row = one[name]
+                row["seconds"] += time.perf_counter() - t0
+                row["successes"] += r["reason_name"] == "SUCCESS"
+                row["amp_updates"] += r["amp_updates"]
+                row["doublings"] += r["restarts"]
+                if name == "learned":
+                    row["fallbacks"] += r["fallback"]
+            one[name]["seconds"] = round(one[name]["seconds"], 3)
+        one["problems"] = len(pick)
+        one["time_to_solution_speedup"] = round(one["plain"]["seconds"] / max(1e-9, one["learned"]["seconds"]), 2)
+        one["work_ratio"] = round(one["learned"]["amp_updates"] / max(1.0, one["plain"]["amp_updates"]), 3)
+        out["one_at_a_time"] = one
     if large > 0:
         g = I.rng(I.derive_seed(0x5A17 + 7))
         res = {"plain": [], "learned": []}

@@ -338,7 +338,12 @@ int qfs_predict_batch(int32_t P, const qfs_template *tmpl, const qfs_params *par
                       int32_t *m0, int32_t *starts);
 
 /* qfs_instantiate with M starting at max(m_init, predicted M) (doubling on the
- * validation cost as usual, Sec. 3) and the predicted number of leading starts. When
+ * validation cost as usual, Sec. 3) and a number of leading starts chosen for wall time:
+ * one problem's starts run together, so a sweep takes about T0 + k b / BW for k starts
+ * (T0 the sweep's serial chain, about 17.5 us per gate; BW about 3.7 TB/s; b = (2L + 1)
+ * M 2^n 8 bytes per start), and k minimises the expected time with the predicted
+ * per-start success rate (the pruned starts run after a failed first run), pruning only
+ * when that saves at least a tenth of the time of all starts. When
  * that run does not succeed and starts were pruned, the pruned starts run after it
  * with the plain method's control from the M the first run ended at (their own initial
  * gates), fallback = 1, and the better of the two runs is returned (success first, then

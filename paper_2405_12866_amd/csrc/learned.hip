@@ -124,11 +124,13 @@ void template_features(const qfs_template &t, float *out) {
 
 // Network outputs -> (M0, kept starts). With a predicted per-start success rate p, k
 // kept starts cost k start-runs and, with probability (1 - p)^k that none succeeds, the
-// S - k pruned ones run afterwards; k minimises k + (1 - p)^k (S - k).
-void decide(const float *y, int n, int S, int32_t *m0, int32_t *starts) {
+// S - k pruned ones run afterwards; k minimises k + (1 - p)^k (S - k) (the batched run,
+// where the device is kept full and time follows work).
+void decide(const float *y, int n, int S, int32_t *m0, int32_t *starts, double *prob = nullptr) {
   const double lg = std::min<double>(n, std::max(1.0, std::nearbyint((double)y[0])));
   *m0 = (int32_t)std::ldexp(1.0, (int)lg);
   const double p = std::min(1.0, std::max(0.0, 1.0 / (1.0 + std::exp(-(double)y[1]))));
+  if (prob) *prob = p;
   int best = S;
   double best_cost = (double)S;
   for (int k = 1; k < S; ++k) {
@@ -141,8 +143,33 @@ void decide(const float *y, int n, int S, int32_t *m0, int32_t *starts) {
   *starts = best;
 }
 
+// One problem at a time the starts run together, so the time of a sweep is not
+// proportional to the starts: about T0 + k b / BW for k starts of b bytes each (T0 the
+// serial chain of the sweep, about 17.5 us per gate on the MI355X, BW about 3.7 TB/s of
+// algorithmic bytes, b = (2 L + 1) M 2^n 8 bytes), i.e. proportional to
+// 1 + k / k_sat with k_sat = T0 BW / b. The kept starts k then minimise the expected
+// time (1 + k / k_sat) + (1 - p)^k (1 + (S - k) / k_sat) against 1 + S / k_sat for
+// all S, and starts are pruned only when that saves at least a tenth of the time: small
+// problems (k_sat >> S) keep every start, since pruning them saves no measurable time and
+// risks the fallback's second run.
+int decide_single(double p, int n, int L, int m0, int S) {
+  const double b = (2.0 * L + 1.0) * (double)m0 * std::ldexp(1.0, n) * 8.0;
+  const double k_sat = (17.5e-6 * L) * 3.7e12 / b;
+  const double all = 1.0 + S / k_sat;
+  int best = S;
+  double best_cost = all;
+  for (int k = 1; k < S; ++k) {
+    const double cost = 1.0 + k / k_sat + std::pow(1.0 - p, k) * (1.0 + (S - k) / k_sat);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = k;
+    }
+  }
+  return best_cost < 0.9 * all ? best : S;
+}
+
 int predict_many(int P, const qfs_template *tmpl, const qfs_params &p, int32_t *m0, int32_t *starts,
-                 hipStream_t s) {
+                 hipStream_t s, double *prob = nullptr) {
   std::vector<float> feat((size_t)P * kMlpF), y((size_t)P * kMlpO);
   for (int i = 0; i < P; ++i) {
     if (!valid_template(&tmpl[i])) return set_error_detail("learned: invalid template"), QFS_EINVAL;
@@ -158,7 +185,8 @@ int predict_many(int P, const qfs_template *tmpl, const qfs_params &p, int32_t *
   QFS_HIP(hipMemcpyAsync(y.data(), yd.ptr, sizeof(float) * y.size(), hipMemcpyDeviceToHost, s));
   QFS_HIP(hipStreamSynchronize(s));
   const int S = std::max(1, p.multistarts);
-  for (int i = 0; i < P; ++i) decide(y.data() + (size_t)i * kMlpO, tmpl[i].n_qubits, S, m0 + i, starts + i);
+  for (int i = 0; i < P; ++i)
+    decide(y.data() + (size_t)i * kMlpO, tmpl[i].n_qubits, S, m0 + i, starts + i, prob ? prob + i : nullptr);
   return QFS_OK;
 }
 
@@ -196,8 +224,10 @@ int qfs_instantiate_learned(const qfs_template *tmpl, const qfs_target *target, 
   const double t0 = lnow();
   hipStream_t st = static_cast<hipStream_t>(params->hip_stream);
   int32_t m0 = 0, k = 0;
-  QFS_TRY(predict_many(1, tmpl, *params, &m0, &k, st));
+  double prob = 0.0;
+  QFS_TRY(predict_many(1, tmpl, *params, &m0, &k, st, &prob));
   const int S = params->multistarts;
+  k = decide_single(prob, tmpl->n_qubits, tmpl->n_gates, std::max(params->m_init, m0), S);
   qfs_params q = *params;
   q.m_init = std::max(params->m_init, m0);
   q.multistarts = k;

@@ -206,7 +206,9 @@ def test_learned_gain_over_plain():
 def test_learned_single_problem_entry_with_shipped_weights():
     """The shipped weight file drives qfs_instantiate_learned (plain engine): the predicted
     M and start count agree between the single and batched prediction calls, a success is
-    a real solution, and the counters cover the runs that took place."""
+    a real solution, and the counters cover the runs that took place. One problem at a
+    time, the starts to keep follow the wall-time model: these 3-5 qubit problems leave
+    the device far from full, so all 16 starts run."""
     Q.qfs_mlp_load(PR.DEFAULT_WEIGHTS)
     probs = I.batched_problems(6, seed_base=0x5A17 + 42, n_range=(3, 5), L_range=(2, 6))
     m0s, ks = Q.qfs_predict_batch([(p["n"], p["pairs"]) for p in probs], dict(multistarts=16))
@@ -222,7 +224,7 @@ def test_learned_single_problem_entry_with_shipped_weights():
         say(f"  problem {i}: n={p['n']} L={len(p['pairs'])} M0={m0} k={ks[i]} -> "
             f"{info['reason_name']} fallback={info['fallback']} starts_run={info['starts_run']}")
         assert info["m_predicted"] == m0
-        assert info["starts_run"] == (16 if info["fallback"] else int(ks[i]))
+        assert info["starts_run"] == 16 and not info["fallback"]
         assert info["m_final"] >= m0 or info["fallback"]
         if info["reason_name"] == "SUCCESS":
             ok += 1
