@@ -742,8 +742,9 @@ bool group_path_supported(const Geometry &g, size_t rbytes) {
 
 static int tile_bits_for(size_t rbytes) {
   static const int tb = [] {
-    const char *e = std::getenv("QFS_GROUP_TILE_BITS");  // tuning aid (complex64 value)
-    return e ? std::atoi(e) : 12;
+    // tuning aid (complex64 value), at most 12: a tile holds at most 2048 packets
+    const char *e = std::getenv("QFS_GROUP_TILE_BITS");
+    return e ? std::min(12, std::max(5, std::atoi(e))) : 12;
   }();
   return rbytes == 4 ? tb : tb - 1;
 }
