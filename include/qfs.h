@@ -391,8 +391,12 @@ int qfs_instantiate_samples(const qfs_template *tmpl, const qfs_c128 *psi,
  * drawn from params->seed (role 3, stream = start, index 256 gate + D col + row of a
  * column-major Ginibre block). gates_out: device [L][D][D]. Precision FP64 or MIXED
  * (complex64 states, complex128 sweeps once the best running c_train < refine_below).
- * params->timing and full_unitary are not supported here (full_unitary: QFS_EINVAL).
- * Errors: QFS_EINVAL, QFS_EUNSUPPORTED, QFS_ENOMEM, QFS_EDEVICE. */
+ * params->timing and full_unitary are not supported here (full_unitary: QFS_EINVAL). When
+ * the starts' sets and B lists do not fit (device out of memory, or more than
+ * params->device_mem_budget bytes when that is set) the starts run as two halves,
+ * recursively, each with its own control loop (App. A), and the better result is returned
+ * (success first, then lower c_train; res->start_groups counts the groups).
+ * Errors: QFS_EINVAL, QFS_EUNSUPPORTED, QFS_ENOMEM (one start does not fit), QFS_EDEVICE. */
 int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi,
                           const qfs_c128 *phi, int32_t n_samples, int32_t n_val,
                           const qfs_params *params, const qfs_c128 *gates_in,

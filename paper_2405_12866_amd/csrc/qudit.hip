@@ -592,8 +592,8 @@ __global__ void k_qd_haar(uint64_t seed, int32_t start0, int32_t starts, int32_t
 // start); with drawn gates, a one-qudit gate's slot becomes v (x) I_d with v Haar on U(d)
 // from the d x d Ginibre block at indices 256 gate + d col + row of the start's stream.
 template <int d>
-__global__ void k_qd_kinds(uint64_t seed, int32_t starts, int32_t L, const int32_t *kinds, const c128 *fixed,
-                           int32_t drawn, c128 *out) {
+__global__ void k_qd_kinds(uint64_t seed, int32_t start0, int32_t starts, int32_t L, const int32_t *kinds,
+                           const c128 *fixed, int32_t drawn, c128 *out) {
   constexpr int D = d * d;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)starts * L) return;
@@ -606,7 +606,8 @@ __global__ void k_qd_kinds(uint64_t seed, int32_t starts, int32_t L, const int32
   if (kinds[k] != QFS_GATE_1Q || !drawn) return;
   c128 q[d][d];  // [col][row]
   for (int c = 0; c < d; ++c)
-    for (int r = 0; r < d; ++r) q[c][r] = complex_normal(seed, kRoleInit, (uint32_t)s, (uint64_t)k * 256u + (uint64_t)(c * d + r));
+    for (int r = 0; r < d; ++r)
+      q[c][r] = complex_normal(seed, kRoleInit, (uint32_t)(start0 + s), (uint64_t)k * 256u + (uint64_t)(c * d + r));
   for (int c = 0; c < d; ++c) {
     for (int rep = 0; rep < 2; ++rep)
       for (int o = 0; o < c; ++o) {
@@ -720,10 +721,22 @@ struct QdSweeper {
     return launch_dist_finalize(P, dpart.as<double>(), slots.as<int32_t>(), nslots, Mrows, out, st);
   }
 
+  size_t budget = 0;  // device bytes the sweeper may hold (0: as much as allocates)
+
   int alloc(int Mnew, int Mvnew) {
     M = Mnew;
     Mv = Mvnew;
     const size_t cb = sizeof(cx<R>);
+    if (budget) {
+      const size_t need = cb * set() * (2 + (size_t)std::max(L - 1, 1) * S + S) +
+                          (Mv > 0 ? cb * N * Mv * (2 + (size_t)S) : 0) +
+                          sizeof(c128) * (size_t)S * kQdMaxP * kQdMaxDD;
+      if (need > budget) {
+        set_error_detail("qudits: the sets and B lists of " + std::to_string(S) + " starts need " +
+                         std::to_string(need) + " bytes, above the device budget");
+        return QFS_ENOMEM;
+      }
+    }
     QFS_TRY(psi.alloc(cb * set()));
     QFS_TRY(phi.alloc(cb * set()));
     QFS_TRY(blist.alloc(cb * set() * (size_t)std::max(L - 1, 1) * S));
@@ -1029,6 +1042,7 @@ int qd_run(int d, const qfs_template *t, QdData &data, const qfs_params &p, c128
   w.g64 = g64;
   w.vst = vst;
   w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
+  w.budget = p.device_mem_budget;
   QFS_TRY(w.alloc(cs.M, n_val));
   QFS_TRY(data.load<R>(w));
   std::vector<int> active;
@@ -1136,46 +1150,50 @@ int qd_run(int d, const qfs_template *t, QdData &data, const qfs_params &p, c128
 
 // Multistart instantiation from initial gates (given or Haar-drawn) on the samples of
 // `data`, FP64 or MIXED with refinement.
-int qd_instantiate_impl(int d, const qfs_template *tmpl, QdData &data, const qfs_params &p,
-                        const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res, double t0) {
+// One group of starts [start0, start0 + S) with its own control loop (all starts when
+// the device memory holds them): the returned start's gates (host) and counters.
+struct QdGroupResult {
+  int reason = QFS_MAX_ITER, m_final = 0, sweeps = 0, restarts = 0, best = 0, m_total = 0, refined = 0;
+  double c_train = INFINITY, c_val = INFINITY, sweep_seconds = 0.0, amp_updates = 0.0;
+  int64_t start_sweeps = 0;
+  std::vector<qfs_c128> gates;
+};
+
+int qd_group(int d, const qfs_template *tmpl, const QdData &cfg, const qfs_params &p, const qfs_c128 *gates_in,
+             int start0, int S, double t0, QdGroupResult &r) {
   const int n = tmpl->n_qubits, L = tmpl->n_gates, D = d * d;
   const int64_t N = qd_pow(d, n);
-  if (p.multistarts < 1 || p.m_init < 1 || p.max_iter < 1 || p.plateau_window < 1 || !(p.beta >= 0 && p.beta <= 1) ||
-      (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) || p.full_unitary) {
-    set_error_detail("qudits: bad params");
-    return QFS_EINVAL;
-  }
   hipStream_t st = static_cast<hipStream_t>(p.hip_stream);
+  QdData data;  // the group's own sets (drawn sets are drawn again from the same streams)
+  data.psi = cfg.psi;
+  data.phi = cfg.phi;
+  data.n_train = cfg.n_train;
+  data.n_val = cfg.n_val;
+  data.tgt = cfg.tgt;
+  data.seed = cfg.seed;
+  data.m_val = cfg.m_val;
   data.d = d;
   data.n = n;
   data.N = N;
   data.st = st;
-  const int S = p.multistarts;
-  if (gates_in)
-    QFS_TRY(check_gates_unitary_n(gates_in, (size_t)S * L, D, "gates_in", st));
   DevBuf gates;
   QFS_TRY(gates.alloc(sizeof(c128) * (size_t)S * L * D * D));
   if (gates_in) {
-    QFS_HIP(hipMemcpyAsync(gates.ptr, gates_in, sizeof(c128) * (size_t)S * L * D * D, hipMemcpyDeviceToDevice, st));
+    QFS_HIP(hipMemcpyAsync(gates.ptr, gates_in + (size_t)start0 * L * D * D, sizeof(c128) * (size_t)S * L * D * D,
+                           hipMemcpyDeviceToDevice, st));
   } else {
     const int64_t tot = (int64_t)S * L;
     const dim3 grid((unsigned)((tot + 63) / 64));
     if (d == 2)
-      hipLaunchKernelGGL(k_qd_haar<2>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_haar<2>, grid, dim3(64), 0, st, p.seed, start0, S, L, gates.as<c128>());
     else if (d == 3)
-      hipLaunchKernelGGL(k_qd_haar<3>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_haar<3>, grid, dim3(64), 0, st, p.seed, start0, S, L, gates.as<c128>());
     else
-      hipLaunchKernelGGL(k_qd_haar<4>, grid, dim3(64), 0, st, p.seed, 0, S, L, gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_haar<4>, grid, dim3(64), 0, st, p.seed, start0, S, L, gates.as<c128>());
     QFS_HIP(hipGetLastError());
   }
   DevBuf dkinds;
   if (tmpl->kinds) {
-    bool any_fixed = false;
-    for (int k = 0; k < L; ++k) any_fixed |= tmpl->kinds[k] == QFS_GATE_FIXED;
-    if (any_fixed && !tmpl->fixed_gates) {
-      set_error_detail("qudits: constant gates need tmpl->fixed_gates");
-      return QFS_EINVAL;
-    }
     QFS_TRY(dkinds.alloc(sizeof(int32_t) * L));
     QFS_HIP(hipMemcpyAsync(dkinds.ptr, tmpl->kinds, sizeof(int32_t) * L, hipMemcpyHostToDevice, st));
     const int64_t tot = (int64_t)S * L;
@@ -1183,14 +1201,14 @@ int qd_instantiate_impl(int d, const qfs_template *tmpl, QdData &data, const qfs
     const c128 *fx = reinterpret_cast<const c128 *>(tmpl->fixed_gates);
     const int drawn = gates_in ? 0 : 1;
     if (d == 2)
-      hipLaunchKernelGGL(k_qd_kinds<2>, grid, dim3(64), 0, st, p.seed, S, L, dkinds.as<int32_t>(), fx, drawn,
-                         gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_kinds<2>, grid, dim3(64), 0, st, p.seed, start0, S, L, dkinds.as<int32_t>(), fx,
+                         drawn, gates.as<c128>());
     else if (d == 3)
-      hipLaunchKernelGGL(k_qd_kinds<3>, grid, dim3(64), 0, st, p.seed, S, L, dkinds.as<int32_t>(), fx, drawn,
-                         gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_kinds<3>, grid, dim3(64), 0, st, p.seed, start0, S, L, dkinds.as<int32_t>(), fx,
+                         drawn, gates.as<c128>());
     else
-      hipLaunchKernelGGL(k_qd_kinds<4>, grid, dim3(64), 0, st, p.seed, S, L, dkinds.as<int32_t>(), fx, drawn,
-                         gates.as<c128>());
+      hipLaunchKernelGGL(k_qd_kinds<4>, grid, dim3(64), 0, st, p.seed, start0, S, L, dkinds.as<int32_t>(), fx,
+                         drawn, gates.as<c128>());
     QFS_HIP(hipGetLastError());
   }
   DevBuf vstore;
@@ -1214,11 +1232,10 @@ int qd_instantiate_impl(int d, const qfs_template *tmpl, QdData &data, const qfs
   cs.m_total = cs.M;
   QFS_TRY(data.init(cs.M));
   bool refine = false;
-  int refined = 0;
   if (p.precision == QFS_PREC_MIXED) {
     QFS_TRY(qd_run<float>(d, tmpl, data, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
     if (refine) {
-      refined = 1;
+      r.refined = 1;
       QFS_TRY(qd_run<double>(d, tmpl, data, p, gates.as<c128>(), vstore.as<c128>(), S, cs, t0, refine));
     }
   } else {
@@ -1233,23 +1250,92 @@ int qd_instantiate_impl(int d, const qfs_template *tmpl, QdData &data, const qfs
       }
   }
   const int c = cs.chosen;
-  QFS_HIP(hipMemcpyAsync(gates_out, gates.as<c128>() + (size_t)c * L * D * D, sizeof(c128) * (size_t)L * D * D,
-                         hipMemcpyDeviceToDevice, st));
+  r.gates.resize((size_t)L * D * D);
+  QFS_HIP(hipMemcpyAsync(r.gates.data(), gates.as<c128>() + (size_t)c * L * D * D, sizeof(c128) * r.gates.size(),
+                         hipMemcpyDeviceToHost, st));
+  QFS_HIP(hipStreamSynchronize(st));
+  r.reason = cs.reason[c];
+  r.m_final = cs.M;
+  r.sweeps = (int32_t)cs.total[c];
+  r.restarts = cs.restarts;
+  r.best = start0 + c;
+  r.m_total = cs.m_total;
+  r.c_train = cs.ct[c];
+  r.c_val = cs.cv[c];
+  r.start_sweeps = cs.start_sweeps;
+  r.sweep_seconds = cs.sweep_seconds;
+  r.amp_updates = cs.amp_updates;
+  return QFS_OK;
+}
+
+// App. A: when the starts' sets and B lists do not fit the device (out of memory, or
+// params->device_mem_budget), the starts run as two halves, recursively, one after the
+// other, each with its own control loop.
+int qd_split(int d, const qfs_template *tmpl, const QdData &cfg, const qfs_params &p, const qfs_c128 *gates_in,
+             int start0, int S, double t0, std::vector<QdGroupResult> &results) {
+  QdGroupResult r;
+  const int rc = qd_group(d, tmpl, cfg, p, gates_in, start0, S, t0, r);
+  if (rc == QFS_ENOMEM && S > 1) {
+    (void)hipStreamSynchronize(static_cast<hipStream_t>(p.hip_stream));
+    (void)hipGetLastError();
+    const int h = S / 2;
+    QFS_TRY(qd_split(d, tmpl, cfg, p, gates_in, start0, h, t0, results));
+    return qd_split(d, tmpl, cfg, p, gates_in, start0 + h, S - h, t0, results);
+  }
+  if (rc != QFS_OK) return rc;
+  results.push_back(std::move(r));
+  return QFS_OK;
+}
+
+// Multistart instantiation from initial gates (given or Haar-drawn) on the samples of
+// `cfg`, FP64 or MIXED with refinement; the returned start is the best of the groups
+// (a success first, then the lower training cost).
+int qd_instantiate_impl(int d, const qfs_template *tmpl, const QdData &cfg, const qfs_params &p,
+                        const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res, double t0) {
+  const int L = tmpl->n_gates, D = d * d;
+  if (p.multistarts < 1 || p.m_init < 1 || p.max_iter < 1 || p.plateau_window < 1 || !(p.beta >= 0 && p.beta <= 1) ||
+      (p.precision != QFS_PREC_FP64 && p.precision != QFS_PREC_MIXED) || p.full_unitary) {
+    set_error_detail("qudits: bad params");
+    return QFS_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(p.hip_stream);
+  const int S = p.multistarts;
+  if (gates_in)
+    QFS_TRY(check_gates_unitary_n(gates_in, (size_t)S * L, D, "gates_in", st));
+  if (tmpl->kinds) {
+    bool any_fixed = false;
+    for (int k = 0; k < L; ++k) any_fixed |= tmpl->kinds[k] == QFS_GATE_FIXED;
+    if (any_fixed && !tmpl->fixed_gates) {
+      set_error_detail("qudits: constant gates need tmpl->fixed_gates");
+      return QFS_EINVAL;
+    }
+  }
+  std::vector<QdGroupResult> results;
+  QFS_TRY(qd_split(d, tmpl, cfg, p, gates_in, 0, S, t0, results));
+  size_t bi = 0;
+  for (size_t i = 1; i < results.size(); ++i) {
+    const bool si = results[i].reason == QFS_SUCCESS, sb = results[bi].reason == QFS_SUCCESS;
+    if ((si && !sb) || (si == sb && results[i].c_train < results[bi].c_train)) bi = i;
+  }
+  const QdGroupResult &r = results[bi];
+  QFS_HIP(hipMemcpyAsync(gates_out, r.gates.data(), sizeof(c128) * r.gates.size(), hipMemcpyHostToDevice, st));
   QFS_HIP(hipStreamSynchronize(st));
   std::memset(res, 0, sizeof(*res));
-  res->reason = cs.reason[c];
-  res->m_final = cs.M;
-  res->sweeps = (int32_t)cs.total[c];
-  res->restarts = cs.restarts;
-  res->best_start = c;
-  res->m_total = cs.m_total;
-  res->start_groups = 1;
-  res->refined = refined;
-  res->c_train = cs.ct[c];
-  res->c_val = cs.cv[c];
-  res->start_sweeps = cs.start_sweeps;
-  res->sweep_seconds = cs.sweep_seconds;
-  res->amp_updates = cs.amp_updates;
+  res->reason = r.reason;
+  res->m_final = r.m_final;
+  res->sweeps = r.sweeps;
+  res->restarts = r.restarts;
+  res->best_start = r.best;
+  res->m_total = r.m_total;
+  res->start_groups = (int32_t)results.size();
+  res->refined = r.refined;
+  res->c_train = r.c_train;
+  res->c_val = r.c_val;
+  for (const auto &x : results) {
+    res->start_sweeps += x.start_sweeps;
+    res->sweep_seconds += x.sweep_seconds;
+    res->amp_updates += x.amp_updates;
+  }
   res->seconds = qd_now() - t0;
   return QFS_OK;
 }

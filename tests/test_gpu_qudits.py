@@ -445,3 +445,39 @@ def test_qudit_kinds_rejected_when_malformed():
     with pytest.raises(Q.QfsError) as e:
         Q.qfs_qudit_instantiate(3, 3, [(0, 1)], psi, psi, params=Q.qfs_default_params(), kinds=[7])
     assert e.value.code == Q.QFS_EINVAL
+
+
+def test_qutrit_starts_split_under_a_memory_budget():
+    """App. A: when the starts do not fit the device budget they run as two halves, each
+    with its own control loop, and the better result is returned. A budget that holds two
+    of four starts gives two groups; each group follows the oracle run of its own starts
+    (starts 2, 3 through their Haar draws as initial gates)."""
+    say("qutrit multistart split under a budget")
+    n = 3
+    g = np.random.default_rng(97)
+    pairs = [(0, 1), (1, 2), (0, 1)]
+    tg = np.stack([I.haar_unitary(9, g) for _ in pairs])
+    psi = _samples(3, n, 27, g)
+    phi = O.qd_apply_circuit(3, n, psi, pairs, tg)
+    p = O.default_params(multistarts=4, m_init=3, seed=7, dist_tol=1e-11, max_iter=300)
+    g_gpu, got = Q.qfs_qudit_instantiate(3, n, pairs, dev(psi), dev(phi), n_val=9,
+                                         params=dict(p, precision=Q.QFS_PREC_FP64, device_mem_budget=800_000))
+    assert got["start_groups"] == 2, got
+    halves = []
+    for s0 in (0, 2):
+        gi = np.stack([np.stack([O.qd_haar_gate(3, 7, s, k) for k in range(len(pairs))]) for s in (s0, s0 + 1)])
+        gr, ir = O.qd_instantiate(3, n, pairs, psi, phi, n_val=9, params=dict(p, multistarts=2), gates_in=gi)
+        ir["best_start"] += s0
+        halves.append((gr, ir))
+    succ = [h[1]["reason_name"] == "SUCCESS" for h in halves]
+    pick = 1 if (succ[1] and not succ[0]) or (succ[0] == succ[1] and halves[1][1]["c_train"] < halves[0][1]["c_train"]) else 0
+    g_ref, ref = halves[pick]
+    say(f"  halves {[h[1]['reason_name'] for h in halves]}; device {got['reason_name']} start={got['best_start']}")
+    for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final"):
+        assert got[k] == ref[k], (k, got, ref)
+    assert abs(got["c_train"] - ref["c_train"]) <= 1e-9 * max(ref["c_train"], 1e-12) + 1e-20
+    assert np.max(np.abs(host(g_gpu) - g_ref)) < 1e-8
+    # without the budget all four starts run as one group
+    _, one = Q.qfs_qudit_instantiate(3, n, pairs, dev(psi), dev(phi), n_val=9,
+                                     params=dict(p, precision=Q.QFS_PREC_FP64))
+    assert one["start_groups"] == 1
