@@ -280,7 +280,8 @@ def qudits_leg(dev, steps):
     (M from 9, doubling up to 144 against 9 validation samples) on 6 and 7 qutrits
     (brickwork, 4 sublayers), 16 starts, App. A rules, MIXED, same seed. (c) Sweeps of 5
     ququarts (d = 4, 16 x 16 gates), as (a). (d) Gate kinds: time to 1e-8 of a 6-qutrit
-    template of one-qutrit gates around constant CSUM gates, states drawn on the device."""
+    template of one-qutrit gates around constant CSUM gates, states drawn on the device.
+    (e) 64 qutrit problems through the batched entry against one at a time."""
     import numpy as np
     import torch
 
@@ -386,6 +387,37 @@ def qudits_leg(dev, steps):
                                   "seconds": round(time.perf_counter() - t0, 4), "reason": r["reason_name"],
                                   "m_final": r["m_final"], "sweeps": r["sweeps"], "c_train": r["c_train"],
                                   "c_val": r["c_val"]}
+    # (e) problems side by side: 64 qutrit problems (4-6 qutrits, 4-10 random-pair gates,
+    # targets from their templates, states drawn on the device), 16 starts each, MIXED,
+    # App. A rules from M = 9: the batched entry against the same problems one at a time
+    rng = np.random.default_rng(0x5A17 + 12)
+    bprobs = []
+    for i in range(64):
+        nq = int(rng.integers(4, 7))
+        prs = I.random_pair_template(nq, int(rng.integers(4, 11)), rng)
+        tgb = torch.as_tensor(np.stack([I.haar_unitary(9, rng) for _ in prs])).to(dev)
+        bprobs.append(dict(n=nq, pairs=prs, target_pairs=prs, target_gates=tgb))
+    pb = Q.qfs_default_params(seed=43, m_init=9, time_budget_s=30.0)
+    Q.qfs_qudit_instantiate_batch(3, bprobs[:4], pb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rb = Q.qfs_qudit_instantiate_batch(3, bprobs, pb)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ok_one = 0
+    for pr in bprobs:
+        _, r1 = Q.qfs_qudit_instantiate_target(3, pr["n"], pr["pairs"], target_pairs=pr["target_pairs"],
+                                               target_gates=pr["target_gates"], params=pb)
+        ok_one += r1["reason_name"] == "SUCCESS"
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    out["batched_qutrits"] = {"workload": "64 qutrit problems (4-6 qutrits, 4-10 random-pair two-qutrit gates, "
+                                          "targets from the templates, states drawn on the device), 16 starts, "
+                                          "MIXED, App. A rules from M = 9",
+                              "batched_s": round(t_batch, 3), "one_at_a_time_s": round(t_one, 3),
+                              "successes": sum(r["reason_name"] == "SUCCESS" for r in rb),
+                              "successes_one_at_a_time": ok_one, "speedup": round(t_one / t_batch, 2)}
     return out
 
 

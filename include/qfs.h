@@ -417,6 +417,17 @@ int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_
                                  const qfs_params *params, const qfs_c128 *gates_in,
                                  qfs_c128 *gates_out, qfs_result *res);
 
+/* P qudit problems (templates tmpls[i], targets targets[i] in any form) with the same
+ * params, each as qfs_qudit_instantiate_target, run side by side on up to eight streams of
+ * their own (the qudit path is bound by the latency of its small kernels, so problems on
+ * separate streams fill the device together); each problem's sweeps keep to its stream.
+ * gates_out: host array of P device pointers ([L_i][D][D] each); res: host [P]. The
+ * caller's stream (params->hip_stream) is synchronised first. On an error no further
+ * problem starts and the first error is returned (its detail names the problem). */
+int qfs_qudit_instantiate_batch(int32_t d, int32_t P, const qfs_template *tmpls,
+                                const qfs_target *targets, const qfs_params *params,
+                                qfs_c128 *const *gates_out, qfs_result *res);
+
 /* One qudit sweep for `starts` starts sharing a training set, as qfs_sweep: psi, phi
  * device [M][N]; kinds host [L] or NULL (constant gates are the gates' own slots, applied
  * and kept); gates device [starts][L][D][D] updated in place; c_train host [starts] (Eq. 9

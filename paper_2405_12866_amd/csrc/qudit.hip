@@ -9,10 +9,12 @@
 // Kernels are templated on the state precision R and on d; the environment partials,
 // the polar update and the costs are FP64.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "philox.h"
@@ -656,6 +658,7 @@ struct QdSweeper {
   // reduction and polar update overlap the other half's propagation and reduction
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  bool one_stream = false;  // keep the whole sweep on `st` (problems run side by side)
 
   QdSweeper() = default;
   QdSweeper(const QdSweeper &) = delete;
@@ -784,7 +787,7 @@ struct QdSweeper {
       const char *e = std::getenv("QFS_BWD_SPLIT");  // 0: one stream for the backward pass
       return !(e && std::atoi(e) == 0);
     }();
-    const bool split = split_ok && nslots >= 2;
+    const bool split = split_ok && !one_stream && nslots >= 2;
     if (split && !side) {
       QFS_TRY(pool_stream(2, &side));
       QFS_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
@@ -935,6 +938,7 @@ struct QdData {
   uint64_t seed = 0;
   int m_val = 0;
   int M = 0, Mv = 0, generation = 0;
+  bool one_stream = false;  // the sweeps keep to the call's stream
   DevBuf tpsi, tphi, vpsi, vphi, work, slot0;
 
   bool drawn() const { return tgt != nullptr; }
@@ -1043,6 +1047,7 @@ int qd_run(int d, const qfs_template *t, QdData &data, const qfs_params &p, c128
   w.vst = vst;
   w.beta = effective_beta(p.beta, p.beta_normalized != 0, cs.M);
   w.budget = p.device_mem_budget;
+  w.one_stream = data.one_stream;
   QFS_TRY(w.alloc(cs.M, n_val));
   QFS_TRY(data.load<R>(w));
   std::vector<int> active;
@@ -1172,6 +1177,7 @@ int qd_group(int d, const qfs_template *tmpl, const QdData &cfg, const qfs_param
   data.tgt = cfg.tgt;
   data.seed = cfg.seed;
   data.m_val = cfg.m_val;
+  data.one_stream = cfg.one_stream;
   data.d = d;
   data.n = n;
   data.N = N;
@@ -1340,47 +1346,18 @@ int qd_instantiate_impl(int d, const qfs_template *tmpl, const QdData &cfg, cons
   return QFS_OK;
 }
 
-}  // namespace
-}  // namespace qfs
+constexpr int kQdBatchStreams = 8;  // problems run side by side by the batched entry
 
-using namespace qfs;
-
-extern "C" {
-
-int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi, const qfs_c128 *phi,
-                          int32_t n_samples, int32_t n_val, const qfs_params *params,
-                          const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res) {
-  const double t0 = qd_now();
-  QFS_TRY(qd_validate(d, tmpl));
-  if (!params || !psi || !phi || !gates_out || !res) {
-    set_error_detail("qudits: null argument");
-    return QFS_EINVAL;
-  }
-  const int64_t N = qd_pow(d, tmpl->n_qubits);
-  const int n_train = n_samples - n_val;
-  if (n_val < 0 || n_train < 1 || n_train > N) {
-    set_error_detail("qudits: bad sample counts");
-    return QFS_EINVAL;
-  }
-  QdData data;
-  data.psi = psi;
-  data.phi = phi;
-  data.n_train = n_train;
-  data.n_val = n_val;
-  return qd_instantiate_impl(d, tmpl, data, *params, gates_in, gates_out, res, t0);
-}
-
-int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_target *target,
-                                 const qfs_params *params, const qfs_c128 *gates_in, qfs_c128 *gates_out,
-                                 qfs_result *res) {
+// One problem: argument checks, then the multistart run on the samples or drawn states of
+// its target. one_stream keeps every sweep on the call's stream (no second stream for half
+// the starts), so problems on several streams do not share one.
+int qd_entry(int d, const qfs_template *tmpl, const qfs_target *target, const qfs_params *params,
+             const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res, bool one_stream) {
   const double t0 = qd_now();
   if (!target) {
     set_error_detail("qudits: null target");
     return QFS_EINVAL;
   }
-  if (target->kind == QFS_TARGET_SAMPLES)
-    return qfs_qudit_instantiate(d, tmpl, target->psi, target->phi, target->n_samples, target->n_val, params,
-                                 gates_in, gates_out, res);
   QFS_TRY(qd_validate(d, tmpl));
   if (!params || !gates_out || !res) {
     set_error_detail("qudits: null argument");
@@ -1388,6 +1365,20 @@ int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_
   }
   const int n = tmpl->n_qubits;
   const int64_t N = qd_pow(d, n);
+  QdData data;
+  data.one_stream = one_stream;
+  if (target->kind == QFS_TARGET_SAMPLES) {
+    const int n_train = target->n_samples - target->n_val;
+    if (!target->psi || !target->phi || target->n_val < 0 || n_train < 1 || n_train > N) {
+      set_error_detail(!target->psi || !target->phi ? "qudits: null argument" : "qudits: bad sample counts");
+      return QFS_EINVAL;
+    }
+    data.psi = target->psi;
+    data.phi = target->phi;
+    data.n_train = n_train;
+    data.n_val = target->n_val;
+    return qd_instantiate_impl(d, tmpl, data, *params, gates_in, gates_out, res, t0);
+  }
   if (target->kind == QFS_TARGET_DENSE) {
     if (!target->U || N > (int64_t(1) << 16)) {
       set_error_detail("qudits: a dense target needs U and d^n <= 2^16");
@@ -1410,11 +1401,81 @@ int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_
     set_error_detail("qudits: unknown target kind");
     return QFS_EINVAL;
   }
-  QdData data;
   data.tgt = target;
   data.seed = params->seed;
   data.m_val = params->m_val;
   return qd_instantiate_impl(d, tmpl, data, *params, gates_in, gates_out, res, t0);
+}
+
+}  // namespace
+}  // namespace qfs
+
+using namespace qfs;
+
+extern "C" {
+
+int qfs_qudit_instantiate(int32_t d, const qfs_template *tmpl, const qfs_c128 *psi, const qfs_c128 *phi,
+                          int32_t n_samples, int32_t n_val, const qfs_params *params,
+                          const qfs_c128 *gates_in, qfs_c128 *gates_out, qfs_result *res) {
+  qfs_target t{};
+  t.kind = QFS_TARGET_SAMPLES;
+  t.psi = psi;
+  t.phi = phi;
+  t.n_samples = n_samples;
+  t.n_val = n_val;
+  return qd_entry(d, tmpl, &t, params, gates_in, gates_out, res, false);
+}
+
+int qfs_qudit_instantiate_target(int32_t d, const qfs_template *tmpl, const qfs_target *target,
+                                 const qfs_params *params, const qfs_c128 *gates_in, qfs_c128 *gates_out,
+                                 qfs_result *res) {
+  return qd_entry(d, tmpl, target, params, gates_in, gates_out, res, false);
+}
+
+int qfs_qudit_instantiate_batch(int32_t d, int32_t P, const qfs_template *tmpls, const qfs_target *targets,
+                                const qfs_params *params, qfs_c128 *const *gates_out, qfs_result *res) {
+  if (P < 1 || !tmpls || !targets || !params || !gates_out || !res) {
+    set_error_detail("qudits batch: need P >= 1 and every array");
+    return QFS_EINVAL;
+  }
+  int dev = 0;
+  QFS_HIP(hipGetDevice(&dev));
+  // the caller's stream first: work it holds for the inputs comes before the problems
+  QFS_HIP(hipStreamSynchronize(static_cast<hipStream_t>(params->hip_stream)));
+  const int W = std::min<int>(P, kQdBatchStreams);
+  std::atomic<int> next{0};
+  std::vector<int> rc(W, QFS_OK);
+  std::vector<std::string> detail(W);
+  auto worker = [&](int w) {
+    hipStream_t st = nullptr;
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      rc[w] = QFS_EDEVICE;
+      detail[w] = "qudits batch: no stream for a worker";
+      return;
+    }
+    qfs_params q = *params;
+    q.hip_stream = st;
+    for (int i = next.fetch_add(1); i < P; i = next.fetch_add(1)) {
+      const int r = qd_entry(d, &tmpls[i], &targets[i], &q, nullptr, gates_out[i], &res[i], true);
+      if (r != QFS_OK) {
+        rc[w] = r;
+        detail[w] = "problem " + std::to_string(i) + ": " + qfs_last_error_detail();
+        next.store(P);  // no new problems once one has failed
+        break;
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  };
+  std::vector<std::thread> pool;
+  for (int w = 0; w < W; ++w) pool.emplace_back(worker, w);
+  for (auto &t : pool) t.join();
+  for (int w = 0; w < W; ++w)
+    if (rc[w] != QFS_OK) {
+      set_error_detail(detail[w]);
+      return rc[w];
+    }
+  return QFS_OK;
 }
 
 int qfs_qudit_sweep(int32_t d, int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, int32_t M,

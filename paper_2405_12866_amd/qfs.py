@@ -76,7 +76,7 @@ EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_
            "qfs_mlp_load", "qfs_mlp_forward", "qfs_mlp_grad", "qfs_mlp_train", "qfs_predict_m",
            "qfs_predict_batch", "qfs_instantiate_learned", "qfs_instantiate_batch_learned",
            "qfs_instantiate_batch_ex", "qfs_qudit_instantiate", "qfs_qudit_instantiate_target",
-           "qfs_qudit_sweep"]
+           "qfs_qudit_instantiate_batch", "qfs_qudit_sweep"]
 
 
 def load():
@@ -143,6 +143,9 @@ def load():
         lib.qfs_qudit_instantiate_target.argtypes = [I32, C.POINTER(Template), C.POINTER(Target),
                                                      C.POINTER(Params), P, P, C.POINTER(Result)]
         lib.qfs_qudit_sweep.argtypes = [I32, I32, I32, P, P, I32, P, P, I32, P, I32, D, P, P]
+        lib.qfs_qudit_instantiate_batch.argtypes = [I32, I32, C.POINTER(Template), C.POINTER(Target),
+                                                    C.POINTER(Params), C.POINTER(C.c_void_p),
+                                                    C.POINTER(Result)]
         for name in EXPORTS:
             if name not in ("qfs_strerror", "qfs_last_error_detail", "qfs_version",
                             "qfs_default_params"):
@@ -607,6 +610,29 @@ def qfs_qudit_instantiate_target(d, n, pairs, *, U=None, target_pairs=None, targ
                                                C.c_void_p(out.data_ptr()), C.byref(res)),
            "qfs_qudit_instantiate_target")
     return out, _info(res)
+
+
+def qfs_qudit_instantiate_batch(d, problems, params=None):
+    """Qudit problems side by side: ``problems`` is a list of dicts with n, pairs, optional
+    kinds / fixed_gates, and one target form (U; target_pairs + target_gates; psi + phi +
+    n_val). Returns (list of gates [L, d^2, d^2] device tensors, list of result dicts)."""
+    import torch
+    P = len(problems)
+    keep = []
+    tmpls = (Template * P)()
+    tgts = (Target * P)()
+    outs = []
+    dev = None
+    for i, pr in enumerate(problems):
+        tmpls[i] = _template(pr["n"], pr["pairs"], keep, pr.get("kinds"), pr.get("fixed_gates"))
+        dev = _fill_target(tgts[i], pr["n"], keep, **{k: pr[k] for k in _TARGET_KEYS if k in pr})
+        outs.append(torch.empty((tmpls[i].n_gates, d * d, d * d), dtype=torch.complex128, device=dev))
+    ptrs = (C.c_void_p * P)(*[o.data_ptr() for o in outs])
+    res = (Result * P)()
+    par = _params(params)
+    _check(load().qfs_qudit_instantiate_batch(d, P, tmpls, tgts, C.byref(par), ptrs, res),
+           "qfs_qudit_instantiate_batch")
+    return outs, [_info(r) for r in res]
 
 
 def qfs_state_distance(n, x, y):

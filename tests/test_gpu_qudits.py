@@ -481,3 +481,37 @@ def test_qutrit_starts_split_under_a_memory_budget():
     _, one = Q.qfs_qudit_instantiate(3, n, pairs, dev(psi), dev(phi), n_val=9,
                                      params=dict(p, precision=Q.QFS_PREC_FP64))
     assert one["start_groups"] == 1
+
+
+def test_qudit_batch_equals_one_at_a_time():
+    """The batched qudit entry runs problems side by side on streams of their own; each
+    problem's result equals that of the single entry with the same params (the same
+    kernels on the same starts): circuit targets with drawn states, a fixed sample set,
+    and a gate-kinds template."""
+    say("qudit batch vs single entries")
+    g = np.random.default_rng(98)
+    probs = []
+    for n, L, seed in ((3, 3, 1), (4, 4, 2), (3, 5, 3), (5, 4, 4)):
+        pairs = I.random_pair_template(n, L, np.random.default_rng(seed))
+        tg = np.stack([I.haar_unitary(9, g) for _ in pairs])
+        probs.append(dict(n=n, pairs=pairs, target_pairs=pairs, target_gates=dev(tg)))
+    psi = _samples(3, 3, 27, g)
+    tg = np.stack([I.haar_unitary(9, g) for _ in range(3)])
+    phi = O.qd_apply_circuit(3, 3, psi, [(0, 1), (1, 2), (0, 2)], tg)
+    probs.append(dict(n=3, pairs=[(0, 1), (1, 2), (0, 2)], psi=dev(psi), phi=dev(phi), n_val=9))
+    fixed = np.stack([_csum(3)] * len(KINDS))
+    probs.append(dict(n=3, pairs=KIND_PAIRS, kinds=KINDS, fixed_gates=dev(fixed), target_pairs=KIND_PAIRS,
+                      target_gates=dev(_kind_slots(3, KINDS, g))))
+    p = Q.qfs_default_params(multistarts=4, m_init=3, seed=17, dist_tol=1e-10, max_iter=300,
+                             precision=Q.QFS_PREC_FP64)
+    gb, rb = Q.qfs_qudit_instantiate_batch(3, probs, p)
+    for i, pr in enumerate(probs):
+        tkeys = {k: pr[k] for k in ("target_pairs", "target_gates", "psi", "phi", "n_val") if k in pr}
+        gs, rs = Q.qfs_qudit_instantiate_target(3, pr["n"], pr["pairs"], params=p, kinds=pr.get("kinds"),
+                                                fixed_gates=pr.get("fixed_gates"), **tkeys)
+        say(f"  problem {i}: {rs['reason_name']} sweeps={rs['sweeps']} batch {rb[i]['reason_name']} "
+            f"sweeps={rb[i]['sweeps']}")
+        for k in ("reason_name", "best_start", "sweeps", "restarts", "m_final"):
+            assert rb[i][k] == rs[k], (i, k, rb[i], rs)
+        assert abs(rb[i]["c_train"] - rs["c_train"]) <= 1e-12 * max(rs["c_train"], 1e-12) + 1e-24
+        assert np.max(np.abs(host(gb[i]) - host(gs))) < 1e-12
