@@ -194,3 +194,16 @@ def test_qudit_target_arguments_rejected_without_device_work():
         lib.qfs_default_params(C.byref(p))
         setattr(p, field, bad)
         assert call(3, tmpl, dense, p) == Q.QFS_EINVAL, field
+
+
+def test_qudit_batch_arguments_rejected_without_device_work():
+    lib = Q.load()
+    par = Q.Params()
+    lib.qfs_default_params(C.byref(par))
+    tm = (Q.Template * 1)()
+    tg = (Q.Target * 1)()
+    ptrs = (C.c_void_p * 1)(None)
+    res = (Q.Result * 1)()
+    assert lib.qfs_qudit_instantiate_batch(3, 0, tm, tg, C.byref(par), ptrs, res) == Q.QFS_EINVAL
+    assert lib.qfs_qudit_instantiate_batch(3, 1, None, tg, C.byref(par), ptrs, res) == Q.QFS_EINVAL
+    assert lib.qfs_qudit_instantiate_batch(3, 1, tm, tg, None, ptrs, res) == Q.QFS_EINVAL
