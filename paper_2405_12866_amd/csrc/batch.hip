@@ -756,10 +756,8 @@ int launch_batch_gates(BProb *probs_dev, const int32_t *prob_of, const int32_t *
 
 template <typename R, int NT>
 static int launch_sweep_t(const BatchArgs &a, int grid, size_t lds, hipStream_t s) {
-  if (lds > 64 * 1024) {
-    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch_sweep<R, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  }
+  static size_t attr = 0;
+  QFS_TRY(ensure_dynamic_lds(reinterpret_cast<const void *>(&k_batch_sweep<R, NT>), lds, &attr));
   hipLaunchKernelGGL((k_batch_sweep<R, NT>), dim3(grid), dim3(NT), lds, s, a);
   QFS_HIP(hipGetLastError());
   return QFS_OK;

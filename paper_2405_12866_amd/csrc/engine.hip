@@ -34,6 +34,16 @@ int pool_stream(int index, hipStream_t *out) {
   return QFS_OK;
 }
 
+int ensure_dynamic_lds(const void *fn, size_t bytes, size_t *have) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (bytes > 64 * 1024 && bytes > *have) {
+    QFS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    *have = bytes;
+  }
+  return QFS_OK;
+}
+
 namespace {
 
 enum { kClsStep = 0, kClsForward = 1, kClsDist = 2, kClsPolar = 3, kClasses = 4 };

@@ -867,10 +867,7 @@ int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *
   size_t &ab = attr[sizeof(R) == 4 ? 0 : 1][dist ? 1 : 0];
   const void *fn = dist ? reinterpret_cast<const void *>(k_bwd_group<R, true>)
                         : reinterpret_cast<const void *>(k_bwd_group<R, false>);
-  if (lds > 64 * 1024 && lds > ab) {
-    QFS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ab = lds;
-  }
+  QFS_TRY(ensure_dynamic_lds(fn, lds, &ab));
   const int64_t tiles = (int64_t)g.nch << A.nX;
   const int P = (int)std::min<int64_t>({tiles, (int64_t)std::max(1, pstride),
                                          (int64_t)std::max(1, blocks_per_start)});
@@ -989,11 +986,7 @@ int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef 
   const int threads = items >= 1024 ? 1024 : 512;
   auto go = [&](auto kernel) -> int {
     static size_t attr = 0;
-    if (lds > 64 * 1024 && lds > attr) {
-      QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      attr = lds;
-    }
+    QFS_TRY(ensure_dynamic_lds(reinterpret_cast<const void *>(kernel), lds, &attr));
     hipLaunchKernelGGL(kernel, dim3(gx * nz, nslots, 1), dim3(threads), lds, s, a, b, nz, g.n, g.logC, plan_dev,
                        ngroups, gslot_dev, static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, L,
                        gates_in_lds);

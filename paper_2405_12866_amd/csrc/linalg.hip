@@ -213,12 +213,8 @@ __global__ void k_zero_lower(int m, c128 *G) {
 
 static int cholesky_upper_blocked(int m, c128 *G, int *flag, hipStream_t s) {
   constexpr size_t kPanelLds = 144 * 1024;
-  static bool attr_set = false;
-  if (!attr_set) {
-    QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_chol_panel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPanelLds));
-    attr_set = true;
-  }
+  static size_t attr = 0;
+  QFS_TRY(ensure_dynamic_lds(reinterpret_cast<const void *>(&k_chol_panel), kPanelLds, &attr));
   const c128 one = cmake(1.0, 0.0), mone = cmake(-1.0, 0.0);
   for (int j = 0; j < m;) {
     const int w = m - j;

@@ -143,6 +143,10 @@ struct DevBuf {
 // Random numbers (rng.hip). Philox roles of the drawn sets: training states, validation
 // states (stream = the validation set's generation), initial gates (stream = start).
 enum { kRoleTrain = 1, kRoleVal = 2, kRoleInit = 3 };
+// Raise kernel fn's dynamic-LDS limit to at least `bytes` (above 64 KB it must be asked
+// for per kernel); *have caches what was set. Serialised across threads: problems may be
+// run from several host threads at once.
+int ensure_dynamic_lds(const void *fn, size_t bytes, size_t *have);
 int launch_ginibre(int64_t rows, int64_t col0, int64_t col1, int64_t ld, uint64_t seed,
                    uint32_t role, uint32_t stream, c128 *A, hipStream_t s);
 int launch_haar_gates(uint64_t seed, int32_t start0, int32_t starts, int32_t L, c128 *out,

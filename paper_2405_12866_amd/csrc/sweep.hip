@@ -1065,11 +1065,7 @@ int launch_forward_fused(const Geometry &g, const Geometry *gv, const int32_t *p
     // both sizes share this lambda's instantiation)
     static size_t attr_bytes[2] = {0, 0};
     size_t &ab = attr_bytes[threads == 1024 ? 1 : 0];
-    if (lds > 64 * 1024 && lds > ab) {
-      QFS_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      ab = lds;
-    }
+    QFS_TRY(ensure_dynamic_lds(reinterpret_cast<const void *>(kernel), lds, &ab));
     hipLaunchKernelGGL(kernel, dim3(gx * nz, nslots, 1), dim3(threads), lds, s, a, b, nz, g.n, g.logC, pairs_dev,
                        static_cast<const cx<R> *>(gates.gR), gates.gstride, slot_to_start, coalesce_b,
                        kinds_dev, bneed_dev);
