@@ -65,15 +65,13 @@ int ceil_log2(int64_t x) {
 int master_ld(int M) { return 1 << std::max(1, ceil_log2(std::max(M, 2))); }
 
 size_t lds_max_bytes() {
-  static size_t cached = 0;
-  if (cached == 0) {
+  static const size_t cached = [] {  // (initialised once, thread-safe)
     int dev = 0, v = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-      cached = (size_t)v;
-    else
-      cached = 64 * 1024;
-  }
+      return (size_t)v;
+    return (size_t)64 * 1024;
+  }();
   return cached;
 }
 
