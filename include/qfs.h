@@ -29,6 +29,7 @@
 #ifndef QFS_H
 #define QFS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -56,6 +57,16 @@ const char *qfs_strerror(int code);
 const char *qfs_last_error_detail(void);
 /* Library version string. */
 const char *qfs_version(void);
+/* Device memory kept between calls. When a call of qfs_instantiate (and of the entry
+ * points built on it: qfs_instantiate_samples, the learned single-problem entry) ends, the
+ * library keeps its device buffers, up to a quarter of the device's memory, and reuses
+ * them in later calls that need buffers of the same sizes, instead of freeing and
+ * allocating them again. An allocation that fails frees the kept buffers first, and the
+ * free-memory budget of a call counts them as free. This frees the buffers kept for the
+ * current device and stores their total size in *bytes_freed (may be null). Blocks are
+ * kept only once the device has finished with them, so it may be called at any time, from
+ * any thread. Returns QFS_OK or QFS_EDEVICE. */
+int qfs_release_device_cache(size_t *bytes_freed);
 
 /* ---------------------------------------------------------------- problem */
 /* Gate kinds (Sec. 2.1: QFactor updates gates of any size directly as unitaries;

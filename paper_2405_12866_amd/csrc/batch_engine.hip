@@ -251,8 +251,12 @@ int qfs::batch_instantiate(int32_t P, const qfs_template *tmpl, const qfs_target
   }
   // ---------------------------------------------------------------- device memory
   size_t fr = 0, tot = 0;
+  int dev = 0;
   QFS_HIP(hipMemGetInfo(&fr, &tot));
-  const size_t budget = p.device_mem_budget ? p.device_mem_budget : (size_t)(0.9 * (double)fr);
+  QFS_HIP(hipGetDevice(&dev));
+  // (blocks the single-problem engine caches are freed on demand by DevBuf::alloc)
+  const size_t budget =
+      p.device_mem_budget ? p.device_mem_budget : (size_t)(0.9 * (double)(fr + device_cache_held(dev)));
   const size_t njobs_all = (size_t)P * S;
   const size_t need = c128s * sizeof(c128) + ints * 4 + njobs_all * (sizeof(BJob) + 8) + P * sizeof(BProb);
   if (need > budget) {

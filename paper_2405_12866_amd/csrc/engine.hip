@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -42,6 +43,83 @@ int ensure_dynamic_lds(const void *fn, size_t bytes, size_t *have) {
     *have = bytes;
   }
   return QFS_OK;
+}
+
+// Device blocks kept between calls of the engine, by device and exact size. hipMalloc of
+// the large working sets and hipFree (which drains the device) otherwise cost several
+// hundred microseconds each in every call, during which the device idles. The cache holds
+// at most a quarter of the device's memory; blocks beyond that are freed.
+namespace {
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<std::pair<int, size_t>, void *> blocks;
+  std::map<int, size_t> held;
+};
+BlockCache &block_cache() {
+  static BlockCache *c = new BlockCache;  // never destroyed: no HIP calls at process exit
+  return *c;
+}
+bool cache_poison() {
+  // debugging aid: cached blocks are filled with 0xff bytes (NaN for every float type), so
+  // that code reading a block before writing it shows up
+  static const bool on = [] {
+    const char *e = std::getenv("QFS_CACHE_POISON");
+    return e && std::atoi(e) != 0;
+  }();
+  return on;
+}
+}  // namespace
+
+void *device_cache_take(int dev, size_t bytes) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.blocks.find({dev, bytes});
+  if (it == c.blocks.end()) return nullptr;
+  void *p = it->second;
+  c.blocks.erase(it);
+  c.held[dev] -= bytes;
+  return p;
+}
+
+size_t device_cache_held(int dev) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.held.find(dev);
+  return it == c.held.end() ? 0 : it->second;
+}
+
+size_t device_cache_trim(int dev) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  size_t freed = 0;
+  for (auto it = c.blocks.lower_bound({dev, 0}); it != c.blocks.end() && it->first.first == dev;) {
+    (void)hipFree(it->second);
+    freed += it->first.second;
+    it = c.blocks.erase(it);
+  }
+  c.held[dev] -= freed;
+  return freed;
+}
+
+// Takes idle blocks (the device has drained since their last use) of device dev.
+static void device_cache_put(int dev, std::vector<std::pair<void *, size_t>> &blks) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    tot = 0;
+  }
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto &b : blks) {
+    if (c.held[dev] + b.second > tot / 4) {
+      (void)hipFree(b.first);
+      continue;
+    }
+    if (cache_poison() && hipMemset(b.first, 0xff, b.second) != hipSuccess) (void)hipGetLastError();
+    c.blocks.emplace(std::make_pair(dev, b.second), b.first);
+    c.held[dev] += b.second;
+  }
+  blks.clear();
 }
 
 namespace {
@@ -109,9 +187,34 @@ bool has_kinds(const qfs_template *t) {
 }
 
 // Memory accounting for one call: every allocation goes through here so that the
-// budget (device_mem_budget or the free memory) is enforced before hipMalloc.
+// budget (device_mem_budget or the free memory) is enforced before hipMalloc. Blocks come
+// from the cache of earlier calls when one of the exact size is there. A block the call
+// gives back (a buffer freed or resized, or the call's end) is kept, not freed and not
+// reused within the call; when the call ends, the device is drained once and its blocks go
+// to the cache. On a device out-of-memory the kept blocks and the cache are freed and the
+// allocation is tried once more.
 struct Arena {
   size_t budget = 0, used = 0;
+  int dev = 0;
+  std::vector<std::pair<void *, size_t>> kept;
+  Arena() {
+    if (hipGetDevice(&dev) != hipSuccess) (void)hipGetLastError();
+  }
+  Arena(const Arena &) = delete;
+  Arena &operator=(const Arena &) = delete;
+  ~Arena() {
+    if (kept.empty()) return;
+    if (hipDeviceSynchronize() == hipSuccess) {
+      device_cache_put(dev, kept);
+    } else {
+      (void)hipGetLastError();
+      for (auto &b : kept) (void)hipFree(b.first);
+      kept.clear();
+    }
+  }
+  static void give_back(void *self, void *p, size_t bytes) {
+    static_cast<Arena *>(self)->kept.emplace_back(p, bytes);
+  }
   int alloc(DevBuf &b, size_t bytes) {
     const size_t old = b.bytes;
     if (used - old + bytes > budget) {
@@ -121,7 +224,29 @@ struct Arena {
     }
     used -= old;
     b.release();
-    QFS_TRY(b.alloc(bytes));
+    if (bytes == 0) return QFS_OK;
+    void *p = device_cache_take(dev, bytes);
+    if (!p) {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        // the blocks this call gave back are idle once the device has drained
+        QFS_HIP(hipDeviceSynchronize());
+        for (auto &k : kept) (void)hipFree(k.first);
+        kept.clear();
+        (void)device_cache_trim(dev);
+        e = hipMalloc(&p, bytes);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error_detail(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? QFS_ENOMEM : QFS_EDEVICE;
+      }
+    }
+    b.ptr = p;
+    b.bytes = bytes;
+    b.give_back = &Arena::give_back;
+    b.owner = this;
     used += bytes;
     return QFS_OK;
   }
@@ -644,6 +769,8 @@ class Group {
   DevBuf blist_, astate_, vstate_;
   DevBuf g64_, g32_, vstore_, pairs_dev_, kinds_dev_;
   DevBuf partials_, dpart_, costs_, slots_, work_;
+  DevBuf zslot_;  // one slot entry 0 (target simulation)
+  DevBuf oflag_;  // set by the orthonormalisations on a non-positive pivot
   std::vector<GateGroup> groups_;  // grouped backward pass (backward_mode GROUPED)
   DevBuf bneed_dev_, gpartials_, vop_, fplan_dev_, fgslot_dev_;
   std::vector<int32_t> bneed_h_, fplan_h_, fgslot_h_;
@@ -687,12 +814,13 @@ class Group {
   }
   int backward_any() { return fp64_ ? sweep_backward<double>(ctx_) : sweep_backward<float>(ctx_); }
   int read_costs(std::vector<double> &ct, std::vector<double> &cv, std::vector<double> *c0);
+  int check_orth();
 };
 
 int Group::draw_training(int c0, int c1) {
   QFS_TRY(launch_ginibre(N_, c0, c1, ldm_, p_.seed, kRoleTrain, 0, psi64_.as<c128>(), stream_));
   QFS_TRY(arena_.alloc(work_, work_bytes_orth(N_, c1)));
-  QFS_TRY(orthonormalize_columns(N_, ldm_, c0, c1, psi64_.as<c128>(), work_.ptr, stream_));
+  QFS_TRY(orthonormalize_columns(N_, ldm_, c0, c1, psi64_.as<c128>(), work_.ptr, stream_, oflag_.as<int>()));
   arena_.free(work_);
   return QFS_OK;
 }
@@ -709,18 +837,13 @@ int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld) {
                          stream_));
   const qfs_template *ct = tgt_->circuit;
   const Geometry g{n_, (int32_t)N_, ceil_log2(ld), 1, M};  // the master is one chunk
-  int32_t zero = 0;
-  DevBuf slot;
-  QFS_TRY(slot.alloc(sizeof(int32_t)));
-  QFS_HIP(hipMemcpyAsync(slot.ptr, &zero, sizeof(int32_t), hipMemcpyHostToDevice, stream_));
   GateRef gr{reinterpret_cast<const c128 *>(tgt_->circuit_gates),
              reinterpret_cast<const c128 *>(tgt_->circuit_gates), 0};
   for (int k = 0; k < ct->n_gates; ++k) {
     QFS_TRY(launch_apply<double>(g, ct->pairs[2 * k], ct->pairs[2 * k + 1], k, false, gr,
                                  SBuf<double>{phi.as<c128>(), 0}, SBuf<double>{phi.as<c128>(), 0},
-                                 slot.as<int32_t>(), 1, stream_));
+                                 zslot_.as<int32_t>(), 1, stream_));
   }
-  QFS_HIP(hipStreamSynchronize(stream_));
   return QFS_OK;
 }
 
@@ -746,7 +869,7 @@ int Group::draw_validation() {
   QFS_TRY(launch_ginibre(N_, 0, Mv_, ldmv_, p_.seed, kRoleVal, (uint32_t)generation_,
                          psiv64_.as<c128>(), stream_));
   QFS_TRY(arena_.alloc(work_, work_bytes_orth(N_, Mv_)));
-  QFS_TRY(orthonormalize_columns(N_, ldmv_, 0, Mv_, psiv64_.as<c128>(), work_.ptr, stream_));
+  QFS_TRY(orthonormalize_columns(N_, ldmv_, 0, Mv_, psiv64_.as<c128>(), work_.ptr, stream_, oflag_.as<int>()));
   arena_.free(work_);
   return make_targets(psiv64_, phiv64_, Mv_, ldmv_);
 }
@@ -1014,6 +1137,18 @@ int Group::restore_gates(const std::vector<int> &starts, int par) {
   return launch_copy_slots(rslots_.as<int32_t>(), (int)starts.size(), snap_copy(par, true), stream_);
 }
 
+// The orthonormalisations queued since the last check (after a stream synchronisation).
+int Group::check_orth() {
+  int h = 0;
+  QFS_HIP(hipMemcpyAsync(&h, oflag_.ptr, sizeof(int), hipMemcpyDeviceToHost, stream_));
+  QFS_HIP(hipStreamSynchronize(stream_));
+  if (h) {
+    set_error_detail("orthonormalisation: non-positive Cholesky pivot (dependent columns)");
+    return QFS_ENUMERIC;
+  }
+  return QFS_OK;
+}
+
 int Group::read_costs(std::vector<double> &ct, std::vector<double> &cv, std::vector<double> *c0) {
   QFS_HIP(hipMemcpyAsync(h_costs_, costs_.ptr, sizeof(double) * 3 * S_, hipMemcpyDeviceToHost, stream_));
   QFS_HIP(hipStreamSynchronize(stream_));
@@ -1054,6 +1189,10 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_HIP(hipMemcpyAsync(pairs_dev_.ptr, pairs_.data(), sizeof(int32_t) * 2 * L_, hipMemcpyHostToDevice,
                          stream_));
   QFS_TRY(launch_zero(costs_.ptr, costs_.bytes, stream_));
+  QFS_TRY(arena_.alloc(zslot_, 16));
+  QFS_TRY(arena_.alloc(oflag_, 16));
+  QFS_TRY(launch_zero(zslot_.ptr, zslot_.bytes, stream_));
+  QFS_TRY(launch_zero(oflag_.ptr, oflag_.bytes, stream_));
 
   // training set and A tensor (computed once per training set)
   QFS_TRY(arena_.alloc(psi64_, sizeof(c128) * N_ * ldm_));
@@ -1147,6 +1286,7 @@ int Group::run(GroupResult &out, double t_start) {
 
   QFS_TRY(forward_any(true));
   QFS_TRY(read_costs(ct, cv, &c0));
+  QFS_TRY(check_orth());
   for (int s = 0; s < S_; ++s) {
     c_prev[s] = c0[s];
     ct[s] = c0[s];
@@ -1252,10 +1392,8 @@ int Group::run(GroupResult &out, double t_start) {
       QFS_HIP(hipStreamSynchronize(stream_));
       arena_.free(psi64_);
       arena_.free(phi64_);
-      std::swap(psi64_.ptr, npsi.ptr);
-      std::swap(psi64_.bytes, npsi.bytes);
-      std::swap(phi64_.ptr, nphi.ptr);
-      std::swap(phi64_.bytes, nphi.bytes);
+      psi64_.swap(npsi);
+      phi64_.swap(nphi);
       const int M_old = M_;
       M_ = M_new;
       ldm_ = ld_new;
@@ -1287,6 +1425,7 @@ int Group::run(GroupResult &out, double t_start) {
       QFS_TRY(set_slots(active));
       QFS_TRY(forward_any(true));
       QFS_TRY(read_costs(nct, ncv, &c0));
+      QFS_TRY(check_orth());
       for (int s : active) c_prev[s] = c0[s];
       par = 0;
       QFS_TRY(begin_segment(true));
@@ -1451,6 +1590,14 @@ const char *qfs_last_error_detail(void) { return g_detail.c_str(); }
 
 const char *qfs_version(void) { return "qfs-hip 0.2 (gfx950)"; }
 
+int qfs_release_device_cache(size_t *bytes_freed) {
+  int dev = 0;
+  QFS_HIP(hipGetDevice(&dev));
+  const size_t b = qfs::device_cache_trim(dev);
+  if (bytes_freed) *bytes_freed = b;
+  return QFS_OK;
+}
+
 void qfs_default_params(qfs_params *p) {
   if (!p) return;
   std::memset(p, 0, sizeof(*p));
@@ -1531,8 +1678,11 @@ int qfs_instantiate(const qfs_template *tmpl, const qfs_target *target, const qf
   size_t budget = p.device_mem_budget;
   if (budget == 0) {
     size_t fr = 0, tot = 0;
+    int dev = 0;
     QFS_HIP(hipMemGetInfo(&fr, &tot));
-    budget = (size_t)(0.92 * (double)fr);
+    QFS_HIP(hipGetDevice(&dev));
+    // blocks cached from earlier calls are free for this one
+    budget = (size_t)(0.92 * (double)(fr + device_cache_held(dev)));
   }
   std::vector<GroupResult> results;
   QFS_TRY(run_split(tmpl, target, p, gates_in, 0, p.multistarts, budget, t0, results));

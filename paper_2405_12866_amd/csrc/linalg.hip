@@ -282,7 +282,7 @@ size_t work_bytes_orth(int64_t rows, int64_t cols) {
 }
 
 int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c128 *A, void *work,
-                           hipStream_t s) {
+                           hipStream_t s, int *flag_dev) {
   const int m = (int)(c1 - c0);
   if (m <= 0) return QFS_OK;
   c128 *P = static_cast<c128 *>(work);          // c0 x m (<= c1 x c1)
@@ -290,8 +290,8 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
   c128 *T = Gm + (size_t)m * m;                   // m x m
   c128 *Tmp = T + (size_t)m * m;                  // rows x m
   c128 *parts = Tmp + (size_t)rows * m;           // gram_parts(m) x m x m
-  int *flag = reinterpret_cast<int *>(parts + (size_t)gram_parts(m) * m * m);
-  QFS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  int *flag = flag_dev ? flag_dev : reinterpret_cast<int *>(parts + (size_t)gram_parts(m) * m * m);
+  if (!flag_dev) QFS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
   c128 *An = A + c0;
   const c128 one = cmake(1.0, 0.0), zero = cmake(0.0, 0.0), mone = cmake(-1.0, 0.0);
   if (c0 > 0) {
@@ -312,6 +312,7 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
                        dim3(256), 0, s, rows, m, Tmp, m, An, (int)ld);
     QFS_HIP(hipGetLastError());
   }
+  if (flag_dev) return QFS_OK;  // the caller reads the flag
   int h_flag = 0;
   QFS_HIP(hipMemcpyAsync(&h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   QFS_HIP(hipStreamSynchronize(s));

@@ -15,6 +15,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/qfs.h"
@@ -107,10 +108,21 @@ int pool_stream(int index, hipStream_t *out);
   } while (0)
 
 // ------------------------------------------------------------------ device buffers
-// A simple owning device allocation; the engine keeps a few of these per call.
+// Blocks that calls of the single-problem engine give back when they end, kept for the
+// next call of the same size instead of hipFree (engine.hip). Every block in the cache is
+// idle: a call gives its blocks back only after the device has drained.
+void *device_cache_take(int dev, size_t bytes);
+size_t device_cache_held(int dev);
+size_t device_cache_trim(int dev);  // frees the device's cached blocks; returns the bytes freed
+
+// A simple owning device allocation; the engine keeps a few of these per call. An
+// allocator that takes blocks back (the engine's per-call Arena) sets give_back, and
+// release() then hands the block to it instead of freeing it.
 struct DevBuf {
   void *ptr = nullptr;
   size_t bytes = 0;
+  void (*give_back)(void *owner, void *ptr, size_t bytes) = nullptr;
+  void *owner = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
@@ -119,6 +131,12 @@ struct DevBuf {
     release();
     if (b == 0) return QFS_OK;
     hipError_t e = hipMalloc(&ptr, b);
+    if (e == hipErrorOutOfMemory) {
+      // blocks held for later calls go first
+      (void)hipGetLastError();
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess && device_cache_trim(dev) > 0) e = hipMalloc(&ptr, b);
+    }
     if (e != hipSuccess) {
       ptr = nullptr;
       (void)hipGetLastError();
@@ -129,9 +147,22 @@ struct DevBuf {
     return QFS_OK;
   }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+      if (give_back)
+        give_back(owner, ptr, bytes);
+      else
+        (void)hipFree(ptr);
+    }
     ptr = nullptr;
     bytes = 0;
+    give_back = nullptr;
+    owner = nullptr;
+  }
+  void swap(DevBuf &o) {
+    std::swap(ptr, o.ptr);
+    std::swap(bytes, o.bytes);
+    std::swap(give_back, o.give_back);
+    std::swap(owner, o.owner);
   }
   template <typename T>
   T *as() const {
@@ -163,10 +194,13 @@ int launch_zgemm(bool conjtrans_a, int m, int n, int k, c128 alpha, const c128 *
                  const c128 *B, int ldb, c128 beta, c128 *C, int ldc, hipStream_t s);
 // Orthonormalise columns [c0, c1) of the rows x ld matrix A against columns [0, c0)
 // and among themselves: QR with real positive diag(R) (CholeskyQR2 after two block
-// Gram-Schmidt projections). Uses `work` (device, >= work_bytes_orth(rows, c1)).
+// Gram-Schmidt projections). Uses `work` (device, >= work_bytes_orth(rows, c1)). With
+// flag_dev null it waits for the stream and returns QFS_ENUMERIC on a non-positive
+// Cholesky pivot; else it returns at once and sets *flag_dev (device, zeroed by the caller)
+// to 1 on such a pivot.
 size_t work_bytes_orth(int64_t rows, int64_t cols);
 int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c128 *A,
-                           void *work, hipStream_t s);
+                           void *work, hipStream_t s, int *flag_dev = nullptr);
 
 // Layout conversions (linalg.hip)
 // sample-major [M][N] c128  <->  chunked amplitude-major layout in R (zero padding).

@@ -67,7 +67,8 @@ class Result(C.Structure):
                 ("amp_updates", C.c_double)]
 
 
-EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_default_params",
+EXPORTS = ["qfs_strerror", "qfs_last_error_detail", "qfs_version", "qfs_release_device_cache",
+           "qfs_default_params",
            "qfs_instantiate", "qfs_instantiate_batch", "qfs_instantiate_samples", "qfs_draw_states", "qfs_haar_gates",
            "qfs_apply_gates", "qfs_dense_apply", "qfs_environment", "qfs_environment_noalloc",
            "qfs_polar_update",
@@ -102,6 +103,7 @@ def load():
         lib.qfs_strerror.argtypes = [C.c_int]
         lib.qfs_last_error_detail.restype = C.c_char_p
         lib.qfs_version.restype = C.c_char_p
+        lib.qfs_release_device_cache.argtypes = [C.POINTER(C.c_size_t)]
         lib.qfs_default_params.argtypes = [C.POINTER(Params)]
         lib.qfs_instantiate.argtypes = [C.POINTER(Template), C.POINTER(Target), C.POINTER(Params),
                                         P, P, C.POINTER(Result)]
@@ -358,6 +360,13 @@ def qfs_features(n, pairs):
     tmpl = Template(n, arr.shape[0], pp)
     _check(load().qfs_features(C.byref(tmpl), out.ctypes.data_as(C.c_void_p)), "qfs_features")
     return out
+
+
+def qfs_release_device_cache():
+    """Free the device buffers the library keeps between calls; returns the bytes freed."""
+    freed = C.c_size_t(0)
+    _check(load().qfs_release_device_cache(C.byref(freed)), "qfs_release_device_cache")
+    return freed.value
 
 
 def qfs_mlp_num_params():
