@@ -733,6 +733,8 @@ class Group {
 
     if (gexec_) (void)hipGraphExecDestroy(gexec_);
     if (gfork_) (void)hipEventDestroy(gfork_);
+    if (vfork_) (void)hipEventDestroy(vfork_);
+    if (vjoin_) (void)hipEventDestroy(vjoin_);
     if (gjoin_) (void)hipEventDestroy(gjoin_);
 
   }
@@ -758,6 +760,7 @@ class Group {
   // (running starts, M, precision: each of those marks it dirty).
   hipStream_t cap_ = nullptr;
   hipEvent_t gfork_ = nullptr, gjoin_ = nullptr;
+  hipEvent_t vfork_ = nullptr, vjoin_ = nullptr;  // validation set-up stream
   hipGraphExec_t gexec_ = nullptr;
   bool gdirty_ = true;
   int sweep_once();
@@ -770,6 +773,7 @@ class Group {
   DevBuf g64_, g32_, vstore_, pairs_dev_, kinds_dev_;
   DevBuf partials_, dpart_, costs_, slots_, work_;
   DevBuf zslot_;  // one slot entry 0 (target simulation)
+  DevBuf workv_;  // orthonormalisation work of the validation set
   DevBuf oflag_;  // set by the orthonormalisations on a non-positive pivot
   std::vector<GateGroup> groups_;  // grouped backward pass (backward_mode GROUPED)
   DevBuf bneed_dev_, gpartials_, vop_, fplan_dev_, fgslot_dev_;
@@ -805,8 +809,8 @@ class Group {
   GroupResult *res_ = nullptr;
 
   int draw_training(int c0, int c1);
-  int make_targets(DevBuf &psi, DevBuf &phi, int M, int ld);
-  int draw_validation();
+  int make_targets(DevBuf &psi, DevBuf &phi, int M, int ld, hipStream_t s);
+  int draw_validation(hipStream_t s);
   int setup_working();
   int set_slots(const std::vector<int> &active);
   int forward_any(bool with_c0) {
@@ -826,15 +830,14 @@ int Group::draw_training(int c0, int c1) {
 }
 
 // phi = U psi (dense product, or simulation of the target circuit), FP64.
-int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld) {
+int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld, hipStream_t s) {
   if (tgt_->kind == QFS_TARGET_DENSE) {
     QFS_TRY(launch_zgemm(false, (int)N_, M, (int)N_, cmake(1.0, 0.0),
                          reinterpret_cast<const c128 *>(tgt_->U), (int)N_, psi.as<c128>(), ld,
-                         cmake(0.0, 0.0), phi.as<c128>(), ld, stream_));
+                         cmake(0.0, 0.0), phi.as<c128>(), ld, s));
     return QFS_OK;
   }
-  QFS_HIP(hipMemcpyAsync(phi.ptr, psi.ptr, sizeof(c128) * (size_t)N_ * ld, hipMemcpyDeviceToDevice,
-                         stream_));
+  QFS_HIP(hipMemcpyAsync(phi.ptr, psi.ptr, sizeof(c128) * (size_t)N_ * ld, hipMemcpyDeviceToDevice, s));
   const qfs_template *ct = tgt_->circuit;
   const Geometry g{n_, (int32_t)N_, ceil_log2(ld), 1, M};  // the master is one chunk
   GateRef gr{reinterpret_cast<const c128 *>(tgt_->circuit_gates),
@@ -842,12 +845,14 @@ int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld) {
   for (int k = 0; k < ct->n_gates; ++k) {
     QFS_TRY(launch_apply<double>(g, ct->pairs[2 * k], ct->pairs[2 * k + 1], k, false, gr,
                                  SBuf<double>{phi.as<c128>(), 0}, SBuf<double>{phi.as<c128>(), 0},
-                                 zslot_.as<int32_t>(), 1, stream_));
+                                 zslot_.as<int32_t>(), 1, s));
   }
   return QFS_OK;
 }
 
-int Group::draw_validation() {
+// The validation set (Sec. 3: held-out samples, drawn apart from the training set), on
+// stream s.
+int Group::draw_validation(hipStream_t s) {
   if (tgt_->kind == QFS_TARGET_SAMPLES) {
     Mv_ = tgt_->n_val;
     ldmv_ = master_ld(std::max(Mv_, 1));
@@ -856,8 +861,8 @@ int Group::draw_validation() {
     QFS_TRY(arena_.alloc(phiv64_, sizeof(c128) * N_ * ldmv_));
     const c128 *ps = reinterpret_cast<const c128 *>(tgt_->psi) + (size_t)n_train_ * N_;
     const c128 *ph = reinterpret_cast<const c128 *>(tgt_->phi) + (size_t)n_train_ * N_;
-    QFS_TRY(launch_to_internal<double>(n_, Mv_, ceil_log2(ldmv_), 1, ps, psiv64_.as<c128>(), stream_));
-    QFS_TRY(launch_to_internal<double>(n_, Mv_, ceil_log2(ldmv_), 1, ph, phiv64_.as<c128>(), stream_));
+    QFS_TRY(launch_to_internal<double>(n_, Mv_, ceil_log2(ldmv_), 1, ps, psiv64_.as<c128>(), s));
+    QFS_TRY(launch_to_internal<double>(n_, Mv_, ceil_log2(ldmv_), 1, ph, phiv64_.as<c128>(), s));
     return QFS_OK;
   }
   Mv_ = p_.m_val > 0 ? p_.m_val : M_;
@@ -865,13 +870,13 @@ int Group::draw_validation() {
   ldmv_ = master_ld(Mv_);
   QFS_TRY(arena_.alloc(psiv64_, sizeof(c128) * N_ * ldmv_));
   QFS_TRY(arena_.alloc(phiv64_, sizeof(c128) * N_ * ldmv_));
-  QFS_TRY(launch_zero(psiv64_.ptr, psiv64_.bytes, stream_));
+  QFS_TRY(launch_zero(psiv64_.ptr, psiv64_.bytes, s));
   QFS_TRY(launch_ginibre(N_, 0, Mv_, ldmv_, p_.seed, kRoleVal, (uint32_t)generation_,
-                         psiv64_.as<c128>(), stream_));
-  QFS_TRY(arena_.alloc(work_, work_bytes_orth(N_, Mv_)));
-  QFS_TRY(orthonormalize_columns(N_, ldmv_, 0, Mv_, psiv64_.as<c128>(), work_.ptr, stream_, oflag_.as<int>()));
-  arena_.free(work_);
-  return make_targets(psiv64_, phiv64_, Mv_, ldmv_);
+                         psiv64_.as<c128>(), s));
+  QFS_TRY(arena_.alloc(workv_, work_bytes_orth(N_, Mv_)));
+  QFS_TRY(orthonormalize_columns(N_, ldmv_, 0, Mv_, psiv64_.as<c128>(), workv_.ptr, s, oflag_.as<int>()));
+  arena_.free(workv_);
+  return make_targets(psiv64_, phiv64_, Mv_, ldmv_, s);
 }
 
 // Working sets in the sweep precision (chunk width chosen for the fused forward pass
@@ -1193,6 +1198,16 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_TRY(arena_.alloc(oflag_, 16));
   QFS_TRY(launch_zero(zslot_.ptr, zslot_.bytes, stream_));
   QFS_TRY(launch_zero(oflag_.ptr, oflag_.bytes, stream_));
+  // the validation set is drawn beside the training set, on a stream of its own: both are
+  // chains of small kernels that leave most of the device idle
+  hipStream_t vs = stream_;
+  if (!samples && !full_unitary) {
+    QFS_TRY(pool_stream(5, &vs));
+    QFS_HIP(hipEventCreateWithFlags(&vfork_, hipEventDisableTiming));
+    QFS_HIP(hipEventCreateWithFlags(&vjoin_, hipEventDisableTiming));
+    QFS_HIP(hipEventRecord(vfork_, stream_));
+    QFS_HIP(hipStreamWaitEvent(vs, vfork_, 0));
+  }
 
   // training set and A tensor (computed once per training set)
   QFS_TRY(arena_.alloc(psi64_, sizeof(c128) * N_ * ldm_));
@@ -1206,15 +1221,15 @@ int Group::run(GroupResult &out, double t_start) {
   } else if (full_unitary) {
     // full-unitary QFactor: the computational basis, so phi holds U's columns
     QFS_TRY(launch_unit_columns(N_, ldm_, psi64_.as<c128>(), stream_));
-    QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
+    QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
   } else {
     QFS_TRY(draw_training(0, M_));
-    QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
+    QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
   }
   if (full_unitary)
     Mv_ = 0;
   else
-    QFS_TRY(draw_validation());
+    QFS_TRY(draw_validation(vs));
 
   // initial gates (App. A: random per start from the seed, or given)
   QFS_TRY(arena_.alloc(g64_, sizeof(c128) * 16 * (size_t)L_ * S_));
@@ -1235,6 +1250,10 @@ int Group::run(GroupResult &out, double t_start) {
   QFS_TRY(launch_narrow((int64_t)16 * L_ * S_, g64_.as<c128>(), g32_.as<c64>(), stream_));
   QFS_TRY(arena_.alloc(vstore_, sizeof(c128) * 16 * (size_t)L_ * S_));
   QFS_TRY(launch_identity4((int64_t)L_ * S_, vstore_.as<c128>(), stream_));
+  if (vs != stream_) {
+    QFS_HIP(hipEventRecord(vjoin_, vs));
+    QFS_HIP(hipStreamWaitEvent(stream_, vjoin_, 0));
+  }
 
   groups_ = plan_gate_groups(L_, pairs_.data(), kinds_.empty() ? nullptr : kinds_.data());
   SweepCtx &c = ctx_;
@@ -1404,11 +1423,11 @@ int Group::run(GroupResult &out, double t_start) {
                                            phi64_.as<c128>(), stream_));
       } else {
         QFS_TRY(draw_training(M_old, M_));
-        QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_));
+        QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
         ++generation_;
         arena_.free(psiv64_);
         arena_.free(phiv64_);
-        QFS_TRY(draw_validation());
+        QFS_TRY(draw_validation(stream_));
       }
       QFS_TRY(setup_working());
       ctx_.beta = effective_beta(p_.beta, p_.beta_normalized != 0, M_);
