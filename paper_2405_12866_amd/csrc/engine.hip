@@ -101,6 +101,38 @@ size_t device_cache_trim(int dev) {
   return freed;
 }
 
+// Pinned host buffers for the per-sweep costs, kept for later calls (hipHostMalloc and
+// hipHostFree cost tens to hundreds of microseconds each). Never freed: the pool holds at
+// most one buffer per call that ran at the same time.
+namespace {
+std::mutex g_pin_mu;
+std::multimap<size_t, void *> g_pins;
+}  // namespace
+
+static void *pinned_take(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pins.lower_bound(bytes);
+    if (it != g_pins.end()) {
+      void *p = it->second;
+      g_pins.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  if (hipHostMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+// (only once no copy into the buffer is pending)
+static void pinned_put(void *p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pins.emplace(bytes, p);
+}
+
 // Takes idle blocks (the device has drained since their last use) of device dev.
 static void device_cache_put(int dev, std::vector<std::pair<void *, size_t>> &blks) {
   size_t fr = 0, tot = 0;
@@ -720,7 +752,13 @@ class Group {
     stream_ = as_stream(p.hip_stream);
   }
   ~Group() {
-    if (h_costs_) (void)hipHostFree(h_costs_);
+    if (h_costs_) {
+      // a run-ahead sweep's cost copies may still be in flight
+      if (hipDeviceSynchronize() == hipSuccess)
+        pinned_put(h_costs_, h_costs_bytes_);
+      else
+        (void)hipGetLastError();
+    }
     if (seg0_) (void)hipEventDestroy(seg0_);
     for (auto &d : done_)
       for (hipEvent_t e : d)
@@ -782,6 +820,7 @@ class Group {
   // pinned [1 + 2 kParts][3 S] (c_train, c_val, c_0): read_costs's copy, then one copy per
   // sweep parity and part, written on the part's stream right after its sweep
   double *h_costs_ = nullptr;
+  size_t h_costs_bytes_ = 0;
   double *cost_buf(int par, int part) { return h_costs_ + (size_t)(1 + par * SweepCtx::kParts + part) * 3 * S_; }
   // The control loop's sweeps: run-ahead (spec_), per sweep parity the starts and parts it
   // was issued with and an event per part at its end (timing reference seg0_), and the
@@ -810,7 +849,7 @@ class Group {
 
   int draw_training(int c0, int c1);
   int make_targets(DevBuf &psi, DevBuf &phi, int M, int ld, hipStream_t s);
-  int draw_validation(hipStream_t s);
+  int draw_validation(hipStream_t s, bool targets = true);
   int setup_working();
   int set_slots(const std::vector<int> &active);
   int forward_any(bool with_c0) {
@@ -851,8 +890,8 @@ int Group::make_targets(DevBuf &psi, DevBuf &phi, int M, int ld, hipStream_t s) 
 }
 
 // The validation set (Sec. 3: held-out samples, drawn apart from the training set), on
-// stream s.
-int Group::draw_validation(hipStream_t s) {
+// stream s; targets false leaves its target states to a make_targets call.
+int Group::draw_validation(hipStream_t s, bool targets) {
   if (tgt_->kind == QFS_TARGET_SAMPLES) {
     Mv_ = tgt_->n_val;
     ldmv_ = master_ld(std::max(Mv_, 1));
@@ -876,7 +915,7 @@ int Group::draw_validation(hipStream_t s) {
   QFS_TRY(arena_.alloc(workv_, work_bytes_orth(N_, Mv_)));
   QFS_TRY(orthonormalize_columns(N_, ldmv_, 0, Mv_, psiv64_.as<c128>(), workv_.ptr, s, oflag_.as<int>()));
   arena_.free(workv_);
-  return make_targets(psiv64_, phiv64_, Mv_, ldmv_, s);
+  return targets ? make_targets(psiv64_, phiv64_, Mv_, ldmv_, s) : QFS_OK;
 }
 
 // Working sets in the sweep precision (chunk width chosen for the fused forward pass
@@ -1182,8 +1221,9 @@ int Group::run(GroupResult &out, double t_start) {
   timer_.on = p_.timing != 0;
   res_ = &out;
 
-  QFS_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_costs_),
-                        sizeof(double) * 3 * S_ * (1 + 2 * SweepCtx::kParts)));
+  h_costs_bytes_ = sizeof(double) * 3 * S_ * (1 + 2 * SweepCtx::kParts);
+  h_costs_ = static_cast<double *>(pinned_take(h_costs_bytes_));
+  if (!h_costs_) return set_error_detail("hipHostMalloc of the cost buffer failed"), QFS_EDEVICE;
   QFS_HIP(hipEventCreate(&seg0_));
   for (auto &d : done_)
     for (hipEvent_t &e : d) QFS_HIP(hipEventCreate(&e));
@@ -1223,13 +1263,18 @@ int Group::run(GroupResult &out, double t_start) {
     QFS_TRY(launch_unit_columns(N_, ldm_, psi64_.as<c128>(), stream_));
     QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
   } else {
+    // both orthonormalisations are queued before either target simulation, so that the
+    // two chains start together
     QFS_TRY(draw_training(0, M_));
+    QFS_TRY(draw_validation(vs, false));
     QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
   }
   if (full_unitary)
     Mv_ = 0;
-  else
+  else if (samples)
     QFS_TRY(draw_validation(vs));
+  else
+    QFS_TRY(make_targets(psiv64_, phiv64_, Mv_, ldmv_, vs));
 
   // initial gates (App. A: random per start from the seed, or given)
   QFS_TRY(arena_.alloc(g64_, sizeof(c128) * 16 * (size_t)L_ * S_));
