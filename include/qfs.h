@@ -59,7 +59,7 @@ const char *qfs_last_error_detail(void);
 const char *qfs_version(void);
 /* Device memory kept between calls. When a call of qfs_instantiate (and of the entry
  * points built on it: qfs_instantiate_samples, the learned single-problem entry) ends, the
- * library keeps its device buffers, up to a quarter of the device's memory, and reuses
+ * library keeps its device buffers, up to an eighth of the device's memory, and reuses
  * them in later calls that need buffers of the same sizes, instead of freeing and
  * allocating them again. An allocation that fails frees the kept buffers first, and the
  * free-memory budget of a call counts them as free. This frees the buffers kept for the

@@ -48,7 +48,7 @@ int ensure_dynamic_lds(const void *fn, size_t bytes, size_t *have) {
 // Device blocks kept between calls of the engine, by device and exact size. hipMalloc of
 // the large working sets and hipFree (which drains the device) otherwise cost several
 // hundred microseconds each in every call, during which the device idles. The cache holds
-// at most a quarter of the device's memory; blocks beyond that are freed.
+// at most an eighth of the device's memory; blocks beyond that are freed.
 namespace {
 struct BlockCache {
   std::mutex mu;
@@ -143,7 +143,7 @@ static void device_cache_put(int dev, std::vector<std::pair<void *, size_t>> &bl
   BlockCache &c = block_cache();
   std::lock_guard<std::mutex> lk(c.mu);
   for (auto &b : blks) {
-    if (c.held[dev] + b.second > tot / 4) {
+    if (c.held[dev] + b.second > tot / 8) {
       (void)hipFree(b.first);
       continue;
     }
