@@ -264,6 +264,83 @@ __global__ __launch_bounds__(64) void k_tri_inverse_upper(int m, const c128 *R, 
   for (int i = lane; i < m; i += 64) T[(int64_t)i * m + c] = tcol[i];
 }
 
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// T = R^-1 for m <= 64 NJ, one wave per row c of T: from T R = I,
+//   T[c][k] = (delta_ck - sum_{c <= j < k} T[c][j] R[j][k]) / R[k][k],  k = c .. m - 1.
+// Lane l keeps the running sums s_i of the rows i = l + 64 u of row c; at step k the lane
+// holding k finishes T[c][k] (reciprocal diagonal taken beforehand), every lane reads it
+// from that lane's registers, and the lanes add T[c][k] R[k][i] to s_i for i > k, reading
+// row k of R (contiguous; four rows are loaded while the four before them are used). No
+// reduction and no barrier per step, unlike the dot-product form above.
+template <int NJ>
+__global__ __launch_bounds__(64) void k_tri_inverse_rows(int m, const c128 *__restrict__ R,
+                                                         c128 *__restrict__ T) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  c128 sv[NJ];
+  double inv[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int i = lane + 64 * u;
+    sv[u] = cmake(0.0, 0.0);
+    inv[u] = i < m ? 1.0 / R[(int64_t)i * m + i].re : 0.0;
+  }
+#pragma unroll
+  for (int uk = 0; uk < NJ; ++uk) {
+    const int ks = max(c, 64 * uk), k1 = min(m, 64 * uk + 64);
+    if (ks >= k1) continue;
+    c128 buf[4][NJ], nbuf[4][NJ];
+    auto load4 = [&](int kb, c128 (&dst)[4][NJ]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kb + q;
+#pragma unroll
+        for (int u = uk; u < NJ; ++u) {
+          const int i = lane + 64 * u;
+          dst[q][u] = (k < k1 && i > k && i < m) ? R[(int64_t)k * m + i] : cmake(0.0, 0.0);
+        }
+      }
+    };
+    load4(ks, buf);
+    for (int kb = ks; kb < k1; kb += 4) {
+      load4(kb + 4, nbuf);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kb + q;
+        if (k < k1) {
+          const int kl = k & 63;
+          const double dre = (k == c ? 1.0 : 0.0) - sv[uk].re, dim = -sv[uk].im;
+          const double tre = readlane_f64(dre * inv[uk], kl), tim = readlane_f64(dim * inv[uk], kl);
+          if (lane == kl) sv[uk] = cmake(tre, tim);  // this slot now holds T[c][k]
+#pragma unroll
+          for (int u = uk; u < NJ; ++u) {
+            const int i = lane + 64 * u;
+            if (i > k) {
+              const c128 r = buf[q][u];
+              sv[u].re += tre * r.re - tim * r.im;
+              sv[u].im += tre * r.im + tim * r.re;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = uk; u < NJ; ++u) buf[q][u] = nbuf[q][u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int i = lane + 64 * u;
+    if (i < m) T[(int64_t)c * m + i] = i < c ? cmake(0.0, 0.0) : sv[u];
+  }
+}
+
 __global__ void k_copy_cols(int64_t rows, int cols, const c128 *src, int lds, c128 *dst, int ldd) {
   const int64_t total = rows * cols;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
@@ -303,8 +380,10 @@ int orthonormalize_columns(int64_t rows, int64_t ld, int64_t c0, int64_t c1, c12
   for (int pass = 0; pass < 2; ++pass) {
     QFS_TRY(gram_splitk(m, m, (int)rows, An, (int)ld, An, (int)ld, Gm, parts, s));
     QFS_TRY(cholesky_upper_blocked(m, Gm, flag, s));
-    hipLaunchKernelGGL(k_tri_inverse_upper, dim3(m), dim3(64), sizeof(c128) * (size_t)m, s, m, Gm,
-                       T);
+    if (m <= 256)
+      hipLaunchKernelGGL(k_tri_inverse_rows<4>, dim3(m), dim3(64), 0, s, m, Gm, T);
+    else
+      hipLaunchKernelGGL(k_tri_inverse_upper, dim3(m), dim3(64), sizeof(c128) * (size_t)m, s, m, Gm, T);
     QFS_HIP(hipGetLastError());
     QFS_TRY(launch_zgemm(false, (int)rows, m, m, one, An, (int)ld, T, m, zero, Tmp, m, s));
     const int64_t total = rows * m;
