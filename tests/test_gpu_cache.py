@@ -75,3 +75,39 @@ def test_release_returns_kept_buffers():
     # a call after the release allocates afresh and still works
     g, info = _call(6, 4, 13, Q.QFS_PREC_MIXED, 8, 4)
     assert np.isfinite(info["c_train"]) and info["sweeps"] >= 1
+
+
+def test_concurrent_calls_match_sequential():
+    """Two host threads, each on its own stream, run calls at the same time (the kept
+    buffers, the pinned cost buffers and the pool streams are shared): every result
+    equals the one-at-a-time result bit for bit."""
+    import threading
+    say("cache: concurrent calls")
+    cases = [(6, 4, 21, Q.QFS_PREC_MIXED, 2, 40), (7, 4, 22, Q.QFS_PREC_MIXED, 16, 10)]
+    ref = [_call(*c) for c in cases]
+    out = [[None, None], [None, None]]
+    errs = []
+
+    def worker(t):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for rep in range(2):
+                    out[t][rep] = _call(*cases[t])
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=worker, args=(t,)) for t in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=100)
+    assert not any(x.is_alive() for x in th), "a worker did not finish"
+    assert not errs, errs
+    for t, c in enumerate(cases):
+        g1, i1 = ref[t]
+        for rep in range(2):
+            g2, i2 = out[t][rep]
+            for k in KEYS:
+                assert i1[k] == i2[k], (c, rep, k, i1[k], i2[k])
+            assert np.array_equal(g1, g2), (c, rep)
