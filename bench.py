@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttd", action="store_true", help="skip the time-to-distance runs")
     ap.add_argument("--timing", type=int, default=1)
+    ap.add_argument("--repeats", type=int, default=10,
+                    help="further calls of the headline workload for the median and IQR")
     ap.add_argument("--graphs", type=int, default=0, help="replay sweeps from HIP graphs (params.graphs)")
     ap.add_argument("--bwd-split", type=int, default=1,
                     help="0: run the backward pass of all starts on one stream in every call (the "
@@ -873,6 +875,26 @@ def main():
     value = info["start_sweeps"] / dt
     N = 1 << n
     S_amp = M * N
+    # spread: the same call repeated (whole call on the host clock after a device
+    # synchronisation; the sweeps alone by the library's hipEvents)
+    rep = None
+    if args.repeats > 0:
+        import numpy as np
+        whole, sweeps_only = [], []
+        for _ in range(args.repeats):
+            t1 = time.perf_counter()
+            _, ri = Q.qfs_instantiate(n, pairs, target_pairs=pairs, target_gates=tg,
+                                      params=dict(base, max_iter=args.steps))
+            torch.cuda.synchronize()
+            whole.append(1e3 * (time.perf_counter() - t1) / args.steps)
+            sweeps_only.append(1e3 * ri["sweep_seconds"] / args.steps)
+        q = lambda v, f: float(np.percentile(v, f))
+        rep = {"calls": args.repeats, "steps_per_call": args.steps,
+               "ms_per_step_whole_call": {"median": round(q(whole, 50), 4),
+                                          "iqr": [round(q(whole, 25), 4), round(q(whole, 75), 4)]},
+               "ms_per_step_sweeps_only": {"median": round(q(sweeps_only, 50), 4),
+                                           "iqr": [round(q(sweeps_only, 25), 4), round(q(sweeps_only, 75), 4)]},
+               "start_sweeps_per_s_median": round(S * 1e3 / q(whole, 50), 2)}
     # instrumented region (same workload): hipEvents around every kernel launch on the
     # call's stream give the per-kernel durations for the roofline
     roof, classes = None, None
@@ -921,6 +943,7 @@ def main():
         "sweep_algorithmic_frac": round(sweep_alg_bytes * info["start_sweeps"] / dt / 1e9 / HBM_PEAK_GBPS, 4),
         "kernel_classes": classes,
         "final_c_train": info["c_train"], "final_c_val": info["c_val"],
+        "repeats": rep,
     }
     if args.sec8d:
         extra["measurement_rows"] = sec8d(dev)
