@@ -1453,8 +1453,7 @@ int Group::run(GroupResult &out, double t_start) {
       QFS_TRY(launch_zero(npsi.ptr, npsi.bytes, stream_));
       QFS_HIP(hipMemcpy2DAsync(npsi.ptr, sizeof(c128) * ld_new, psi64_.ptr, sizeof(c128) * ldm_,
                                sizeof(c128) * M_, N_, hipMemcpyDeviceToDevice, stream_));
-      QFS_HIP(hipStreamSynchronize(stream_));
-      arena_.free(psi64_);
+      arena_.free(psi64_);  // (kept until the call ends: the copy above may still read it)
       arena_.free(phi64_);
       psi64_.swap(npsi);
       phi64_.swap(nphi);
@@ -1467,12 +1466,24 @@ int Group::run(GroupResult &out, double t_start) {
         QFS_TRY(launch_to_internal<double>(n_, M_, ceil_log2(ldm_), 1, reinterpret_cast<const c128 *>(tgt_->phi),
                                            phi64_.as<c128>(), stream_));
       } else {
+        // the new validation generation on its own stream, as in the set-up
+        hipStream_t vs = stream_;
+        if (vfork_) {
+          QFS_TRY(pool_stream(5, &vs));
+          QFS_HIP(hipEventRecord(vfork_, stream_));
+          QFS_HIP(hipStreamWaitEvent(vs, vfork_, 0));
+        }
         QFS_TRY(draw_training(M_old, M_));
-        QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
         ++generation_;
         arena_.free(psiv64_);
         arena_.free(phiv64_);
-        QFS_TRY(draw_validation(stream_));
+        QFS_TRY(draw_validation(vs, false));
+        QFS_TRY(make_targets(psi64_, phi64_, M_, ldm_, stream_));
+        QFS_TRY(make_targets(psiv64_, phiv64_, Mv_, ldmv_, vs));
+        if (vs != stream_) {
+          QFS_HIP(hipEventRecord(vjoin_, vs));
+          QFS_HIP(hipStreamWaitEvent(stream_, vjoin_, 0));
+        }
       }
       QFS_TRY(setup_working());
       ctx_.beta = effective_beta(p_.beta, p_.beta_normalized != 0, M_);
