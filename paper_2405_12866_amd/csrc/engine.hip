@@ -790,6 +790,7 @@ class Group {
   std::vector<int32_t> pairs_;
   std::vector<int32_t> kinds_;  // empty: every gate two-qubit
   const c128 *fixed_ = nullptr;
+  std::vector<int32_t> fmode_;  // per gate: how the grouped forward pass applies it
   hipStream_t stream_ = nullptr;
   hipStream_t side_ = nullptr;  // second stream of the backward pass (default priority)
   hipEvent_t fork_ = nullptr, join_ = nullptr;
@@ -964,8 +965,19 @@ int Group::setup_working() {
   // chunk width
   c.fplan = c.fgslot = nullptr;
   c.fngroups = 0;
+  if (c.grouped && fused && !fp64_ && fmode_.empty()) {
+    // how the forward pass applies each gate (the constant gates are the template's in
+    // every start)
+    std::vector<c128> fixed_h;
+    if (!kinds_.empty() && fixed_) {
+      fixed_h.resize((size_t)L_ * 16);
+      QFS_HIP(hipMemcpy(fixed_h.data(), fixed_, sizeof(c128) * fixed_h.size(), hipMemcpyDeviceToHost));
+    }
+    fmode_ = forward_gate_modes(L_, kinds_.empty() ? nullptr : kinds_.data(),
+                                fixed_h.empty() ? nullptr : fixed_h.data(), 1);
+  }
   if (c.grouped && fused && !fp64_ && build_forward_plan(c.g, L_, pairs_.data(), groups_, bneed_h_.data(),
-                                                         fplan_h_, fgslot_h_) == QFS_OK) {
+                                                         fmode_.data(), fplan_h_, fgslot_h_) == QFS_OK) {
     if (!fplan_dev_.ptr) QFS_TRY(arena_.alloc(fplan_dev_, sizeof(int32_t) * fplan_h_.size()));
     if (!fgslot_dev_.ptr) QFS_TRY(arena_.alloc(fgslot_dev_, sizeof(int32_t) * fgslot_h_.size()));
     QFS_HIP(hipMemcpyAsync(fplan_dev_.ptr, fplan_h_.data(), sizeof(int32_t) * fplan_h_.size(),
@@ -2037,7 +2049,21 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
     c.groups = &groups;
     c.bneed_dev = bneed.as<int32_t>();
     c.gpartials = gpart.as<c128>();
-    if (f32 && fused && build_forward_plan(c.g, L, pairs, groups, need.data(), fplan_h, fgslot_h) == QFS_OK) {
+    // how the forward pass applies each gate; a constant gate counts as a CNOT only if it
+    // is one in every start's gates
+    std::vector<int32_t> fmode;
+    if (f32 && fused) {
+      std::vector<c128> gh;
+      bool any_fixed = false;
+      for (int k = 0; kinds && k < L; ++k) any_fixed |= kinds[k] == QFS_GATE_FIXED;
+      if (any_fixed) {
+        gh.resize((size_t)starts * L * 16);
+        QFS_HIP(hipMemcpyAsync(gh.data(), gates, sizeof(c128) * gh.size(), hipMemcpyDeviceToHost, s));
+        QFS_HIP(hipStreamSynchronize(s));
+      }
+      fmode = forward_gate_modes(L, kinds, gh.empty() ? nullptr : gh.data(), starts);
+    }
+    if (f32 && fused && build_forward_plan(c.g, L, pairs, groups, need.data(), fmode.data(), fplan_h, fgslot_h) == QFS_OK) {
       QFS_TRY(fplan_d.alloc(sizeof(int32_t) * fplan_h.size()));
       QFS_TRY(fgslot_d.alloc(sizeof(int32_t) * fgslot_h.size()));
       QFS_HIP(hipMemcpyAsync(fplan_d.ptr, fplan_h.data(), sizeof(int32_t) * fplan_h.size(), hipMemcpyHostToDevice, s));

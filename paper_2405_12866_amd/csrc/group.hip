@@ -518,7 +518,8 @@ struct FwdGroupSeg {
 
 // Plan entry of a group (forward order): k_lo, k_hi, the chunk-local positions of its four
 // slots (qubits first, then fillers), store flag (the entry B_{k_lo} is read); per gate k:
-// the slots of its two qubits at gslot[2k], gslot[2k + 1].
+// the slots of its two qubits at gslot[kFwdGS k], gslot[kFwdGS k + 1], and how the gate is
+// applied at gslot[kFwdGS k + 2] (kFwdDense, kFwd1Q, kFwdCnotA, kFwdCnotB).
 constexpr int kFwdPlan = 8;
 
 // Gate on item slots (SA, SB) applied to the four amplitudes whose other two slots take the
@@ -581,6 +582,71 @@ __device__ __forceinline__ void item_gate_slots(int sa, int sb, cx<R> (&x)[16], 
     case 12: item_gate<3, 0, R, MF>(x, u, G4); break;
     case 13: item_gate<3, 1, R, MF>(x, u, G4); break;
     default: item_gate<3, 2, R, MF>(x, u, G4); break;
+  }
+}
+
+// A one-qubit gate v (x) I_2 on item slot SA (the pair's first qubit), as 2x2 products on
+// the vector ALU: v00 = u[0][0], v01 = u[0][2], v10 = u[2][0], v11 = u[2][2] of the 4x4 form.
+template <int SA, typename R>
+__device__ __forceinline__ void item_1q(cx<R> (&x)[16], cx<R> v00, cx<R> v01, cx<R> v10, cx<R> v11) {
+  // (the convergent no-op keeps the slot cases apart, as in item_gate)
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i & (1 << SA)) continue;
+    const cx<R> x0 = x[i], x1 = x[i | (1 << SA)];
+    cx<R> y0 = cmake<R>(0, 0), y1 = cmake<R>(0, 0);
+    cfma(y0, v00, x0);
+    cfma(y0, v01, x1);
+    cfma(y1, v10, x0);
+    cfma(y1, v11, x1);
+    x[i] = y0;
+    x[i | (1 << SA)] = y1;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename R>
+__device__ __forceinline__ void item_1q_slot(int sa, cx<R> (&x)[16], cx<R> v00, cx<R> v01, cx<R> v10,
+                                             cx<R> v11) {
+  switch (sa) {
+    case 0: item_1q<0, R>(x, v00, v01, v10, v11); break;
+    case 1: item_1q<1, R>(x, v00, v01, v10, v11); break;
+    case 2: item_1q<2, R>(x, v00, v01, v10, v11); break;
+    default: item_1q<3, R>(x, v00, v01, v10, v11); break;
+  }
+}
+
+// A CNOT (control item slot SC, target slot ST) exchanges the amplitudes it maps onto each
+// other: no arithmetic.
+template <int SC, int ST, typename R>
+__device__ __forceinline__ void item_cnot(cx<R> (&x)[16]) {
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (!(i & (1 << SC)) || (i & (1 << ST))) continue;
+    const cx<R> t = x[i];
+    x[i] = x[i | (1 << ST)];
+    x[i | (1 << ST)] = t;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename R>
+__device__ __forceinline__ void item_cnot_slots(int sc, int st, cx<R> (&x)[16]) {
+  switch (sc * 4 + st) {
+    case 1: item_cnot<0, 1, R>(x); break;
+    case 2: item_cnot<0, 2, R>(x); break;
+    case 3: item_cnot<0, 3, R>(x); break;
+    case 4: item_cnot<1, 0, R>(x); break;
+    case 6: item_cnot<1, 2, R>(x); break;
+    case 7: item_cnot<1, 3, R>(x); break;
+    case 8: item_cnot<2, 0, R>(x); break;
+    case 9: item_cnot<2, 1, R>(x); break;
+    case 11: item_cnot<2, 3, R>(x); break;
+    case 12: item_cnot<3, 0, R>(x); break;
+    case 13: item_cnot<3, 1, R>(x); break;
+    default: item_cnot<3, 2, R>(x); break;
   }
 }
 
@@ -657,7 +723,19 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
       }
       if (!apply) continue;
       for (int k = k_lo; k <= k_hi; ++k) {
-        const int sa = gslot[2 * k], sb = gslot[2 * k + 1];
+        const int sa = gslot[kFwdGS * k], sb = gslot[kFwdGS * k + 1], mode = gslot[kFwdGS * k + 2];
+        if (mode == kFwdCnotA || mode == kFwdCnotB) {
+          const bool ca = mode == kFwdCnotA;
+          item_cnot_slots<R>(ca ? sa : sb, ca ? sb : sa, x);
+        } else if (mode == kFwd1Q) {
+          // v = the 2x2 block u[2a][2a'] of the gate's v (x) I_2 form
+          const int b0 = k * 16;
+          const cx<R> v00 = gates_in_lds ? lgates[b0] : cmake<R>(gates_c[b0].re, gates_c[b0].im);
+          const cx<R> v01 = gates_in_lds ? lgates[b0 + 2] : cmake<R>(gates_c[b0 + 2].re, gates_c[b0 + 2].im);
+          const cx<R> v10 = gates_in_lds ? lgates[b0 + 8] : cmake<R>(gates_c[b0 + 8].re, gates_c[b0 + 8].im);
+          const cx<R> v11 = gates_in_lds ? lgates[b0 + 10] : cmake<R>(gates_c[b0 + 10].re, gates_c[b0 + 10].im);
+          item_1q_slot<R>(sa, x, v00, v01, v10, v11);
+        } else {
         Gate4 G4;
         cx<R> u[16];
         if (mf) {
@@ -672,6 +750,7 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
             for (int e = 0; e < 16; ++e) u[e] = cmake<R>(gates_c[k * 16 + e].re, gates_c[k * 16 + e].im);
           }
           item_gate_slots<R, false>(sa, sb, x, u, G4);
+        }
         }
       }
       if (ok) {
@@ -911,12 +990,42 @@ int launch_group_finalize(int P, const c128 *gpartials, int pstride, const int32
 
 
 // ------------------------------------------------------------------ grouped forward, host
+std::vector<int32_t> forward_gate_modes(int L, const int32_t *kinds, const c128 *gates_host, int copies) {
+  std::vector<int32_t> mode(L, kFwdDense);
+  if (!kinds) return mode;
+  // exactly a CNOT, control on the pair's first (A) or second (B) qubit: the 4x4 entries
+  // (row-major) that are 1, every other entry 0
+  static const int onesA[4] = {0, 5, 11, 14}, onesB[4] = {0, 7, 10, 13};
+  auto is_perm = [](const c128 *u, const int (&ones)[4]) {
+    for (int e = 0; e < 16; ++e) {
+      const bool one = e == ones[0] || e == ones[1] || e == ones[2] || e == ones[3];
+      if (u[e].re != (one ? 1.0 : 0.0) || u[e].im != 0.0) return false;
+    }
+    return true;
+  };
+  for (int k = 0; k < L; ++k) {
+    if (kinds[k] == QFS_GATE_1Q) {
+      mode[k] = kFwd1Q;
+    } else if (kinds[k] == QFS_GATE_FIXED && gates_host && copies > 0) {
+      bool a = true, b = true;
+      for (int c = 0; c < copies; ++c) {
+        const c128 *u = gates_host + ((size_t)c * L + k) * 16;
+        a = a && is_perm(u, onesA);
+        b = b && is_perm(u, onesB);
+      }
+      mode[k] = a ? kFwdCnotA : b ? kFwdCnotB : kFwdDense;
+    }
+  }
+  return mode;
+}
+
 int build_forward_plan(const Geometry &g, int L, const int32_t *pairs, const std::vector<GateGroup> &groups,
-                       const int32_t *bneed_host, std::vector<int32_t> &plan, std::vector<int32_t> &gslot) {
+                       const int32_t *bneed_host, const int32_t *mode_host, std::vector<int32_t> &plan,
+                       std::vector<int32_t> &gslot) {
   const int nC = g.n + g.logC;
   if (nC < 4) return QFS_EUNSUPPORTED;
   plan.assign(groups.size() * kFwdPlan, 0);
-  gslot.assign(2 * (size_t)L, 0);
+  gslot.assign(kFwdGS * (size_t)L, 0);
   const int ng = (int)groups.size();
   for (int fi = 0; fi < ng; ++fi) {
     const GateGroup &gg = groups[ng - 1 - fi];  // forward order
@@ -941,8 +1050,9 @@ int build_forward_plan(const Geometry &g, int L, const int32_t *pairs, const std
       return -1;
     };
     for (int k = gg.k_lo; k <= gg.k_hi; ++k) {
-      gslot[2 * k] = slot(pairs[2 * k]);
-      gslot[2 * k + 1] = slot(pairs[2 * k + 1]);
+      gslot[kFwdGS * k] = slot(pairs[2 * k]);
+      gslot[kFwdGS * k + 1] = slot(pairs[2 * k + 1]);
+      gslot[kFwdGS * k + 2] = mode_host ? mode_host[k] : kFwdDense;
     }
   }
   return QFS_OK;

@@ -400,10 +400,19 @@ int launch_group_pass(const Geometry &g, const int32_t *pairs, const GateGroup *
                       LaunchEvents ev = {});
 // Forward pass by gate groups (the groups in forward order, one LDS round trip per group;
 // complex64 states, the products on the matrix cores):
-// plan [ngroups][8] and per-gate slots [L][2] from build_forward_plan (host; bneed_host
-// [L] marks the B entries the backward pass reads), copied to the device by the caller.
+// plan [ngroups][8] and per-gate entries [L][kFwdGS] (the slots of the gate's two qubits and
+// how it is applied) from build_forward_plan (host; bneed_host [L] marks the B entries the
+// backward pass reads; mode_host [L] from forward_gate_modes, or null: every gate dense),
+// copied to the device by the caller.
+enum { kFwdGS = 4 };
+enum { kFwdDense = 0, kFwd1Q = 1, kFwdCnotA = 2, kFwdCnotB = 3 };
+// How each gate is applied in the grouped forward pass: one-qubit gates (v (x) I_2) as 2x2
+// products, constant gates that are exactly a CNOT (in every one of `copies` host copies of
+// the gates, [copies][L][16]) as an exchange of amplitudes, the rest as dense 4x4 products.
+std::vector<int32_t> forward_gate_modes(int L, const int32_t *kinds, const c128 *gates_host, int copies);
 int build_forward_plan(const Geometry &g, int L, const int32_t *pairs, const std::vector<GateGroup> &groups,
-                       const int32_t *bneed_host, std::vector<int32_t> &plan, std::vector<int32_t> &gslot);
+                       const int32_t *bneed_host, const int32_t *mode_host, std::vector<int32_t> &plan,
+                       std::vector<int32_t> &gslot);
 template <typename R>
 int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef gates, const cx<R> *psi,
                           cx<R> *blist, int64_t bstride, const cx<R> *phi_ref, double *c0_partials,
