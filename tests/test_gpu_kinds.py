@@ -149,6 +149,42 @@ def test_mixed_u3_cnot_teacher_forced():
                 assert np.max(np.abs(u.conj().T @ u - np.eye(4))) < 1e-12
 
 
+CNOT_A = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
+CNOT_B = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], dtype=np.complex128)
+SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], dtype=np.complex128)
+
+
+def test_mixed_constant_gate_forms_teacher_forced():
+    """complex64 states on a random-pair template whose constant gates are CNOTs with the
+    control on either qubit of the pair (applied as amplitude exchanges in the grouped
+    forward pass), SWAPs and Haar 4x4 gates (applied as dense products), among one- and
+    two-qubit variable gates: each sweep teacher-forced against the oracle."""
+    say("kinds mixed teacher-forced: CNOT forms")
+    n, L, M, starts = 8, 40, 32, 2
+    g = np.random.default_rng(90)
+    pairs = I.random_pair_template(n, L, g)
+    kinds = np.array([I.GATE_FIXED, I.GATE_1Q, I.GATE_2Q, I.GATE_1Q] * (L // 4), dtype=np.int32)
+    forms = [CNOT_A, CNOT_B, SWAP, None]
+    fixed = np.stack([forms[(k // 4) % 4] if forms[(k // 4) % 4] is not None else I.haar_unitary(4, g)
+                      for k in range(L)])
+    tg = I.kinds_target_gates(kinds, fixed, g)
+    psi = I.orthonormal_samples(n, M, g)
+    phi = O.apply_circuit(n, psi, pairs, tg)
+    gates = np.stack([O.initial_gates(91, s, kinds, fixed) for s in range(starts)])
+    dpsi, dphi, dg = dev(psi), dev(phi), dev(gates)
+    c_init = max(O.sweep(n, pairs, psi, phi, gates[0], kinds=kinds)[1], 1e-3)
+    for sweep in range(6):
+        start = host(dg).copy()
+        c_gpu = Q.qfs_sweep(n, pairs, dpsi, dphi, dg, precision=Q.QFS_PREC_MIXED, kinds=kinds)
+        new = host(dg)
+        for s in range(starts):
+            _, c_ref = O.sweep(n, pairs, psi, phi, start[s], kinds=kinds)
+            assert abs(c_gpu[s] - c_ref) <= 1e-6 * max(c_ref, c_init), (sweep, s, c_gpu[s], c_ref)
+            for k in range(L):
+                if kinds[k] == I.GATE_FIXED:
+                    assert np.array_equal(new[s][k], fixed[k]), (sweep, s, k)
+
+
 def test_instantiate_u3_cnot_fp64_matches_oracle_control_flow():
     """Initial one-qubit gates drawn on the device as on the oracle (Haar 2x2 from the same
     counter stream), then the same control flow: reason, start, sweeps, doublings, cost."""
