@@ -965,17 +965,6 @@ int Group::setup_working() {
   // chunk width
   c.fplan = c.fgslot = nullptr;
   c.fngroups = 0;
-  if (c.grouped && fused && !fp64_ && fmode_.empty()) {
-    // how the forward pass applies each gate (the constant gates are the template's in
-    // every start)
-    std::vector<c128> fixed_h;
-    if (!kinds_.empty() && fixed_) {
-      fixed_h.resize((size_t)L_ * 16);
-      QFS_HIP(hipMemcpy(fixed_h.data(), fixed_, sizeof(c128) * fixed_h.size(), hipMemcpyDeviceToHost));
-    }
-    fmode_ = forward_gate_modes(L_, kinds_.empty() ? nullptr : kinds_.data(),
-                                fixed_h.empty() ? nullptr : fixed_h.data(), 1);
-  }
   if (c.grouped && fused && !fp64_ && build_forward_plan(c.g, L_, pairs_.data(), groups_, bneed_h_.data(),
                                                          fmode_.data(), fplan_h_, fgslot_h_) == QFS_OK) {
     if (!fplan_dev_.ptr) QFS_TRY(arena_.alloc(fplan_dev_, sizeof(int32_t) * fplan_h_.size()));
@@ -1236,6 +1225,19 @@ int Group::run(GroupResult &out, double t_start) {
   h_costs_bytes_ = sizeof(double) * 3 * S_ * (1 + 2 * SweepCtx::kParts);
   h_costs_ = static_cast<double *>(pinned_take(h_costs_bytes_));
   if (!h_costs_) return set_error_detail("hipHostMalloc of the cost buffer failed"), QFS_EDEVICE;
+  // how the grouped forward pass applies each gate (the constant gates are the template's
+  // in every start), before any work is queued on the stream
+  {
+    std::vector<c128> fixed_h;
+    if (!kinds_.empty() && fixed_) {
+      fixed_h.resize((size_t)L_ * 16);
+      QFS_HIP(hipMemcpyAsync(fixed_h.data(), fixed_, sizeof(c128) * fixed_h.size(), hipMemcpyDeviceToHost,
+                             stream_));
+      QFS_HIP(hipStreamSynchronize(stream_));
+    }
+    fmode_ = forward_gate_modes(L_, kinds_.empty() ? nullptr : kinds_.data(),
+                                fixed_h.empty() ? nullptr : fixed_h.data(), 1);
+  }
   QFS_HIP(hipEventCreate(&seg0_));
   for (auto &d : done_)
     for (hipEvent_t &e : d) QFS_HIP(hipEventCreate(&e));
