@@ -404,6 +404,7 @@ struct SweepCtx {
   // forward pass by groups (complex64, fused): device plan, per-gate slots, group count
   const int32_t *fplan = nullptr, *fgslot = nullptr;
   int fngroups = 0;
+  bool fforms = false;  // the forward plan holds one-qubit or CNOT gate forms
   // Grouped sweeps run the starts in up to nparts parts (2 by default: on MI355X more
   // parts measured no faster, their kernels slowing each other down), part p on
   // pstream[p] (pstream[0] is the call's stream), each part's forward pass right after its
@@ -446,7 +447,7 @@ int sweep_forward(SweepCtx &c, bool with_c0) {
       if (c.grouped && c.fplan) {
         QFS_TRY(launch_forward_groups<float>(c.g, val ? &c.gv : nullptr, c.L, gr, psi, B, bstride,
                                              with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
-                                             c.nslots, c.fplan, c.fngroups, c.fgslot, c.stream));
+                                             c.nslots, c.fplan, c.fngroups, c.fgslot, c.fforms, c.stream));
       } else {
         QFS_TRY(launch_forward_fused<R>(c.g, val ? &c.gv : nullptr, c.pairs_dev, c.L, gr, psi, B, bstride,
                                         with_c0 ? phi : nullptr, c.dpart0, psiv, phiv, c.dpart1, c.slots,
@@ -976,6 +977,7 @@ int Group::setup_working() {
     c.fplan = fplan_dev_.as<int32_t>();
     c.fgslot = fgslot_dev_.as<int32_t>();
     c.fngroups = (int)groups_.size();
+    c.fforms = std::any_of(fmode_.begin(), fmode_.end(), [](int32_t m) { return m != kFwdDense; });
   }
   if (!c.grouped && !partials_.ptr) {  // environment partials of the per-gate pass
     QFS_TRY(arena_.alloc(partials_, sizeof(c128) * 16 * (size_t)kPcap * S_));
@@ -2074,6 +2076,7 @@ int qfs_sweep(int32_t n, int32_t L, const int32_t *pairs, const int32_t *kinds, 
       c.fplan = fplan_d.as<int32_t>();
       c.fgslot = fgslot_d.as<int32_t>();
       c.fngroups = (int)groups.size();
+      c.fforms = std::any_of(fmode.begin(), fmode.end(), [](int32_t m) { return m != kFwdDense; });
     }
   }
   if (f32) {

@@ -650,7 +650,9 @@ __device__ __forceinline__ void item_cnot_slots(int sc, int st, cx<R> (&x)[16]) 
   }
 }
 
-template <typename R, int FB>
+// FORMS: the plan holds one-qubit or CNOT gate forms (a separate instantiation, so that the
+// dense-only kernel keeps its code as small as before).
+template <typename R, int FB, bool FORMS>
 __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdGroupSeg<R> seg1, int nseg,
                                                        int n, int logC, const int32_t *plan_in, int ngroups,
                                                        const int32_t *gslot_in, const cx<R> *gates_in,
@@ -723,11 +725,12 @@ __global__ __launch_bounds__(FB) void k_forward_groups(FwdGroupSeg<R> seg0, FwdG
       }
       if (!apply) continue;
       for (int k = k_lo; k <= k_hi; ++k) {
-        const int sa = gslot[kFwdGS * k], sb = gslot[kFwdGS * k + 1], mode = gslot[kFwdGS * k + 2];
-        if (mode == kFwdCnotA || mode == kFwdCnotB) {
+        const int sa = gslot[kFwdGS * k], sb = gslot[kFwdGS * k + 1];
+        const int mode = FORMS ? gslot[kFwdGS * k + 2] : kFwdDense;
+        if (FORMS && (mode == kFwdCnotA || mode == kFwdCnotB)) {
           const bool ca = mode == kFwdCnotA;
           item_cnot_slots<R>(ca ? sa : sb, ca ? sb : sa, x);
-        } else if (mode == kFwd1Q) {
+        } else if (FORMS && mode == kFwd1Q) {
           // v = the 2x2 block u[2a][2a'] of the gate's v (x) I_2 form
           const int b0 = k * 16;
           const cx<R> v00 = gates_in_lds ? lgates[b0] : cmake<R>(gates_c[b0].re, gates_c[b0].im);
@@ -1063,7 +1066,7 @@ int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef 
                           cx<R> *blist, int64_t bstride, const cx<R> *phi_ref, double *c0_partials,
                           const cx<R> *psiv, const cx<R> *phiv, double *val_partials,
                           const int32_t *slot_to_start, int nslots, const int32_t *plan_dev, int ngroups,
-                          const int32_t *gslot_dev, hipStream_t s) {
+                          const int32_t *gslot_dev, bool forms, hipStream_t s) {
   if (nslots <= 0) return QFS_OK;
   FwdGroupSeg<R> a{}, b{};
   a.src = psi;
@@ -1103,15 +1106,19 @@ int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef 
     QFS_HIP(hipGetLastError());
     return QFS_OK;
   };
-  if (threads == 1024) return go(k_forward_groups<R, 1024>);
-  return go(k_forward_groups<R, 512>);
+  if (forms) {
+    if (threads == 1024) return go(k_forward_groups<R, 1024, true>);
+    return go(k_forward_groups<R, 512, true>);
+  }
+  if (threads == 1024) return go(k_forward_groups<R, 1024, false>);
+  return go(k_forward_groups<R, 512, false>);
 }
 
 #define QFS_FINST(R)                                                                              \
   template int launch_forward_groups<R>(const Geometry &, const Geometry *, int, GateRef, const cx<R> *, \
                                         cx<R> *, int64_t, const cx<R> *, double *, const cx<R> *,  \
                                         const cx<R> *, double *, const int32_t *, int,            \
-                                        const int32_t *, int, const int32_t *, hipStream_t);
+                                        const int32_t *, int, const int32_t *, bool, hipStream_t);
 QFS_FINST(float)
 #undef QFS_FINST
 

@@ -409,6 +409,7 @@ enum { kFwdDense = 0, kFwd1Q = 1, kFwdCnotA = 2, kFwdCnotB = 3 };
 // How each gate is applied in the grouped forward pass: one-qubit gates (v (x) I_2) as 2x2
 // products, constant gates that are exactly a CNOT (in every one of `copies` host copies of
 // the gates, [copies][L][16]) as an exchange of amplitudes, the rest as dense 4x4 products.
+// launch_forward_groups takes forms = any gate not dense (a kernel built for the forms).
 std::vector<int32_t> forward_gate_modes(int L, const int32_t *kinds, const c128 *gates_host, int copies);
 int build_forward_plan(const Geometry &g, int L, const int32_t *pairs, const std::vector<GateGroup> &groups,
                        const int32_t *bneed_host, const int32_t *mode_host, std::vector<int32_t> &plan,
@@ -418,7 +419,7 @@ int launch_forward_groups(const Geometry &g, const Geometry *gv, int L, GateRef 
                           cx<R> *blist, int64_t bstride, const cx<R> *phi_ref, double *c0_partials,
                           const cx<R> *psiv, const cx<R> *phiv, double *val_partials,
                           const int32_t *slot_to_start, int nslots, const int32_t *plan_dev, int ngroups,
-                          const int32_t *gslot_dev, hipStream_t s);
+                          const int32_t *gslot_dev, bool forms, hipStream_t s);
 // Work-groups per start of a grouped pass when `running_starts` starts sweep together
 // (whatever streams they are split over).
 int group_blocks_per_start(int running_starts);
